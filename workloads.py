@@ -1,0 +1,157 @@
+"""Seeded synthetic inputs for the voxel-lattice step.
+
+This module builds inputs only: material grids, palettes, parameter sets,
+fixed masks, external forces and initial velocities.  It holds none of the
+method's arithmetic, and both the GPU library's tests and the oracle's tests
+draw their inputs from it.  Every random choice goes through
+``numpy.random.Generator(PCG64(seed))``.
+
+A workload is a dict:
+  grid      uint8 (nz, ny, nx), material index per cell, 0 = empty
+  materials list of dicts {E, nu, rho, cte, mu_s, mu_d}; index 0 is empty
+  params    dict of simulation parameters (voxel_size, gravity, zeta_*, ...)
+  fixed     uint8 per cell or None
+  forces    float64 (ncell, 3) or None
+  velocity  float64 (ncell, 3) or None
+  amp/phase float64 per cell or None (per-voxel actuation signal)
+  steps     number of steps the scenario runs
+"""
+import numpy as np
+
+EMPTY = {"E": 1.0, "nu": 0.0, "rho": 1.0, "cte": 0.0, "mu_s": 0.0, "mu_d": 0.0}
+
+
+def _mat(E, nu=0.35, rho=1000.0, cte=0.0, mu_s=1.0, mu_d=0.5):
+    return {"E": float(E), "nu": float(nu), "rho": float(rho), "cte": float(cte),
+            "mu_s": float(mu_s), "mu_d": float(mu_d)}
+
+
+def _base_params(**kw):
+    p = {"voxel_size": 1e-3, "gravity": 0.0, "zeta_bond": 0.0, "zeta_slow": 0.0, "zeta_col": 0.0,
+         "temp_amp": 0.0, "temp_freq": 0.0, "temp_phase": 0.0, "dt_scale": 1.0,
+         "origin": (0.0, 0.0, 0.0), "floor_on": 0, "self_collision_on": 0, "contact_cap": 32}
+    p.update(kw)
+    return p
+
+
+def _workload(grid, materials, params, steps, fixed=None, forces=None, velocity=None,
+              amp=None, phase=None, name=""):
+    return {"name": name, "grid": np.ascontiguousarray(grid, dtype=np.uint8), "materials": materials,
+            "params": params, "steps": int(steps), "fixed": fixed, "forces": forces,
+            "velocity": velocity, "amp": amp, "phase": phase}
+
+
+def cell_coords(shape):
+    """(x, y, z) integer index arrays of a (nz, ny, nx) grid, flattened."""
+    nz, ny, nx = shape
+    c = np.arange(nx * ny * nz)
+    return c % nx, (c // nx) % ny, c // (nx * ny)
+
+
+def cantilever(nx=20, ny=4, nz=4, steps=10000):
+    """Cantilever of nx*ny*nz 1 mm voxels, E = 1 MPa, nu = 0.35, rho = 1000,
+    x = 0 layer fixed, gravity, light damping."""
+    grid = np.ones((nz, ny, nx), np.uint8)
+    x, _, _ = cell_coords(grid.shape)
+    fixed = (x == 0).astype(np.uint8)
+    params = _base_params(gravity=9.81, zeta_bond=0.1, zeta_slow=0.01)
+    return _workload(grid, [EMPTY, _mat(1e6)], params, steps, fixed=fixed, name="cantilever_20x4x4")
+
+
+def random_block(n=100, seed=2, steps=1000, drop_height=5e-3, impact=False):
+    """n^3 cells iid {empty 0.1, soft 1 MPa 0.45, stiff 100 MPa 0.45} on a floor
+    with friction.  ``impact=False``: bottom at ``drop_height`` at rest.
+    ``impact=True``: bottom on the floor, moving down at the speed of a
+    ``drop_height`` free fall."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    grid = rng.choice(np.array([0, 1, 2], np.uint8), size=(n, n, n), p=[0.1, 0.45, 0.45])
+    mats = [EMPTY, _mat(1e6), _mat(1e8)]
+    g = 9.81
+    z0 = 0.0 if impact else drop_height
+    params = _base_params(gravity=g, zeta_bond=0.5, zeta_col=0.5, floor_on=1, origin=(0.0, 0.0, z0))
+    vel = None
+    if impact:
+        vel = np.zeros((grid.size, 3))
+        vel[:, 2] = -np.sqrt(2.0 * g * drop_height)
+    name = "random_block_%d%s" % (n, "_impact" if impact else "")
+    return _workload(grid, mats, params, steps, velocity=vel, name=name)
+
+
+def blob_lattice(n=256, seed=3, steps=500, sites=64, n_mat=4):
+    """n^3 lattice, every cell filled, materials assigned by nearest of
+    ``sites`` seeded points (Voronoi blobs).  Material k has E log-uniform in
+    [0.1, 100] MPa and CTE uniform in [0, 0.01]/K; temperature signal
+    20 K sin(2 pi 5 Hz t); self-collision on; no gravity, no floor."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pts = rng.uniform(0, n, size=(sites, 3))
+    lab = rng.integers(0, n_mat, size=sites)
+    E = 10.0 ** rng.uniform(5.0, 8.0, size=n_mat)
+    cte = rng.uniform(0.0, 0.01, size=n_mat)
+    grid = np.empty((n, n, n), np.uint8)
+    xs = np.arange(n) + 0.5
+    X, Y = np.meshgrid(xs, xs, indexing="xy")  # (ny, nx)
+    for z in range(n):
+        best = np.full((n, n), np.inf)
+        arg = np.zeros((n, n), np.int64)
+        for s in range(sites):
+            d = (X - pts[s, 0]) ** 2 + (Y - pts[s, 1]) ** 2 + (z + 0.5 - pts[s, 2]) ** 2
+            m = d < best
+            best[m] = d[m]
+            arg[m] = s
+        grid[z] = (lab[arg] + 1).astype(np.uint8)
+    mats = [EMPTY] + [_mat(E[k], cte=cte[k]) for k in range(n_mat)]
+    params = _base_params(zeta_bond=0.5, zeta_col=0.5, temp_amp=20.0, temp_freq=5.0,
+                          self_collision_on=1)
+    return _workload(grid, mats, params, steps, name="blob_lattice_%d" % n)
+
+
+def batch_objects(count=4096, seed=4, steps=2000, lo=8, hi=32):
+    """``count`` independent objects with bounding boxes iid U{lo..hi} per
+    axis, cells iid uniform over {empty, soft, stiff, actuated+, actuated-}
+    (actuation: CTE +/-0.01 under a 20 K, 5 Hz signal, i.e. phases 0 and pi),
+    each on a floor under gravity."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mats = [EMPTY, _mat(1e6), _mat(1e8), _mat(1e6, cte=0.01), _mat(1e6, cte=-0.01)]
+    objs = []
+    for i in range(count):
+        nx, ny, nz = (int(v) for v in rng.integers(lo, hi + 1, size=3))
+        grid = rng.integers(0, 5, size=(nz, ny, nx)).astype(np.uint8)
+        params = _base_params(gravity=9.81, zeta_bond=0.5, zeta_col=0.5, floor_on=1,
+                              temp_amp=20.0, temp_freq=5.0)
+        objs.append(_workload(grid, mats, params, steps, name="batch_obj_%d" % i))
+    return objs
+
+
+def solid_cube(n, E=1e6, steps=100, **kw):
+    """A full n^3 block of one material (performance shape of the paper's
+    cubic-block sweep)."""
+    grid = np.ones((n, n, n), np.uint8)
+    params = _base_params(**kw)
+    return _workload(grid, [EMPTY, _mat(E)], params, steps, name="cube_%d" % n)
+
+
+def random_grid(shape, n_mat, fill, seed):
+    """Cells iid: empty with probability 1 - fill, else uniform over 1..n_mat."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    filled = rng.uniform(size=shape) < fill
+    mat = rng.integers(1, n_mat + 1, size=shape)
+    return np.where(filled, mat, 0).astype(np.uint8)
+
+
+def random_materials(n_mat, seed, cte_max=0.0):
+    """Materials with E log-uniform in [0.1, 100] MPa, rho in [500, 2000],
+    nu in [0.2, 0.45] and CTE uniform in [-cte_max, cte_max]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = [EMPTY]
+    for _ in range(n_mat):
+        out.append(_mat(10.0 ** rng.uniform(5, 8), nu=rng.uniform(0.2, 0.45),
+                        rho=rng.uniform(500, 2000), cte=rng.uniform(-cte_max, cte_max)))
+    return out
+
+
+def random_state(ncell, seed, u_scale, v_scale, w_scale, rot_scale):
+    """Perturbed state: displacements, velocities, angular velocities and small
+    rotation vectors drawn iid normal with the given scales."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return {"u": rng.normal(0, u_scale, (ncell, 3)), "v": rng.normal(0, v_scale, (ncell, 3)),
+            "w": rng.normal(0, w_scale, (ncell, 3)), "rot": rng.normal(0, rot_scale, (ncell, 3))}
