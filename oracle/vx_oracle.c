@@ -121,7 +121,11 @@ typedef struct {
     double kv, kphi;       /* translational / rotational stiffness to ground */
     double cte, mu_s, mu_d;
     double amp, phase;     /* actuation amplitude (K) and phase (rad) */
-    vec3 D, P, W;          /* position, linear momentum, angular momentum */
+    /* Position D of the paper's state, held as the rest position of the
+     * cell plus a displacement U so that bond stretches never subtract two
+     * large absolute coordinates (lattice offsets are exact integers times l). */
+    vec3 D0, U;
+    vec3 P, W;             /* linear momentum, angular momentum */
     quat q;                /* orientation, body -> world */
     vec3 Fext;
     int fixed, is_static, surface;
@@ -171,6 +175,15 @@ static void set_err(vxo_sim *s, const char *m) {
 /* ------------------------------------------------------------------ */
 /* setup                                                              */
 /* ------------------------------------------------------------------ */
+/* Separation D_B - D_A of two voxels: exact lattice offset plus the
+ * difference of displacements. */
+static vec3 separation(const vxo_sim *s, const voxel *A, const voxel *B) {
+    double l = s->l;
+    return vadd(v3((B->ix - A->ix) * l, (B->iy - A->iy) * l, (B->iz - A->iz) * l), vsub(B->U, A->U));
+}
+/* Absolute position D of a voxel. */
+static vec3 position(const voxel *V) { return vadd(V->D0, V->U); }
+
 /* Composite of two moduli: springs of half length in series (Eq. 1, 2). */
 static double composite(double a, double b) { return 2.0 * a * b / (a + b); }
 
@@ -238,8 +251,9 @@ vxo_sim *vxo_create(const uint8_t *grid, int nx, int ny, int nz,
                 V->kphi = mt->E * l * l * l / 6.0;
                 V->cte = mt->cte; V->mu_s = mt->mu_s; V->mu_d = mt->mu_d;
                 V->amp = prm->temp_amp; V->phase = prm->temp_phase;
-                V->D = v3(prm->origin[0] + (x + 0.5) * l, prm->origin[1] + (y + 0.5) * l,
-                          prm->origin[2] + (z + 0.5) * l);
+                V->D0 = v3(prm->origin[0] + (x + 0.5) * l, prm->origin[1] + (y + 0.5) * l,
+                           prm->origin[2] + (z + 0.5) * l);
+                V->U = v3(0.0, 0.0, 0.0);
                 V->q.w = 1.0; V->q.x = V->q.y = V->q.z = 0.0;
                 for (int k = 0; k < 6; k++) V->bond_slot[k] = -1;
                 V->cand = (int *)malloc(sizeof(int) * (size_t)s->cand_cap);
@@ -341,10 +355,8 @@ int vxo_set_velocity(vxo_sim *s, const double *vel) {
 }
 
 void vxo_read_state(const vxo_sim *s, double *u, double *q, double *vel, double *omega) {
-    double l = s->l;
     for (int c = 0; c < s->ncell; c++) {
         int v = s->cell_to_vox[c];
-        int x = c % s->nx, y = (c / s->nx) % s->ny, z = c / (s->nx * s->ny);
         if (v < 0) {
             if (u) { u[3 * c] = u[3 * c + 1] = u[3 * c + 2] = 0.0; }
             if (q) { q[4 * c] = 1.0; q[4 * c + 1] = q[4 * c + 2] = q[4 * c + 3] = 0.0; }
@@ -353,11 +365,7 @@ void vxo_read_state(const vxo_sim *s, double *u, double *q, double *vel, double 
             continue;
         }
         const voxel *V = &s->vox[v];
-        if (u) {
-            u[3 * c] = V->D.x - (s->p.origin[0] + (x + 0.5) * l);
-            u[3 * c + 1] = V->D.y - (s->p.origin[1] + (y + 0.5) * l);
-            u[3 * c + 2] = V->D.z - (s->p.origin[2] + (z + 0.5) * l);
-        }
+        if (u) { u[3 * c] = V->U.x; u[3 * c + 1] = V->U.y; u[3 * c + 2] = V->U.z; }
         if (q) { q[4 * c] = V->q.w; q[4 * c + 1] = V->q.x; q[4 * c + 2] = V->q.y; q[4 * c + 3] = V->q.z; }
         if (vel) { vel[3 * c] = V->P.x / V->m; vel[3 * c + 1] = V->P.y / V->m; vel[3 * c + 2] = V->P.z / V->m; }
         if (omega) { omega[3 * c] = V->W.x / V->I; omega[3 * c + 1] = V->W.y / V->I; omega[3 * c + 2] = V->W.z / V->I; }
@@ -366,14 +374,10 @@ void vxo_read_state(const vxo_sim *s, double *u, double *q, double *vel, double 
 
 void vxo_write_state(vxo_sim *s, const double *u, const double *q, const double *vel,
                      const double *omega) {
-    double l = s->l;
     for (int v = 0; v < s->nvox; v++) {
         voxel *V = &s->vox[v];
         int c = V->cell;
-        if (u)
-            V->D = v3(s->p.origin[0] + (V->ix + 0.5) * l + u[3 * c],
-                      s->p.origin[1] + (V->iy + 0.5) * l + u[3 * c + 1],
-                      s->p.origin[2] + (V->iz + 0.5) * l + u[3 * c + 2]);
+        if (u) V->U = v3(u[3 * c], u[3 * c + 1], u[3 * c + 2]);
         if (q) { V->q.w = q[4 * c]; V->q.x = q[4 * c + 1]; V->q.y = q[4 * c + 2]; V->q.z = q[4 * c + 3]; }
         if (vel) V->P = vscale(v3(vel[3 * c], vel[3 * c + 1], vel[3 * c + 2]), V->m);
         if (omega) V->W = vscale(v3(omega[3 * c], omega[3 * c + 1], omega[3 * c + 2]), V->I);
@@ -418,7 +422,8 @@ static void bond_force(vxo_sim *s, bond *b) {
     /* Transform into the frame of voxel 1, then permute the bond axis onto
      * +x: voxel 1 sits at the origin with zero rotation, so only voxel 2's
      * six displacements remain (text before Eq. 13). */
-    vec3 d = perm_to_local(a, qrotate_inv(A->q, vsub(B->D, A->D)));
+    vec3 dAB = separation(s, A, B);
+    vec3 d = perm_to_local(a, qrotate_inv(A->q, dAB));
     vec3 th = perm_to_local(a, qlog_rotvec(qmul(qconj(A->q), B->q)));
     double X2 = d.x - L, Y2 = d.y, Z2 = d.z;
     /* Nodal forces K u of the 12-DOF beam (Eq. 7) with u1 = 0.  READING:
@@ -439,10 +444,10 @@ static void bond_force(vxo_sim *s, bond *b) {
      * translation and rotation removed. */
     vec3 v1 = vscale(A->P, 1.0 / A->m), v2 = vscale(B->P, 1.0 / B->m);
     vec3 w1 = vscale(A->W, 1.0 / A->I), w2 = vscale(B->W, 1.0 / B->I);
-    vec3 Da = vscale(vadd(A->D, B->D), 0.5);
     vec3 Va = vscale(vadd(v1, v2), 0.5);
     vec3 Wa = vscale(vadd(w1, w2), 0.5);
-    vec3 Vr = vadd(vsub(v2, Va), vcross(vsub(B->D, Da), Wa));
+    vec3 r2 = vscale(dAB, 0.5);  /* D2 - Da, Da the mean position of the pair */
+    vec3 Vr = vadd(vsub(v2, Va), vcross(r2, Wa));
     vec3 Wr = vsub(w2, Wa);
     F2 = vsub(F2, vscale(Vr, b->ct));
     M2 = vsub(M2, vscale(Wr, b->cr));
@@ -464,7 +469,7 @@ static void rebuild_candidates(vxo_sim *s) {
             if (!B->surface) continue;
             int man = abs(A->ix - B->ix) + abs(A->iy - B->iy) + abs(A->iz - B->iz);
             if (man <= 3) continue;
-            if (!(vnorm(vsub(A->D, B->D)) < H)) continue;
+            if (!(vnorm(separation(s, B, A)) < H)) continue;
             /* voxel ids ascend with j, so both lists stay sorted */
             if (A->ncand < s->cand_cap) A->cand[A->ncand++] = j; else s->overflow = 1;
             if (B->ncand < s->cand_cap) B->cand[B->ncand++] = i; else s->overflow = 1;
@@ -567,7 +572,7 @@ static int step_once(vxo_sim *s) {
         V->Fn = 0.0;
         if (s->p.floor_on) {
             double size = l * (1.0 + V->eps);
-            double pen = 0.5 * size - V->D.z;
+            double pen = 0.5 * size - position(V).z;
             if (pen > 0.0) {
                 double cd = 2.0 * s->p.zeta_col * sqrt(V->m * V->kv);
                 double Fn = V->kv * pen - cd * vel.z;
@@ -583,7 +588,7 @@ static int step_once(vxo_sim *s) {
             vec3 Fc = v3(0, 0, 0);
             for (int k = 0; k < V->ncand; k++) {
                 const voxel *U = &s->vox[V->cand[k]];
-                vec3 r = vsub(V->D, U->D);
+                vec3 r = separation(s, U, V);  /* D_v - D_u */
                 double dist = vnorm(r);
                 double c = 0.5 * l * (1.0 + V->eps) + 0.5 * l * (1.0 + U->eps);
                 if (!(dist < c) || !(dist > 0.0)) continue;
@@ -610,7 +615,7 @@ static int step_once(vxo_sim *s) {
         if (s->p.floor_on) friction(s, V);
         V->P = vadd(V->P, vscale(V->F, dt));
         vec3 vel = vscale(V->P, 1.0 / V->m);
-        V->D = vadd(V->D, vscale(vel, dt));
+        V->U = vadd(V->U, vscale(vel, dt));
         V->W = vadd(V->W, vscale(V->M, dt));
         /* READING: the orientation is a unit quaternion advanced by the
          * exact rotation (phi / I) dt, the rotational analogue of Eq. 30 */
@@ -618,7 +623,7 @@ static int step_once(vxo_sim *s) {
         V->q = qnormalize(qmul(qexp_rotvec(vscale(om, dt)), V->q));
         double sp = vnorm(vel);
         if (sp > vmax) vmax = sp;
-        if (!finite3(V->D) || !finite3(V->P) || !finite3(V->W) || !isfinite(V->q.w)) ok = 0;
+        if (!finite3(V->U) || !finite3(V->P) || !finite3(V->W) || !isfinite(V->q.w)) ok = 0;
     }
     s->step++;
     s->t = (double)s->step * dt;
@@ -670,16 +675,16 @@ void vxo_energy(vxo_sim *s, double *out) {
     for (int v = 0; v < s->nvox; v++) {
         voxel *V = &s->vox[v];
         ke += 0.5 * vdot(V->P, V->P) / V->m + 0.5 * vdot(V->W, V->W) / V->I;
-        ug += V->m * s->p.gravity * V->D.z;
+        ug += V->m * s->p.gravity * position(V).z;
         V->F = v3(0, 0, 0); V->M = v3(0, 0, 0);
         Ptot = vadd(Ptot, V->P);
-        Ltot = vadd(Ltot, vadd(vcross(V->D, V->P), V->W));
+        Ltot = vadd(Ltot, vadd(vcross(position(V), V->P), V->W));
     }
     for (int bi = 0; bi < s->nbond; bi++) {
         bond *b = &s->bonds[bi];
         const voxel *A = &s->vox[b->v1], *B = &s->vox[b->v2];
         double L = l * (1.0 + 0.5 * (A->eps + B->eps));
-        vec3 d = perm_to_local(b->axis, qrotate_inv(A->q, vsub(B->D, A->D)));
+        vec3 d = perm_to_local(b->axis, qrotate_inv(A->q, separation(s, A, B)));
         vec3 th = perm_to_local(b->axis, qlog_rotvec(qmul(qconj(A->q), B->q)));
         double X2 = d.x - L, Y2 = d.y, Z2 = d.z;
         /* 1/2 u2^T K22 u2, K22 the lower-right 6x6 block of Eq. 7 */
@@ -701,7 +706,7 @@ void vxo_energy(vxo_sim *s, double *out) {
         vec3 F = V->F;
         F.z -= V->m * s->p.gravity;
         if (s->p.floor_on) {
-            double pen = 0.5 * l * (1.0 + V->eps) - V->D.z;
+            double pen = 0.5 * l * (1.0 + V->eps) - position(V).z;
             if (pen > 0.0) { uf += 0.5 * V->kv * pen * pen; F.z += V->kv * pen; }
         }
         if (V->fixed) continue;
