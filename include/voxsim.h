@@ -1,0 +1,175 @@
+/*
+ * voxsim: explicit time step of a heterogeneous soft-body voxel lattice on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Hiller & Lipson, "Dynamic Simulation of Soft Heterogeneous
+ * Objects" (arXiv 1212.2845).  Each voxel of a cubic lattice is a mass with
+ * three translational and three rotational degrees of freedom; every
+ * face-adjacent pair of filled voxels is joined by an Euler-Bernoulli beam
+ * whose stiffness is the composite of the two materials.  One step computes
+ * every bond force from the current state, adds bond and ground damping,
+ * gravity, the floor with Coulomb friction, voxel-voxel contact and thermal
+ * actuation, and then updates all voxels at once.
+ *
+ * Conventions for every call:
+ *   - Return value is a status: VX_OK or one of the negative codes below.
+ *     No C++ exception crosses this interface.  vx_last_error(h) returns a
+ *     message for the last failing call on that handle.
+ *   - Host arrays passed in are borrowed for the duration of the call and
+ *     copied; the caller keeps ownership.
+ *   - Device memory: the library allocates none.  The caller allocates one
+ *     workspace of vx_workspace_bytes() bytes (e.g. a torch uint8 tensor on
+ *     the GPU), binds it with vx_bind_workspace(), and keeps it alive until
+ *     vx_destroy().  The library never frees it.
+ *   - All GPU work is enqueued on the stream given to vx_create (a
+ *     hipStream_t; NULL is the null stream).  The host blocks only in the
+ *     read calls and in the status check at the end of vx_step.
+ *   - A handle is used by one host thread at a time.
+ *   - Lattice arrays are dense over nx*ny*nz cells, cell index
+ *     x + nx*(y + ny*z); material index 0 is "empty".
+ *   - Units are SI (m, kg, s, Pa, K, N).  Gravity acts along -z; the floor
+ *     is the plane z = 0.
+ */
+#ifndef VOXSIM_H
+#define VOXSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define VX_OK 0
+#define VX_EINVAL (-1)     /* bad argument; nothing was changed */
+#define VX_EDEVICE (-2)    /* a HIP call failed */
+#define VX_EUNSTABLE (-3)  /* a non-finite value appeared in the state (the
+                              paper's TimeStep returning false) */
+#define VX_EOVERFLOW (-4)  /* a voxel had more collision candidates than
+                              contact_cap */
+#define VX_ESTATE (-5)     /* call out of order (e.g. step before bind) */
+
+/* One palette entry.  Index 0 of every palette is the empty material and
+ * its fields are ignored.  The paper's AddMat takes E and the Poisson
+ * ratio and defaults the rest (appendix, CVX_Object::AddMat). */
+typedef struct vx_material {
+    double E;     /* elastic modulus, Pa, > 0 */
+    double nu;    /* Poisson ratio, in (-1, 0.5) */
+    double rho;   /* density, kg/m^3, > 0 */
+    double cte;   /* coefficient of thermal expansion, 1/K */
+    double mu_s;  /* static friction coefficient against the floor, >= 0 */
+    double mu_d;  /* dynamic friction coefficient against the floor, >= 0 */
+} vx_material;
+
+/* Simulation parameters: the paper's setters (SetSlowDampZ,
+ * SetCollisionDampZ, SetBondDampZ, appendix) folded into one struct. */
+typedef struct vx_params {
+    double voxel_size;      /* lattice dimension l, m, > 0 */
+    double gravity;         /* m/s^2 along -z, >= 0 */
+    double zeta_bond;       /* damping ratio between bonded voxels, [0, 1) */
+    double zeta_slow;       /* damping ratio of each voxel to ground, >= 0 */
+    double zeta_col;        /* damping ratio of floor / voxel contact, >= 0 */
+    double temp_amp;        /* temperature signal amplitude, K */
+    double temp_freq;       /* temperature signal frequency, Hz */
+    double temp_phase;      /* temperature signal phase, rad */
+    double dt_scale;        /* multiplies the stable timestep, (0, 1]; 0 -> 1 */
+    double origin[3];       /* world position of the lower corner of cell 0 */
+    int32_t floor_on;       /* 1: floor at z = 0 with friction */
+    int32_t self_collision_on; /* 1: voxel-voxel contact between surface voxels */
+    int32_t contact_cap;    /* max collision candidates per surface voxel (0 -> 32) */
+    int32_t reserved;       /* must be 0 */
+} vx_params;
+
+typedef struct vx_sim *vx_handle;
+
+/* Create a simulation from a material grid (the paper's InitializeMatter /
+ * AddMat / SetMat / Import, appendix).  precision is 32 or 64: the type the
+ * state is stored and stepped in.  Computes all per-bond constants (Eq. 1-12),
+ * the stable timestep (Eq. 31-32) and the surface voxel list on the host.
+ * Errors: VX_EINVAL for a bad size, material index >= n_mat, E <= 0,
+ * rho <= 0, nu outside (-1, 0.5), l <= 0, or precision not 32/64.  On
+ * success *out is a new handle (free with vx_destroy). */
+int vx_create(const uint8_t *grid, int32_t nx, int32_t ny, int32_t nz,
+              const vx_material *palette, int32_t n_mat, const vx_params *params,
+              int32_t precision, void *stream, vx_handle *out);
+
+/* Bytes of device workspace this simulation needs (state ping-pong,
+ * per-voxel flags and materials, bond scratch, collision lists). */
+int vx_workspace_bytes(vx_handle h, uint64_t *bytes);
+
+/* Bind a device buffer of at least vx_workspace_bytes bytes, aligned to
+ * 256 bytes, and upload the initial state.  The buffer stays owned by the
+ * caller.  Errors: VX_EINVAL if too small or misaligned, VX_EDEVICE on a
+ * failed copy. */
+int vx_bind_workspace(vx_handle h, void *device_ptr, uint64_t bytes);
+
+/* Per-cell fixed mask (nonzero = immobile, the paper's AddFixedRegion). */
+int vx_set_fixed(vx_handle h, const uint8_t *mask);
+
+/* Constant external force per cell, dense ncell x 3 (N); zero rows mean
+ * "not forced" (the paper's AddForcedRegion). */
+int vx_set_forces(vx_handle h, const double *force);
+
+/* Region helpers with the paper's fractional workspace coordinates
+ * (AddFixedRegion / AddForcedRegion, appendix): loc and size in [0,1] per
+ * axis.  A voxel "touches" the region when its cube overlaps the box with
+ * positive volume.  The forced region's total force is split equally among
+ * the voxels it touches; it replaces earlier forces on those voxels. */
+int vx_fixed_region(vx_handle h, const double loc[3], const double size[3]);
+int vx_forced_region(vx_handle h, const double loc[3], const double size[3],
+                     const double force[3]);
+
+/* Per-cell temperature signal amplitude (K) and phase (rad); either may be
+ * NULL, meaning the global value of vx_params.  The voxel's temperature is
+ * amp * sin(2 pi temp_freq t + phase) (Volumetric Actuation). */
+int vx_set_actuation(vx_handle h, const double *amp, const double *phase);
+
+/* Initial velocity per cell, dense ncell x 3 (m/s); sets P = m v. */
+int vx_set_velocity(vx_handle h, const double *velocity);
+
+/* Advance n steps at the stable timestep (the paper's TimeStep, called n
+ * times).  Errors: VX_ESTATE before bind, VX_EUNSTABLE if any state value
+ * became non-finite, VX_EOVERFLOW if a candidate list overflowed. */
+int vx_step(vx_handle h, int64_t n);
+
+/* Copy the state to the host, widened to double, dense per cell (empty
+ * cells read as zero displacement, identity rotation, zero velocity):
+ * u = displacement from the rest position (ncell x 3), q = orientation
+ * quaternion (w, x, y, z) (ncell x 4), vel = linear velocity (ncell x 3),
+ * omega = angular velocity (ncell x 3).  Any pointer may be NULL. */
+int vx_read_state(vx_handle h, double *u, double *q, double *vel, double *omega);
+
+/* Overwrite the state (same layout as vx_read_state; NULL = keep). */
+int vx_write_state(vx_handle h, const double *u, const double *q, const double *vel,
+                   const double *omega);
+
+/* Per-cell flags: is_static (floor static-friction state) and surface. */
+int vx_read_flags(vx_handle h, uint8_t *is_static, uint8_t *surface);
+
+int vx_get_dt(vx_handle h, double *dt);       /* timestep, s */
+int vx_get_time(vx_handle h, double *t);      /* simulated time, s */
+
+/* out[0] steps taken, out[1] candidate-list rebuilds, out[2] candidate
+ * pairs in the current list, out[3] number of voxels (filled cells). */
+int vx_counters(vx_handle h, int64_t out[4]);
+
+/* Current collision candidate pairs as (cell_a, cell_b) with
+ * cell_a < cell_b; writes at most max_pairs and returns the total count in
+ * *n_pairs. */
+int vx_candidates(vx_handle h, int32_t *cell_a, int32_t *cell_b, int32_t max_pairs,
+                  int32_t *n_pairs);
+
+/* Select the step implementation: 0 = fused LDS-tiled kernel (default),
+ * 1 = split per-axis bond kernels plus a gather kernel. */
+int vx_set_kernel(vx_handle h, int32_t kind);
+
+/* Free host-side data of the handle (not the caller's workspace). */
+int vx_destroy(vx_handle h);
+
+const char *vx_last_error(vx_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

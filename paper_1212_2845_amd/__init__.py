@@ -1,0 +1,287 @@
+"""voxsim: MI355X (gfx950) explicit time step of a heterogeneous voxel lattice.
+
+Thin ctypes binding over the C ABI of ``libvoxsim.so`` (declared in
+``include/voxsim.h``).  Every step of the simulation runs in the library's HIP
+kernels; this module only marshals arguments and lets PyTorch own the device
+workspace and supply the stream.  There is no fallback: if the shared library
+is missing the import of :func:`lib` raises.
+
+Method: Hiller & Lipson, "Dynamic Simulation of Soft Heterogeneous Objects"
+(arXiv 1212.2845), section "Physics Engine".
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvoxsim.so")
+
+VX_OK = 0
+VX_EINVAL = -1
+VX_EDEVICE = -2
+VX_EUNSTABLE = -3
+VX_EOVERFLOW = -4
+VX_ESTATE = -5
+
+KERNEL_FUSED = 0
+KERNEL_SPLIT = 1
+
+EXPORTED = ["vx_create", "vx_workspace_bytes", "vx_bind_workspace", "vx_set_fixed", "vx_set_forces",
+            "vx_fixed_region", "vx_forced_region", "vx_set_actuation", "vx_set_velocity", "vx_step",
+            "vx_read_state", "vx_write_state", "vx_read_flags", "vx_get_dt", "vx_get_time",
+            "vx_counters", "vx_candidates", "vx_set_kernel", "vx_destroy", "vx_last_error"]
+
+
+class VoxsimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("voxsim error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Material(C.Structure):
+    _fields_ = [("E", C.c_double), ("nu", C.c_double), ("rho", C.c_double),
+                ("cte", C.c_double), ("mu_s", C.c_double), ("mu_d", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [("voxel_size", C.c_double), ("gravity", C.c_double),
+                ("zeta_bond", C.c_double), ("zeta_slow", C.c_double), ("zeta_col", C.c_double),
+                ("temp_amp", C.c_double), ("temp_freq", C.c_double), ("temp_phase", C.c_double),
+                ("dt_scale", C.c_double), ("origin", C.c_double * 3),
+                ("floor_on", C.c_int32), ("self_collision_on", C.c_int32),
+                ("contact_cap", C.c_int32), ("reserved", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libvoxsim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libvoxsim.so not found at %s; build it with "
+                          "python -m paper_1212_2845_amd.build" % LIB_PATH)
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    i32, i64, u64 = C.c_int32, C.c_int64, C.c_uint64
+    L.vx_create.argtypes = [P, i32, i32, i32, P, i32, P, i32, P, C.POINTER(P)]
+    L.vx_workspace_bytes.argtypes = [P, C.POINTER(u64)]
+    L.vx_bind_workspace.argtypes = [P, P, u64]
+    L.vx_set_fixed.argtypes = [P, P]
+    L.vx_set_forces.argtypes = [P, P]
+    L.vx_fixed_region.argtypes = [P, P, P]
+    L.vx_forced_region.argtypes = [P, P, P, P]
+    L.vx_set_actuation.argtypes = [P, P, P]
+    L.vx_set_velocity.argtypes = [P, P]
+    L.vx_step.argtypes = [P, i64]
+    L.vx_read_state.argtypes = [P, P, P, P, P]
+    L.vx_write_state.argtypes = [P, P, P, P, P]
+    L.vx_read_flags.argtypes = [P, P, P]
+    L.vx_get_dt.argtypes = [P, C.POINTER(C.c_double)]
+    L.vx_get_time.argtypes = [P, C.POINTER(C.c_double)]
+    L.vx_counters.argtypes = [P, C.POINTER(C.c_int64)]
+    L.vx_candidates.argtypes = [P, P, P, i32, C.POINTER(i32)]
+    L.vx_set_kernel.argtypes = [P, i32]
+    L.vx_destroy.argtypes = [P]
+    L.vx_last_error.argtypes = [P]
+    L.vx_last_error.restype = C.c_char_p
+    for n in EXPORTED:
+        if n != "vx_last_error":
+            getattr(L, n).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def make_palette(materials):
+    arr = (Material * len(materials))()
+    for i, m in enumerate(materials):
+        arr[i] = Material(m.get("E", 1.0), m.get("nu", 0.0), m.get("rho", 1.0), m.get("cte", 0.0),
+                          m.get("mu_s", 0.0), m.get("mu_d", 0.0))
+    return arr
+
+
+def make_params(**kw):
+    p = Params()
+    p.voxel_size = kw.get("voxel_size", 1e-3)
+    p.gravity = kw.get("gravity", 0.0)
+    p.zeta_bond = kw.get("zeta_bond", 0.0)
+    p.zeta_slow = kw.get("zeta_slow", 0.0)
+    p.zeta_col = kw.get("zeta_col", 0.0)
+    p.temp_amp = kw.get("temp_amp", 0.0)
+    p.temp_freq = kw.get("temp_freq", 0.0)
+    p.temp_phase = kw.get("temp_phase", 0.0)
+    p.dt_scale = kw.get("dt_scale", 1.0)
+    o = kw.get("origin", (0.0, 0.0, 0.0))
+    p.origin[0], p.origin[1], p.origin[2] = o
+    p.floor_on = int(kw.get("floor_on", 0))
+    p.self_collision_on = int(kw.get("self_collision_on", 0))
+    p.contact_cap = int(kw.get("contact_cap", 32))
+    p.reserved = 0
+    return p
+
+
+class Sim:
+    """One lattice simulation on the GPU.
+
+    ``grid`` is a uint8 array of shape (nz, ny, nx) (a C-order flatten gives the
+    library's cell order, x fastest); ``materials`` a list of dicts with keys
+    E, nu, rho, cte, mu_s, mu_d (index 0 = empty); ``precision`` 32 or 64.
+    The device workspace is a torch uint8 tensor allocated on first use.
+    """
+
+    def __init__(self, grid, materials, precision=64, device=None, stream=None, kernel=KERNEL_FUSED,
+                 **params):
+        L = lib()
+        g = np.ascontiguousarray(grid, dtype=np.uint8)
+        if g.ndim != 3:
+            raise ValueError("grid must be 3-D (nz, ny, nx)")
+        self.nz, self.ny, self.nx = g.shape
+        self.ncell = g.size
+        self.grid = g
+        self.precision = int(precision)
+        self._pal = make_palette(materials)
+        self._prm = make_params(**params)
+        self._device = device
+        self._stream = stream
+        self._ws = None
+        h = C.c_void_p()
+        rc = L.vx_create(_ptr(g), self.nx, self.ny, self.nz, C.cast(self._pal, C.c_void_p), len(materials),
+                         C.cast(C.pointer(self._prm), C.c_void_p), self.precision, self._stream_ptr(),
+                         C.byref(h))
+        if rc != VX_OK:
+            raise VoxsimError(rc, "vx_create rejected the lattice, palette or parameters")
+        self.h = h
+        self._check(L.vx_set_kernel(self.h, int(kernel)))
+
+    # -- plumbing -----------------------------------------------------------
+    def _stream_ptr(self):
+        if self._stream is not None:
+            return C.c_void_p(int(self._stream))
+        return None
+
+    def _check(self, rc):
+        if rc != VX_OK:
+            raise VoxsimError(rc, lib().vx_last_error(self.h).decode())
+
+    def workspace_bytes(self):
+        n = C.c_uint64()
+        self._check(lib().vx_workspace_bytes(self.h, C.byref(n)))
+        return n.value
+
+    def bind(self):
+        """Allocate the device workspace with torch and bind it."""
+        if self._ws is not None:
+            return
+        import torch
+        dev = self._device or torch.device("cuda", torch.cuda.current_device())
+        nbytes = self.workspace_bytes()
+        self._ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self._check(lib().vx_bind_workspace(self.h, C.c_void_p(self._ws.data_ptr()), nbytes))
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.vx_destroy(h)
+            self.h = None
+
+    # -- setters --------------------------------------------------------------
+    def set_kernel(self, kind):
+        self._check(lib().vx_set_kernel(self.h, int(kind)))
+
+    def set_fixed(self, mask):
+        m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+        assert m.size == self.ncell
+        self._check(lib().vx_set_fixed(self.h, _ptr(m)))
+
+    def set_forces(self, F):
+        f = np.ascontiguousarray(F, dtype=np.float64).reshape(self.ncell, 3)
+        self._check(lib().vx_set_forces(self.h, _ptr(f)))
+
+    def fixed_region(self, loc, size):
+        a = np.asarray(loc, np.float64); b = np.asarray(size, np.float64)
+        self._check(lib().vx_fixed_region(self.h, _ptr(a), _ptr(b)))
+
+    def forced_region(self, loc, size, force):
+        a = np.asarray(loc, np.float64); b = np.asarray(size, np.float64); f = np.asarray(force, np.float64)
+        self._check(lib().vx_forced_region(self.h, _ptr(a), _ptr(b), _ptr(f)))
+
+    def set_actuation(self, amp=None, phase=None):
+        a = None if amp is None else np.ascontiguousarray(amp, dtype=np.float64).reshape(-1)
+        p = None if phase is None else np.ascontiguousarray(phase, dtype=np.float64).reshape(-1)
+        self._check(lib().vx_set_actuation(self.h, _ptr(a), _ptr(p)))
+
+    def set_velocity(self, v):
+        vv = np.ascontiguousarray(v, dtype=np.float64).reshape(self.ncell, 3)
+        self._check(lib().vx_set_velocity(self.h, _ptr(vv)))
+
+    # -- stepping and reading ----------------------------------------------------
+    def step(self, n=1):
+        self.bind()
+        self._check(lib().vx_step(self.h, int(n)))
+
+    def step_rc(self, n=1):
+        """Step and return the status code instead of raising."""
+        self.bind()
+        return lib().vx_step(self.h, int(n))
+
+    @property
+    def dt(self):
+        d = C.c_double()
+        self._check(lib().vx_get_dt(self.h, C.byref(d)))
+        return d.value
+
+    @property
+    def time(self):
+        d = C.c_double()
+        self._check(lib().vx_get_time(self.h, C.byref(d)))
+        return d.value
+
+    def counters(self):
+        out = (C.c_int64 * 4)()
+        self._check(lib().vx_counters(self.h, out))
+        return {"steps": out[0], "rebuilds": out[1], "pairs": out[2], "voxels": out[3]}
+
+    def read_state(self):
+        n = self.ncell
+        u = np.empty((n, 3)); q = np.empty((n, 4)); v = np.empty((n, 3)); w = np.empty((n, 3))
+        self._check(lib().vx_read_state(self.h, _ptr(u), _ptr(q), _ptr(v), _ptr(w)))
+        return {"u": u, "q": q, "v": v, "w": w}
+
+    def write_state(self, u=None, q=None, v=None, w=None):
+        conv = lambda a, k: None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(self.ncell, k)
+        u, q, v, w = conv(u, 3), conv(q, 4), conv(v, 3), conv(w, 3)
+        self._check(lib().vx_write_state(self.h, _ptr(u), _ptr(q), _ptr(v), _ptr(w)))
+
+    def read_flags(self):
+        st = np.empty(self.ncell, np.uint8); su = np.empty(self.ncell, np.uint8)
+        self._check(lib().vx_read_flags(self.h, _ptr(st), _ptr(su)))
+        return {"static": st, "surface": su}
+
+    def candidates(self):
+        n = C.c_int32()
+        self._check(lib().vx_candidates(self.h, None, None, 0, C.byref(n)))
+        k = n.value
+        a = np.empty(max(k, 1), np.int32); b = np.empty(max(k, 1), np.int32)
+        self._check(lib().vx_candidates(self.h, _ptr(a), _ptr(b), k, C.byref(n)))
+        return set(zip(a[:k].tolist(), b[:k].tolist()))
+
+
+def from_workload(w, precision=64, kernel=KERNEL_FUSED, stream=None):
+    """Build a Sim from a workload dict of the seeded input generators."""
+    s = Sim(w["grid"], w["materials"], precision=precision, kernel=kernel, stream=stream, **w["params"])
+    if w.get("fixed") is not None:
+        s.set_fixed(w["fixed"])
+    if w.get("forces") is not None:
+        s.set_forces(w["forces"])
+    if w.get("amp") is not None or w.get("phase") is not None:
+        s.set_actuation(w.get("amp"), w.get("phase"))
+    if w.get("velocity") is not None:
+        s.set_velocity(w["velocity"])
+    return s

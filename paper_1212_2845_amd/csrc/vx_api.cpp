@@ -1,0 +1,711 @@
+// Host side of the voxsim C ABI: validation, packing of the material grid
+// into per-voxel and per-material-pair tables, timestep selection, the
+// workspace carve-out and the step loop.  Device work is in the .hip files.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/voxsim.h"
+#include "vx_launch.hpp"
+#include "vx_types.hpp"
+
+using namespace vx;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr uint64_t kAlign = 256;
+
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    uint64_t state[2], mat, flags, mats, pairs, bonds, act_amp, act_phase, forced_cells, forced_F;
+    uint64_t contact_F, surf_cells, cand, cand_n, keys, sorted, bstart, bfill, scalars, scan_tmp;
+    uint64_t total;
+};
+
+// Small device-side scalars, one 256-byte block.
+struct Scalars {
+    unsigned err_flag;
+    unsigned overflow;
+    unsigned rebuild_flag;
+    unsigned pad0;
+    unsigned long long vmax_bits;
+    double macc;
+    unsigned long long pair_count;
+    unsigned long long rebuilds;
+};
+
+}  // namespace
+
+struct vx_sim {
+    int nx = 0, ny = 0, nz = 0;
+    long long ncell = 0;
+    vx_params p{};
+    int precision = 64;
+    size_t tsize = 8;
+    hipStream_t stream = nullptr;
+    int n_mat = 0;
+    std::vector<vx_material> pal;
+    std::vector<uint8_t> grid, flags;
+    std::vector<double> amp, phase;      // per cell; valid where FLAG_ACT
+    bool has_act = false;
+    std::vector<double> force;           // ncell x 3 (host copy)
+    std::vector<int> forced_cells;
+    std::vector<double> forced_F;
+    int forced_cap = 0;
+    std::vector<int> surf_cells;
+    long long nvox = 0;
+    double dt = 0.0;
+    long long step = 0;
+    int kernel_kind = 0;
+    int cand_cap = 32;
+    int table_size = 1;
+    size_t scan_tmp_bytes = 0;
+    double cmax = 0.0;
+    // initial state in double, 13 x ncell (used until bind)
+    std::vector<double> state0;
+    // device
+    bool bound = false;
+    char *ws = nullptr;
+    Layout L{};
+    int cur = 0;                          // which state buffer holds state n
+    std::string err;
+};
+
+static int fail(vx_sim *h, int code, const std::string &msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+#define HIP_OK(h, call)                                                        \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess)                                                  \
+            return fail(h, VX_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// packing
+// ---------------------------------------------------------------------------
+static double composite(double a, double b) { return 2.0 * a * b / (a + b); }
+
+template <typename T>
+static void pack_tables(const vx_sim *h, std::vector<MatConst<T>> &mc, std::vector<PairConst<T>> &pc) {
+    const double l = h->p.voxel_size;
+    mc.assign(h->n_mat, MatConst<T>{});
+    for (int i = 1; i < h->n_mat; ++i) {
+        const vx_material &M = h->pal[i];
+        const double m = M.rho * l * l * l;
+        const double I = m * l * l / 6.0;           // solid cube about its centre
+        const double kv = M.E * l;
+        const double kphi = M.E * l * l * l / 6.0;
+        MatConst<T> &c = mc[i];
+        c.m = (T)m; c.inv_m = (T)(1.0 / m); c.I = (T)I; c.inv_I = (T)(1.0 / I);
+        c.cg = (T)(2.0 * h->p.zeta_slow * std::sqrt(m * kv));
+        c.cgr = (T)(2.0 * h->p.zeta_slow * std::sqrt(I * kphi));
+        c.cfloor = (T)(2.0 * h->p.zeta_col * std::sqrt(m * kv));
+        c.kv = (T)kv; c.cte = (T)M.cte; c.mu_s = (T)M.mu_s; c.mu_d = (T)M.mu_d; c.E = (T)M.E;
+    }
+    pc.assign((size_t)h->n_mat * h->n_mat, PairConst<T>{});
+    for (int i = 1; i < h->n_mat; ++i)
+        for (int j = 1; j < h->n_mat; ++j) {
+            const vx_material &A = h->pal[i], &B = h->pal[j];
+            const double Ec = composite(A.E, B.E);
+            const double Gc = composite(A.E / (2.0 * (1.0 + A.nu)), B.E / (2.0 * (1.0 + B.nu)));
+            const double Is = l * l * l * l / 12.0, J = l * l * l * l / 6.0;
+            const double a1 = Ec * l * l / l, a2 = Gc * J / l;
+            const double b1 = 12.0 * Ec * Is / (l * l * l), b2 = 6.0 * Ec * Is / (l * l);
+            const double b3 = 2.0 * Ec * Is / l;
+            const double ma = A.rho * l * l * l, mb = B.rho * l * l * l;
+            const double mmin = std::min(ma, mb);
+            const double Imin = mmin * l * l / 6.0;
+            PairConst<T> &c = pc[(size_t)i * h->n_mat + j];
+            c.a1 = (T)a1; c.a2 = (T)a2; c.b1 = (T)b1; c.b2 = (T)b2; c.b3 = (T)b3;
+            c.ct = (T)(2.0 * h->p.zeta_bond * std::sqrt(mmin * a1));
+            c.cr = (T)(2.0 * h->p.zeta_bond * std::sqrt(Imin * b3));
+            c.kc = (T)(Ec * l);
+            c.cc = (T)(2.0 * h->p.zeta_col * std::sqrt(mmin * Ec * l));
+        }
+}
+
+static long long cell_of(const vx_sim *h, int x, int y, int z) {
+    return (long long)x + (long long)h->nx * ((long long)y + (long long)h->ny * z);
+}
+
+static void compute_layout(vx_sim *h) {
+    const uint64_t n = (uint64_t)h->ncell, ts = h->tsize;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) { uint64_t o = off; off = align_up(off + std::max<uint64_t>(bytes, 1)); return o; };
+    Layout &L = h->L;
+    L.state[0] = take(N_WORDS * n * ts);
+    L.state[1] = take(N_WORDS * n * ts);
+    L.mat = take(n);
+    L.flags = take(n);
+    L.mats = take((uint64_t)h->n_mat * (h->precision == 64 ? sizeof(MatConst<double>) : sizeof(MatConst<float>)));
+    L.pairs = take((uint64_t)h->n_mat * h->n_mat *
+                   (h->precision == 64 ? sizeof(PairConst<double>) : sizeof(PairConst<float>)));
+    L.bonds = take(27 * n * ts);
+    L.act_amp = take(n * ts);
+    L.act_phase = take(n * ts);
+    h->forced_cap = std::max<int>((int)h->forced_cells.size(), 1024);
+    L.forced_cells = take((uint64_t)h->forced_cap * 4);
+    L.forced_F = take((uint64_t)h->forced_cap * 3 * ts);
+    const bool col = h->p.self_collision_on != 0;
+    const uint64_t ns = col ? h->surf_cells.size() : 0;
+    L.contact_F = take(col ? 3 * n * ts : 0);
+    L.surf_cells = take(ns * 4);
+    L.cand = take(ns * (uint64_t)h->cand_cap * 4);
+    L.cand_n = take(ns * 4);
+    L.keys = take(ns * 4);
+    L.sorted = take(ns * 4);
+    L.bstart = take(col ? ((uint64_t)h->table_size + 1) * 4 : 0);
+    L.bfill = take(col ? (uint64_t)h->table_size * 4 : 0);
+    L.scalars = take(sizeof(Scalars));
+    L.scan_tmp = take(col ? h->scan_tmp_bytes : 0);
+    L.total = off;
+}
+
+template <typename T>
+static StepArgs<T> make_args(vx_sim *h) {
+    StepArgs<T> a{};
+    char *ws = h->ws;
+    a.s_in = (const T *)(ws + h->L.state[h->cur]);
+    a.s_out = (T *)(ws + h->L.state[1 - h->cur]);
+    a.stride = h->ncell;
+    a.mat = (const uint8_t *)(ws + h->L.mat);
+    a.flags = (uint8_t *)(ws + h->L.flags);
+    a.mats = (const MatConst<T> *)(ws + h->L.mats);
+    a.pairs = (const PairConst<T> *)(ws + h->L.pairs);
+    a.n_mat = h->n_mat;
+    a.nx = h->nx; a.ny = h->ny; a.nz = h->nz;
+    a.l = (T)h->p.voxel_size;
+    a.dt = (T)h->dt;
+    a.gravity = (T)h->p.gravity;
+    a.origin_z = (T)h->p.origin[2];
+    for (int k = 0; k < 3; ++k) a.origin[k] = h->p.origin[k];
+    const double tn = (double)h->step * h->dt;
+    const double wt = 2.0 * kPi * h->p.temp_freq * tn;
+    a.wt = wt;
+    a.dT_global = (T)(h->p.temp_amp * std::sin(wt + h->p.temp_phase));
+    a.act_amp = (const T *)(ws + h->L.act_amp);
+    a.act_phase = (const T *)(ws + h->L.act_phase);
+    a.forced_cells = (const int *)(ws + h->L.forced_cells);
+    a.forced_F = (const T *)(ws + h->L.forced_F);
+    a.n_forced = (int)h->forced_cells.size();
+    a.floor_on = h->p.floor_on;
+    a.track_vmax = h->p.self_collision_on;
+    a.contact_F = (const T *)(ws + h->L.contact_F);
+    a.bonds = (T *)(ws + h->L.bonds);
+    Scalars *sc = (Scalars *)(ws + h->L.scalars);
+    a.err_flag = &sc->err_flag;
+    a.vmax_bits = &sc->vmax_bits;
+    return a;
+}
+
+static CollideArgs make_collide(vx_sim *h) {
+    CollideArgs c{};
+    char *ws = h->ws;
+    c.surf_cells = (const int *)(ws + h->L.surf_cells);
+    c.n_surf = (int)h->surf_cells.size();
+    c.cap = h->cand_cap;
+    c.cand = (int *)(ws + h->L.cand);
+    c.cand_n = (int *)(ws + h->L.cand_n);
+    Scalars *sc = (Scalars *)(ws + h->L.scalars);
+    c.overflow = &sc->overflow;
+    c.rebuild_flag = &sc->rebuild_flag;
+    c.macc = &sc->macc;
+    c.vmax_bits = &sc->vmax_bits;
+    c.cell_keys = (int *)(ws + h->L.keys);
+    c.sorted_idx = (int *)(ws + h->L.sorted);
+    c.bucket_start = (int *)(ws + h->L.bstart);
+    c.bucket_fill = (int *)(ws + h->L.bfill);
+    c.table_size = h->table_size;
+    c.pair_count = &sc->pair_count;
+    c.horizon = 2.0 * h->p.voxel_size;
+    c.threshold = 2.0 * h->p.voxel_size - h->cmax;
+    c.scan_tmp = (void *)(ws + h->L.scan_tmp);
+    c.scan_tmp_bytes = h->scan_tmp_bytes;
+    c.rebuild_counter = &sc->rebuilds;
+    return c;
+}
+
+// Upload the per-voxel, per-material and region data (not the state).
+template <typename T>
+static int upload_static(vx_sim *h) {
+    std::vector<MatConst<T>> mc;
+    std::vector<PairConst<T>> pc;
+    pack_tables<T>(h, mc, pc);
+    char *ws = h->ws;
+    hipStream_t s = h->stream;
+    HIP_OK(h, hipMemcpyAsync(ws + h->L.mat, h->grid.data(), h->ncell, hipMemcpyHostToDevice, s));
+    HIP_OK(h, hipMemcpyAsync(ws + h->L.flags, h->flags.data(), h->ncell, hipMemcpyHostToDevice, s));
+    HIP_OK(h, hipMemcpyAsync(ws + h->L.mats, mc.data(), mc.size() * sizeof(MatConst<T>), hipMemcpyHostToDevice, s));
+    HIP_OK(h, hipMemcpyAsync(ws + h->L.pairs, pc.data(), pc.size() * sizeof(PairConst<T>), hipMemcpyHostToDevice, s));
+    std::vector<T> a(h->ncell), ph(h->ncell);
+    if (h->has_act)
+        for (long long c = 0; c < h->ncell; ++c) { a[c] = (T)h->amp[c]; ph[c] = (T)h->phase[c]; }
+    HIP_OK(h, hipMemcpyAsync(ws + h->L.act_amp, a.data(), h->ncell * sizeof(T), hipMemcpyHostToDevice, s));
+    HIP_OK(h, hipMemcpyAsync(ws + h->L.act_phase, ph.data(), h->ncell * sizeof(T), hipMemcpyHostToDevice, s));
+    if ((int)h->forced_cells.size() > h->forced_cap)
+        return fail(h, VX_ESTATE, "more forced voxels than the workspace was sized for; set forces before the first step");
+    std::vector<T> ff(h->forced_F.size());
+    for (size_t i = 0; i < ff.size(); ++i) ff[i] = (T)h->forced_F[i];
+    if (!h->forced_cells.empty()) {
+        HIP_OK(h, hipMemcpyAsync(ws + h->L.forced_cells, h->forced_cells.data(), h->forced_cells.size() * 4, hipMemcpyHostToDevice, s));
+        HIP_OK(h, hipMemcpyAsync(ws + h->L.forced_F, ff.data(), ff.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    HIP_OK(h, hipStreamSynchronize(s));
+    return VX_OK;
+}
+
+template <typename T>
+static int upload_state(vx_sim *h, const std::vector<double> &st) {
+    std::vector<T> buf(st.size());
+    for (size_t i = 0; i < st.size(); ++i) buf[i] = (T)st[i];
+    HIP_OK(h, hipMemcpyAsync(h->ws + h->L.state[h->cur], buf.data(), buf.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
+    // the other buffer gets the same contents so that empty cells are defined
+    HIP_OK(h, hipMemcpyAsync(h->ws + h->L.state[1 - h->cur], buf.data(), buf.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    return VX_OK;
+}
+
+template <typename T>
+static int download_state(vx_sim *h, std::vector<double> &st) {
+    std::vector<T> buf((size_t)N_WORDS * h->ncell);
+    HIP_OK(h, hipMemcpyAsync(buf.data(), h->ws + h->L.state[h->cur], buf.size() * sizeof(T), hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    st.resize(buf.size());
+    for (size_t i = 0; i < buf.size(); ++i) st[i] = (double)buf[i];
+    return VX_OK;
+}
+
+static int get_state(vx_sim *h, std::vector<double> &st) {
+    if (!h->bound) { st = h->state0; return VX_OK; }
+    return h->precision == 64 ? download_state<double>(h, st) : download_state<float>(h, st);
+}
+
+static int put_state(vx_sim *h, const std::vector<double> &st) {
+    if (!h->bound) { h->state0 = st; return VX_OK; }
+    return h->precision == 64 ? upload_state<double>(h, st) : upload_state<float>(h, st);
+}
+
+static int reupload_static(vx_sim *h) {
+    if (!h->bound) return VX_OK;
+    return h->precision == 64 ? upload_static<double>(h) : upload_static<float>(h);
+}
+
+static double mass_of(const vx_sim *h, int m) {
+    const double l = h->p.voxel_size;
+    return h->pal[m].rho * l * l * l;
+}
+
+static void update_cmax(vx_sim *h) {
+    const double l = h->p.voxel_size;
+    double cmax = l;
+    for (long long c = 0; c < h->ncell; ++c) {
+        const int m = h->grid[c];
+        if (!m) continue;
+        const double a = (h->flags[c] & FLAG_ACT) ? h->amp[c] : h->p.temp_amp;
+        cmax = std::max(cmax, l * (1.0 + std::fabs(h->pal[m].cte * a)));
+    }
+    h->cmax = cmax;
+}
+
+template <typename T>
+static int request_rebuild(vx_sim *h) {
+    if (!h->bound || !h->p.self_collision_on) return VX_OK;
+    const unsigned one = 1;
+    Scalars *sc = (Scalars *)(h->ws + h->L.scalars);
+    HIP_OK(h, hipMemcpyAsync(&sc->rebuild_flag, &one, sizeof(one), hipMemcpyHostToDevice, h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    return VX_OK;
+}
+
+template <typename T>
+static int run_steps(vx_sim *h, int64_t n) {
+    const bool col = h->p.self_collision_on != 0;
+    for (int64_t i = 0; i < n; ++i) {
+        StepArgs<T> a = make_args<T>(h);
+        if (col) {
+            CollideArgs c = make_collide(h);
+            HIP_OK(h, launch_rebuild<T>(a, c, h->stream));
+            HIP_OK(h, launch_contact<T>(a, c, (T *)(h->ws + h->L.contact_F), h->stream));
+        }
+        if (h->kernel_kind == 1) {
+            HIP_OK(h, launch_split_step<T>(a, h->stream));
+        } else {
+            HIP_OK(h, launch_fused_step<T>(a, h->stream));
+        }
+        if (col) {
+            CollideArgs c = make_collide(h);
+            HIP_OK(h, launch_motion_update<T>(a, c, h->stream));
+        }
+        h->cur = 1 - h->cur;
+        h->step++;
+    }
+    Scalars sc;
+    HIP_OK(h, hipMemcpyAsync(&sc, h->ws + h->L.scalars, sizeof(sc), hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    if (sc.err_flag) return fail(h, VX_EUNSTABLE, "non-finite value in the voxel state");
+    if (sc.overflow) return fail(h, VX_EOVERFLOW, "collision candidate list overflow (raise contact_cap)");
+    return VX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int vx_create(const uint8_t *grid, int32_t nx, int32_t ny, int32_t nz, const vx_material *palette,
+              int32_t n_mat, const vx_params *params, int32_t precision, void *stream, vx_handle *out) {
+    if (!out) return VX_EINVAL;
+    *out = nullptr;
+    if (!grid || !palette || !params || nx <= 0 || ny <= 0 || nz <= 0 || n_mat < 1 || n_mat > 256)
+        return VX_EINVAL;
+    if (precision != 32 && precision != 64) return VX_EINVAL;
+    const long long ncell = (long long)nx * ny * nz;
+    if (ncell > (1LL << 31) / 16) return VX_EINVAL;
+    const vx_params &p = *params;
+    if (!(p.voxel_size > 0.0) || !(p.gravity >= 0.0) || !(p.zeta_bond >= 0.0) || !(p.zeta_slow >= 0.0) ||
+        !(p.zeta_col >= 0.0) || !(p.dt_scale >= 0.0) || p.dt_scale > 1.0 || p.contact_cap < 0 || p.reserved != 0)
+        return VX_EINVAL;
+    for (int i = 1; i < n_mat; ++i) {
+        const vx_material &m = palette[i];
+        if (!(m.E > 0.0) || !(m.rho > 0.0) || !(m.nu > -1.0 && m.nu < 0.5) || !(m.mu_s >= 0.0) || !(m.mu_d >= 0.0) ||
+            !std::isfinite(m.cte))
+            return VX_EINVAL;
+    }
+    for (long long c = 0; c < ncell; ++c)
+        if (grid[c] >= n_mat) return VX_EINVAL;
+    vx_sim *h = new vx_sim();
+    h->nx = nx; h->ny = ny; h->nz = nz; h->ncell = ncell;
+    h->p = p;
+    if (h->p.dt_scale == 0.0) h->p.dt_scale = 1.0;
+    h->precision = precision;
+    h->tsize = precision == 64 ? 8 : 4;
+    h->stream = (hipStream_t)stream;
+    h->n_mat = n_mat;
+    h->pal.assign(palette, palette + n_mat);
+    h->grid.assign(grid, grid + ncell);
+    h->flags.assign(ncell, 0);
+    h->amp.assign(ncell, 0.0);
+    h->phase.assign(ncell, 0.0);
+    h->force.assign(3 * ncell, 0.0);
+    h->cand_cap = p.contact_cap > 0 ? p.contact_cap : 32;
+    const double l = p.voxel_size;
+    // stable timestep over bonded pairs: dt = 1 / (2 pi max sqrt(k_b / m_min))
+    std::vector<char> pair_seen((size_t)n_mat * n_mat, 0);
+    long long nvox = 0;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const long long c = cell_of(h, x, y, z);
+                const int m = grid[c];
+                if (!m) continue;
+                ++nvox;
+                bool surf = false;
+                const int idx[3] = {x, y, z}, dim[3] = {nx, ny, nz};
+                const long long stp[3] = {1, nx, (long long)nx * ny};
+                for (int a = 0; a < 3; ++a) {
+                    if (idx[a] == 0 || grid[c - stp[a]] == 0) surf = true;
+                    if (idx[a] + 1 >= dim[a] || grid[c + stp[a]] == 0) surf = true;
+                    if (idx[a] + 1 < dim[a] && grid[c + stp[a]] != 0)
+                        pair_seen[(size_t)m * n_mat + grid[c + stp[a]]] = 1;
+                }
+                if (surf) { h->flags[c] |= FLAG_SURFACE; h->surf_cells.push_back((int)c); }
+            }
+    h->nvox = nvox;
+    double wmax = 0.0;
+    bool any_bond = false;
+    for (int i = 1; i < n_mat; ++i)
+        for (int j = 1; j < n_mat; ++j) {
+            if (!pair_seen[(size_t)i * n_mat + j]) continue;
+            any_bond = true;
+            const double kb = composite(palette[i].E, palette[j].E) * l;
+            const double mmin = std::min(palette[i].rho, palette[j].rho) * l * l * l;
+            wmax = std::max(wmax, std::sqrt(kb / mmin));
+        }
+    if (!any_bond)
+        for (long long c = 0; c < ncell; ++c)
+            if (grid[c]) wmax = std::max(wmax, std::sqrt(palette[grid[c]].E * l / (palette[grid[c]].rho * l * l * l)));
+    h->dt = wmax > 0.0 ? h->p.dt_scale / (2.0 * kPi * wmax) : 0.0;
+    // rest state
+    h->state0.assign((size_t)N_WORDS * ncell, 0.0);
+    for (long long c = 0; c < ncell; ++c) h->state0[W_QW * ncell + c] = 1.0;
+    // collision hash table: power of two >= 2 x surface count
+    int ts = 1;
+    while (ts < 2 * (int)std::max<size_t>(h->surf_cells.size(), 1)) ts <<= 1;
+    h->table_size = ts;
+    h->scan_tmp_bytes = p.self_collision_on ? scan_temp_bytes(ts + 1) : 0;
+    update_cmax(h);
+    *out = h;
+    return VX_OK;
+}
+
+int vx_workspace_bytes(vx_handle h, uint64_t *bytes) {
+    if (!h || !bytes) return VX_EINVAL;
+    compute_layout(h);
+    *bytes = h->L.total;
+    return VX_OK;
+}
+
+int vx_bind_workspace(vx_handle h, void *device_ptr, uint64_t bytes) {
+    if (!h) return VX_EINVAL;
+    if (h->bound) return fail(h, VX_ESTATE, "workspace already bound");
+    compute_layout(h);
+    if (!device_ptr || bytes < h->L.total) return fail(h, VX_EINVAL, "workspace too small");
+    if (((uintptr_t)device_ptr) % kAlign) return fail(h, VX_EINVAL, "workspace not 256-byte aligned");
+    h->ws = (char *)device_ptr;
+    h->bound = true;
+    h->cur = 0;
+    int r = reupload_static(h);
+    if (r != VX_OK) { h->bound = false; return r; }
+    Scalars sc{};
+    sc.rebuild_flag = h->p.self_collision_on ? 1u : 0u;
+    HIP_OK(h, hipMemcpyAsync(h->ws + h->L.scalars, &sc, sizeof(sc), hipMemcpyHostToDevice, h->stream));
+    if (h->p.self_collision_on) {
+        HIP_OK(h, hipMemcpyAsync(h->ws + h->L.surf_cells, h->surf_cells.data(), h->surf_cells.size() * 4,
+                                 hipMemcpyHostToDevice, h->stream));
+        std::vector<int> zeros(h->surf_cells.size(), 0);
+        HIP_OK(h, hipMemcpyAsync(h->ws + h->L.cand_n, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice, h->stream));
+        std::vector<int> zt(h->table_size, 0);
+        HIP_OK(h, hipMemcpyAsync(h->ws + h->L.bfill, zt.data(), zt.size() * 4, hipMemcpyHostToDevice, h->stream));
+    }
+    r = put_state(h, h->state0);
+    if (r != VX_OK) { h->bound = false; return r; }
+    return VX_OK;
+}
+
+int vx_set_fixed(vx_handle h, const uint8_t *mask) {
+    if (!h || !mask) return VX_EINVAL;
+    std::vector<double> st;
+    int r = get_state(h, st);
+    if (r) return r;
+    for (long long c = 0; c < h->ncell; ++c) {
+        if (!h->grid[c]) continue;
+        if (mask[c]) {
+            h->flags[c] |= FLAG_FIXED;
+            for (int w = W_PX; w <= W_LZ; ++w) st[(size_t)w * h->ncell + c] = 0.0;
+        } else {
+            h->flags[c] &= (uint8_t)~FLAG_FIXED;
+        }
+    }
+    r = put_state(h, st);
+    if (r) return r;
+    return reupload_static(h);
+}
+
+static int apply_forces(vx_sim *h) {
+    h->forced_cells.clear();
+    h->forced_F.clear();
+    for (long long c = 0; c < h->ncell; ++c) {
+        h->flags[c] &= (uint8_t)~FLAG_FORCED;
+        if (!h->grid[c]) continue;
+        const double *f = &h->force[3 * c];
+        if (f[0] != 0.0 || f[1] != 0.0 || f[2] != 0.0) {
+            h->flags[c] |= FLAG_FORCED;
+            h->forced_cells.push_back((int)c);
+            h->forced_F.insert(h->forced_F.end(), f, f + 3);
+        }
+    }
+    return reupload_static(h);
+}
+
+int vx_set_forces(vx_handle h, const double *force) {
+    if (!h || !force) return VX_EINVAL;
+    for (long long i = 0; i < 3 * h->ncell; ++i)
+        if (!std::isfinite(force[i])) return fail(h, VX_EINVAL, "non-finite force");
+    h->force.assign(force, force + 3 * h->ncell);
+    return apply_forces(h);
+}
+
+// A voxel touches the box [lo, hi) (fractions of the workspace) when its
+// cube [i/n, (i+1)/n) overlaps it with positive length on every axis.
+static bool touches(const vx_sim *h, long long c, const double *loc, const double *size) {
+    const int idx[3] = {(int)(c % h->nx), (int)((c / h->nx) % h->ny), (int)(c / ((long long)h->nx * h->ny))};
+    const int dim[3] = {h->nx, h->ny, h->nz};
+    for (int a = 0; a < 3; ++a) {
+        const double lo = (double)idx[a] / dim[a], hi = (double)(idx[a] + 1) / dim[a];
+        if (!(lo < loc[a] + size[a] && hi > loc[a])) return false;
+    }
+    return true;
+}
+
+int vx_fixed_region(vx_handle h, const double loc[3], const double size[3]) {
+    if (!h || !loc || !size) return VX_EINVAL;
+    std::vector<uint8_t> mask(h->ncell, 0);
+    for (long long c = 0; c < h->ncell; ++c)
+        mask[c] = (h->grid[c] && ((h->flags[c] & FLAG_FIXED) || touches(h, c, loc, size))) ? 1 : 0;
+    return vx_set_fixed(h, mask.data());
+}
+
+int vx_forced_region(vx_handle h, const double loc[3], const double size[3], const double force[3]) {
+    if (!h || !loc || !size || !force) return VX_EINVAL;
+    std::vector<long long> sel;
+    for (long long c = 0; c < h->ncell; ++c)
+        if (h->grid[c] && touches(h, c, loc, size)) sel.push_back(c);
+    if (sel.empty()) return VX_OK;
+    for (long long c : sel)
+        for (int k = 0; k < 3; ++k) h->force[3 * c + k] = force[k] / (double)sel.size();
+    return apply_forces(h);
+}
+
+int vx_set_actuation(vx_handle h, const double *amp, const double *phase) {
+    if (!h) return VX_EINVAL;
+    h->has_act = amp || phase;
+    for (long long c = 0; c < h->ncell; ++c) {
+        h->amp[c] = amp ? amp[c] : h->p.temp_amp;
+        h->phase[c] = phase ? phase[c] : h->p.temp_phase;
+        if (h->has_act && h->grid[c]) h->flags[c] |= FLAG_ACT; else h->flags[c] &= (uint8_t)~FLAG_ACT;
+    }
+    update_cmax(h);
+    return reupload_static(h);
+}
+
+int vx_set_velocity(vx_handle h, const double *velocity) {
+    if (!h || !velocity) return VX_EINVAL;
+    std::vector<double> st;
+    int r = get_state(h, st);
+    if (r) return r;
+    for (long long c = 0; c < h->ncell; ++c) {
+        if (!h->grid[c] || (h->flags[c] & FLAG_FIXED)) continue;
+        const double m = mass_of(h, h->grid[c]);
+        for (int k = 0; k < 3; ++k) st[(size_t)(W_PX + k) * h->ncell + c] = m * velocity[3 * c + k];
+    }
+    return put_state(h, st);
+}
+
+int vx_step(vx_handle h, int64_t n) {
+    if (!h || n < 0) return VX_EINVAL;
+    if (!h->bound) return fail(h, VX_ESTATE, "vx_step before vx_bind_workspace");
+    if (n == 0) return VX_OK;
+    return h->precision == 64 ? run_steps<double>(h, n) : run_steps<float>(h, n);
+}
+
+int vx_read_state(vx_handle h, double *u, double *q, double *vel, double *omega) {
+    if (!h) return VX_EINVAL;
+    std::vector<double> st;
+    int r = get_state(h, st);
+    if (r) return r;
+    const long long n = h->ncell;
+    const double l = h->p.voxel_size;
+    for (long long c = 0; c < n; ++c) {
+        const int m = h->grid[c];
+        const double mass = m ? mass_of(h, m) : 1.0;
+        const double I = mass * l * l / 6.0;
+        for (int k = 0; k < 3; ++k) {
+            if (u) u[3 * c + k] = m ? st[(size_t)(W_UX + k) * n + c] : 0.0;
+            if (vel) vel[3 * c + k] = m ? st[(size_t)(W_PX + k) * n + c] / mass : 0.0;
+            if (omega) omega[3 * c + k] = m ? st[(size_t)(W_LX + k) * n + c] / I : 0.0;
+        }
+        if (q)
+            for (int k = 0; k < 4; ++k) q[4 * c + k] = m ? st[(size_t)(W_QW + k) * n + c] : (k == 0 ? 1.0 : 0.0);
+    }
+    return VX_OK;
+}
+
+int vx_write_state(vx_handle h, const double *u, const double *q, const double *vel, const double *omega) {
+    if (!h) return VX_EINVAL;
+    std::vector<double> st;
+    int r = get_state(h, st);
+    if (r) return r;
+    const long long n = h->ncell;
+    const double l = h->p.voxel_size;
+    for (long long c = 0; c < n; ++c) {
+        const int m = h->grid[c];
+        if (!m) continue;
+        const double mass = mass_of(h, m), I = mass * l * l / 6.0;
+        for (int k = 0; k < 3; ++k) {
+            if (u) st[(size_t)(W_UX + k) * n + c] = u[3 * c + k];
+            if (vel) st[(size_t)(W_PX + k) * n + c] = mass * vel[3 * c + k];
+            if (omega) st[(size_t)(W_LX + k) * n + c] = I * omega[3 * c + k];
+        }
+        if (q)
+            for (int k = 0; k < 4; ++k) st[(size_t)(W_QW + k) * n + c] = q[4 * c + k];
+    }
+    r = put_state(h, st);
+    if (r) return r;
+    return h->precision == 64 ? request_rebuild<double>(h) : request_rebuild<float>(h);
+}
+
+int vx_read_flags(vx_handle h, uint8_t *is_static, uint8_t *surface) {
+    if (!h) return VX_EINVAL;
+    std::vector<uint8_t> fl(h->flags);
+    if (h->bound) {
+        HIP_OK(h, hipMemcpyAsync(fl.data(), h->ws + h->L.flags, h->ncell, hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(h, hipStreamSynchronize(h->stream));
+    }
+    for (long long c = 0; c < h->ncell; ++c) {
+        if (is_static) is_static[c] = (fl[c] & FLAG_STATIC) ? 1 : 0;
+        if (surface) surface[c] = (fl[c] & FLAG_SURFACE) ? 1 : 0;
+    }
+    return VX_OK;
+}
+
+int vx_get_dt(vx_handle h, double *dt) {
+    if (!h || !dt) return VX_EINVAL;
+    *dt = h->dt;
+    return VX_OK;
+}
+
+int vx_get_time(vx_handle h, double *t) {
+    if (!h || !t) return VX_EINVAL;
+    *t = (double)h->step * h->dt;
+    return VX_OK;
+}
+
+int vx_counters(vx_handle h, int64_t out[4]) {
+    if (!h || !out) return VX_EINVAL;
+    Scalars sc{};
+    if (h->bound) {
+        HIP_OK(h, hipMemcpyAsync(&sc, h->ws + h->L.scalars, sizeof(sc), hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(h, hipStreamSynchronize(h->stream));
+    }
+    out[0] = h->step;
+    out[1] = (int64_t)sc.rebuilds;
+    out[2] = (int64_t)sc.pair_count / 2;
+    out[3] = h->nvox;
+    return VX_OK;
+}
+
+int vx_candidates(vx_handle h, int32_t *cell_a, int32_t *cell_b, int32_t max_pairs, int32_t *n_pairs) {
+    if (!h || !n_pairs || max_pairs < 0) return VX_EINVAL;
+    *n_pairs = 0;
+    if (!h->bound || !h->p.self_collision_on) return VX_OK;
+    const size_t ns = h->surf_cells.size();
+    std::vector<int> cand(ns * h->cand_cap), cn(ns);
+    HIP_OK(h, hipMemcpyAsync(cand.data(), h->ws + h->L.cand, cand.size() * 4, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(h, hipMemcpyAsync(cn.data(), h->ws + h->L.cand_n, cn.size() * 4, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    int32_t k = 0;
+    for (size_t i = 0; i < ns; ++i)
+        for (int j = 0; j < cn[i]; ++j) {
+            const int other = cand[i * h->cand_cap + j];
+            if (other <= h->surf_cells[i]) continue;
+            if (k < max_pairs && cell_a && cell_b) { cell_a[k] = h->surf_cells[i]; cell_b[k] = other; }
+            ++k;
+        }
+    *n_pairs = k;
+    return VX_OK;
+}
+
+int vx_set_kernel(vx_handle h, int32_t kind) {
+    if (!h || (kind != 0 && kind != 1)) return VX_EINVAL;
+    h->kernel_kind = kind;
+    return VX_OK;
+}
+
+int vx_destroy(vx_handle h) {
+    delete h;
+    return VX_OK;
+}
+
+const char *vx_last_error(vx_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+}  // extern "C"

@@ -1,0 +1,308 @@
+// Self-collision (section "Self collision detection and handling"):
+// surface voxels only, a candidate list of pairs inside the collision
+// horizon (centre distance < 2 l) excluding lattice neighbours within
+// Manhattan distance 3, rebuilt only when the accumulated maximum motion
+// could let an unlisted pair touch, and a per-step contact force from each
+// voxel's own sorted list (every pair is evaluated from both sides, so no
+// atomics touch the forces).
+//
+// Candidate search is a uniform grid of cell size = horizon, hashed into a
+// power-of-two table and bucketed by a counting sort (count, scan,
+// scatter).  Bucket order is not deterministic; each voxel's list is kept
+// sorted by partner cell, so the lists themselves are.
+#include "vx_device.hpp"
+#include "vx_launch.hpp"
+
+namespace vx {
+
+namespace {
+
+constexpr int kScanBlock = 1024;   // entries per scan block (256 threads x 4)
+
+__device__ __forceinline__ int cell_hash(int cx, int cy, int cz, int mask) {
+    const unsigned h = ((unsigned)cx * 73856093u) ^ ((unsigned)cy * 19349663u) ^ ((unsigned)cz * 83492791u);
+    return (int)(h & (unsigned)mask);
+}
+
+template <typename T>
+__device__ __forceinline__ void voxel_pos(const StepArgs<T> &a, int c, int &ix, int &iy, int &iz, T &x, T &y,
+                                          T &z, const T *origin) {
+    ix = c % a.nx;
+    iy = (c / a.nx) % a.ny;
+    iz = c / (a.nx * a.ny);
+    x = origin[0] + (T(ix) + T(0.5)) * a.l + a.s_in[W_UX * a.stride + c];
+    y = origin[1] + (T(iy) + T(0.5)) * a.l + a.s_in[W_UY * a.stride + c];
+    z = origin[2] + (T(iz) + T(0.5)) * a.l + a.s_in[W_UZ * a.stride + c];
+}
+
+struct Origin3 { double v[3]; };
+
+template <typename T>
+__device__ __forceinline__ void grid_cell(T x, T y, T z, double H, int &cx, int &cy, int &cz) {
+    cx = (int)floor((double)x / H);
+    cy = (int)floor((double)y / H);
+    cz = (int)floor((double)z / H);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_keys(StepArgs<T> a, CollideArgs c, Origin3 o) {
+    if (*c.rebuild_flag == 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *c.pair_count = 0ull;
+    if (i >= c.n_surf) return;
+    const T org[3] = {(T)o.v[0], (T)o.v[1], (T)o.v[2]};
+    int ix, iy, iz, cx, cy, cz;
+    T x, y, z;
+    voxel_pos(a, c.surf_cells[i], ix, iy, iz, x, y, z, org);
+    grid_cell(x, y, z, c.horizon, cx, cy, cz);
+    const int key = cell_hash(cx, cy, cz, c.table_size - 1);
+    c.cell_keys[i] = key;
+    atomicAdd(&c.bucket_fill[key], 1);
+}
+
+// Scan of bucket counts -> bucket_start (exclusive), in three phases.
+__global__ void __launch_bounds__(256) k_scan_reduce(CollideArgs c) {
+    if (*c.rebuild_flag == 0) return;
+    __shared__ int red[256];
+    const int base = blockIdx.x * kScanBlock;
+    int s = 0;
+    for (int k = 0; k < 4; ++k) {
+        const int j = base + threadIdx.x * 4 + k;
+        if (j < c.table_size) s += c.bucket_fill[j];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ((int *)c.scan_tmp)[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(1024) k_scan_blocks(CollideArgs c, int nblocks) {
+    if (*c.rebuild_flag == 0) return;
+    __shared__ int buf[1024];
+    __shared__ int carry;
+    int *bs = (int *)c.scan_tmp;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nblocks; base += 1024) {
+        const int j = base + threadIdx.x;
+        const int v = j < nblocks ? bs[j] : 0;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        // Hillis-Steele inclusive scan
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int t = (int)threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (j < nblocks) bs[j] = carry + buf[threadIdx.x] - v;   // exclusive
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += buf[1023];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply(CollideArgs c) {
+    if (*c.rebuild_flag == 0) return;
+    __shared__ int buf[256];
+    const int base = blockIdx.x * kScanBlock;
+    int v[4], s = 0;
+    for (int k = 0; k < 4; ++k) {
+        const int j = base + threadIdx.x * 4 + k;
+        v[k] = j < c.table_size ? c.bucket_fill[j] : 0;
+        s += v[k];
+    }
+    buf[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int t = (int)threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+        __syncthreads();
+        buf[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int run = ((const int *)c.scan_tmp)[blockIdx.x] + buf[threadIdx.x] - s;
+    for (int k = 0; k < 4; ++k) {
+        const int j = base + threadIdx.x * 4 + k;
+        if (j < c.table_size) {
+            c.bucket_start[j] = run;
+            c.bucket_fill[j] = run;   // becomes the scatter cursor
+        }
+        run += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) c.bucket_start[c.table_size] = c.n_surf;
+}
+
+__global__ void __launch_bounds__(256) k_scatter(CollideArgs c) {
+    if (*c.rebuild_flag == 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= c.n_surf) return;
+    const int pos = atomicAdd(&c.bucket_fill[c.cell_keys[i]], 1);
+    c.sorted_idx[pos] = i;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_candidates(StepArgs<T> a, CollideArgs c, Origin3 o) {
+    if (*c.rebuild_flag == 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= c.n_surf) return;
+    const T org[3] = {(T)o.v[0], (T)o.v[1], (T)o.v[2]};
+    const int ci = c.surf_cells[i];
+    int ix, iy, iz, cx, cy, cz;
+    T x, y, z;
+    voxel_pos(a, ci, ix, iy, iz, x, y, z, org);
+    grid_cell(x, y, z, c.horizon, cx, cy, cz);
+    const T uxi = a.s_in[W_UX * a.stride + ci], uyi = a.s_in[W_UY * a.stride + ci],
+            uzi = a.s_in[W_UZ * a.stride + ci];
+    const T H = (T)c.horizon;
+    int *list = c.cand + (long long)i * c.cap;
+    int count = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int tx = cx + dx, ty = cy + dy, tz = cz + dz;
+                const int key = cell_hash(tx, ty, tz, c.table_size - 1);
+                const int b0 = c.bucket_start[key], b1 = c.bucket_start[key + 1];
+                for (int k = b0; k < b1; ++k) {
+                    const int j = c.sorted_idx[k];
+                    const int cj = c.surf_cells[j];
+                    if (cj == ci) continue;
+                    int jx, jy, jz, gx, gy, gz;
+                    T xj, yj, zj;
+                    voxel_pos(a, cj, jx, jy, jz, xj, yj, zj, org);
+                    grid_cell(xj, yj, zj, c.horizon, gx, gy, gz);
+                    if (gx != tx || gy != ty || gz != tz) continue;   // another cell in this bucket
+                    const int man = abs(jx - ix) + abs(jy - iy) + abs(jz - iz);
+                    if (man <= 3) continue;
+                    const T rx = T(ix - jx) * a.l + (uxi - a.s_in[W_UX * a.stride + cj]);
+                    const T ry = T(iy - jy) * a.l + (uyi - a.s_in[W_UY * a.stride + cj]);
+                    const T rz = T(iz - jz) * a.l + (uzi - a.s_in[W_UZ * a.stride + cj]);
+                    if (!(dsqrt(rx * rx + ry * ry + rz * rz) < H)) continue;
+                    if (count < c.cap) {
+                        // insertion keeps the list sorted by partner cell
+                        int p = count;
+                        while (p > 0 && list[p - 1] > cj) { list[p] = list[p - 1]; --p; }
+                        list[p] = cj;
+                    } else {
+                        atomicOr(c.overflow, 1u);
+                    }
+                    ++count;
+                }
+            }
+    const int kept = count < c.cap ? count : c.cap;
+    c.cand_n[i] = kept;
+    uint8_t fl = a.flags[ci];
+    fl = kept > 0 ? (uint8_t)(fl | FLAG_CAND) : (uint8_t)(fl & ~FLAG_CAND);
+    a.flags[ci] = fl;
+    if (count) atomicAdd(c.pair_count, (unsigned long long)count);
+}
+
+__global__ void __launch_bounds__(256) k_rebuild_done(CollideArgs c) {
+    if (*c.rebuild_flag == 0) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < c.table_size) c.bucket_fill[j] = 0;
+}
+
+__global__ void k_rebuild_clear(CollideArgs c) {
+    if (*c.rebuild_flag == 0) return;
+    *c.rebuild_flag = 0;
+    *c.macc = 0.0;
+    *c.rebuild_counter += 1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_contact(StepArgs<T> a, CollideArgs c, T *cf) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= c.n_surf) return;
+    const int n = c.cand_n[i];
+    if (n == 0) return;
+    const long long st = a.stride;
+    const int ci = c.surf_cells[i];
+    const uint8_t mi = a.mat[ci];
+    const MatConst<T> Mi = a.mats[mi];
+    const T ei = voxel_strain(a, ci, a.flags[ci], Mi.cte);
+    const int ix = ci % a.nx, iy = (ci / a.nx) % a.ny, iz = ci / (a.nx * a.ny);
+    const T ux = a.s_in[W_UX * st + ci], uy = a.s_in[W_UY * st + ci], uz = a.s_in[W_UZ * st + ci];
+    const T vx = a.s_in[W_PX * st + ci] * Mi.inv_m, vy = a.s_in[W_PY * st + ci] * Mi.inv_m,
+            vz = a.s_in[W_PZ * st + ci] * Mi.inv_m;
+    T Fx = T(0), Fy = T(0), Fz = T(0);
+    const int *list = c.cand + (long long)i * c.cap;
+    for (int k = 0; k < n; ++k) {
+        const int cj = list[k];
+        const uint8_t mj = a.mat[cj];
+        const MatConst<T> Mj = a.mats[mj];
+        const int jx = cj % a.nx, jy = (cj / a.nx) % a.ny, jz = cj / (a.nx * a.ny);
+        const T rx = T(ix - jx) * a.l + (ux - a.s_in[W_UX * st + cj]);
+        const T ry = T(iy - jy) * a.l + (uy - a.s_in[W_UY * st + cj]);
+        const T rz = T(iz - jz) * a.l + (uz - a.s_in[W_UZ * st + cj]);
+        const T dist = dsqrt(rx * rx + ry * ry + rz * rz);
+        const T ej = voxel_strain(a, cj, a.flags[cj], Mj.cte);
+        const T cdist = T(0.5) * a.l * (T(1) + ei) + T(0.5) * a.l * (T(1) + ej);
+        if (!(dist < cdist) || !(dist > T(0))) continue;
+        const T inv = T(1) / dist;
+        const T nx = rx * inv, ny = ry * inv, nz = rz * inv;
+        const PairConst<T> pc = a.pairs[mi * a.n_mat + mj];
+        const T vjx = a.s_in[W_PX * st + cj] * Mj.inv_m, vjy = a.s_in[W_PY * st + cj] * Mj.inv_m,
+                vjz = a.s_in[W_PZ * st + cj] * Mj.inv_m;
+        const T vn = (vx - vjx) * nx + (vy - vjy) * ny + (vz - vjz) * nz;
+        T f = pc.kc * (cdist - dist) - pc.cc * vn;
+        if (f < T(0)) f = T(0);
+        Fx += f * nx; Fy += f * ny; Fz += f * nz;
+    }
+    cf[ci] = Fx; cf[st + ci] = Fy; cf[2 * st + ci] = Fz;
+}
+
+template <typename T>
+__global__ void k_motion(StepArgs<T> a, CollideArgs c) {
+    const double v = __longlong_as_double((long long)*c.vmax_bits);
+    *c.vmax_bits = 0ull;
+    const double m = *c.macc + v * (double)a.dt;
+    *c.macc = m;
+    if (2.0 * m >= c.threshold) *c.rebuild_flag = 1u;
+}
+
+}  // namespace
+
+size_t scan_temp_bytes(int n) { return (size_t)((n + kScanBlock - 1) / kScanBlock + 1) * sizeof(int); }
+
+template <typename T>
+hipError_t launch_rebuild(const StepArgs<T> &a, const CollideArgs &c, hipStream_t s) {
+    if (c.n_surf == 0) return hipSuccess;
+    Origin3 o;
+    o.v[0] = a.origin[0]; o.v[1] = a.origin[1]; o.v[2] = a.origin[2];
+    const unsigned gs = (unsigned)((c.n_surf + 255) / 256);
+    const int nblk = (c.table_size + kScanBlock - 1) / kScanBlock;
+    k_keys<T><<<gs, 256, 0, s>>>(a, c, o);
+    k_scan_reduce<<<nblk, 256, 0, s>>>(c);
+    k_scan_blocks<<<1, 1024, 0, s>>>(c, nblk);
+    k_scan_apply<<<nblk, 256, 0, s>>>(c);
+    k_scatter<<<gs, 256, 0, s>>>(c);
+    k_candidates<T><<<gs, 256, 0, s>>>(a, c, o);
+    k_rebuild_done<<<(unsigned)((c.table_size + 255) / 256), 256, 0, s>>>(c);
+    k_rebuild_clear<<<1, 1, 0, s>>>(c);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_contact(const StepArgs<T> &a, const CollideArgs &c, T *contact_F, hipStream_t s) {
+    if (c.n_surf == 0) return hipSuccess;
+    k_contact<T><<<(unsigned)((c.n_surf + 255) / 256), 256, 0, s>>>(a, c, contact_F);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_motion_update(const StepArgs<T> &a, const CollideArgs &c, hipStream_t s) {
+    k_motion<T><<<1, 1, 0, s>>>(a, c);
+    return hipGetLastError();
+}
+
+template hipError_t launch_rebuild<float>(const StepArgs<float> &, const CollideArgs &, hipStream_t);
+template hipError_t launch_rebuild<double>(const StepArgs<double> &, const CollideArgs &, hipStream_t);
+template hipError_t launch_contact<float>(const StepArgs<float> &, const CollideArgs &, float *, hipStream_t);
+template hipError_t launch_contact<double>(const StepArgs<double> &, const CollideArgs &, double *, hipStream_t);
+template hipError_t launch_motion_update<float>(const StepArgs<float> &, const CollideArgs &, hipStream_t);
+template hipError_t launch_motion_update<double>(const StepArgs<double> &, const CollideArgs &, hipStream_t);
+
+}  // namespace vx

@@ -1,0 +1,54 @@
+// Kernel launchers shared between the host API and the kernel files.
+#pragma once
+
+#include "vx_types.hpp"
+
+namespace vx {
+
+// Split path: three per-axis bond kernels then the gather/integrate kernel.
+template <typename T>
+hipError_t launch_split_step(const StepArgs<T> &a, hipStream_t s);
+
+// Fused path: one LDS-tiled kernel per step.
+template <typename T>
+hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s);
+
+// Collision support (self-collision on).
+struct CollideArgs {
+    const int *surf_cells;       // surface voxel cells, ascending
+    int n_surf;
+    int cap;                     // candidate slots per surface voxel
+    int *cand;                   // n_surf x cap partner cells, ascending
+    int *cand_n;                 // n_surf
+    unsigned *overflow;          // set when a list overflows
+    unsigned *rebuild_flag;      // device flag: 1 = rebuild before next step
+    double *macc;                // accumulated maximum motion
+    unsigned long long *vmax_bits;
+    int *cell_keys;              // n_surf hashed cell keys
+    int *sorted_idx;             // n_surf surface indices sorted by key
+    int *bucket_start;           // table_size + 1
+    int *bucket_fill;            // table_size (scratch counters)
+    int table_size;              // power of two
+    unsigned long long *pair_count;  // total candidate entries
+    double horizon;              // 2 l
+    double threshold;            // rebuild when 2 * macc >= threshold (= horizon - c_max)
+    void *scan_tmp;              // block sums of the bucket scan
+    size_t scan_tmp_bytes;
+    unsigned long long *rebuild_counter;
+};
+
+// Bytes of scratch the bucket scan needs for a table of n entries.
+size_t scan_temp_bytes(int n);
+
+// Rebuild the candidate lists from the state a.s_in if the device rebuild
+// flag is set; every kernel of the chain exits at once otherwise.
+template <typename T>
+hipError_t launch_rebuild(const StepArgs<T> &a, const CollideArgs &c, hipStream_t s);
+
+template <typename T>
+hipError_t launch_contact(const StepArgs<T> &a, const CollideArgs &c, T *contact_F, hipStream_t s);
+
+template <typename T>
+hipError_t launch_motion_update(const StepArgs<T> &a, const CollideArgs &c, hipStream_t s);
+
+}  // namespace vx

@@ -1,0 +1,183 @@
+"""Parity of the HIP step (through the C ABI) with the FP64 oracle.
+
+Bars: FP64 state within 1e-10 of the oracle (displacement error over the
+largest displacement; velocities likewise over their largest magnitude), FP32
+largest displacement within 1e-4, and bitwise equality wherever the same
+arithmetic runs (run-to-run, split vs fused kernels).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1212_2845_amd as vx
+import workloads
+from parity import build_gpu, build_oracle, compare, perturbed_state
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+FP32_MAXDISP_TOL = 1e-4
+KERNELS = [vx.KERNEL_SPLIT, vx.KERNEL_FUSED]
+
+
+def announce(msg):
+    print("[case] " + msg, flush=True)
+
+
+def run_pair(w, steps, precision=64, kernel=vx.KERNEL_FUSED):
+    g = build_gpu(w, precision=precision, kernel=kernel)
+    o = build_oracle(w)
+    g.step(steps)
+    assert o.step(steps) == 0
+    return g, o
+
+
+def filled_of(w):
+    return w["grid"].reshape(-1) > 0
+
+
+def hetero_block(shape=(5, 6, 7), seed=41, fill=0.85, act=True):
+    mats = workloads.random_materials(3, seed=seed, cte_max=0.01)
+    g = workloads.random_grid(shape, 3, fill, seed + 1)
+    w = workloads._workload(g, mats, workloads._base_params(zeta_bond=0.3, zeta_slow=0.01,
+                                                            temp_amp=15.0, temp_freq=200.0),
+                            300, name="hetero_%dx%dx%d" % shape)
+    n = g.size
+    w["state"] = perturbed_state(n, seed + 2, u_scale=2e-6, v_scale=2e-3, w_scale=1.0, rot_scale=2e-3)
+    if act:
+        rng = np.random.Generator(np.random.PCG64(seed + 3))
+        w["amp"] = rng.uniform(5.0, 20.0, n)
+        w["phase"] = rng.uniform(0.0, 2 * math.pi, n)
+    return w
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_cantilever_fp64(kernel):
+    w = workloads.cantilever(steps=1000)
+    announce("cantilever_20x4x4 fp64 kernel=%d 1000 steps" % kernel)
+    g, o = run_pair(w, 1000, 64, kernel)
+    e = compare(g.read_state(), o.read_state(), filled_of(w))
+    print(e, flush=True)
+    assert e["u"] < FP64_TOL and e["v"] < FP64_TOL and e["w"] < FP64_TOL and e["q"] < 1e-12
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_hetero_block_fp64(kernel):
+    """Several materials, empty cells, perturbed rotations, per-voxel
+    actuation: every bond orientation and branch of the bond math."""
+    w = hetero_block()
+    announce("hetero block fp64 kernel=%d" % kernel)
+    g, o = run_pair(w, 300, 64, kernel)
+    e = compare(g.read_state(), o.read_state(), filled_of(w))
+    print(e, flush=True)
+    assert max(e["u"], e["v"], e["w"]) < FP64_TOL and e["q"] < 1e-12
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_impact_on_floor_fp64(kernel):
+    """Reduced impact case: random soft/stiff block hitting the floor at the
+    speed of a 5 mm drop, friction on."""
+    w = workloads.random_block(n=10, seed=2, impact=True)
+    announce("impact 10^3 fp64 kernel=%d" % kernel)
+    g, o = run_pair(w, 400, 64, kernel)
+    e = compare(g.read_state(), o.read_state(), filled_of(w))
+    print(e, flush=True)
+    assert max(e["u"], e["v"], e["w"]) < FP64_TOL
+    assert np.array_equal(g.read_flags()["static"], o.read_flags()["static"])
+
+
+def test_two_cubes_collision_fp64():
+    n, gap = 3, 1
+    nx = 2 * n + gap
+    grid = np.zeros((n, n, nx), np.uint8)
+    grid[:, :, :n] = 1
+    grid[:, :, n + gap:] = 1
+    x, _, _ = workloads.cell_coords(grid.shape)
+    v = np.zeros((grid.size, 3))
+    v[x < n, 0] = 2.0
+    v[x >= n + gap, 0] = -2.0
+    w = workloads._workload(grid, [workloads.EMPTY, workloads._mat(1e6)],
+                            workloads._base_params(zeta_bond=0.5, zeta_col=0.5, self_collision_on=1),
+                            600, velocity=v, name="two_cubes")
+    announce("two cubes collision fp64")
+    g, o = run_pair(w, 600, 64)
+    e = compare(g.read_state(), o.read_state(), filled_of(w))
+    print(e, g.counters(), o.rebuilds, flush=True)
+    assert max(e["u"], e["v"], e["w"]) < FP64_TOL
+    assert g.candidates() == o.candidates()
+    assert g.counters()["rebuilds"] == o.rebuilds
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_cantilever_fp32_max_displacement(kernel):
+    w = workloads.cantilever(steps=1000)
+    announce("cantilever fp32 kernel=%d" % kernel)
+    g, o = run_pair(w, 1000, 32, kernel)
+    ug = np.linalg.norm(g.read_state()["u"], axis=1).max()
+    uo = np.linalg.norm(o.read_state()["u"], axis=1).max()
+    print(ug, uo, abs(ug / uo - 1), flush=True)
+    assert abs(ug / uo - 1.0) < FP32_MAXDISP_TOL
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_hetero_block_fp32(kernel):
+    w = hetero_block(seed=51)
+    announce("hetero block fp32 kernel=%d" % kernel)
+    g, o = run_pair(w, 300, 32, kernel)
+    e = compare(g.read_state(), o.read_state(), filled_of(w))
+    print(e, flush=True)
+    ug = np.linalg.norm(g.read_state()["u"], axis=1).max()
+    uo = np.linalg.norm(o.read_state()["u"], axis=1).max()
+    assert abs(ug / uo - 1.0) < FP32_MAXDISP_TOL
+    assert e["u"] < 1e-3
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 2), (3, 1, 1), (1, 4, 1), (2, 3, 67), (5, 33, 17)])
+def test_edge_shapes_fp64(shape):
+    """Single voxel (no bonds: free fall), single bonds along each axis,
+    thin and ragged lattices that leave partial tiles."""
+    mats = workloads.random_materials(2, seed=61)
+    g = workloads.random_grid(shape, 2, 0.9 if np.prod(shape) > 4 else 1.0, seed=62)
+    w = workloads._workload(g, mats, workloads._base_params(gravity=9.81, zeta_bond=0.2), 200)
+    w["state"] = perturbed_state(g.size, 63, 1e-6, 1e-3, 0.5, 1e-3)
+    announce("edge shape %s" % (shape,))
+    for kernel in KERNELS:
+        gs, o = run_pair(w, 200, 64, kernel)
+        e = compare(gs.read_state(), o.read_state(), filled_of(w))
+        assert max(e["u"], e["v"], e["w"]) < FP64_TOL, (kernel, e)
+
+
+def test_empty_lattice_steps():
+    g = np.zeros((3, 3, 3), np.uint8)
+    s = vx.Sim(g, [workloads.EMPTY, workloads._mat(1e6)])
+    announce("empty lattice")
+    s.step(5)
+    assert s.counters()["voxels"] == 0
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_deterministic_and_split_equals_fused(precision):
+    w = hetero_block(shape=(9, 10, 11), seed=71)
+    announce("determinism p=%d" % precision)
+    states = []
+    for kernel in (vx.KERNEL_FUSED, vx.KERNEL_FUSED, vx.KERNEL_SPLIT):
+        s = build_gpu(w, precision, kernel)
+        s.step(100)
+        states.append(s.read_state())
+    for k in ("u", "q", "v", "w"):
+        assert np.array_equal(states[0][k], states[1][k])
+        assert np.array_equal(states[0][k], states[2][k])
+
+
+def test_unstable_reports_error():
+    """Bond damping far above 1 is unstable (the paper warns of values
+    above 1): the step reports VX_EUNSTABLE instead of running on."""
+    g = np.ones((6, 6, 6), np.uint8)
+    s = vx.Sim(g, [workloads.EMPTY, workloads._mat(1e6)], zeta_bond=3.0)
+    st = perturbed_state(g.size, 81, 1e-7, 1e-4, 0.0, 0.0)
+    s.write_state(u=st["u"], v=st["v"])
+    announce("unstable")
+    rc = s.step_rc(3000)
+    assert rc == vx.VX_EUNSTABLE
