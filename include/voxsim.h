@@ -160,9 +160,22 @@ int vx_counters(vx_handle h, int64_t out[4]);
 int vx_candidates(vx_handle h, int32_t *cell_a, int32_t *cell_b, int32_t max_pairs,
                   int32_t *n_pairs);
 
-/* Select the step implementation: 0 = fused LDS-tiled kernel (default),
+/* Select the step implementation: 0 = fused LDS-tiled kernel (default;
+ * palettes of more than 16 materials always use the split path),
  * 1 = split per-axis bond kernels plus a gather kernel. */
 int vx_set_kernel(vx_handle h, int32_t kind);
+
+/* Tile of the fused kernel: shape index 0..4 = 32x8, 64x4, 16x16, 50x5,
+ * 20x12 cells per workgroup in x-y (-1: chosen from the lattice size), zc =
+ * z slabs per workgroup (0: chosen from the lattice size).  Results agree
+ * across tiles to rounding; one tile is bitwise reproducible. */
+int vx_set_fused_tile(vx_handle h, int32_t shape, int32_t zc);
+int vx_get_fused_tile(vx_handle h, int32_t *shape, int32_t *tx, int32_t *ty, int32_t *zc);
+
+/* Time every fused tile shape and z chunk on this lattice (iters launches
+ * each, from the current state, without advancing it) and keep the fastest.
+ * Errors: VX_ESTATE before bind. */
+int vx_autotune(vx_handle h, int32_t iters, int32_t *shape, int32_t *zc);
 
 /* Free host-side data of the handle (not the caller's workspace). */
 int vx_destroy(vx_handle h);

@@ -30,7 +30,10 @@ KERNEL_SPLIT = 1
 EXPORTED = ["vx_create", "vx_workspace_bytes", "vx_bind_workspace", "vx_set_fixed", "vx_set_forces",
             "vx_fixed_region", "vx_forced_region", "vx_set_actuation", "vx_set_velocity", "vx_step",
             "vx_read_state", "vx_write_state", "vx_read_flags", "vx_get_dt", "vx_get_time",
-            "vx_counters", "vx_candidates", "vx_set_kernel", "vx_destroy", "vx_last_error"]
+            "vx_counters", "vx_candidates", "vx_set_kernel", "vx_set_fused_tile", "vx_get_fused_tile",
+            "vx_autotune", "vx_destroy", "vx_last_error"]
+
+FUSED_SHAPES = [(32, 8), (64, 4), (16, 16), (50, 5), (20, 12)]
 
 
 class VoxsimError(RuntimeError):
@@ -85,6 +88,10 @@ def lib():
     L.vx_counters.argtypes = [P, C.POINTER(C.c_int64)]
     L.vx_candidates.argtypes = [P, P, P, i32, C.POINTER(i32)]
     L.vx_set_kernel.argtypes = [P, i32]
+    L.vx_set_fused_tile.argtypes = [P, i32, i32]
+    pi32 = C.POINTER(i32)
+    L.vx_get_fused_tile.argtypes = [P, pi32, pi32, pi32, pi32]
+    L.vx_autotune.argtypes = [P, i32, pi32, pi32]
     L.vx_destroy.argtypes = [P]
     L.vx_last_error.argtypes = [P]
     L.vx_last_error.restype = C.c_char_p
@@ -194,6 +201,20 @@ class Sim:
     # -- setters --------------------------------------------------------------
     def set_kernel(self, kind):
         self._check(lib().vx_set_kernel(self.h, int(kind)))
+
+    def set_fused_tile(self, shape=-1, zc=0):
+        self._check(lib().vx_set_fused_tile(self.h, int(shape), int(zc)))
+
+    def fused_tile(self):
+        v = [C.c_int32() for _ in range(4)]
+        self._check(lib().vx_get_fused_tile(self.h, *[C.byref(x) for x in v]))
+        return {"shape": v[0].value, "tx": v[1].value, "ty": v[2].value, "zc": v[3].value}
+
+    def autotune(self, iters=5):
+        self.bind()
+        sh = C.c_int32(); zc = C.c_int32()
+        self._check(lib().vx_autotune(self.h, int(iters), C.byref(sh), C.byref(zc)))
+        return self.fused_tile()
 
     def set_fixed(self, mask):
         m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)

@@ -24,7 +24,7 @@ constexpr uint64_t kAlign = 256;
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t state[2], mat, flags, mats, pairs, bonds, act_amp, act_phase, forced_cells, forced_F;
+    uint64_t state[2], mat, flags[2], mats, pairs, bonds, act_amp, act_phase, forced_cells, forced_F;
     uint64_t contact_F, surf_cells, cand, cand_n, keys, sorted, bstart, bfill, scalars, scan_tmp;
     uint64_t total;
 };
@@ -74,7 +74,10 @@ struct vx_sim {
     bool bound = false;
     char *ws = nullptr;
     Layout L{};
-    int cur = 0;                          // which state buffer holds state n
+    int cur = 0;                          // which state / flags buffer holds step n
+    bool flags_live = false;              // device flags hold dynamic bits
+    int fused_shape = -1;                 // tile shape of the fused kernel (-1: heuristic)
+    int fused_zc = 0;                     // z chunk of the fused kernel (0: heuristic)
     std::string err;
 };
 
@@ -146,7 +149,8 @@ static void compute_layout(vx_sim *h) {
     L.state[0] = take(N_WORDS * n * ts);
     L.state[1] = take(N_WORDS * n * ts);
     L.mat = take(n);
-    L.flags = take(n);
+    L.flags[0] = take(n);
+    L.flags[1] = take(n);
     L.mats = take((uint64_t)h->n_mat * (h->precision == 64 ? sizeof(MatConst<double>) : sizeof(MatConst<float>)));
     L.pairs = take((uint64_t)h->n_mat * h->n_mat *
                    (h->precision == 64 ? sizeof(PairConst<double>) : sizeof(PairConst<float>)));
@@ -179,7 +183,8 @@ static StepArgs<T> make_args(vx_sim *h) {
     a.s_out = (T *)(ws + h->L.state[1 - h->cur]);
     a.stride = h->ncell;
     a.mat = (const uint8_t *)(ws + h->L.mat);
-    a.flags = (uint8_t *)(ws + h->L.flags);
+    a.flags = (const uint8_t *)(ws + h->L.flags[h->cur]);
+    a.flags_out = (uint8_t *)(ws + h->L.flags[1 - h->cur]);
     a.mats = (const MatConst<T> *)(ws + h->L.mats);
     a.pairs = (const PairConst<T> *)(ws + h->L.pairs);
     a.n_mat = h->n_mat;
@@ -192,6 +197,7 @@ static StepArgs<T> make_args(vx_sim *h) {
     const double tn = (double)h->step * h->dt;
     const double wt = 2.0 * kPi * h->p.temp_freq * tn;
     a.wt = wt;
+    a.wt_red = (T)std::fmod(wt, 2.0 * kPi);
     a.dT_global = (T)(h->p.temp_amp * std::sin(wt + h->p.temp_phase));
     a.act_amp = (const T *)(ws + h->L.act_amp);
     a.act_phase = (const T *)(ws + h->L.act_phase);
@@ -244,7 +250,22 @@ static int upload_static(vx_sim *h) {
     char *ws = h->ws;
     hipStream_t s = h->stream;
     HIP_OK(h, hipMemcpyAsync(ws + h->L.mat, h->grid.data(), h->ncell, hipMemcpyHostToDevice, s));
-    HIP_OK(h, hipMemcpyAsync(ws + h->L.flags, h->flags.data(), h->ncell, hipMemcpyHostToDevice, s));
+    {
+        // static bits from the host, dynamic bits (friction state, contact
+        // candidates) from the device copy of the current step
+        std::vector<uint8_t> fl(h->flags);
+        if (h->flags_live) {
+            std::vector<uint8_t> dev(h->ncell);
+            HIP_OK(h, hipMemcpyAsync(dev.data(), ws + h->L.flags[h->cur], h->ncell, hipMemcpyDeviceToHost, s));
+            HIP_OK(h, hipStreamSynchronize(s));
+            const uint8_t dyn = FLAG_STATIC | FLAG_CAND;
+            for (long long c = 0; c < h->ncell; ++c) fl[c] = (uint8_t)((fl[c] & ~dyn) | (dev[c] & dyn));
+        }
+        HIP_OK(h, hipMemcpyAsync(ws + h->L.flags[0], fl.data(), h->ncell, hipMemcpyHostToDevice, s));
+        HIP_OK(h, hipMemcpyAsync(ws + h->L.flags[1], fl.data(), h->ncell, hipMemcpyHostToDevice, s));
+        HIP_OK(h, hipStreamSynchronize(s));
+        h->flags_live = true;
+    }
     HIP_OK(h, hipMemcpyAsync(ws + h->L.mats, mc.data(), mc.size() * sizeof(MatConst<T>), hipMemcpyHostToDevice, s));
     HIP_OK(h, hipMemcpyAsync(ws + h->L.pairs, pc.data(), pc.size() * sizeof(PairConst<T>), hipMemcpyHostToDevice, s));
     std::vector<T> a(h->ncell), ph(h->ncell);
@@ -327,6 +348,30 @@ static int request_rebuild(vx_sim *h) {
     return VX_OK;
 }
 
+// Tile shape of the fused kernel: the one wasting the fewest lanes on the
+// lattice's x-y extent, with the ring (halo) and boundary-bond overhead of
+// small tiles as a tie breaker.
+static int heuristic_shape(const vx_sim *h) {
+    int best = 0;
+    double best_cost = 1e300;
+    for (int i = 0; i < kNumFusedShapes; ++i) {
+        const int tx = kFusedShapes[i].tx, ty = kFusedShapes[i].ty;
+        const double padded = (double)((h->nx + tx - 1) / tx * tx) * (double)((h->ny + ty - 1) / ty * ty);
+        const double slots = padded / ((double)h->nx * h->ny);
+        const double halo = 2.0 * (tx + ty) / (double)(tx * ty);
+        const double cost = slots * (1.0 + 0.3 * halo);
+        if (cost < best_cost - 1e-12) { best_cost = cost; best = i; }
+    }
+    return best;
+}
+
+static FusedCfg fused_cfg(const vx_sim *h) {
+    FusedCfg c;
+    c.shape = h->fused_shape >= 0 ? h->fused_shape : heuristic_shape(h);
+    c.zc = h->fused_zc;
+    return c;
+}
+
 template <typename T>
 static int run_steps(vx_sim *h, int64_t n) {
     const bool col = h->p.self_collision_on != 0;
@@ -337,10 +382,10 @@ static int run_steps(vx_sim *h, int64_t n) {
             HIP_OK(h, launch_rebuild<T>(a, c, h->stream));
             HIP_OK(h, launch_contact<T>(a, c, (T *)(h->ws + h->L.contact_F), h->stream));
         }
-        if (h->kernel_kind == 1) {
+        if (h->kernel_kind == 1 || h->n_mat > kFusedMaxMat) {
             HIP_OK(h, launch_split_step<T>(a, h->stream));
         } else {
-            HIP_OK(h, launch_fused_step<T>(a, h->stream));
+            HIP_OK(h, launch_fused_step<T>(a, fused_cfg(h), h->stream));
         }
         if (col) {
             CollideArgs c = make_collide(h);
@@ -354,6 +399,50 @@ static int run_steps(vx_sim *h, int64_t n) {
     HIP_OK(h, hipStreamSynchronize(h->stream));
     if (sc.err_flag) return fail(h, VX_EUNSTABLE, "non-finite value in the voxel state");
     if (sc.overflow) return fail(h, VX_EOVERFLOW, "collision candidate list overflow (raise contact_cap)");
+    return VX_OK;
+}
+
+template <typename T>
+static int autotune(vx_sim *h, int iters, int32_t *shape_out, int32_t *zc_out) {
+    const bool col = h->p.self_collision_on != 0;
+    StepArgs<T> a = make_args<T>(h);
+    if (col) {
+        CollideArgs c = make_collide(h);
+        HIP_OK(h, launch_rebuild<T>(a, c, h->stream));
+        HIP_OK(h, launch_contact<T>(a, c, (T *)(h->ws + h->L.contact_F), h->stream));
+    }
+    hipEvent_t e0, e1;
+    HIP_OK(h, hipEventCreate(&e0));
+    HIP_OK(h, hipEventCreate(&e1));
+    float best = 1e30f;
+    FusedCfg best_cfg{0, 0};
+    const int zcs[] = {2, 4, 8, 16, 32, 64};
+    for (int sh = 0; sh < kNumFusedShapes; ++sh)
+        for (int zc : zcs) {
+            if (zc > h->nz && zc != zcs[0]) continue;
+            FusedCfg cfg{sh, zc};
+            // warm-up launch, then the timed ones; outputs go to the next
+            // buffers and are overwritten by the first real step
+            HIP_OK(h, launch_fused_step<T>(a, cfg, h->stream));
+            HIP_OK(h, hipEventRecord(e0, h->stream));
+            for (int i = 0; i < iters; ++i) HIP_OK(h, launch_fused_step<T>(a, cfg, h->stream));
+            HIP_OK(h, hipEventRecord(e1, h->stream));
+            HIP_OK(h, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_OK(h, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; best_cfg = cfg; }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    // the timing launches touched the speed accumulator
+    Scalars *sc = (Scalars *)(h->ws + h->L.scalars);
+    const unsigned long long zero = 0;
+    HIP_OK(h, hipMemcpyAsync(&sc->vmax_bits, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    h->fused_shape = best_cfg.shape;
+    h->fused_zc = best_cfg.zc;
+    if (shape_out) *shape_out = best_cfg.shape;
+    if (zc_out) *zc_out = best_cfg.zc;
     return VX_OK;
 }
 
@@ -638,7 +727,7 @@ int vx_read_flags(vx_handle h, uint8_t *is_static, uint8_t *surface) {
     if (!h) return VX_EINVAL;
     std::vector<uint8_t> fl(h->flags);
     if (h->bound) {
-        HIP_OK(h, hipMemcpyAsync(fl.data(), h->ws + h->L.flags, h->ncell, hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(h, hipMemcpyAsync(fl.data(), h->ws + h->L.flags[h->cur], h->ncell, hipMemcpyDeviceToHost, h->stream));
         HIP_OK(h, hipStreamSynchronize(h->stream));
     }
     for (long long c = 0; c < h->ncell; ++c) {
@@ -693,6 +782,34 @@ int vx_candidates(vx_handle h, int32_t *cell_a, int32_t *cell_b, int32_t max_pai
         }
     *n_pairs = k;
     return VX_OK;
+}
+
+int vx_set_fused_tile(vx_handle h, int32_t shape, int32_t zc) {
+    if (!h || shape < -1 || shape >= kNumFusedShapes || zc < 0) return VX_EINVAL;
+    h->fused_shape = shape;
+    h->fused_zc = zc;
+    return VX_OK;
+}
+
+int vx_get_fused_tile(vx_handle h, int32_t *shape, int32_t *tx, int32_t *ty, int32_t *zc) {
+    if (!h) return VX_EINVAL;
+    const FusedCfg c = fused_cfg(h);
+    if (shape) *shape = c.shape;
+    if (tx) *tx = kFusedShapes[c.shape].tx;
+    if (ty) *ty = kFusedShapes[c.shape].ty;
+    if (zc) {
+        const int t = kFusedShapes[c.shape].tx, u = kFusedShapes[c.shape].ty;
+        const long long cols = (long long)((h->nx + t - 1) / t) * ((h->ny + u - 1) / u);
+        *zc = c.zc > 0 ? std::min(c.zc, h->nz) : fused_default_zc(h->nz, cols);
+    }
+    return VX_OK;
+}
+
+int vx_autotune(vx_handle h, int32_t iters, int32_t *shape, int32_t *zc) {
+    if (!h || iters <= 0) return VX_EINVAL;
+    if (!h->bound) return fail(h, VX_ESTATE, "vx_autotune before vx_bind_workspace");
+    if (h->n_mat > kFusedMaxMat) return fail(h, VX_ESTATE, "palette too large for the fused kernel");
+    return h->precision == 64 ? autotune<double>(h, iters, shape, zc) : autotune<float>(h, iters, shape, zc);
 }
 
 int vx_set_kernel(vx_handle h, int32_t kind) {

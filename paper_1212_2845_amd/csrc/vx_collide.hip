@@ -193,9 +193,11 @@ __global__ void __launch_bounds__(256) k_candidates(StepArgs<T> a, CollideArgs c
             }
     const int kept = count < c.cap ? count : c.cap;
     c.cand_n[i] = kept;
-    uint8_t fl = a.flags[ci];
+    // the candidate bit lives in the flags of the current step
+    uint8_t *flags = const_cast<uint8_t *>(a.flags);
+    uint8_t fl = flags[ci];
     fl = kept > 0 ? (uint8_t)(fl | FLAG_CAND) : (uint8_t)(fl & ~FLAG_CAND);
-    a.flags[ci] = fl;
+    flags[ci] = fl;
     if (count) atomicAdd(c.pair_count, (unsigned long long)count);
 }
 
@@ -222,7 +224,7 @@ __global__ void __launch_bounds__(256) k_contact(StepArgs<T> a, CollideArgs c, T
     const int ci = c.surf_cells[i];
     const uint8_t mi = a.mat[ci];
     const MatConst<T> Mi = a.mats[mi];
-    const T ei = voxel_strain(a, ci, a.flags[ci], Mi.cte);
+    const T ei = voxel_strain(a, (unsigned)ci, a.flags[ci], Mi.cte);
     const int ix = ci % a.nx, iy = (ci / a.nx) % a.ny, iz = ci / (a.nx * a.ny);
     const T ux = a.s_in[W_UX * st + ci], uy = a.s_in[W_UY * st + ci], uz = a.s_in[W_UZ * st + ci];
     const T vx = a.s_in[W_PX * st + ci] * Mi.inv_m, vy = a.s_in[W_PY * st + ci] * Mi.inv_m,
@@ -238,7 +240,7 @@ __global__ void __launch_bounds__(256) k_contact(StepArgs<T> a, CollideArgs c, T
         const T ry = T(iy - jy) * a.l + (uy - a.s_in[W_UY * st + cj]);
         const T rz = T(iz - jz) * a.l + (uz - a.s_in[W_UZ * st + cj]);
         const T dist = dsqrt(rx * rx + ry * ry + rz * rz);
-        const T ej = voxel_strain(a, cj, a.flags[cj], Mj.cte);
+        const T ej = voxel_strain(a, (unsigned)cj, a.flags[cj], Mj.cte);
         const T cdist = T(0.5) * a.l * (T(1) + ei) + T(0.5) * a.l * (T(1) + ej);
         if (!(dist < cdist) || !(dist > T(0))) continue;
         const T inv = T(1) / dist;

@@ -21,6 +21,93 @@ template <> __device__ __forceinline__ void dsincos<double>(double a, double *s,
 template <typename T> __device__ __forceinline__ bool dfinite(T a);
 template <> __device__ __forceinline__ bool dfinite<float>(float a) { return isfinite(a); }
 template <> __device__ __forceinline__ bool dfinite<double>(double a) { return isfinite(a); }
+template <typename T> __device__ __forceinline__ T dsin(T a);
+template <> __device__ __forceinline__ float dsin<float>(float a) { return sinf(a); }
+template <> __device__ __forceinline__ double dsin<double>(double a) { return sin(a); }
+
+// Reciprocal of x > 0: FP32 hardware estimate (1 ulp); FP64 hardware
+// estimate refined by Newton steps to full precision.
+template <typename T> __device__ __forceinline__ T frcp(T x);
+template <> __device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double frcp<double>(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+// Series used on the common path, with the library functions as fallback
+// outside their range.  Term counts make the truncation error smaller than
+// half an ulp of the type over the whole fast range.
+template <typename T> struct Series;
+template <> struct Series<float> {
+    static constexpr float kLogU = 0.01f;    // (|v| / w)^2 below which atan(t)/t is a polynomial
+    static constexpr float kExpA2 = 0.01f;   // |w dt|^2 below which cos / sinc are polynomials
+    static constexpr float kNormD = 1e-4f;   // |q|^2 - 1 below which 1/|q| is 1 - d/2 + 3d^2/8
+};
+template <> struct Series<double> {
+    static constexpr double kLogU = 0.01;
+    static constexpr double kExpA2 = 0.01;
+    static constexpr double kNormD = 1e-6;
+};
+
+// atan(t)/t for u = t^2 < kLogU (alternating Taylor series 1 - u/3 + u^2/5 - ...).
+template <typename T> __device__ __forceinline__ T atan_over_t(T u);
+template <> __device__ __forceinline__ float atan_over_t<float>(float u) {
+    float p = -1.0f / 7.0f;
+    p = fmaf(p, u, 1.0f / 5.0f);
+    p = fmaf(p, u, -1.0f / 3.0f);
+    return fmaf(p, u, 1.0f);
+}
+template <> __device__ __forceinline__ double atan_over_t<double>(double u) {
+    double p = -1.0 / 15.0;
+    p = fma(p, u, 1.0 / 13.0);
+    p = fma(p, u, -1.0 / 11.0);
+    p = fma(p, u, 1.0 / 9.0);
+    p = fma(p, u, -1.0 / 7.0);
+    p = fma(p, u, 1.0 / 5.0);
+    p = fma(p, u, -1.0 / 3.0);
+    return fma(p, u, 1.0);
+}
+
+// cos(h) and sin(h) / (2 h) for a2 = (2 h)^2 < kExpA2 (Taylor in h^2 = a2/4).
+template <typename T> __device__ __forceinline__ void half_angle_series(T a2, T *c, T *sk);
+template <> __device__ __forceinline__ void half_angle_series<float>(float a2, float *c, float *sk) {
+    const float h2 = 0.25f * a2;
+    float pc = 1.0f / 24.0f;
+    pc = fmaf(pc, h2, -0.5f);
+    *c = fmaf(pc, h2, 1.0f);
+    float ps = 1.0f / 120.0f;
+    ps = fmaf(ps, h2, -1.0f / 6.0f);
+    *sk = 0.5f * fmaf(ps, h2, 1.0f);
+}
+template <> __device__ __forceinline__ void half_angle_series<double>(double a2, double *c, double *sk) {
+    const double h2 = 0.25 * a2;
+    double pc = 1.0 / 40320.0;
+    pc = fma(pc, h2, -1.0 / 720.0);
+    pc = fma(pc, h2, 1.0 / 24.0);
+    pc = fma(pc, h2, -0.5);
+    *c = fma(pc, h2, 1.0);
+    double ps = 1.0 / 362880.0;
+    ps = fma(ps, h2, -1.0 / 5040.0);
+    ps = fma(ps, h2, 1.0 / 120.0);
+    ps = fma(ps, h2, -1.0 / 6.0);
+    *sk = 0.5 * fma(ps, h2, 1.0);
+}
+
+// Element c of array base through a 32-bit byte offset from a uniform base,
+// so the load/store addresses as SGPR base + one shared VGPR offset.
+template <typename T>
+__device__ __forceinline__ T ldc(const T *base, unsigned c) {
+    return *(const T *)((const char *)base + (size_t)(c * (unsigned)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void stc(T *base, unsigned c, T v) {
+    *(T *)((char *)base + (size_t)(c * (unsigned)sizeof(T))) = v;
+}
 
 // Kinematic quantities of one voxel that its bonds read.
 template <typename T>
@@ -57,46 +144,88 @@ struct BondOut {
     T m2x, m2y, m2z;
 };
 
-// One beam bond along lattice axis AX between voxel A (lower index, voxel
-// 1) and voxel B (voxel 2).  Co-rotational: the bond is expressed in the
-// frame of voxel 1 with the axis permuted onto +x, where only voxel 2's six
-// displacements remain (reduced forces of Eq. 13-24, with the z-force sign
-// of the full matrix Eq. 7); the result is rotated back to the world frame
-// and bond damping (Eq. 33-35) is added.
-template <typename T, int AX>
-__device__ __forceinline__ BondOut<T> bond_eval(const VoxKin<T> &A, const Rot<T> &RA,
-                                                const VoxKin<T> &B, const PairConst<T> &pc, T l) {
-    constexpr int A0 = AX, A1 = (AX + 1) % 3, A2 = (AX + 2) % 3;
-    // world separation of the two centres
-    T d[3] = {B.ux - A.ux, B.uy - A.uy, B.uz - A.uz};
-    d[AX] += l;
-    const V3<T> ex = RA.c[A0], ey = RA.c[A1], ez = RA.c[A2];
+// Constants of one bond.  On a cubic lattice (area l^2, I = l^4/12,
+// J = l^4/6) Eq. 8-12 give b1 = a1, b2 = a1 l/2 and b3 = a1 l^2/6, and with
+// the voxel inertia m l^2/6 the rotational damping coefficient of Eq. 35 is
+// the translational one (Eq. 34) times l^2/6, so three numbers per material
+// pair determine the bond.
+template <typename T>
+struct BondK {
+    T a1, a2, ct;
+};
+
+// Lattice constants shared by every bond: l, l/2, l^2/6, l^2/3.
+template <typename T>
+struct LatK {
+    T l, hl, l26, l23;
+};
+
+template <typename T>
+__device__ __forceinline__ LatK<T> lat_consts(T l) {
+    LatK<T> c;
+    c.l = l; c.hl = T(0.5) * l; c.l26 = l * l / T(6); c.l23 = l * l / T(3);
+    return c;
+}
+
+template <typename T>
+__device__ __forceinline__ BondK<T> bond_k(const PairConst<T> &pc) {
+    BondK<T> k;
+    k.a1 = pc.a1; k.a2 = pc.a2; k.ct = pc.ct;
+    return k;
+}
+
+// Rotation vector of q_A^-1 q_B (voxel 2's rotation relative to voxel 1, in
+// voxel 1's body frame), on the short branch: 2 atan2(|v|, |w|) v / |v|.
+template <typename T>
+__device__ __forceinline__ void rel_rotvec(const VoxKin<T> &A, const VoxKin<T> &B, T th[3]) {
+    const T rw = A.qw * B.qw + A.qx * B.qx + A.qy * B.qy + A.qz * B.qz;
+    const T rx = A.qw * B.qx - A.qx * B.qw - A.qy * B.qz + A.qz * B.qy;
+    const T ry = A.qw * B.qy + A.qx * B.qz - A.qy * B.qw - A.qz * B.qx;
+    const T rz = A.qw * B.qz - A.qx * B.qy + A.qy * B.qx - A.qz * B.qw;
+    const T aw = rw < T(0) ? -rw : rw;
+    const T s2 = rx * rx + ry * ry + rz * rz;
+    const T iw = frcp(aw);
+    const T u = s2 * iw * iw;
+    T k;
+    if (u < Series<T>::kLogU) {
+        k = T(2) * iw * atan_over_t(u);
+    } else {
+        const T s = dsqrt(s2);
+        k = T(2) * datan2(s, aw) / s;
+    }
+    if (rw < T(0)) k = -k;
+    th[0] = k * rx; th[1] = k * ry; th[2] = k * rz;
+}
+
+// One beam bond between voxel A (voxel 1, lower lattice index) and voxel B
+// (voxel 2).  Co-rotational: the bond is expressed in the frame of voxel 1
+// with its axis permuted onto +x (basis ex, ey, ez: columns of voxel 1's
+// rotation), where only voxel 2's six displacements remain (reduced forces
+// of Eq. 13-24, with the z-force sign of the full matrix Eq. 7).  d is the
+// world separation D_B - D_A, (tx, ty, tz) the relative rotation in the
+// bond frame.  The result is rotated back to the world frame and bond
+// damping (Eq. 33-35) is added.
+template <typename T>
+__device__ __forceinline__ BondOut<T> bond_core(const VoxKin<T> &A, const VoxKin<T> &B, const T d[3],
+                                                const V3<T> &ex, const V3<T> &ey, const V3<T> &ez, T tx,
+                                                T ty, T tz, const BondK<T> &K, const LatK<T> &C) {
     const T dlx = ex.x * d[0] + ex.y * d[1] + ex.z * d[2];
     const T dly = ey.x * d[0] + ey.y * d[1] + ey.z * d[2];
     const T dlz = ez.x * d[0] + ez.y * d[1] + ez.z * d[2];
-    // relative rotation q_A^-1 q_B as a rotation vector in A's body frame
-    T rw = A.qw * B.qw + A.qx * B.qx + A.qy * B.qy + A.qz * B.qz;
-    T rx = A.qw * B.qx - A.qx * B.qw - A.qy * B.qz + A.qz * B.qy;
-    T ry = A.qw * B.qy + A.qx * B.qz - A.qy * B.qw - A.qz * B.qx;
-    T rz = A.qw * B.qz - A.qx * B.qy + A.qy * B.qx - A.qz * B.qw;
-    if (rw < T(0)) { rw = -rw; rx = -rx; ry = -ry; rz = -rz; }
-    const T s = dsqrt(rx * rx + ry * ry + rz * rz);
-    const T k = (s > T(0)) ? T(2) * datan2(s, rw) / s : T(2) / rw;
-    const T th[3] = {k * rx, k * ry, k * rz};
-    const T tx = th[A0], ty = th[A1], tz = th[A2];
     // rest length stretched by the mean thermal strain (Eq. 40)
-    const T L = l * (T(1) + T(0.5) * (A.eps + B.eps));
+    const T L = C.l * (T(1) + T(0.5) * (A.eps + B.eps));
     const T X2 = dlx - L, Y2 = dly, Z2 = dlz;
+    const T b1 = K.a1, b2 = K.a1 * C.hl, b3 = K.a1 * C.l26, b3x2 = K.a1 * C.l23;
     // local nodal forces K u (u1 = 0)
-    const T f2x = pc.a1 * X2;
-    const T f2y = pc.b1 * Y2 - pc.b2 * tz;
-    const T f2z = pc.b1 * Z2 + pc.b2 * ty;
-    const T m2x = pc.a2 * tx;
-    const T m2y = pc.b2 * Z2 + T(2) * pc.b3 * ty;
-    const T m2z = -pc.b2 * Y2 + T(2) * pc.b3 * tz;
+    const T f2x = K.a1 * X2;
+    const T f2y = b1 * Y2 - b2 * tz;
+    const T f2z = b1 * Z2 + b2 * ty;
+    const T m2x = K.a2 * tx;
+    const T m2y = b2 * Z2 + b3x2 * ty;
+    const T m2z = -b2 * Y2 + b3x2 * tz;
     const T m1x = -m2x;
-    const T m1y = pc.b2 * Z2 + pc.b3 * ty;
-    const T m1z = -pc.b2 * Y2 + pc.b3 * tz;
+    const T m1y = b2 * Z2 + b3 * ty;
+    const T m1z = -b2 * Y2 + b3 * tz;
     BondOut<T> o;
     // the bond acts with the opposite of K u, rotated back to the world
     o.f2x = -(f2x * ex.x + f2y * ey.x + f2z * ez.x);
@@ -110,70 +239,129 @@ __device__ __forceinline__ BondOut<T> bond_eval(const VoxKin<T> &A, const Rot<T>
     o.m1z = -(m1x * ex.z + m1y * ey.z + m1z * ez.z);
     // bond damping: relative velocity without the pair's rigid motion
     const T h = T(0.5), q4 = T(0.25);
+    const T cr = K.ct * C.l26;
     const T wax = A.wx + B.wx, way = A.wy + B.wy, waz = A.wz + B.wz;
     const T vrx = h * (B.vx - A.vx) + q4 * (d[1] * waz - d[2] * way);
     const T vry = h * (B.vy - A.vy) + q4 * (d[2] * wax - d[0] * waz);
     const T vrz = h * (B.vz - A.vz) + q4 * (d[0] * way - d[1] * wax);
     const T wrx = h * (B.wx - A.wx), wry = h * (B.wy - A.wy), wrz = h * (B.wz - A.wz);
-    o.f2x -= pc.ct * vrx; o.f2y -= pc.ct * vry; o.f2z -= pc.ct * vrz;
-    o.m2x -= pc.cr * wrx; o.m2y -= pc.cr * wry; o.m2z -= pc.cr * wrz;
-    o.m1x += pc.cr * wrx; o.m1y += pc.cr * wry; o.m1z += pc.cr * wrz;
+    o.f2x -= K.ct * vrx; o.f2y -= K.ct * vry; o.f2z -= K.ct * vrz;
+    o.m2x -= cr * wrx; o.m2y -= cr * wry; o.m2z -= cr * wrz;
+    o.m1x += cr * wrx; o.m1y += cr * wry; o.m1z += cr * wrz;
     return o;
 }
 
-// Thermal strain of a voxel at t_n: cte times its temperature signal.
+// Bond along lattice axis AX (compile-time).
+template <typename T, int AX>
+__device__ __forceinline__ BondOut<T> bond_eval(const VoxKin<T> &A, const Rot<T> &RA, const VoxKin<T> &B,
+                                                const BondK<T> &K, const LatK<T> &C) {
+    constexpr int A0 = AX, A1 = (AX + 1) % 3, A2 = (AX + 2) % 3;
+    T d[3] = {B.ux - A.ux, B.uy - A.uy, B.uz - A.uz};
+    d[AX] += C.l;
+    T th[3];
+    rel_rotvec(A, B, th);
+    return bond_core(A, B, d, RA.c[A0], RA.c[A1], RA.c[A2], th[A0], th[A1], th[A2], K, C);
+}
+
+// Bond along x (yaxis = false) or y (yaxis = true), chosen per lane.
 template <typename T>
-__device__ __forceinline__ T voxel_strain(const StepArgs<T> &a, long long c, uint8_t fl, T cte) {
+__device__ __forceinline__ BondOut<T> bond_eval_xy(const VoxKin<T> &A, const Rot<T> &RA, const VoxKin<T> &B,
+                                                   const BondK<T> &K, const LatK<T> &C, bool yaxis) {
+    T d[3] = {B.ux - A.ux, B.uy - A.uy, B.uz - A.uz};
+    d[0] += yaxis ? T(0) : C.l;
+    d[1] += yaxis ? C.l : T(0);
+    T th[3];
+    rel_rotvec(A, B, th);
+    const V3<T> ex = yaxis ? RA.c[1] : RA.c[0];
+    const V3<T> ey = yaxis ? RA.c[2] : RA.c[1];
+    const V3<T> ez = yaxis ? RA.c[0] : RA.c[2];
+    const T tx = yaxis ? th[1] : th[0], ty = yaxis ? th[2] : th[1], tz = yaxis ? th[0] : th[2];
+    return bond_core(A, B, d, ex, ey, ez, tx, ty, tz, K, C);
+}
+
+// FP32 evaluates the signal from the host-reduced phase 2 pi f t_n mod 2 pi.
+template <typename T>
+__device__ __forceinline__ T voxel_strain(const StepArgs<T> &a, unsigned c, uint8_t fl, T cte) {
     T dT = a.dT_global;
     if (fl & FLAG_ACT) {
-        const double arg = a.wt + (double)a.act_phase[c];
-        dT = a.act_amp[c] * (T)sin(arg);
+        if constexpr (sizeof(T) == 8) {
+            dT = ldc(a.act_amp, c) * dsin<T>(a.wt + ldc(a.act_phase, c));
+        } else {
+            dT = ldc(a.act_amp, c) * dsin<T>(a.wt_red + ldc(a.act_phase, c));
+        }
     }
     return cte * dT;
 }
 
+// Raw state words of one voxel.
 template <typename T>
-__device__ __forceinline__ VoxKin<T> load_kin(const T *__restrict__ s, long long stride, long long c,
-                                              const MatConst<T> &mc, T eps) {
+struct VoxRaw {
+    T ux, uy, uz, qw, qx, qy, qz, px, py, pz, lx, ly, lz;
+};
+
+template <typename T>
+__device__ __forceinline__ VoxRaw<T> load_raw(const T *__restrict__ s, long long st, unsigned c) {
+    VoxRaw<T> r;
+    r.ux = ldc(s + W_UX * st, c); r.uy = ldc(s + W_UY * st, c); r.uz = ldc(s + W_UZ * st, c);
+    r.qw = ldc(s + W_QW * st, c); r.qx = ldc(s + W_QX * st, c);
+    r.qy = ldc(s + W_QY * st, c); r.qz = ldc(s + W_QZ * st, c);
+    r.px = ldc(s + W_PX * st, c); r.py = ldc(s + W_PY * st, c); r.pz = ldc(s + W_PZ * st, c);
+    r.lx = ldc(s + W_LX * st, c); r.ly = ldc(s + W_LY * st, c); r.lz = ldc(s + W_LZ * st, c);
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_raw(T *__restrict__ o, long long st, unsigned c, T ux, T uy, T uz, T qw,
+                                          T qx, T qy, T qz, T px, T py, T pz, T lx, T ly, T lz) {
+    stc(o + W_UX * st, c, ux); stc(o + W_UY * st, c, uy); stc(o + W_UZ * st, c, uz);
+    stc(o + W_QW * st, c, qw); stc(o + W_QX * st, c, qx); stc(o + W_QY * st, c, qy); stc(o + W_QZ * st, c, qz);
+    stc(o + W_PX * st, c, px); stc(o + W_PY * st, c, py); stc(o + W_PZ * st, c, pz);
+    stc(o + W_LX * st, c, lx); stc(o + W_LY * st, c, ly); stc(o + W_LZ * st, c, lz);
+}
+
+template <typename T>
+__device__ __forceinline__ VoxKin<T> kin_of(const VoxRaw<T> &r, const MatConst<T> &mc, T eps) {
     VoxKin<T> k;
-    k.ux = s[W_UX * stride + c]; k.uy = s[W_UY * stride + c]; k.uz = s[W_UZ * stride + c];
-    k.qw = s[W_QW * stride + c]; k.qx = s[W_QX * stride + c];
-    k.qy = s[W_QY * stride + c]; k.qz = s[W_QZ * stride + c];
-    k.vx = s[W_PX * stride + c] * mc.inv_m; k.vy = s[W_PY * stride + c] * mc.inv_m;
-    k.vz = s[W_PZ * stride + c] * mc.inv_m;
-    k.wx = s[W_LX * stride + c] * mc.inv_I; k.wy = s[W_LY * stride + c] * mc.inv_I;
-    k.wz = s[W_LZ * stride + c] * mc.inv_I;
+    k.ux = r.ux; k.uy = r.uy; k.uz = r.uz;
+    k.qw = r.qw; k.qx = r.qx; k.qy = r.qy; k.qz = r.qz;
+    k.vx = r.px * mc.inv_m; k.vy = r.py * mc.inv_m; k.vz = r.pz * mc.inv_m;
+    k.wx = r.lx * mc.inv_I; k.wy = r.ly * mc.inv_I; k.wz = r.lz * mc.inv_I;
     k.eps = eps;
     return k;
+}
+
+template <typename T>
+__device__ __forceinline__ VoxKin<T> load_kin(const T *__restrict__ s, long long stride, unsigned c,
+                                              const MatConst<T> &mc, T eps) {
+    return kin_of(load_raw(s, stride, c), mc, eps);
 }
 
 // Everything after the bond sum for one voxel: external force, gravity,
 // ground damping, floor, contact, Coulomb friction, then the synchronous
 // "double Euler" update (Eq. 27-30) with the orientation advanced by the
-// exact rotation w dt.  Writes the new state of cell c.
+// exact rotation w dt.  r is the voxel's state at t_n; writes the new state
+// of cell c.
 template <typename T>
-__device__ __forceinline__ void voxel_update(const StepArgs<T> &a, long long c, uint8_t fl,
-                                             const MatConst<T> &mc, T eps, T Fx, T Fy, T Fz,
-                                             T Mx, T My, T Mz, T *vmax_local) {
-    const T *__restrict__ s = a.s_in;
+__device__ __forceinline__ void voxel_update(const StepArgs<T> &a, unsigned c, uint8_t fl,
+                                             const MatConst<T> &mc, T eps, const VoxRaw<T> &r, T Fx,
+                                             T Fy, T Fz, T Mx, T My, T Mz, T *vmax_local) {
+    // vmax_local tracks the largest squared speed
     T *__restrict__ o = a.s_out;
     const long long st = a.stride;
-    T ux = s[W_UX * st + c], uy = s[W_UY * st + c], uz = s[W_UZ * st + c];
-    T qw = s[W_QW * st + c], qx = s[W_QX * st + c], qy = s[W_QY * st + c], qz = s[W_QZ * st + c];
-    T px = s[W_PX * st + c], py = s[W_PY * st + c], pz = s[W_PZ * st + c];
-    T lx = s[W_LX * st + c], ly = s[W_LY * st + c], lz = s[W_LZ * st + c];
+    T ux = r.ux, uy = r.uy, uz = r.uz;
+    const T qw = r.qw, qx = r.qx, qy = r.qy, qz = r.qz;
+    T px = r.px, py = r.py, pz = r.pz;
+    T lx = r.lx, ly = r.ly, lz = r.lz;
     if (fl & FLAG_FIXED) {
-        o[W_UX * st + c] = ux; o[W_UY * st + c] = uy; o[W_UZ * st + c] = uz;
-        o[W_QW * st + c] = qw; o[W_QX * st + c] = qx; o[W_QY * st + c] = qy; o[W_QZ * st + c] = qz;
-        o[W_PX * st + c] = T(0); o[W_PY * st + c] = T(0); o[W_PZ * st + c] = T(0);
-        o[W_LX * st + c] = T(0); o[W_LY * st + c] = T(0); o[W_LZ * st + c] = T(0);
+        store_raw(o, st, c, ux, uy, uz, qw, qx, qy, qz, T(0), T(0), T(0), T(0), T(0), T(0));
+        stc(a.flags_out, c, fl);
         return;
     }
     if (fl & FLAG_FORCED) {
         int lo = 0, hi = a.n_forced - 1;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if ((long long)a.forced_cells[mid] < c) lo = mid + 1; else hi = mid;
+            if ((unsigned)a.forced_cells[mid] < c) lo = mid + 1; else hi = mid;
         }
         Fx += a.forced_F[3 * lo]; Fy += a.forced_F[3 * lo + 1]; Fz += a.forced_F[3 * lo + 2];
     }
@@ -184,7 +372,7 @@ __device__ __forceinline__ void voxel_update(const StepArgs<T> &a, long long c, 
     Mx -= wx * mc.cgr; My -= wy * mc.cgr; Mz -= wz * mc.cgr;
     T Fn = T(0);
     if (a.floor_on) {
-        const long long nxy = (long long)a.nx * a.ny;
+        const unsigned nxy = (unsigned)a.nx * (unsigned)a.ny;
         const int iz = (int)(c / nxy);
         const T Dz = a.origin_z + (T(iz) + T(0.5)) * a.l + uz;
         const T pen = T(0.5) * a.l * (T(1) + eps) - Dz;
@@ -195,7 +383,7 @@ __device__ __forceinline__ void voxel_update(const StepArgs<T> &a, long long c, 
         }
     }
     if (fl & FLAG_CAND) {
-        Fx += a.contact_F[c]; Fy += a.contact_F[st + c]; Fz += a.contact_F[2 * st + c];
+        Fx += ldc(a.contact_F, c); Fy += ldc(a.contact_F + st, c); Fz += ldc(a.contact_F + 2 * st, c);
     }
     // Coulomb friction against the floor (Eq. 36-38)
     uint8_t nf = fl;
@@ -230,8 +418,8 @@ __device__ __forceinline__ void voxel_update(const StepArgs<T> &a, long long c, 
         } else {
             nf &= (uint8_t)~FLAG_STATIC;
         }
-        if (nf != fl) a.flags[c] = nf;
     }
+    stc(a.flags_out, c, nf);
     // integrate
     const T dt = a.dt;
     px += Fx * dt; py += Fy * dt; pz += Fz * dt;
@@ -239,9 +427,12 @@ __device__ __forceinline__ void voxel_update(const StepArgs<T> &a, long long c, 
     ux += nvx * dt; uy += nvy * dt; uz += nvz * dt;
     lx += Mx * dt; ly += My * dt; lz += Mz * dt;
     const T rx = lx * mc.inv_I * dt, ry = ly * mc.inv_I * dt, rz = lz * mc.inv_I * dt;
-    const T ang = dsqrt(rx * rx + ry * ry + rz * rz);
-    T dw = T(1), sk = T(0.5);
-    if (ang > T(0)) {
+    const T a2 = rx * rx + ry * ry + rz * rz;
+    T dw, sk;
+    if (a2 < Series<T>::kExpA2) {
+        half_angle_series(a2, &dw, &sk);
+    } else {
+        const T ang = dsqrt(a2);
         T sn, cs;
         dsincos(T(0.5) * ang, &sn, &cs);
         dw = cs;
@@ -253,18 +444,37 @@ __device__ __forceinline__ void voxel_update(const StepArgs<T> &a, long long c, 
     T nx = dw * qx + dx * qw + dy * qz - dz * qy;
     T ny = dw * qy - dx * qz + dy * qw + dz * qx;
     T nz = dw * qz + dx * qy - dy * qx + dz * qw;
-    const T qn = dsqrt(nw * nw + nx * nx + ny * ny + nz * nz);
-    nw /= qn; nx /= qn; ny /= qn; nz /= qn;
-    o[W_UX * st + c] = ux; o[W_UY * st + c] = uy; o[W_UZ * st + c] = uz;
-    o[W_QW * st + c] = nw; o[W_QX * st + c] = nx; o[W_QY * st + c] = ny; o[W_QZ * st + c] = nz;
-    o[W_PX * st + c] = px; o[W_PY * st + c] = py; o[W_PZ * st + c] = pz;
-    o[W_LX * st + c] = lx; o[W_LY * st + c] = ly; o[W_LZ * st + c] = lz;
+    const T n2 = nw * nw + nx * nx + ny * ny + nz * nz;
+    const T dn = n2 - T(1);
+    T inv;
+    if (dn < Series<T>::kNormD && dn > -Series<T>::kNormD) {
+        inv = fma(dn, fma(dn, T(0.375), T(-0.5)), T(1));
+    } else {
+        inv = T(1) / dsqrt(n2);
+    }
+    nw *= inv; nx *= inv; ny *= inv; nz *= inv;
+    store_raw(o, st, c, ux, uy, uz, nw, nx, ny, nz, px, py, pz, lx, ly, lz);
     const bool ok = dfinite(ux) && dfinite(uy) && dfinite(uz) && dfinite(nw) && dfinite(nx) &&
                     dfinite(ny) && dfinite(nz) && dfinite(px) && dfinite(py) && dfinite(pz) &&
                     dfinite(lx) && dfinite(ly) && dfinite(lz);
     if (!ok) atomicOr(a.err_flag, 1u);
-    const T sp = dsqrt(nvx * nvx + nvy * nvy + nvz * nvz);
-    if (sp > *vmax_local) *vmax_local = sp;
+    const T sp2 = nvx * nvx + nvy * nvy + nvz * nvz;
+    if (sp2 > *vmax_local) *vmax_local = sp2;
+}
+
+// Wavefront maximum of the squared speed v2, then one atomic per wave of the
+// speed into the device-wide maximum (non-negative doubles order like their
+// bit patterns).
+template <typename T>
+__device__ __forceinline__ void wave_vmax(unsigned long long *dst, T v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const T o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0 && v > T(0)) {
+        const double d = sqrt((double)v);
+        atomicMax(dst, (unsigned long long)__double_as_longlong(d));
+    }
 }
 
 }  // namespace vx

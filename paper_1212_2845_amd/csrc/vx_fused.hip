@@ -1,15 +1,333 @@
-// Fused step kernel (placeholder: forwards to the split path).
+// Fused step kernel: one launch per step, each voxel's state read from HBM
+// once and written once.
+//
+// A workgroup owns a TX x TY column of cells and marches up a chunk of z
+// slabs (2.5-D blocking).  For each slab the own cells and a one-cell ring
+// around the tile are staged in LDS as kinematic quantities; every x- and
+// y-bond touching the tile is evaluated once (bonds that enter the tile
+// from the ring as well), its result kept in LDS, and the bond to the slab
+// above is evaluated in registers with its voxel-2 half carried to the next
+// slab.  Each thread then sums its own voxel's at most six bond results in
+// the fixed order -x, +x, -y, +y, -z, +z (no atomics) and integrates.  The
+// per-bond and per-voxel arithmetic is the same device code as the split
+// path; material and material-pair constants are staged in LDS once per
+// workgroup.
+//
+// Workgroups are numbered so that consecutive tiles land on the same XCD
+// (the dispatcher deals workgroups round-robin over the 8 XCDs), keeping
+// the ring loads of neighbouring tiles in one L2.
 #include "vx_device.hpp"
 #include "vx_launch.hpp"
 
 namespace vx {
 
-template <typename T>
-hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s) {
-    return launch_split_step<T>(a, s);
+namespace {
+
+constexpr int kXcds = 8;
+constexpr int kKin = 14;   // ux uy uz qw qx qy qz vx vy vz wx wy wz eps
+
+template <typename T, int TX, int TY>
+struct Smem {
+    static constexpr int RW = TX + 2, RH = TY + 2, NR = RW * RH;
+    static constexpr int NBX = (TX + 1) * TY, NBY = TX * (TY + 1);
+    T kin[kKin][NR];
+    T bx[9][NBX];
+    T by[9][NBY];
+    uint8_t mat[NR];
+};
+
+struct FusedGrid {
+    int tiles_x, tiles_y, chunks, zc;
+};
+
+template <typename T, int NR>
+__device__ __forceinline__ void put_kin(T (*kin)[NR], int slot, const VoxKin<T> &k) {
+    kin[0][slot] = k.ux; kin[1][slot] = k.uy; kin[2][slot] = k.uz;
+    kin[3][slot] = k.qw; kin[4][slot] = k.qx; kin[5][slot] = k.qy; kin[6][slot] = k.qz;
+    kin[7][slot] = k.vx; kin[8][slot] = k.vy; kin[9][slot] = k.vz;
+    kin[10][slot] = k.wx; kin[11][slot] = k.wy; kin[12][slot] = k.wz;
+    kin[13][slot] = k.eps;
 }
 
-template hipError_t launch_fused_step<float>(const StepArgs<float> &, hipStream_t);
-template hipError_t launch_fused_step<double>(const StepArgs<double> &, hipStream_t);
+template <typename T, int NR>
+__device__ __forceinline__ VoxKin<T> get_kin(const T (*kin)[NR], int slot) {
+    VoxKin<T> k;
+    k.ux = kin[0][slot]; k.uy = kin[1][slot]; k.uz = kin[2][slot];
+    k.qw = kin[3][slot]; k.qx = kin[4][slot]; k.qy = kin[5][slot]; k.qz = kin[6][slot];
+    k.vx = kin[7][slot]; k.vy = kin[8][slot]; k.vz = kin[9][slot];
+    k.wx = kin[10][slot]; k.wy = kin[11][slot]; k.wz = kin[12][slot];
+    k.eps = kin[13][slot];
+    return k;
+}
+
+template <typename T, int NB>
+__device__ __forceinline__ void put_bond(T (*b)[NB], int i, const BondOut<T> &o) {
+    b[0][i] = o.f2x; b[1][i] = o.f2y; b[2][i] = o.f2z;
+    b[3][i] = o.m1x; b[4][i] = o.m1y; b[5][i] = o.m1z;
+    b[6][i] = o.m2x; b[7][i] = o.m2y; b[8][i] = o.m2z;
+}
+
+// Own voxel of one slab: material, flags, strain, raw state, kinematics.
+template <typename T>
+struct Own {
+    uint8_t m, fl;
+    T eps;
+    VoxRaw<T> r;
+    VoxKin<T> k;
+};
+
+// Per-workgroup copies of the material and material-pair tables.
+template <typename T>
+struct Tables {
+    const MatConst<T> *mat;   // n_mat entries
+    const T *pair;            // n_mat^2 x 4: a1, a2, ct, -
+    int n_mat;
+    __device__ __forceinline__ BondK<T> bond(int m1, int m2) const {
+        const T *p = pair + 4 * (m1 * n_mat + m2);
+        BondK<T> k;
+        k.a1 = p[0]; k.a2 = p[1]; k.ct = p[2];
+        return k;
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void load_own(const StepArgs<T> &a, const Tables<T> &tb, unsigned c, Own<T> &o) {
+    o.m = ldc(a.mat, c);
+    if (o.m) {
+        o.fl = ldc(a.flags, c);
+        o.r = load_raw(a.s_in, a.stride, c);
+        const MatConst<T> &mc = tb.mat[o.m];
+        o.eps = voxel_strain(a, c, o.fl, mc.cte);
+        o.k = kin_of(o.r, mc, o.eps);
+    }
+}
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_fused(StepArgs<T> a, FusedGrid g) {
+    using S = Smem<T, TX, TY>;
+    constexpr int NT = TX * TY, RW = S::RW, NR = S::NR, NBX = S::NBX, NBY = S::NBY;
+    static_assert(2 * (TX + TY) <= NT, "ring must fit one cell per thread");
+    __shared__ S sm;
+    extern __shared__ __align__(16) unsigned char dyn[];
+
+    // material tables into LDS
+    Tables<T> tb;
+    tb.n_mat = a.n_mat;
+    {
+        MatConst<T> *smat = (MatConst<T> *)dyn;
+        T *spair = (T *)(dyn + ((a.n_mat * sizeof(MatConst<T>) + 15) & ~(size_t)15));
+        const T *gm = (const T *)a.mats;
+        T *sm_ = (T *)smat;
+        const int nmw = a.n_mat * (int)(sizeof(MatConst<T>) / sizeof(T));
+        for (int i = threadIdx.x; i < nmw; i += NT) sm_[i] = gm[i];
+        const int np = a.n_mat * a.n_mat;
+        for (int i = threadIdx.x; i < np; i += NT) {
+            spair[4 * i] = a.pairs[i].a1;
+            spair[4 * i + 1] = a.pairs[i].a2;
+            spair[4 * i + 2] = a.pairs[i].ct;
+            spair[4 * i + 3] = T(0);
+        }
+        tb.mat = smat;
+        tb.pair = spair;
+    }
+    const LatK<T> C = lat_consts(a.l);
+
+    // XCD-aware tile order (bijective for any grid size)
+    const int nwg = gridDim.x, b = blockIdx.x;
+    const int q = nwg / kXcds, rem = nwg % kXcds, xcd = b % kXcds, kk = b / kXcds;
+    const int L = xcd < rem ? xcd * (q + 1) + kk : rem * (q + 1) + (xcd - rem) * q + kk;
+    const int tile_x = L % g.tiles_x;
+    const int tile_y = (L / g.tiles_x) % g.tiles_y;
+    const int chunk = L / (g.tiles_x * g.tiles_y);
+
+    const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+    const int x = tile_x * TX + tx, y = tile_y * TY + ty;
+    const bool inxy = x < a.nx && y < a.ny;
+    const int z0 = chunk * g.zc;
+    const int z1 = min(z0 + g.zc, a.nz);
+    const unsigned nxy = (unsigned)a.nx * (unsigned)a.ny;
+    const unsigned col = inxy ? (unsigned)x + (unsigned)a.nx * (unsigned)y : 0u;
+    const int own = (tx + 1) + RW * (ty + 1);
+
+    // ring cell of this thread (one-cell border of the tile, corners excluded)
+    const bool ring = tid < 2 * (TX + TY);
+    int rx = 0, ry = 0;
+    if (tid < TY) { rx = -1; ry = tid; }
+    else if (tid < 2 * TY) { rx = TX; ry = tid - TY; }
+    else if (tid < 2 * TY + TX) { rx = tid - 2 * TY; ry = -1; }
+    else if (ring) { rx = tid - 2 * TY - TX; ry = TY; }
+    const int gxr = tile_x * TX + rx, gyr = tile_y * TY + ry;
+    const bool ring_in = ring && gxr >= 0 && gxr < a.nx && gyr >= 0 && gyr < a.ny;
+    const unsigned ring_col = ring_in ? (unsigned)gxr + (unsigned)a.nx * (unsigned)gyr : 0u;
+    const int ring_slot = (rx + 1) + RW * (ry + 1);
+    // boundary bond entering the tile: x from (-1, tid) or y from (tid - TY, -1)
+    const bool bnd = tid < TX + TY;
+    const bool bnd_y = tid >= TY;
+    const int bnd_lo = bnd_y ? (tid - TY + 1) : RW * (tid + 1);
+    const int bnd_up = bnd_y ? bnd_lo + RW : bnd_lo + 1;
+    const int bnd_i = bnd_y ? (tid - TY) : (TX + 1) * tid;
+
+    __syncthreads();
+
+    T vmax = T(0);
+    Own<T> A{}, B{};
+    if (inxy && z0 < z1) load_own(a, tb, col + (unsigned)z0 * nxy, A);
+
+    // bond from the slab below the chunk: only its voxel-2 half is needed
+    bool has_carry = false;
+    T cFx = T(0), cFy = T(0), cFz = T(0), cMx = T(0), cMy = T(0), cMz = T(0);
+    if (A.m && z0 > 0) {
+        Own<T> P{};
+        load_own(a, tb, col + (unsigned)(z0 - 1) * nxy, P);
+        if (P.m) {
+            const Rot<T> Rp = rot_of(P.k.qw, P.k.qx, P.k.qy, P.k.qz);
+            const BondOut<T> o = bond_eval<T, 2>(P.k, Rp, A.k, tb.bond(P.m, A.m), C);
+            cFx = o.f2x; cFy = o.f2y; cFz = o.f2z; cMx = o.m2x; cMy = o.m2y; cMz = o.m2z;
+            has_carry = true;
+        }
+    }
+
+    // one slab: cur holds slab z, nxt receives slab z + 1
+    auto slab = [&](Own<T> &cur, Own<T> &nxt, int z) __attribute__((always_inline)) {
+        nxt.m = 0;
+        if (inxy && z + 1 < a.nz) load_own(a, tb, col + (unsigned)(z + 1) * nxy, nxt);
+
+        if (cur.m) put_kin<T, NR>(sm.kin, own, cur.k);
+        sm.mat[own] = cur.m;
+        if (ring) {
+            uint8_t mr = 0;
+            if (ring_in) {
+                Own<T> R{};
+                load_own(a, tb, ring_col + (unsigned)z * nxy, R);
+                mr = R.m;
+                if (mr) put_kin<T, NR>(sm.kin, ring_slot, R.k);
+            }
+            sm.mat[ring_slot] = mr;
+        }
+        __syncthreads();
+
+        Rot<T> Rc{};
+        if (cur.m) Rc = rot_of(cur.k.qw, cur.k.qx, cur.k.qy, cur.k.qz);
+        {
+            const uint8_t mu = sm.mat[own + 1];
+            if (cur.m && mu) {
+                const VoxKin<T> ku = get_kin<T, NR>(sm.kin, own + 1);
+                put_bond<T, NBX>(sm.bx, (tx + 1) + (TX + 1) * ty, bond_eval<T, 0>(cur.k, Rc, ku, tb.bond(cur.m, mu), C));
+            }
+        }
+        {
+            const uint8_t mu = sm.mat[own + RW];
+            if (cur.m && mu) {
+                const VoxKin<T> ku = get_kin<T, NR>(sm.kin, own + RW);
+                put_bond<T, NBY>(sm.by, tx + TX * (ty + 1), bond_eval<T, 1>(cur.k, Rc, ku, tb.bond(cur.m, mu), C));
+            }
+        }
+        if (bnd) {
+            const uint8_t ml = sm.mat[bnd_lo], mu = sm.mat[bnd_up];
+            if (ml && mu) {
+                const VoxKin<T> kl = get_kin<T, NR>(sm.kin, bnd_lo), ku = get_kin<T, NR>(sm.kin, bnd_up);
+                const Rot<T> Rl = rot_of(kl.qw, kl.qx, kl.qy, kl.qz);
+                const BondOut<T> o = bond_eval_xy(kl, Rl, ku, tb.bond(ml, mu), C, bnd_y);
+                if (bnd_y) put_bond<T, NBY>(sm.by, bnd_i, o); else put_bond<T, NBX>(sm.bx, bnd_i, o);
+            }
+        }
+        // neighbour materials for the gather, read before the slab's LDS can
+        // be overwritten by faster threads moving on to the next slab
+        const bool n_mx = sm.mat[own - 1] != 0, n_px = sm.mat[own + 1] != 0;
+        const bool n_my = sm.mat[own - RW] != 0, n_py = sm.mat[own + RW] != 0;
+        const bool has_zb = cur.m && nxt.m;
+        BondOut<T> oz{};
+        if (has_zb) oz = bond_eval<T, 2>(cur.k, Rc, nxt.k, tb.bond(cur.m, nxt.m), C);
+        __syncthreads();
+
+        if (cur.m) {
+            T Fx = T(0), Fy = T(0), Fz = T(0), Mx = T(0), My = T(0), Mz = T(0);
+            if (n_mx) {
+                const int i = tx + (TX + 1) * ty;
+                Fx += sm.bx[0][i]; Fy += sm.bx[1][i]; Fz += sm.bx[2][i];
+                Mx += sm.bx[6][i]; My += sm.bx[7][i]; Mz += sm.bx[8][i];
+            }
+            if (n_px) {
+                const int i = (tx + 1) + (TX + 1) * ty;
+                Fx -= sm.bx[0][i]; Fy -= sm.bx[1][i]; Fz -= sm.bx[2][i];
+                Mx += sm.bx[3][i]; My += sm.bx[4][i]; Mz += sm.bx[5][i];
+            }
+            if (n_my) {
+                const int i = tx + TX * ty;
+                Fx += sm.by[0][i]; Fy += sm.by[1][i]; Fz += sm.by[2][i];
+                Mx += sm.by[6][i]; My += sm.by[7][i]; Mz += sm.by[8][i];
+            }
+            if (n_py) {
+                const int i = tx + TX * (ty + 1);
+                Fx -= sm.by[0][i]; Fy -= sm.by[1][i]; Fz -= sm.by[2][i];
+                Mx += sm.by[3][i]; My += sm.by[4][i]; Mz += sm.by[5][i];
+            }
+            if (has_carry) {
+                Fx += cFx; Fy += cFy; Fz += cFz;
+                Mx += cMx; My += cMy; Mz += cMz;
+            }
+            if (has_zb) {
+                Fx -= oz.f2x; Fy -= oz.f2y; Fz -= oz.f2z;
+                Mx += oz.m1x; My += oz.m1y; Mz += oz.m1z;
+            }
+            voxel_update(a, col + (unsigned)z * nxy, cur.fl, tb.mat[cur.m], cur.eps, cur.r, Fx, Fy, Fz, Mx, My,
+                         Mz, &vmax);
+        }
+        has_carry = has_zb;
+        cFx = oz.f2x; cFy = oz.f2y; cFz = oz.f2z; cMx = oz.m2x; cMy = oz.m2y; cMz = oz.m2z;
+    };
+
+    // two slabs per trip so that the roles of A and B alternate without copies
+    for (int z = z0; z < z1; z += 2) {
+        slab(A, B, z);
+        if (z + 1 < z1) slab(B, A, z + 1);
+    }
+    if (a.track_vmax) wave_vmax(a.vmax_bits, vmax);
+}
+
+template <typename T, int TX, int TY>
+hipError_t launch_tiles(const StepArgs<T> &a, int zc, hipStream_t s) {
+    FusedGrid g;
+    g.tiles_x = (a.nx + TX - 1) / TX;
+    g.tiles_y = (a.ny + TY - 1) / TY;
+    const long long cols = (long long)g.tiles_x * g.tiles_y;
+    if (zc <= 0) zc = fused_default_zc(a.nz, cols);
+    zc = zc > a.nz ? a.nz : zc;
+    g.zc = zc;
+    g.chunks = (a.nz + zc - 1) / zc;
+    const long long nwg = cols * g.chunks;
+    const size_t dyn = ((a.n_mat * sizeof(MatConst<T>) + 15) & ~(size_t)15) +
+                       (size_t)a.n_mat * a.n_mat * 4 * sizeof(T);
+    k_fused<T, TX, TY><<<(unsigned)nwg, TX * TY, dyn, s>>>(a, g);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int fused_default_zc(int nz, long long cols) {
+    // enough workgroups to fill the chip several times over, but chunks of
+    // at least 4 slabs so that the extra slab below each chunk stays cheap
+    const long long target = 4096;
+    long long zc = (nz * cols + target - 1) / target;
+    if (zc < 4) zc = 4;
+    if (zc > nz) zc = nz;
+    return (int)zc;
+}
+
+const FusedShape kFusedShapes[kNumFusedShapes] = {{32, 8}, {64, 4}, {16, 16}, {50, 5}, {20, 12}};
+
+template <typename T>
+hipError_t launch_fused_step(const StepArgs<T> &a, const FusedCfg &cfg, hipStream_t s) {
+    switch (cfg.shape) {
+        case 1: return launch_tiles<T, 64, 4>(a, cfg.zc, s);
+        case 2: return launch_tiles<T, 16, 16>(a, cfg.zc, s);
+        case 3: return launch_tiles<T, 50, 5>(a, cfg.zc, s);
+        case 4: return launch_tiles<T, 20, 12>(a, cfg.zc, s);
+        default: return launch_tiles<T, 32, 8>(a, cfg.zc, s);
+    }
+}
+
+template hipError_t launch_fused_step<float>(const StepArgs<float> &, const FusedCfg &, hipStream_t);
+template hipError_t launch_fused_step<double>(const StepArgs<double> &, const FusedCfg &, hipStream_t);
 
 }  // namespace vx

@@ -9,9 +9,24 @@ namespace vx {
 template <typename T>
 hipError_t launch_split_step(const StepArgs<T> &a, hipStream_t s);
 
-// Fused path: one LDS-tiled kernel per step.
+// Fused path: one LDS-tiled kernel per step.  cfg.shape indexes
+// kFusedShapes (tile TX x TY); cfg.zc is the z chunk per workgroup (0 picks
+// fused_default_zc).
+struct FusedShape {
+    int tx, ty;
+};
+constexpr int kNumFusedShapes = 5;
+extern const FusedShape kFusedShapes[kNumFusedShapes];
+struct FusedCfg {
+    int shape;
+    int zc;
+};
+int fused_default_zc(int nz, long long cols);
+// Largest palette whose tables fit the fused kernel's LDS.
+constexpr int kFusedMaxMat = 16;
+
 template <typename T>
-hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s);
+hipError_t launch_fused_step(const StepArgs<T> &a, const FusedCfg &cfg, hipStream_t s);
 
 // Collision support (self-collision on).
 struct CollideArgs {

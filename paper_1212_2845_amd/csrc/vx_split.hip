@@ -30,30 +30,17 @@ __global__ void __launch_bounds__(256) k_bonds(StepArgs<T> a) {
     const uint8_t mb = a.mat[cn];
     if (mb == 0) return;
     const MatConst<T> A = a.mats[ma], B = a.mats[mb];
-    const T ea = voxel_strain(a, c, a.flags[c], A.cte);
-    const T eb = voxel_strain(a, cn, a.flags[cn], B.cte);
-    const VoxKin<T> ka = load_kin(a.s_in, a.stride, c, A, ea);
-    const VoxKin<T> kb = load_kin(a.s_in, a.stride, cn, B, eb);
+    const T ea = voxel_strain(a, (unsigned)c, a.flags[c], A.cte);
+    const T eb = voxel_strain(a, (unsigned)cn, a.flags[cn], B.cte);
+    const VoxKin<T> ka = load_kin(a.s_in, a.stride, (unsigned)c, A, ea);
+    const VoxKin<T> kb = load_kin(a.s_in, a.stride, (unsigned)cn, B, eb);
     const Rot<T> R = rot_of(ka.qw, ka.qx, ka.qy, ka.qz);
-    const BondOut<T> o = bond_eval<T, AX>(ka, R, kb, a.pairs[ma * a.n_mat + mb], a.l);
+    const BondOut<T> o = bond_eval<T, AX>(ka, R, kb, bond_k(a.pairs[ma * a.n_mat + mb]), lat_consts(a.l));
     T *b = a.bonds + (long long)AX * 9 * a.stride;
     const long long st = a.stride;
     b[0 * st + c] = o.f2x; b[1 * st + c] = o.f2y; b[2 * st + c] = o.f2z;
     b[3 * st + c] = o.m1x; b[4 * st + c] = o.m1y; b[5 * st + c] = o.m1z;
     b[6 * st + c] = o.m2x; b[7 * st + c] = o.m2y; b[8 * st + c] = o.m2z;
-}
-
-template <typename T>
-__device__ __forceinline__ void block_vmax(const StepArgs<T> &a, T v) {
-    // wavefront max, then one atomic per wave
-    for (int off = 32; off > 0; off >>= 1) {
-        const T o = __shfl_xor(v, off, 64);
-        v = o > v ? o : v;
-    }
-    if ((threadIdx.x & 63) == 0 && v > T(0)) {
-        const double d = (double)v;
-        atomicMax(a.vmax_bits, (unsigned long long)__double_as_longlong(d));
-    }
 }
 
 template <typename T>
@@ -86,11 +73,12 @@ __global__ void __launch_bounds__(256) k_gather(StepArgs<T> a) {
             }
             const MatConst<T> mc = a.mats[m];
             const uint8_t fl = a.flags[c];
-            const T eps = voxel_strain(a, c, fl, mc.cte);
-            voxel_update(a, c, fl, mc, eps, Fx, Fy, Fz, Mx, My, Mz, &vmax);
+            const T eps = voxel_strain(a, (unsigned)c, fl, mc.cte);
+            const VoxRaw<T> r = load_raw(a.s_in, st, (unsigned)c);
+            voxel_update(a, (unsigned)c, fl, mc, eps, r, Fx, Fy, Fz, Mx, My, Mz, &vmax);
         }
     }
-    if (a.track_vmax) block_vmax(a, vmax);
+    if (a.track_vmax) wave_vmax(a.vmax_bits, vmax);
 }
 
 template <typename T>

@@ -57,7 +57,8 @@ struct StepArgs {
     T *s_out;
     long long stride;          // = ncell
     const uint8_t *mat;
-    uint8_t *flags;
+    const uint8_t *flags;      // flags at t_n (read)
+    uint8_t *flags_out;        // flags at t_n+1 (written for every filled voxel)
     const MatConst<T> *mats;
     const PairConst<T> *pairs;
     int n_mat;
@@ -69,6 +70,7 @@ struct StepArgs {
     double origin[3];          // world position of the lower corner of cell 0
     T dT_global;               // temperature of voxels without own signal, at t_n
     double wt;                 // 2 pi f t_n
+    T wt_red;                  // 2 pi f t_n reduced to [0, 2 pi)
     const T *act_amp;          // per cell, used where FLAG_ACT
     const T *act_phase;
     const int *forced_cells;   // sorted

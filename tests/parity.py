@@ -43,16 +43,22 @@ def rel_err(a, b, scale=None):
     return float(np.abs(a - b).max() / s)
 
 
-def compare(gpu_state, ora_state, filled):
+def compare(gpu_state, ora_state, filled, voxel_size=1e-3):
     """Per-quantity relative errors over filled cells.  Displacement and
-    velocity-like quantities use the oracle's largest magnitude as scale;
-    the quaternion is compared up to sign."""
+    velocity use the oracle's largest magnitude of that quantity as scale;
+    angular velocity uses the larger of its own largest magnitude and
+    max|v| / l (the spin a velocity difference of max|v| across one voxel
+    implies), so that a motion without rotation does not divide by rounding
+    noise; the quaternion is compared in absolute terms, up to sign."""
     out = {}
-    for k in ("u", "v", "w"):
+    for k in ("u", "v"):
         out[k] = rel_err(gpu_state[k][filled], ora_state[k][filled])
+    vmax = np.abs(ora_state["v"][filled]).max() if filled.any() else 0.0
+    wscale = max(np.abs(ora_state["w"][filled]).max() if filled.any() else 0.0, vmax / voxel_size)
+    out["w"] = rel_err(gpu_state["w"][filled], ora_state["w"][filled], wscale if wscale > 0 else None)
     qg = gpu_state["q"][filled]; qo = ora_state["q"][filled]
     sign = np.where((qg * qo).sum(1, keepdims=True) < 0, -1.0, 1.0)
-    out["q"] = float(np.abs(qg * sign - qo).max())
+    out["q"] = float(np.abs(qg * sign - qo).max()) if filled.any() else 0.0
     return out
 
 

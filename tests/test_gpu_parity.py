@@ -2,8 +2,8 @@
 
 Bars: FP64 state within 1e-10 of the oracle (displacement error over the
 largest displacement; velocities likewise over their largest magnitude), FP32
-largest displacement within 1e-4, and bitwise equality wherever the same
-arithmetic runs (run-to-run, split vs fused kernels).
+largest displacement within 1e-4, bitwise equality run to run, and the
+split and fused kernels (same device functions) equal to rounding.
 """
 import math
 
@@ -149,6 +149,47 @@ def test_edge_shapes_fp64(shape):
         assert max(e["u"], e["v"], e["w"]) < FP64_TOL, (kernel, e)
 
 
+@pytest.mark.parametrize("shape_id", range(len(vx.FUSED_SHAPES)))
+@pytest.mark.parametrize("zc", [1, 3, 0])
+def test_fused_tiles_fp64(shape_id, zc):
+    """Every fused tile shape and z-chunk (odd chunk lengths, chunk of one
+    slab, default) on a ragged lattice that leaves partial tiles in x and y
+    and a partial last chunk in z."""
+    w = hetero_block(shape=(7, 13, 53), seed=91)
+    announce("fused tile %s zc=%d" % (vx.FUSED_SHAPES[shape_id], zc))
+    g = build_gpu(w, 64, vx.KERNEL_FUSED)
+    g.set_fused_tile(shape_id, zc)
+    o = build_oracle(w)
+    g.step(60)
+    assert o.step(60) == 0
+    e = compare(g.read_state(), o.read_state(), filled_of(w))
+    assert max(e["u"], e["v"], e["w"]) < FP64_TOL and e["q"] < 1e-12, e
+
+
+def test_autotune_keeps_state():
+    """Autotuning times launches from the current state without advancing it."""
+    w = hetero_block(shape=(9, 10, 11), seed=95)
+    announce("autotune")
+    g = build_gpu(w, 32, vx.KERNEL_FUSED)
+    g.step(10)
+    before = g.read_state()
+    t0 = g.time
+    cfg = g.autotune(iters=2)
+    assert 0 <= cfg["shape"] < len(vx.FUSED_SHAPES) and cfg["zc"] >= 1
+    after = g.read_state()
+    assert g.time == t0
+    for k in ("u", "q", "v", "w"):
+        assert np.array_equal(before[k], after[k])
+    # same tiles as g: the heuristic tile for 10 steps, the tuned one after
+    ref = build_gpu(w, 32, vx.KERNEL_FUSED)
+    ref.step(10)
+    ref.set_fused_tile(cfg["shape"], cfg["zc"])
+    ref.step(10)
+    g.step(10)
+    e = compare(g.read_state(), ref.read_state(), filled_of(w))
+    assert e["u"] == 0.0 and e["q"] == 0.0
+
+
 def test_empty_lattice_steps():
     g = np.zeros((3, 3, 3), np.uint8)
     s = vx.Sim(g, [workloads.EMPTY, workloads._mat(1e6)])
@@ -158,7 +199,11 @@ def test_empty_lattice_steps():
 
 
 @pytest.mark.parametrize("precision", [32, 64])
-def test_deterministic_and_split_equals_fused(precision):
+def test_deterministic_and_split_matches_fused(precision):
+    """Run-to-run bitwise equality of the fused kernel; the split path runs
+    the same device functions but the compiler may contract them into FMAs
+    differently, so it agrees to rounding (FP64 1e-12, FP32 1e-5 of the
+    largest displacement)."""
     w = hetero_block(shape=(9, 10, 11), seed=71)
     announce("determinism p=%d" % precision)
     states = []
@@ -168,7 +213,10 @@ def test_deterministic_and_split_equals_fused(precision):
         states.append(s.read_state())
     for k in ("u", "q", "v", "w"):
         assert np.array_equal(states[0][k], states[1][k])
-        assert np.array_equal(states[0][k], states[2][k])
+    filled = filled_of(w)
+    e = compare(states[2], states[0], filled)
+    tol = 1e-12 if precision == 64 else 1e-5
+    assert e["u"] < tol and e["q"] < tol, e
 
 
 def test_unstable_reports_error():
