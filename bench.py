@@ -1,26 +1,28 @@
 """Throughput of the voxel-lattice time step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload random_block_100]
-                    [--precision 32|64] [--kernel fused|split] [--no-cpu]
+                    [--precision 32|64] [--kernel fused|split] [--no-cpu] [--no-fp64]
+                    [--no-hbm-leg] [--no-autotune]
 
-Default workload: a 100^3 lattice whose cells are drawn from a seed as empty
+Headline workload: a 100^3 lattice whose cells are drawn from a seed as empty
 (p = 0.1), soft 1 MPa (p = 0.45) or stiff 100 MPa (p = 0.45), density 1000,
-resting 5 mm above a rigid floor with friction, gravity on.  A step is one
-pass of the whole hot path (actuation, every bond, gather, floor/friction,
-integrate) over the lattice.  The state is resident in HBM before timing
-starts.  Prints one JSON line.
+5 mm above a rigid floor with friction, gravity on.  A step is one pass of the
+whole hot path (actuation, every bond, gather, floor/friction, integrate) over
+the lattice.  Its state (52 MB in FP32) fits the GPU's 256 MB last-level cache,
+so a second leg runs the HBM-resident case: a 256^3 lattice of 4 materials
+assigned from 64 seeded Voronoi blobs, thermal actuation, self-collision on.
 
-The metric is voxel-steps/s = filled voxels x steps / wall time of the K
-timed steps (HIP events on the stream the kernels are launched on, with a
-device synchronisation on both sides).
+The state is resident on the GPU before timing starts.  Prints one JSON line.
+voxel-steps/s = filled voxels x steps / wall time of the K timed steps (HIP
+events on the stream the kernels run on, device synchronisation on both
+sides).  The roofline figure uses the step kernel's own average launch time,
+measured the same way over dry-run launches that do not advance the state.
 """
 import argparse
 import json
 import os
 import sys
 import time
-
-import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -34,28 +36,33 @@ ALG_BYTES = {32: 13 * 4 * 2 + 3, 64: 13 * 8 * 2 + 3}
 def build_workload(name):
     import workloads
     if name.startswith("random_block_"):
-        n = int(name.split("_")[-1])
-        return workloads.random_block(n=n, seed=2)
+        return workloads.random_block(n=int(name.split("_")[-1]), seed=2)
     if name.startswith("blob_lattice_"):
-        n = int(name.split("_")[-1])
-        w = workloads.blob_lattice(n=n, seed=3)
-        return w
+        return workloads.blob_lattice(n=int(name.split("_")[-1]), seed=3)
     if name.startswith("cube_"):
-        n = int(name.split("_")[-1])
-        return workloads.solid_cube(n, zeta_bond=0.5, gravity=9.81, floor_on=1)
+        return workloads.solid_cube(int(name.split("_")[-1]), zeta_bond=0.5, gravity=9.81, floor_on=1)
     if name == "cantilever":
         return workloads.cantilever()
     raise SystemExit("unknown workload %s" % name)
 
 
-def time_gpu(w, precision, kernel, steps, warmup, autotune=True):
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def time_gpu(w, precision, kernel, steps, warmup, autotune=True, tile=None):
+    """Returns a dict with voxels, ms for `steps` steps, the tile and the
+    step kernel's own average launch time.  tile = (shape, zc) fixes the
+    fused kernel's tile instead of autotuning it."""
     import torch
     import paper_1212_2845_amd as vx
     torch.cuda.init()
     stream = torch.cuda.current_stream()
     s = vx.from_workload(w, precision=precision, kernel=kernel, stream=stream.cuda_stream)
     s.bind()
-    if autotune and kernel == vx.KERNEL_FUSED:
+    if tile is not None:
+        s.set_fused_tile(*tile)
+    elif autotune and kernel == vx.KERNEL_FUSED:
         s.autotune(iters=3)
     nvox = s.counters()["voxels"]
     if warmup:
@@ -68,11 +75,24 @@ def time_gpu(w, precision, kernel, steps, warmup, autotune=True):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    return nvox, ms, s
+    kernel_ms = s.time_kernel(iters=max(10, min(steps, 50)))
+    out = {"voxels": nvox, "ms": ms, "kernel_ms": kernel_ms,
+           "tile": s.fused_tile() if kernel == vx.KERNEL_FUSED else None}
+    del s
+    torch.cuda.empty_cache()
+    return out
 
 
-def cpu_baseline(w, budget_s=12.0):
-    """Oracle (FP64, one thread) on a bounded sample of the same workload."""
+def roofline(precision, nvox, kernel_ms):
+    alg = ALG_BYTES[precision]
+    achieved = alg * nvox / (kernel_ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_fused",
+            "kernel_ms": kernel_ms, "alg_bytes_per_voxel_step": alg, "voxels_per_launch": nvox}
+
+
+def cpu_baseline(w, budget_s=12.0, note=""):
+    """The oracle (FP64, one thread) on a bounded sample of the workload."""
     import oracle
     o = oracle.Sim(w["grid"], w["materials"], **w["params"])
     if w.get("fixed") is not None:
@@ -92,8 +112,8 @@ def cpu_baseline(w, budget_s=12.0):
         if el > budget_s or n >= 2000:
             break
     return {"value": nvox * n / el, "unit": "voxel-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "%d steps of the same %d-voxel lattice after 1 untimed step, FP64, one thread"
-                      % (n, nvox)}
+            "sample": "%d steps of the %d-voxel %s lattice after 1 untimed step, FP64, one thread%s"
+                      % (n, nvox, w["name"], note)}
 
 
 def main():
@@ -106,10 +126,17 @@ def main():
     ap.add_argument("--kernel", default="fused", choices=["fused", "split"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-hbm-leg", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tile", default=None, metavar="SHAPE:ZC",
+                    help="fix the fused tile of the first leg (shape index, z chunk) instead of autotuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (for scaling profiler byte counters)")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 4
@@ -120,50 +147,50 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5}), flush=True)
         return
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
     import paper_1212_2845_amd as vx
     kernel = vx.KERNEL_FUSED if args.kernel == "fused" else vx.KERNEL_SPLIT
+    autotune = not args.no_autotune
+    tile = tuple(int(v) for v in args.tile.split(":")) if args.tile else None
+
     w = build_workload(args.workload)
-    print("[bench] workload %s precision %d kernel %s steps %d warmup %d"
-          % (args.workload, args.precision, args.kernel, args.steps, args.warmup), file=sys.stderr, flush=True)
-    nvox, ms, sim = time_gpu(w, args.precision, kernel, args.steps, args.warmup, not args.no_autotune)
-    tile = sim.fused_tile() if kernel == vx.KERNEL_FUSED else None
-    value = nvox * args.steps / (ms / 1e3)
-    ms_step = ms / args.steps
-    alg = ALG_BYTES[args.precision]
-    achieved = alg * nvox / (ms_step / 1e3) / 1e9
+    log("workload %s precision %d kernel %s steps %d warmup %d"
+        % (args.workload, args.precision, args.kernel, args.steps, args.warmup))
+    r = time_gpu(w, args.precision, kernel, args.steps, args.warmup, autotune, tile)
     out = {
         "metric": "voxel-steps/s",
-        "value": value,
+        "value": r["voxels"] * args.steps / (r["ms"] / 1e3),
         "unit": "voxel-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r["ms"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if args.precision == 32 else "f64",
         "data": "synthetic",
-        "config": {"workload": w["name"], "cells": int(w["grid"].size), "voxels": int(nvox),
-                   "kernel": args.kernel, "tile": tile},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "alg_bytes_per_voxel_step": alg},
+        "config": {"workload": w["name"], "cells": int(w["grid"].size), "voxels": int(r["voxels"]),
+                   "kernel": args.kernel, "tile": r["tile"], "state_bytes": int(w["grid"].size) * 13 *
+                   (4 if args.precision == 32 else 8), "cache_resident": True},
+        "roofline": roofline(args.precision, r["voxels"], r["kernel_ms"]),
     }
-    del sim
     if not args.no_fp64 and args.precision == 32:
-        print("[bench] fp64 leg", file=sys.stderr, flush=True)
-        n64, ms64, s64 = time_gpu(w, 64, kernel, args.steps, args.warmup, not args.no_autotune)
-        tile64 = s64.fused_tile() if kernel == vx.KERNEL_FUSED else None
-        del s64
-        out["fp64"] = {"value": n64 * args.steps / (ms64 / 1e3), "ms_per_step": ms64 / args.steps, "tile": tile64,
-                       "roofline_frac": ALG_BYTES[64] * n64 / (ms64 / args.steps / 1e3) / 1e9 / HBM_PEAK_GBS}
+        log("fp64 leg")
+        r64 = time_gpu(w, 64, kernel, args.steps, args.warmup, autotune)
+        out["fp64"] = {"value": r64["voxels"] * args.steps / (r64["ms"] / 1e3),
+                       "ms_per_step": r64["ms"] / args.steps, "tile": r64["tile"],
+                       "roofline": roofline(64, r64["voxels"], r64["kernel_ms"])}
+    if not args.no_hbm_leg:
+        log("hbm-resident leg: blob_lattice_256")
+        w3 = build_workload("blob_lattice_256")
+        r3 = time_gpu(w3, 32, kernel, args.steps, args.warmup, autotune)
+        out["hbm_resident"] = {"workload": w3["name"], "dtype": "f32",
+                               "value": r3["voxels"] * args.steps / (r3["ms"] / 1e3),
+                               "ms_per_step": r3["ms"] / args.steps, "tile": r3["tile"],
+                               "roofline": roofline(32, r3["voxels"], r3["kernel_ms"])}
+        del w3
     if not args.no_cpu:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 

@@ -177,6 +177,12 @@ int vx_get_fused_tile(vx_handle h, int32_t *shape, int32_t *tx, int32_t *ty, int
  * Errors: VX_ESTATE before bind. */
 int vx_autotune(vx_handle h, int32_t iters, int32_t *shape, int32_t *zc);
 
+/* Average wall time of one launch of the step kernel(s) alone (the fused
+ * kernel, or the four kernels of the split path), over iters dry-run
+ * launches from the current state, measured with HIP events on the
+ * handle's stream; the state does not advance.  For roofline figures. */
+int vx_time_kernel(vx_handle h, int32_t iters, double *ms_per_launch);
+
 /* Free host-side data of the handle (not the caller's workspace). */
 int vx_destroy(vx_handle h);
 

@@ -31,7 +31,7 @@ EXPORTED = ["vx_create", "vx_workspace_bytes", "vx_bind_workspace", "vx_set_fixe
             "vx_fixed_region", "vx_forced_region", "vx_set_actuation", "vx_set_velocity", "vx_step",
             "vx_read_state", "vx_write_state", "vx_read_flags", "vx_get_dt", "vx_get_time",
             "vx_counters", "vx_candidates", "vx_set_kernel", "vx_set_fused_tile", "vx_get_fused_tile",
-            "vx_autotune", "vx_destroy", "vx_last_error"]
+            "vx_autotune", "vx_time_kernel", "vx_destroy", "vx_last_error"]
 
 FUSED_SHAPES = [(32, 8), (64, 4), (16, 16), (50, 5), (20, 12)]
 
@@ -92,6 +92,7 @@ def lib():
     pi32 = C.POINTER(i32)
     L.vx_get_fused_tile.argtypes = [P, pi32, pi32, pi32, pi32]
     L.vx_autotune.argtypes = [P, i32, pi32, pi32]
+    L.vx_time_kernel.argtypes = [P, i32, C.POINTER(C.c_double)]
     L.vx_destroy.argtypes = [P]
     L.vx_last_error.argtypes = [P]
     L.vx_last_error.restype = C.c_char_p
@@ -209,6 +210,13 @@ class Sim:
         v = [C.c_int32() for _ in range(4)]
         self._check(lib().vx_get_fused_tile(self.h, *[C.byref(x) for x in v]))
         return {"shape": v[0].value, "tx": v[1].value, "ty": v[2].value, "zc": v[3].value}
+
+    def time_kernel(self, iters=20):
+        """Average ms of one step-kernel launch (dry runs, state unchanged)."""
+        self.bind()
+        ms = C.c_double()
+        self._check(lib().vx_time_kernel(self.h, int(iters), C.byref(ms)))
+        return ms.value
 
     def autotune(self, iters=5):
         self.bind()

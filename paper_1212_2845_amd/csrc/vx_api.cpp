@@ -446,6 +446,39 @@ static int autotune(vx_sim *h, int iters, int32_t *shape_out, int32_t *zc_out) {
     return VX_OK;
 }
 
+// Average duration of the step kernel(s) alone, from the current state,
+// without advancing it (same dry-run launches as the autotuner).
+template <typename T>
+static int time_kernel(vx_sim *h, int iters, double *ms_per_launch) {
+    StepArgs<T> a = make_args<T>(h);
+    if (h->p.self_collision_on) {
+        CollideArgs c = make_collide(h);
+        HIP_OK(h, launch_rebuild<T>(a, c, h->stream));
+        HIP_OK(h, launch_contact<T>(a, c, (T *)(h->ws + h->L.contact_F), h->stream));
+    }
+    const bool split = h->kernel_kind == 1 || h->n_mat > kFusedMaxMat;
+    const FusedCfg cfg = fused_cfg(h);
+    auto launch = [&]() { return split ? launch_split_step<T>(a, h->stream) : launch_fused_step<T>(a, cfg, h->stream); };
+    hipEvent_t e0, e1;
+    HIP_OK(h, hipEventCreate(&e0));
+    HIP_OK(h, hipEventCreate(&e1));
+    HIP_OK(h, launch());
+    HIP_OK(h, hipEventRecord(e0, h->stream));
+    for (int i = 0; i < iters; ++i) HIP_OK(h, launch());
+    HIP_OK(h, hipEventRecord(e1, h->stream));
+    HIP_OK(h, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_OK(h, hipEventElapsedTime(&ms, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    Scalars *sc = (Scalars *)(h->ws + h->L.scalars);
+    const unsigned long long zero = 0;
+    HIP_OK(h, hipMemcpyAsync(&sc->vmax_bits, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    *ms_per_launch = (double)ms / iters;
+    return VX_OK;
+}
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -810,6 +843,13 @@ int vx_autotune(vx_handle h, int32_t iters, int32_t *shape, int32_t *zc) {
     if (!h->bound) return fail(h, VX_ESTATE, "vx_autotune before vx_bind_workspace");
     if (h->n_mat > kFusedMaxMat) return fail(h, VX_ESTATE, "palette too large for the fused kernel");
     return h->precision == 64 ? autotune<double>(h, iters, shape, zc) : autotune<float>(h, iters, shape, zc);
+}
+
+int vx_time_kernel(vx_handle h, int32_t iters, double *ms_per_launch) {
+    if (!h || iters <= 0 || !ms_per_launch) return VX_EINVAL;
+    if (!h->bound) return fail(h, VX_ESTATE, "vx_time_kernel before vx_bind_workspace");
+    return h->precision == 64 ? time_kernel<double>(h, iters, ms_per_launch)
+                              : time_kernel<float>(h, iters, ms_per_launch);
 }
 
 int vx_set_kernel(vx_handle h, int32_t kind) {

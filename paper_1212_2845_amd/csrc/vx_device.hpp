@@ -9,6 +9,13 @@ namespace vx {
 
 template <typename T> struct V3 { T x, y, z; };
 
+template <int I, typename T>
+__device__ __forceinline__ T comp(const V3<T> &v) {
+    if constexpr (I == 0) return v.x;
+    else if constexpr (I == 1) return v.y;
+    else return v.z;
+}
+
 template <typename T> __device__ __forceinline__ T dsqrt(T a);
 template <> __device__ __forceinline__ float dsqrt<float>(float a) { return sqrtf(a); }
 template <> __device__ __forceinline__ double dsqrt<double>(double a) { return sqrt(a); }
@@ -119,19 +126,25 @@ struct VoxKin {
     T eps;                 // thermal strain at t_n
 };
 
-// Columns of the rotation matrix of a unit quaternion (body -> world).
+// Columns of the rotation matrix of a unit quaternion (body -> world), and
+// its diagonal minus one (small near the identity, computed without
+// cancellation).
 template <typename T>
 struct Rot {
     V3<T> c[3];
+    T dm1[3];
 };
 
 template <typename T>
 __device__ __forceinline__ Rot<T> rot_of(T w, T x, T y, T z) {
     Rot<T> R;
-    const T one = T(1), two = T(2);
-    R.c[0] = {one - two * (y * y + z * z), two * (x * y + w * z), two * (x * z - w * y)};
-    R.c[1] = {two * (x * y - w * z), one - two * (x * x + z * z), two * (y * z + w * x)};
-    R.c[2] = {two * (x * z + w * y), two * (y * z - w * x), one - two * (x * x + y * y)};
+    const T two = T(2);
+    R.dm1[0] = -two * (y * y + z * z);
+    R.dm1[1] = -two * (x * x + z * z);
+    R.dm1[2] = -two * (x * x + y * y);
+    R.c[0] = {T(1) + R.dm1[0], two * (x * y + w * z), two * (x * z - w * y)};
+    R.c[1] = {two * (x * y - w * z), T(1) + R.dm1[1], two * (y * z + w * x)};
+    R.c[2] = {two * (x * z + w * y), two * (y * z - w * x), T(1) + R.dm1[2]};
     return R;
 }
 
@@ -201,20 +214,22 @@ __device__ __forceinline__ void rel_rotvec(const VoxKin<T> &A, const VoxKin<T> &
 // (voxel 2).  Co-rotational: the bond is expressed in the frame of voxel 1
 // with its axis permuted onto +x (basis ex, ey, ez: columns of voxel 1's
 // rotation), where only voxel 2's six displacements remain (reduced forces
-// of Eq. 13-24, with the z-force sign of the full matrix Eq. 7).  d is the
-// world separation D_B - D_A, (tx, ty, tz) the relative rotation in the
-// bond frame.  The result is rotated back to the world frame and bond
-// damping (Eq. 33-35) is added.
+// of Eq. 13-24, with the z-force sign of the full matrix Eq. 7).  The
+// separation D_B - D_A is du + l e_axis (du the difference of
+// displacements); ex_a, ey_a, ez_a are the axis components of the basis
+// and exm1 = ex_a - 1, so the stretch X2 = ex.du + l (ex_a - 1) - l eps_mean
+// never subtracts two numbers close to l.  (tx, ty, tz) is the relative
+// rotation in the bond frame.  The result is rotated back to the world
+// frame and bond damping (Eq. 33-35) is added.
 template <typename T>
-__device__ __forceinline__ BondOut<T> bond_core(const VoxKin<T> &A, const VoxKin<T> &B, const T d[3],
-                                                const V3<T> &ex, const V3<T> &ey, const V3<T> &ez, T tx,
-                                                T ty, T tz, const BondK<T> &K, const LatK<T> &C) {
-    const T dlx = ex.x * d[0] + ex.y * d[1] + ex.z * d[2];
-    const T dly = ey.x * d[0] + ey.y * d[1] + ey.z * d[2];
-    const T dlz = ez.x * d[0] + ez.y * d[1] + ez.z * d[2];
+__device__ __forceinline__ BondOut<T> bond_core(const VoxKin<T> &A, const VoxKin<T> &B, const T du[3],
+                                                const T d[3], const V3<T> &ex, const V3<T> &ey,
+                                                const V3<T> &ez, T exm1, T ey_a, T ez_a, T tx, T ty, T tz,
+                                                const BondK<T> &K, const LatK<T> &C) {
     // rest length stretched by the mean thermal strain (Eq. 40)
-    const T L = C.l * (T(1) + T(0.5) * (A.eps + B.eps));
-    const T X2 = dlx - L, Y2 = dly, Z2 = dlz;
+    const T X2 = ex.x * du[0] + ex.y * du[1] + ex.z * du[2] + C.l * (exm1 - T(0.5) * (A.eps + B.eps));
+    const T Y2 = ey.x * du[0] + ey.y * du[1] + ey.z * du[2] + C.l * ey_a;
+    const T Z2 = ez.x * du[0] + ez.y * du[1] + ez.z * du[2] + C.l * ez_a;
     const T b1 = K.a1, b2 = K.a1 * C.hl, b3 = K.a1 * C.l26, b3x2 = K.a1 * C.l23;
     // local nodal forces K u (u1 = 0)
     const T f2x = K.a1 * X2;
@@ -256,18 +271,21 @@ template <typename T, int AX>
 __device__ __forceinline__ BondOut<T> bond_eval(const VoxKin<T> &A, const Rot<T> &RA, const VoxKin<T> &B,
                                                 const BondK<T> &K, const LatK<T> &C) {
     constexpr int A0 = AX, A1 = (AX + 1) % 3, A2 = (AX + 2) % 3;
-    T d[3] = {B.ux - A.ux, B.uy - A.uy, B.uz - A.uz};
+    const T du[3] = {B.ux - A.ux, B.uy - A.uy, B.uz - A.uz};
+    T d[3] = {du[0], du[1], du[2]};
     d[AX] += C.l;
     T th[3];
     rel_rotvec(A, B, th);
-    return bond_core(A, B, d, RA.c[A0], RA.c[A1], RA.c[A2], th[A0], th[A1], th[A2], K, C);
+    return bond_core(A, B, du, d, RA.c[A0], RA.c[A1], RA.c[A2], RA.dm1[A0], comp<AX>(RA.c[A1]),
+                     comp<AX>(RA.c[A2]), th[A0], th[A1], th[A2], K, C);
 }
 
 // Bond along x (yaxis = false) or y (yaxis = true), chosen per lane.
 template <typename T>
 __device__ __forceinline__ BondOut<T> bond_eval_xy(const VoxKin<T> &A, const Rot<T> &RA, const VoxKin<T> &B,
                                                    const BondK<T> &K, const LatK<T> &C, bool yaxis) {
-    T d[3] = {B.ux - A.ux, B.uy - A.uy, B.uz - A.uz};
+    const T du[3] = {B.ux - A.ux, B.uy - A.uy, B.uz - A.uz};
+    T d[3] = {du[0], du[1], du[2]};
     d[0] += yaxis ? T(0) : C.l;
     d[1] += yaxis ? C.l : T(0);
     T th[3];
@@ -275,8 +293,10 @@ __device__ __forceinline__ BondOut<T> bond_eval_xy(const VoxKin<T> &A, const Rot
     const V3<T> ex = yaxis ? RA.c[1] : RA.c[0];
     const V3<T> ey = yaxis ? RA.c[2] : RA.c[1];
     const V3<T> ez = yaxis ? RA.c[0] : RA.c[2];
+    const T exm1 = yaxis ? RA.dm1[1] : RA.dm1[0];
+    const T ey_a = yaxis ? ey.y : ey.x, ez_a = yaxis ? ez.y : ez.x;
     const T tx = yaxis ? th[1] : th[0], ty = yaxis ? th[2] : th[1], tz = yaxis ? th[0] : th[2];
-    return bond_core(A, B, d, ex, ey, ez, tx, ty, tz, K, C);
+    return bond_core(A, B, du, d, ex, ey, ez, exm1, ey_a, ez_a, tx, ty, tz, K, C);
 }
 
 // FP32 evaluates the signal from the host-reduced phase 2 pi f t_n mod 2 pi.
@@ -374,8 +394,9 @@ __device__ __forceinline__ void voxel_update(const StepArgs<T> &a, unsigned c, u
     if (a.floor_on) {
         const unsigned nxy = (unsigned)a.nx * (unsigned)a.ny;
         const int iz = (int)(c / nxy);
-        const T Dz = a.origin_z + (T(iz) + T(0.5)) * a.l + uz;
-        const T pen = T(0.5) * a.l * (T(1) + eps) - Dz;
+        // s/2 - D_z with D_z = origin + (iz + 1/2) l + u_z; the half-voxel
+        // terms cancel exactly
+        const T pen = T(0.5) * a.l * eps - uz - (a.origin_z + T(iz) * a.l);
         if (pen > T(0)) {
             Fn = mc.kv * pen - mc.cfloor * vz;
             if (Fn < T(0)) Fn = T(0);

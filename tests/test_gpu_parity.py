@@ -229,3 +229,76 @@ def test_unstable_reports_error():
     announce("unstable")
     rc = s.step_rc(3000)
     assert rc == vx.VX_EUNSTABLE
+
+
+def _neighbourhood_oracle(w, state, cell, nx, ny, nz, dt):
+    """Oracle on the 3x3x3 block around `cell` (cells outside the lattice
+    empty), with the same materials, parameters, state and timestep dt (the
+    block alone would pick its own stable step from fewer material pairs);
+    returns the oracle's state of the centre after one step."""
+    x, y, z = cell % nx, (cell // nx) % ny, cell // (nx * ny)
+    sub = np.zeros((3, 3, 3), np.uint8)
+    idx = np.full((3, 3, 3), -1, np.int64)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if abs(dx) + abs(dy) + abs(dz) > 1:
+                    continue            # only the face neighbours act on the centre
+                X, Y, Z = x + dx, y + dy, z + dz
+                if 0 <= X < nx and 0 <= Y < ny and 0 <= Z < nz:
+                    c = X + nx * (Y + ny * Z)
+                    sub[dz + 1, dy + 1, dx + 1] = w["grid"].reshape(-1)[c]
+                    idx[dz + 1, dy + 1, dx + 1] = c
+    params = dict(w["params"])
+    o = params.get("origin", (0.0, 0.0, 0.0))
+    l = params["voxel_size"]
+    params["origin"] = (o[0] + (x - 1) * l, o[1] + (y - 1) * l, o[2] + (z - 1) * l)
+    params["self_collision_on"] = 0
+    params["dt_scale"] = 1.0
+    dt_own = oracle.Sim(sub, w["materials"], **params).dt
+    params["dt_scale"] = dt / dt_own
+    assert params["dt_scale"] <= 1.0
+    orc = oracle.Sim(sub, w["materials"], **params)
+    assert abs(orc.dt / dt - 1.0) < 1e-15
+    sel = idx.reshape(-1)
+    st = {}
+    for k, d in (("u", 3), ("q", 4), ("v", 3), ("w", 3)):
+        a = np.zeros((27, d))
+        if k == "q":
+            a[:, 0] = 1.0
+        a[sel >= 0] = state[k][sel[sel >= 0]]
+        st[k] = a
+    orc.write_state(**st)
+    assert orc.step(1) == 0
+    r = orc.read_state()
+    return {k: r[k][13] for k in r}
+
+
+@pytest.mark.parametrize("precision,tol", [(64, 1e-10), (32, 1e-4)])
+def test_full_size_blob_lattice_sampled(precision, tol):
+    """256^3 lattice of the HBM-resident benchmark, in the launch
+    configuration bench.py times (fused kernel, autotuned tile): one step
+    from a perturbed state, then 48 sampled voxels (interior, faces, edges,
+    corners) recomputed one by one by the oracle on their neighbourhood."""
+    n = 256
+    w = workloads.blob_lattice(n=n, seed=3)
+    w["params"]["temp_phase"] = 0.7      # non-zero temperature at t = 0
+    ncell = n ** 3
+    announce("full size 256^3 p=%d" % precision)
+    st = perturbed_state(ncell, 97, 1e-6, 1e-3, 0.5, 1e-3)
+    g = vx.from_workload(w, precision=precision, kernel=vx.KERNEL_FUSED)
+    g.write_state(**st)
+    g.autotune(iters=1)
+    if precision == 32:
+        st = g.read_state()          # the FP32-rounded input both sides start from
+    g.step(1)
+    out = g.read_state()
+    rng = np.random.Generator(np.random.PCG64(98))
+    picks = [0, n - 1, n * n - 1, ncell - 1, n * n * (n // 2) + n * 5 + 7]
+    picks += rng.integers(0, ncell, 43).tolist()
+    for c in picks:
+        ref = _neighbourhood_oracle(w, st, int(c), n, n, n, g.dt)
+        for k in ("u", "v", "w", "q"):
+            scale = max(np.abs(ref[k]).max(), np.abs(st[k][c]).max(), 1e-30)
+            err = np.abs(out[k][c] - ref[k]).max() / scale
+            assert err < tol, (c, k, err, out[k][c], ref[k])
