@@ -91,6 +91,55 @@ def roofline(precision, nvox, kernel_ms):
             "kernel_ms": kernel_ms, "alg_bytes_per_voxel_step": alg, "voxels_per_launch": nvox}
 
 
+def time_batch(count, steps, one_by_one_sample=64, one_by_one_steps=100):
+    """Batched objects: one persistent launch for all objects vs the same
+    objects stepped one at a time through the single-lattice path."""
+    import torch
+    import paper_1212_2845_amd as vx
+    import workloads
+    objs = workloads.batch_objects(count=count, seed=4, steps=steps)
+    mats, params = objs[0]["materials"], objs[0]["params"]
+    stream = torch.cuda.current_stream()
+    b = vx.Batch([o["grid"] for o in objs], mats, precision=32, stream=stream.cuda_stream, **params)
+    b.bind()
+    n_wg = b.autotune(steps=20)
+    nvox = b.counters()["voxels"]
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del b
+    torch.cuda.empty_cache()
+    # one at a time: a sample of the same objects, each its own lattice
+    sample = objs[:one_by_one_sample]
+    sims = [vx.from_workload(o, precision=32, stream=stream.cuda_stream) for o in sample]
+    for s in sims:
+        s.bind()
+        s.step(2)
+    nvox1 = sum(s.counters()["voxels"] for s in sims)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.step(one_by_one_steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    del sims
+    torch.cuda.empty_cache()
+    batched = nvox * steps / (ms / 1e3)
+    single = nvox1 * one_by_one_steps / el
+    return {"workload": "batch_objects_%d" % count, "objects": count, "voxels": nvox, "steps": steps,
+            "dtype": "f32", "value": batched, "ms": ms, "workgroups": n_wg,
+            "one_by_one": {"value": single, "objects": len(sample), "steps": one_by_one_steps,
+                           "note": "first %d objects, each stepped alone through the fused single-lattice path"
+                                   % len(sample)},
+            "speedup": batched / single,
+            "roofline": roofline(32, nvox, ms / steps)}
+
+
 def cpu_baseline(w, budget_s=12.0, note=""):
     """The oracle (FP64, one thread) on a bounded sample of the workload."""
     import oracle
@@ -128,6 +177,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-hbm-leg", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-batch-leg", action="store_true")
+    ap.add_argument("--batch-objects", type=int, default=4096)
+    ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--tile", default=None, metavar="SHAPE:ZC",
                     help="fix the fused tile of the first leg (shape index, z chunk) instead of autotuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -171,7 +223,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "cells": int(w["grid"].size), "voxels": int(r["voxels"]),
                    "kernel": args.kernel, "tile": r["tile"], "state_bytes": int(w["grid"].size) * 13 *
-                   (4 if args.precision == 32 else 8), "cache_resident": True},
+                   (4 if args.precision == 32 else 8),
+                   "cache_resident": 2 * int(w["grid"].size) * 13 * (4 if args.precision == 32 else 8) < 256e6},
         "roofline": roofline(args.precision, r["voxels"], r["kernel_ms"]),
     }
     if not args.no_fp64 and args.precision == 32:
@@ -189,6 +242,9 @@ def main():
                                "ms_per_step": r3["ms"] / args.steps, "tile": r3["tile"],
                                "roofline": roofline(32, r3["voxels"], r3["kernel_ms"])}
         del w3
+    if not args.no_batch_leg:
+        log("batched leg: %d objects, %d steps" % (args.batch_objects, args.batch_steps))
+        out["batched"] = time_batch(args.batch_objects, args.batch_steps)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w)

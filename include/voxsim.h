@@ -183,6 +183,60 @@ int vx_autotune(vx_handle h, int32_t iters, int32_t *shape, int32_t *zc);
  * handle's stream; the state does not advance.  For roofline figures. */
 int vx_time_kernel(vx_handle h, int32_t iters, double *ms_per_launch);
 
+/* ------------------------------------------------------------------ */
+/* Batches: many independent objects stepped by one persistent launch  */
+/* ------------------------------------------------------------------ */
+
+/* One object of a batch: its own material grid (cell order as vx_create)
+ * and the world position of its cell (0,0,0)'s lower corner (only z is
+ * used, for the floor). */
+typedef struct vx_object {
+    const uint8_t *grid;
+    int32_t nx, ny, nz;
+    int32_t reserved;      /* must be 0 */
+    double origin[3];
+} vx_object;
+
+typedef struct vx_batch_sim *vx_batch;
+
+/* Create a batch of n_obj objects sharing one palette (at most 16
+ * materials) and one parameter set (self-collision must be off: objects do
+ * not interact).  Each object gets its own stable timestep (Eq. 31-32 over
+ * its own bonds) and its own time.  The grids are copied.  Errors:
+ * VX_EINVAL as vx_create, or if the concatenated state would exceed 4 GiB. */
+int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *palette, int32_t n_mat,
+                    const vx_params *params, int32_t precision, void *stream, vx_batch *out);
+int vx_batch_workspace_bytes(vx_batch b, uint64_t *bytes);
+/* Bind the caller's device workspace (256-byte aligned) and upload the rest
+ * state of every object. */
+int vx_batch_bind_workspace(vx_batch b, void *device_ptr, uint64_t bytes);
+
+/* Advance every object n steps: one persistent kernel launch per
+ * max_steps_per_launch steps (default 2000), each workgroup looping all
+ * steps over its own objects.  Errors: VX_ESTATE before bind, VX_EUNSTABLE
+ * on a non-finite state. */
+int vx_batch_step(vx_batch b, int64_t n);
+
+/* Read / overwrite one object's state; layouts as vx_read_state over the
+ * object's own cells. */
+int vx_batch_read_state(vx_batch b, int32_t obj, double *u, double *q, double *vel, double *omega);
+int vx_batch_write_state(vx_batch b, int32_t obj, const double *u, const double *q, const double *vel,
+                         const double *omega);
+int vx_batch_get_dt(vx_batch b, int32_t obj, double *dt);
+/* out[0] steps, out[1] objects, out[2] cells, out[3] filled voxels. */
+int vx_batch_counters(vx_batch b, int64_t out[4]);
+
+/* Workgroups of the persistent launch (0: a default of 4 per compute unit,
+ * at most one per object) and steps per launch (0: keep).  Objects are
+ * assigned to workgroups by longest-processing-time packing on cell count. */
+int vx_batch_set_launch(vx_batch b, int32_t n_workgroups, int32_t max_steps_per_launch);
+
+/* Time candidate workgroup counts over `steps` steps and keep the fastest;
+ * the state and time are restored afterwards. */
+int vx_batch_autotune(vx_batch b, int32_t steps, int32_t *n_workgroups);
+int vx_batch_destroy(vx_batch b);
+const char *vx_batch_last_error(vx_batch b);
+
 /* Free host-side data of the handle (not the caller's workspace). */
 int vx_destroy(vx_handle h);
 

@@ -31,7 +31,10 @@ EXPORTED = ["vx_create", "vx_workspace_bytes", "vx_bind_workspace", "vx_set_fixe
             "vx_fixed_region", "vx_forced_region", "vx_set_actuation", "vx_set_velocity", "vx_step",
             "vx_read_state", "vx_write_state", "vx_read_flags", "vx_get_dt", "vx_get_time",
             "vx_counters", "vx_candidates", "vx_set_kernel", "vx_set_fused_tile", "vx_get_fused_tile",
-            "vx_autotune", "vx_time_kernel", "vx_destroy", "vx_last_error"]
+            "vx_autotune", "vx_time_kernel", "vx_destroy", "vx_last_error",
+            "vx_batch_create", "vx_batch_workspace_bytes", "vx_batch_bind_workspace", "vx_batch_step",
+            "vx_batch_read_state", "vx_batch_write_state", "vx_batch_get_dt", "vx_batch_counters",
+            "vx_batch_set_launch", "vx_batch_autotune", "vx_batch_destroy", "vx_batch_last_error"]
 
 FUSED_SHAPES = [(32, 8), (64, 4), (16, 16), (50, 5), (20, 12)]
 
@@ -45,6 +48,11 @@ class VoxsimError(RuntimeError):
 class Material(C.Structure):
     _fields_ = [("E", C.c_double), ("nu", C.c_double), ("rho", C.c_double),
                 ("cte", C.c_double), ("mu_s", C.c_double), ("mu_d", C.c_double)]
+
+
+class Object(C.Structure):
+    _fields_ = [("grid", C.c_void_p), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("reserved", C.c_int32), ("origin", C.c_double * 3)]
 
 
 class Params(C.Structure):
@@ -96,8 +104,21 @@ def lib():
     L.vx_destroy.argtypes = [P]
     L.vx_last_error.argtypes = [P]
     L.vx_last_error.restype = C.c_char_p
+    L.vx_batch_create.argtypes = [P, i32, P, i32, P, i32, P, C.POINTER(P)]
+    L.vx_batch_workspace_bytes.argtypes = [P, C.POINTER(u64)]
+    L.vx_batch_bind_workspace.argtypes = [P, P, u64]
+    L.vx_batch_step.argtypes = [P, i64]
+    L.vx_batch_read_state.argtypes = [P, i32, P, P, P, P]
+    L.vx_batch_write_state.argtypes = [P, i32, P, P, P, P]
+    L.vx_batch_get_dt.argtypes = [P, i32, C.POINTER(C.c_double)]
+    L.vx_batch_counters.argtypes = [P, C.POINTER(C.c_int64)]
+    L.vx_batch_set_launch.argtypes = [P, i32, i32]
+    L.vx_batch_autotune.argtypes = [P, i32, pi32]
+    L.vx_batch_destroy.argtypes = [P]
+    L.vx_batch_last_error.argtypes = [P]
+    L.vx_batch_last_error.restype = C.c_char_p
     for n in EXPORTED:
-        if n != "vx_last_error":
+        if n not in ("vx_last_error", "vx_batch_last_error"):
             getattr(L, n).restype = C.c_int
     _lib = L
     return L
@@ -314,3 +335,93 @@ def from_workload(w, precision=64, kernel=KERNEL_FUSED, stream=None):
     if w.get("velocity") is not None:
         s.set_velocity(w["velocity"])
     return s
+
+
+class Batch:
+    """Many independent objects (same palette and parameters) stepped by one
+    persistent launch.  ``grids`` is a list of uint8 arrays (nz, ny, nx);
+    ``origins`` an optional list of (x, y, z) lower-corner positions."""
+
+    def __init__(self, grids, materials, precision=32, device=None, stream=None, origins=None, **params):
+        L = lib()
+        self._grids = [np.ascontiguousarray(g, dtype=np.uint8) for g in grids]
+        n = len(self._grids)
+        objs = (Object * n)()
+        for i, g in enumerate(self._grids):
+            objs[i].grid = g.ctypes.data_as(C.c_void_p)
+            objs[i].nz, objs[i].ny, objs[i].nx = g.shape
+            objs[i].reserved = 0
+            o = origins[i] if origins is not None else params.get("origin", (0.0, 0.0, 0.0))
+            objs[i].origin[0], objs[i].origin[1], objs[i].origin[2] = o
+        self._objs = objs
+        self._pal = make_palette(materials)
+        self._prm = make_params(**params)
+        self.precision = int(precision)
+        self._device = device
+        self._stream = stream
+        self._ws = None
+        h = C.c_void_p()
+        rc = L.vx_batch_create(C.cast(objs, C.c_void_p), n, C.cast(self._pal, C.c_void_p), len(materials),
+                               C.cast(C.pointer(self._prm), C.c_void_p), self.precision,
+                               None if stream is None else C.c_void_p(int(stream)), C.byref(h))
+        if rc != VX_OK:
+            raise VoxsimError(rc, "vx_batch_create rejected the objects, palette or parameters")
+        self.h = h
+        self.n = n
+
+    def _check(self, rc):
+        if rc != VX_OK:
+            raise VoxsimError(rc, lib().vx_batch_last_error(self.h).decode())
+
+    def bind(self):
+        if self._ws is not None:
+            return
+        import torch
+        dev = self._device or torch.device("cuda", torch.cuda.current_device())
+        nb = C.c_uint64()
+        self._check(lib().vx_batch_workspace_bytes(self.h, C.byref(nb)))
+        self._ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+        self._check(lib().vx_batch_bind_workspace(self.h, C.c_void_p(self._ws.data_ptr()), nb.value))
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.vx_batch_destroy(h)
+            self.h = None
+
+    def set_launch(self, n_workgroups=0, max_steps_per_launch=0):
+        self._check(lib().vx_batch_set_launch(self.h, int(n_workgroups), int(max_steps_per_launch)))
+
+    def autotune(self, steps=20):
+        self.bind()
+        nw = C.c_int32()
+        self._check(lib().vx_batch_autotune(self.h, int(steps), C.byref(nw)))
+        return nw.value
+
+    def step(self, n=1):
+        self.bind()
+        self._check(lib().vx_batch_step(self.h, int(n)))
+
+    def dt(self, i):
+        d = C.c_double()
+        self._check(lib().vx_batch_get_dt(self.h, int(i), C.byref(d)))
+        return d.value
+
+    def counters(self):
+        out = (C.c_int64 * 4)()
+        self._check(lib().vx_batch_counters(self.h, out))
+        return {"steps": out[0], "objects": out[1], "cells": out[2], "voxels": out[3]}
+
+    def read_state(self, i):
+        self.bind()
+        nc = self._grids[i].size
+        u = np.empty((nc, 3)); q = np.empty((nc, 4)); v = np.empty((nc, 3)); w = np.empty((nc, 3))
+        self._check(lib().vx_batch_read_state(self.h, int(i), _ptr(u), _ptr(q), _ptr(v), _ptr(w)))
+        return {"u": u, "q": q, "v": v, "w": w}
+
+    def write_state(self, i, u=None, q=None, v=None, w=None):
+        self.bind()
+        nc = self._grids[i].size
+        conv = lambda a, k: None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(nc, k)
+        u, q, v, w = conv(u, 3), conv(q, 4), conv(v, 3), conv(w, 3)
+        self._check(lib().vx_batch_write_state(self.h, int(i), _ptr(u), _ptr(q), _ptr(v), _ptr(w)))

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/voxsim.h"
+#include "vx_host.hpp"
 #include "vx_launch.hpp"
 #include "vx_types.hpp"
 
@@ -96,45 +97,9 @@ static int fail(vx_sim *h, int code, const std::string &msg) {
 // ---------------------------------------------------------------------------
 // packing
 // ---------------------------------------------------------------------------
-static double composite(double a, double b) { return 2.0 * a * b / (a + b); }
-
 template <typename T>
 static void pack_tables(const vx_sim *h, std::vector<MatConst<T>> &mc, std::vector<PairConst<T>> &pc) {
-    const double l = h->p.voxel_size;
-    mc.assign(h->n_mat, MatConst<T>{});
-    for (int i = 1; i < h->n_mat; ++i) {
-        const vx_material &M = h->pal[i];
-        const double m = M.rho * l * l * l;
-        const double I = m * l * l / 6.0;           // solid cube about its centre
-        const double kv = M.E * l;
-        const double kphi = M.E * l * l * l / 6.0;
-        MatConst<T> &c = mc[i];
-        c.m = (T)m; c.inv_m = (T)(1.0 / m); c.I = (T)I; c.inv_I = (T)(1.0 / I);
-        c.cg = (T)(2.0 * h->p.zeta_slow * std::sqrt(m * kv));
-        c.cgr = (T)(2.0 * h->p.zeta_slow * std::sqrt(I * kphi));
-        c.cfloor = (T)(2.0 * h->p.zeta_col * std::sqrt(m * kv));
-        c.kv = (T)kv; c.cte = (T)M.cte; c.mu_s = (T)M.mu_s; c.mu_d = (T)M.mu_d; c.E = (T)M.E;
-    }
-    pc.assign((size_t)h->n_mat * h->n_mat, PairConst<T>{});
-    for (int i = 1; i < h->n_mat; ++i)
-        for (int j = 1; j < h->n_mat; ++j) {
-            const vx_material &A = h->pal[i], &B = h->pal[j];
-            const double Ec = composite(A.E, B.E);
-            const double Gc = composite(A.E / (2.0 * (1.0 + A.nu)), B.E / (2.0 * (1.0 + B.nu)));
-            const double Is = l * l * l * l / 12.0, J = l * l * l * l / 6.0;
-            const double a1 = Ec * l * l / l, a2 = Gc * J / l;
-            const double b1 = 12.0 * Ec * Is / (l * l * l), b2 = 6.0 * Ec * Is / (l * l);
-            const double b3 = 2.0 * Ec * Is / l;
-            const double ma = A.rho * l * l * l, mb = B.rho * l * l * l;
-            const double mmin = std::min(ma, mb);
-            const double Imin = mmin * l * l / 6.0;
-            PairConst<T> &c = pc[(size_t)i * h->n_mat + j];
-            c.a1 = (T)a1; c.a2 = (T)a2; c.b1 = (T)b1; c.b2 = (T)b2; c.b3 = (T)b3;
-            c.ct = (T)(2.0 * h->p.zeta_bond * std::sqrt(mmin * a1));
-            c.cr = (T)(2.0 * h->p.zeta_bond * std::sqrt(Imin * b3));
-            c.kc = (T)(Ec * l);
-            c.cc = (T)(2.0 * h->p.zeta_col * std::sqrt(mmin * Ec * l));
-        }
+    build_tables<T>(h->pal.data(), h->n_mat, h->p, mc, pc);
 }
 
 static long long cell_of(const vx_sim *h, int x, int y, int z) {
@@ -543,19 +508,9 @@ int vx_create(const uint8_t *grid, int32_t nx, int32_t ny, int32_t nz, const vx_
                 if (surf) { h->flags[c] |= FLAG_SURFACE; h->surf_cells.push_back((int)c); }
             }
     h->nvox = nvox;
-    double wmax = 0.0;
-    bool any_bond = false;
-    for (int i = 1; i < n_mat; ++i)
-        for (int j = 1; j < n_mat; ++j) {
-            if (!pair_seen[(size_t)i * n_mat + j]) continue;
-            any_bond = true;
-            const double kb = composite(palette[i].E, palette[j].E) * l;
-            const double mmin = std::min(palette[i].rho, palette[j].rho) * l * l * l;
-            wmax = std::max(wmax, std::sqrt(kb / mmin));
-        }
-    if (!any_bond)
-        for (long long c = 0; c < ncell; ++c)
-            if (grid[c]) wmax = std::max(wmax, std::sqrt(palette[grid[c]].E * l / (palette[grid[c]].rho * l * l * l)));
+    std::vector<char> seen_vox(n_mat, 0);
+    for (long long c = 0; c < ncell; ++c) seen_vox[grid[c]] = 1;
+    const double wmax = max_bond_omega(palette, n_mat, l, pair_seen, seen_vox);
     h->dt = wmax > 0.0 ? h->p.dt_scale / (2.0 * kPi * wmax) : 0.0;
     // rest state
     h->state0.assign((size_t)N_WORDS * ncell, 0.0);

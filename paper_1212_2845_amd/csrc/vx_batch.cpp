@@ -1,0 +1,450 @@
+// Host side of the batched C ABI: many independent voxel objects packed
+// into one set of arrays and stepped by one persistent launch.  Each object
+// gets its own stable timestep (Eq. 31-32 over its own bonds); objects are
+// assigned to workgroups by longest-processing-time packing on cell count.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include "../../include/voxsim.h"
+#include "vx_host.hpp"
+#include "vx_launch.hpp"
+#include "vx_types.hpp"
+
+using namespace vx;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct ObjHost {
+    long long off;
+    int nx, ny, nz;
+    int tx, ty;
+    double dt;
+    double origin_z;
+    long long nvox;
+};
+
+}  // namespace
+
+struct vx_batch_sim {
+    int precision = 32;
+    size_t tsize = 4;
+    hipStream_t stream = nullptr;
+    vx_params p{};
+    int n_mat = 0;
+    std::vector<vx_material> pal;
+    std::vector<ObjHost> objs;
+    std::vector<uint8_t> grid;   // concatenated material ids
+    long long total = 0;         // cells
+    long long nvox = 0;
+    int n_wg = 0;                // workgroups of the persistent launch (0: default)
+    int max_steps_per_launch = 2000;
+    long long step = 0;
+    int cur = 0;
+    bool bound = false;
+    char *ws = nullptr;
+    struct {
+        uint64_t state[2], mat, flags[2], mats, pairs, objs, wg_start, wg_objs, scalars, total;
+    } L{};
+    int wg_cap = 0;              // capacity of the workgroup tables
+    std::string err;
+};
+
+static int bfail(vx_batch_sim *h, int code, const std::string &m) {
+    if (h) h->err = m;
+    return code;
+}
+
+#define BHIP_OK(h, call)                                                                 \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) return bfail(h, VX_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+static void pack_tables(const vx_batch_sim *h, std::vector<MatConst<T>> &mc, std::vector<PairConst<T>> &pc) {
+    build_tables<T>(h->pal.data(), h->n_mat, h->p, mc, pc);
+}
+
+static int default_wg(const vx_batch_sim *h) {
+    // a few workgroups per compute unit, never more than objects
+    return (int)std::min<long long>((long long)h->objs.size(), 256LL * 4);
+}
+
+static void layout(vx_batch_sim *h) {
+    const uint64_t n = (uint64_t)h->total, ts = h->tsize;
+    uint64_t off = 0;
+    auto take = [&](uint64_t b) { uint64_t o = off; off = align_up(off + std::max<uint64_t>(b, 1)); return o; };
+    h->L.state[0] = take(N_WORDS * n * ts);
+    h->L.state[1] = take(N_WORDS * n * ts);
+    h->L.mat = take(n);
+    h->L.flags[0] = take(n);
+    h->L.flags[1] = take(n);
+    h->L.mats = take((uint64_t)h->n_mat * (ts == 8 ? sizeof(MatConst<double>) : sizeof(MatConst<float>)));
+    h->L.pairs = take((uint64_t)h->n_mat * h->n_mat * (ts == 8 ? sizeof(PairConst<double>) : sizeof(PairConst<float>)));
+    h->L.objs = take(h->objs.size() * (ts == 8 ? sizeof(BatchObj<double>) : sizeof(BatchObj<float>)));
+    h->wg_cap = (int)h->objs.size();
+    h->L.wg_start = take(((uint64_t)h->wg_cap + 1) * 4);
+    h->L.wg_objs = take((uint64_t)h->objs.size() * 4);
+    h->L.scalars = take(256);
+    h->L.total = off;
+}
+
+// Longest-processing-time packing: biggest objects first, each to the
+// workgroup with the least work so far (work = cells, as every cell of an
+// object's tiles is visited each step).
+static void lpt(const vx_batch_sim *h, int n_wg, std::vector<int> &start, std::vector<int> &order) {
+    std::vector<int> ids(h->objs.size());
+    std::iota(ids.begin(), ids.end(), 0);
+    auto work = [&](int i) { const ObjHost &o = h->objs[i]; return (long long)o.nx * o.ny * o.nz; };
+    std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return work(a) > work(b); });
+    using P = std::pair<long long, int>;
+    std::priority_queue<P, std::vector<P>, std::greater<P>> q;
+    for (int w = 0; w < n_wg; ++w) q.push({0, w});
+    std::vector<std::vector<int>> lists(n_wg);
+    for (int i : ids) {
+        P top = q.top();
+        q.pop();
+        lists[top.second].push_back(i);
+        q.push({top.first + work(i), top.second});
+    }
+    start.assign(n_wg + 1, 0);
+    order.clear();
+    for (int w = 0; w < n_wg; ++w) {
+        start[w] = (int)order.size();
+        order.insert(order.end(), lists[w].begin(), lists[w].end());
+    }
+    start[n_wg] = (int)order.size();
+}
+
+template <typename T>
+static int upload_all(vx_batch_sim *h) {
+    hipStream_t s = h->stream;
+    std::vector<MatConst<T>> mc;
+    std::vector<PairConst<T>> pc;
+    pack_tables<T>(h, mc, pc);
+    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.mats, mc.data(), mc.size() * sizeof(MatConst<T>), hipMemcpyHostToDevice, s));
+    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.pairs, pc.data(), pc.size() * sizeof(PairConst<T>), hipMemcpyHostToDevice, s));
+    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.mat, h->grid.data(), h->total, hipMemcpyHostToDevice, s));
+    std::vector<uint8_t> fl(h->total, 0);
+    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.flags[0], fl.data(), h->total, hipMemcpyHostToDevice, s));
+    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.flags[1], fl.data(), h->total, hipMemcpyHostToDevice, s));
+    std::vector<BatchObj<T>> ob(h->objs.size());
+    for (size_t i = 0; i < ob.size(); ++i) {
+        const ObjHost &o = h->objs[i];
+        ob[i].off = (unsigned)o.off; ob[i].nx = o.nx; ob[i].ny = o.ny; ob[i].nz = o.nz;
+        ob[i].tx = o.tx; ob[i].ty = o.ty; ob[i].dt = (T)o.dt; ob[i].origin_z = (T)o.origin_z;
+    }
+    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.objs, ob.data(), ob.size() * sizeof(BatchObj<T>), hipMemcpyHostToDevice, s));
+    // rest state: zero everywhere except the quaternion w
+    std::vector<T> st((size_t)N_WORDS * h->total, T(0));
+    std::fill(st.begin() + (size_t)W_QW * h->total, st.begin() + (size_t)(W_QW + 1) * h->total, T(1));
+    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.state[0], st.data(), st.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.state[1], st.data(), st.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    std::vector<unsigned char> zero(256, 0);
+    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.scalars, zero.data(), 256, hipMemcpyHostToDevice, s));
+    BHIP_OK(h, hipStreamSynchronize(s));
+    return VX_OK;
+}
+
+template <typename T>
+static int run(vx_batch_sim *h, int64_t n) {
+    const int n_wg = h->n_wg > 0 ? h->n_wg : default_wg(h);
+    std::vector<int> start, order;
+    lpt(h, n_wg, start, order);
+    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.wg_start, start.data(), start.size() * 4, hipMemcpyHostToDevice, h->stream));
+    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.wg_objs, order.data(), order.size() * 4, hipMemcpyHostToDevice, h->stream));
+    BatchArgs<T> b{};
+    StepArgs<T> &a = b.base;
+    a.stride = h->total;
+    a.mat = (const uint8_t *)(h->ws + h->L.mat);
+    a.mats = (const MatConst<T> *)(h->ws + h->L.mats);
+    a.pairs = (const PairConst<T> *)(h->ws + h->L.pairs);
+    a.n_mat = h->n_mat;
+    a.l = (T)h->p.voxel_size;
+    a.gravity = (T)h->p.gravity;
+    a.floor_on = h->p.floor_on;
+    a.track_vmax = 0;
+    a.n_forced = 0;
+    a.err_flag = (unsigned *)(h->ws + h->L.scalars);
+    a.vmax_bits = (unsigned long long *)(h->ws + h->L.scalars + 8);
+    b.state[0] = (T *)(h->ws + h->L.state[0]);
+    b.state[1] = (T *)(h->ws + h->L.state[1]);
+    b.flags[0] = (uint8_t *)(h->ws + h->L.flags[0]);
+    b.flags[1] = (uint8_t *)(h->ws + h->L.flags[1]);
+    b.objs = (const BatchObj<T> *)(h->ws + h->L.objs);
+    b.wg_start = (const int *)(h->ws + h->L.wg_start);
+    b.wg_objs = (const int *)(h->ws + h->L.wg_objs);
+    b.temp_amp = h->p.temp_amp;
+    b.temp_freq = h->p.temp_freq;
+    b.temp_phase = h->p.temp_phase;
+    int64_t left = n;
+    while (left > 0) {
+        const int k = (int)std::min<int64_t>(left, h->max_steps_per_launch);
+        b.steps = k;
+        b.cur0 = h->cur;
+        b.step0 = h->step;
+        BHIP_OK(h, launch_batch<T>(b, n_wg, h->stream));
+        h->cur = (h->cur + k) & 1;
+        h->step += k;
+        left -= k;
+    }
+    unsigned errf = 0;
+    BHIP_OK(h, hipMemcpyAsync(&errf, h->ws + h->L.scalars, 4, hipMemcpyDeviceToHost, h->stream));
+    BHIP_OK(h, hipStreamSynchronize(h->stream));
+    if (errf) return bfail(h, VX_EUNSTABLE, "non-finite value in a batched object's state");
+    return VX_OK;
+}
+
+template <typename T>
+static int read_obj(vx_batch_sim *h, int obj, double *u, double *q, double *vel, double *omega) {
+    const ObjHost &o = h->objs[obj];
+    const long long nc = (long long)o.nx * o.ny * o.nz;
+    std::vector<T> w((size_t)N_WORDS * nc);
+    for (int k = 0; k < N_WORDS; ++k)
+        BHIP_OK(h, hipMemcpyAsync(w.data() + (size_t)k * nc,
+                                  h->ws + h->L.state[h->cur] + ((size_t)k * h->total + o.off) * sizeof(T),
+                                  nc * sizeof(T), hipMemcpyDeviceToHost, h->stream));
+    BHIP_OK(h, hipStreamSynchronize(h->stream));
+    const double l = h->p.voxel_size;
+    for (long long c = 0; c < nc; ++c) {
+        const int m = h->grid[o.off + c];
+        const double mass = m ? h->pal[m].rho * l * l * l : 1.0, I = mass * l * l / 6.0;
+        for (int k = 0; k < 3; ++k) {
+            if (u) u[3 * c + k] = m ? (double)w[(size_t)(W_UX + k) * nc + c] : 0.0;
+            if (vel) vel[3 * c + k] = m ? (double)w[(size_t)(W_PX + k) * nc + c] / mass : 0.0;
+            if (omega) omega[3 * c + k] = m ? (double)w[(size_t)(W_LX + k) * nc + c] / I : 0.0;
+        }
+        if (q)
+            for (int k = 0; k < 4; ++k) q[4 * c + k] = m ? (double)w[(size_t)(W_QW + k) * nc + c] : (k == 0 ? 1.0 : 0.0);
+    }
+    return VX_OK;
+}
+
+template <typename T>
+static int write_obj(vx_batch_sim *h, int obj, const double *u, const double *q, const double *vel,
+                     const double *omega) {
+    const ObjHost &o = h->objs[obj];
+    const long long nc = (long long)o.nx * o.ny * o.nz;
+    std::vector<T> w((size_t)N_WORDS * nc);
+    for (int k = 0; k < N_WORDS; ++k)
+        BHIP_OK(h, hipMemcpyAsync(w.data() + (size_t)k * nc,
+                                  h->ws + h->L.state[h->cur] + ((size_t)k * h->total + o.off) * sizeof(T),
+                                  nc * sizeof(T), hipMemcpyDeviceToHost, h->stream));
+    BHIP_OK(h, hipStreamSynchronize(h->stream));
+    const double l = h->p.voxel_size;
+    for (long long c = 0; c < nc; ++c) {
+        const int m = h->grid[o.off + c];
+        if (!m) continue;
+        const double mass = h->pal[m].rho * l * l * l, I = mass * l * l / 6.0;
+        for (int k = 0; k < 3; ++k) {
+            if (u) w[(size_t)(W_UX + k) * nc + c] = (T)u[3 * c + k];
+            if (vel) w[(size_t)(W_PX + k) * nc + c] = (T)(mass * vel[3 * c + k]);
+            if (omega) w[(size_t)(W_LX + k) * nc + c] = (T)(I * omega[3 * c + k]);
+        }
+        if (q)
+            for (int k = 0; k < 4; ++k) w[(size_t)(W_QW + k) * nc + c] = (T)q[4 * c + k];
+    }
+    for (int b = 0; b < 2; ++b)
+        for (int k = 0; k < N_WORDS; ++k)
+            BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.state[b] + ((size_t)k * h->total + o.off) * sizeof(T),
+                                      w.data() + (size_t)k * nc, nc * sizeof(T), hipMemcpyHostToDevice, h->stream));
+    BHIP_OK(h, hipStreamSynchronize(h->stream));
+    return VX_OK;
+}
+
+extern "C" {
+
+int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *palette, int32_t n_mat,
+                    const vx_params *params, int32_t precision, void *stream, vx_batch *out) {
+    if (!out) return VX_EINVAL;
+    *out = nullptr;
+    if (!objs || n_obj <= 0 || !palette || n_mat < 1 || n_mat > kFusedMaxMat || !params) return VX_EINVAL;
+    if (precision != 32 && precision != 64) return VX_EINVAL;
+    const vx_params &p = *params;
+    if (!(p.voxel_size > 0.0) || !(p.gravity >= 0.0) || !(p.zeta_bond >= 0.0) || !(p.zeta_slow >= 0.0) ||
+        !(p.zeta_col >= 0.0) || !(p.dt_scale >= 0.0) || p.dt_scale > 1.0 || p.reserved != 0 ||
+        p.self_collision_on != 0)
+        return VX_EINVAL;
+    for (int i = 1; i < n_mat; ++i) {
+        const vx_material &m = palette[i];
+        if (!(m.E > 0.0) || !(m.rho > 0.0) || !(m.nu > -1.0 && m.nu < 0.5) || !(m.mu_s >= 0.0) || !(m.mu_d >= 0.0) ||
+            !std::isfinite(m.cte))
+            return VX_EINVAL;
+    }
+    vx_batch_sim *h = new vx_batch_sim();
+    h->precision = precision;
+    h->tsize = precision == 64 ? 8 : 4;
+    h->stream = (hipStream_t)stream;
+    h->p = p;
+    if (h->p.dt_scale == 0.0) h->p.dt_scale = 1.0;
+    h->n_mat = n_mat;
+    h->pal.assign(palette, palette + n_mat);
+    const double l = p.voxel_size;
+    long long off = 0;
+    for (int i = 0; i < n_obj; ++i) {
+        const vx_object &o = objs[i];
+        if (!o.grid || o.nx <= 0 || o.ny <= 0 || o.nz <= 0) { delete h; return VX_EINVAL; }
+        const long long nc = (long long)o.nx * o.ny * o.nz;
+        ObjHost oh{};
+        oh.off = off; oh.nx = o.nx; oh.ny = o.ny; oh.nz = o.nz;
+        oh.tx = std::min(o.nx, 64);
+        oh.ty = std::min(o.ny, 256 / oh.tx);
+        oh.origin_z = o.origin[2];
+        // the object's own stable timestep over its bonded material pairs
+        std::vector<char> seen((size_t)n_mat * n_mat, 0), seen_vox(n_mat, 0);
+        for (int z = 0; z < o.nz; ++z)
+            for (int y = 0; y < o.ny; ++y)
+                for (int x = 0; x < o.nx; ++x) {
+                    const long long c = x + (long long)o.nx * (y + (long long)o.ny * z);
+                    const int m = o.grid[c];
+                    if (m >= n_mat) { delete h; return VX_EINVAL; }
+                    if (!m) continue;
+                    ++oh.nvox;
+                    seen_vox[m] = 1;
+                    const int idx[3] = {x, y, z}, dim[3] = {o.nx, o.ny, o.nz};
+                    const long long st[3] = {1, o.nx, (long long)o.nx * o.ny};
+                    for (int a = 0; a < 3; ++a) {
+                        if (idx[a] + 1 >= dim[a]) continue;
+                        const int m2 = o.grid[c + st[a]];
+                        if (m2) seen[(size_t)m * n_mat + m2] = 1;
+                    }
+                }
+        const double wmax = max_bond_omega(palette, n_mat, l, seen, seen_vox);
+        oh.dt = wmax > 0.0 ? h->p.dt_scale / (2.0 * kPi * wmax) : 0.0;
+        h->grid.insert(h->grid.end(), o.grid, o.grid + nc);
+        h->nvox += oh.nvox;
+        h->objs.push_back(oh);
+        off += nc;
+    }
+    h->total = off;
+    if (h->total * (long long)N_WORDS * (long long)h->tsize > (1LL << 32) - 1) { delete h; return VX_EINVAL; }
+    layout(h);
+    *out = h;
+    return VX_OK;
+}
+
+int vx_batch_workspace_bytes(vx_batch h, uint64_t *bytes) {
+    if (!h || !bytes) return VX_EINVAL;
+    *bytes = h->L.total;
+    return VX_OK;
+}
+
+int vx_batch_bind_workspace(vx_batch h, void *device_ptr, uint64_t bytes) {
+    if (!h) return VX_EINVAL;
+    if (h->bound) return bfail(h, VX_ESTATE, "workspace already bound");
+    if (!device_ptr || bytes < h->L.total) return bfail(h, VX_EINVAL, "workspace too small");
+    if (((uintptr_t)device_ptr) % kAlign) return bfail(h, VX_EINVAL, "workspace not 256-byte aligned");
+    h->ws = (char *)device_ptr;
+    h->bound = true;
+    const int r = h->precision == 64 ? upload_all<double>(h) : upload_all<float>(h);
+    if (r != VX_OK) h->bound = false;
+    return r;
+}
+
+int vx_batch_step(vx_batch h, int64_t n) {
+    if (!h || n < 0) return VX_EINVAL;
+    if (!h->bound) return bfail(h, VX_ESTATE, "vx_batch_step before vx_batch_bind_workspace");
+    if (n == 0) return VX_OK;
+    return h->precision == 64 ? run<double>(h, n) : run<float>(h, n);
+}
+
+int vx_batch_read_state(vx_batch h, int32_t obj, double *u, double *q, double *vel, double *omega) {
+    if (!h || obj < 0 || obj >= (int)h->objs.size()) return VX_EINVAL;
+    if (!h->bound) return bfail(h, VX_ESTATE, "read before bind");
+    return h->precision == 64 ? read_obj<double>(h, obj, u, q, vel, omega) : read_obj<float>(h, obj, u, q, vel, omega);
+}
+
+int vx_batch_write_state(vx_batch h, int32_t obj, const double *u, const double *q, const double *vel,
+                         const double *omega) {
+    if (!h || obj < 0 || obj >= (int)h->objs.size()) return VX_EINVAL;
+    if (!h->bound) return bfail(h, VX_ESTATE, "write before bind");
+    return h->precision == 64 ? write_obj<double>(h, obj, u, q, vel, omega)
+                              : write_obj<float>(h, obj, u, q, vel, omega);
+}
+
+int vx_batch_get_dt(vx_batch h, int32_t obj, double *dt) {
+    if (!h || !dt || obj < 0 || obj >= (int)h->objs.size()) return VX_EINVAL;
+    *dt = h->objs[obj].dt;
+    return VX_OK;
+}
+
+int vx_batch_counters(vx_batch h, int64_t out[4]) {
+    if (!h || !out) return VX_EINVAL;
+    out[0] = h->step;
+    out[1] = (int64_t)h->objs.size();
+    out[2] = h->total;
+    out[3] = h->nvox;
+    return VX_OK;
+}
+
+int vx_batch_set_launch(vx_batch h, int32_t n_workgroups, int32_t max_steps_per_launch) {
+    if (!h || n_workgroups < 0 || max_steps_per_launch < 0) return VX_EINVAL;
+    h->n_wg = std::min<int>(n_workgroups, (int)h->objs.size());
+    if (max_steps_per_launch > 0) h->max_steps_per_launch = max_steps_per_launch;
+    return VX_OK;
+}
+
+int vx_batch_autotune(vx_batch h, int32_t steps, int32_t *n_workgroups) {
+    if (!h || steps <= 0) return VX_EINVAL;
+    if (!h->bound) return bfail(h, VX_ESTATE, "autotune before bind");
+    // time candidate workgroup counts on the real objects; the state is
+    // saved and restored around the trial steps
+    const size_t bytes = (size_t)N_WORDS * h->total * h->tsize;
+    const int cur0 = h->cur;
+    const long long step0 = h->step;
+    // keep a copy of the current state in the other buffer's place after the
+    // trials by re-running from a host copy
+    std::vector<char> save(bytes), fsave(h->total);
+    BHIP_OK(h, hipMemcpyAsync(save.data(), h->ws + h->L.state[cur0], bytes, hipMemcpyDeviceToHost, h->stream));
+    BHIP_OK(h, hipMemcpyAsync(fsave.data(), h->ws + h->L.flags[cur0], h->total, hipMemcpyDeviceToHost, h->stream));
+    BHIP_OK(h, hipStreamSynchronize(h->stream));
+    const int nobj = (int)h->objs.size();
+    const int cands[] = {256, 512, 768, 1024, 1536, 2048, 3072, 4096};
+    hipEvent_t e0, e1;
+    BHIP_OK(h, hipEventCreate(&e0));
+    BHIP_OK(h, hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_wg = default_wg(h);
+    for (int c : cands) {
+        const int nw = std::min(c, nobj);
+        h->n_wg = nw;
+        BHIP_OK(h, hipEventRecord(e0, h->stream));
+        int r = h->precision == 64 ? run<double>(h, steps) : run<float>(h, steps);
+        if (r != VX_OK) { hipEventDestroy(e0); hipEventDestroy(e1); return r; }
+        BHIP_OK(h, hipEventRecord(e1, h->stream));
+        BHIP_OK(h, hipEventSynchronize(e1));
+        float ms = 0.f;
+        BHIP_OK(h, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) { best = ms; best_wg = nw; }
+        if (nw == nobj) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    h->n_wg = best_wg;
+    h->cur = cur0;
+    h->step = step0;
+    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.state[cur0], save.data(), bytes, hipMemcpyHostToDevice, h->stream));
+    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.flags[cur0], fsave.data(), h->total, hipMemcpyHostToDevice, h->stream));
+    BHIP_OK(h, hipStreamSynchronize(h->stream));
+    if (n_workgroups) *n_workgroups = best_wg;
+    return VX_OK;
+}
+
+int vx_batch_destroy(vx_batch h) {
+    delete h;
+    return VX_OK;
+}
+
+const char *vx_batch_last_error(vx_batch h) { return h ? h->err.c_str() : "null handle"; }
+
+}  // extern "C"

@@ -26,15 +26,19 @@ namespace {
 constexpr int kXcds = 8;
 constexpr int kKin = 14;   // ux uy uz qw qx qy qz vx vy vz wx wy wz eps
 
-template <typename T, int TX, int TY>
+// LDS of one workgroup: a slab of kinematics with its ring, and the x- and
+// y-bond results, sized for NR ring cells and NBX / NBY bonds.
+template <typename T, int NR_, int NBX_, int NBY_>
 struct Smem {
-    static constexpr int RW = TX + 2, RH = TY + 2, NR = RW * RH;
-    static constexpr int NBX = (TX + 1) * TY, NBY = TX * (TY + 1);
+    static constexpr int NR = NR_, NBX = NBX_, NBY = NBY_;
     T kin[kKin][NR];
     T bx[9][NBX];
     T by[9][NBY];
     uint8_t mat[NR];
 };
+
+template <typename T, int TX, int TY>
+using TileSmem = Smem<T, (TX + 2) * (TY + 2), (TX + 1) * TY, TX * (TY + 1)>;
 
 struct FusedGrid {
     int tiles_x, tiles_y, chunks, zc;
@@ -102,49 +106,51 @@ __device__ __forceinline__ void load_own(const StepArgs<T> &a, const Tables<T> &
     }
 }
 
-template <typename T, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY) k_fused(StepArgs<T> a, FusedGrid g) {
-    using S = Smem<T, TX, TY>;
-    constexpr int NT = TX * TY, RW = S::RW, NR = S::NR, NBX = S::NBX, NBY = S::NBY;
-    static_assert(2 * (TX + TY) <= NT, "ring must fit one cell per thread");
-    __shared__ S sm;
-    extern __shared__ __align__(16) unsigned char dyn[];
-
-    // material tables into LDS
+// Load the material tables into LDS (all threads of the workgroup; the
+// caller synchronises before use).
+template <typename T>
+__device__ __forceinline__ Tables<T> stage_tables(const StepArgs<T> &a, unsigned char *dyn, int nthreads) {
     Tables<T> tb;
     tb.n_mat = a.n_mat;
-    {
-        MatConst<T> *smat = (MatConst<T> *)dyn;
-        T *spair = (T *)(dyn + ((a.n_mat * sizeof(MatConst<T>) + 15) & ~(size_t)15));
-        const T *gm = (const T *)a.mats;
-        T *sm_ = (T *)smat;
-        const int nmw = a.n_mat * (int)(sizeof(MatConst<T>) / sizeof(T));
-        for (int i = threadIdx.x; i < nmw; i += NT) sm_[i] = gm[i];
-        const int np = a.n_mat * a.n_mat;
-        for (int i = threadIdx.x; i < np; i += NT) {
-            spair[4 * i] = a.pairs[i].a1;
-            spair[4 * i + 1] = a.pairs[i].a2;
-            spair[4 * i + 2] = a.pairs[i].ct;
-            spair[4 * i + 3] = T(0);
-        }
-        tb.mat = smat;
-        tb.pair = spair;
+    MatConst<T> *smat = (MatConst<T> *)dyn;
+    T *spair = (T *)(dyn + ((a.n_mat * sizeof(MatConst<T>) + 15) & ~(size_t)15));
+    const T *gm = (const T *)a.mats;
+    T *sm_ = (T *)smat;
+    const int nmw = a.n_mat * (int)(sizeof(MatConst<T>) / sizeof(T));
+    for (int i = threadIdx.x; i < nmw; i += nthreads) sm_[i] = gm[i];
+    const int np = a.n_mat * a.n_mat;
+    for (int i = threadIdx.x; i < np; i += nthreads) {
+        spair[4 * i] = a.pairs[i].a1;
+        spair[4 * i + 1] = a.pairs[i].a2;
+        spair[4 * i + 2] = a.pairs[i].ct;
+        spair[4 * i + 3] = T(0);
     }
-    const LatK<T> C = lat_consts(a.l);
+    tb.mat = smat;
+    tb.pair = spair;
+    return tb;
+}
 
-    // XCD-aware tile order (bijective for any grid size)
-    const int nwg = gridDim.x, b = blockIdx.x;
-    const int q = nwg / kXcds, rem = nwg % kXcds, xcd = b % kXcds, kk = b / kXcds;
-    const int L = xcd < rem ? xcd * (q + 1) + kk : rem * (q + 1) + (xcd - rem) * q + kk;
-    const int tile_x = L % g.tiles_x;
-    const int tile_y = (L / g.tiles_x) % g.tiles_y;
-    const int chunk = L / (g.tiles_x * g.tiles_y);
+template <typename T>
+__host__ __device__ inline size_t tables_bytes(int n_mat) {
+    return ((n_mat * sizeof(MatConst<T>) + 15) & ~(size_t)15) + (size_t)n_mat * n_mat * 4 * sizeof(T);
+}
 
-    const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+// One column of cells: the TX x TY tile (tile_x, tile_y) of lattice a,
+// marched over slabs [z0, z1).  Called by every thread of the workgroup
+// (threads beyond TX * TY only help with the ring and the barriers).  TX and
+// TY may be compile-time constants (fused kernel) or runtime values within
+// the LDS sizes of S (batched kernel).
+template <typename T, typename S>
+__device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<T> &tb, const LatK<T> &C,
+                                      const int TX, const int TY, int tile_x, int tile_y, int z0, int z1,
+                                      T &vmax) {
+    constexpr int NR = S::NR, NBX = S::NBX, NBY = S::NBY;
+    const int RW = TX + 2;
+    const int tid = threadIdx.x;
+    const bool lane_in = tid < TX * TY;
+    const int tx = lane_in ? tid % TX : 0, ty = lane_in ? tid / TX : 0;
     const int x = tile_x * TX + tx, y = tile_y * TY + ty;
-    const bool inxy = x < a.nx && y < a.ny;
-    const int z0 = chunk * g.zc;
-    const int z1 = min(z0 + g.zc, a.nz);
+    const bool inxy = lane_in && x < a.nx && y < a.ny;
     const unsigned nxy = (unsigned)a.nx * (unsigned)a.ny;
     const unsigned col = inxy ? (unsigned)x + (unsigned)a.nx * (unsigned)y : 0u;
     const int own = (tx + 1) + RW * (ty + 1);
@@ -167,9 +173,6 @@ __global__ void __launch_bounds__(TX *TY) k_fused(StepArgs<T> a, FusedGrid g) {
     const int bnd_up = bnd_y ? bnd_lo + RW : bnd_lo + 1;
     const int bnd_i = bnd_y ? (tid - TY) : (TX + 1) * tid;
 
-    __syncthreads();
-
-    T vmax = T(0);
     Own<T> A{}, B{};
     if (inxy && z0 < z1) load_own(a, tb, col + (unsigned)z0 * nxy, A);
 
@@ -192,8 +195,10 @@ __global__ void __launch_bounds__(TX *TY) k_fused(StepArgs<T> a, FusedGrid g) {
         nxt.m = 0;
         if (inxy && z + 1 < a.nz) load_own(a, tb, col + (unsigned)(z + 1) * nxy, nxt);
 
-        if (cur.m) put_kin<T, NR>(sm.kin, own, cur.k);
-        sm.mat[own] = cur.m;
+        if (lane_in) {
+            if (cur.m) put_kin<T, NR>(sm.kin, own, cur.k);
+            sm.mat[own] = cur.m;
+        }
         if (ring) {
             uint8_t mr = 0;
             if (ring_in) {
@@ -209,14 +214,14 @@ __global__ void __launch_bounds__(TX *TY) k_fused(StepArgs<T> a, FusedGrid g) {
         Rot<T> Rc{};
         if (cur.m) Rc = rot_of(cur.k.qw, cur.k.qx, cur.k.qy, cur.k.qz);
         {
-            const uint8_t mu = sm.mat[own + 1];
+            const uint8_t mu = lane_in ? sm.mat[own + 1] : 0;
             if (cur.m && mu) {
                 const VoxKin<T> ku = get_kin<T, NR>(sm.kin, own + 1);
                 put_bond<T, NBX>(sm.bx, (tx + 1) + (TX + 1) * ty, bond_eval<T, 0>(cur.k, Rc, ku, tb.bond(cur.m, mu), C));
             }
         }
         {
-            const uint8_t mu = sm.mat[own + RW];
+            const uint8_t mu = lane_in ? sm.mat[own + RW] : 0;
             if (cur.m && mu) {
                 const VoxKin<T> ku = get_kin<T, NR>(sm.kin, own + RW);
                 put_bond<T, NBY>(sm.by, tx + TX * (ty + 1), bond_eval<T, 1>(cur.k, Rc, ku, tb.bond(cur.m, mu), C));
@@ -233,8 +238,11 @@ __global__ void __launch_bounds__(TX *TY) k_fused(StepArgs<T> a, FusedGrid g) {
         }
         // neighbour materials for the gather, read before the slab's LDS can
         // be overwritten by faster threads moving on to the next slab
-        const bool n_mx = sm.mat[own - 1] != 0, n_px = sm.mat[own + 1] != 0;
-        const bool n_my = sm.mat[own - RW] != 0, n_py = sm.mat[own + RW] != 0;
+        bool n_mx = false, n_px = false, n_my = false, n_py = false;
+        if (lane_in) {
+            n_mx = sm.mat[own - 1] != 0; n_px = sm.mat[own + 1] != 0;
+            n_my = sm.mat[own - RW] != 0; n_py = sm.mat[own + RW] != 0;
+        }
         const bool has_zb = cur.m && nxt.m;
         BondOut<T> oz{};
         if (has_zb) oz = bond_eval<T, 2>(cur.k, Rc, nxt.k, tb.bond(cur.m, nxt.m), C);
@@ -282,7 +290,80 @@ __global__ void __launch_bounds__(TX *TY) k_fused(StepArgs<T> a, FusedGrid g) {
         slab(A, B, z);
         if (z + 1 < z1) slab(B, A, z + 1);
     }
+}
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_fused(StepArgs<T> a, FusedGrid g) {
+    static_assert(2 * (TX + TY) <= TX * TY, "ring must fit one cell per thread");
+    __shared__ TileSmem<T, TX, TY> sm;
+    extern __shared__ __align__(16) unsigned char dyn[];
+    const Tables<T> tb = stage_tables(a, dyn, TX * TY);
+    const LatK<T> C = lat_consts(a.l);
+
+    // XCD-aware tile order (bijective for any grid size)
+    const int nwg = gridDim.x, b = blockIdx.x;
+    const int q = nwg / kXcds, rem = nwg % kXcds, xcd = b % kXcds, kk = b / kXcds;
+    const int L = xcd < rem ? xcd * (q + 1) + kk : rem * (q + 1) + (xcd - rem) * q + kk;
+    const int tile_x = L % g.tiles_x;
+    const int tile_y = (L / g.tiles_x) % g.tiles_y;
+    const int chunk = L / (g.tiles_x * g.tiles_y);
+    const int z0 = chunk * g.zc;
+    const int z1 = min(z0 + g.zc, a.nz);
+    __syncthreads();
+
+    T vmax = T(0);
+    march(a, sm, tb, C, TX, TY, tile_x, tile_y, z0, z1, vmax);
     if (a.track_vmax) wave_vmax(a.vmax_bits, vmax);
+}
+
+// Largest runtime tile of the batched kernel: TX, TY <= 64, TX * TY <= 256,
+// so (TX + 2)(TY + 2) <= 396 ring slots and (TX + 1) TY, TX (TY + 1) <= 320.
+constexpr int kBatchThreads = 256;
+using BatchSmemF = Smem<float, 396, 320, 320>;
+using BatchSmemD = Smem<double, 396, 320, 320>;
+template <typename T> struct BatchSmemOf;
+template <> struct BatchSmemOf<float> { using type = BatchSmemF; };
+template <> struct BatchSmemOf<double> { using type = BatchSmemD; };
+
+// Batched persistent step: each workgroup owns a list of whole objects and
+// runs every step of the launch for all of them, with only workgroup
+// barriers between steps (objects are independent, so no grid-wide sync).
+// Each object's x-y extent is covered by runtime TX x TY tiles; per-object
+// timestep and time.
+template <typename T>
+__global__ void __launch_bounds__(kBatchThreads) k_batch(BatchArgs<T> b) {
+    __shared__ typename BatchSmemOf<T>::type sm;
+    extern __shared__ __align__(16) unsigned char dyn[];
+    const Tables<T> tb = stage_tables(b.base, dyn, kBatchThreads);
+    const LatK<T> C = lat_consts(b.base.l);
+    __syncthreads();
+    const int o0 = b.wg_start[blockIdx.x], o1 = b.wg_start[blockIdx.x + 1];
+    T vmax = T(0);
+    for (int k = 0; k < b.steps; ++k) {
+        const int p = (b.cur0 + k) & 1;
+        const long long n = b.step0 + k;
+        for (int oi = o0; oi < o1; ++oi) {
+            const BatchObj<T> ob = b.objs[b.wg_objs[oi]];
+            StepArgs<T> a = b.base;
+            a.s_in = b.state[p] + ob.off;
+            a.s_out = b.state[1 - p] + ob.off;
+            a.mat = b.base.mat + ob.off;
+            a.flags = b.flags[p] + ob.off;
+            a.flags_out = b.flags[1 - p] + ob.off;
+            a.nx = ob.nx; a.ny = ob.ny; a.nz = ob.nz;
+            a.dt = ob.dt;
+            a.origin_z = ob.origin_z;
+            const double wt = 6.283185307179586 * b.temp_freq * ((double)n * (double)ob.dt);
+            a.dT_global = (T)(b.temp_amp * sin(wt + b.temp_phase));
+            a.wt = wt;
+            a.wt_red = (T)fmod(wt, 6.283185307179586);
+            const int tiles_x = (ob.nx + ob.tx - 1) / ob.tx, tiles_y = (ob.ny + ob.ty - 1) / ob.ty;
+            for (int ty = 0; ty < tiles_y; ++ty)
+                for (int tx = 0; tx < tiles_x; ++tx) march(a, sm, tb, C, ob.tx, ob.ty, tx, ty, 0, ob.nz, vmax);
+        }
+        // this step's writes are the next step's reads (same workgroup)
+        __syncthreads();
+    }
 }
 
 template <typename T, int TX, int TY>
@@ -296,9 +377,7 @@ hipError_t launch_tiles(const StepArgs<T> &a, int zc, hipStream_t s) {
     g.zc = zc;
     g.chunks = (a.nz + zc - 1) / zc;
     const long long nwg = cols * g.chunks;
-    const size_t dyn = ((a.n_mat * sizeof(MatConst<T>) + 15) & ~(size_t)15) +
-                       (size_t)a.n_mat * a.n_mat * 4 * sizeof(T);
-    k_fused<T, TX, TY><<<(unsigned)nwg, TX * TY, dyn, s>>>(a, g);
+    k_fused<T, TX, TY><<<(unsigned)nwg, TX * TY, tables_bytes<T>(a.n_mat), s>>>(a, g);
     return hipGetLastError();
 }
 
@@ -327,6 +406,14 @@ hipError_t launch_fused_step(const StepArgs<T> &a, const FusedCfg &cfg, hipStrea
     }
 }
 
+template <typename T>
+hipError_t launch_batch(const BatchArgs<T> &b, int n_wg, hipStream_t s) {
+    k_batch<T><<<(unsigned)n_wg, kBatchThreads, tables_bytes<T>(b.base.n_mat), s>>>(b);
+    return hipGetLastError();
+}
+
+template hipError_t launch_batch<float>(const BatchArgs<float> &, int, hipStream_t);
+template hipError_t launch_batch<double>(const BatchArgs<double> &, int, hipStream_t);
 template hipError_t launch_fused_step<float>(const StepArgs<float> &, const FusedCfg &, hipStream_t);
 template hipError_t launch_fused_step<double>(const StepArgs<double> &, const FusedCfg &, hipStream_t);
 

@@ -28,6 +28,33 @@ constexpr int kFusedMaxMat = 16;
 template <typename T>
 hipError_t launch_fused_step(const StepArgs<T> &a, const FusedCfg &cfg, hipStream_t s);
 
+// Batched objects: per-object descriptor and the persistent launch.
+template <typename T>
+struct BatchObj {
+    unsigned off;           // first cell of the object in the concatenated arrays
+    int nx, ny, nz;
+    int tx, ty;             // tile of the object's x-y extent (tx, ty <= 64, tx * ty <= 256)
+    T dt;                   // the object's stable timestep
+    T origin_z;             // world z of the object's lower face
+};
+
+template <typename T>
+struct BatchArgs {
+    StepArgs<T> base;       // palette, parameters, material ids (concatenated)
+    T *state[2];            // ping-pong state of all objects (stride = total cells)
+    uint8_t *flags[2];
+    const BatchObj<T> *objs;
+    const int *wg_start;    // n_wg + 1 offsets into wg_objs
+    const int *wg_objs;     // object ids, grouped by workgroup
+    int steps;              // steps run by this launch
+    int cur0;               // buffer holding the state at the first step
+    long long step0;        // step index of the first step (for the time t_n)
+    double temp_amp, temp_freq, temp_phase;
+};
+
+template <typename T>
+hipError_t launch_batch(const BatchArgs<T> &b, int n_wg, hipStream_t s);
+
 // Collision support (self-collision on).
 struct CollideArgs {
     const int *surf_cells;       // surface voxel cells, ascending

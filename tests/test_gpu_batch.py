@@ -1,0 +1,118 @@
+"""Batched persistent stepping: many independent objects in one launch.
+
+Each object of a batch must evolve as it does alone: against the
+single-lattice fused path (same device arithmetic; different tiles, so equal
+to rounding) and against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import paper_1212_2845_amd as vx
+import workloads
+from parity import build_oracle, compare, perturbed_state
+
+pytestmark = pytest.mark.gpu
+
+MATS = [workloads.EMPTY, workloads._mat(1e6), workloads._mat(1e8), workloads._mat(1e6, cte=0.01),
+        workloads._mat(1e6, cte=-0.01)]
+PARAMS = dict(gravity=9.81, zeta_bond=0.5, zeta_col=0.5, floor_on=1, temp_amp=20.0, temp_freq=200.0)
+
+
+def announce(msg):
+    print("[case] " + msg, flush=True)
+
+
+def make_objects(n, seed, lo=3, hi=12, perturb=True):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    grids, states = [], []
+    for i in range(n):
+        nx, ny, nz = (int(v) for v in rng.integers(lo, hi + 1, size=3))
+        g = rng.integers(0, 5, size=(nz, ny, nx)).astype(np.uint8)
+        if i % 4 == 0:
+            g[g == 2] = 1               # some objects without the stiff material: a larger dt
+        grids.append(g)
+        states.append(perturbed_state(g.size, seed + 100 + i, 1e-6, 1e-3, 0.5, 1e-3) if perturb else None)
+    return grids, states
+
+
+def run_batch(grids, states, steps, precision, **kw):
+    b = vx.Batch(grids, MATS, precision=precision, **PARAMS)
+    b.bind()
+    for k, v in kw.items():
+        if k == "launch":
+            b.set_launch(*v)
+    for i, st in enumerate(states):
+        if st is not None:
+            b.write_state(i, **st)
+    b.step(steps)
+    return b
+
+
+@pytest.mark.parametrize("precision,tol", [(64, 1e-12), (32, 2e-5)])
+def test_batch_matches_single_objects(precision, tol):
+    grids, states = make_objects(12, seed=11)
+    announce("batch of 12 vs single p=%d" % precision)
+    b = run_batch(grids, states, 150, precision)
+    for i, g in enumerate(grids):
+        s = vx.Sim(g, MATS, precision=precision, **PARAMS)
+        s.write_state(**states[i])
+        assert abs(s.dt / b.dt(i) - 1.0) < 1e-15
+        s.step(150)
+        e = compare(b.read_state(i), s.read_state(), g.reshape(-1) > 0)
+        assert max(e["u"], e["v"], e["w"]) < tol and e["q"] < tol, (i, e)
+
+
+def test_batch_matches_oracle_fp64():
+    grids, states = make_objects(4, seed=21, lo=3, hi=7)
+    announce("batch vs oracle")
+    b = run_batch(grids, states, 200, 64)
+    for i, g in enumerate(grids):
+        w = workloads._workload(g, MATS, workloads._base_params(**PARAMS), 200)
+        w["state"] = states[i]
+        o = build_oracle(w)
+        assert abs(o.dt / b.dt(i) - 1.0) < 1e-15
+        assert o.step(200) == 0
+        e = compare(b.read_state(i), o.read_state(), g.reshape(-1) > 0)
+        assert max(e["u"], e["v"], e["w"]) < 1e-10 and e["q"] < 1e-12, (i, e)
+
+
+def test_batch_launch_split_is_bitwise():
+    """Splitting the steps over several launches, or changing the number of
+    workgroups, runs the same arithmetic per object."""
+    grids, states = make_objects(10, seed=31)
+    announce("batch launch split")
+    ref = run_batch(grids, states, 60, 32)
+    alt = run_batch(grids, states, 60, 32, launch=(3, 7))
+    for i in range(len(grids)):
+        a, r = alt.read_state(i), ref.read_state(i)
+        for k in ("u", "q", "v", "w"):
+            assert np.array_equal(a[k], r[k]), (i, k)
+
+
+def test_batch_autotune_restores_state():
+    grids, states = make_objects(16, seed=41)
+    announce("batch autotune")
+    b = vx.Batch(grids, MATS, precision=32, **PARAMS)
+    b.bind()
+    for i, st in enumerate(states):
+        b.write_state(i, **st)
+    before = [b.read_state(i) for i in range(len(grids))]
+    nw = b.autotune(steps=5)
+    assert 1 <= nw <= len(grids)
+    assert b.counters()["steps"] == 0
+    for i in range(len(grids)):
+        now = b.read_state(i)
+        for k in ("u", "q", "v", "w"):
+            assert np.array_equal(now[k], before[i][k])
+
+
+def test_batch_of_generated_objects_runs():
+    """A slice of the 4096-object workload (8^3 .. 32^3, five classes) on the
+    floor: finite, and the bottom layers rest on the floor."""
+    objs = workloads.batch_objects(count=64, seed=4, steps=200)
+    announce("batch of 64 generated objects")
+    b = vx.Batch([o["grid"] for o in objs], objs[0]["materials"], precision=32, **objs[0]["params"])
+    b.step(200)
+    for i in (0, 17, 63):
+        st = b.read_state(i)
+        assert np.isfinite(st["u"]).all() and np.isfinite(st["v"]).all()
