@@ -140,6 +140,67 @@ def time_batch(count, steps, one_by_one_sample=64, one_by_one_steps=100):
             "roofline": roofline(32, nvox, ms / steps)}
 
 
+def time_adjoint(steps=5000, K=100):
+    """Differentiable rollout of the design lattice (64 blocks of 20^3,
+    per-voxel moduli and phases, FP32) from rest: a plain forward of `steps`
+    steps in parameter mode vs the forward with checkpoints plus the reverse
+    run (segment recompute included) of the same rollout on a fresh handle,
+    loss = mean x displacement."""
+    import numpy as np
+    import torch
+    import paper_1212_2845_amd as vx
+    import workloads
+    stream = torch.cuda.current_stream()
+
+    def make(w):
+        s = vx.from_workload(w, precision=32, stream=stream.cuda_stream)
+        s.set_stiffness(w["E"])
+        s.bind()
+        return s
+
+    # warm-up of every kernel on a small lattice of the same kind
+    ws = workloads.design_lattice(count=4, size=8, steps=40)
+    s = make(ws)
+    s.step(5)
+    s.grad_bind(40, 10)
+    s.grad_forward(40)
+    s.grad_backward(dL_du=np.ones((ws["grid"].size, 3)))
+    del s
+    w = workloads.design_lattice(steps=steps)
+    filled = w["grid"].reshape(-1) > 0
+    nvox = int(filled.sum())
+    wu = np.zeros((w["grid"].size, 3))
+    wu[filled, 0] = 1.0 / nvox
+    s = make(w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    del s
+    s = make(w)
+    gbytes = s.grad_bind(steps, K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.grad_forward(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g = s.grad_backward(dL_du=wu)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    del s
+    torch.cuda.empty_cache()
+    t_fa = t2 - t0
+    return {"workload": w["name"], "voxels": nvox, "cells": int(w["grid"].size), "steps": steps,
+            "checkpoint_every": K, "dtype": "f32", "grad_workspace_bytes": int(gbytes),
+            "forward_s": t_fwd, "grad_forward_s": t1 - t0, "grad_backward_s": t2 - t1,
+            "fwd_adj_over_fwd": t_fa / t_fwd,
+            "value": nvox * steps / t_fa, "unit": "voxel-steps/s (forward + reverse)",
+            "grad_E_absmax": float(np.abs(g["E"]).max()), "grad_phase_absmax": float(np.abs(g["phase"]).max()),
+            "note": "parameter mode runs the split kernels; wall time with host synchronisation at each "
+                    "checkpoint and the host copies of the adjoint in and the gradients out"}
+
+
 def cpu_baseline(w, budget_s=12.0, note=""):
     """The oracle (FP64, one thread) on a bounded sample of the workload."""
     import oracle
@@ -178,6 +239,8 @@ def main():
     ap.add_argument("--no-hbm-leg", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batch-leg", action="store_true")
+    ap.add_argument("--no-adjoint-leg", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=5000)
     ap.add_argument("--batch-objects", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--tile", default=None, metavar="SHAPE:ZC",
@@ -245,6 +308,9 @@ def main():
     if not args.no_batch_leg:
         log("batched leg: %d objects, %d steps" % (args.batch_objects, args.batch_steps))
         out["batched"] = time_batch(args.batch_objects, args.batch_steps)
+    if not args.no_adjoint_leg:
+        log("adjoint leg: design lattice, %d steps" % args.adjoint_steps)
+        out["adjoint"] = time_adjoint(args.adjoint_steps)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w)

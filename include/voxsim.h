@@ -184,6 +184,66 @@ int vx_autotune(vx_handle h, int32_t iters, int32_t *shape, int32_t *zc);
 int vx_time_kernel(vx_handle h, int32_t iters, double *ms_per_launch);
 
 /* ------------------------------------------------------------------ */
+/* Parameter mode and differentiable rollouts                          */
+/* ------------------------------------------------------------------ */
+/* The paper motivates the simulator as the inner loop of automated design
+ * (Sec. 1, Sec. 6): these calls give the gradient of a function of the
+ * final state with respect to per-voxel design parameters, by the reverse
+ * (adjoint) of the explicit step of Sec. 2-3 (bond forces Eq. 7, 13-24,
+ * damping Eq. 33-35, floor and friction Eq. 36-38, integration Eq. 27-30,
+ * actuation Eq. 39-40).  Branch decisions (floor contact, friction state)
+ * are those of the recorded forward run; the gradient is that of the
+ * piecewise-smooth map on the taken branch. */
+
+/* Per-voxel elastic modulus E[ncell] (Pa; read only at filled cells; NULL
+ * returns to the palette's moduli).  It replaces the palette modulus in
+ * the bond constants (Eq. 1-2, 8-12), the bond damping (Eq. 34-35), the
+ * floor stiffness and the ground damping; density, Poisson's ratio,
+ * expansion and friction stay the palette's.  The timestep stays the one
+ * chosen at create, so every bond's sqrt(k/m_min) must stay at or below
+ * the bound it was chosen for (include a material as stiff as the stiffest
+ * modulus in the palette).  While set, steps run the split kernels.
+ * Errors: VX_EINVAL for a non-positive or non-finite modulus, or one above
+ * the timestep's bound. */
+int vx_set_stiffness(vx_handle h, const double *E);
+
+/* Bytes of the gradient workspace for rollouts of up to max_steps steps
+ * with a checkpoint every K steps: ceil(max_steps/K) checkpoints plus a
+ * K-step recompute buffer, adjoint state and per-bond adjoint records
+ * (about (ceil(max_steps/K) + K) x (13 words + 1 byte) + K x 6 words +
+ * 128 words per cell). */
+int vx_grad_workspace_bytes(vx_handle h, int64_t max_steps, int32_t K, uint64_t *bytes);
+
+/* Bind a caller-owned, 256-byte aligned device buffer of at least
+ * vx_grad_workspace_bytes(h, max_steps, K) bytes.  Needs the main
+ * workspace bound and self-collision off.  Replaces an earlier binding.
+ * Errors: VX_ESTATE, VX_EINVAL (too small, misaligned, K or max_steps < 1). */
+int vx_grad_bind(vx_handle h, void *device_ptr, uint64_t bytes, int64_t max_steps, int32_t K);
+
+/* Advance n steps (1 <= n <= max_steps) like vx_step and record the
+ * checkpoints of the run.  Without vx_set_stiffness it first sets every
+ * voxel's modulus to its palette value.  Errors as vx_step; VX_ESTATE
+ * without a gradient workspace. */
+int vx_grad_forward(vx_handle h, int64_t n);
+
+/* Reverse run over the rollout recorded by the last vx_grad_forward, which
+ * must end at the current state (any step, state write or setter in
+ * between invalidates it: VX_ESTATE).
+ * Inputs (host, NULL = zero): adjoint of the final state, dL/du (3 per
+ * cell), dL/dq (4 per cell, quaternion w,x,y,z), dL/dv (3), dL/dw (3), in
+ * the layout of vx_read_state.
+ * Outputs (host, NULL = not wanted), per cell, zero at empty cells:
+ *   g_E      dL/dE of vx_set_stiffness's moduli;
+ *   g_phase  dL/dphase, g_amp dL/damp of vx_set_actuation's per-voxel
+ *            signal (zero when the voxel follows the global signal);
+ *   g_u0, g_q0, g_v0, g_w0  adjoint of the rollout's initial state.
+ * The adjoint state is kept in the state's precision; the parameter
+ * gradients are accumulated in FP64. */
+int vx_grad_backward(vx_handle h, const double *dL_du, const double *dL_dq, const double *dL_dv,
+                     const double *dL_dw, double *g_E, double *g_phase, double *g_amp, double *g_u0,
+                     double *g_q0, double *g_v0, double *g_w0);
+
+/* ------------------------------------------------------------------ */
 /* Batches: many independent objects stepped by one persistent launch  */
 /* ------------------------------------------------------------------ */
 

@@ -32,6 +32,8 @@ EXPORTED = ["vx_create", "vx_workspace_bytes", "vx_bind_workspace", "vx_set_fixe
             "vx_read_state", "vx_write_state", "vx_read_flags", "vx_get_dt", "vx_get_time",
             "vx_counters", "vx_candidates", "vx_set_kernel", "vx_set_fused_tile", "vx_get_fused_tile",
             "vx_autotune", "vx_time_kernel", "vx_destroy", "vx_last_error",
+            "vx_set_stiffness", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
+            "vx_grad_backward",
             "vx_batch_create", "vx_batch_workspace_bytes", "vx_batch_bind_workspace", "vx_batch_step",
             "vx_batch_read_state", "vx_batch_write_state", "vx_batch_get_dt", "vx_batch_counters",
             "vx_batch_set_launch", "vx_batch_autotune", "vx_batch_destroy", "vx_batch_last_error"]
@@ -75,6 +77,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libvoxsim.so not found at %s; build it with "
                           "python -m paper_1212_2845_amd.build" % LIB_PATH)
+    # torch ships its own HIP runtime under the same soname as ROCm's; load
+    # it first so that the library and torch share one runtime (device
+    # pointers from torch tensors are then valid in the library's calls)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p
     i32, i64, u64 = C.c_int32, C.c_int64, C.c_uint64
@@ -101,6 +110,11 @@ def lib():
     L.vx_get_fused_tile.argtypes = [P, pi32, pi32, pi32, pi32]
     L.vx_autotune.argtypes = [P, i32, pi32, pi32]
     L.vx_time_kernel.argtypes = [P, i32, C.POINTER(C.c_double)]
+    L.vx_set_stiffness.argtypes = [P, P]
+    L.vx_grad_workspace_bytes.argtypes = [P, i64, i32, C.POINTER(u64)]
+    L.vx_grad_bind.argtypes = [P, P, u64, i64, i32]
+    L.vx_grad_forward.argtypes = [P, i64]
+    L.vx_grad_backward.argtypes = [P] + [P] * 11
     L.vx_destroy.argtypes = [P]
     L.vx_last_error.argtypes = [P]
     L.vx_last_error.restype = C.c_char_p
@@ -321,6 +335,77 @@ class Sim:
         a = np.empty(max(k, 1), np.int32); b = np.empty(max(k, 1), np.int32)
         self._check(lib().vx_candidates(self.h, _ptr(a), _ptr(b), k, C.byref(n)))
         return set(zip(a[:k].tolist(), b[:k].tolist()))
+
+
+    # -- parameter mode and differentiable rollouts --------------------------
+    def set_stiffness(self, E):
+        """Per-voxel elastic modulus (ncell values; None returns to the palette)."""
+        e = None if E is None else np.ascontiguousarray(E, dtype=np.float64).reshape(-1)
+        if e is not None:
+            assert e.size == self.ncell
+        self._check(lib().vx_set_stiffness(self.h, _ptr(e)))
+
+    def grad_bind(self, max_steps, K):
+        """Allocate (torch) and bind the gradient workspace for rollouts of up
+        to max_steps steps with a checkpoint every K steps."""
+        import torch
+        self.bind()
+        n = C.c_uint64()
+        self._check(lib().vx_grad_workspace_bytes(self.h, int(max_steps), int(K), C.byref(n)))
+        if getattr(self, "_gws", None) is None or self._gws.numel() < n.value:
+            self._gws = None
+            self._gws = torch.empty(n.value, dtype=torch.uint8, device=self._ws.device)
+        self._check(lib().vx_grad_bind(self.h, C.c_void_p(self._gws.data_ptr()), n.value, int(max_steps), int(K)))
+        return n.value
+
+    def grad_forward(self, n):
+        self._check(lib().vx_grad_forward(self.h, int(n)))
+
+    def grad_backward(self, dL_du=None, dL_dq=None, dL_dv=None, dL_dw=None):
+        """Gradients of a function of the final state (adjoints given per
+        cell, None = 0) w.r.t. the moduli, the per-voxel actuation phase and
+        amplitude, and the rollout's initial state."""
+        n = self.ncell
+        conv = lambda a, k: None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(n, k)
+        du, dq, dv, dw = conv(dL_du, 3), conv(dL_dq, 4), conv(dL_dv, 3), conv(dL_dw, 3)
+        out = {"E": np.empty(n), "phase": np.empty(n), "amp": np.empty(n), "u0": np.empty((n, 3)),
+               "q0": np.empty((n, 4)), "v0": np.empty((n, 3)), "w0": np.empty((n, 3))}
+        self._check(lib().vx_grad_backward(self.h, _ptr(du), _ptr(dq), _ptr(dv), _ptr(dw), _ptr(out["E"]),
+                                           _ptr(out["phase"]), _ptr(out["amp"]), _ptr(out["u0"]),
+                                           _ptr(out["q0"]), _ptr(out["v0"]), _ptr(out["w0"])))
+        return out
+
+
+def _rollout_fn():
+    import torch
+
+    class RolloutFn(torch.autograd.Function):
+        """Final displacement and velocity (ncell x 3 each, float64, CPU) of an
+        n-step rollout from the Sim's current state, differentiable w.r.t. the
+        per-voxel modulus E and actuation phase (ncell each).  The actuation
+        amplitude is held fixed at amp."""
+
+        @staticmethod
+        def forward(ctx, E, phase, sim, amp, n):
+            sim.set_stiffness(E.detach().cpu().numpy())
+            sim.set_actuation(amp, phase.detach().cpu().numpy())
+            sim.grad_forward(n)
+            st = sim.read_state()
+            ctx.sim = sim
+            return torch.from_numpy(st["u"]), torch.from_numpy(st["v"])
+
+        @staticmethod
+        def backward(ctx, gu, gv):
+            g = ctx.sim.grad_backward(dL_du=gu.cpu().numpy(), dL_dv=gv.cpu().numpy())
+            return torch.from_numpy(g["E"]), torch.from_numpy(g["phase"]), None, None, None
+
+    return RolloutFn
+
+
+def rollout(sim, E, phase, amp, n):
+    """(u, v) after n steps from sim's current state; differentiable in E and
+    phase through the library's reverse run (sim needs grad_bind first)."""
+    return _rollout_fn().apply(E, phase, sim, amp, n)
 
 
 def from_workload(w, precision=64, kernel=KERNEL_FUSED, stream=None):

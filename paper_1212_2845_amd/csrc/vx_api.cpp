@@ -12,87 +12,9 @@
 
 #include "../../include/voxsim.h"
 #include "vx_host.hpp"
-#include "vx_launch.hpp"
-#include "vx_types.hpp"
+#include "vx_sim.hpp"
 
 using namespace vx;
-
-namespace {
-
-constexpr double kPi = 3.14159265358979323846;
-constexpr uint64_t kAlign = 256;
-
-uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-struct Layout {
-    uint64_t state[2], mat, flags[2], mats, pairs, bonds, act_amp, act_phase, forced_cells, forced_F;
-    uint64_t contact_F, surf_cells, cand, cand_n, keys, sorted, bstart, bfill, scalars, scan_tmp;
-    uint64_t total;
-};
-
-// Small device-side scalars, one 256-byte block.
-struct Scalars {
-    unsigned err_flag;
-    unsigned overflow;
-    unsigned rebuild_flag;
-    unsigned pad0;
-    unsigned long long vmax_bits;
-    double macc;
-    unsigned long long pair_count;
-    unsigned long long rebuilds;
-};
-
-}  // namespace
-
-struct vx_sim {
-    int nx = 0, ny = 0, nz = 0;
-    long long ncell = 0;
-    vx_params p{};
-    int precision = 64;
-    size_t tsize = 8;
-    hipStream_t stream = nullptr;
-    int n_mat = 0;
-    std::vector<vx_material> pal;
-    std::vector<uint8_t> grid, flags;
-    std::vector<double> amp, phase;      // per cell; valid where FLAG_ACT
-    bool has_act = false;
-    std::vector<double> force;           // ncell x 3 (host copy)
-    std::vector<int> forced_cells;
-    std::vector<double> forced_F;
-    int forced_cap = 0;
-    std::vector<int> surf_cells;
-    long long nvox = 0;
-    double dt = 0.0;
-    long long step = 0;
-    int kernel_kind = 0;
-    int cand_cap = 32;
-    int table_size = 1;
-    size_t scan_tmp_bytes = 0;
-    double cmax = 0.0;
-    // initial state in double, 13 x ncell (used until bind)
-    std::vector<double> state0;
-    // device
-    bool bound = false;
-    char *ws = nullptr;
-    Layout L{};
-    int cur = 0;                          // which state / flags buffer holds step n
-    bool flags_live = false;              // device flags hold dynamic bits
-    int fused_shape = -1;                 // tile shape of the fused kernel (-1: heuristic)
-    int fused_zc = 0;                     // z chunk of the fused kernel (0: heuristic)
-    std::string err;
-};
-
-static int fail(vx_sim *h, int code, const std::string &msg) {
-    if (h) h->err = msg;
-    return code;
-}
-
-#define HIP_OK(h, call)                                                        \
-    do {                                                                       \
-        hipError_t e_ = (call);                                                \
-        if (e_ != hipSuccess)                                                  \
-            return fail(h, VX_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
 
 // ---------------------------------------------------------------------------
 // packing
@@ -137,74 +59,11 @@ static void compute_layout(vx_sim *h) {
     L.bfill = take(col ? (uint64_t)h->table_size * 4 : 0);
     L.scalars = take(sizeof(Scalars));
     L.scan_tmp = take(col ? h->scan_tmp_bytes : 0);
+    L.E_cell = take(n * ts);
     L.total = off;
 }
 
-template <typename T>
-static StepArgs<T> make_args(vx_sim *h) {
-    StepArgs<T> a{};
-    char *ws = h->ws;
-    a.s_in = (const T *)(ws + h->L.state[h->cur]);
-    a.s_out = (T *)(ws + h->L.state[1 - h->cur]);
-    a.stride = h->ncell;
-    a.mat = (const uint8_t *)(ws + h->L.mat);
-    a.flags = (const uint8_t *)(ws + h->L.flags[h->cur]);
-    a.flags_out = (uint8_t *)(ws + h->L.flags[1 - h->cur]);
-    a.mats = (const MatConst<T> *)(ws + h->L.mats);
-    a.pairs = (const PairConst<T> *)(ws + h->L.pairs);
-    a.n_mat = h->n_mat;
-    a.nx = h->nx; a.ny = h->ny; a.nz = h->nz;
-    a.l = (T)h->p.voxel_size;
-    a.dt = (T)h->dt;
-    a.gravity = (T)h->p.gravity;
-    a.origin_z = (T)h->p.origin[2];
-    for (int k = 0; k < 3; ++k) a.origin[k] = h->p.origin[k];
-    const double tn = (double)h->step * h->dt;
-    const double wt = 2.0 * kPi * h->p.temp_freq * tn;
-    a.wt = wt;
-    a.wt_red = (T)std::fmod(wt, 2.0 * kPi);
-    a.dT_global = (T)(h->p.temp_amp * std::sin(wt + h->p.temp_phase));
-    a.act_amp = (const T *)(ws + h->L.act_amp);
-    a.act_phase = (const T *)(ws + h->L.act_phase);
-    a.forced_cells = (const int *)(ws + h->L.forced_cells);
-    a.forced_F = (const T *)(ws + h->L.forced_F);
-    a.n_forced = (int)h->forced_cells.size();
-    a.floor_on = h->p.floor_on;
-    a.track_vmax = h->p.self_collision_on;
-    a.contact_F = (const T *)(ws + h->L.contact_F);
-    a.bonds = (T *)(ws + h->L.bonds);
-    Scalars *sc = (Scalars *)(ws + h->L.scalars);
-    a.err_flag = &sc->err_flag;
-    a.vmax_bits = &sc->vmax_bits;
-    return a;
-}
 
-static CollideArgs make_collide(vx_sim *h) {
-    CollideArgs c{};
-    char *ws = h->ws;
-    c.surf_cells = (const int *)(ws + h->L.surf_cells);
-    c.n_surf = (int)h->surf_cells.size();
-    c.cap = h->cand_cap;
-    c.cand = (int *)(ws + h->L.cand);
-    c.cand_n = (int *)(ws + h->L.cand_n);
-    Scalars *sc = (Scalars *)(ws + h->L.scalars);
-    c.overflow = &sc->overflow;
-    c.rebuild_flag = &sc->rebuild_flag;
-    c.macc = &sc->macc;
-    c.vmax_bits = &sc->vmax_bits;
-    c.cell_keys = (int *)(ws + h->L.keys);
-    c.sorted_idx = (int *)(ws + h->L.sorted);
-    c.bucket_start = (int *)(ws + h->L.bstart);
-    c.bucket_fill = (int *)(ws + h->L.bfill);
-    c.table_size = h->table_size;
-    c.pair_count = &sc->pair_count;
-    c.horizon = 2.0 * h->p.voxel_size;
-    c.threshold = 2.0 * h->p.voxel_size - h->cmax;
-    c.scan_tmp = (void *)(ws + h->L.scan_tmp);
-    c.scan_tmp_bytes = h->scan_tmp_bytes;
-    c.rebuild_counter = &sc->rebuilds;
-    return c;
-}
 
 // Upload the per-voxel, per-material and region data (not the state).
 template <typename T>
@@ -238,6 +97,10 @@ static int upload_static(vx_sim *h) {
         for (long long c = 0; c < h->ncell; ++c) { a[c] = (T)h->amp[c]; ph[c] = (T)h->phase[c]; }
     HIP_OK(h, hipMemcpyAsync(ws + h->L.act_amp, a.data(), h->ncell * sizeof(T), hipMemcpyHostToDevice, s));
     HIP_OK(h, hipMemcpyAsync(ws + h->L.act_phase, ph.data(), h->ncell * sizeof(T), hipMemcpyHostToDevice, s));
+    std::vector<T> ec(h->ncell, T(0));
+    if (h->has_E)
+        for (long long c = 0; c < h->ncell; ++c) ec[c] = (T)h->E_cell[c];
+    HIP_OK(h, hipMemcpyAsync(ws + h->L.E_cell, ec.data(), h->ncell * sizeof(T), hipMemcpyHostToDevice, s));
     if ((int)h->forced_cells.size() > h->forced_cap)
         return fail(h, VX_ESTATE, "more forced voxels than the workspace was sized for; set forces before the first step");
     std::vector<T> ff(h->forced_F.size());
@@ -277,11 +140,13 @@ static int get_state(vx_sim *h, std::vector<double> &st) {
 }
 
 static int put_state(vx_sim *h, const std::vector<double> &st) {
+    h->tape_valid = false;
     if (!h->bound) { h->state0 = st; return VX_OK; }
     return h->precision == 64 ? upload_state<double>(h, st) : upload_state<float>(h, st);
 }
 
 static int reupload_static(vx_sim *h) {
+    h->tape_valid = false;
     if (!h->bound) return VX_OK;
     return h->precision == 64 ? upload_static<double>(h) : upload_static<float>(h);
 }
@@ -347,7 +212,7 @@ static int run_steps(vx_sim *h, int64_t n) {
             HIP_OK(h, launch_rebuild<T>(a, c, h->stream));
             HIP_OK(h, launch_contact<T>(a, c, (T *)(h->ws + h->L.contact_F), h->stream));
         }
-        if (h->kernel_kind == 1 || h->n_mat > kFusedMaxMat) {
+        if (h->kernel_kind == 1 || h->n_mat > kFusedMaxMat || h->has_E) {
             HIP_OK(h, launch_split_step<T>(a, h->stream));
         } else {
             HIP_OK(h, launch_fused_step<T>(a, fused_cfg(h), h->stream));
@@ -421,7 +286,7 @@ static int time_kernel(vx_sim *h, int iters, double *ms_per_launch) {
         HIP_OK(h, launch_rebuild<T>(a, c, h->stream));
         HIP_OK(h, launch_contact<T>(a, c, (T *)(h->ws + h->L.contact_F), h->stream));
     }
-    const bool split = h->kernel_kind == 1 || h->n_mat > kFusedMaxMat;
+    const bool split = h->kernel_kind == 1 || h->n_mat > kFusedMaxMat || h->has_E;
     const FusedCfg cfg = fused_cfg(h);
     auto launch = [&]() { return split ? launch_split_step<T>(a, h->stream) : launch_fused_step<T>(a, cfg, h->stream); };
     hipEvent_t e0, e1;
@@ -512,6 +377,7 @@ int vx_create(const uint8_t *grid, int32_t nx, int32_t ny, int32_t nz, const vx_
     for (long long c = 0; c < ncell; ++c) seen_vox[grid[c]] = 1;
     const double wmax = max_bond_omega(palette, n_mat, l, pair_seen, seen_vox);
     h->dt = wmax > 0.0 ? h->p.dt_scale / (2.0 * kPi * wmax) : 0.0;
+    h->wmax = wmax;
     // rest state
     h->state0.assign((size_t)N_WORDS * ncell, 0.0);
     for (long long c = 0; c < ncell; ++c) h->state0[W_QW * ncell + c] = 1.0;
@@ -662,7 +528,48 @@ int vx_step(vx_handle h, int64_t n) {
     if (!h || n < 0) return VX_EINVAL;
     if (!h->bound) return fail(h, VX_ESTATE, "vx_step before vx_bind_workspace");
     if (n == 0) return VX_OK;
+    h->tape_valid = false;
     return h->precision == 64 ? run_steps<double>(h, n) : run_steps<float>(h, n);
+}
+
+int vx_set_stiffness(vx_handle h, const double *E) {
+    if (!h) return VX_EINVAL;
+    if (!E) {
+        h->has_E = false;
+        h->E_cell.clear();
+        return reupload_static(h);
+    }
+    const double l = h->p.voxel_size;
+    const long long stp[3] = {1, h->nx, (long long)h->nx * h->ny};
+    double w = 0.0;
+    bool any_bond = false;
+    for (long long c = 0; c < h->ncell; ++c) {
+        const int m = h->grid[c];
+        if (!m) continue;
+        if (!(E[c] > 0.0) || !std::isfinite(E[c])) return fail(h, VX_EINVAL, "per-voxel modulus must be positive and finite");
+        const int idx[3] = {(int)(c % h->nx), (int)((c / h->nx) % h->ny), (int)(c / stp[2])};
+        const int dim[3] = {h->nx, h->ny, h->nz};
+        for (int a = 0; a < 3; ++a) {
+            if (idx[a] + 1 >= dim[a] || !h->grid[c + stp[a]]) continue;
+            const long long cn = c + stp[a];
+            any_bond = true;
+            const double kb = composite(E[c], E[cn]) * l;
+            const double mm = std::min(mass_of(h, m), mass_of(h, h->grid[cn]));
+            w = std::max(w, std::sqrt(kb / mm));
+        }
+    }
+    if (!any_bond)
+        for (long long c = 0; c < h->ncell; ++c)
+            if (h->grid[c]) w = std::max(w, std::sqrt(E[c] * l / mass_of(h, h->grid[c])));
+    // the timestep stays the one chosen at create: the moduli may not raise
+    // the highest bond frequency it was chosen for
+    if (w > h->wmax * (1.0 + 1e-12))
+        return fail(h, VX_EINVAL, "per-voxel modulus above the stable bound of the timestep chosen at create");
+    h->E_cell.assign(h->ncell, 0.0);
+    for (long long c = 0; c < h->ncell; ++c)
+        if (h->grid[c]) h->E_cell[c] = E[c];
+    h->has_E = true;
+    return reupload_static(h);
 }
 
 int vx_read_state(vx_handle h, double *u, double *q, double *vel, double *omega) {

@@ -5,39 +5,53 @@
 
 #include "vx_types.hpp"
 
+// The per-bond and per-voxel math compiles for the host too (for unit
+// checks of the hand-written derivatives); kernels use it on the device.
+#define VX_HD __host__ __device__ __forceinline__
+
 namespace vx {
 
 template <typename T> struct V3 { T x, y, z; };
 
 template <int I, typename T>
-__device__ __forceinline__ T comp(const V3<T> &v) {
+VX_HD T comp(const V3<T> &v) {
     if constexpr (I == 0) return v.x;
     else if constexpr (I == 1) return v.y;
     else return v.z;
 }
 
-template <typename T> __device__ __forceinline__ T dsqrt(T a);
-template <> __device__ __forceinline__ float dsqrt<float>(float a) { return sqrtf(a); }
-template <> __device__ __forceinline__ double dsqrt<double>(double a) { return sqrt(a); }
-template <typename T> __device__ __forceinline__ T datan2(T y, T x);
-template <> __device__ __forceinline__ float datan2<float>(float y, float x) { return atan2f(y, x); }
-template <> __device__ __forceinline__ double datan2<double>(double y, double x) { return atan2(y, x); }
-template <typename T> __device__ __forceinline__ void dsincos(T a, T *s, T *c);
-template <> __device__ __forceinline__ void dsincos<float>(float a, float *s, float *c) { sincosf(a, s, c); }
-template <> __device__ __forceinline__ void dsincos<double>(double a, double *s, double *c) { sincos(a, s, c); }
-template <typename T> __device__ __forceinline__ bool dfinite(T a);
-template <> __device__ __forceinline__ bool dfinite<float>(float a) { return isfinite(a); }
-template <> __device__ __forceinline__ bool dfinite<double>(double a) { return isfinite(a); }
-template <typename T> __device__ __forceinline__ T dsin(T a);
-template <> __device__ __forceinline__ float dsin<float>(float a) { return sinf(a); }
-template <> __device__ __forceinline__ double dsin<double>(double a) { return sin(a); }
+template <typename T> VX_HD T dsqrt(T a);
+template <> VX_HD float dsqrt<float>(float a) { return sqrtf(a); }
+template <> VX_HD double dsqrt<double>(double a) { return sqrt(a); }
+template <typename T> VX_HD T datan2(T y, T x);
+template <> VX_HD float datan2<float>(float y, float x) { return atan2f(y, x); }
+template <> VX_HD double datan2<double>(double y, double x) { return atan2(y, x); }
+template <typename T> VX_HD void dsincos(T a, T *s, T *c);
+template <> VX_HD void dsincos<float>(float a, float *s, float *c) { sincosf(a, s, c); }
+template <> VX_HD void dsincos<double>(double a, double *s, double *c) { sincos(a, s, c); }
+template <typename T> VX_HD bool dfinite(T a);
+template <> VX_HD bool dfinite<float>(float a) { return isfinite(a); }
+template <> VX_HD bool dfinite<double>(double a) { return isfinite(a); }
+template <typename T> VX_HD T dsin(T a);
+template <> VX_HD float dsin<float>(float a) { return sinf(a); }
+template <> VX_HD double dsin<double>(double a) { return sin(a); }
 
 // Reciprocal of x > 0: FP32 hardware estimate (1 ulp); FP64 hardware
 // estimate refined by Newton steps to full precision.
-template <typename T> __device__ __forceinline__ T frcp(T x);
-template <> __device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ __forceinline__ double frcp<double>(double x) {
+template <typename T> VX_HD T frcp(T x);
+template <> VX_HD float frcp<float>(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+template <> VX_HD double frcp<double>(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
     double y = __builtin_amdgcn_rcp(x);
+#else
+    double y = 1.0 / x;
+#endif
     double e = fma(-x, y, 1.0);
     y = fma(y, e, y);
     e = fma(-x, y, 1.0);
@@ -62,14 +76,14 @@ template <> struct Series<double> {
 };
 
 // atan(t)/t for u = t^2 < kLogU (alternating Taylor series 1 - u/3 + u^2/5 - ...).
-template <typename T> __device__ __forceinline__ T atan_over_t(T u);
-template <> __device__ __forceinline__ float atan_over_t<float>(float u) {
+template <typename T> VX_HD T atan_over_t(T u);
+template <> VX_HD float atan_over_t<float>(float u) {
     float p = -1.0f / 7.0f;
     p = fmaf(p, u, 1.0f / 5.0f);
     p = fmaf(p, u, -1.0f / 3.0f);
     return fmaf(p, u, 1.0f);
 }
-template <> __device__ __forceinline__ double atan_over_t<double>(double u) {
+template <> VX_HD double atan_over_t<double>(double u) {
     double p = -1.0 / 15.0;
     p = fma(p, u, 1.0 / 13.0);
     p = fma(p, u, -1.0 / 11.0);
@@ -81,8 +95,8 @@ template <> __device__ __forceinline__ double atan_over_t<double>(double u) {
 }
 
 // cos(h) and sin(h) / (2 h) for a2 = (2 h)^2 < kExpA2 (Taylor in h^2 = a2/4).
-template <typename T> __device__ __forceinline__ void half_angle_series(T a2, T *c, T *sk);
-template <> __device__ __forceinline__ void half_angle_series<float>(float a2, float *c, float *sk) {
+template <typename T> VX_HD void half_angle_series(T a2, T *c, T *sk);
+template <> VX_HD void half_angle_series<float>(float a2, float *c, float *sk) {
     const float h2 = 0.25f * a2;
     float pc = 1.0f / 24.0f;
     pc = fmaf(pc, h2, -0.5f);
@@ -91,7 +105,7 @@ template <> __device__ __forceinline__ void half_angle_series<float>(float a2, f
     ps = fmaf(ps, h2, -1.0f / 6.0f);
     *sk = 0.5f * fmaf(ps, h2, 1.0f);
 }
-template <> __device__ __forceinline__ void half_angle_series<double>(double a2, double *c, double *sk) {
+template <> VX_HD void half_angle_series<double>(double a2, double *c, double *sk) {
     const double h2 = 0.25 * a2;
     double pc = 1.0 / 40320.0;
     pc = fma(pc, h2, -1.0 / 720.0);
@@ -108,11 +122,11 @@ template <> __device__ __forceinline__ void half_angle_series<double>(double a2,
 // Element c of array base through a 32-bit byte offset from a uniform base,
 // so the load/store addresses as SGPR base + one shared VGPR offset.
 template <typename T>
-__device__ __forceinline__ T ldc(const T *base, unsigned c) {
+VX_HD T ldc(const T *base, unsigned c) {
     return *(const T *)((const char *)base + (size_t)(c * (unsigned)sizeof(T)));
 }
 template <typename T>
-__device__ __forceinline__ void stc(T *base, unsigned c, T v) {
+VX_HD void stc(T *base, unsigned c, T v) {
     *(T *)((char *)base + (size_t)(c * (unsigned)sizeof(T))) = v;
 }
 
@@ -136,7 +150,7 @@ struct Rot {
 };
 
 template <typename T>
-__device__ __forceinline__ Rot<T> rot_of(T w, T x, T y, T z) {
+VX_HD Rot<T> rot_of(T w, T x, T y, T z) {
     Rot<T> R;
     const T two = T(2);
     R.dm1[0] = -two * (y * y + z * z);
@@ -174,14 +188,14 @@ struct LatK {
 };
 
 template <typename T>
-__device__ __forceinline__ LatK<T> lat_consts(T l) {
+VX_HD LatK<T> lat_consts(T l) {
     LatK<T> c;
     c.l = l; c.hl = T(0.5) * l; c.l26 = l * l / T(6); c.l23 = l * l / T(3);
     return c;
 }
 
 template <typename T>
-__device__ __forceinline__ BondK<T> bond_k(const PairConst<T> &pc) {
+VX_HD BondK<T> bond_k(const PairConst<T> &pc) {
     BondK<T> k;
     k.a1 = pc.a1; k.a2 = pc.a2; k.ct = pc.ct;
     return k;
@@ -190,7 +204,7 @@ __device__ __forceinline__ BondK<T> bond_k(const PairConst<T> &pc) {
 // Rotation vector of q_A^-1 q_B (voxel 2's rotation relative to voxel 1, in
 // voxel 1's body frame), on the short branch: 2 atan2(|v|, |w|) v / |v|.
 template <typename T>
-__device__ __forceinline__ void rel_rotvec(const VoxKin<T> &A, const VoxKin<T> &B, T th[3]) {
+VX_HD void rel_rotvec(const VoxKin<T> &A, const VoxKin<T> &B, T th[3]) {
     const T rw = A.qw * B.qw + A.qx * B.qx + A.qy * B.qy + A.qz * B.qz;
     const T rx = A.qw * B.qx - A.qx * B.qw - A.qy * B.qz + A.qz * B.qy;
     const T ry = A.qw * B.qy + A.qx * B.qz - A.qy * B.qw - A.qz * B.qx;
@@ -222,7 +236,7 @@ __device__ __forceinline__ void rel_rotvec(const VoxKin<T> &A, const VoxKin<T> &
 // rotation in the bond frame.  The result is rotated back to the world
 // frame and bond damping (Eq. 33-35) is added.
 template <typename T>
-__device__ __forceinline__ BondOut<T> bond_core(const VoxKin<T> &A, const VoxKin<T> &B, const T du[3],
+VX_HD BondOut<T> bond_core(const VoxKin<T> &A, const VoxKin<T> &B, const T du[3],
                                                 const T d[3], const V3<T> &ex, const V3<T> &ey,
                                                 const V3<T> &ez, T exm1, T ey_a, T ez_a, T tx, T ty, T tz,
                                                 const BondK<T> &K, const LatK<T> &C) {
@@ -268,7 +282,7 @@ __device__ __forceinline__ BondOut<T> bond_core(const VoxKin<T> &A, const VoxKin
 
 // Bond along lattice axis AX (compile-time).
 template <typename T, int AX>
-__device__ __forceinline__ BondOut<T> bond_eval(const VoxKin<T> &A, const Rot<T> &RA, const VoxKin<T> &B,
+VX_HD BondOut<T> bond_eval(const VoxKin<T> &A, const Rot<T> &RA, const VoxKin<T> &B,
                                                 const BondK<T> &K, const LatK<T> &C) {
     constexpr int A0 = AX, A1 = (AX + 1) % 3, A2 = (AX + 2) % 3;
     const T du[3] = {B.ux - A.ux, B.uy - A.uy, B.uz - A.uz};
@@ -282,7 +296,7 @@ __device__ __forceinline__ BondOut<T> bond_eval(const VoxKin<T> &A, const Rot<T>
 
 // Bond along x (yaxis = false) or y (yaxis = true), chosen per lane.
 template <typename T>
-__device__ __forceinline__ BondOut<T> bond_eval_xy(const VoxKin<T> &A, const Rot<T> &RA, const VoxKin<T> &B,
+VX_HD BondOut<T> bond_eval_xy(const VoxKin<T> &A, const Rot<T> &RA, const VoxKin<T> &B,
                                                    const BondK<T> &K, const LatK<T> &C, bool yaxis) {
     const T du[3] = {B.ux - A.ux, B.uy - A.uy, B.uz - A.uz};
     T d[3] = {du[0], du[1], du[2]};
@@ -301,7 +315,7 @@ __device__ __forceinline__ BondOut<T> bond_eval_xy(const VoxKin<T> &A, const Rot
 
 // FP32 evaluates the signal from the host-reduced phase 2 pi f t_n mod 2 pi.
 template <typename T>
-__device__ __forceinline__ T voxel_strain(const StepArgs<T> &a, unsigned c, uint8_t fl, T cte) {
+VX_HD T voxel_strain(const StepArgs<T> &a, unsigned c, uint8_t fl, T cte) {
     T dT = a.dT_global;
     if (fl & FLAG_ACT) {
         if constexpr (sizeof(T) == 8) {
@@ -313,6 +327,21 @@ __device__ __forceinline__ T voxel_strain(const StepArgs<T> &a, unsigned c, uint
     return cte * dT;
 }
 
+// d eps / d phase and d eps / d amp of a voxel with its own actuation
+// signal (FLAG_ACT), at the same argument as voxel_strain.
+template <typename T>
+VX_HD void voxel_strain_d(const StepArgs<T> &a, unsigned c, T cte, T *d_phase, T *d_amp) {
+    const T amp = ldc(a.act_amp, c);
+    T sn, cs;
+    if constexpr (sizeof(T) == 8) {
+        dsincos<T>(a.wt + ldc(a.act_phase, c), &sn, &cs);
+    } else {
+        dsincos<T>(a.wt_red + ldc(a.act_phase, c), &sn, &cs);
+    }
+    *d_phase = cte * amp * cs;
+    *d_amp = cte * sn;
+}
+
 // Raw state words of one voxel.
 template <typename T>
 struct VoxRaw {
@@ -320,7 +349,7 @@ struct VoxRaw {
 };
 
 template <typename T>
-__device__ __forceinline__ VoxRaw<T> load_raw(const T *__restrict__ s, long long st, unsigned c) {
+VX_HD VoxRaw<T> load_raw(const T *__restrict__ s, long long st, unsigned c) {
     VoxRaw<T> r;
     r.ux = ldc(s + W_UX * st, c); r.uy = ldc(s + W_UY * st, c); r.uz = ldc(s + W_UZ * st, c);
     r.qw = ldc(s + W_QW * st, c); r.qx = ldc(s + W_QX * st, c);
@@ -331,7 +360,7 @@ __device__ __forceinline__ VoxRaw<T> load_raw(const T *__restrict__ s, long long
 }
 
 template <typename T>
-__device__ __forceinline__ void store_raw(T *__restrict__ o, long long st, unsigned c, T ux, T uy, T uz, T qw,
+VX_HD void store_raw(T *__restrict__ o, long long st, unsigned c, T ux, T uy, T uz, T qw,
                                           T qx, T qy, T qz, T px, T py, T pz, T lx, T ly, T lz) {
     stc(o + W_UX * st, c, ux); stc(o + W_UY * st, c, uy); stc(o + W_UZ * st, c, uz);
     stc(o + W_QW * st, c, qw); stc(o + W_QX * st, c, qx); stc(o + W_QY * st, c, qy); stc(o + W_QZ * st, c, qz);
@@ -340,7 +369,7 @@ __device__ __forceinline__ void store_raw(T *__restrict__ o, long long st, unsig
 }
 
 template <typename T>
-__device__ __forceinline__ VoxKin<T> kin_of(const VoxRaw<T> &r, const MatConst<T> &mc, T eps) {
+VX_HD VoxKin<T> kin_of(const VoxRaw<T> &r, const MatConst<T> &mc, T eps) {
     VoxKin<T> k;
     k.ux = r.ux; k.uy = r.uy; k.uz = r.uz;
     k.qw = r.qw; k.qx = r.qx; k.qy = r.qy; k.qz = r.qz;
@@ -351,134 +380,197 @@ __device__ __forceinline__ VoxKin<T> kin_of(const VoxRaw<T> &r, const MatConst<T
 }
 
 template <typename T>
-__device__ __forceinline__ VoxKin<T> load_kin(const T *__restrict__ s, long long stride, unsigned c,
+VX_HD VoxKin<T> load_kin(const T *__restrict__ s, long long stride, unsigned c,
                                               const MatConst<T> &mc, T eps) {
     return kin_of(load_raw(s, stride, c), mc, eps);
 }
 
-// Everything after the bond sum for one voxel: external force, gravity,
-// ground damping, floor, contact, Coulomb friction, then the synchronous
-// "double Euler" update (Eq. 27-30) with the orientation advanced by the
-// exact rotation w dt.  r is the voxel's state at t_n; writes the new state
-// of cell c.
+// Material constants of one voxel whose modulus E overrides the palette's
+// (parameter mode): the stiffness-dependent fields recomputed from E.
 template <typename T>
-__device__ __forceinline__ void voxel_update(const StepArgs<T> &a, unsigned c, uint8_t fl,
-                                             const MatConst<T> &mc, T eps, const VoxRaw<T> &r, T Fx,
-                                             T Fy, T Fz, T Mx, T My, T Mz, T *vmax_local) {
-    // vmax_local tracks the largest squared speed
-    T *__restrict__ o = a.s_out;
-    const long long st = a.stride;
+VX_HD MatConst<T> mat_with_E(MatConst<T> mc, T E, T l, T zeta_slow, T zeta_col) {
+    mc.E = E;
+    mc.kv = E * l;
+    mc.cg = T(2) * zeta_slow * dsqrt(mc.m * mc.kv);
+    mc.cgr = T(2) * zeta_slow * dsqrt(mc.I * E * l * l * l / T(6));
+    mc.cfloor = T(2) * zeta_col * dsqrt(mc.m * mc.kv);
+    return mc;
+}
+
+// Per-step environment of one voxel's update.
+template <typename T>
+struct UpdEnv {
+    T dt, gravity, l;
+    T z0;            // world z of the voxel's rest lower face minus half a voxel: origin_z + iz l
+    int floor_on;
+    T Fext[3];       // external force (FLAG_FORCED)
+    T Fc[3];         // contact force (FLAG_CAND)
+};
+
+// Branch taken by the floor and friction logic (recorded for the adjoint).
+enum : int { FR_NONE = 0, FR_HOLD = 1, FR_HALT_HOLD = 2, FR_HALT_SLIDE = 3, FR_SLIDE = 4 };
+
+// Everything after the bond sum for one voxel: external force, gravity,
+// ground damping, floor, contact, Coulomb friction (Eq. 36-38), then the
+// synchronous "double Euler" update (Eq. 27-30) with the orientation
+// advanced by the exact rotation w dt.  r is the voxel's state at t_n;
+// returns the state at t_n+1 in o and the new flags in *nf_out.
+template <typename T>
+VX_HD void update_core(const UpdEnv<T> &e, uint8_t fl, const MatConst<T> &mc, T eps, const VoxRaw<T> &r, T Fx,
+                       T Fy, T Fz, T Mx, T My, T Mz, VoxRaw<T> &o, uint8_t *nf_out, int *branch) {
+    // One exit with every output assigned from scalars: early returns or
+    // whole-struct copies of o make the compiler route it through private
+    // memory.
     T ux = r.ux, uy = r.uy, uz = r.uz;
     const T qw = r.qw, qx = r.qx, qy = r.qy, qz = r.qz;
     T px = r.px, py = r.py, pz = r.pz;
     T lx = r.lx, ly = r.ly, lz = r.lz;
+    T ow = qw, ox = qx, oy = qy, oz = qz;
+    int br = FR_NONE;
+    uint8_t nf = fl;
     if (fl & FLAG_FIXED) {
-        store_raw(o, st, c, ux, uy, uz, qw, qx, qy, qz, T(0), T(0), T(0), T(0), T(0), T(0));
-        stc(a.flags_out, c, fl);
-        return;
+        px = py = pz = T(0);
+        lx = ly = lz = T(0);
+    } else {
+        if (fl & FLAG_FORCED) { Fx += e.Fext[0]; Fy += e.Fext[1]; Fz += e.Fext[2]; }
+        Fz -= mc.m * e.gravity;
+        const T vx = px * mc.inv_m, vy = py * mc.inv_m, vz = pz * mc.inv_m;
+        const T wx = lx * mc.inv_I, wy = ly * mc.inv_I, wz = lz * mc.inv_I;
+        Fx -= vx * mc.cg; Fy -= vy * mc.cg; Fz -= vz * mc.cg;
+        Mx -= wx * mc.cgr; My -= wy * mc.cgr; Mz -= wz * mc.cgr;
+        T Fn = T(0);
+        if (e.floor_on) {
+            // s/2 - D_z with D_z = origin + (iz + 1/2) l + u_z; the half-voxel
+            // terms cancel exactly
+            const T pen = T(0.5) * e.l * eps - uz - e.z0;
+            if (pen > T(0)) {
+                Fn = mc.kv * pen - mc.cfloor * vz;
+                if (Fn < T(0)) Fn = T(0);
+                Fz += Fn;
+            }
+        }
+        if (fl & FLAG_CAND) { Fx += e.Fc[0]; Fy += e.Fc[1]; Fz += e.Fc[2]; }
+        if (e.floor_on) {
+            if (Fn > T(0)) {
+                const T Fl = dsqrt(Fx * Fx + Fy * Fy);
+                bool done = false;
+                if (nf & FLAG_STATIC) {
+                    if (Fl <= mc.mu_s * Fn) {
+                        Fx = T(0); Fy = T(0); px = T(0); py = T(0);
+                        done = true;
+                        br = FR_HOLD;
+                    } else {
+                        nf &= (uint8_t)~FLAG_STATIC;
+                    }
+                }
+                if (!done) {
+                    const T vl = dsqrt(vx * vx + vy * vy);
+                    if (vl <= mc.mu_d * Fn * e.dt * mc.inv_m) {
+                        px = T(0); py = T(0);
+                        nf |= FLAG_STATIC;
+                        if (Fl <= mc.mu_s * Fn) {
+                            Fx = T(0); Fy = T(0);
+                            br = FR_HALT_HOLD;
+                        } else {
+                            const T f = mc.mu_d * Fn / Fl;
+                            Fx -= f * Fx; Fy -= f * Fy;
+                            br = FR_HALT_SLIDE;
+                        }
+                    } else {
+                        const T f = mc.mu_d * Fn / vl;
+                        Fx -= f * vx; Fy -= f * vy;
+                        br = FR_SLIDE;
+                    }
+                }
+            } else {
+                nf &= (uint8_t)~FLAG_STATIC;
+            }
+        }
+        // integrate
+        const T dt = e.dt;
+        px += Fx * dt; py += Fy * dt; pz += Fz * dt;
+        const T nvx = px * mc.inv_m, nvy = py * mc.inv_m, nvz = pz * mc.inv_m;
+        ux += nvx * dt; uy += nvy * dt; uz += nvz * dt;
+        lx += Mx * dt; ly += My * dt; lz += Mz * dt;
+        const T rx = lx * mc.inv_I * dt, ry = ly * mc.inv_I * dt, rz = lz * mc.inv_I * dt;
+        const T a2 = rx * rx + ry * ry + rz * rz;
+        T dw, sk;
+        if (a2 < Series<T>::kExpA2) {
+            half_angle_series(a2, &dw, &sk);
+        } else {
+            const T ang = dsqrt(a2);
+            T sn, cs;
+            dsincos(T(0.5) * ang, &sn, &cs);
+            dw = cs;
+            sk = sn / ang;
+        }
+        const T dx = sk * rx, dy = sk * ry, dz = sk * rz;
+        // dq * q, then normalise
+        const T nw = dw * qw - dx * qx - dy * qy - dz * qz;
+        const T nx = dw * qx + dx * qw + dy * qz - dz * qy;
+        const T ny = dw * qy - dx * qz + dy * qw + dz * qx;
+        const T nz = dw * qz + dx * qy - dy * qx + dz * qw;
+        const T n2 = nw * nw + nx * nx + ny * ny + nz * nz;
+        const T dn = n2 - T(1);
+        T inv;
+        if (dn < Series<T>::kNormD && dn > -Series<T>::kNormD) {
+            inv = fma(dn, fma(dn, T(0.375), T(-0.5)), T(1));
+        } else {
+            inv = T(1) / dsqrt(n2);
+        }
+        ow = nw * inv; ox = nx * inv; oy = ny * inv; oz = nz * inv;
     }
+    o.ux = ux; o.uy = uy; o.uz = uz;
+    o.qw = ow; o.qx = ox; o.qy = oy; o.qz = oz;
+    o.px = px; o.py = py; o.pz = pz;
+    o.lx = lx; o.ly = ly; o.lz = lz;
+    *nf_out = nf;
+    *branch = br;
+}
+
+// Voxel update of cell c from its bond sums: gathers the per-voxel inputs
+// of update_core, writes the new state and flags, flags non-finite values
+// and tracks the largest squared speed in *vmax_local.
+template <typename T>
+__device__ __forceinline__ UpdEnv<T> upd_env(const StepArgs<T> &a, unsigned c, uint8_t fl) {
+    UpdEnv<T> e;
+    e.dt = a.dt; e.gravity = a.gravity; e.l = a.l; e.floor_on = a.floor_on;
+    const unsigned nxy = (unsigned)a.nx * (unsigned)a.ny;
+    e.z0 = a.origin_z + T((int)(c / nxy)) * a.l;
+    e.Fext[0] = e.Fext[1] = e.Fext[2] = T(0);
+    e.Fc[0] = e.Fc[1] = e.Fc[2] = T(0);
     if (fl & FLAG_FORCED) {
         int lo = 0, hi = a.n_forced - 1;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
             if ((unsigned)a.forced_cells[mid] < c) lo = mid + 1; else hi = mid;
         }
-        Fx += a.forced_F[3 * lo]; Fy += a.forced_F[3 * lo + 1]; Fz += a.forced_F[3 * lo + 2];
-    }
-    Fz -= mc.m * a.gravity;
-    const T vx = px * mc.inv_m, vy = py * mc.inv_m, vz = pz * mc.inv_m;
-    const T wx = lx * mc.inv_I, wy = ly * mc.inv_I, wz = lz * mc.inv_I;
-    Fx -= vx * mc.cg; Fy -= vy * mc.cg; Fz -= vz * mc.cg;
-    Mx -= wx * mc.cgr; My -= wy * mc.cgr; Mz -= wz * mc.cgr;
-    T Fn = T(0);
-    if (a.floor_on) {
-        const unsigned nxy = (unsigned)a.nx * (unsigned)a.ny;
-        const int iz = (int)(c / nxy);
-        // s/2 - D_z with D_z = origin + (iz + 1/2) l + u_z; the half-voxel
-        // terms cancel exactly
-        const T pen = T(0.5) * a.l * eps - uz - (a.origin_z + T(iz) * a.l);
-        if (pen > T(0)) {
-            Fn = mc.kv * pen - mc.cfloor * vz;
-            if (Fn < T(0)) Fn = T(0);
-            Fz += Fn;
-        }
+        e.Fext[0] = a.forced_F[3 * lo]; e.Fext[1] = a.forced_F[3 * lo + 1]; e.Fext[2] = a.forced_F[3 * lo + 2];
     }
     if (fl & FLAG_CAND) {
-        Fx += ldc(a.contact_F, c); Fy += ldc(a.contact_F + st, c); Fz += ldc(a.contact_F + 2 * st, c);
+        const long long st = a.stride;
+        e.Fc[0] = ldc(a.contact_F, c); e.Fc[1] = ldc(a.contact_F + st, c); e.Fc[2] = ldc(a.contact_F + 2 * st, c);
     }
-    // Coulomb friction against the floor (Eq. 36-38)
-    uint8_t nf = fl;
-    if (a.floor_on) {
-        if (Fn > T(0)) {
-            const T Fl = dsqrt(Fx * Fx + Fy * Fy);
-            bool done = false;
-            if (nf & FLAG_STATIC) {
-                if (Fl <= mc.mu_s * Fn) {
-                    Fx = T(0); Fy = T(0); px = T(0); py = T(0);
-                    done = true;
-                } else {
-                    nf &= (uint8_t)~FLAG_STATIC;
-                }
-            }
-            if (!done) {
-                const T vl = dsqrt(vx * vx + vy * vy);
-                if (vl <= mc.mu_d * Fn * a.dt * mc.inv_m) {
-                    px = T(0); py = T(0);
-                    nf |= FLAG_STATIC;
-                    if (Fl <= mc.mu_s * Fn) {
-                        Fx = T(0); Fy = T(0);
-                    } else {
-                        const T f = mc.mu_d * Fn / Fl;
-                        Fx -= f * Fx; Fy -= f * Fy;
-                    }
-                } else {
-                    const T f = mc.mu_d * Fn / vl;
-                    Fx -= f * vx; Fy -= f * vy;
-                }
-            }
-        } else {
-            nf &= (uint8_t)~FLAG_STATIC;
-        }
-    }
+    return e;
+}
+
+template <typename T>
+__device__ __forceinline__ void voxel_update(const StepArgs<T> &a, unsigned c, uint8_t fl,
+                                             const MatConst<T> &mc, T eps, const VoxRaw<T> &r, T Fx,
+                                             T Fy, T Fz, T Mx, T My, T Mz, T *vmax_local) {
+    const UpdEnv<T> e = upd_env(a, c, fl);
+    VoxRaw<T> o;
+    uint8_t nf;
+    int branch;
+    update_core(e, fl, mc, eps, r, Fx, Fy, Fz, Mx, My, Mz, o, &nf, &branch);
+    store_raw(a.s_out, a.stride, c, o.ux, o.uy, o.uz, o.qw, o.qx, o.qy, o.qz, o.px, o.py, o.pz, o.lx, o.ly, o.lz);
     stc(a.flags_out, c, nf);
-    // integrate
-    const T dt = a.dt;
-    px += Fx * dt; py += Fy * dt; pz += Fz * dt;
-    const T nvx = px * mc.inv_m, nvy = py * mc.inv_m, nvz = pz * mc.inv_m;
-    ux += nvx * dt; uy += nvy * dt; uz += nvz * dt;
-    lx += Mx * dt; ly += My * dt; lz += Mz * dt;
-    const T rx = lx * mc.inv_I * dt, ry = ly * mc.inv_I * dt, rz = lz * mc.inv_I * dt;
-    const T a2 = rx * rx + ry * ry + rz * rz;
-    T dw, sk;
-    if (a2 < Series<T>::kExpA2) {
-        half_angle_series(a2, &dw, &sk);
-    } else {
-        const T ang = dsqrt(a2);
-        T sn, cs;
-        dsincos(T(0.5) * ang, &sn, &cs);
-        dw = cs;
-        sk = sn / ang;
-    }
-    const T dx = sk * rx, dy = sk * ry, dz = sk * rz;
-    // dq * q, then normalise
-    T nw = dw * qw - dx * qx - dy * qy - dz * qz;
-    T nx = dw * qx + dx * qw + dy * qz - dz * qy;
-    T ny = dw * qy - dx * qz + dy * qw + dz * qx;
-    T nz = dw * qz + dx * qy - dy * qx + dz * qw;
-    const T n2 = nw * nw + nx * nx + ny * ny + nz * nz;
-    const T dn = n2 - T(1);
-    T inv;
-    if (dn < Series<T>::kNormD && dn > -Series<T>::kNormD) {
-        inv = fma(dn, fma(dn, T(0.375), T(-0.5)), T(1));
-    } else {
-        inv = T(1) / dsqrt(n2);
-    }
-    nw *= inv; nx *= inv; ny *= inv; nz *= inv;
-    store_raw(o, st, c, ux, uy, uz, nw, nx, ny, nz, px, py, pz, lx, ly, lz);
-    const bool ok = dfinite(ux) && dfinite(uy) && dfinite(uz) && dfinite(nw) && dfinite(nx) &&
-                    dfinite(ny) && dfinite(nz) && dfinite(px) && dfinite(py) && dfinite(pz) &&
-                    dfinite(lx) && dfinite(ly) && dfinite(lz);
+    if (fl & FLAG_FIXED) return;
+    const bool ok = dfinite(o.ux) && dfinite(o.uy) && dfinite(o.uz) && dfinite(o.qw) && dfinite(o.qx) &&
+                    dfinite(o.qy) && dfinite(o.qz) && dfinite(o.px) && dfinite(o.py) && dfinite(o.pz) &&
+                    dfinite(o.lx) && dfinite(o.ly) && dfinite(o.lz);
     if (!ok) atomicOr(a.err_flag, 1u);
+    const T nvx = o.px * mc.inv_m, nvy = o.py * mc.inv_m, nvz = o.pz * mc.inv_m;
     const T sp2 = nvx * nvx + nvy * nvy + nvz * nvz;
     if (sp2 > *vmax_local) *vmax_local = sp2;
 }

@@ -1,0 +1,229 @@
+// Host side of differentiable rollouts (parameter mode): the forward run
+// stores a checkpoint of the state every K steps; the reverse run walks the
+// segments backwards, recomputes each segment's states and bond sums from
+// its checkpoint with the forward kernels, then applies the reverse step
+// kernels from the last step of the segment to the first.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "vx_host.hpp"
+#include "vx_sim.hpp"
+
+using namespace vx;
+
+namespace {
+
+void grad_layout(const vx_sim *h, int64_t max_steps, int K, GradLayout &G) {
+    const uint64_t n = (uint64_t)h->ncell, ts = h->tsize;
+    const uint64_t sb = align_up(N_WORDS * n * ts), fb = align_up(n), fmb = align_up(6 * n * ts);
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) { uint64_t o = off; off = align_up(off + std::max<uint64_t>(bytes, 1)); return o; };
+    G.max_steps = max_steps;
+    G.K = K;
+    G.n_ck = (int)((max_steps + K - 1) / K);
+    G.ck_state = take(G.n_ck * sb);
+    G.ck_flags = take(G.n_ck * fb);
+    G.seg_state = take((uint64_t)K * sb);
+    G.seg_flags = take((uint64_t)K * fb);
+    G.fm = take((uint64_t)K * fmb);
+    G.lam[0] = take(sb);
+    G.lam[1] = take(sb);
+    G.gfm = take(6 * n * ts);
+    G.gloc = take(2 * n * ts);
+    G.rec = take(3ull * kAdjRecWords * n * ts);
+    G.gE = take(n * 8);
+    G.gphase = take(n * 8);
+    G.gamp = take(n * 8);
+    G.total = off;
+}
+
+uint64_t state_slot(const vx_sim *h) { return align_up((uint64_t)N_WORDS * h->ncell * h->tsize); }
+uint64_t flags_slot(const vx_sim *h) { return align_up((uint64_t)h->ncell); }
+uint64_t fm_slot(const vx_sim *h) { return align_up(6ull * h->ncell * h->tsize); }
+
+double voxel_mass_of(const vx_sim *h, long long c) {
+    return voxel_mass(h->pal[h->grid[c]], h->p.voxel_size);
+}
+
+template <typename T>
+int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const double *dL_dv, const double *dL_dw,
+                    double *g_E, double *g_phase, double *g_amp, double *g_u0, double *g_q0, double *g_v0,
+                    double *g_w0) {
+    const GradLayout &G = h->GL;
+    const long long n = h->ncell;
+    const double l = h->p.voxel_size;
+    char *gw = h->gws;
+    hipStream_t s = h->stream;
+    const uint64_t sb = state_slot(h), fb = flags_slot(h), fmb = fm_slot(h);
+    // adjoint of the final state, in the stored words (v = P / m, w = L / I)
+    std::vector<T> lam((size_t)N_WORDS * n, T(0));
+    for (long long c = 0; c < n; ++c) {
+        if (!h->grid[c]) continue;
+        const double m = voxel_mass_of(h, c), I = m * l * l / 6.0;
+        for (int k = 0; k < 3; ++k) {
+            if (dL_du) lam[(size_t)(W_UX + k) * n + c] = (T)dL_du[3 * c + k];
+            if (dL_dv) lam[(size_t)(W_PX + k) * n + c] = (T)(dL_dv[3 * c + k] / m);
+            if (dL_dw) lam[(size_t)(W_LX + k) * n + c] = (T)(dL_dw[3 * c + k] / I);
+        }
+        if (dL_dq)
+            for (int k = 0; k < 4; ++k) lam[(size_t)(W_QW + k) * n + c] = (T)dL_dq[4 * c + k];
+    }
+    HIP_OK(h, hipMemcpyAsync(gw + G.lam[0], lam.data(), lam.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    HIP_OK(h, hipMemsetAsync(gw + G.lam[1], 0, lam.size() * sizeof(T), s));
+    HIP_OK(h, hipMemsetAsync(gw + G.gE, 0, n * 8, s));
+    HIP_OK(h, hipMemsetAsync(gw + G.gphase, 0, n * 8, s));
+    HIP_OK(h, hipMemsetAsync(gw + G.gamp, 0, n * 8, s));
+    int li = 0;
+    const int64_t N = h->tape_n;
+    const int K = G.K;
+    const int nseg = (int)((N + K - 1) / K);
+    for (int j = nseg - 1; j >= 0; --j) {
+        const long long s0 = h->tape_step0 + (long long)j * K;
+        const int len = (int)std::min<int64_t>(K, N - (int64_t)j * K);
+        auto st_ptr = [&](int i) {
+            return (T *)(gw + (i == 0 ? G.ck_state + (uint64_t)j * sb : G.seg_state + (uint64_t)i * sb));
+        };
+        auto fl_ptr = [&](int i) {
+            return (uint8_t *)(gw + (i == 0 ? G.ck_flags + (uint64_t)j * fb : G.seg_flags + (uint64_t)i * fb));
+        };
+        // recompute the segment: states x_s0+1 .. x_s0+len-1 and the bond
+        // sums of every step (the last step's new state goes to the unused
+        // slot 0)
+        for (int i = 0; i < len; ++i) {
+            StepArgs<T> a = make_args<T>(h);
+            set_step_time(a, h, s0 + i);
+            a.s_in = st_ptr(i);
+            a.flags = fl_ptr(i);
+            a.s_out = i + 1 < len ? st_ptr(i + 1) : (T *)(gw + G.seg_state);
+            a.flags_out = i + 1 < len ? fl_ptr(i + 1) : (uint8_t *)(gw + G.seg_flags);
+            a.fm_out = (T *)(gw + G.fm + (uint64_t)i * fmb);
+            a.track_vmax = 0;
+            HIP_OK(h, launch_split_step<T>(a, s));
+        }
+        for (int i = len - 1; i >= 0; --i) {
+            StepArgs<T> a = make_args<T>(h);
+            set_step_time(a, h, s0 + i);
+            a.s_in = st_ptr(i);
+            a.flags = fl_ptr(i);
+            a.s_out = nullptr;
+            a.flags_out = nullptr;
+            AdjArgs<T> g;
+            g.fm = (const T *)(gw + G.fm + (uint64_t)i * fmb);
+            g.lam_in = (const T *)(gw + G.lam[li]);
+            g.lam_out = (T *)(gw + G.lam[1 - li]);
+            g.gfm = (T *)(gw + G.gfm);
+            g.gloc = (T *)(gw + G.gloc);
+            g.rec = (T *)(gw + G.rec);
+            g.g_E = (double *)(gw + G.gE);
+            g.g_phase = (double *)(gw + G.gphase);
+            g.g_amp = (double *)(gw + G.gamp);
+            HIP_OK(h, launch_adjoint_step<T>(a, g, s));
+            li = 1 - li;
+        }
+    }
+    HIP_OK(h, hipMemcpyAsync(lam.data(), gw + G.lam[li], lam.size() * sizeof(T), hipMemcpyDeviceToHost, s));
+    std::vector<double> gE(n), gp(n), ga(n);
+    HIP_OK(h, hipMemcpyAsync(gE.data(), gw + G.gE, n * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(h, hipMemcpyAsync(gp.data(), gw + G.gphase, n * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(h, hipMemcpyAsync(ga.data(), gw + G.gamp, n * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(h, hipStreamSynchronize(s));
+    Scalars sc;
+    HIP_OK(h, hipMemcpyAsync(&sc, h->ws + h->L.scalars, sizeof(sc), hipMemcpyDeviceToHost, s));
+    HIP_OK(h, hipStreamSynchronize(s));
+    if (sc.err_flag) return fail(h, VX_EUNSTABLE, "non-finite value in the voxel state");
+    for (long long c = 0; c < n; ++c) {
+        const bool f = h->grid[c] != 0;
+        if (g_E) g_E[c] = f ? gE[c] : 0.0;
+        if (g_phase) g_phase[c] = f ? gp[c] : 0.0;
+        if (g_amp) g_amp[c] = f ? ga[c] : 0.0;
+        const double m = f ? voxel_mass_of(h, c) : 0.0, I = m * l * l / 6.0;
+        for (int k = 0; k < 3; ++k) {
+            if (g_u0) g_u0[3 * c + k] = f ? (double)lam[(size_t)(W_UX + k) * n + c] : 0.0;
+            if (g_v0) g_v0[3 * c + k] = f ? (double)lam[(size_t)(W_PX + k) * n + c] * m : 0.0;
+            if (g_w0) g_w0[3 * c + k] = f ? (double)lam[(size_t)(W_LX + k) * n + c] * I : 0.0;
+        }
+        if (g_q0)
+            for (int k = 0; k < 4; ++k) g_q0[4 * c + k] = f ? (double)lam[(size_t)(W_QW + k) * n + c] : 0.0;
+    }
+    return VX_OK;
+}
+
+template <typename T>
+int checkpoint(vx_sim *h, int j) {
+    const uint64_t sb = state_slot(h), fb = flags_slot(h);
+    HIP_OK(h, hipMemcpyAsync(h->gws + h->GL.ck_state + (uint64_t)j * sb, h->ws + h->L.state[h->cur],
+                             (size_t)N_WORDS * h->ncell * sizeof(T), hipMemcpyDeviceToDevice, h->stream));
+    HIP_OK(h, hipMemcpyAsync(h->gws + h->GL.ck_flags + (uint64_t)j * fb, h->ws + h->L.flags[h->cur], h->ncell,
+                             hipMemcpyDeviceToDevice, h->stream));
+    return VX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vx_grad_workspace_bytes(vx_handle h, int64_t max_steps, int32_t K, uint64_t *bytes) {
+    if (!h || !bytes || max_steps < 1 || K < 1) return VX_EINVAL;
+    GradLayout G;
+    grad_layout(h, max_steps, std::min<int64_t>(K, max_steps), G);
+    *bytes = G.total;
+    return VX_OK;
+}
+
+int vx_grad_bind(vx_handle h, void *device_ptr, uint64_t bytes, int64_t max_steps, int32_t K) {
+    if (!h || max_steps < 1 || K < 1) return VX_EINVAL;
+    if (h->p.self_collision_on) return fail(h, VX_ESTATE, "differentiable rollouts need self-collision off");
+    if (!h->bound) return fail(h, VX_ESTATE, "vx_grad_bind before vx_bind_workspace");
+    GradLayout G;
+    grad_layout(h, max_steps, (int)std::min<int64_t>(K, max_steps), G);
+    if (!device_ptr || bytes < G.total) return fail(h, VX_EINVAL, "gradient workspace too small");
+    if (((uintptr_t)device_ptr) % kAlign) return fail(h, VX_EINVAL, "gradient workspace not 256-byte aligned");
+    h->gws = (char *)device_ptr;
+    h->GL = G;
+    h->tape_valid = false;
+    return VX_OK;
+}
+
+int vx_set_stiffness(vx_handle h, const double *E);
+
+int vx_grad_forward(vx_handle h, int64_t n) {
+    if (!h || n < 1) return VX_EINVAL;
+    if (!h->gws) return fail(h, VX_ESTATE, "vx_grad_forward before vx_grad_bind");
+    if (n > h->GL.max_steps) return fail(h, VX_EINVAL, "more steps than the gradient workspace was sized for");
+    if (!h->has_E) {
+        // parameter mode with the palette's moduli
+        std::vector<double> E(h->ncell, 0.0);
+        for (long long c = 0; c < h->ncell; ++c)
+            if (h->grid[c]) E[c] = h->pal[h->grid[c]].E;
+        const int r = vx_set_stiffness(h, E.data());
+        if (r) return r;
+    }
+    const long long step0 = h->step;
+    const int K = h->GL.K;
+    for (int64_t done = 0, j = 0; done < n; done += K, ++j) {
+        int r = h->precision == 64 ? checkpoint<double>(h, (int)j) : checkpoint<float>(h, (int)j);
+        if (r) return r;
+        r = vx_step(h, std::min<int64_t>(K, n - done));
+        if (r) return r;
+    }
+    h->tape_valid = true;
+    h->tape_n = n;
+    h->tape_step0 = step0;
+    return VX_OK;
+}
+
+int vx_grad_backward(vx_handle h, const double *dL_du, const double *dL_dq, const double *dL_dv, const double *dL_dw,
+                     double *g_E, double *g_phase, double *g_amp, double *g_u0, double *g_q0, double *g_v0,
+                     double *g_w0) {
+    if (!h) return VX_EINVAL;
+    if (!h->tape_valid || h->step != h->tape_step0 + h->tape_n)
+        return fail(h, VX_ESTATE, "no recorded rollout ends at the current state (vx_grad_forward first)");
+    return h->precision == 64
+               ? grad_backward_t<double>(h, dL_du, dL_dq, dL_dv, dL_dw, g_E, g_phase, g_amp, g_u0, g_q0, g_v0, g_w0)
+               : grad_backward_t<float>(h, dL_du, dL_dq, dL_dv, dL_dw, g_E, g_phase, g_amp, g_u0, g_q0, g_v0, g_w0);
+}
+
+}  // extern "C"

@@ -35,6 +35,7 @@ void build_tables(const vx_material *pal, int n_mat, const vx_params &p, std::ve
         c.cgr = (T)(2.0 * p.zeta_slow * std::sqrt(I * kphi));
         c.cfloor = (T)(2.0 * p.zeta_col * std::sqrt(m * kv));
         c.kv = (T)kv; c.cte = (T)M.cte; c.mu_s = (T)M.mu_s; c.mu_d = (T)M.mu_d; c.E = (T)M.E;
+        c.gfac = (T)(1.0 / (2.0 * (1.0 + M.nu)));
     }
     pc.assign((size_t)n_mat * n_mat, PairConst<T>{});
     for (int i = 1; i < n_mat; ++i)

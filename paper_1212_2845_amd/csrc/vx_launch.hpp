@@ -9,6 +9,26 @@ namespace vx {
 template <typename T>
 hipError_t launch_split_step(const StepArgs<T> &a, hipStream_t s);
 
+// Reverse of one split step (parameter mode, no self-collision).  a holds
+// the forward step's arguments at t_n (s_in = x_n, flags at t_n, E_cell);
+// the adjoint buffers are laid out like the state (word k of cell c at
+// k * stride + c).
+constexpr int kAdjRecWords = 30;   // per-bond record: both ends' 14 adjoints, then the two moduli
+
+template <typename T>
+struct AdjArgs {
+    const T *fm;            // bond force and moment sums at x_n, 6 words
+    const T *lam_in;        // adjoint of x_n+1, 13 words
+    T *lam_out;             // adjoint of x_n, 13 words
+    T *gfm;                 // adjoint of the bond sums, 6 words
+    T *gloc;                // update's adjoints of the strain and of the modulus, 2 words
+    T *rec;                 // per-bond records, 3 axes x 30 words
+    double *g_E, *g_phase, *g_amp;   // accumulated over the reverse steps
+};
+
+template <typename T>
+hipError_t launch_adjoint_step(const StepArgs<T> &a, const AdjArgs<T> &g, hipStream_t s);
+
 // Fused path: one LDS-tiled kernel per step.  cfg.shape indexes
 // kFusedShapes (tile TX x TY); cfg.zc is the z chunk per workgroup (0 picks
 // fused_default_zc).

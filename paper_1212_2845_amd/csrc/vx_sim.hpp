@@ -1,0 +1,199 @@
+// Internal state of one single-lattice handle and the helpers shared by the
+// host files that implement its C ABI (plain stepping and differentiable
+// rollouts).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/voxsim.h"
+#include "vx_launch.hpp"
+#include "vx_types.hpp"
+
+namespace vx {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr uint64_t kAlign = 256;
+
+inline uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    uint64_t state[2], mat, flags[2], mats, pairs, bonds, act_amp, act_phase, forced_cells, forced_F;
+    uint64_t contact_F, surf_cells, cand, cand_n, keys, sorted, bstart, bfill, scalars, scan_tmp;
+    uint64_t E_cell;
+    uint64_t total;
+};
+
+// Carve-out of the caller's gradient workspace for a rollout of up to
+// max_steps steps with a checkpoint every K steps.
+struct GradLayout {
+    int64_t max_steps;
+    int K;
+    int n_ck;                    // checkpoints: states at steps 0, K, 2K, ...
+    uint64_t ck_state, ck_flags; // n_ck x (13 words x ncell), n_ck x ncell bytes
+    uint64_t seg_state, seg_flags; // K slots: states of one segment (slot 0 unused)
+    uint64_t fm;                 // K slots x 6 words x ncell: bond sums of each segment step
+    uint64_t lam[2];             // adjoint state, 13 words x ncell each
+    uint64_t gfm;                // adjoint of the bond sums, 6 words x ncell
+    uint64_t gloc;               // per-voxel adjoints of strain and modulus from the update, 2 x ncell
+    uint64_t rec;                // per-bond adjoint records, 3 axes x 30 words x ncell
+    uint64_t gE, gphase, gamp;   // FP64 accumulators, ncell each
+    uint64_t total;
+};
+
+// Small device-side scalars, one 256-byte block.
+struct Scalars {
+    unsigned err_flag;
+    unsigned overflow;
+    unsigned rebuild_flag;
+    unsigned pad0;
+    unsigned long long vmax_bits;
+    double macc;
+    unsigned long long pair_count;
+    unsigned long long rebuilds;
+};
+
+
+}  // namespace vx
+
+using namespace vx;
+
+struct vx_sim {
+    int nx = 0, ny = 0, nz = 0;
+    long long ncell = 0;
+    vx_params p{};
+    int precision = 64;
+    size_t tsize = 8;
+    hipStream_t stream = nullptr;
+    int n_mat = 0;
+    std::vector<vx_material> pal;
+    std::vector<uint8_t> grid, flags;
+    std::vector<double> amp, phase;      // per cell; valid where FLAG_ACT
+    bool has_act = false;
+    std::vector<double> force;           // ncell x 3 (host copy)
+    std::vector<int> forced_cells;
+    std::vector<double> forced_F;
+    int forced_cap = 0;
+    std::vector<int> surf_cells;
+    long long nvox = 0;
+    double dt = 0.0;
+    long long step = 0;
+    int kernel_kind = 0;
+    int cand_cap = 32;
+    int table_size = 1;
+    size_t scan_tmp_bytes = 0;
+    double cmax = 0.0;
+    // initial state in double, 13 x ncell (used until bind)
+    std::vector<double> state0;
+    // device
+    bool bound = false;
+    char *ws = nullptr;
+    Layout L{};
+    int cur = 0;                          // which state / flags buffer holds step n
+    bool flags_live = false;              // device flags hold dynamic bits
+    int fused_shape = -1;                 // tile shape of the fused kernel (-1: heuristic)
+    int fused_zc = 0;                     // z chunk of the fused kernel (0: heuristic)
+    // parameter mode: per-cell elastic modulus (split kernels)
+    bool has_E = false;
+    std::vector<double> E_cell;
+    double wmax = 0.0;                    // sqrt(k_b / m_min) the timestep was chosen for
+    // differentiable rollouts
+    char *gws = nullptr;
+    vx::GradLayout GL{};
+    bool tape_valid = false;              // a recorded rollout ends at the current state
+    int64_t tape_n = 0;
+    long long tape_step0 = 0;
+    std::string err;
+};
+
+inline int fail(vx_sim *h, int code, const std::string &msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+#define HIP_OK(h, call)                                                        \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess)                                                  \
+            return fail(h, VX_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Time-dependent fields of the step arguments at step index n (t_n = n dt).
+template <typename T>
+inline void set_step_time(vx::StepArgs<T> &a, const vx_sim *h, long long n) {
+    const double tn = (double)n * h->dt;
+    const double wt = 2.0 * vx::kPi * h->p.temp_freq * tn;
+    a.wt = wt;
+    a.wt_red = (T)std::fmod(wt, 2.0 * vx::kPi);
+    a.dT_global = (T)(h->p.temp_amp * std::sin(wt + h->p.temp_phase));
+}
+
+template <typename T>
+inline vx::StepArgs<T> make_args(vx_sim *h) {
+    StepArgs<T> a{};
+    char *ws = h->ws;
+    a.s_in = (const T *)(ws + h->L.state[h->cur]);
+    a.s_out = (T *)(ws + h->L.state[1 - h->cur]);
+    a.stride = h->ncell;
+    a.mat = (const uint8_t *)(ws + h->L.mat);
+    a.flags = (const uint8_t *)(ws + h->L.flags[h->cur]);
+    a.flags_out = (uint8_t *)(ws + h->L.flags[1 - h->cur]);
+    a.mats = (const MatConst<T> *)(ws + h->L.mats);
+    a.pairs = (const PairConst<T> *)(ws + h->L.pairs);
+    a.n_mat = h->n_mat;
+    a.nx = h->nx; a.ny = h->ny; a.nz = h->nz;
+    a.l = (T)h->p.voxel_size;
+    a.dt = (T)h->dt;
+    a.gravity = (T)h->p.gravity;
+    a.origin_z = (T)h->p.origin[2];
+    for (int k = 0; k < 3; ++k) a.origin[k] = h->p.origin[k];
+    set_step_time(a, h, h->step);
+    a.act_amp = (const T *)(ws + h->L.act_amp);
+    a.act_phase = (const T *)(ws + h->L.act_phase);
+    a.forced_cells = (const int *)(ws + h->L.forced_cells);
+    a.forced_F = (const T *)(ws + h->L.forced_F);
+    a.n_forced = (int)h->forced_cells.size();
+    a.floor_on = h->p.floor_on;
+    a.track_vmax = h->p.self_collision_on;
+    a.contact_F = (const T *)(ws + h->L.contact_F);
+    a.bonds = (T *)(ws + h->L.bonds);
+    a.E_cell = h->has_E ? (const T *)(ws + h->L.E_cell) : nullptr;
+    a.fm_out = nullptr;
+    a.zeta_bond = (T)h->p.zeta_bond;
+    a.zeta_slow = (T)h->p.zeta_slow;
+    a.zeta_col = (T)h->p.zeta_col;
+    Scalars *sc = (Scalars *)(ws + h->L.scalars);
+    a.err_flag = &sc->err_flag;
+    a.vmax_bits = &sc->vmax_bits;
+    return a;
+}
+
+inline vx::CollideArgs make_collide(vx_sim *h) {
+    CollideArgs c{};
+    char *ws = h->ws;
+    c.surf_cells = (const int *)(ws + h->L.surf_cells);
+    c.n_surf = (int)h->surf_cells.size();
+    c.cap = h->cand_cap;
+    c.cand = (int *)(ws + h->L.cand);
+    c.cand_n = (int *)(ws + h->L.cand_n);
+    Scalars *sc = (Scalars *)(ws + h->L.scalars);
+    c.overflow = &sc->overflow;
+    c.rebuild_flag = &sc->rebuild_flag;
+    c.macc = &sc->macc;
+    c.vmax_bits = &sc->vmax_bits;
+    c.cell_keys = (int *)(ws + h->L.keys);
+    c.sorted_idx = (int *)(ws + h->L.sorted);
+    c.bucket_start = (int *)(ws + h->L.bstart);
+    c.bucket_fill = (int *)(ws + h->L.bfill);
+    c.table_size = h->table_size;
+    c.pair_count = &sc->pair_count;
+    c.horizon = 2.0 * h->p.voxel_size;
+    c.threshold = 2.0 * h->p.voxel_size - h->cmax;
+    c.scan_tmp = (void *)(ws + h->L.scan_tmp);
+    c.scan_tmp_bytes = h->scan_tmp_bytes;
+    c.rebuild_counter = &sc->rebuilds;
+    return c;
+}

@@ -3,7 +3,7 @@
 // gather kernel sums each voxel's at most six bonds in a fixed order and
 // integrates.  Simple and atomic-free; the fused kernel computes the same
 // per-bond and per-voxel arithmetic without the scratch round trip.
-#include "vx_device.hpp"
+#include "vx_adjoint.hpp"
 #include "vx_launch.hpp"
 
 namespace vx {
@@ -35,7 +35,11 @@ __global__ void __launch_bounds__(256) k_bonds(StepArgs<T> a) {
     const VoxKin<T> ka = load_kin(a.s_in, a.stride, (unsigned)c, A, ea);
     const VoxKin<T> kb = load_kin(a.s_in, a.stride, (unsigned)cn, B, eb);
     const Rot<T> R = rot_of(ka.qw, ka.qx, ka.qy, ka.qz);
-    const BondOut<T> o = bond_eval<T, AX>(ka, R, kb, bond_k(a.pairs[ma * a.n_mat + mb]), lat_consts(a.l));
+    const LatK<T> C = lat_consts(a.l);
+    const BondK<T> K = a.E_cell ? bond_k_from_E(a.E_cell[c], a.E_cell[cn], A.gfac, B.gfac, A.m < B.m ? A.m : B.m,
+                                                a.zeta_bond, C)
+                                : bond_k(a.pairs[ma * a.n_mat + mb]);
+    const BondOut<T> o = bond_eval<T, AX>(ka, R, kb, K, C);
     T *b = a.bonds + (long long)AX * 9 * a.stride;
     const long long st = a.stride;
     b[0 * st + c] = o.f2x; b[1 * st + c] = o.f2y; b[2 * st + c] = o.f2z;
@@ -71,9 +75,14 @@ __global__ void __launch_bounds__(256) k_gather(StepArgs<T> a) {
                     Mx += b[3 * st + c]; My += b[4 * st + c]; Mz += b[5 * st + c];
                 }
             }
-            const MatConst<T> mc = a.mats[m];
+            MatConst<T> mc = a.mats[m];
+            if (a.E_cell) mc = mat_with_E(mc, a.E_cell[c], a.l, a.zeta_slow, a.zeta_col);
             const uint8_t fl = a.flags[c];
             const T eps = voxel_strain(a, (unsigned)c, fl, mc.cte);
+            if (a.fm_out) {
+                a.fm_out[0 * st + c] = Fx; a.fm_out[1 * st + c] = Fy; a.fm_out[2 * st + c] = Fz;
+                a.fm_out[3 * st + c] = Mx; a.fm_out[4 * st + c] = My; a.fm_out[5 * st + c] = Mz;
+            }
             const VoxRaw<T> r = load_raw(a.s_in, st, (unsigned)c);
             voxel_update(a, (unsigned)c, fl, mc, eps, r, Fx, Fy, Fz, Mx, My, Mz, &vmax);
         }

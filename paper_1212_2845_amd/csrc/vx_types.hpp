@@ -37,7 +37,8 @@ struct MatConst {
     T kv;              // voxel stiffness E l (floor penalty)
     T cte, mu_s, mu_d;
     T E;               // elastic modulus (contact stiffness)
-    T pad[4];
+    T gfac;            // 1 / (2 (1 + nu)): shear modulus per unit E
+    T pad[3];
 };
 
 // Per-material-pair beam constants (Eq. 8-12) and bond damping (Eq. 34-35).
@@ -82,6 +83,9 @@ struct StepArgs {
     T *bonds;                  // split path: 3 axes x 9 words x ncell
     unsigned *err_flag;
     unsigned long long *vmax_bits;
+    const T *E_cell;           // per-cell elastic modulus (parameter mode), or null
+    T *fm_out;                 // split gather: per-voxel bond force and moment sums (6 x ncell), or null
+    T zeta_bond, zeta_slow, zeta_col;
 };
 
 }  // namespace vx

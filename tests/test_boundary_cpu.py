@@ -171,3 +171,77 @@ def test_set_forces_rejects_non_finite():
     F = np.zeros((2, 3)); F[1, 0] = np.nan
     with pytest.raises(vx.VoxsimError):
         s.set_forces(F)
+
+
+# --- parameter mode and differentiable rollouts (host-side checks) ----------
+
+def _grad_obj():
+    w = workloads.grad_object(seed=3, scenario="free")
+    s = vx.from_workload(w, precision=64)
+    g = w["grid"].reshape(-1)
+    E = np.array([w["materials"][m]["E"] if m else 0.0 for m in g])
+    return w, s, E
+
+
+def test_set_stiffness_validates_moduli():
+    w, s, E = _grad_obj()
+    s.set_stiffness(E)           # the palette's own moduli
+    s.set_stiffness(None)
+    for bad in (0.0, -1.0, np.nan, np.inf):
+        E2 = E.copy(); E2[w["block"][5]] = bad
+        with pytest.raises(vx.VoxsimError) as e:
+            s.set_stiffness(E2)
+        assert e.value.code == vx.VX_EINVAL
+
+
+def test_set_stiffness_rejects_moduli_above_the_timestep_bound():
+    """The timestep is fixed at create from the stiffest bonded pair (here
+    the 4 MPa anchor); a block pair stiffer than that would be unstable."""
+    w, s, E = _grad_obj()
+    E2 = E.copy(); E2[w["block"]] = 3.9e6
+    s.set_stiffness(E2)
+    E2[w["block"]] = 4.2e6
+    with pytest.raises(vx.VoxsimError) as e:
+        s.set_stiffness(E2)
+    assert e.value.code == vx.VX_EINVAL
+
+
+def test_grad_calls_need_their_state():
+    w, s, E = _grad_obj()
+    L = vx.lib()
+    # gradient workspace before the main one
+    assert L.vx_grad_bind(s.h, None, 0, 10, 2) == vx.VX_ESTATE
+    # forward without a gradient workspace, backward without a recorded run
+    assert L.vx_grad_forward(s.h, 5) == vx.VX_ESTATE
+    assert L.vx_grad_backward(s.h, *([None] * 11)) == vx.VX_ESTATE
+    assert L.vx_grad_forward(s.h, 0) == vx.VX_EINVAL
+
+
+def test_grad_workspace_size_grows_with_checkpoints_and_segment():
+    w, s, E = _grad_obj()
+    L = vx.lib()
+    def nbytes(steps, K):
+        n = C.c_uint64()
+        assert L.vx_grad_workspace_bytes(s.h, steps, K, C.byref(n)) == vx.VX_OK
+        return n.value
+    ncell = w["grid"].size
+    # per cell: checkpoints and segment slots of 13 FP64 words + 1 flag byte,
+    # 6-word bond sums per segment slot, 2 x 13 adjoint words, 6 + 2 words,
+    # 90 record words, 3 FP64 accumulators
+    per_cell = lambda nck, K: (nck + K) * (13 * 8 + 1) + K * 48 + 26 * 8 + 8 * 8 + 90 * 8 + 24
+    for steps, K in ((100, 10), (100, 7), (5000, 100)):
+        nck = -(-steps // K)
+        assert nbytes(steps, K) >= per_cell(nck, K) * ncell
+        assert nbytes(steps, K) <= per_cell(nck, K) * ncell + 256 * (2 * nck + 3 * K + 20)
+    assert nbytes(100, 200) == nbytes(100, 100)
+    assert L.vx_grad_workspace_bytes(s.h, 0, 1, C.byref(C.c_uint64())) == vx.VX_EINVAL
+    assert L.vx_grad_workspace_bytes(s.h, 10, 0, C.byref(C.c_uint64())) == vx.VX_EINVAL
+
+
+def test_grad_bind_rejects_self_collision():
+    g = np.ones((3, 3, 3), np.uint8)
+    rc, h = _create(g, [workloads.EMPTY, M1], 64, **workloads._base_params(self_collision_on=1))
+    assert rc == vx.VX_OK
+    assert vx.lib().vx_grad_bind(h, None, 0, 10, 2) == vx.VX_ESTATE
+    assert b"self-collision" in vx.lib().vx_last_error(h)
+    vx.lib().vx_destroy(h)

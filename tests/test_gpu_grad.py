@@ -1,0 +1,217 @@
+"""Reverse (adjoint) run of the step on the GPU against central differences
+of the FP64 oracle.
+
+Expected values come from tests/gradcheck.py: the oracle run with one
+modulus or phase perturbed up and down.  Objects are 4^3 blocks in which
+every voxel has its own palette entry (workloads.grad_object), in three
+regimes: free flight with fixed and forced voxels and ground damping,
+sliding on the floor, and resting on the floor (static friction).  The
+GPU runs in parameter mode (per-voxel moduli through vx_set_stiffness) with
+checkpoint segments that do not divide the step count.
+"""
+import numpy as np
+import pytest
+
+import paper_1212_2845_amd as vx
+import workloads
+from gradcheck import fd_direction, fd_modulus, fd_phase, loss_weights, oracle_loss
+from parity import build_oracle, compare
+
+pytestmark = pytest.mark.gpu
+
+SCENARIOS = ["free", "slide", "rest"]
+
+
+def announce(msg):
+    print("[case] " + msg, flush=True)
+
+
+def gpu_sim(w, precision=64):
+    s = vx.from_workload(w, precision=precision)
+    E = np.zeros(w["grid"].size)
+    g = w["grid"].reshape(-1)
+    for c in range(E.size):
+        if g[c]:
+            E[c] = w["materials"][g[c]]["E"]
+    s.set_stiffness(E)
+    return s
+
+
+def gpu_grad(w, wu, wv, precision=64, K=16):
+    s = gpu_sim(w, precision)
+    s.grad_bind(w["steps"], K)
+    s.grad_forward(w["steps"])
+    g = s.grad_backward(dL_du=wu, dL_dv=wv)
+    st = s.read_state()
+    return g, float((wu * st["u"]).sum() + (wv * st["v"]).sum())
+
+
+def norm_err(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("scenario", SCENARIOS)
+def test_parameter_mode_forward_matches_oracle(scenario):
+    """Per-voxel moduli through vx_set_stiffness give the oracle's trajectory
+    of the same moduli as palette entries."""
+    w = workloads.grad_object(seed=7, scenario=scenario)
+    announce("parameter-mode forward %s" % scenario)
+    s = gpu_sim(w)
+    o = build_oracle(w)
+    assert abs(s.dt / o.dt - 1) < 1e-15
+    s.step(w["steps"])
+    assert o.step(w["steps"]) == 0
+    e = compare(s.read_state(), o.read_state(), w["grid"].reshape(-1) > 0)
+    assert max(e["u"], e["v"], e["w"]) < 1e-10 and e["q"] < 1e-12, e
+
+
+@pytest.mark.parametrize("scenario", SCENARIOS)
+def test_gradient_matches_oracle_fd_every_coordinate(scenario):
+    """dL/dE and dL/dphase of every block voxel vs central differences of
+    the oracle (h = 1e-4), FP64; error over the largest gradient entry."""
+    w = workloads.grad_object(seed=11, scenario=scenario)
+    wu, wv = loss_weights(w, seed=12)
+    announce("fd every coordinate %s" % scenario)
+    g, L = gpu_grad(w, wu, wv)
+    assert abs(L / oracle_loss(w, wu, wv) - 1) < 1e-10
+    b = w["block"]
+    fdE = np.array([fd_modulus(w, wu, wv, k) for k in range(b.size)])
+    fdP = np.array([fd_phase(w, wu, wv, c) for c in b])
+    eE, eP = norm_err(g["E"][b], fdE), norm_err(g["phase"][b], fdP)
+    print("[grad] %s E err %.3e phase err %.3e" % (scenario, eE, eP), flush=True)
+    assert eE < 1e-4 and eP < 1e-4, (eE, eP)
+
+
+@pytest.mark.parametrize("scenario", SCENARIOS)
+def test_gradient_matches_oracle_fd_directions(scenario):
+    """Directional derivatives along 8 random joint directions in (relative
+    modulus, phase), normalised by |g| |d|.  Step h = 1e-5: perturbing all
+    128 parameters at once by 1e-4 can move a resting voxel across the
+    static-friction threshold inside the difference interval (a kink of
+    the trajectory map), which 1e-5 avoids on these seeds."""
+    w = workloads.grad_object(seed=21, scenario=scenario)
+    wu, wv = loss_weights(w, seed=22)
+    announce("fd directions %s" % scenario)
+    g, _ = gpu_grad(w, wu, wv, K=33)
+    b = w["block"]
+    rng = np.random.Generator(np.random.PCG64(23))
+    for i in range(8):
+        dE = rng.normal(size=b.size)
+        dp = np.zeros(w["grid"].size); dp[b] = rng.normal(size=b.size)
+        gvec = np.concatenate([g["E"][b] * w["E_block"], g["phase"][b]])
+        dvec = np.concatenate([dE, dp[b]])
+        an = float(gvec @ dvec)
+        fd = fd_direction(w, wu, wv, dE, dp, h=1e-5)
+        err = abs(an - fd) / (np.linalg.norm(gvec) * np.linalg.norm(dvec))
+        assert err < 1e-5, (i, an, fd, err)
+
+
+def test_gradient_of_initial_state_matches_oracle_fd():
+    """dL/d(initial velocity) of a few voxels vs central differences."""
+    w = workloads.grad_object(seed=31, scenario="free")
+    wu, wv = loss_weights(w, seed=32)
+    announce("initial-state gradient")
+    g, _ = gpu_grad(w, wu, wv)
+    b = w["block"]
+    rng = np.random.Generator(np.random.PCG64(33))
+    scale = np.abs(g["v0"][b]).max()
+    for c in rng.choice(b, 6, replace=False):
+        for k in range(3):
+            h = 1e-6
+            vp = w["velocity"].copy(); vp[c, k] += h
+            vm = w["velocity"].copy(); vm[c, k] -= h
+            wp = dict(w, velocity=vp); wm = dict(w, velocity=vm)
+            fd = (oracle_loss(wp, wu, wv) - oracle_loss(wm, wu, wv)) / (2 * h)
+            if w["fixed"][c]:
+                continue
+            assert abs(g["v0"][c, k] - fd) < 1e-6 * scale, (c, k, g["v0"][c, k], fd)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_checkpoint_interval_does_not_change_gradients(precision):
+    """The reverse run recomputes each segment with the forward kernels, so
+    any checkpoint interval gives bitwise the same gradients."""
+    w = workloads.grad_object(seed=41, scenario="slide", steps=60)
+    wu, wv = loss_weights(w, seed=42)
+    announce("checkpoint interval p=%d" % precision)
+    ref, _ = gpu_grad(w, wu, wv, precision, K=60)
+    for K in (1, 7, 100):
+        g, _ = gpu_grad(w, wu, wv, precision, K=K)
+        for k in ("E", "phase", "u0", "v0"):
+            assert np.array_equal(g[k], ref[k]), (K, k)
+
+
+def test_fp32_gradient_close_to_fp64():
+    w = workloads.grad_object(seed=51, scenario="slide")
+    wu, wv = loss_weights(w, seed=52)
+    announce("fp32 vs fp64 gradient")
+    g64, _ = gpu_grad(w, wu, wv, 64)
+    g32, _ = gpu_grad(w, wu, wv, 32)
+    b = w["block"]
+    eE, eP = norm_err(g32["E"][b], g64["E"][b]), norm_err(g32["phase"][b], g64["phase"][b])
+    print("[grad] fp32 vs fp64 E %.3e phase %.3e" % (eE, eP), flush=True)
+    assert eE < 1e-3 and eP < 1e-3, (eE, eP)
+
+
+def test_rollout_autograd_function():
+    """torch.autograd through the library's reverse run."""
+    import torch
+    w = workloads.grad_object(seed=61, scenario="free")
+    wu, wv = loss_weights(w, seed=62)
+    announce("autograd rollout")
+    s = gpu_sim(w)
+    s.grad_bind(w["steps"], 16)
+    E0 = s  # keep the Sim alive
+    g = w["grid"].reshape(-1)
+    E = torch.tensor([w["materials"][g[c]]["E"] if g[c] else 0.0 for c in range(g.size)],
+                     dtype=torch.float64, requires_grad=True)
+    ph = torch.tensor(w["phase"], dtype=torch.float64, requires_grad=True)
+    u, v = vx.rollout(s, E, ph, w["amp"], w["steps"])
+    L = (torch.from_numpy(wu) * u).sum() + (torch.from_numpy(wv) * v).sum()
+    L.backward()
+    ref, _ = gpu_grad(w, wu, wv)
+    b = w["block"]
+    assert np.allclose(E.grad.numpy()[b], ref["E"][b], rtol=1e-12, atol=0)
+    assert np.allclose(ph.grad.numpy()[b], ref["phase"][b], rtol=1e-12, atol=0)
+    del E0
+
+
+def test_design_lattice_gradient_full_size():
+    """The 64 x 20^3 design lattice (5000 steps, FP32, checkpoint every 100
+    steps, the bench's configuration), loss = mean x displacement.  The
+    blocks share no bond, so each block's gradients must equal those of the
+    same block run alone (same per-voxel arithmetic, so bitwise); the small
+    runs are the regime the oracle comparisons above cover.  Central
+    differences are no check at this size: with half a million voxels on
+    a floor, some voxel always sits at the static-friction threshold, where
+    the step zeroes its lateral momentum, so the loss jumps inside any
+    difference interval."""
+    w = workloads.design_lattice()
+    n = w["steps"]
+    announce("design lattice full size")
+    filled = w["grid"].reshape(-1) > 0
+    N = int(filled.sum())
+    wu = np.zeros((w["grid"].size, 3)); wu[filled, 0] = 1.0 / N
+    s = vx.from_workload(w, precision=32)
+    s.set_stiffness(w["E"])
+    s.grad_bind(n, 100)
+    s.grad_forward(n)
+    g = s.grad_backward(dL_du=wu)
+    del s
+    assert np.isfinite(g["E"]).all() and np.isfinite(g["phase"]).all()
+    assert np.abs(g["E"][filled]).max() > 0 and np.abs(g["phase"][filled]).max() > 0
+    nz, ny, nx = w["grid"].shape
+    size, pitch = 20, 21
+    for (i, j) in ((0, 0), (3, 5), (7, 7)):
+        sl = (slice(None), slice(j * pitch, j * pitch + size), slice(i * pitch, i * pitch + size))
+        cells = np.arange(w["grid"].size).reshape(w["grid"].shape)[sl].reshape(-1)
+        wb = workloads._workload(w["grid"][sl], w["materials"], w["params"], n, amp=w["amp"][cells],
+                                 phase=w["phase"][cells])
+        sb = vx.from_workload(wb, precision=32)
+        sb.set_stiffness(w["E"][cells])
+        sb.grad_bind(n, 100)
+        sb.grad_forward(n)
+        gb = sb.grad_backward(dL_du=wu[cells])
+        for k in ("E", "phase", "amp"):
+            assert np.array_equal(gb[k], g[k][cells]), (i, j, k)
+        assert np.array_equal(gb["u0"], g["u0"][cells]) and np.array_equal(gb["v0"], g["v0"][cells])

@@ -525,3 +525,57 @@ def test_torsion_mode_frequency():
     period = 2 * half_periods.mean() * dt
     assert len(half_periods) > 10
     assert abs(period / (2 * math.pi / wd) - 1.0) < 1e-3
+
+
+# --- pins of the finite-difference gradient harness (expected values of the
+# adjoint tests) ------------------------------------------------------------
+
+def _axial_pair(E1, E2, F, amp=None, phase=None, freq=0.0):
+    """Two voxels along x, voxel 1 fixed, constant force F on voxel 2, heavy
+    bond damping; relaxed to the static state."""
+    grid = np.array([[[1, 2]]], np.uint8)
+    mats = [workloads.EMPTY, workloads._mat(E1, cte=0.01), workloads._mat(E2, cte=0.01)]
+    params = workloads._base_params(zeta_bond=0.5, temp_freq=freq)
+    o = oracle.Sim(grid, mats, **params)
+    o.set_fixed(np.array([1, 0], np.uint8))
+    f = np.zeros((2, 3)); f[1, 0] = F
+    o.set_forces(f)
+    if amp is not None:
+        o.set_actuation(amp, phase)
+    return o
+
+
+def test_fd_harness_modulus_derivative_of_axial_compliance():
+    """Static stretch of a bonded pair: X2 = F / (E_c l) with E_c the
+    composite modulus (Eq. 1, 8), so d u_x2 / d E2 = -F / (l E_c^2) *
+    2 E1^2 / (E1 + E2)^2.  Central differences of the relaxed oracle must
+    reproduce it."""
+    E1, E2, F, l, h = 1e6, 2.5e6, 1e-5, 1e-3, 1e-4
+    def ux(e2):
+        o = _axial_pair(E1, e2, F)
+        assert o.step(3000) == 0
+        return o.read_state()["u"][1, 0]
+    fd = (ux(E2 * (1 + h)) - ux(E2 * (1 - h))) / (2 * h * E2)
+    Ec = 2 * E1 * E2 / (E1 + E2)
+    exact = -F / (l * Ec ** 2) * 2 * E1 ** 2 / (E1 + E2) ** 2
+    assert abs(fd / exact - 1) < 1e-6, (fd, exact)
+
+
+def test_fd_harness_phase_derivative_of_thermal_stretch():
+    """Quasi-static thermal stretch of a pair with per-voxel signals
+    (Eq. 39-40): the bond's rest length is l (1 + (eps1 + eps2) / 2), so the
+    free end sits at u_x2 = l (eps1 + eps2) / 2 and d u_x2 / d phase2 =
+    l cte A cos(w t + phase2) / 2 at the signal's time.  A 0.5 Hz signal
+    moves negligibly over the run, so the relaxed state tracks it."""
+    l, A, cte, h = 1e-3, 20.0, 0.01, 1e-4
+    amp = np.array([A, A]); ph0 = np.array([0.3, 1.1])
+    def ux(p2):
+        o = _axial_pair(1e6, 1e6, 0.0, amp, np.array([ph0[0], p2]), freq=0.5)
+        assert o.step(3000) == 0
+        return o.read_state()["u"][1, 0], o.time
+    (up, t), (um, _) = ux(ph0[1] + h), ux(ph0[1] - h)
+    fd = (up - um) / (2 * h)
+    # the force-free pair follows the rest length with a lag of order the
+    # damping time over the signal period (~1e-4 here)
+    exact = l * cte * A * np.cos(2 * np.pi * 0.5 * t + ph0[1]) / 2
+    assert abs(fd / exact - 1) < 1e-3, (fd, exact)

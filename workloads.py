@@ -155,3 +155,101 @@ def random_state(ncell, seed, u_scale, v_scale, w_scale, rot_scale):
     rng = np.random.Generator(np.random.PCG64(seed))
     return {"u": rng.normal(0, u_scale, (ncell, 3)), "v": rng.normal(0, v_scale, (ncell, 3)),
             "w": rng.normal(0, w_scale, (ncell, 3)), "rot": rng.normal(0, rot_scale, (ncell, 3))}
+
+
+def grad_object(seed, n=4, scenario="free", steps=200, temp_freq=500.0):
+    """Small object for gradient checks: an n^3 block in which every voxel
+    has its own palette entry (modulus log-uniform in [0.5, 2] MPa, CTE
+    0.01), a per-voxel actuation signal (20 K, phase U[0, 2 pi)), and a
+    detached two-voxel anchor of a 4 MPa material one empty cell beyond
+    +x.  The anchor's bond is the stiffest, so it alone sets the timestep:
+    perturbing any block modulus leaves dt unchanged.
+
+    scenario "free":  no gravity or floor; random initial velocities and
+                      spins; two fixed and two forced block voxels; bond
+                      and ground damping on.
+    scenario "slide": block on the floor under gravity, sliding at 5 cm/s
+                      along +x (Coulomb sliding branch), bond and floor
+                      damping on.
+    scenario "rest":  block on the floor under gravity, at rest (static
+                      friction branches).
+
+    Returns a workload plus ``block`` (cell indices of the block voxels,
+    ascending) and ``E_block`` (their moduli, in that order)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, nz = n + 3, n, n
+    grid = np.zeros((nz, ny, nx), np.uint8)
+    block = []
+    mats = [EMPTY]
+    E_block = np.exp(rng.uniform(np.log(0.5e6), np.log(2e6), size=n ** 3))
+    k = 0
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(n):
+                mats.append(_mat(E_block[k], cte=0.01))
+                grid[z, y, x] = len(mats) - 1
+                block.append(x + nx * (y + ny * z))
+                k += 1
+    mats.append(_mat(4e6))
+    grid[0, 0, n + 1] = grid[0, 0, n + 2] = len(mats) - 1
+    block = np.array(block)
+    ncell = grid.size
+    amp = np.zeros(ncell)
+    amp[block] = 20.0
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=ncell)
+    fixed = forces = velocity = None
+    if scenario == "free":
+        params = _base_params(zeta_bond=0.3, zeta_slow=0.01, temp_freq=temp_freq)
+        velocity = np.zeros((ncell, 3))
+        velocity[block] = rng.normal(0.0, 1e-3, size=(block.size, 3))
+        fixed = np.zeros(ncell, np.uint8)
+        fixed[block[rng.choice(block.size, 2, replace=False)]] = 1
+        forces = np.zeros((ncell, 3))
+        forces[block[rng.choice(block.size, 2, replace=False)]] = rng.normal(0.0, 1e-4, size=(2, 3))
+    elif scenario in ("slide", "rest"):
+        params = _base_params(gravity=9.81, zeta_bond=0.3, zeta_col=0.5, floor_on=1, temp_freq=temp_freq)
+        if scenario == "slide":
+            velocity = np.zeros((ncell, 3))
+            velocity[block, 0] = 0.05
+    else:
+        raise ValueError(scenario)
+    w = _workload(grid, mats, params, steps, fixed=fixed, forces=forces, velocity=velocity,
+                  amp=amp, phase=phase, name="grad_object_%s_%d" % (scenario, n))
+    w["block"] = block
+    w["E_block"] = E_block
+    return w
+
+
+def design_lattice(count=64, size=20, gap=1, seed=5, steps=5000):
+    """Many full size^3 design blocks in one lattice, on a sqrt(count) x
+    sqrt(count) layout in x-y separated by ``gap`` empty cells (so no bonds
+    join them), on the floor under gravity with friction.  Every voxel has
+    its own modulus E_v = 1 MPa * 100^sigmoid(s_v) with logits s_v ~ N(0, 1)
+    and its own actuation phase U[0, 2 pi) (CTE 0.01, 20 K, 5 Hz).  The
+    palette's one material is 100 MPa, the top of the modulus range, so the
+    timestep is the one of the stiffest design and does not depend on the
+    parameters.  Returns a workload plus ``E`` (per cell) and ``logits``."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    side = int(round(count ** 0.5))
+    assert side * side == count
+    pitch = size + gap
+    nx = ny = side * pitch - gap
+    nz = size
+    grid = np.zeros((nz, ny, nx), np.uint8)
+    for i in range(side):
+        for j in range(side):
+            grid[:, j * pitch:j * pitch + size, i * pitch:i * pitch + size] = 1
+    mats = [EMPTY, _mat(1e8, cte=0.01)]
+    params = _base_params(gravity=9.81, zeta_bond=0.5, zeta_col=0.5, floor_on=1, temp_amp=20.0,
+                          temp_freq=5.0)
+    ncell = grid.size
+    logits = rng.normal(0.0, 1.0, size=ncell)
+    E = 1e6 * 100.0 ** (1.0 / (1.0 + np.exp(-logits)))
+    E[grid.reshape(-1) == 0] = 0.0
+    amp = np.where(grid.reshape(-1) > 0, 20.0, 0.0)
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=ncell)
+    w = _workload(grid, mats, params, steps, amp=amp, phase=phase,
+                  name="design_lattice_%dx%d" % (count, size))
+    w["E"] = E
+    w["logits"] = logits
+    return w
