@@ -83,12 +83,49 @@ def time_gpu(w, precision, kernel, steps, warmup, autotune=True, tile=None):
     return out
 
 
-def roofline(precision, nvox, kernel_ms):
+# Sources the fused step kernel is compiled from; profiler counters count
+# for the current kernel only if they were taken on these exact files.
+FUSED_SOURCES = ["vx_fused.hip", "vx_device.hpp", "vx_types.hpp", "vx_launch.hpp"]
+
+
+def fused_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in FUSED_SOURCES:
+        with open(os.path.join(ROOT, "paper_1212_2845_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision, tile):
+    """HBM bytes per launch of the fused kernel (rocprofv3 FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy's readings) from profiles/traffic.json,
+    or None when none was taken for this workload and tile on the current
+    kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if tile is None or not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        db = json.load(fh)
+    e = db.get("%s|f%d|tile%d:%d" % (workload, precision, tile["shape"], tile["zc"]))
+    if e is None or e.get("src") != fused_source_hash():
+        return None
+    return e
+
+
+def roofline(precision, nvox, kernel_ms, workload=None, tile=None, kernel="k_fused"):
     alg = ALG_BYTES[precision]
     achieved = alg * nvox / (kernel_ms / 1e3) / 1e9
-    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_fused",
-            "kernel_ms": kernel_ms, "alg_bytes_per_voxel_step": alg, "voxels_per_launch": nvox}
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
+           "kernel_ms": kernel_ms, "alg_bytes_per_voxel_step": alg, "voxels_per_launch": nvox}
+    t = measured_traffic(workload, precision, tile) if workload else None
+    if t is not None:
+        out["traffic"] = t["traffic"]
+        out["traffic_unit"] = "bytes per launch"
+        out["traffic_over_algorithmic"] = t["traffic"] / (alg * nvox)
+        out["traffic_profile"] = "profiles/" + t["profile"]
+    return out
 
 
 def time_batch(count, steps, one_by_one_sample=64, one_by_one_steps=100):
@@ -137,7 +174,8 @@ def time_batch(count, steps, one_by_one_sample=64, one_by_one_steps=100):
                            "note": "first %d objects, each stepped alone through the fused single-lattice path"
                                    % len(sample)},
             "speedup": batched / single,
-            "roofline": roofline(32, nvox, ms / steps)}
+            "roofline": dict(roofline(32, nvox, ms / steps, kernel="k_batch"),
+                             note="kernel_ms is per step: one persistent launch runs all steps")}
 
 
 def time_adjoint(steps=5000, K=100):
@@ -288,14 +326,14 @@ def main():
                    "kernel": args.kernel, "tile": r["tile"], "state_bytes": int(w["grid"].size) * 13 *
                    (4 if args.precision == 32 else 8),
                    "cache_resident": 2 * int(w["grid"].size) * 13 * (4 if args.precision == 32 else 8) < 256e6},
-        "roofline": roofline(args.precision, r["voxels"], r["kernel_ms"]),
+        "roofline": roofline(args.precision, r["voxels"], r["kernel_ms"], w["name"], r["tile"]),
     }
     if not args.no_fp64 and args.precision == 32:
         log("fp64 leg")
         r64 = time_gpu(w, 64, kernel, args.steps, args.warmup, autotune)
         out["fp64"] = {"value": r64["voxels"] * args.steps / (r64["ms"] / 1e3),
                        "ms_per_step": r64["ms"] / args.steps, "tile": r64["tile"],
-                       "roofline": roofline(64, r64["voxels"], r64["kernel_ms"])}
+                       "roofline": roofline(64, r64["voxels"], r64["kernel_ms"], w["name"], r64["tile"])}
     if not args.no_hbm_leg:
         log("hbm-resident leg: blob_lattice_256")
         w3 = build_workload("blob_lattice_256")
@@ -303,7 +341,7 @@ def main():
         out["hbm_resident"] = {"workload": w3["name"], "dtype": "f32",
                                "value": r3["voxels"] * args.steps / (r3["ms"] / 1e3),
                                "ms_per_step": r3["ms"] / args.steps, "tile": r3["tile"],
-                               "roofline": roofline(32, r3["voxels"], r3["kernel_ms"])}
+                               "roofline": roofline(32, r3["voxels"], r3["kernel_ms"], w3["name"], r3["tile"])}
         del w3
     if not args.no_batch_leg:
         log("batched leg: %d objects, %d steps" % (args.batch_objects, args.batch_steps))
