@@ -160,6 +160,19 @@ int vx_counters(vx_handle h, int64_t out[4]);
 int vx_candidates(vx_handle h, int32_t *cell_a, int32_t *cell_b, int32_t max_pairs,
                   int32_t *n_pairs);
 
+/* Energies and momenta of the current state, summed over all voxels in
+ * FP64 (deterministic order), at time t_n for the actuation strain:
+ *   out[0] kinetic energy, sum |P|^2 / 2m + |phi|^2 / 2I (Eq. 27-28 state);
+ *   out[1] elastic energy of the bonds, sum 1/2 u2^T K22 u2 with u2 voxel 2's
+ *          displacement and rotation in voxel 1's bond frame and K22 the
+ *          lower-right block of the beam stiffness (Eq. 7);
+ *   out[2] gravitational energy sum m g z (z of the voxel centre);
+ *   out[3] floor penalty energy sum 1/2 k delta^2 over voxels in contact;
+ *   out[4..6] total linear momentum; out[7..9] total angular momentum about
+ *          the world origin (sum of D x P + phi).
+ * Blocks until the result is on the host.  Errors: VX_ESTATE before bind. */
+int vx_energy(vx_handle h, double out[10]);
+
 /* Select the step implementation: 0 = fused LDS-tiled kernel (default;
  * palettes of more than 16 materials always use the split path),
  * 1 = split per-axis bond kernels plus a gather kernel. */

@@ -32,7 +32,7 @@ EXPORTED = ["vx_create", "vx_workspace_bytes", "vx_bind_workspace", "vx_set_fixe
             "vx_read_state", "vx_write_state", "vx_read_flags", "vx_get_dt", "vx_get_time",
             "vx_counters", "vx_candidates", "vx_set_kernel", "vx_set_fused_tile", "vx_get_fused_tile",
             "vx_autotune", "vx_time_kernel", "vx_destroy", "vx_last_error",
-            "vx_set_stiffness", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
+            "vx_energy", "vx_set_stiffness", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
             "vx_grad_backward",
             "vx_batch_create", "vx_batch_workspace_bytes", "vx_batch_bind_workspace", "vx_batch_step",
             "vx_batch_read_state", "vx_batch_write_state", "vx_batch_get_dt", "vx_batch_counters",
@@ -110,6 +110,7 @@ def lib():
     L.vx_get_fused_tile.argtypes = [P, pi32, pi32, pi32, pi32]
     L.vx_autotune.argtypes = [P, i32, pi32, pi32]
     L.vx_time_kernel.argtypes = [P, i32, C.POINTER(C.c_double)]
+    L.vx_energy.argtypes = [P, C.POINTER(C.c_double)]
     L.vx_set_stiffness.argtypes = [P, P]
     L.vx_grad_workspace_bytes.argtypes = [P, i64, i32, C.POINTER(u64)]
     L.vx_grad_bind.argtypes = [P, P, u64, i64, i32]
@@ -322,6 +323,15 @@ class Sim:
         conv = lambda a, k: None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(self.ncell, k)
         u, q, v, w = conv(u, 3), conv(q, 4), conv(v, 3), conv(w, 3)
         self._check(lib().vx_write_state(self.h, _ptr(u), _ptr(q), _ptr(v), _ptr(w)))
+
+    def energy(self):
+        """Energies and momenta of the current state (see vx_energy)."""
+        self.bind()
+        out = (C.c_double * 10)()
+        self._check(lib().vx_energy(self.h, out))
+        v = list(out)
+        return {"kinetic": v[0], "elastic": v[1], "gravity": v[2], "floor": v[3], "momentum": v[4:7],
+                "angular_momentum": v[7:10]}
 
     def read_flags(self):
         st = np.empty(self.ncell, np.uint8); su = np.empty(self.ncell, np.uint8)

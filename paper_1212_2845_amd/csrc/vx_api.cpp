@@ -60,6 +60,7 @@ static void compute_layout(vx_sim *h) {
     L.scalars = take(sizeof(Scalars));
     L.scan_tmp = take(col ? h->scan_tmp_bytes : 0);
     L.E_cell = take(n * ts);
+    L.energy = take((uint64_t)energy_blocks((long long)n) * kEnergyWords * 8);
     L.total = off;
 }
 
@@ -262,8 +263,8 @@ static int autotune(vx_sim *h, int iters, int32_t *shape_out, int32_t *zc_out) {
             HIP_OK(h, hipEventElapsedTime(&ms, e0, e1));
             if (ms < best) { best = ms; best_cfg = cfg; }
         }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     // the timing launches touched the speed accumulator
     Scalars *sc = (Scalars *)(h->ws + h->L.scalars);
     const unsigned long long zero = 0;
@@ -299,13 +300,28 @@ static int time_kernel(vx_sim *h, int iters, double *ms_per_launch) {
     HIP_OK(h, hipEventSynchronize(e1));
     float ms = 0.f;
     HIP_OK(h, hipEventElapsedTime(&ms, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     Scalars *sc = (Scalars *)(h->ws + h->L.scalars);
     const unsigned long long zero = 0;
     HIP_OK(h, hipMemcpyAsync(&sc->vmax_bits, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
     HIP_OK(h, hipStreamSynchronize(h->stream));
     *ms_per_launch = (double)ms / iters;
+    return VX_OK;
+}
+
+template <typename T>
+static int energy(vx_sim *h, double *out) {
+    StepArgs<T> a = make_args<T>(h);
+    double *part = (double *)(h->ws + h->L.energy);
+    HIP_OK(h, launch_energy<T>(a, part, h->stream));
+    const int nb = energy_blocks(h->ncell);
+    std::vector<double> buf((size_t)nb * kEnergyWords);
+    HIP_OK(h, hipMemcpyAsync(buf.data(), part, buf.size() * 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    for (int i = 0; i < kEnergyWords; ++i) out[i] = 0.0;
+    for (int b = 0; b < nb; ++b)
+        for (int i = 0; i < kEnergyWords; ++i) out[i] += buf[(size_t)b * kEnergyWords + i];
     return VX_OK;
 }
 
@@ -530,6 +546,12 @@ int vx_step(vx_handle h, int64_t n) {
     if (n == 0) return VX_OK;
     h->tape_valid = false;
     return h->precision == 64 ? run_steps<double>(h, n) : run_steps<float>(h, n);
+}
+
+int vx_energy(vx_handle h, double out[10]) {
+    if (!h || !out) return VX_EINVAL;
+    if (!h->bound) return fail(h, VX_ESTATE, "vx_energy before vx_bind_workspace");
+    return h->precision == 64 ? energy<double>(h, out) : energy<float>(h, out);
 }
 
 int vx_set_stiffness(vx_handle h, const double *E) {

@@ -428,8 +428,8 @@ int vx_batch_autotune(vx_batch h, int32_t steps, int32_t *n_workgroups) {
         if (ms < best) { best = ms; best_wg = nw; }
         if (nw == nobj) break;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     h->n_wg = best_wg;
     h->cur = cur0;
     h->step = step0;

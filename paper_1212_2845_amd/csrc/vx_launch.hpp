@@ -29,6 +29,13 @@ struct AdjArgs {
 template <typename T>
 hipError_t launch_adjoint_step(const StepArgs<T> &a, const AdjArgs<T> &g, hipStream_t s);
 
+// Energies and momenta of the current state (a.s_in): kEnergyWords FP64
+// partial sums per workgroup of energy_blocks(ncell) workgroups.
+constexpr int kEnergyWords = 10;   // KE, U_elastic, U_gravity, U_floor, P (3), L (3)
+int energy_blocks(long long ncell);
+template <typename T>
+hipError_t launch_energy(const StepArgs<T> &a, double *partials, hipStream_t s);
+
 // Fused path: one LDS-tiled kernel per step.  cfg.shape indexes
 // kFusedShapes (tile TX x TY); cfg.zc is the z chunk per workgroup (0 picks
 // fused_default_zc).

@@ -24,6 +24,7 @@ struct Layout {
     uint64_t state[2], mat, flags[2], mats, pairs, bonds, act_amp, act_phase, forced_cells, forced_F;
     uint64_t contact_F, surf_cells, cand, cand_n, keys, sorted, bstart, bfill, scalars, scan_tmp;
     uint64_t E_cell;
+    uint64_t energy;
     uint64_t total;
 };
 
