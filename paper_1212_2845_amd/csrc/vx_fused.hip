@@ -106,6 +106,37 @@ __device__ __forceinline__ void load_own(const StepArgs<T> &a, const Tables<T> &
     }
 }
 
+// Raw words of one cell in flight: material, flags and all state words,
+// loaded without waiting on any of them (also for an empty cell, whose
+// state words exist and are ignored), so that a prefetch one slab ahead
+// costs no stall until the values are used.
+template <typename T>
+struct Pre {
+    uint8_t m, fl;
+    VoxRaw<T> r;
+};
+
+template <typename T>
+__device__ __forceinline__ void issue_pre(const StepArgs<T> &a, unsigned c, Pre<T> &p) {
+    p.m = ldc(a.mat, c);
+    p.fl = ldc(a.flags, c);
+    p.r = load_raw(a.s_in, a.stride, c);
+}
+
+// Strain and kinematics of a prefetched cell.
+template <typename T>
+__device__ __forceinline__ void finish_pre(const StepArgs<T> &a, const Tables<T> &tb, unsigned c, const Pre<T> &p,
+                                           Own<T> &o) {
+    o.m = p.m;
+    if (p.m) {
+        o.fl = p.fl;
+        o.r = p.r;
+        const MatConst<T> &mc = tb.mat[p.m];
+        o.eps = voxel_strain(a, c, p.fl, mc.cte);
+        o.k = kin_of(p.r, mc, o.eps);
+    }
+}
+
 // Load the material tables into LDS (all threads of the workgroup; the
 // caller synchronises before use).
 template <typename T>
@@ -175,6 +206,10 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
 
     Own<T> A{}, B{};
     if (inxy && z0 < z1) load_own(a, tb, col + (unsigned)z0 * nxy, A);
+    // ring cell of the first slab; later slabs' ring cells are issued one
+    // slab ahead
+    Pre<T> RA{}, RB{};
+    if (ring_in && z0 < z1) issue_pre(a, ring_col + (unsigned)z0 * nxy, RA);
 
     // bond from the slab below the chunk: only its voxel-2 half is needed
     bool has_carry = false;
@@ -190,10 +225,13 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
         }
     }
 
-    // one slab: cur holds slab z, nxt receives slab z + 1
-    auto slab = [&](Own<T> &cur, Own<T> &nxt, int z) __attribute__((always_inline)) {
-        nxt.m = 0;
-        if (inxy && z + 1 < a.nz) load_own(a, tb, col + (unsigned)(z + 1) * nxy, nxt);
+    // one slab: cur holds slab z (its loads issued one slab earlier), nxt
+    // receives slab z + 1; rcur / rnxt the same for this thread's ring cell
+    auto slab = [&](Own<T> &cur, Own<T> &nxt, Pre<T> &rcur, Pre<T> &rnxt, int z) __attribute__((always_inline)) {
+        Pre<T> pn{};
+        if (inxy && z + 1 < a.nz) issue_pre(a, col + (unsigned)(z + 1) * nxy, pn);
+        rnxt.m = 0;
+        if (ring_in && z + 1 < z1) issue_pre(a, ring_col + (unsigned)(z + 1) * nxy, rnxt);
 
         if (lane_in) {
             if (cur.m) put_kin<T, NR>(sm.kin, own, cur.k);
@@ -203,7 +241,7 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
             uint8_t mr = 0;
             if (ring_in) {
                 Own<T> R{};
-                load_own(a, tb, ring_col + (unsigned)z * nxy, R);
+                finish_pre(a, tb, ring_col + (unsigned)z * nxy, rcur, R);
                 mr = R.m;
                 if (mr) put_kin<T, NR>(sm.kin, ring_slot, R.k);
             }
@@ -243,6 +281,7 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
             n_mx = sm.mat[own - 1] != 0; n_px = sm.mat[own + 1] != 0;
             n_my = sm.mat[own - RW] != 0; n_py = sm.mat[own + RW] != 0;
         }
+        finish_pre(a, tb, col + (unsigned)(z + 1) * nxy, pn, nxt);
         const bool has_zb = cur.m && nxt.m;
         BondOut<T> oz{};
         if (has_zb) oz = bond_eval<T, 2>(cur.k, Rc, nxt.k, tb.bond(cur.m, nxt.m), C);
@@ -287,8 +326,8 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
 
     // two slabs per trip so that the roles of A and B alternate without copies
     for (int z = z0; z < z1; z += 2) {
-        slab(A, B, z);
-        if (z + 1 < z1) slab(B, A, z + 1);
+        slab(A, B, RA, RB, z);
+        if (z + 1 < z1) slab(B, A, RB, RA, z + 1);
     }
 }
 
