@@ -527,6 +527,41 @@ def test_torsion_mode_frequency():
     assert abs(period / (2 * math.pi / wd) - 1.0) < 1e-3
 
 
+def _oblique_tip_cantilever(Fy, Fz, steps=2000):
+    w = workloads.cantilever(steps=steps)
+    o = oracle.Sim(w["grid"], w["materials"], **dict(w["params"], gravity=0.0))
+    o.set_fixed(w["fixed"])
+    x, _, _ = workloads.cell_coords(w["grid"].shape)
+    tip = x == w["grid"].shape[2] - 1
+    f = np.zeros((w["grid"].size, 3))
+    f[tip] = np.array([0.0, Fy, Fz]) / tip.sum()
+    o.set_forces(f)
+    assert o.step(steps) == 0
+    return o.read_state(), w["grid"].shape
+
+
+def test_mirror_symmetry_is_exact_to_second_order():
+    """The 20x4x4 cantilever under an oblique tip load (0, Fy, Fz) and its
+    mirror image across the y mid-plane (load (0, -Fy, Fz)) must give
+    mirrored trajectories: u -> (u_x, -u_y, u_z) and, for the reflection
+    of an axial quantity, q -> (w, -x, y, -z).  The formulation is not
+    exactly mirror-invariant: a y-bond's frame is its lower-index voxel's,
+    which the mirror swaps, so a residual of second order in the load
+    remains (relative residual proportional to the load)."""
+    res = []
+    for s in (1e-6, 5e-7):
+        a, shape = _oblique_tip_cantilever(s, 2 * s)
+        b, _ = _oblique_tip_cantilever(-s, 2 * s)
+        nz, ny, nx = shape
+        mir = np.arange(nx * ny * nz).reshape(nz, ny, nx)[:, ::-1, :].reshape(-1)
+        ua = a["u"][mir] * np.array([1.0, -1.0, 1.0])
+        res.append(np.abs(b["u"] - ua).max() / np.abs(a["u"]).max())
+        qa = a["q"][mir] * np.array([1.0, -1.0, 1.0, -1.0])
+        assert np.abs(b["q"] - qa).max() < 1e-13
+    assert res[0] < 1e-9, res
+    assert 1.7 < res[0] / res[1] < 2.3, res
+
+
 # --- pins of the finite-difference gradient harness (expected values of the
 # adjoint tests) ------------------------------------------------------------
 
