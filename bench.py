@@ -151,28 +151,52 @@ def time_batch(count, steps, one_by_one_sample=64, one_by_one_steps=100):
     ms = e0.elapsed_time(e1)
     del b
     torch.cuda.empty_cache()
-    # one at a time: a sample of the same objects, each its own lattice
+    # one at a time: a sample of the same objects, each its own lattice,
+    # every object's steps recorded into one HIP graph (stream capture of
+    # vx_step_enqueue) and replayed, so that launch overhead is not counted
     sample = objs[:one_by_one_sample]
-    sims = [vx.from_workload(o, precision=32, stream=stream.cuda_stream) for o in sample]
+    side = torch.cuda.Stream()
+    sims = [vx.from_workload(o, precision=32, stream=side.cuda_stream) for o in sample]
     for s in sims:
         s.bind()
         s.step(2)
     nvox1 = sum(s.counters()["voxels"] for s in sims)
     torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        for s in sims:
+            s.step_enqueue(one_by_one_steps)
+    graph.replay()
+    torch.cuda.synchronize()
+    # replay() launches on the current stream: time it there
+    cs = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(cs)
+    graph.replay()
+    e1.record(cs)
+    torch.cuda.synchronize()
+    ms1 = e0.elapsed_time(e1)
+    for s in sims:
+        s.status()
+    # the same loop without graphs, one vx_step call per object
     t0 = time.perf_counter()
     for s in sims:
         s.step(one_by_one_steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    del sims
+    del graph, sims
     torch.cuda.empty_cache()
     batched = nvox * steps / (ms / 1e3)
-    single = nvox1 * one_by_one_steps / el
+    single = nvox1 * one_by_one_steps / (ms1 / 1e3)
+    single_eager = nvox1 * one_by_one_steps / el
     return {"workload": "batch_objects_%d" % count, "objects": count, "voxels": nvox, "steps": steps,
             "dtype": "f32", "value": batched, "ms": ms, "workgroups": n_wg,
             "one_by_one": {"value": single, "objects": len(sample), "steps": one_by_one_steps,
-                           "note": "first %d objects, each stepped alone through the fused single-lattice path"
-                                   % len(sample)},
+                           "eager_value": single_eager,
+                           "note": "first %d objects, each stepped alone through the fused single-lattice "
+                                   "path; value: all these objects' steps in one captured HIP graph, "
+                                   "replayed; eager_value: one vx_step call per object" % len(sample)},
             "speedup": batched / single,
             "roofline": dict(roofline(32, nvox, ms / steps, kernel="k_batch"),
                              note="kernel_ms is per step: one persistent launch runs all steps")}

@@ -133,6 +133,21 @@ int vx_set_velocity(vx_handle h, const double *velocity);
  * became non-finite, VX_EOVERFLOW if a candidate list overflowed. */
 int vx_step(vx_handle h, int64_t n);
 
+/* Enqueue n steps on the handle's stream and return at once: the call
+ * performs kernel launches only (no host synchronisation, no memory set or
+ * copy), so it may be recorded into a HIP graph by stream capture of that
+ * stream.  A recorded sequence replays the steps with the step times and
+ * the buffer order it was recorded with: it starts from the ping-pong
+ * buffer the capture started from, so replaying it repeatedly continues the
+ * state only for an even n.  The handle's step counter counts enqueued
+ * steps.  Non-finite states and candidate overflows are reported by the
+ * next vx_step or vx_status.  Errors: VX_ESTATE before bind. */
+int vx_step_enqueue(vx_handle h, int64_t n);
+
+/* Wait for the handle's stream and report the device status: VX_OK,
+ * VX_EUNSTABLE (a non-finite value was produced) or VX_EOVERFLOW. */
+int vx_status(vx_handle h);
+
 /* Copy the state to the host, widened to double, dense per cell (empty
  * cells read as zero displacement, identity rotation, zero velocity):
  * u = displacement from the rest position (ncell x 3), q = orientation

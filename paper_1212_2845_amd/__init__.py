@@ -32,7 +32,7 @@ EXPORTED = ["vx_create", "vx_workspace_bytes", "vx_bind_workspace", "vx_set_fixe
             "vx_read_state", "vx_write_state", "vx_read_flags", "vx_get_dt", "vx_get_time",
             "vx_counters", "vx_candidates", "vx_set_kernel", "vx_set_fused_tile", "vx_get_fused_tile",
             "vx_autotune", "vx_time_kernel", "vx_destroy", "vx_last_error",
-            "vx_energy", "vx_set_stiffness", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
+            "vx_step_enqueue", "vx_status", "vx_energy", "vx_set_stiffness", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
             "vx_grad_backward",
             "vx_batch_create", "vx_batch_workspace_bytes", "vx_batch_bind_workspace", "vx_batch_step",
             "vx_batch_read_state", "vx_batch_write_state", "vx_batch_get_dt", "vx_batch_counters",
@@ -111,6 +111,8 @@ def lib():
     L.vx_autotune.argtypes = [P, i32, pi32, pi32]
     L.vx_time_kernel.argtypes = [P, i32, C.POINTER(C.c_double)]
     L.vx_energy.argtypes = [P, C.POINTER(C.c_double)]
+    L.vx_step_enqueue.argtypes = [P, i64]
+    L.vx_status.argtypes = [P]
     L.vx_set_stiffness.argtypes = [P, P]
     L.vx_grad_workspace_bytes.argtypes = [P, i64, i32, C.POINTER(u64)]
     L.vx_grad_bind.argtypes = [P, P, u64, i64, i32]
@@ -295,6 +297,14 @@ class Sim:
         """Step and return the status code instead of raising."""
         self.bind()
         return lib().vx_step(self.h, int(n))
+
+    def step_enqueue(self, n=1):
+        """Enqueue n steps without waiting (capturable into a HIP graph)."""
+        self._check(lib().vx_step_enqueue(self.h, int(n)))
+
+    def status(self):
+        """Wait for the stream; raise on a non-finite state or overflow."""
+        self._check(lib().vx_status(self.h))
 
     @property
     def dt(self):

@@ -204,7 +204,7 @@ static FusedCfg fused_cfg(const vx_sim *h) {
 }
 
 template <typename T>
-static int run_steps(vx_sim *h, int64_t n) {
+static int enqueue_steps(vx_sim *h, int64_t n) {
     const bool col = h->p.self_collision_on != 0;
     for (int64_t i = 0; i < n; ++i) {
         StepArgs<T> a = make_args<T>(h);
@@ -225,12 +225,23 @@ static int run_steps(vx_sim *h, int64_t n) {
         h->cur = 1 - h->cur;
         h->step++;
     }
+    return VX_OK;
+}
+
+// Wait for the stream and report the device status flags.
+static int poll_status(vx_sim *h) {
     Scalars sc;
     HIP_OK(h, hipMemcpyAsync(&sc, h->ws + h->L.scalars, sizeof(sc), hipMemcpyDeviceToHost, h->stream));
     HIP_OK(h, hipStreamSynchronize(h->stream));
     if (sc.err_flag) return fail(h, VX_EUNSTABLE, "non-finite value in the voxel state");
     if (sc.overflow) return fail(h, VX_EOVERFLOW, "collision candidate list overflow (raise contact_cap)");
     return VX_OK;
+}
+
+template <typename T>
+static int run_steps(vx_sim *h, int64_t n) {
+    const int r = enqueue_steps<T>(h, n);
+    return r ? r : poll_status(h);
 }
 
 template <typename T>
@@ -552,6 +563,19 @@ int vx_energy(vx_handle h, double out[10]) {
     if (!h || !out) return VX_EINVAL;
     if (!h->bound) return fail(h, VX_ESTATE, "vx_energy before vx_bind_workspace");
     return h->precision == 64 ? energy<double>(h, out) : energy<float>(h, out);
+}
+
+int vx_step_enqueue(vx_handle h, int64_t n) {
+    if (!h || n < 0) return VX_EINVAL;
+    if (!h->bound) return fail(h, VX_ESTATE, "vx_step_enqueue before vx_bind_workspace");
+    h->tape_valid = false;
+    return h->precision == 64 ? enqueue_steps<double>(h, n) : enqueue_steps<float>(h, n);
+}
+
+int vx_status(vx_handle h) {
+    if (!h) return VX_EINVAL;
+    if (!h->bound) return VX_OK;
+    return poll_status(h);
 }
 
 int vx_set_stiffness(vx_handle h, const double *E) {

@@ -116,3 +116,35 @@ def test_batch_of_generated_objects_runs():
     for i in (0, 17, 63):
         st = b.read_state(i)
         assert np.isfinite(st["u"]).all() and np.isfinite(st["v"]).all()
+
+
+@pytest.mark.parametrize("collide", [0, 1])
+def test_graph_captured_steps_replay_like_eager(collide):
+    """vx_step_enqueue recorded by stream capture into a HIP graph replays
+    the recorded steps exactly as eager stepping runs them, replay after
+    replay, with eager host work (state writes, status checks) between."""
+    import torch
+    w = workloads._workload(np.ones((6, 5, 7), np.uint8), MATS[:3],
+                            workloads._base_params(**dict(PARAMS, self_collision_on=collide)), 12)
+    st0 = perturbed_state(w["grid"].size, 77, 1e-6, 1e-3, 0.5, 1e-3)
+    announce("graph capture collide=%d" % collide)
+    ref = vx.from_workload(w, precision=32)
+    ref.write_state(**st0)
+    ref.step(12)
+    want = ref.read_state()
+    side = torch.cuda.Stream()
+    s = vx.from_workload(w, precision=32, stream=side.cuda_stream)
+    s.bind()
+    s.write_state(**st0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        s.step_enqueue(12)
+    for rep in range(3):
+        s.write_state(**st0)
+        g.replay()
+        torch.cuda.synchronize()
+        s.status()
+        got = s.read_state()
+        for k in ("u", "q", "v", "w"):
+            assert np.array_equal(got[k], want[k]), (rep, k)
