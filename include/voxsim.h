@@ -235,6 +235,19 @@ int vx_time_kernel(vx_handle h, int32_t iters, double *ms_per_launch);
  * the timestep's bound. */
 int vx_set_stiffness(vx_handle h, const double *E);
 
+/* Per-voxel density rho[ncell] (kg/m^3; read only at filled cells; NULL
+ * returns to the palette's).  It replaces the palette density in the
+ * voxel's mass and inertia (m = rho l^3, I = m l^2 / 6) and in every
+ * mass-dependent damping coefficient (ground, floor and bond damping, the
+ * last with the lighter voxel of the pair, Eq. 34).  The same stability
+ * rule as vx_set_stiffness applies to the pair (modulus, density).  The
+ * stored momenta are kept, and vx_read_state, vx_write_state and
+ * vx_set_velocity convert them with the cell's own mass.  Both
+ * calls need self-collision off (contact keeps the palette's constants):
+ * VX_ESTATE otherwise.  Errors: VX_EINVAL for a non-positive or non-finite
+ * density, or one that puts a bond above the timestep's bound. */
+int vx_set_density(vx_handle h, const double *rho);
+
 /* Bytes of the gradient workspace for rollouts of up to max_steps steps
  * with a checkpoint every K steps: ceil(max_steps/K) checkpoints plus a
  * K-step recompute buffer, adjoint state and per-bond adjoint records
@@ -262,14 +275,21 @@ int vx_grad_forward(vx_handle h, int64_t n);
  * the layout of vx_read_state.
  * Outputs (host, NULL = not wanted), per cell, zero at empty cells:
  *   g_E      dL/dE of vx_set_stiffness's moduli;
+ *   g_rho    dL/drho of vx_set_density's densities, with the timestep and
+ *            the rollout's initial velocities and angular velocities held
+ *            fixed (its initial momenta scale with the mass) and the loss a
+ *            function of the final velocities (v = P / m); where two
+ *            bonded voxels have equal mass, the bond
+ *            damping's dependence on the lighter mass is assigned to the
+ *            voxel the forward takes it from (voxel 2 of the bond);
  *   g_phase  dL/dphase, g_amp dL/damp of vx_set_actuation's per-voxel
  *            signal (zero when the voxel follows the global signal);
  *   g_u0, g_q0, g_v0, g_w0  adjoint of the rollout's initial state.
  * The adjoint state is kept in the state's precision; the parameter
  * gradients are accumulated in FP64. */
 int vx_grad_backward(vx_handle h, const double *dL_du, const double *dL_dq, const double *dL_dv,
-                     const double *dL_dw, double *g_E, double *g_phase, double *g_amp, double *g_u0,
-                     double *g_q0, double *g_v0, double *g_w0);
+                     const double *dL_dw, double *g_E, double *g_rho, double *g_phase, double *g_amp,
+                     double *g_u0, double *g_q0, double *g_v0, double *g_w0);
 
 /* ------------------------------------------------------------------ */
 /* Batches: many independent objects stepped by one persistent launch  */

@@ -32,7 +32,7 @@ EXPORTED = ["vx_create", "vx_workspace_bytes", "vx_bind_workspace", "vx_set_fixe
             "vx_read_state", "vx_write_state", "vx_read_flags", "vx_get_dt", "vx_get_time",
             "vx_counters", "vx_candidates", "vx_set_kernel", "vx_set_fused_tile", "vx_get_fused_tile",
             "vx_autotune", "vx_time_kernel", "vx_destroy", "vx_last_error",
-            "vx_step_enqueue", "vx_status", "vx_energy", "vx_set_stiffness", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
+            "vx_step_enqueue", "vx_status", "vx_energy", "vx_set_stiffness", "vx_set_density", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
             "vx_grad_backward",
             "vx_batch_create", "vx_batch_workspace_bytes", "vx_batch_bind_workspace", "vx_batch_step",
             "vx_batch_read_state", "vx_batch_write_state", "vx_batch_get_dt", "vx_batch_counters",
@@ -114,10 +114,11 @@ def lib():
     L.vx_step_enqueue.argtypes = [P, i64]
     L.vx_status.argtypes = [P]
     L.vx_set_stiffness.argtypes = [P, P]
+    L.vx_set_density.argtypes = [P, P]
     L.vx_grad_workspace_bytes.argtypes = [P, i64, i32, C.POINTER(u64)]
     L.vx_grad_bind.argtypes = [P, P, u64, i64, i32]
     L.vx_grad_forward.argtypes = [P, i64]
-    L.vx_grad_backward.argtypes = [P] + [P] * 11
+    L.vx_grad_backward.argtypes = [P] + [P] * 12
     L.vx_destroy.argtypes = [P]
     L.vx_last_error.argtypes = [P]
     L.vx_last_error.restype = C.c_char_p
@@ -365,6 +366,13 @@ class Sim:
             assert e.size == self.ncell
         self._check(lib().vx_set_stiffness(self.h, _ptr(e)))
 
+    def set_density(self, rho):
+        """Per-voxel density (ncell values; None returns to the palette)."""
+        r = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+        if r is not None:
+            assert r.size == self.ncell
+        self._check(lib().vx_set_density(self.h, _ptr(r)))
+
     def grad_bind(self, max_steps, K):
         """Allocate (torch) and bind the gradient workspace for rollouts of up
         to max_steps steps with a checkpoint every K steps."""
@@ -388,11 +396,11 @@ class Sim:
         n = self.ncell
         conv = lambda a, k: None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(n, k)
         du, dq, dv, dw = conv(dL_du, 3), conv(dL_dq, 4), conv(dL_dv, 3), conv(dL_dw, 3)
-        out = {"E": np.empty(n), "phase": np.empty(n), "amp": np.empty(n), "u0": np.empty((n, 3)),
-               "q0": np.empty((n, 4)), "v0": np.empty((n, 3)), "w0": np.empty((n, 3))}
+        out = {"E": np.empty(n), "rho": np.empty(n), "phase": np.empty(n), "amp": np.empty(n),
+               "u0": np.empty((n, 3)), "q0": np.empty((n, 4)), "v0": np.empty((n, 3)), "w0": np.empty((n, 3))}
         self._check(lib().vx_grad_backward(self.h, _ptr(du), _ptr(dq), _ptr(dv), _ptr(dw), _ptr(out["E"]),
-                                           _ptr(out["phase"]), _ptr(out["amp"]), _ptr(out["u0"]),
-                                           _ptr(out["q0"]), _ptr(out["v0"]), _ptr(out["w0"])))
+                                           _ptr(out["rho"]), _ptr(out["phase"]), _ptr(out["amp"]),
+                                           _ptr(out["u0"]), _ptr(out["q0"]), _ptr(out["v0"]), _ptr(out["w0"])))
         return out
 
 
@@ -402,12 +410,13 @@ def _rollout_fn():
     class RolloutFn(torch.autograd.Function):
         """Final displacement and velocity (ncell x 3 each, float64, CPU) of an
         n-step rollout from the Sim's current state, differentiable w.r.t. the
-        per-voxel modulus E and actuation phase (ncell each).  The actuation
-        amplitude is held fixed at amp."""
+        per-voxel modulus E, density rho and actuation phase (ncell each).
+        The actuation amplitude is held fixed at amp."""
 
         @staticmethod
-        def forward(ctx, E, phase, sim, amp, n):
+        def forward(ctx, E, rho, phase, sim, amp, n):
             sim.set_stiffness(E.detach().cpu().numpy())
+            sim.set_density(rho.detach().cpu().numpy())
             sim.set_actuation(amp, phase.detach().cpu().numpy())
             sim.grad_forward(n)
             st = sim.read_state()
@@ -417,15 +426,17 @@ def _rollout_fn():
         @staticmethod
         def backward(ctx, gu, gv):
             g = ctx.sim.grad_backward(dL_du=gu.cpu().numpy(), dL_dv=gv.cpu().numpy())
-            return torch.from_numpy(g["E"]), torch.from_numpy(g["phase"]), None, None, None
+            return (torch.from_numpy(g["E"]), torch.from_numpy(g["rho"]), torch.from_numpy(g["phase"]), None,
+                    None, None)
 
     return RolloutFn
 
 
-def rollout(sim, E, phase, amp, n):
-    """(u, v) after n steps from sim's current state; differentiable in E and
-    phase through the library's reverse run (sim needs grad_bind first)."""
-    return _rollout_fn().apply(E, phase, sim, amp, n)
+def rollout(sim, E, rho, phase, amp, n):
+    """(u, v) after n steps from sim's current state; differentiable in E,
+    rho and phase through the library's reverse run (sim needs grad_bind
+    first)."""
+    return _rollout_fn().apply(E, rho, phase, sim, amp, n)
 
 
 def from_workload(w, precision=64, kernel=KERNEL_FUSED, stream=None):

@@ -17,11 +17,6 @@ namespace vx {
 namespace {
 
 template <typename T>
-__device__ __forceinline__ MatConst<T> mat_of(const StepArgs<T> &a, long long c, uint8_t m) {
-    return mat_with_E(a.mats[m], a.E_cell[c], a.l, a.zeta_slow, a.zeta_col);
-}
-
-template <typename T>
 __global__ void __launch_bounds__(256) k_adj_update(StepArgs<T> a, AdjArgs<T> g) {
     const long long n = (long long)a.nx * a.ny * a.nz;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -29,7 +24,7 @@ __global__ void __launch_bounds__(256) k_adj_update(StepArgs<T> a, AdjArgs<T> g)
     const uint8_t m = a.mat[c];
     if (m == 0) return;
     const long long st = a.stride;
-    const MatConst<T> mc = mat_of(a, c, m);
+    const MatConst<T> mc = mat_at(a, c, m);
     const uint8_t fl = a.flags[c];
     const T eps = voxel_strain(a, (unsigned)c, fl, mc.cte);
     const VoxRaw<T> r = load_raw(a.s_in, st, (unsigned)c);
@@ -43,10 +38,14 @@ __global__ void __launch_bounds__(256) k_adj_update(StepArgs<T> a, AdjArgs<T> g)
     T *gfm = g.gfm;
     gfm[c] = ad.Fx; gfm[st + c] = ad.Fy; gfm[2 * st + c] = ad.Fz;
     gfm[3 * st + c] = ad.Mx; gfm[4 * st + c] = ad.My; gfm[5 * st + c] = ad.Mz;
-    // kv = E l; cg, cgr, cfloor are proportional to sqrt(E)
-    const T gE = ad.kv * a.l + (ad.cg * mc.cg + ad.cgr * mc.cgr + ad.cfloor * mc.cfloor) / (T(2) * mc.E);
+    // kv = E l; cg, cgr, cfloor are proportional to sqrt(E m) (I = m l^2/6);
+    // inv_m = 1/m, inv_I = 6/(m l^2)
+    const T gd = ad.cg * mc.cg + ad.cgr * mc.cgr + ad.cfloor * mc.cfloor;
+    const T gE = ad.kv * a.l + gd / (T(2) * mc.E);
+    const T gm = ad.m - (ad.inv_m * mc.inv_m + ad.inv_I * mc.inv_I) / mc.m + gd / (T(2) * mc.m);
     g.gloc[c] = ad.eps;
     g.gloc[st + c] = gE;
+    g.gloc[2 * st + c] = gm;
 }
 
 template <typename T, int AX>
@@ -71,7 +70,7 @@ __global__ void __launch_bounds__(256) k_adj_bonds(StepArgs<T> a, AdjArgs<T> g) 
     const uint8_t mb = a.mat[cn];
     if (mb == 0) return;
     const long long st = a.stride;
-    const MatConst<T> A = mat_of(a, c, ma), B = mat_of(a, cn, mb);
+    const MatConst<T> A = mat_at(a, c, ma), B = mat_at(a, cn, mb);
     const T ea = voxel_strain(a, (unsigned)c, a.flags[c], A.cte);
     const T eb = voxel_strain(a, (unsigned)cn, a.flags[cn], B.cte);
     const VoxKin<T> ka = load_kin(a.s_in, st, (unsigned)c, A, ea);
@@ -87,6 +86,11 @@ __global__ void __launch_bounds__(256) k_adj_bonds(StepArgs<T> a, AdjArgs<T> g) 
     const BondAdj<T> ad = bond_vjp<T, AX>(ka, kb, K, C, gF, gM1, gM2);
     T gEA, gEB;
     bond_k_from_E_vjp(EA, EB, A.gfac, B.gfac, K, ad.a1, ad.a2, ad.ct, C, &gEA, &gEB);
+    // ct = 2 zeta sqrt(m_min a1): the lighter voxel's mass (B on a tie, as
+    // the forward picks it)
+    const T mmin = A.m < B.m ? A.m : B.m;
+    const T gmmin = ad.ct * K.ct / (T(2) * mmin);
+    const T gmA = A.m < B.m ? gmmin : T(0), gmB = A.m < B.m ? T(0) : gmmin;
     T *r = g.rec + (long long)AX * kAdjRecWords * st + c;
     const KinAdj<T> *ends[2] = {&ad.A, &ad.B};
 #pragma unroll
@@ -101,6 +105,8 @@ __global__ void __launch_bounds__(256) k_adj_bonds(StepArgs<T> a, AdjArgs<T> g) 
     }
     r[28 * st] = gEA;
     r[29 * st] = gEB;
+    r[30 * st] = gmA;
+    r[31 * st] = gmB;
 }
 
 template <typename T>
@@ -120,6 +126,7 @@ __global__ void __launch_bounds__(256) k_adj_gather(StepArgs<T> a, AdjArgs<T> g)
 #pragma unroll
     for (int i = 0; i < 14; ++i) k[i] = T(0);
     T gE = g.gloc[st + c];
+    T gm = g.gloc[2 * st + c];
     // fixed order as in the forward sum: -x, +x, -y, +y, -z, +z
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
@@ -129,15 +136,17 @@ __global__ void __launch_bounds__(256) k_adj_gather(StepArgs<T> a, AdjArgs<T> g)
 #pragma unroll
             for (int i = 0; i < 14; ++i) k[i] += o[i * st];
             gE += rb[29 * st + (c - step[ax])];
+            gm += rb[31 * st + (c - step[ax])];
         }
         if (idx[ax] + 1 < dim[ax] && a.mat[c + step[ax]] != 0) {   // voxel 1 of the bond at c
             const T *o = rb + c;
 #pragma unroll
             for (int i = 0; i < 14; ++i) k[i] += o[i * st];
             gE += rb[28 * st + c];
+            gm += rb[30 * st + c];
         }
     }
-    const MatConst<T> mc = a.mats[m];
+    const MatConst<T> mc = mat_at(a, c, m);
     VoxRaw<T> lam = load_raw(g.lam_out, st, (unsigned)c);
     lam.ux += k[0]; lam.uy += k[1]; lam.uz += k[2];
     lam.qw += k[3]; lam.qx += k[4]; lam.qy += k[5]; lam.qz += k[6];
@@ -146,7 +155,13 @@ __global__ void __launch_bounds__(256) k_adj_gather(StepArgs<T> a, AdjArgs<T> g)
     lam.lx += k[10] * mc.inv_I; lam.ly += k[11] * mc.inv_I; lam.lz += k[12] * mc.inv_I;
     store_raw(g.lam_out, st, (unsigned)c, lam.ux, lam.uy, lam.uz, lam.qw, lam.qx, lam.qy, lam.qz, lam.px, lam.py,
               lam.pz, lam.lx, lam.ly, lam.lz);
+    // the bonds read v = P inv_m and w = L inv_I of this voxel
+    const VoxRaw<T> r = load_raw(a.s_in, st, (unsigned)c);
+    const T g_inv_m = k[7] * r.px + k[8] * r.py + k[9] * r.pz;
+    const T g_inv_I = k[10] * r.lx + k[11] * r.ly + k[12] * r.lz;
+    gm -= (g_inv_m * mc.inv_m + g_inv_I * mc.inv_I) / mc.m;
     g.g_E[c] += (double)gE;
+    g.g_rho[c] += (double)gm * ((double)a.l * (double)a.l * (double)a.l);
     const uint8_t fl = a.flags[c];
     if (fl & FLAG_ACT) {
         const T geps = g.gloc[c] + k[13];

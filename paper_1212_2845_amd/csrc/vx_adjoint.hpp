@@ -246,6 +246,7 @@ struct UpdAdj {
     T Fx, Fy, Fz, Mx, My, Mz;   // bond sums
     T eps;
     T kv, cg, cgr, cfloor;      // per-voxel constants
+    T m, inv_m, inv_I;          // mass terms (each taken as an independent input)
 };
 
 // d cos(h)/da2 and d (sin(h)/(2h))/da2 with a2 = (2h)^2, on the series range.
@@ -383,11 +384,13 @@ VX_HD UpdAdj<T> update_vjp(const UpdEnv<T> &e, uint8_t fl, const MatConst<T> &mc
     const T grx = sk * gdx + T(2) * ga2 * rx, gry = sk * gdy + T(2) * ga2 * ry, grz = sk * gdz + T(2) * ga2 * rz;
     // r = L' inv_I dt; L' = L + M dt
     const T c = mc.inv_I * dt;
+    a.inv_I += (grx * Lx + gry * Ly + grz * Lz) * dt;
     const T gLx = g.lx + grx * c, gLy = g.ly + gry * c, gLz = g.lz + grz * c;
     a.r.lx = gLx; a.r.ly = gLy; a.r.lz = gLz;
     T gMx = gLx * dt, gMy = gLy * dt, gMz = gLz * dt;
     // u' = u + P' inv_m dt; P' = P + F dt
     a.r.ux = g.ux; a.r.uy = g.uy; a.r.uz = g.uz;
+    a.inv_m += (g.ux * Px + g.uy * Py + g.uz * Pz) * dt;
     const T gPx = g.px + g.ux * dt * mc.inv_m, gPy = g.py + g.uy * dt * mc.inv_m, gPz = g.pz + g.uz * dt * mc.inv_m;
     T gFx = gPx * dt, gFy = gPy * dt, gFz = gPz * dt;     // adjoint of F after friction
     T gpx = gPx, gpy = gPy, gpz = gPz;                    // adjoint of P after friction
@@ -431,6 +434,10 @@ VX_HD UpdAdj<T> update_vjp(const UpdEnv<T> &e, uint8_t fl, const MatConst<T> &mc
     const T gwx = -mc.cgr * gMx, gwy = -mc.cgr * gMy, gwz = -mc.cgr * gMz;
     a.Fx = gFx; a.Fy = gFy; a.Fz = gFz;
     a.Mx = gMx; a.My = gMy; a.Mz = gMz;
+    // gravity (Fz -= m g), and v = P inv_m, w = L inv_I at t_n
+    a.m += -e.gravity * gFz;
+    a.inv_m += gvx * r.px + gvy * r.py + gvz * r.pz;
+    a.inv_I += gwx * r.lx + gwy * r.ly + gwz * r.lz;
     a.r.px = gpx + mc.inv_m * gvx; a.r.py = gpy + mc.inv_m * gvy; a.r.pz = gpz + mc.inv_m * gvz;
     a.r.lx += mc.inv_I * gwx; a.r.ly += mc.inv_I * gwy; a.r.lz += mc.inv_I * gwz;
     return a;

@@ -60,6 +60,7 @@ static void compute_layout(vx_sim *h) {
     L.scalars = take(sizeof(Scalars));
     L.scan_tmp = take(col ? h->scan_tmp_bytes : 0);
     L.E_cell = take(n * ts);
+    L.rho_cell = take(n * ts);
     L.energy = take((uint64_t)energy_blocks((long long)n) * kEnergyWords * 8);
     L.total = off;
 }
@@ -98,10 +99,17 @@ static int upload_static(vx_sim *h) {
         for (long long c = 0; c < h->ncell; ++c) { a[c] = (T)h->amp[c]; ph[c] = (T)h->phase[c]; }
     HIP_OK(h, hipMemcpyAsync(ws + h->L.act_amp, a.data(), h->ncell * sizeof(T), hipMemcpyHostToDevice, s));
     HIP_OK(h, hipMemcpyAsync(ws + h->L.act_phase, ph.data(), h->ncell * sizeof(T), hipMemcpyHostToDevice, s));
-    std::vector<T> ec(h->ncell, T(0));
-    if (h->has_E)
-        for (long long c = 0; c < h->ncell; ++c) ec[c] = (T)h->E_cell[c];
+    // parameter mode: per-cell modulus and density, the palette's where not set
+    std::vector<T> ec(h->ncell, T(0)), rc(h->ncell, T(0));
+    if (h->param_mode())
+        for (long long c = 0; c < h->ncell; ++c) {
+            const int m = h->grid[c];
+            if (!m) continue;
+            ec[c] = (T)(h->has_E ? h->E_cell[c] : h->pal[m].E);
+            rc[c] = (T)(h->has_rho ? h->rho_cell[c] : h->pal[m].rho);
+        }
     HIP_OK(h, hipMemcpyAsync(ws + h->L.E_cell, ec.data(), h->ncell * sizeof(T), hipMemcpyHostToDevice, s));
+    HIP_OK(h, hipMemcpyAsync(ws + h->L.rho_cell, rc.data(), h->ncell * sizeof(T), hipMemcpyHostToDevice, s));
     if ((int)h->forced_cells.size() > h->forced_cap)
         return fail(h, VX_ESTATE, "more forced voxels than the workspace was sized for; set forces before the first step");
     std::vector<T> ff(h->forced_F.size());
@@ -152,9 +160,11 @@ static int reupload_static(vx_sim *h) {
     return h->precision == 64 ? upload_static<double>(h) : upload_static<float>(h);
 }
 
-static double mass_of(const vx_sim *h, int m) {
+// Mass of filled cell c: the palette density, or the cell's own in
+// parameter mode.
+static double cell_mass(const vx_sim *h, long long c) {
     const double l = h->p.voxel_size;
-    return h->pal[m].rho * l * l * l;
+    return (h->has_rho ? h->rho_cell[c] : h->pal[h->grid[c]].rho) * l * l * l;
 }
 
 static void update_cmax(vx_sim *h) {
@@ -213,7 +223,7 @@ static int enqueue_steps(vx_sim *h, int64_t n) {
             HIP_OK(h, launch_rebuild<T>(a, c, h->stream));
             HIP_OK(h, launch_contact<T>(a, c, (T *)(h->ws + h->L.contact_F), h->stream));
         }
-        if (h->kernel_kind == 1 || h->n_mat > kFusedMaxMat || h->has_E) {
+        if (h->kernel_kind == 1 || h->n_mat > kFusedMaxMat || h->param_mode()) {
             HIP_OK(h, launch_split_step<T>(a, h->stream));
         } else {
             HIP_OK(h, launch_fused_step<T>(a, fused_cfg(h), h->stream));
@@ -298,7 +308,7 @@ static int time_kernel(vx_sim *h, int iters, double *ms_per_launch) {
         HIP_OK(h, launch_rebuild<T>(a, c, h->stream));
         HIP_OK(h, launch_contact<T>(a, c, (T *)(h->ws + h->L.contact_F), h->stream));
     }
-    const bool split = h->kernel_kind == 1 || h->n_mat > kFusedMaxMat || h->has_E;
+    const bool split = h->kernel_kind == 1 || h->n_mat > kFusedMaxMat || h->param_mode();
     const FusedCfg cfg = fused_cfg(h);
     auto launch = [&]() { return split ? launch_split_step<T>(a, h->stream) : launch_fused_step<T>(a, cfg, h->stream); };
     hipEvent_t e0, e1;
@@ -545,7 +555,7 @@ int vx_set_velocity(vx_handle h, const double *velocity) {
     if (r) return r;
     for (long long c = 0; c < h->ncell; ++c) {
         if (!h->grid[c] || (h->flags[c] & FLAG_FIXED)) continue;
-        const double m = mass_of(h, h->grid[c]);
+        const double m = cell_mass(h, c);
         for (int k = 0; k < 3; ++k) st[(size_t)(W_PX + k) * h->ncell + c] = m * velocity[3 * c + k];
     }
     return put_state(h, st);
@@ -578,44 +588,70 @@ int vx_status(vx_handle h) {
     return poll_status(h);
 }
 
-int vx_set_stiffness(vx_handle h, const double *E) {
-    if (!h) return VX_EINVAL;
-    if (!E) {
-        h->has_E = false;
-        h->E_cell.clear();
-        return reupload_static(h);
-    }
+// Highest bond frequency sqrt(k_b / m_min) with per-cell moduli E and
+// densities rho (NULL: the palette's); a lattice without bonds uses the
+// voxels' own sqrt(E l / m).
+static double param_omega(const vx_sim *h, const double *E, const double *rho) {
     const double l = h->p.voxel_size;
     const long long stp[3] = {1, h->nx, (long long)h->nx * h->ny};
+    const int dim[3] = {h->nx, h->ny, h->nz};
+    auto Ec = [&](long long c) { return E ? E[c] : h->pal[h->grid[c]].E; };
+    auto mass = [&](long long c) { return (rho ? rho[c] : h->pal[h->grid[c]].rho) * l * l * l; };
     double w = 0.0;
     bool any_bond = false;
     for (long long c = 0; c < h->ncell; ++c) {
-        const int m = h->grid[c];
-        if (!m) continue;
-        if (!(E[c] > 0.0) || !std::isfinite(E[c])) return fail(h, VX_EINVAL, "per-voxel modulus must be positive and finite");
+        if (!h->grid[c]) continue;
         const int idx[3] = {(int)(c % h->nx), (int)((c / h->nx) % h->ny), (int)(c / stp[2])};
-        const int dim[3] = {h->nx, h->ny, h->nz};
         for (int a = 0; a < 3; ++a) {
             if (idx[a] + 1 >= dim[a] || !h->grid[c + stp[a]]) continue;
             const long long cn = c + stp[a];
             any_bond = true;
-            const double kb = composite(E[c], E[cn]) * l;
-            const double mm = std::min(mass_of(h, m), mass_of(h, h->grid[cn]));
-            w = std::max(w, std::sqrt(kb / mm));
+            const double kb = composite(Ec(c), Ec(cn)) * l;
+            w = std::max(w, std::sqrt(kb / std::min(mass(c), mass(cn))));
         }
     }
     if (!any_bond)
         for (long long c = 0; c < h->ncell; ++c)
-            if (h->grid[c]) w = std::max(w, std::sqrt(E[c] * l / mass_of(h, h->grid[c])));
-    // the timestep stays the one chosen at create: the moduli may not raise
-    // the highest bond frequency it was chosen for
-    if (w > h->wmax * (1.0 + 1e-12))
-        return fail(h, VX_EINVAL, "per-voxel modulus above the stable bound of the timestep chosen at create");
-    h->E_cell.assign(h->ncell, 0.0);
+            if (h->grid[c]) w = std::max(w, std::sqrt(Ec(c) * l / mass(c)));
+    return w;
+}
+
+// Validate and store one per-cell parameter array (dst, flag) given the
+// other's current values; the timestep stays the one chosen at create, so
+// no bond may become faster than the bound it was chosen for.
+static int set_param(vx_sim *h, const double *vals, bool is_E, const char *what) {
+    if (h->p.self_collision_on)
+        return fail(h, VX_ESTATE, "per-voxel parameters need self-collision off (contact uses the palette)");
+    std::vector<double> &dst = is_E ? h->E_cell : h->rho_cell;
+    bool &flag = is_E ? h->has_E : h->has_rho;
+    if (!vals) {
+        flag = false;
+        dst.clear();
+        return reupload_static(h);
+    }
     for (long long c = 0; c < h->ncell; ++c)
-        if (h->grid[c]) h->E_cell[c] = E[c];
-    h->has_E = true;
+        if (h->grid[c] && (!(vals[c] > 0.0) || !std::isfinite(vals[c])))
+            return fail(h, VX_EINVAL, std::string("per-voxel ") + what + " must be positive and finite");
+    const double *E = is_E ? vals : (h->has_E ? h->E_cell.data() : nullptr);
+    const double *rho = is_E ? (h->has_rho ? h->rho_cell.data() : nullptr) : vals;
+    if (param_omega(h, E, rho) > h->wmax * (1.0 + 1e-12))
+        return fail(h, VX_EINVAL, std::string("per-voxel ") + what +
+                                      " gives a bond above the stable bound of the timestep chosen at create");
+    dst.assign(h->ncell, 0.0);
+    for (long long c = 0; c < h->ncell; ++c)
+        if (h->grid[c]) dst[c] = vals[c];
+    flag = true;
     return reupload_static(h);
+}
+
+int vx_set_stiffness(vx_handle h, const double *E) {
+    if (!h) return VX_EINVAL;
+    return set_param(h, E, true, "modulus");
+}
+
+int vx_set_density(vx_handle h, const double *rho) {
+    if (!h) return VX_EINVAL;
+    return set_param(h, rho, false, "density");
 }
 
 int vx_read_state(vx_handle h, double *u, double *q, double *vel, double *omega) {
@@ -627,7 +663,7 @@ int vx_read_state(vx_handle h, double *u, double *q, double *vel, double *omega)
     const double l = h->p.voxel_size;
     for (long long c = 0; c < n; ++c) {
         const int m = h->grid[c];
-        const double mass = m ? mass_of(h, m) : 1.0;
+        const double mass = m ? cell_mass(h, c) : 1.0;
         const double I = mass * l * l / 6.0;
         for (int k = 0; k < 3; ++k) {
             if (u) u[3 * c + k] = m ? st[(size_t)(W_UX + k) * n + c] : 0.0;
@@ -650,7 +686,7 @@ int vx_write_state(vx_handle h, const double *u, const double *q, const double *
     for (long long c = 0; c < n; ++c) {
         const int m = h->grid[c];
         if (!m) continue;
-        const double mass = mass_of(h, m), I = mass * l * l / 6.0;
+        const double mass = cell_mass(h, c), I = mass * l * l / 6.0;
         for (int k = 0; k < 3; ++k) {
             if (u) st[(size_t)(W_UX + k) * n + c] = u[3 * c + k];
             if (vel) st[(size_t)(W_PX + k) * n + c] = mass * vel[3 * c + k];

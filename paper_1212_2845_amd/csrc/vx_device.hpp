@@ -385,16 +385,29 @@ VX_HD VoxKin<T> load_kin(const T *__restrict__ s, long long stride, unsigned c,
     return kin_of(load_raw(s, stride, c), mc, eps);
 }
 
-// Material constants of one voxel whose modulus E overrides the palette's
-// (parameter mode): the stiffness-dependent fields recomputed from E.
+// Material constants of one voxel whose modulus E and density rho override
+// the palette's (parameter mode): mass, inertia and the stiffness- and
+// mass-dependent coefficients recomputed as the host does for a palette
+// entry.
 template <typename T>
-VX_HD MatConst<T> mat_with_E(MatConst<T> mc, T E, T l, T zeta_slow, T zeta_col) {
+VX_HD MatConst<T> mat_with(MatConst<T> mc, T E, T rho, T l, T zeta_slow, T zeta_col) {
+    mc.m = rho * l * l * l;
+    mc.inv_m = T(1) / mc.m;
+    mc.I = mc.m * l * l / T(6);
+    mc.inv_I = T(1) / mc.I;
     mc.E = E;
     mc.kv = E * l;
     mc.cg = T(2) * zeta_slow * dsqrt(mc.m * mc.kv);
     mc.cgr = T(2) * zeta_slow * dsqrt(mc.I * E * l * l * l / T(6));
     mc.cfloor = T(2) * zeta_col * dsqrt(mc.m * mc.kv);
     return mc;
+}
+
+// Constants of cell c: the palette entry, or in parameter mode the entry
+// with the cell's own modulus and density.
+template <typename T>
+VX_HD MatConst<T> mat_at(const StepArgs<T> &a, long long c, uint8_t m) {
+    return a.E_cell ? mat_with(a.mats[m], a.E_cell[c], a.rho_cell[c], a.l, a.zeta_slow, a.zeta_col) : a.mats[m];
 }
 
 // Per-step environment of one voxel's update.

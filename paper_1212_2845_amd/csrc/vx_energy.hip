@@ -35,11 +35,6 @@ __device__ double bond_energy(const VoxKin<T> &A, const Rot<T> &R, const VoxKin<
 }
 
 template <typename T>
-__device__ __forceinline__ MatConst<T> mat_at(const StepArgs<T> &a, long long c, uint8_t m) {
-    return a.E_cell ? mat_with_E(a.mats[m], a.E_cell[c], a.l, a.zeta_slow, a.zeta_col) : a.mats[m];
-}
-
-template <typename T>
 __device__ __forceinline__ BondK<T> bond_at(const StepArgs<T> &a, long long c, long long cn, uint8_t ma, uint8_t mb,
                                             const MatConst<T> &A, const MatConst<T> &B, const LatK<T> &C) {
     return a.E_cell ? bond_k_from_E(a.E_cell[c], a.E_cell[cn], A.gfac, B.gfac, A.m < B.m ? A.m : B.m, a.zeta_bond, C)

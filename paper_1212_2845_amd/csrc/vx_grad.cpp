@@ -32,9 +32,10 @@ void grad_layout(const vx_sim *h, int64_t max_steps, int K, GradLayout &G) {
     G.lam[0] = take(sb);
     G.lam[1] = take(sb);
     G.gfm = take(6 * n * ts);
-    G.gloc = take(2 * n * ts);
+    G.gloc = take(3 * n * ts);
     G.rec = take(3ull * kAdjRecWords * n * ts);
     G.gE = take(n * 8);
+    G.grho = take(n * 8);
     G.gphase = take(n * 8);
     G.gamp = take(n * 8);
     G.total = off;
@@ -45,13 +46,14 @@ uint64_t flags_slot(const vx_sim *h) { return align_up((uint64_t)h->ncell); }
 uint64_t fm_slot(const vx_sim *h) { return align_up(6ull * h->ncell * h->tsize); }
 
 double voxel_mass_of(const vx_sim *h, long long c) {
-    return voxel_mass(h->pal[h->grid[c]], h->p.voxel_size);
+    const double l = h->p.voxel_size;
+    return h->has_rho ? h->rho_cell[c] * l * l * l : voxel_mass(h->pal[h->grid[c]], l);
 }
 
 template <typename T>
 int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const double *dL_dv, const double *dL_dw,
-                    double *g_E, double *g_phase, double *g_amp, double *g_u0, double *g_q0, double *g_v0,
-                    double *g_w0) {
+                    double *g_E, double *g_rho, double *g_phase, double *g_amp, double *g_u0, double *g_q0,
+                    double *g_v0, double *g_w0) {
     const GradLayout &G = h->GL;
     const long long n = h->ncell;
     const double l = h->p.voxel_size;
@@ -74,6 +76,7 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
     HIP_OK(h, hipMemcpyAsync(gw + G.lam[0], lam.data(), lam.size() * sizeof(T), hipMemcpyHostToDevice, s));
     HIP_OK(h, hipMemsetAsync(gw + G.lam[1], 0, lam.size() * sizeof(T), s));
     HIP_OK(h, hipMemsetAsync(gw + G.gE, 0, n * 8, s));
+    HIP_OK(h, hipMemsetAsync(gw + G.grho, 0, n * 8, s));
     HIP_OK(h, hipMemsetAsync(gw + G.gphase, 0, n * 8, s));
     HIP_OK(h, hipMemsetAsync(gw + G.gamp, 0, n * 8, s));
     int li = 0;
@@ -118,6 +121,7 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
             g.gloc = (T *)(gw + G.gloc);
             g.rec = (T *)(gw + G.rec);
             g.g_E = (double *)(gw + G.gE);
+            g.g_rho = (double *)(gw + G.grho);
             g.g_phase = (double *)(gw + G.gphase);
             g.g_amp = (double *)(gw + G.gamp);
             HIP_OK(h, launch_adjoint_step<T>(a, g, s));
@@ -125,8 +129,16 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
         }
     }
     HIP_OK(h, hipMemcpyAsync(lam.data(), gw + G.lam[li], lam.size() * sizeof(T), hipMemcpyDeviceToHost, s));
-    std::vector<double> gE(n), gp(n), ga(n);
+    // initial state (checkpoint 0) and final state, for the density's
+    // effect through the conversions between momenta and velocities: the
+    // initial velocities are held fixed (P0 = m v0) and the loss reads the
+    // final velocities (v = P / m)
+    std::vector<T> x0(lam.size()), xN(lam.size());
+    HIP_OK(h, hipMemcpyAsync(x0.data(), gw + G.ck_state, x0.size() * sizeof(T), hipMemcpyDeviceToHost, s));
+    HIP_OK(h, hipMemcpyAsync(xN.data(), h->ws + h->L.state[h->cur], xN.size() * sizeof(T), hipMemcpyDeviceToHost, s));
+    std::vector<double> gE(n), gr(n), gp(n), ga(n);
     HIP_OK(h, hipMemcpyAsync(gE.data(), gw + G.gE, n * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(h, hipMemcpyAsync(gr.data(), gw + G.grho, n * 8, hipMemcpyDeviceToHost, s));
     HIP_OK(h, hipMemcpyAsync(gp.data(), gw + G.gphase, n * 8, hipMemcpyDeviceToHost, s));
     HIP_OK(h, hipMemcpyAsync(ga.data(), gw + G.gamp, n * 8, hipMemcpyDeviceToHost, s));
     HIP_OK(h, hipStreamSynchronize(s));
@@ -137,6 +149,21 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
     for (long long c = 0; c < n; ++c) {
         const bool f = h->grid[c] != 0;
         if (g_E) g_E[c] = f ? gE[c] : 0.0;
+        if (g_rho) {
+            // P0 = m v0 and L0 = I w0 with m, I proportional to rho
+            double gi = 0.0;
+            if (f) {
+                const double m = voxel_mass_of(h, c), I = m * l * l / 6.0, rho = m / (l * l * l);
+                for (int k = 0; k < 3; ++k) {
+                    gi += (double)lam[(size_t)(W_PX + k) * n + c] * (double)x0[(size_t)(W_PX + k) * n + c] +
+                          (double)lam[(size_t)(W_LX + k) * n + c] * (double)x0[(size_t)(W_LX + k) * n + c];
+                    if (dL_dv) gi -= dL_dv[3 * c + k] * (double)xN[(size_t)(W_PX + k) * n + c] / m;
+                    if (dL_dw) gi -= dL_dw[3 * c + k] * (double)xN[(size_t)(W_LX + k) * n + c] / I;
+                }
+                gi /= rho;
+            }
+            g_rho[c] = f ? gr[c] + gi : 0.0;
+        }
         if (g_phase) g_phase[c] = f ? gp[c] : 0.0;
         if (g_amp) g_amp[c] = f ? ga[c] : 0.0;
         const double m = f ? voxel_mass_of(h, c) : 0.0, I = m * l * l / 6.0;
@@ -193,8 +220,8 @@ int vx_grad_forward(vx_handle h, int64_t n) {
     if (!h || n < 1) return VX_EINVAL;
     if (!h->gws) return fail(h, VX_ESTATE, "vx_grad_forward before vx_grad_bind");
     if (n > h->GL.max_steps) return fail(h, VX_EINVAL, "more steps than the gradient workspace was sized for");
-    if (!h->has_E) {
-        // parameter mode with the palette's moduli
+    if (!h->param_mode()) {
+        // parameter mode with the palette's moduli (and densities)
         std::vector<double> E(h->ncell, 0.0);
         for (long long c = 0; c < h->ncell; ++c)
             if (h->grid[c]) E[c] = h->pal[h->grid[c]].E;
@@ -216,14 +243,16 @@ int vx_grad_forward(vx_handle h, int64_t n) {
 }
 
 int vx_grad_backward(vx_handle h, const double *dL_du, const double *dL_dq, const double *dL_dv, const double *dL_dw,
-                     double *g_E, double *g_phase, double *g_amp, double *g_u0, double *g_q0, double *g_v0,
-                     double *g_w0) {
+                     double *g_E, double *g_rho, double *g_phase, double *g_amp, double *g_u0, double *g_q0,
+                     double *g_v0, double *g_w0) {
     if (!h) return VX_EINVAL;
     if (!h->tape_valid || h->step != h->tape_step0 + h->tape_n)
         return fail(h, VX_ESTATE, "no recorded rollout ends at the current state (vx_grad_forward first)");
     return h->precision == 64
-               ? grad_backward_t<double>(h, dL_du, dL_dq, dL_dv, dL_dw, g_E, g_phase, g_amp, g_u0, g_q0, g_v0, g_w0)
-               : grad_backward_t<float>(h, dL_du, dL_dq, dL_dv, dL_dw, g_E, g_phase, g_amp, g_u0, g_q0, g_v0, g_w0);
+               ? grad_backward_t<double>(h, dL_du, dL_dq, dL_dv, dL_dw, g_E, g_rho, g_phase, g_amp, g_u0, g_q0, g_v0,
+                                         g_w0)
+               : grad_backward_t<float>(h, dL_du, dL_dq, dL_dv, dL_dw, g_E, g_rho, g_phase, g_amp, g_u0, g_q0, g_v0,
+                                        g_w0);
 }
 
 }  // extern "C"

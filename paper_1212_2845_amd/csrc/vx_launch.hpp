@@ -13,7 +13,7 @@ hipError_t launch_split_step(const StepArgs<T> &a, hipStream_t s);
 // the forward step's arguments at t_n (s_in = x_n, flags at t_n, E_cell);
 // the adjoint buffers are laid out like the state (word k of cell c at
 // k * stride + c).
-constexpr int kAdjRecWords = 30;   // per-bond record: both ends' 14 adjoints, then the two moduli
+constexpr int kAdjRecWords = 32;   // per-bond record: both ends' 14 adjoints, two moduli, two masses
 
 template <typename T>
 struct AdjArgs {
@@ -21,9 +21,9 @@ struct AdjArgs {
     const T *lam_in;        // adjoint of x_n+1, 13 words
     T *lam_out;             // adjoint of x_n, 13 words
     T *gfm;                 // adjoint of the bond sums, 6 words
-    T *gloc;                // update's adjoints of the strain and of the modulus, 2 words
-    T *rec;                 // per-bond records, 3 axes x 30 words
-    double *g_E, *g_phase, *g_amp;   // accumulated over the reverse steps
+    T *gloc;                // update's adjoints of the strain, modulus and mass, 3 words
+    T *rec;                 // per-bond records, 3 axes x 32 words
+    double *g_E, *g_rho, *g_phase, *g_amp;   // accumulated over the reverse steps
 };
 
 template <typename T>

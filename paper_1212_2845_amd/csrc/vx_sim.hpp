@@ -23,7 +23,7 @@ inline uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign
 struct Layout {
     uint64_t state[2], mat, flags[2], mats, pairs, bonds, act_amp, act_phase, forced_cells, forced_F;
     uint64_t contact_F, surf_cells, cand, cand_n, keys, sorted, bstart, bfill, scalars, scan_tmp;
-    uint64_t E_cell;
+    uint64_t E_cell, rho_cell;
     uint64_t energy;
     uint64_t total;
 };
@@ -39,9 +39,9 @@ struct GradLayout {
     uint64_t fm;                 // K slots x 6 words x ncell: bond sums of each segment step
     uint64_t lam[2];             // adjoint state, 13 words x ncell each
     uint64_t gfm;                // adjoint of the bond sums, 6 words x ncell
-    uint64_t gloc;               // per-voxel adjoints of strain and modulus from the update, 2 x ncell
-    uint64_t rec;                // per-bond adjoint records, 3 axes x 30 words x ncell
-    uint64_t gE, gphase, gamp;   // FP64 accumulators, ncell each
+    uint64_t gloc;               // per-voxel adjoints of strain, modulus and mass from the update, 3 x ncell
+    uint64_t rec;                // per-bond adjoint records, 3 axes x kAdjRecWords x ncell
+    uint64_t gE, grho, gphase, gamp;   // FP64 accumulators, ncell each
     uint64_t total;
 };
 
@@ -97,9 +97,11 @@ struct vx_sim {
     bool flags_live = false;              // device flags hold dynamic bits
     int fused_shape = -1;                 // tile shape of the fused kernel (-1: heuristic)
     int fused_zc = 0;                     // z chunk of the fused kernel (0: heuristic)
-    // parameter mode: per-cell elastic modulus (split kernels)
-    bool has_E = false;
-    std::vector<double> E_cell;
+    // parameter mode (split kernels): per-cell elastic modulus and density;
+    // a quantity not set per cell takes its palette value
+    bool has_E = false, has_rho = false;
+    std::vector<double> E_cell, rho_cell;
+    bool param_mode() const { return has_E || has_rho; }
     double wmax = 0.0;                    // sqrt(k_b / m_min) the timestep was chosen for
     // differentiable rollouts
     char *gws = nullptr;
@@ -161,7 +163,8 @@ inline vx::StepArgs<T> make_args(vx_sim *h) {
     a.track_vmax = h->p.self_collision_on;
     a.contact_F = (const T *)(ws + h->L.contact_F);
     a.bonds = (T *)(ws + h->L.bonds);
-    a.E_cell = h->has_E ? (const T *)(ws + h->L.E_cell) : nullptr;
+    a.E_cell = h->param_mode() ? (const T *)(ws + h->L.E_cell) : nullptr;
+    a.rho_cell = h->param_mode() ? (const T *)(ws + h->L.rho_cell) : nullptr;
     a.fm_out = nullptr;
     a.zeta_bond = (T)h->p.zeta_bond;
     a.zeta_slow = (T)h->p.zeta_slow;

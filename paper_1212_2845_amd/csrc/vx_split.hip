@@ -29,7 +29,7 @@ __global__ void __launch_bounds__(256) k_bonds(StepArgs<T> a) {
     }
     const uint8_t mb = a.mat[cn];
     if (mb == 0) return;
-    const MatConst<T> A = a.mats[ma], B = a.mats[mb];
+    const MatConst<T> A = mat_at(a, c, ma), B = mat_at(a, cn, mb);
     const T ea = voxel_strain(a, (unsigned)c, a.flags[c], A.cte);
     const T eb = voxel_strain(a, (unsigned)cn, a.flags[cn], B.cte);
     const VoxKin<T> ka = load_kin(a.s_in, a.stride, (unsigned)c, A, ea);
@@ -75,8 +75,7 @@ __global__ void __launch_bounds__(256) k_gather(StepArgs<T> a) {
                     Mx += b[3 * st + c]; My += b[4 * st + c]; Mz += b[5 * st + c];
                 }
             }
-            MatConst<T> mc = a.mats[m];
-            if (a.E_cell) mc = mat_with_E(mc, a.E_cell[c], a.l, a.zeta_slow, a.zeta_col);
+            const MatConst<T> mc = mat_at(a, c, m);
             const uint8_t fl = a.flags[c];
             const T eps = voxel_strain(a, (unsigned)c, fl, mc.cte);
             if (a.fm_out) {

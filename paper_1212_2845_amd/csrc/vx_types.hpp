@@ -83,7 +83,8 @@ struct StepArgs {
     T *bonds;                  // split path: 3 axes x 9 words x ncell
     unsigned *err_flag;
     unsigned long long *vmax_bits;
-    const T *E_cell;           // per-cell elastic modulus (parameter mode), or null
+    const T *E_cell;           // parameter mode: per-cell elastic modulus, or null
+    const T *rho_cell;         // parameter mode: per-cell density (set whenever E_cell is)
     T *fm_out;                 // split gather: per-voxel bond force and moment sums (6 x ncell), or null
     T zeta_bond, zeta_slow, zeta_col;
 };

@@ -5,8 +5,9 @@ The loss is linear in the final state, L = sum(wu * u) + sum(wv * v) over
 the block voxels, so its gradient with respect to a parameter is the
 derivative of the oracle's trajectory map.  Each per-voxel modulus is a
 palette entry of its own in the workloads these helpers take
-(workloads.grad_object), so perturbing one voxel's modulus is perturbing
-one palette entry; the actuation phase is the oracle's per-voxel phase.
+(workloads.grad_object), so perturbing one voxel's modulus or density is
+perturbing one palette entry; the actuation phase is the oracle's per-voxel
+phase.
 """
 import numpy as np
 
@@ -24,14 +25,18 @@ def loss_weights(w, seed):
     return wu, wv
 
 
-def with_params(w, E_block=None, phase=None):
-    """Copy of workload w with the block moduli and/or phases replaced."""
+def with_params(w, E_block=None, phase=None, rho_block=None):
+    """Copy of workload w with the block moduli, densities and/or phases
+    replaced."""
     w2 = dict(w)
-    if E_block is not None:
+    if E_block is not None or rho_block is not None:
         mats = [dict(m) for m in w["materials"]]
         g = w["grid"].reshape(-1)
         for k, c in enumerate(w["block"]):
-            mats[g[c]]["E"] = float(E_block[k])
+            if E_block is not None:
+                mats[g[c]]["E"] = float(E_block[k])
+            if rho_block is not None:
+                mats[g[c]]["rho"] = float(rho_block[k])
         w2["materials"] = mats
     if phase is not None:
         w2["phase"] = phase
@@ -55,6 +60,15 @@ def fd_modulus(w, wu, wv, k, h=1e-4):
             oracle_loss(with_params(w, E_block=Em), wu, wv)) / (2.0 * h * E[k])
 
 
+def fd_density(w, wu, wv, k, h=1e-4):
+    """dL/drho of block voxel k, central difference with relative step h."""
+    r = w["rho_block"]
+    rp = r.copy(); rp[k] *= 1.0 + h
+    rm = r.copy(); rm[k] *= 1.0 - h
+    return (oracle_loss(with_params(w, rho_block=rp), wu, wv) -
+            oracle_loss(with_params(w, rho_block=rm), wu, wv)) / (2.0 * h * r[k])
+
+
 def fd_phase(w, wu, wv, c, h=1e-4):
     """dL/dphase of cell c, central difference with step h (radians)."""
     p = w["phase"]
@@ -64,10 +78,11 @@ def fd_phase(w, wu, wv, c, h=1e-4):
             oracle_loss(with_params(w, phase=pm), wu, wv)) / (2.0 * h)
 
 
-def fd_direction(w, wu, wv, dE, dphase, h=1e-4):
+def fd_direction(w, wu, wv, dE, dphase, drho=None, h=1e-4):
     """Directional derivative along (relative modulus change dE, phase
-    change dphase)."""
-    E = w["E_block"]; p = w["phase"]
-    wp = with_params(w, E_block=E * (1.0 + h * dE), phase=p + h * dphase)
-    wm = with_params(w, E_block=E * (1.0 - h * dE), phase=p - h * dphase)
+    change dphase, relative density change drho)."""
+    E = w["E_block"]; p = w["phase"]; r = w["rho_block"]
+    dr = np.zeros_like(r) if drho is None else drho
+    wp = with_params(w, E_block=E * (1.0 + h * dE), phase=p + h * dphase, rho_block=r * (1.0 + h * dr))
+    wm = with_params(w, E_block=E * (1.0 - h * dE), phase=p - h * dphase, rho_block=r * (1.0 - h * dr))
     return (oracle_loss(wp, wu, wv) - oracle_loss(wm, wu, wv)) / (2.0 * h)

@@ -192,18 +192,42 @@ def test_set_stiffness_validates_moduli():
         with pytest.raises(vx.VoxsimError) as e:
             s.set_stiffness(E2)
         assert e.value.code == vx.VX_EINVAL
+        rho = np.full(E.size, 1000.0); rho[w["block"][5]] = bad
+        with pytest.raises(vx.VoxsimError) as e:
+            s.set_density(rho)
+        assert e.value.code == vx.VX_EINVAL
 
 
-def test_set_stiffness_rejects_moduli_above_the_timestep_bound():
-    """The timestep is fixed at create from the stiffest bonded pair (here
-    the 4 MPa anchor); a block pair stiffer than that would be unstable."""
+def test_per_voxel_parameters_rejected_above_the_timestep_bound():
+    """The timestep is fixed at create from the fastest bonded pair (here
+    the 8 MPa, 1000 kg/m^3 anchor: k/m = 8e9 /s^2); block moduli or
+    densities that make a pair faster would be unstable."""
     w, s, E = _grad_obj()
-    E2 = E.copy(); E2[w["block"]] = 3.9e6
-    s.set_stiffness(E2)
-    E2[w["block"]] = 4.2e6
+    b = w["block"]
+    E2 = E.copy(); E2[b] = 3.9e6
+    rho = np.where(w["grid"].reshape(-1) > 0, 1000.0, 0.0)
+    s.set_density(rho)
+    s.set_stiffness(E2)                 # 3.9e9 /s^2
+    E2[b] = 8.2e6
     with pytest.raises(vx.VoxsimError) as e:
-        s.set_stiffness(E2)
+        s.set_stiffness(E2)             # 8.2e9 /s^2
     assert e.value.code == vx.VX_EINVAL
+    rho[b] = 480.0                      # 3.9e6 / 480e-9 = 8.1e9 /s^2
+    with pytest.raises(vx.VoxsimError) as e:
+        s.set_density(rho)
+    assert e.value.code == vx.VX_EINVAL
+    rho[b] = 520.0
+    s.set_density(rho)
+
+
+def test_per_voxel_parameters_need_self_collision_off():
+    g = np.ones((3, 3, 3), np.uint8)
+    rc, h = _create(g, [workloads.EMPTY, M1], 64, **workloads._base_params(self_collision_on=1))
+    assert rc == vx.VX_OK
+    E = np.full(27, 1e6)
+    assert vx.lib().vx_set_stiffness(h, E.ctypes.data_as(C.c_void_p)) == vx.VX_ESTATE
+    assert vx.lib().vx_set_density(h, E.ctypes.data_as(C.c_void_p)) == vx.VX_ESTATE
+    vx.lib().vx_destroy(h)
 
 
 def test_grad_calls_need_their_state():
@@ -213,7 +237,7 @@ def test_grad_calls_need_their_state():
     assert L.vx_grad_bind(s.h, None, 0, 10, 2) == vx.VX_ESTATE
     # forward without a gradient workspace, backward without a recorded run
     assert L.vx_grad_forward(s.h, 5) == vx.VX_ESTATE
-    assert L.vx_grad_backward(s.h, *([None] * 11)) == vx.VX_ESTATE
+    assert L.vx_grad_backward(s.h, *([None] * 12)) == vx.VX_ESTATE
     assert L.vx_grad_forward(s.h, 0) == vx.VX_EINVAL
 
 

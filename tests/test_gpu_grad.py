@@ -14,7 +14,7 @@ import pytest
 
 import paper_1212_2845_amd as vx
 import workloads
-from gradcheck import fd_direction, fd_modulus, fd_phase, loss_weights, oracle_loss
+from gradcheck import fd_density, fd_direction, fd_modulus, fd_phase, loss_weights, oracle_loss
 from parity import build_oracle, compare
 
 pytestmark = pytest.mark.gpu
@@ -26,14 +26,17 @@ def announce(msg):
     print("[case] " + msg, flush=True)
 
 
-def gpu_sim(w, precision=64):
-    s = vx.from_workload(w, precision=precision)
-    E = np.zeros(w["grid"].size)
+def palette_field(w, key):
     g = w["grid"].reshape(-1)
-    for c in range(E.size):
-        if g[c]:
-            E[c] = w["materials"][g[c]]["E"]
-    s.set_stiffness(E)
+    return np.array([w["materials"][m][key] if m else 0.0 for m in g])
+
+
+def gpu_sim(w, precision=64):
+    """Parameter mode: the palette's per-voxel moduli and densities given
+    as per-cell arrays."""
+    s = vx.from_workload(w, precision=precision)
+    s.set_stiffness(palette_field(w, "E"))
+    s.set_density(palette_field(w, "rho"))
     return s
 
 
@@ -65,45 +68,72 @@ def test_parameter_mode_forward_matches_oracle(scenario):
     assert max(e["u"], e["v"], e["w"]) < 1e-10 and e["q"] < 1e-12, e
 
 
+def smooth_fd(f, w, wu, wv, keys):
+    """Central differences at h = 1e-4 and 1e-6 for each coordinate.  Where
+    the two disagree, a friction or contact event lies inside the
+    difference interval (the trajectory map has a kink or jump there) and
+    the coordinate has no usable expected value; elsewhere the 1e-6 value
+    is the derivative."""
+    a = np.array([f(w, wu, wv, k, h=1e-4) for k in keys])
+    c = np.array([f(w, wu, wv, k, h=1e-6) for k in keys])
+    scale = max(np.abs(c).max(), 1e-300)
+    return c, np.abs(a - c) <= 1e-5 * scale, scale
+
+
 @pytest.mark.parametrize("scenario", SCENARIOS)
 def test_gradient_matches_oracle_fd_every_coordinate(scenario):
-    """dL/dE and dL/dphase of every block voxel vs central differences of
-    the oracle (h = 1e-4), FP64; error over the largest gradient entry."""
+    """dL/dE, dL/drho and dL/dphase of every block voxel vs central
+    differences of the oracle, FP64, on the coordinates where the
+    trajectory map is smooth (at least 90% of them); error over the largest
+    gradient entry of each."""
     w = workloads.grad_object(seed=11, scenario=scenario)
     wu, wv = loss_weights(w, seed=12)
     announce("fd every coordinate %s" % scenario)
     g, L = gpu_grad(w, wu, wv)
     assert abs(L / oracle_loss(w, wu, wv) - 1) < 1e-10
     b = w["block"]
-    fdE = np.array([fd_modulus(w, wu, wv, k) for k in range(b.size)])
-    fdP = np.array([fd_phase(w, wu, wv, c) for c in b])
-    eE, eP = norm_err(g["E"][b], fdE), norm_err(g["phase"][b], fdP)
-    print("[grad] %s E err %.3e phase err %.3e" % (scenario, eE, eP), flush=True)
-    assert eE < 1e-4 and eP < 1e-4, (eE, eP)
+    idx = np.arange(b.size)
+    for name, f, keys, an in (("E", fd_modulus, idx, g["E"][b]), ("rho", fd_density, idx, g["rho"][b]),
+                              ("phase", fd_phase, b, g["phase"][b])):
+        fd, ok, scale = smooth_fd(f, w, wu, wv, keys)
+        err = np.abs(an[ok] - fd[ok]).max() / scale
+        print("[grad] %s %s err %.3e on %d of %d coordinates" % (scenario, name, err, ok.sum(), ok.size),
+              flush=True)
+        assert ok.mean() >= 0.9, (name, ok.sum())
+        assert err < 1e-4, (name, err)
 
 
 @pytest.mark.parametrize("scenario", SCENARIOS)
 def test_gradient_matches_oracle_fd_directions(scenario):
     """Directional derivatives along 8 random joint directions in (relative
-    modulus, phase), normalised by |g| |d|.  Step h = 1e-5: perturbing all
-    128 parameters at once by 1e-4 can move a resting voxel across the
-    static-friction threshold inside the difference interval (a kink of
-    the trajectory map), which 1e-5 avoids on these seeds."""
+    modulus, relative density, phase), normalised by |g| |d|, with central
+    differences at h = 1e-5 and 1e-7; a direction along which the two
+    disagree crosses a friction or contact event inside the interval and
+    is skipped (at most 2 of 8)."""
     w = workloads.grad_object(seed=21, scenario=scenario)
     wu, wv = loss_weights(w, seed=22)
     announce("fd directions %s" % scenario)
     g, _ = gpu_grad(w, wu, wv, K=33)
     b = w["block"]
     rng = np.random.Generator(np.random.PCG64(23))
+    used = 0
     for i in range(8):
         dE = rng.normal(size=b.size)
+        dr = rng.normal(size=b.size)
         dp = np.zeros(w["grid"].size); dp[b] = rng.normal(size=b.size)
-        gvec = np.concatenate([g["E"][b] * w["E_block"], g["phase"][b]])
-        dvec = np.concatenate([dE, dp[b]])
+        gvec = np.concatenate([g["E"][b] * w["E_block"], g["rho"][b] * w["rho_block"], g["phase"][b]])
+        dvec = np.concatenate([dE, dr, dp[b]])
+        norm = np.linalg.norm(gvec) * np.linalg.norm(dvec)
         an = float(gvec @ dvec)
-        fd = fd_direction(w, wu, wv, dE, dp, h=1e-5)
-        err = abs(an - fd) / (np.linalg.norm(gvec) * np.linalg.norm(dvec))
-        assert err < 1e-5, (i, an, fd, err)
+        fd = fd_direction(w, wu, wv, dE, dp, drho=dr, h=1e-5)
+        fd2 = fd_direction(w, wu, wv, dE, dp, drho=dr, h=1e-7)
+        if abs(fd - fd2) > 1e-6 * norm:
+            continue
+        used += 1
+        err = abs(an - fd2) / norm
+        assert err < 1e-5, (i, an, fd2, err)
+    print("[grad] %s directions used %d of 8" % (scenario, used), flush=True)
+    assert used >= 6
 
 
 def test_gradient_of_initial_state_matches_oracle_fd():
@@ -137,7 +167,7 @@ def test_checkpoint_interval_does_not_change_gradients(precision):
     ref, _ = gpu_grad(w, wu, wv, precision, K=60)
     for K in (1, 7, 100):
         g, _ = gpu_grad(w, wu, wv, precision, K=K)
-        for k in ("E", "phase", "u0", "v0"):
+        for k in ("E", "rho", "phase", "u0", "v0"):
             assert np.array_equal(g[k], ref[k]), (K, k)
 
 
@@ -149,8 +179,9 @@ def test_fp32_gradient_close_to_fp64():
     g32, _ = gpu_grad(w, wu, wv, 32)
     b = w["block"]
     eE, eP = norm_err(g32["E"][b], g64["E"][b]), norm_err(g32["phase"][b], g64["phase"][b])
-    print("[grad] fp32 vs fp64 E %.3e phase %.3e" % (eE, eP), flush=True)
-    assert eE < 1e-3 and eP < 1e-3, (eE, eP)
+    eR = norm_err(g32["rho"][b], g64["rho"][b])
+    print("[grad] fp32 vs fp64 E %.3e phase %.3e rho %.3e" % (eE, eP, eR), flush=True)
+    assert eE < 1e-3 and eP < 1e-3 and eR < 1e-3, (eE, eP, eR)
 
 
 def test_rollout_autograd_function():
@@ -162,16 +193,16 @@ def test_rollout_autograd_function():
     s = gpu_sim(w)
     s.grad_bind(w["steps"], 16)
     E0 = s  # keep the Sim alive
-    g = w["grid"].reshape(-1)
-    E = torch.tensor([w["materials"][g[c]]["E"] if g[c] else 0.0 for c in range(g.size)],
-                     dtype=torch.float64, requires_grad=True)
+    E = torch.tensor(palette_field(w, "E"), dtype=torch.float64, requires_grad=True)
+    rho = torch.tensor(palette_field(w, "rho"), dtype=torch.float64, requires_grad=True)
     ph = torch.tensor(w["phase"], dtype=torch.float64, requires_grad=True)
-    u, v = vx.rollout(s, E, ph, w["amp"], w["steps"])
+    u, v = vx.rollout(s, E, rho, ph, w["amp"], w["steps"])
     L = (torch.from_numpy(wu) * u).sum() + (torch.from_numpy(wv) * v).sum()
     L.backward()
     ref, _ = gpu_grad(w, wu, wv)
     b = w["block"]
     assert np.allclose(E.grad.numpy()[b], ref["E"][b], rtol=1e-12, atol=0)
+    assert np.allclose(rho.grad.numpy()[b], ref["rho"][b], rtol=1e-12, atol=0)
     assert np.allclose(ph.grad.numpy()[b], ref["phase"][b], rtol=1e-12, atol=0)
     del E0
 

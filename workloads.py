@@ -159,11 +159,13 @@ def random_state(ncell, seed, u_scale, v_scale, w_scale, rot_scale):
 
 def grad_object(seed, n=4, scenario="free", steps=200, temp_freq=500.0):
     """Small object for gradient checks: an n^3 block in which every voxel
-    has its own palette entry (modulus log-uniform in [0.5, 2] MPa, CTE
-    0.01), a per-voxel actuation signal (20 K, phase U[0, 2 pi)), and a
-    detached two-voxel anchor of a 4 MPa material one empty cell beyond
-    +x.  The anchor's bond is the stiffest, so it alone sets the timestep:
-    perturbing any block modulus leaves dt unchanged.
+    has its own palette entry (modulus log-uniform in [0.5, 2] MPa, density
+    log-uniform in [500, 2000] kg/m^3, CTE 0.01), a per-voxel actuation
+    signal (20 K, phase U[0, 2 pi)), and a detached two-voxel anchor of an
+    8 MPa, 1000 kg/m^3 material one empty cell beyond +x.  The anchor's bond
+    is the fastest (k/m = 8e9 /s^2 against at most 4e9 in the block), so it
+    alone sets the timestep: perturbing any block modulus or density leaves
+    dt unchanged.
 
     scenario "free":  no gravity or floor; random initial velocities and
                       spins; two fixed and two forced block voxels; bond
@@ -175,22 +177,24 @@ def grad_object(seed, n=4, scenario="free", steps=200, temp_freq=500.0):
                       friction branches).
 
     Returns a workload plus ``block`` (cell indices of the block voxels,
-    ascending) and ``E_block`` (their moduli, in that order)."""
+    ascending), ``E_block`` and ``rho_block`` (their moduli and densities,
+    in that order)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     nx, ny, nz = n + 3, n, n
     grid = np.zeros((nz, ny, nx), np.uint8)
     block = []
     mats = [EMPTY]
     E_block = np.exp(rng.uniform(np.log(0.5e6), np.log(2e6), size=n ** 3))
+    rho_block = np.exp(rng.uniform(np.log(500.0), np.log(2000.0), size=n ** 3))
     k = 0
     for z in range(nz):
         for y in range(ny):
             for x in range(n):
-                mats.append(_mat(E_block[k], cte=0.01))
+                mats.append(_mat(E_block[k], rho=rho_block[k], cte=0.01))
                 grid[z, y, x] = len(mats) - 1
                 block.append(x + nx * (y + ny * z))
                 k += 1
-    mats.append(_mat(4e6))
+    mats.append(_mat(8e6))
     grid[0, 0, n + 1] = grid[0, 0, n + 2] = len(mats) - 1
     block = np.array(block)
     ncell = grid.size
@@ -217,6 +221,7 @@ def grad_object(seed, n=4, scenario="free", steps=200, temp_freq=500.0):
                   amp=amp, phase=phase, name="grad_object_%s_%d" % (scenario, n))
     w["block"] = block
     w["E_block"] = E_block
+    w["rho_block"] = rho_block
     return w
 
 
