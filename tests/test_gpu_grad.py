@@ -136,6 +136,38 @@ def test_gradient_matches_oracle_fd_directions(scenario):
     assert used >= 6
 
 
+@pytest.mark.parametrize("scenario", SCENARIOS)
+def test_gradient_matches_fp64_reverse_mode_reference(scenario):
+    """Every coordinate of dL/dE, dL/drho, dL/dphase and dL/damp, FP64,
+    against reverse mode of the torch reference (oracle/torch_ref.py, itself
+    pinned to the C oracle).  Both take the derivative on the branches the
+    run takes, so this covers the coordinates where central differences
+    straddle a friction event too.  Error over each gradient's largest
+    entry."""
+    import torch
+    from oracle import torch_ref
+    w = workloads.grad_object(seed=11, scenario=scenario)
+    wu, wv = loss_weights(w, seed=12)
+    announce("reverse-mode reference %s" % scenario)
+    g, _ = gpu_grad(w, wu, wv)
+    lat = torch_ref.Lattice(w)
+    E = lat.E0.clone().requires_grad_(True)
+    rho = lat.rho0.clone().requires_grad_(True)
+    ph = lat.phase0.clone().requires_grad_(True)
+    amp = lat.amp0.clone().requires_grad_(True)
+    u, q, v, om = torch_ref.rollout(lat, w, w["steps"], E=E, rho=rho, phase=ph, amp=amp)
+    c = lat.cells
+    L = (torch.from_numpy(wu[c]) * u).sum() + (torch.from_numpy(wv[c]) * v).sum()
+    L.backward()
+    b = w["block"]
+    pos = {cc: k for k, cc in enumerate(c)}
+    blk = np.array([pos[cc] for cc in b])
+    for name, ref in (("E", E.grad), ("rho", rho.grad), ("phase", ph.grad), ("amp", amp.grad)):
+        err = norm_err(g[name][b], ref.numpy()[blk])
+        print("[grad] %s vs reference %s err %.3e" % (scenario, name, err), flush=True)
+        assert err < 1e-11, (name, err)
+
+
 def test_gradient_of_initial_state_matches_oracle_fd():
     """dL/d(initial velocity) of a few voxels vs central differences."""
     w = workloads.grad_object(seed=31, scenario="free")

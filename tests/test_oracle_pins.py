@@ -614,3 +614,63 @@ def test_fd_harness_phase_derivative_of_thermal_stretch():
     # damping time over the signal period (~1e-4 here)
     exact = l * cte * A * np.cos(2 * np.pi * 0.5 * t + ph0[1]) / 2
     assert abs(fd / exact - 1) < 1e-3, (fd, exact)
+
+
+# --- the differentiable FP64 reference (oracle/torch_ref.py) ---------------
+
+def _ref_loss(lat, w, wu, wv, **params):
+    import torch
+    from oracle import torch_ref
+    u, q, v, om = torch_ref.rollout(lat, w, w["steps"], **params)
+    c = lat.cells
+    return (torch.from_numpy(wu[c]) * u).sum() + (torch.from_numpy(wv[c]) * v).sum()
+
+
+@pytest.mark.parametrize("scenario", ["free", "slide", "rest"])
+def test_torch_reference_trajectory_matches_c_oracle(scenario):
+    """The torch reference steps the same method as the C oracle: same dt,
+    final displacement, velocity and orientation to 1e-10 relative."""
+    from oracle import torch_ref
+    from parity import build_oracle, compare
+    w = workloads.grad_object(seed=5, scenario=scenario, steps=150)
+    lat = torch_ref.Lattice(w)
+    o = build_oracle(w)
+    assert abs(lat.dt / o.dt - 1) < 1e-15
+    assert o.step(w["steps"]) == 0
+    u, q, v, om = torch_ref.rollout(lat, w, w["steps"])
+    n = w["grid"].size
+    ref = {"u": torch_ref.scatter(lat, u, n), "q": torch_ref.scatter(lat, q, n),
+           "v": torch_ref.scatter(lat, v, n), "w": torch_ref.scatter(lat, om, n)}
+    e = compare(ref, o.read_state(), w["grid"].reshape(-1) > 0)
+    assert max(e["u"], e["v"], e["w"]) < 1e-10 and e["q"] < 1e-12, e
+
+
+@pytest.mark.parametrize("scenario", ["free", "rest"])
+def test_torch_reference_gradients_match_c_oracle_differences(scenario):
+    """Reverse mode of the torch reference against central differences of
+    the C oracle for every modulus, density and phase of the block, on the
+    coordinates where the differences at h = 1e-4 and 1e-6 agree."""
+    import torch
+    from oracle import torch_ref
+    from gradcheck import fd_density, fd_modulus, fd_phase, loss_weights
+    w = workloads.grad_object(seed=11, scenario=scenario, steps=120)
+    wu, wv = loss_weights(w, seed=12)
+    lat = torch_ref.Lattice(w)
+    E = lat.E0.clone().requires_grad_(True)
+    rho = lat.rho0.clone().requires_grad_(True)
+    ph = lat.phase0.clone().requires_grad_(True)
+    L = _ref_loss(lat, w, wu, wv, E=E, rho=rho, phase=ph)
+    L.backward()
+    b = w["block"]
+    pos = {c: k for k, c in enumerate(lat.cells)}
+    blk = np.array([pos[c] for c in b])
+    for name, f, keys, an in (("E", fd_modulus, range(b.size), E.grad.numpy()[blk]),
+                              ("rho", fd_density, range(b.size), rho.grad.numpy()[blk]),
+                              ("phase", fd_phase, b, ph.grad.numpy()[blk])):
+        a = np.array([f(w, wu, wv, k, h=1e-4) for k in keys])
+        c = np.array([f(w, wu, wv, k, h=1e-6) for k in keys])
+        scale = np.abs(c).max()
+        ok = np.abs(a - c) <= 1e-5 * scale
+        assert ok.mean() >= 0.9, (name, ok.sum())
+        err = np.abs(an[ok] - c[ok]).max() / scale
+        assert err < 1e-6, (name, err)
