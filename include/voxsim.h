@@ -250,9 +250,9 @@ int vx_set_density(vx_handle h, const double *rho);
 
 /* Bytes of the gradient workspace for rollouts of up to max_steps steps
  * with a checkpoint every K steps: ceil(max_steps/K) checkpoints plus a
- * K-step recompute buffer, adjoint state and per-bond adjoint records
+ * K-step recompute buffer, adjoint state and per-voxel adjoint terms
  * (about (ceil(max_steps/K) + K) x (13 words + 1 byte) + K x 6 words +
- * 128 words per cell). */
+ * 35 words + 4 FP64 words per cell). */
 int vx_grad_workspace_bytes(vx_handle h, int64_t max_steps, int32_t K, uint64_t *bytes);
 
 /* Bind a caller-owned, 256-byte aligned device buffer of at least

@@ -33,7 +33,6 @@ void grad_layout(const vx_sim *h, int64_t max_steps, int K, GradLayout &G) {
     G.lam[1] = take(sb);
     G.gfm = take(6 * n * ts);
     G.gloc = take(3 * n * ts);
-    G.rec = take(3ull * kAdjRecWords * n * ts);
     G.gE = take(n * 8);
     G.grho = take(n * 8);
     G.gphase = take(n * 8);
@@ -119,7 +118,6 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
             g.lam_out = (T *)(gw + G.lam[1 - li]);
             g.gfm = (T *)(gw + G.gfm);
             g.gloc = (T *)(gw + G.gloc);
-            g.rec = (T *)(gw + G.rec);
             g.g_E = (double *)(gw + G.gE);
             g.g_rho = (double *)(gw + G.grho);
             g.g_phase = (double *)(gw + G.gphase);

@@ -13,8 +13,6 @@ hipError_t launch_split_step(const StepArgs<T> &a, hipStream_t s);
 // the forward step's arguments at t_n (s_in = x_n, flags at t_n, E_cell);
 // the adjoint buffers are laid out like the state (word k of cell c at
 // k * stride + c).
-constexpr int kAdjRecWords = 32;   // per-bond record: both ends' 14 adjoints, two moduli, two masses
-
 template <typename T>
 struct AdjArgs {
     const T *fm;            // bond force and moment sums at x_n, 6 words
@@ -22,12 +20,15 @@ struct AdjArgs {
     T *lam_out;             // adjoint of x_n, 13 words
     T *gfm;                 // adjoint of the bond sums, 6 words
     T *gloc;                // update's adjoints of the strain, modulus and mass, 3 words
-    T *rec;                 // per-bond records, 3 axes x 32 words
     double *g_E, *g_rho, *g_phase, *g_amp;   // accumulated over the reverse steps
 };
 
 template <typename T>
 hipError_t launch_adjoint_step(const StepArgs<T> &a, const AdjArgs<T> &g, hipStream_t s);
+// Bond pass and gather of the reverse step in one LDS-tiled launch (after
+// the per-voxel update VJP); no per-bond records.
+template <typename T>
+hipError_t launch_adjoint_fused(const StepArgs<T> &a, const AdjArgs<T> &g, hipStream_t s);
 
 // Energies and momenta of the current state (a.s_in): kEnergyWords FP64
 // partial sums per workgroup of energy_blocks(ncell) workgroups.

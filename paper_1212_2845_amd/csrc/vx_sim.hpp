@@ -40,7 +40,6 @@ struct GradLayout {
     uint64_t lam[2];             // adjoint state, 13 words x ncell each
     uint64_t gfm;                // adjoint of the bond sums, 6 words x ncell
     uint64_t gloc;               // per-voxel adjoints of strain, modulus and mass from the update, 3 x ncell
-    uint64_t rec;                // per-bond adjoint records, 3 axes x kAdjRecWords x ncell
     uint64_t gE, grho, gphase, gamp;   // FP64 accumulators, ncell each
     uint64_t total;
 };

@@ -250,9 +250,9 @@ def test_grad_workspace_size_grows_with_checkpoints_and_segment():
         return n.value
     ncell = w["grid"].size
     # per cell: checkpoints and segment slots of 13 FP64 words + 1 flag byte,
-    # 6-word bond sums per segment slot, 2 x 13 adjoint words, 6 + 2 words,
-    # 90 record words, 3 FP64 accumulators
-    per_cell = lambda nck, K: (nck + K) * (13 * 8 + 1) + K * 48 + 26 * 8 + 8 * 8 + 90 * 8 + 24
+    # 6-word bond sums per segment slot, 2 x 13 adjoint words, 6 + 3 words,
+    # 4 FP64 accumulators
+    per_cell = lambda nck, K: (nck + K) * (13 * 8 + 1) + K * 48 + 26 * 8 + 9 * 8 + 32
     for steps, K in ((100, 10), (100, 7), (5000, 100)):
         nck = -(-steps // K)
         assert nbytes(steps, K) >= per_cell(nck, K) * ncell

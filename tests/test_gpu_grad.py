@@ -243,8 +243,12 @@ def test_design_lattice_gradient_full_size():
     """The 64 x 20^3 design lattice (5000 steps, FP32, checkpoint every 100
     steps, the bench's configuration), loss = mean x displacement.  The
     blocks share no bond, so each block's gradients must equal those of the
-    same block run alone (same per-voxel arithmetic, so bitwise); the small
-    runs are the regime the oracle comparisons above cover.  Central
+    same block run alone; the small runs are the regime the oracle
+    comparisons above cover.  The forward is bitwise the same; the reverse
+    bond pass evaluates a bond that crosses a tile edge in a second inlined
+    copy of the same code, which the compiler may contract differently, and
+    the block sits on other tile edges in the lattice than alone, so the
+    bar is FP32 rounding (1e-5 of each gradient's largest entry).  Central
     differences are no check at this size: with half a million voxels on
     a floor, some voxel always sits at the static-friction threshold, where
     the step zeroes its lateral momentum, so the loss jumps inside any
@@ -275,6 +279,8 @@ def test_design_lattice_gradient_full_size():
         sb.grad_bind(n, 100)
         sb.grad_forward(n)
         gb = sb.grad_backward(dL_du=wu[cells])
-        for k in ("E", "phase", "amp"):
-            assert np.array_equal(gb[k], g[k][cells]), (i, j, k)
-        assert np.array_equal(gb["u0"], g["u0"][cells]) and np.array_equal(gb["v0"], g["v0"][cells])
+        for k in ("E", "rho", "phase", "amp", "u0", "v0"):
+            scale = np.abs(g[k][cells]).max()
+            err = np.abs(gb[k] - g[k][cells]).max() / scale if scale > 0 else np.abs(gb[k]).max()
+            print("[grad] block (%d, %d) %s alone vs in lattice %.3e" % (i, j, k, err), flush=True)
+            assert err < 1e-5, (i, j, k, err)
