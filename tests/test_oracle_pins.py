@@ -562,6 +562,53 @@ def test_mirror_symmetry_is_exact_to_second_order():
     assert 1.7 < res[0] / res[1] < 2.3, res
 
 
+def _checkerboard_amplitudes(zeta, steps, marks, n=24):
+    """24^3 block, no gravity or floor, 1e-9 m/s velocity noise: projection
+    of the velocities on the checkerboard pattern (-1)^(x+y+z) at the given
+    step counts."""
+    w = workloads.solid_cube(n, zeta_bond=zeta)
+    o = oracle.Sim(w["grid"], w["materials"], **w["params"])
+    rng = np.random.Generator(np.random.PCG64(1))
+    o.set_velocity(rng.normal(0.0, 1e-9, size=(w["grid"].size, 3)))
+    x, y, z = workloads.cell_coords(w["grid"].shape)
+    sgn = ((-1.0) ** (x + y + z))[:, None]
+    out, done = {}, 0
+    for m in sorted(marks):
+        assert o.step(m - done) == 0
+        done = m
+        out[m] = float((sgn * o.read_state()["v"]).sum())
+    return out
+
+
+def test_bond_damping_stability_bound():
+    """Symplectic Euler with explicit bond damping on the highest
+    (checkerboard) mode of a homogeneous block: per voxel, 4 axial and 8
+    shear bond stiffnesses give k = 12 a1 and 6 dampers c = 6 c_t, so with
+    the timestep of Eq. 31 a = k dt^2/m = 12/(4 pi^2) and b = c dt/m =
+    12 zeta/(2 pi), and the step's factor is a root of
+    lambda^2 - (2 - a - b) lambda + (1 - b).  At zeta = 1 that root is about
+    -1.067: the mode must grow with alternating sign at that rate (within
+    2%); at zeta = 0.9 (|lambda| = 0.86) nothing grows."""
+    a = 12.0 / (4 * np.pi ** 2)
+    b = 12.0 * 1.0 / (2 * np.pi)
+    roots = np.roots([1.0, -(2 - a - b), 1 - b])
+    lam = roots[np.argmax(np.abs(roots))]
+    amp = _checkerboard_amplitudes(1.0, 300, [250, 251, 300])
+    rate = abs(amp[300] / amp[250]) ** (1.0 / 50)
+    assert abs(rate / abs(lam) - 1) < 0.02, (rate, lam)
+    assert amp[251] / amp[250] < 0          # alternating sign, as lambda < 0
+    # zeta = 0.9: every mode decays, so the largest voxel speed falls
+    w = workloads.solid_cube(24, zeta_bond=0.9)
+    o = oracle.Sim(w["grid"], w["materials"], **w["params"])
+    rng = np.random.Generator(np.random.PCG64(1))
+    o.set_velocity(rng.normal(0.0, 1e-9, size=(w["grid"].size, 3)))
+    assert o.step(50) == 0
+    v50 = np.abs(o.read_state()["v"]).max()
+    assert o.step(250) == 0
+    v300 = np.abs(o.read_state()["v"]).max()
+    assert v300 < 0.5 * v50, (v50, v300)
+
+
 # --- pins of the finite-difference gradient harness (expected values of the
 # adjoint tests) ------------------------------------------------------------
 
