@@ -53,6 +53,25 @@ def hetero_block(shape=(5, 6, 7), seed=41, fill=0.85, act=True):
     return w
 
 
+def test_cantilever_c1_full_run_fp64():
+    """C1 as specified: 10,000 steps FP64 (fused kernel); displacement,
+    orientation, tip deflection and the elastic and gravitational energies
+    of the final state equal the oracle's.  (By then the beam has settled:
+    velocities are ~1e-7 of their peak, so they are compared in the
+    1000-step test above rather than relative to their own final size.)"""
+    w = workloads.cantilever(steps=10000)
+    announce("cantilever_20x4x4 fp64 10000 steps")
+    g, o = run_pair(w, 10000, 64, vx.KERNEL_FUSED)
+    e = compare(g.read_state(), o.read_state(), filled_of(w))
+    assert e["u"] < FP64_TOL and e["q"] < 1e-12, e
+    x, _, _ = workloads.cell_coords(w["grid"].shape)
+    ug, uo = g.read_state()["u"], o.read_state()["u"]
+    assert abs(ug[x == 19, 2].mean() / uo[x == 19, 2].mean() - 1) < 1e-10
+    eg, eo = g.energy(), o.energy()
+    for kg, ko in (("elastic", "elastic"), ("gravity", "gravity")):
+        assert abs(eg[kg] - eo[ko]) <= 1e-8 * max(abs(eo[ko]), 1e-300), (kg, eg[kg], eo[ko])
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_cantilever_fp64(kernel):
     w = workloads.cantilever(steps=1000)

@@ -155,6 +155,33 @@ def test_thick_beam_nonlinear_near_table1():
     assert abs(tip / t["thick"]["mass_spring"] - 1.0) < 0.02
 
 
+def test_gravity_cantilever_c1_matches_linear_solve_and_euler_bernoulli():
+    """C1: the 20x4x4 cantilever (1 MPa, nu 0.35, rho 1000, x = 0 layer
+    fixed) under its own weight, light damping, 10,000 steps.  The tip
+    (mean z displacement of the x = 19 layer) equals the linear direct-
+    stiffness solve of the same lattice and load to 1e-4 (the residue is the
+    geometric nonlinearity of a 0.13 mm deflection and the last of the
+    transient), and exceeds Euler-Bernoulli with lumped nodal loads,
+    sum_k W x_k^2 (3L - x_k) / 6EI with W = 16 m g, x_k = k l, L = 19 l
+    (0.1284 mm), by the lattice's shear compliance, a few per cent."""
+    w = workloads.cantilever(steps=10000)
+    o = oracle.Sim(w["grid"], w["materials"], **w["params"])
+    o.set_fixed(w["fixed"])
+    assert o.step(10000) == 0
+    u = o.read_state()["u"]
+    x, _, _ = workloads.cell_coords(w["grid"].shape)
+    tip = -u[x == 19, 2].mean()
+    m = w["materials"][1]["rho"] * L_VOX ** 3
+    F = np.zeros((w["grid"].size, 3)); F[:, 2] = -m * 9.81
+    U, _ = ds_solve.solve(w["grid"], w["materials"], L_VOX, w["fixed"], F)
+    assert abs(tip / -U[x == 19, 2].mean() - 1) < 1e-4
+    I = (4 * L_VOX) ** 4 / 12.0
+    L = 19 * L_VOX
+    eb = sum(16 * m * 9.81 * (k * L_VOX) ** 2 * (3 * L - k * L_VOX) / (6 * E1 * I) for k in range(1, 20))
+    assert abs(eb - 1.2838e-4) < 1e-8
+    assert 1.0 < tip / eb < 1.06
+
+
 # --------------------------------------------------------------------------
 # P6: axial stretch, exact in the nonlinear model; composite modulus (Eq. 1)
 # --------------------------------------------------------------------------
