@@ -151,6 +151,13 @@ def time_batch(count, steps, one_by_one_sample=64, one_by_one_steps=100):
     ms = e0.elapsed_time(e1)
     del b
     torch.cuda.empty_cache()
+    batched = nvox * steps / (ms / 1e3)
+    result = {"workload": "batch_objects_%d" % count, "objects": count, "voxels": nvox, "steps": steps,
+              "dtype": "f32", "value": batched, "ms": ms, "workgroups": n_wg,
+              "roofline": dict(roofline(32, nvox, ms / steps, kernel="k_batch"),
+                               note="kernel_ms is per step: one persistent launch runs all steps")}
+    if one_by_one_sample <= 0:
+        return result
     # one at a time: a sample of the same objects, each its own lattice,
     # every object's steps recorded into one HIP graph (stream capture of
     # vx_step_enqueue) and replayed, so that launch overhead is not counted
@@ -187,19 +194,15 @@ def time_batch(count, steps, one_by_one_sample=64, one_by_one_steps=100):
     el = time.perf_counter() - t0
     del graph, sims
     torch.cuda.empty_cache()
-    batched = nvox * steps / (ms / 1e3)
     single = nvox1 * one_by_one_steps / (ms1 / 1e3)
     single_eager = nvox1 * one_by_one_steps / el
-    return {"workload": "batch_objects_%d" % count, "objects": count, "voxels": nvox, "steps": steps,
-            "dtype": "f32", "value": batched, "ms": ms, "workgroups": n_wg,
+    return dict(result, **{
             "one_by_one": {"value": single, "objects": len(sample), "steps": one_by_one_steps,
                            "eager_value": single_eager,
                            "note": "first %d objects, each stepped alone through the fused single-lattice "
                                    "path; value: all these objects' steps in one captured HIP graph, "
                                    "replayed; eager_value: one vx_step call per object" % len(sample)},
-            "speedup": batched / single,
-            "roofline": dict(roofline(32, nvox, ms / steps, kernel="k_batch"),
-                             note="kernel_ms is per step: one persistent launch runs all steps")}
+            "speedup": batched / single})
 
 
 def time_adjoint(steps=5000, K=100):
@@ -304,6 +307,9 @@ def main():
     ap.add_argument("--no-adjoint-leg", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
     ap.add_argument("--batch-objects", type=int, default=4096)
+    ap.add_argument("--one-by-one-sample", type=int, default=64,
+                    help="objects in the one-at-a-time comparison of the batched leg (0 skips it, e.g. "
+                         "under profiler counter collection, which does not follow graph launches)")
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--tile", default=None, metavar="SHAPE:ZC",
                     help="fix the fused tile of the first leg (shape index, z chunk) instead of autotuning")
@@ -369,7 +375,7 @@ def main():
         del w3
     if not args.no_batch_leg:
         log("batched leg: %d objects, %d steps" % (args.batch_objects, args.batch_steps))
-        out["batched"] = time_batch(args.batch_objects, args.batch_steps)
+        out["batched"] = time_batch(args.batch_objects, args.batch_steps, args.one_by_one_sample)
     if not args.no_adjoint_leg:
         log("adjoint leg: design lattice, %d steps" % args.adjoint_steps)
         out["adjoint"] = time_adjoint(args.adjoint_steps)
