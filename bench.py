@@ -63,7 +63,7 @@ def time_gpu(w, precision, kernel, steps, warmup, autotune=True, tile=None):
     if tile is not None:
         s.set_fused_tile(*tile)
     elif autotune and kernel == vx.KERNEL_FUSED:
-        s.autotune(iters=3)
+        s.autotune(iters=10)
     nvox = s.counters()["voxels"]
     if warmup:
         s.step(warmup)

@@ -189,8 +189,9 @@ int vx_candidates(vx_handle h, int32_t *cell_a, int32_t *cell_b, int32_t max_pai
 int vx_energy(vx_handle h, double out[10]);
 
 /* Select the step implementation: 0 = fused LDS-tiled kernel (default;
- * palettes of more than 16 materials always use the split path),
- * 1 = split per-axis bond kernels plus a gather kernel. */
+ * palettes of more than 16 materials, parameter mode and lattices whose
+ * state array (13 words per cell) spans 2 GiB or more always use the split
+ * path), 1 = split per-axis bond kernels plus a gather kernel. */
 int vx_set_kernel(vx_handle h, int32_t kind);
 
 /* Tile of the fused kernel: shape index 0..4 = 32x8, 64x4, 16x16, 50x5,
@@ -202,7 +203,8 @@ int vx_get_fused_tile(vx_handle h, int32_t *shape, int32_t *tx, int32_t *ty, int
 
 /* Time every fused tile shape and z chunk on this lattice (iters launches
  * each, from the current state, without advancing it) and keep the fastest.
- * Errors: VX_ESTATE before bind. */
+ * Errors: VX_ESTATE before bind, for a palette of more than 16 materials or
+ * a state array spanning 2 GiB or more (the fused kernel does not run). */
 int vx_autotune(vx_handle h, int32_t iters, int32_t *shape, int32_t *zc);
 
 /* Average wall time of one launch of the step kernel(s) alone (the fused
@@ -311,7 +313,8 @@ typedef struct vx_batch_sim *vx_batch;
  * materials) and one parameter set (self-collision must be off: objects do
  * not interact).  Each object gets its own stable timestep (Eq. 31-32 over
  * its own bonds) and its own time.  The grids are copied.  Errors:
- * VX_EINVAL as vx_create, or if the concatenated state would exceed 4 GiB. */
+ * VX_EINVAL as vx_create, or if one state array (13 words per cell of all
+ * objects) would span 2 GiB or more. */
 int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *palette, int32_t n_mat,
                     const vx_params *params, int32_t precision, void *stream, vx_batch *out);
 int vx_batch_workspace_bytes(vx_batch b, uint64_t *bytes);

@@ -223,7 +223,7 @@ static int enqueue_steps(vx_sim *h, int64_t n) {
             HIP_OK(h, launch_rebuild<T>(a, c, h->stream));
             HIP_OK(h, launch_contact<T>(a, c, (T *)(h->ws + h->L.contact_F), h->stream));
         }
-        if (h->kernel_kind == 1 || h->n_mat > kFusedMaxMat || h->param_mode()) {
+        if (h->use_split()) {
             HIP_OK(h, launch_split_step<T>(a, h->stream));
         } else {
             HIP_OK(h, launch_fused_step<T>(a, fused_cfg(h), h->stream));
@@ -268,7 +268,9 @@ static int autotune(vx_sim *h, int iters, int32_t *shape_out, int32_t *zc_out) {
     HIP_OK(h, hipEventCreate(&e1));
     float best = 1e30f;
     FusedCfg best_cfg{0, 0};
-    const int zcs[] = {2, 4, 8, 16, 32, 64};
+    // z chunks: the number of workgroups against the three resident per CU
+    // decides the tail of the launch, so the grid is fine
+    const int zcs[] = {2, 3, 4, 5, 6, 8, 10, 12, 16, 24, 32, 48, 64};
     for (int sh = 0; sh < kNumFusedShapes; ++sh)
         for (int zc : zcs) {
             if (zc > h->nz && zc != zcs[0]) continue;
@@ -308,7 +310,7 @@ static int time_kernel(vx_sim *h, int iters, double *ms_per_launch) {
         HIP_OK(h, launch_rebuild<T>(a, c, h->stream));
         HIP_OK(h, launch_contact<T>(a, c, (T *)(h->ws + h->L.contact_F), h->stream));
     }
-    const bool split = h->kernel_kind == 1 || h->n_mat > kFusedMaxMat || h->param_mode();
+    const bool split = h->use_split();
     const FusedCfg cfg = fused_cfg(h);
     auto launch = [&]() { return split ? launch_split_step<T>(a, h->stream) : launch_fused_step<T>(a, cfg, h->stream); };
     hipEvent_t e0, e1;
@@ -786,6 +788,8 @@ int vx_autotune(vx_handle h, int32_t iters, int32_t *shape, int32_t *zc) {
     if (!h || iters <= 0) return VX_EINVAL;
     if (!h->bound) return fail(h, VX_ESTATE, "vx_autotune before vx_bind_workspace");
     if (h->n_mat > kFusedMaxMat) return fail(h, VX_ESTATE, "palette too large for the fused kernel");
+    if (!fused_state_fits(h->ncell, h->precision / 8))
+        return fail(h, VX_ESTATE, "lattice too large for the fused kernel");
     return h->precision == 64 ? autotune<double>(h, iters, shape, zc) : autotune<float>(h, iters, shape, zc);
 }
 

@@ -327,7 +327,7 @@ int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *pal
         off += nc;
     }
     h->total = off;
-    if (h->total * (long long)N_WORDS * (long long)h->tsize > (1LL << 32) - 1) { delete h; return VX_EINVAL; }
+    if (!fused_state_fits(h->total, h->tsize)) { delete h; return VX_EINVAL; }
     layout(h);
     *out = h;
     return VX_OK;

@@ -567,16 +567,17 @@ __device__ __forceinline__ UpdEnv<T> upd_env(const StepArgs<T> &a, unsigned c, u
     return e;
 }
 
-template <typename T>
+// store(c, o) writes the new state words of cell c.
+template <typename T, typename Store>
 __device__ __forceinline__ void voxel_update(const StepArgs<T> &a, unsigned c, uint8_t fl,
                                              const MatConst<T> &mc, T eps, const VoxRaw<T> &r, T Fx,
-                                             T Fy, T Fz, T Mx, T My, T Mz, T *vmax_local) {
+                                             T Fy, T Fz, T Mx, T My, T Mz, T *vmax_local, const Store &store) {
     const UpdEnv<T> e = upd_env(a, c, fl);
     VoxRaw<T> o;
     uint8_t nf;
     int branch;
     update_core(e, fl, mc, eps, r, Fx, Fy, Fz, Mx, My, Mz, o, &nf, &branch);
-    store_raw(a.s_out, a.stride, c, o.ux, o.uy, o.uz, o.qw, o.qx, o.qy, o.qz, o.px, o.py, o.pz, o.lx, o.ly, o.lz);
+    store(c, o);
     stc(a.flags_out, c, nf);
     if (fl & FLAG_FIXED) return;
     const bool ok = dfinite(o.ux) && dfinite(o.uy) && dfinite(o.uz) && dfinite(o.qw) && dfinite(o.qx) &&
@@ -586,6 +587,16 @@ __device__ __forceinline__ void voxel_update(const StepArgs<T> &a, unsigned c, u
     const T nvx = o.px * mc.inv_m, nvy = o.py * mc.inv_m, nvz = o.pz * mc.inv_m;
     const T sp2 = nvx * nvx + nvy * nvy + nvz * nvz;
     if (sp2 > *vmax_local) *vmax_local = sp2;
+}
+
+template <typename T>
+__device__ __forceinline__ void voxel_update(const StepArgs<T> &a, unsigned c, uint8_t fl,
+                                             const MatConst<T> &mc, T eps, const VoxRaw<T> &r, T Fx,
+                                             T Fy, T Fz, T Mx, T My, T Mz, T *vmax_local) {
+    voxel_update(a, c, fl, mc, eps, r, Fx, Fy, Fz, Mx, My, Mz, vmax_local, [&](unsigned cc, const VoxRaw<T> &o) {
+        store_raw(a.s_out, a.stride, cc, o.ux, o.uy, o.uz, o.qw, o.qx, o.qy, o.qz, o.px, o.py, o.pz, o.lx, o.ly,
+                  o.lz);
+    });
 }
 
 // Wavefront maximum of the squared speed v2, then one atomic per wave of the

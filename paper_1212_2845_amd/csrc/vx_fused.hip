@@ -7,7 +7,10 @@
 // y-bond touching the tile is evaluated once (bonds that enter the tile
 // from the ring as well), its result kept in LDS, and the bond to the slab
 // above is evaluated in registers with its voxel-2 half carried to the next
-// slab.  Each thread then sums its own voxel's at most six bond results in
+// slab.  The next slab's cells are loaded while the bonds are evaluated and
+// staged in LDS between the bond pass and the update, so that neither the
+// ring cells' loads nor their kinematics occupy registers during the
+// update.  Each thread then sums its own voxel's at most six bond results in
 // the fixed order -x, +x, -y, +y, -z, +z (no atomics) and integrates.  The
 // per-bond and per-voxel arithmetic is the same device code as the split
 // path; material and material-pair constants are staged in LDS once per
@@ -27,13 +30,14 @@ constexpr int kXcds = 8;
 constexpr int kKin = 14;   // ux uy uz qw qx qy qz vx vy vz wx wy wz eps
 
 // LDS of one workgroup: a slab of kinematics with its ring, and the x- and
-// y-bond results, sized for NR ring cells and NBX / NBY bonds.
+// y-bond results (b[0] and b[1]), sized for NR ring cells and NBX / NBY
+// bonds.  Both bond arrays have the larger length, so a bond whose axis is
+// chosen per lane is stored through one address.
 template <typename T, int NR_, int NBX_, int NBY_>
 struct Smem {
-    static constexpr int NR = NR_, NBX = NBX_, NBY = NBY_;
+    static constexpr int NR = NR_, NB = NBX_ > NBY_ ? NBX_ : NBY_;
     T kin[kKin][NR];
-    T bx[9][NBX];
-    T by[9][NBY];
+    T b[2][9][NB];
     uint8_t mat[NR];
 };
 
@@ -71,6 +75,74 @@ __device__ __forceinline__ void put_bond(T (*b)[NB], int i, const BondOut<T> &o)
     b[6][i] = o.m2x; b[7][i] = o.m2y; b[8][i] = o.m2z;
 }
 
+// The state words of a cell through one buffer descriptor per state array.
+// Word w lies w * stride * sizeof(T) bytes after word 0, an offset kept in a
+// scalar register, so the 13 words of a cell share one 32-bit vector offset
+// (c * sizeof(T)) and no per-word 64-bit address is formed or kept: with
+// one pointer per word the two state arrays alone take 52 scalar
+// registers, which the compiler spills into vector lanes and reads back
+// before every load and store.  The descriptor spans the 13 words; the host
+// runs this kernel only when that span is below 2^31 bytes.
+constexpr int kRsrcWord3 = 0x00020000;   // raw 32-bit data format, gfx9 family
+
+template <typename T>
+struct StateBuf {
+    __amdgpu_buffer_rsrc_t in, out;
+    int wb;   // bytes from one state word to the next
+};
+
+template <typename T>
+__device__ __forceinline__ StateBuf<T> state_buf(const StepArgs<T> &a) {
+    StateBuf<T> b;
+    const int bytes = (int)(N_WORDS * a.stride * (long long)sizeof(T));
+    b.in = __builtin_amdgcn_make_buffer_rsrc((void *)a.s_in, 0, bytes, kRsrcWord3);
+    b.out = __builtin_amdgcn_make_buffer_rsrc((void *)a.s_out, 0, bytes, kRsrcWord3);
+    b.wb = (int)(a.stride * (long long)sizeof(T));
+    return b;
+}
+
+template <typename T> __device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off, int soff);
+template <> __device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, unsigned off, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, soff, 0));
+}
+template <> __device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, unsigned off, int soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, soff, 0));
+}
+template <typename T> __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, int soff, T v);
+template <> __device__ __forceinline__ void buf_st<float>(__amdgpu_buffer_rsrc_t r, unsigned off, int soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, soff, 0);
+}
+template <> __device__ __forceinline__ void buf_st<double>(__amdgpu_buffer_rsrc_t r, unsigned off, int soff, double v) {
+    using U2 = unsigned __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, (int)off, soff, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ VoxRaw<T> sb_load(const StateBuf<T> &b, unsigned c) {
+    const unsigned o = c * (unsigned)sizeof(T);
+    VoxRaw<T> r;
+    r.ux = buf_ld<T>(b.in, o, 0);           r.uy = buf_ld<T>(b.in, o, W_UY * b.wb);
+    r.uz = buf_ld<T>(b.in, o, W_UZ * b.wb); r.qw = buf_ld<T>(b.in, o, W_QW * b.wb);
+    r.qx = buf_ld<T>(b.in, o, W_QX * b.wb); r.qy = buf_ld<T>(b.in, o, W_QY * b.wb);
+    r.qz = buf_ld<T>(b.in, o, W_QZ * b.wb); r.px = buf_ld<T>(b.in, o, W_PX * b.wb);
+    r.py = buf_ld<T>(b.in, o, W_PY * b.wb); r.pz = buf_ld<T>(b.in, o, W_PZ * b.wb);
+    r.lx = buf_ld<T>(b.in, o, W_LX * b.wb); r.ly = buf_ld<T>(b.in, o, W_LY * b.wb);
+    r.lz = buf_ld<T>(b.in, o, W_LZ * b.wb);
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void sb_store(const StateBuf<T> &b, unsigned c, const VoxRaw<T> &v) {
+    const unsigned o = c * (unsigned)sizeof(T);
+    buf_st<T>(b.out, o, 0, v.ux);           buf_st<T>(b.out, o, W_UY * b.wb, v.uy);
+    buf_st<T>(b.out, o, W_UZ * b.wb, v.uz); buf_st<T>(b.out, o, W_QW * b.wb, v.qw);
+    buf_st<T>(b.out, o, W_QX * b.wb, v.qx); buf_st<T>(b.out, o, W_QY * b.wb, v.qy);
+    buf_st<T>(b.out, o, W_QZ * b.wb, v.qz); buf_st<T>(b.out, o, W_PX * b.wb, v.px);
+    buf_st<T>(b.out, o, W_PY * b.wb, v.py); buf_st<T>(b.out, o, W_PZ * b.wb, v.pz);
+    buf_st<T>(b.out, o, W_LX * b.wb, v.lx); buf_st<T>(b.out, o, W_LY * b.wb, v.ly);
+    buf_st<T>(b.out, o, W_LZ * b.wb, v.lz);
+}
+
 // Own voxel of one slab: material, flags, strain, raw state, kinematics.
 template <typename T>
 struct Own {
@@ -95,11 +167,12 @@ struct Tables {
 };
 
 template <typename T>
-__device__ __forceinline__ void load_own(const StepArgs<T> &a, const Tables<T> &tb, unsigned c, Own<T> &o) {
+__device__ __forceinline__ void load_own(const StepArgs<T> &a, const StateBuf<T> &sb, const Tables<T> &tb,
+                                         unsigned c, Own<T> &o) {
     o.m = ldc(a.mat, c);
     if (o.m) {
         o.fl = ldc(a.flags, c);
-        o.r = load_raw(a.s_in, a.stride, c);
+        o.r = sb_load(sb, c);
         const MatConst<T> &mc = tb.mat[o.m];
         o.eps = voxel_strain(a, c, o.fl, mc.cte);
         o.k = kin_of(o.r, mc, o.eps);
@@ -117,10 +190,10 @@ struct Pre {
 };
 
 template <typename T>
-__device__ __forceinline__ void issue_pre(const StepArgs<T> &a, unsigned c, Pre<T> &p) {
+__device__ __forceinline__ void issue_pre(const StepArgs<T> &a, const StateBuf<T> &sb, unsigned c, Pre<T> &p) {
     p.m = ldc(a.mat, c);
     p.fl = ldc(a.flags, c);
-    p.r = load_raw(a.s_in, a.stride, c);
+    p.r = sb_load(sb, c);
 }
 
 // Strain and kinematics of a prefetched cell.
@@ -175,7 +248,7 @@ template <typename T, typename S>
 __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<T> &tb, const LatK<T> &C,
                                       const int TX, const int TY, int tile_x, int tile_y, int z0, int z1,
                                       T &vmax) {
-    constexpr int NR = S::NR, NBX = S::NBX, NBY = S::NBY;
+    constexpr int NR = S::NR, NB = S::NB;
     const int RW = TX + 2;
     const int tid = threadIdx.x;
     const bool lane_in = tid < TX * TY;
@@ -185,6 +258,7 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
     const unsigned nxy = (unsigned)a.nx * (unsigned)a.ny;
     const unsigned col = inxy ? (unsigned)x + (unsigned)a.nx * (unsigned)y : 0u;
     const int own = (tx + 1) + RW * (ty + 1);
+    const StateBuf<T> sb = state_buf(a);
 
     // ring cell of this thread (one-cell border of the tile, corners excluded)
     const bool ring = tid < 2 * (TX + TY);
@@ -204,19 +278,36 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
     const int bnd_up = bnd_y ? bnd_lo + RW : bnd_lo + 1;
     const int bnd_i = bnd_y ? (tid - TY) : (TX + 1) * tid;
 
+    // Stage slab z in LDS: kinematics and material of the own cell o and of
+    // this thread's ring cell, whose loads r were issued earlier.
+    auto stage = [&](const Own<T> &o, const Pre<T> &r, int z) __attribute__((always_inline)) {
+        if (lane_in) {
+            if (o.m) put_kin<T, NR>(sm.kin, own, o.k);
+            sm.mat[own] = o.m;
+        }
+        if (ring) {
+            uint8_t mr = 0;
+            if (ring_in) {
+                Own<T> R{};
+                finish_pre(a, tb, ring_col + (unsigned)z * nxy, r, R);
+                mr = R.m;
+                if (mr) put_kin<T, NR>(sm.kin, ring_slot, R.k);
+            }
+            sm.mat[ring_slot] = mr;
+        }
+    };
+
     Own<T> A{}, B{};
-    if (inxy && z0 < z1) load_own(a, tb, col + (unsigned)z0 * nxy, A);
-    // ring cell of the first slab; later slabs' ring cells are issued one
-    // slab ahead
-    Pre<T> RA{}, RB{};
-    if (ring_in && z0 < z1) issue_pre(a, ring_col + (unsigned)z0 * nxy, RA);
+    if (inxy && z0 < z1) load_own(a, sb, tb, col + (unsigned)z0 * nxy, A);
+    Pre<T> rp{};
+    if (ring_in && z0 < z1) issue_pre(a, sb, ring_col + (unsigned)z0 * nxy, rp);
 
     // bond from the slab below the chunk: only its voxel-2 half is needed
     bool has_carry = false;
     T cFx = T(0), cFy = T(0), cFz = T(0), cMx = T(0), cMy = T(0), cMz = T(0);
     if (A.m && z0 > 0) {
         Own<T> P{};
-        load_own(a, tb, col + (unsigned)(z0 - 1) * nxy, P);
+        load_own(a, sb, tb, col + (unsigned)(z0 - 1) * nxy, P);
         if (P.m) {
             const Rot<T> Rp = rot_of(P.k.qw, P.k.qx, P.k.qy, P.k.qz);
             const BondOut<T> o = bond_eval<T, 2>(P.k, Rp, A.k, tb.bond(P.m, A.m), C);
@@ -224,58 +315,48 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
             has_carry = true;
         }
     }
+    if (z0 < z1) stage(A, rp, z0);
 
-    // one slab: cur holds slab z (its loads issued one slab earlier), nxt
-    // receives slab z + 1; rcur / rnxt the same for this thread's ring cell
-    auto slab = [&](Own<T> &cur, Own<T> &nxt, Pre<T> &rcur, Pre<T> &rnxt, int z) __attribute__((always_inline)) {
+    // one slab: cur holds slab z, already staged in LDS; nxt receives slab
+    // z + 1, whose loads (own cell and ring cell) are issued at the start so
+    // that they arrive during the bond evaluations, and which is staged in
+    // LDS once every thread is past its bonds of slab z
+    auto slab = [&](Own<T> &cur, Own<T> &nxt, int z) __attribute__((always_inline)) {
         Pre<T> pn{};
-        if (inxy && z + 1 < a.nz) issue_pre(a, col + (unsigned)(z + 1) * nxy, pn);
-        rnxt.m = 0;
-        if (ring_in && z + 1 < z1) issue_pre(a, ring_col + (unsigned)(z + 1) * nxy, rnxt);
-
-        if (lane_in) {
-            if (cur.m) put_kin<T, NR>(sm.kin, own, cur.k);
-            sm.mat[own] = cur.m;
-        }
-        if (ring) {
-            uint8_t mr = 0;
-            if (ring_in) {
-                Own<T> R{};
-                finish_pre(a, tb, ring_col + (unsigned)z * nxy, rcur, R);
-                mr = R.m;
-                if (mr) put_kin<T, NR>(sm.kin, ring_slot, R.k);
-            }
-            sm.mat[ring_slot] = mr;
-        }
+        if (inxy && z + 1 < a.nz) issue_pre(a, sb, col + (unsigned)(z + 1) * nxy, pn);
+        rp.m = 0;
+        if (ring_in && z + 1 < z1) issue_pre(a, sb, ring_col + (unsigned)(z + 1) * nxy, rp);
         __syncthreads();
 
-        Rot<T> Rc{};
-        if (cur.m) Rc = rot_of(cur.k.qw, cur.k.qx, cur.k.qy, cur.k.qz);
-        {
-            const uint8_t mu = lane_in ? sm.mat[own + 1] : 0;
-            if (cur.m && mu) {
-                const VoxKin<T> ku = get_kin<T, NR>(sm.kin, own + 1);
-                put_bond<T, NBX>(sm.bx, (tx + 1) + (TX + 1) * ty, bond_eval<T, 0>(cur.k, Rc, ku, tb.bond(cur.m, mu), C));
-            }
-        }
-        {
-            const uint8_t mu = lane_in ? sm.mat[own + RW] : 0;
-            if (cur.m && mu) {
-                const VoxKin<T> ku = get_kin<T, NR>(sm.kin, own + RW);
-                put_bond<T, NBY>(sm.by, tx + TX * (ty + 1), bond_eval<T, 1>(cur.k, Rc, ku, tb.bond(cur.m, mu), C));
-            }
-        }
+        // bonds entering the tile from the ring: x from (-1, tid), y from
+        // (tid - TY, -1)
         if (bnd) {
             const uint8_t ml = sm.mat[bnd_lo], mu = sm.mat[bnd_up];
             if (ml && mu) {
                 const VoxKin<T> kl = get_kin<T, NR>(sm.kin, bnd_lo), ku = get_kin<T, NR>(sm.kin, bnd_up);
                 const Rot<T> Rl = rot_of(kl.qw, kl.qx, kl.qy, kl.qz);
                 const BondOut<T> o = bond_eval_xy(kl, Rl, ku, tb.bond(ml, mu), C, bnd_y);
-                if (bnd_y) put_bond<T, NBY>(sm.by, bnd_i, o); else put_bond<T, NBX>(sm.bx, bnd_i, o);
+                put_bond<T, NB>(sm.b[bnd_y ? 1 : 0], bnd_i, o);
             }
         }
-        // neighbour materials for the gather, read before the slab's LDS can
-        // be overwritten by faster threads moving on to the next slab
+        Rot<T> Rc{};
+        if (cur.m) Rc = rot_of(cur.k.qw, cur.k.qx, cur.k.qy, cur.k.qz);
+        {
+            const uint8_t mu = lane_in ? sm.mat[own + 1] : 0;
+            if (cur.m && mu) {
+                const VoxKin<T> ku = get_kin<T, NR>(sm.kin, own + 1);
+                put_bond<T, NB>(sm.b[0], (tx + 1) + (TX + 1) * ty, bond_eval<T, 0>(cur.k, Rc, ku, tb.bond(cur.m, mu), C));
+            }
+        }
+        {
+            const uint8_t mu = lane_in ? sm.mat[own + RW] : 0;
+            if (cur.m && mu) {
+                const VoxKin<T> ku = get_kin<T, NR>(sm.kin, own + RW);
+                put_bond<T, NB>(sm.b[1], tx + TX * (ty + 1), bond_eval<T, 1>(cur.k, Rc, ku, tb.bond(cur.m, mu), C));
+            }
+        }
+        // neighbour materials for the gather, read before the slab's LDS is
+        // restaged
         bool n_mx = false, n_px = false, n_my = false, n_py = false;
         if (lane_in) {
             n_mx = sm.mat[own - 1] != 0; n_px = sm.mat[own + 1] != 0;
@@ -287,27 +368,30 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
         if (has_zb) oz = bond_eval<T, 2>(cur.k, Rc, nxt.k, tb.bond(cur.m, nxt.m), C);
         __syncthreads();
 
+        // the bond results stay in LDS until the next slab's first barrier;
+        // the kinematics of slab z are no longer read
+        if (z + 1 < z1) stage(nxt, rp, z + 1);
         if (cur.m) {
             T Fx = T(0), Fy = T(0), Fz = T(0), Mx = T(0), My = T(0), Mz = T(0);
             if (n_mx) {
                 const int i = tx + (TX + 1) * ty;
-                Fx += sm.bx[0][i]; Fy += sm.bx[1][i]; Fz += sm.bx[2][i];
-                Mx += sm.bx[6][i]; My += sm.bx[7][i]; Mz += sm.bx[8][i];
+                Fx += sm.b[0][0][i]; Fy += sm.b[0][1][i]; Fz += sm.b[0][2][i];
+                Mx += sm.b[0][6][i]; My += sm.b[0][7][i]; Mz += sm.b[0][8][i];
             }
             if (n_px) {
                 const int i = (tx + 1) + (TX + 1) * ty;
-                Fx -= sm.bx[0][i]; Fy -= sm.bx[1][i]; Fz -= sm.bx[2][i];
-                Mx += sm.bx[3][i]; My += sm.bx[4][i]; Mz += sm.bx[5][i];
+                Fx -= sm.b[0][0][i]; Fy -= sm.b[0][1][i]; Fz -= sm.b[0][2][i];
+                Mx += sm.b[0][3][i]; My += sm.b[0][4][i]; Mz += sm.b[0][5][i];
             }
             if (n_my) {
                 const int i = tx + TX * ty;
-                Fx += sm.by[0][i]; Fy += sm.by[1][i]; Fz += sm.by[2][i];
-                Mx += sm.by[6][i]; My += sm.by[7][i]; Mz += sm.by[8][i];
+                Fx += sm.b[1][0][i]; Fy += sm.b[1][1][i]; Fz += sm.b[1][2][i];
+                Mx += sm.b[1][6][i]; My += sm.b[1][7][i]; Mz += sm.b[1][8][i];
             }
             if (n_py) {
                 const int i = tx + TX * (ty + 1);
-                Fx -= sm.by[0][i]; Fy -= sm.by[1][i]; Fz -= sm.by[2][i];
-                Mx += sm.by[3][i]; My += sm.by[4][i]; Mz += sm.by[5][i];
+                Fx -= sm.b[1][0][i]; Fy -= sm.b[1][1][i]; Fz -= sm.b[1][2][i];
+                Mx += sm.b[1][3][i]; My += sm.b[1][4][i]; Mz += sm.b[1][5][i];
             }
             if (has_carry) {
                 Fx += cFx; Fy += cFy; Fz += cFz;
@@ -318,7 +402,7 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
                 Mx += oz.m1x; My += oz.m1y; Mz += oz.m1z;
             }
             voxel_update(a, col + (unsigned)z * nxy, cur.fl, tb.mat[cur.m], cur.eps, cur.r, Fx, Fy, Fz, Mx, My,
-                         Mz, &vmax);
+                         Mz, &vmax, [&](unsigned c, const VoxRaw<T> &o) { sb_store(sb, c, o); });
         }
         has_carry = has_zb;
         cFx = oz.f2x; cFy = oz.f2y; cFz = oz.f2z; cMx = oz.m2x; cMy = oz.m2y; cMz = oz.m2z;
@@ -326,13 +410,17 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
 
     // two slabs per trip so that the roles of A and B alternate without copies
     for (int z = z0; z < z1; z += 2) {
-        slab(A, B, RA, RB, z);
-        if (z + 1 < z1) slab(B, A, RB, RA, z + 1);
+        slab(A, B, z);
+        if (z + 1 < z1) slab(B, A, z + 1);
     }
 }
 
+// FP32 is held to 168 VGPRs, so that three workgroups share a CU (three
+// waves per SIMD; two loop-invariant values go to scratch); FP64 needs more
+// than 256 and runs one wave per SIMD.
 template <typename T, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY) k_fused(StepArgs<T> a, FusedGrid g) {
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
+k_fused(StepArgs<T> a, FusedGrid g) {
     static_assert(2 * (TX + TY) <= TX * TY, "ring must fit one cell per thread");
     __shared__ TileSmem<T, TX, TY> sm;
     extern __shared__ __align__(16) unsigned char dyn[];

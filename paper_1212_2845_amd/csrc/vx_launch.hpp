@@ -52,6 +52,11 @@ struct FusedCfg {
 int fused_default_zc(int nz, long long cols);
 // Largest palette whose tables fit the fused kernel's LDS.
 constexpr int kFusedMaxMat = 16;
+// The fused and batched kernels address all state words of one state array
+// through one buffer descriptor, whose byte span must stay below 2^31.
+inline bool fused_state_fits(long long stride, int tsize) {
+    return (long long)N_WORDS * stride * tsize < (1LL << 31);
+}
 
 template <typename T>
 hipError_t launch_fused_step(const StepArgs<T> &a, const FusedCfg &cfg, hipStream_t s);

@@ -101,6 +101,12 @@ struct vx_sim {
     bool has_E = false, has_rho = false;
     std::vector<double> E_cell, rho_cell;
     bool param_mode() const { return has_E || has_rho; }
+    // the split kernels run when asked for, for palettes over 16 materials,
+    // in parameter mode and for state arrays beyond the fused kernel's span
+    bool use_split() const {
+        return kernel_kind == 1 || n_mat > vx::kFusedMaxMat || param_mode() ||
+               !vx::fused_state_fits(ncell, precision / 8);
+    }
     double wmax = 0.0;                    // sqrt(k_b / m_min) the timestep was chosen for
     // differentiable rollouts
     char *gws = nullptr;
