@@ -269,3 +269,15 @@ def test_grad_bind_rejects_self_collision():
     assert vx.lib().vx_grad_bind(h, None, 0, 10, 2) == vx.VX_ESTATE
     assert b"self-collision" in vx.lib().vx_last_error(h)
     vx.lib().vx_destroy(h)
+
+
+def test_batch_state_span_limit():
+    # the batched kernel addresses one state array (13 words per cell of all
+    # objects) through one buffer descriptor: the array must span < 2^31 B
+    lim = ((1 << 31) + 13 * 8 - 1) // (13 * 8)   # first FP64 cell count at or over 2^31 B
+    mats = [workloads.EMPTY, M1]
+    b = vx.Batch([np.zeros((1, 1, lim - 1), np.uint8)], mats, precision=64)
+    assert b.n == 1
+    with pytest.raises(vx.VoxsimError) as e:
+        vx.Batch([np.zeros((1, 1, lim), np.uint8)], mats, precision=64)
+    assert e.value.code == vx.VX_EINVAL
