@@ -16,7 +16,9 @@ The state is resident on the GPU before timing starts.  Prints one JSON line.
 voxel-steps/s = filled voxels x steps / wall time of the K timed steps (HIP
 events on the stream the kernels run on, device synchronisation on both
 sides).  The roofline figure uses the step kernel's own average launch time,
-measured the same way over dry-run launches that do not advance the state.
+measured the same way over dry-run launches that do not advance the state;
+roofline.copy_probe is the rate of a plain 1 GiB device copy on the same GPU,
+as context for the 8 TB/s peak.
 """
 import argparse
 import json
@@ -266,6 +268,29 @@ def time_adjoint(steps=5000, K=100):
                     "checkpoint and the host copies of the adjoint in and the gradients out"}
 
 
+def copy_probe(mib=1024, reps=5):
+    """Achievable HBM rate on this device: a plain device-to-device copy of
+    mib MiB (read once, written once), best of reps, timed with HIP events."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = 1e30
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBps": 2 * n * 4 / (best / 1e3) / 1e9, "bytes_each_way": n * 4,
+            "note": "torch device copy, best of %d; context for the 8 TB/s peak" % reps}
+
+
 def cpu_baseline(w, budget_s=12.0, note=""):
     """The oracle (FP64, one thread) on a bounded sample of the workload."""
     import oracle
@@ -358,6 +383,7 @@ def main():
                    "cache_resident": 2 * int(w["grid"].size) * 13 * (4 if args.precision == 32 else 8) < 256e6},
         "roofline": roofline(args.precision, r["voxels"], r["kernel_ms"], w["name"], r["tile"]),
     }
+    out["roofline"]["copy_probe"] = copy_probe()
     if not args.no_fp64 and args.precision == 32:
         log("fp64 leg")
         r64 = time_gpu(w, 64, kernel, args.steps, args.warmup, autotune)

@@ -10,7 +10,10 @@
 // the next slab for z.  Threads on the tile's low x and y faces also
 // evaluate the bonds entering from the ring (only the inner end is kept),
 // and the bond entering the chunk from below is evaluated once per column.
-// No per-bond record reaches HBM and no atomics are used.
+// No per-bond record reaches HBM and no atomics are used.  Every word a
+// cell contributes (material, flags, modulus, density, signal, state, bond-
+// sum adjoint) is loaded without waiting on another, and the next slab is
+// staged in LDS between the bond pass and the gather.
 #include "vx_adjoint.hpp"
 #include "vx_launch.hpp"
 
@@ -42,17 +45,62 @@ struct AdjSmem {
     uint8_t mat[NR];
 };
 
+// Every word one cell contributes to the reverse pass, loaded without
+// waiting on any of them (also for an empty cell, whose words exist and are
+// ignored), so that the loads of a slab are in flight together.
 template <typename T>
-__device__ __forceinline__ void load_cell(const StepArgs<T> &a, const AdjArgs<T> &g, unsigned c, AdjCell<T> &o) {
-    o.m = ldc(a.mat, c);
-    if (!o.m) return;
-    const uint8_t fl = ldc(a.flags, c);
-    const MatConst<T> mc = mat_at(a, (long long)c, o.m);
-    const T eps = voxel_strain(a, c, fl, mc.cte);
-    o.k = load_kin(a.s_in, a.stride, c, mc, eps);
+struct AdjPre {
+    uint8_t m, fl;
+    T E, rho, amp, phase;
+    VoxRaw<T> r;
+    T gf[6];
+};
+
+template <typename T>
+__device__ __forceinline__ void issue_adj(const StepArgs<T> &a, const AdjArgs<T> &g, unsigned c, AdjPre<T> &p) {
+    p.m = ldc(a.mat, c);
+    p.fl = ldc(a.flags, c);
+    p.E = a.E_cell ? ldc(a.E_cell, c) : T(0);
+    p.rho = a.rho_cell ? ldc(a.rho_cell, c) : T(0);
+    p.amp = ldc(a.act_amp, c);
+    p.phase = ldc(a.act_phase, c);
+    p.r = load_raw(a.s_in, a.stride, c);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) p.gf[i] = ldc(g.gfm + i * a.stride, c);
+}
+
+// Strain of a cell from its prefetched signal: the same expression as
+// voxel_strain.
+template <typename T>
+__device__ __forceinline__ T strain_of(const StepArgs<T> &a, uint8_t fl, T cte, T amp, T phase) {
+    T dT = a.dT_global;
+    if (fl & FLAG_ACT) {
+        if constexpr (sizeof(T) == 8) {
+            dT = amp * dsin<T>(a.wt + phase);
+        } else {
+            dT = amp * dsin<T>(a.wt_red + phase);
+        }
+    }
+    return cte * dT;
+}
+
+template <typename T>
+__device__ __forceinline__ void finish_adj(const StepArgs<T> &a, const AdjPre<T> &p, AdjCell<T> &o) {
+    o.m = p.m;
+    if (!p.m) return;
+    const MatConst<T> mc = a.E_cell ? mat_with(a.mats[p.m], p.E, p.rho, a.l, a.zeta_slow, a.zeta_col) : a.mats[p.m];
+    const T eps = strain_of(a, p.fl, mc.cte, p.amp, p.phase);
+    o.k = kin_of(p.r, mc, eps);
     o.E = mc.E; o.mass = mc.m; o.gfac = mc.gfac;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) o.gf[i] = ldc(g.gfm + i * a.stride, c);
+    for (int i = 0; i < 6; ++i) o.gf[i] = p.gf[i];
+}
+
+template <typename T>
+__device__ __forceinline__ void load_cell(const StepArgs<T> &a, const AdjArgs<T> &g, unsigned c, AdjCell<T> &o) {
+    AdjPre<T> p;
+    issue_adj(a, g, c, p);
+    finish_adj(a, p, o);
 }
 
 template <typename T, typename S>
@@ -175,57 +223,59 @@ __global__ void __launch_bounds__(TX *TY) k_adj_fused(StepArgs<T> a, AdjArgs<T> 
     const int bnd_i = bnd_y ? (tid - TY) : (TX + 1) * tid;
     const LatK<T> C = lat_consts(a.l);
 
-    AdjCell<T> cur{}, nxt{};
-    if (inxy && z0 < z1) load_cell(a, g, col + (unsigned)z0 * nxy, cur);
-    // voxel-2 end of the bond entering the chunk from below
-    T cin[kEnd];
-    bool has_cin = false;
-#pragma unroll
-    for (int i = 0; i < kEnd; ++i) cin[i] = T(0);
-    if (cur.m && z0 > 0) {
-        AdjCell<T> P{};
-        load_cell(a, g, col + (unsigned)(z0 - 1) * nxy, P);
-        if (P.m) {
-            T ea[kEnd];
-            bond_ends<T, 2>(P, cur, a.zeta_bond, C, ea, cin);
-            has_cin = true;
-        }
-    }
-
-    for (int z = z0; z < z1; ++z) {
-        nxt.m = 0;
-        if (inxy && z + 1 < a.nz) load_cell(a, g, col + (unsigned)(z + 1) * nxy, nxt);
+    // Stage slab z in LDS: the own cell o and this thread's ring cell,
+    // whose loads r were issued earlier.
+    auto stage = [&](const AdjCell<T> &o, const AdjPre<T> &r) __attribute__((always_inline)) {
         if (inxy) {
-            if (cur.m) put_cell<T>(sm, own, cur);
-            sm.mat[own] = cur.m;
+            if (o.m) put_cell<T>(sm, own, o);
+            sm.mat[own] = o.m;
         } else {
             sm.mat[own] = 0;
         }
         if (ring) {
             AdjCell<T> R{};
-            if (ring_in) load_cell(a, g, ring_col + (unsigned)z * nxy, R);
+            if (ring_in) finish_adj(a, r, R);
             if (R.m) put_cell<T>(sm, ring_slot, R);
             sm.mat[ring_slot] = R.m;
         }
+    };
+
+    AdjCell<T> A{}, B{};
+    if (inxy && z0 < z1) load_cell(a, g, col + (unsigned)z0 * nxy, A);
+    AdjPre<T> rp{};
+    if (ring_in && z0 < z1) issue_adj(a, g, ring_col + (unsigned)z0 * nxy, rp);
+    // voxel-2 end of the bond entering the chunk from below
+    T cin[kEnd];
+    bool has_cin = false;
+#pragma unroll
+    for (int i = 0; i < kEnd; ++i) cin[i] = T(0);
+    if (A.m && z0 > 0) {
+        AdjCell<T> P{};
+        load_cell(a, g, col + (unsigned)(z0 - 1) * nxy, P);
+        if (P.m) {
+            T ea[kEnd];
+            bond_ends<T, 2>(P, A, a.zeta_bond, C, ea, cin);
+            has_cin = true;
+        }
+    }
+    if (z0 < z1) stage(A, rp);
+
+    // one slab: cur (slab z) is staged in LDS; slab z + 1 is staged once
+    // every thread is past its bonds of slab z.  In FP32 the loads of slab
+    // z + 1 (own cell and ring cell) are issued first and arrive during the
+    // bond VJPs; FP64, whose registers are already full, issues them where
+    // they are used.
+    constexpr bool early = sizeof(T) == 4;
+    auto slab = [&](AdjCell<T> &cur, AdjCell<T> &nxt, int z) __attribute__((always_inline)) {
+        AdjPre<T> pn{};
+        if constexpr (early) {
+            if (inxy && z + 1 < a.nz) issue_adj(a, g, col + (unsigned)(z + 1) * nxy, pn);
+            rp.m = 0;
+            if (ring_in && z + 1 < z1) issue_adj(a, g, ring_col + (unsigned)(z + 1) * nxy, rp);
+        }
         __syncthreads();
 
-        T acc[kEnd];
-#pragma unroll
-        for (int i = 0; i < kEnd; ++i) acc[i] = T(0);
-        if (cur.m && sm.mat[own + 1]) {
-            const AdjCell<T> B = get_cell<T>(sm, own + 1);
-            T ea[kEnd], eb[kEnd];
-            bond_ends<T, 0>(cur, B, a.zeta_bond, C, ea, eb);
-#pragma unroll
-            for (int i = 0; i < kEnd; ++i) { acc[i] += ea[i]; sm.rx[i][(tx + 1) + (TX + 1) * ty] = eb[i]; }
-        }
-        if (cur.m && sm.mat[own + RW]) {
-            const AdjCell<T> B = get_cell<T>(sm, own + RW);
-            T ea[kEnd], eb[kEnd];
-            bond_ends<T, 1>(cur, B, a.zeta_bond, C, ea, eb);
-#pragma unroll
-            for (int i = 0; i < kEnd; ++i) { acc[i] += ea[i]; sm.ry[i][tx + TX * (ty + 1)] = eb[i]; }
-        }
+        // bonds entering the tile from the ring (only their inner end is kept)
         if (bnd && sm.mat[bnd_lo] && sm.mat[bnd_up]) {
             const AdjCell<T> Lc = get_cell<T>(sm, bnd_lo), U = get_cell<T>(sm, bnd_up);
             T ea[kEnd], eb[kEnd];
@@ -239,10 +289,32 @@ __global__ void __launch_bounds__(TX *TY) k_adj_fused(StepArgs<T> a, AdjArgs<T> 
                 for (int i = 0; i < kEnd; ++i) sm.rx[i][bnd_i] = eb[i];
             }
         }
-        // neighbour materials for the gather, read before a faster thread can
-        // overwrite the slab's LDS
+        T acc[kEnd];
+#pragma unroll
+        for (int i = 0; i < kEnd; ++i) acc[i] = T(0);
+        if (cur.m && sm.mat[own + 1]) {
+            const AdjCell<T> Bc = get_cell<T>(sm, own + 1);
+            T ea[kEnd], eb[kEnd];
+            bond_ends<T, 0>(cur, Bc, a.zeta_bond, C, ea, eb);
+#pragma unroll
+            for (int i = 0; i < kEnd; ++i) { acc[i] += ea[i]; sm.rx[i][(tx + 1) + (TX + 1) * ty] = eb[i]; }
+        }
+        if (cur.m && sm.mat[own + RW]) {
+            const AdjCell<T> Bc = get_cell<T>(sm, own + RW);
+            T ea[kEnd], eb[kEnd];
+            bond_ends<T, 1>(cur, Bc, a.zeta_bond, C, ea, eb);
+#pragma unroll
+            for (int i = 0; i < kEnd; ++i) { acc[i] += ea[i]; sm.ry[i][tx + TX * (ty + 1)] = eb[i]; }
+        }
+        // neighbour materials for the gather, read before the slab's LDS is
+        // restaged
         const bool n_mx = cur.m && sm.mat[own - 1] != 0;
         const bool n_my = cur.m && sm.mat[own - RW] != 0;
+        nxt.m = 0;
+        if (inxy && z + 1 < a.nz) {
+            if constexpr (!early) issue_adj(a, g, col + (unsigned)(z + 1) * nxy, pn);
+            finish_adj(a, pn, nxt);
+        }
         T cout[kEnd];
         const bool has_z = cur.m && nxt.m;
         if (has_z) {
@@ -253,6 +325,13 @@ __global__ void __launch_bounds__(TX *TY) k_adj_fused(StepArgs<T> a, AdjArgs<T> 
         }
         __syncthreads();
 
+        // the bond ends stay in LDS until the next slab's first barrier; the
+        // cells of slab z are no longer read
+        if constexpr (!early) {
+            rp.m = 0;
+            if (ring_in && z + 1 < z1) issue_adj(a, g, ring_col + (unsigned)(z + 1) * nxy, rp);
+        }
+        if (z + 1 < z1) stage(nxt, rp);
         if (cur.m) {
             if (n_mx) {
 #pragma unroll
@@ -271,7 +350,12 @@ __global__ void __launch_bounds__(TX *TY) k_adj_fused(StepArgs<T> a, AdjArgs<T> 
         has_cin = has_z;
 #pragma unroll
         for (int i = 0; i < kEnd; ++i) cin[i] = has_z ? cout[i] : T(0);
-        cur = nxt;
+    };
+
+    // one slab per trip (two per trip, without the copy, costs registers)
+    for (int z = z0; z < z1; ++z) {
+        slab(A, B, z);
+        A = B;
     }
 }
 
@@ -284,7 +368,8 @@ hipError_t launch_adjoint_fused(const StepArgs<T> &a, const AdjArgs<T> &g, hipSt
     fg.tiles_x = (a.nx + TX - 1) / TX;
     fg.tiles_y = (a.ny + TY - 1) / TY;
     const long long cols = (long long)fg.tiles_x * fg.tiles_y;
-    fg.zc = fused_default_zc(a.nz, cols);
+    // two workgroups per CU in FP32 (221 VGPRs, 67 KB LDS), one in FP64
+    fg.zc = balanced_zc(a.nz, cols, sizeof(T) == 4 ? 2 : 1);
     fg.chunks = (a.nz + fg.zc - 1) / fg.zc;
     k_adj_fused<T, TX, TY><<<(unsigned)(cols * fg.chunks), TX * TY, 0, s>>>(a, g, fg);
     return hipGetLastError();

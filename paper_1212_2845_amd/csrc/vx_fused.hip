@@ -196,18 +196,19 @@ __device__ __forceinline__ void issue_pre(const StepArgs<T> &a, const StateBuf<T
     p.r = sb_load(sb, c);
 }
 
-// Strain and kinematics of a prefetched cell.
+// Strain and kinematics of a prefetched cell, computed for an empty cell
+// too (material 0's constants, results unused): assigning every field
+// unconditionally lets the compiler keep the prefetched words in the
+// registers of o instead of copying them.
 template <typename T>
 __device__ __forceinline__ void finish_pre(const StepArgs<T> &a, const Tables<T> &tb, unsigned c, const Pre<T> &p,
                                            Own<T> &o) {
     o.m = p.m;
-    if (p.m) {
-        o.fl = p.fl;
-        o.r = p.r;
-        const MatConst<T> &mc = tb.mat[p.m];
-        o.eps = voxel_strain(a, c, p.fl, mc.cte);
-        o.k = kin_of(p.r, mc, o.eps);
-    }
+    o.fl = p.fl;
+    o.r = p.r;
+    const MatConst<T> &mc = tb.mat[p.m];
+    o.eps = voxel_strain(a, c, p.fl, mc.cte);
+    o.k = kin_of(p.r, mc, o.eps);
 }
 
 // Load the material tables into LDS (all threads of the workgroup; the
@@ -288,7 +289,7 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
         if (ring) {
             uint8_t mr = 0;
             if (ring_in) {
-                Own<T> R{};
+                Own<T> R;
                 finish_pre(a, tb, ring_col + (unsigned)z * nxy, r, R);
                 mr = R.m;
                 if (mr) put_kin<T, NR>(sm.kin, ring_slot, R.k);
@@ -322,9 +323,14 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
     // that they arrive during the bond evaluations, and which is staged in
     // LDS once every thread is past its bonds of slab z
     auto slab = [&](Own<T> &cur, Own<T> &nxt, int z) __attribute__((always_inline)) {
-        Pre<T> pn{};
+        // a cell not loaded reads as empty with no flags (finish_pre then
+        // reads nothing more from memory; its state words are not used)
+        Pre<T> pn;
+        pn.m = 0;
+        pn.fl = 0;
         if (inxy && z + 1 < a.nz) issue_pre(a, sb, col + (unsigned)(z + 1) * nxy, pn);
         rp.m = 0;
+        rp.fl = 0;
         if (ring_in && z + 1 < z1) issue_pre(a, sb, ring_col + (unsigned)(z + 1) * nxy, rp);
         __syncthreads();
 
@@ -339,8 +345,7 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
                 put_bond<T, NB>(sm.b[bnd_y ? 1 : 0], bnd_i, o);
             }
         }
-        Rot<T> Rc{};
-        if (cur.m) Rc = rot_of(cur.k.qw, cur.k.qx, cur.k.qy, cur.k.qz);
+        const Rot<T> Rc = rot_of(cur.k.qw, cur.k.qx, cur.k.qy, cur.k.qz);
         {
             const uint8_t mu = lane_in ? sm.mat[own + 1] : 0;
             if (cur.m && mu) {
@@ -364,7 +369,7 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
         }
         finish_pre(a, tb, col + (unsigned)(z + 1) * nxy, pn, nxt);
         const bool has_zb = cur.m && nxt.m;
-        BondOut<T> oz{};
+        BondOut<T> oz;
         if (has_zb) oz = bond_eval<T, 2>(cur.k, Rc, nxt.k, tb.bond(cur.m, nxt.m), C);
         __syncthreads();
 
@@ -499,7 +504,7 @@ hipError_t launch_tiles(const StepArgs<T> &a, int zc, hipStream_t s) {
     g.tiles_x = (a.nx + TX - 1) / TX;
     g.tiles_y = (a.ny + TY - 1) / TY;
     const long long cols = (long long)g.tiles_x * g.tiles_y;
-    if (zc <= 0) zc = fused_default_zc(a.nz, cols);
+    if (zc <= 0) zc = balanced_zc(a.nz, cols, fused_wg_per_cu((int)sizeof(T)));
     zc = zc > a.nz ? a.nz : zc;
     g.zc = zc;
     g.chunks = (a.nz + zc - 1) / zc;
@@ -510,14 +515,45 @@ hipError_t launch_tiles(const StepArgs<T> &a, int zc, hipStream_t s) {
 
 }  // namespace
 
-int fused_default_zc(int nz, long long cols) {
-    // enough workgroups to fill the chip several times over, but chunks of
-    // at least 4 slabs so that the extra slab below each chunk stays cheap
-    const long long target = 4096;
-    long long zc = (nz * cols + target - 1) / target;
-    if (zc < 4) zc = 4;
-    if (zc > nz) zc = nz;
-    return (int)zc;
+int device_cus() {
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    if (cache[dev] > 0) return cache[dev];
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    cache[dev] = n;
+    return n;
+}
+
+int balanced_zc(int nz, long long cols, int wg_per_cu) {
+    const long long slots = (long long)device_cus() * wg_per_cu;
+    // a large lattice fills the chip many times over whatever the chunk:
+    // chunks of nz * cols / 4096 slabs (at least 4, so that the extra slab
+    // below each chunk stays cheap), which keep the tail of the launch short
+    if ((long long)nz * cols >= 32 * slots) {
+        long long zc = ((long long)nz * cols + 4095) / 4096;
+        if (zc < 4) zc = 4;
+        return (int)(zc > nz ? nz : zc);
+    }
+    // otherwise the number of rounds of resident workgroups decides: the
+    // chunk minimising rounds x (zc + 1) slab passes (the extra one for the
+    // chunk's lower bond), the smaller chunk on a tie
+    int best = nz;
+    long long best_cost = -1;
+    for (int zc = 1; zc <= nz; ++zc) {
+        const long long chunks = (nz + zc - 1) / zc;
+        const long long rounds = (cols * chunks + slots - 1) / slots;
+        const long long cost = rounds * (zc + 1);
+        if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = zc; }
+    }
+    return best;
 }
 
 const FusedShape kFusedShapes[kNumFusedShapes] = {{32, 8}, {64, 4}, {16, 16}, {50, 5}, {20, 12}};

@@ -39,7 +39,7 @@ hipError_t launch_energy(const StepArgs<T> &a, double *partials, hipStream_t s);
 
 // Fused path: one LDS-tiled kernel per step.  cfg.shape indexes
 // kFusedShapes (tile TX x TY); cfg.zc is the z chunk per workgroup (0 picks
-// fused_default_zc).
+// balanced_zc for the kernel's occupancy, fused_wg_per_cu).
 struct FusedShape {
     int tx, ty;
 };
@@ -49,7 +49,13 @@ struct FusedCfg {
     int shape;
     int zc;
 };
-int fused_default_zc(int nz, long long cols);
+// Compute units of the current device (256 if it cannot be queried).
+int device_cus();
+// Default z chunk of a column-marching kernel with cols tile columns and
+// wg_per_cu resident workgroups per CU.
+int balanced_zc(int nz, long long cols, int wg_per_cu);
+// Resident workgroups per CU of the fused step kernel (register-bound).
+constexpr int fused_wg_per_cu(int tsize) { return tsize == 4 ? 3 : 1; }
 // Largest palette whose tables fit the fused kernel's LDS.
 constexpr int kFusedMaxMat = 16;
 // The fused and batched kernels address all state words of one state array
