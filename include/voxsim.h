@@ -144,6 +144,22 @@ int vx_step(vx_handle h, int64_t n);
  * next vx_step or vx_status.  Errors: VX_ESTATE before bind. */
 int vx_step_enqueue(vx_handle h, int64_t n);
 
+/* Record state word `word` (0..12 in the order u_x, u_y, u_z, q_w, q_x,
+ * q_y, q_z, P_x, P_y, P_z, L_x, L_y, L_z; u the displacement from the rest
+ * position) of the n cells listed in `cells` (a DEVICE array of int32 cell
+ * indices, x + nx (y + ny z)) from the current state into `out` (a DEVICE
+ * array of n values of the state precision: float for 32, double for 64).
+ * Both arrays stay owned by the caller.  This is the sampling step of a long
+ * run such as the impulse-response record behind a modal spectrum (the
+ * paper's dynamic validation, section Validation, Table 2): one small kernel
+ * on the handle's stream, no host synchronisation, so it may be captured in
+ * a HIP graph together with vx_step_enqueue (the captured probe reads the
+ * ping-pong buffer that is current at capture time, so a captured
+ * step-then-probe sequence stays consistent only for an even step count).
+ * An index outside the lattice reads as NaN.  Errors: VX_EINVAL for n < 0,
+ * a word outside 0..12 or NULL arrays with n > 0; VX_ESTATE before bind. */
+int vx_probe(vx_handle h, const int32_t *cells, int32_t n, int32_t word, void *out);
+
 /* Wait for the handle's stream and report the device status: VX_OK,
  * VX_EUNSTABLE (a non-finite value was produced) or VX_EOVERFLOW. */
 int vx_status(vx_handle h);

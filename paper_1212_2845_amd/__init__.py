@@ -32,12 +32,14 @@ EXPORTED = ["vx_create", "vx_workspace_bytes", "vx_bind_workspace", "vx_set_fixe
             "vx_read_state", "vx_write_state", "vx_read_flags", "vx_get_dt", "vx_get_time",
             "vx_counters", "vx_candidates", "vx_set_kernel", "vx_set_fused_tile", "vx_get_fused_tile",
             "vx_autotune", "vx_time_kernel", "vx_destroy", "vx_last_error",
-            "vx_step_enqueue", "vx_status", "vx_energy", "vx_set_stiffness", "vx_set_density", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
+            "vx_step_enqueue", "vx_status", "vx_probe", "vx_energy", "vx_set_stiffness", "vx_set_density", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
             "vx_grad_backward",
             "vx_batch_create", "vx_batch_workspace_bytes", "vx_batch_bind_workspace", "vx_batch_step",
             "vx_batch_read_state", "vx_batch_write_state", "vx_batch_get_dt", "vx_batch_counters",
             "vx_batch_set_launch", "vx_batch_autotune", "vx_batch_destroy", "vx_batch_last_error"]
 
+# state words, in the order vx_probe numbers them
+WORDS = ["ux", "uy", "uz", "qw", "qx", "qy", "qz", "px", "py", "pz", "lx", "ly", "lz"]
 FUSED_SHAPES = [(32, 8), (64, 4), (16, 16), (50, 5), (20, 12)]
 
 
@@ -113,6 +115,7 @@ def lib():
     L.vx_energy.argtypes = [P, C.POINTER(C.c_double)]
     L.vx_step_enqueue.argtypes = [P, i64]
     L.vx_status.argtypes = [P]
+    L.vx_probe.argtypes = [P, P, i32, i32, P]
     L.vx_set_stiffness.argtypes = [P, P]
     L.vx_set_density.argtypes = [P, P]
     L.vx_grad_workspace_bytes.argtypes = [P, i64, i32, C.POINTER(u64)]
@@ -306,6 +309,18 @@ class Sim:
     def status(self):
         """Wait for the stream; raise on a non-finite state or overflow."""
         self._check(lib().vx_status(self.h))
+
+    def probe(self, cells, word, out):
+        """Enqueue a copy of state word ``word`` (0..12, see WORDS) of the
+        cells in the int32 device tensor ``cells`` into the device tensor
+        ``out`` (float32 or float64 as the state) without waiting."""
+        import torch
+        assert cells.is_cuda and out.is_cuda and cells.dtype == torch.int32
+        assert out.dtype == (torch.float64 if self.precision == 64 else torch.float32)
+        assert cells.is_contiguous() and out.is_contiguous() and out.numel() >= cells.numel()
+        self.bind()
+        self._check(lib().vx_probe(self.h, C.c_void_p(cells.data_ptr()), int(cells.numel()), int(word),
+                                   C.c_void_p(out.data_ptr())))
 
     @property
     def dt(self):

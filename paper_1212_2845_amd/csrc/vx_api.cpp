@@ -577,6 +577,19 @@ int vx_energy(vx_handle h, double out[10]) {
     return h->precision == 64 ? energy<double>(h, out) : energy<float>(h, out);
 }
 
+int vx_probe(vx_handle h, const int32_t *cells, int32_t n, int32_t word, void *out) {
+    if (!h || n < 0 || word < 0 || word >= N_WORDS || (n > 0 && (!cells || !out))) return VX_EINVAL;
+    if (!h->bound) return fail(h, VX_ESTATE, "vx_probe before vx_bind_workspace");
+    const char *st = h->ws + h->L.state[h->cur];
+    if (h->precision == 64)
+        HIP_OK(h, launch_probe<double>((const double *)st, h->ncell, h->ncell, cells, n, word, (double *)out,
+                                       h->stream));
+    else
+        HIP_OK(h, launch_probe<float>((const float *)st, h->ncell, h->ncell, cells, n, word, (float *)out,
+                                      h->stream));
+    return VX_OK;
+}
+
 int vx_step_enqueue(vx_handle h, int64_t n) {
     if (!h || n < 0) return VX_EINVAL;
     if (!h->bound) return fail(h, VX_ESTATE, "vx_step_enqueue before vx_bind_workspace");

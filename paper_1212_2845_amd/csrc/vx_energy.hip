@@ -108,7 +108,34 @@ __global__ void __launch_bounds__(kEnergyThreads) k_energy(StepArgs<T> a, double
     if (threadIdx.x < kEnergyWords) partials[(long long)blockIdx.x * kEnergyWords + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// One state word of listed cells into a device array: the recording step of
+// a long run (e.g. a probe voxel's displacement every few steps for a modal
+// spectrum) without a host synchronisation.  An index outside the lattice
+// reads as NaN.
+template <typename T>
+__global__ void __launch_bounds__(256) k_probe(const T *__restrict__ state, long long stride, long long ncell,
+                                               const int32_t *__restrict__ cells, int n, int word,
+                                               T *__restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int32_t c = cells[i];
+    out[i] = (c >= 0 && (long long)c < ncell) ? state[(long long)word * stride + c] : T(__builtin_nan(""));
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_probe(const T *state, long long stride, long long ncell, const int32_t *cells, int n, int word,
+                        T *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_probe<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(state, stride, ncell, cells, n, word, out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_probe<float>(const float *, long long, long long, const int32_t *, int, int, float *,
+                                        hipStream_t);
+template hipError_t launch_probe<double>(const double *, long long, long long, const int32_t *, int, int,
+                                         double *, hipStream_t);
 
 int energy_blocks(long long ncell) { return (int)((ncell + kEnergyThreads - 1) / kEnergyThreads); }
 

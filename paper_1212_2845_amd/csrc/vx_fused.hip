@@ -196,19 +196,18 @@ __device__ __forceinline__ void issue_pre(const StepArgs<T> &a, const StateBuf<T
     p.r = sb_load(sb, c);
 }
 
-// Strain and kinematics of a prefetched cell, computed for an empty cell
-// too (material 0's constants, results unused): assigning every field
-// unconditionally lets the compiler keep the prefetched words in the
-// registers of o instead of copying them.
+// Strain and kinematics of a prefetched cell.
 template <typename T>
 __device__ __forceinline__ void finish_pre(const StepArgs<T> &a, const Tables<T> &tb, unsigned c, const Pre<T> &p,
                                            Own<T> &o) {
     o.m = p.m;
-    o.fl = p.fl;
-    o.r = p.r;
-    const MatConst<T> &mc = tb.mat[p.m];
-    o.eps = voxel_strain(a, c, p.fl, mc.cte);
-    o.k = kin_of(p.r, mc, o.eps);
+    if (p.m) {
+        o.fl = p.fl;
+        o.r = p.r;
+        const MatConst<T> &mc = tb.mat[p.m];
+        o.eps = voxel_strain(a, c, p.fl, mc.cte);
+        o.k = kin_of(p.r, mc, o.eps);
+    }
 }
 
 // Load the material tables into LDS (all threads of the workgroup; the
@@ -289,7 +288,7 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
         if (ring) {
             uint8_t mr = 0;
             if (ring_in) {
-                Own<T> R;
+                Own<T> R{};
                 finish_pre(a, tb, ring_col + (unsigned)z * nxy, r, R);
                 mr = R.m;
                 if (mr) put_kin<T, NR>(sm.kin, ring_slot, R.k);
@@ -323,14 +322,9 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
     // that they arrive during the bond evaluations, and which is staged in
     // LDS once every thread is past its bonds of slab z
     auto slab = [&](Own<T> &cur, Own<T> &nxt, int z) __attribute__((always_inline)) {
-        // a cell not loaded reads as empty with no flags (finish_pre then
-        // reads nothing more from memory; its state words are not used)
-        Pre<T> pn;
-        pn.m = 0;
-        pn.fl = 0;
+        Pre<T> pn{};
         if (inxy && z + 1 < a.nz) issue_pre(a, sb, col + (unsigned)(z + 1) * nxy, pn);
         rp.m = 0;
-        rp.fl = 0;
         if (ring_in && z + 1 < z1) issue_pre(a, sb, ring_col + (unsigned)(z + 1) * nxy, rp);
         __syncthreads();
 
@@ -369,7 +363,7 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
         }
         finish_pre(a, tb, col + (unsigned)(z + 1) * nxy, pn, nxt);
         const bool has_zb = cur.m && nxt.m;
-        BondOut<T> oz;
+        BondOut<T> oz{};
         if (has_zb) oz = bond_eval<T, 2>(cur.k, Rc, nxt.k, tb.bond(cur.m, nxt.m), C);
         __syncthreads();
 

@@ -36,6 +36,9 @@ constexpr int kEnergyWords = 10;   // KE, U_elastic, U_gravity, U_floor, P (3), 
 int energy_blocks(long long ncell);
 template <typename T>
 hipError_t launch_energy(const StepArgs<T> &a, double *partials, hipStream_t s);
+template <typename T>
+hipError_t launch_probe(const T *state, long long stride, long long ncell, const int32_t *cells, int n, int word,
+                        T *out, hipStream_t s);
 
 // Fused path: one LDS-tiled kernel per step.  cfg.shape indexes
 // kFusedShapes (tile TX x TY); cfg.zc is the z chunk per workgroup (0 picks

@@ -281,3 +281,24 @@ def test_batch_state_span_limit():
     with pytest.raises(vx.VoxsimError) as e:
         vx.Batch([np.zeros((1, 1, lim), np.uint8)], mats, precision=64)
     assert e.value.code == vx.VX_EINVAL
+
+
+def test_modal_helpers():
+    # the beam formula at rho = 1 kg/m^3, L = 20 mm gives the printed
+    # beam-theory column of Table 2 (section Validation), to its 4-5 digits
+    import json
+    from paper_1212_2845_amd import modal
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "table2_modes.json")))
+    l = 1e-3
+    f = modal.beam_frequencies(1e6, l ** 4 / 12.0, 1.0 * l * l, 0.02, n=6)
+    for a, b in zip(f, g["beam_theory_hz"]):
+        assert abs(a / b - 1.0) < 5e-4, (f, g["beam_theory_hz"])
+    # peak finder on tones between FFT bins: 0.13 s of samples, 7.7 Hz bins
+    dt, n = 6.5e-6, 20000
+    t = np.arange(n) * dt
+    tones = [403.7, 2531.2, 7081.3]
+    x = sum(a * np.sin(2 * np.pi * ft * t + p) for ft, a, p in zip(tones, [1.0, 0.1, 0.01], [0.3, 1.0, 2.0]))
+    got = modal.peaks(x, dt, 3)
+    assert len(got) == 3
+    for a, b in zip(got, tones):
+        assert abs(a / b - 1.0) < 2e-4, (got, tones)

@@ -58,6 +58,23 @@ def cantilever(nx=20, ny=4, nz=4, steps=10000):
     return _workload(grid, [EMPTY, _mat(1e6)], params, steps, fixed=fixed, name="cantilever_20x4x4")
 
 
+def thin_beam(nx=20, rho=1.0, zeta_bond=0.01, tip_velocity=1e-3, steps=820000):
+    """The paper's dynamic validation beam: nx x 1 x 1 voxels of 1 mm, E =
+    1 MPa, nu = 0.35, the x = 0 voxel fixed, no gravity and only the trace
+    bond damping zeta_bond; the impulse at the free end is an initial z
+    velocity of the tip voxel.  rho = 1 kg/m^3 is the reading under which
+    the paper's beam-theory frequencies follow from its formula (the density
+    is not stated)."""
+    grid = np.ones((1, 1, nx), np.uint8)
+    fixed = np.zeros(nx, np.uint8)
+    fixed[0] = 1
+    v = np.zeros((nx, 3))
+    v[nx - 1, 2] = tip_velocity
+    params = _base_params(zeta_bond=zeta_bond)
+    return _workload(grid, [EMPTY, _mat(1e6, rho=rho)], params, steps, fixed=fixed, velocity=v,
+                     name="thin_beam_%dx1x1" % nx)
+
+
 def random_block(n=100, seed=2, steps=1000, drop_height=5e-3, impact=False):
     """n^3 cells iid {empty 0.1, soft 1 MPa 0.45, stiff 100 MPa 0.45} on a floor
     with friction.  ``impact=False``: bottom at ``drop_height`` at rest.
