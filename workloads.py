@@ -242,6 +242,24 @@ def grad_object(seed, n=4, scenario="free", steps=200, temp_freq=500.0):
     return w
 
 
+def walker(nx=8, ny=2, nz=2, seed=6, freq=100.0, steps=6000):
+    """A soft bar (E = 1 MPa, rho = 1000, CTE 0.01) lying on the floor under
+    gravity with friction (mu_s 1, mu_d 0.5), every voxel actuated at 20 K
+    and freq Hz with its own phase, U[0, 2 pi) from the seed: the object of
+    the gradient-driven design loop (phases tuned for travel along +x).
+    Returns a workload plus ``E`` and ``rho`` per cell."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    grid = np.ones((nz, ny, nx), np.uint8)
+    mats = [EMPTY, _mat(1e6, cte=0.01)]
+    params = _base_params(gravity=9.81, zeta_bond=0.5, zeta_col=0.5, floor_on=1, temp_freq=freq)
+    n = grid.size
+    w = _workload(grid, mats, params, steps, amp=np.full(n, 20.0), phase=rng.uniform(0.0, 2 * np.pi, n),
+                  name="walker_%dx%dx%d" % (nx, ny, nz))
+    w["E"] = np.full(n, 1e6)
+    w["rho"] = np.full(n, 1000.0)
+    return w
+
+
 def design_lattice(count=64, size=20, gap=1, seed=5, steps=5000):
     """Many full size^3 design blocks in one lattice, on a sqrt(count) x
     sqrt(count) layout in x-y separated by ``gap`` empty cells (so no bonds
