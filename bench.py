@@ -2,7 +2,8 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload random_block_100]
                     [--precision 32|64] [--kernel fused|split] [--no-cpu] [--no-fp64]
-                    [--no-hbm-leg] [--no-autotune]
+                    [--no-hbm-leg] [--no-batch-leg] [--no-collision-leg] [--no-adjoint-leg]
+                    [--no-autotune]
 
 Headline workload: a 100^3 lattice whose cells are drawn from a seed as empty
 (p = 0.1), soft 1 MPa (p = 0.45) or stiff 100 MPa (p = 0.45), density 1000,
@@ -11,6 +12,12 @@ whole hot path (actuation, every bond, gather, floor/friction, integrate) over
 the lattice.  Its state (52 MB in FP32) fits the GPU's 256 MB last-level cache,
 so a second leg runs the HBM-resident case: a 256^3 lattice of 4 materials
 assigned from 64 seeded Voronoi blobs, thermal actuation, self-collision on.
+
+Further legs: FP64 on the headline lattice; 4096 batched objects in one
+persistent launch against the same objects one at a time; the iteration
+rates of the paper's four self-collision schemes on a clapper; the
+differentiable rollout of the 64 x 20^3 design lattice (forward + reverse
+against the plain forward); the oracle on one host core.
 
 The state is resident on the GPU before timing starts.  Prints one JSON line.
 voxel-steps/s = filled voxels x steps / wall time of the K timed steps (HIP
@@ -268,6 +275,35 @@ def time_adjoint(steps=5000, K=100):
                     "checkpoint and the host copies of the adjoint in and the gradients out"}
 
 
+def time_collision_schemes(steps=5000):
+    """Iteration rates of the self-collision schemes of the paper's Table 3
+    (candidates from all voxels or the surface; rebuilt every step or by the
+    horizon rule) on the clapper, FP32, wall time of `steps` steps each."""
+    import torch
+    import paper_1212_2845_amd as vx
+    import workloads
+    w = workloads.clapper(steps=steps)
+    out = {"workload": w["name"], "voxels": int((w["grid"] > 0).sum()), "steps": steps, "dtype": "f32",
+           "unit": "iterations/s", "note": "wall time of vx_step over the steps, host launches included"}
+    rates = {}
+    for all_voxels, every, name in [(1, 1, "all+every"), (0, 1, "surf+every"), (1, 0, "all+horizon"),
+                                    (0, 0, "surf+horizon")]:
+        s = vx.Sim(w["grid"], w["materials"], precision=32, stream=torch.cuda.current_stream().cuda_stream,
+                   **w["params"])
+        s.set_collision_mode(all_voxels, every)
+        s.set_fixed(w["fixed"])
+        s.step(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        rates[name] = steps / (time.perf_counter() - t0)
+        rates[name + " rebuilds"] = s.counters()["rebuilds"]
+        del s
+    out["rates"] = rates
+    return out
+
+
 def copy_probe(mib=1024, reps=5):
     """Achievable HBM rate on this device: a plain device-to-device copy of
     mib MiB (read once, written once), best of reps, timed with HIP events."""
@@ -329,6 +365,7 @@ def main():
     ap.add_argument("--no-hbm-leg", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batch-leg", action="store_true")
+    ap.add_argument("--no-collision-leg", action="store_true")
     ap.add_argument("--no-adjoint-leg", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
     ap.add_argument("--batch-objects", type=int, default=4096)
@@ -402,6 +439,9 @@ def main():
     if not args.no_batch_leg:
         log("batched leg: %d objects, %d steps" % (args.batch_objects, args.batch_steps))
         out["batched"] = time_batch(args.batch_objects, args.batch_steps, args.one_by_one_sample)
+    if not args.no_collision_leg:
+        log("collision-scheme leg: clapper")
+        out["collision_schemes"] = time_collision_schemes()
     if not args.no_adjoint_leg:
         log("adjoint leg: design lattice, %d steps" % args.adjoint_steps)
         out["adjoint"] = time_adjoint(args.adjoint_steps)

@@ -204,6 +204,19 @@ int vx_candidates(vx_handle h, int32_t *cell_a, int32_t *cell_b, int32_t max_pai
  * Blocks until the result is on the host.  Errors: VX_ESTATE before bind. */
 int vx_energy(vx_handle h, double out[10]);
 
+/* Self-collision detection scheme (section "Self collision detection and
+ * handling" and Table 3, "Speedup of self collision schemes"): all_voxels = 0
+ * takes only the surface voxels into the candidate search (default), 1 every
+ * filled voxel; every_step = 0 rebuilds the candidate lists only when the
+ * accumulated maximum motion could let an unlisted pair touch (the horizon
+ * rule, default), 1 before every step.  The schemes differ in cost, not in
+ * the contact forces as long as interior voxels stay out of contact.
+ * all_voxels can change only before vx_bind_workspace (it sizes the
+ * workspace); every_step at any time.  Effective only with
+ * self_collision_on.  Errors: VX_EINVAL for values other than 0/1,
+ * VX_ESTATE for an all_voxels change after bind. */
+int vx_set_collision_mode(vx_handle h, int32_t all_voxels, int32_t every_step);
+
 /* Select the step implementation: 0 = fused LDS-tiled kernel (default;
  * palettes of more than 16 materials, parameter mode and lattices whose
  * state array (13 words per cell) spans 2 GiB or more always use the split

@@ -32,7 +32,7 @@ EXPORTED = ["vx_create", "vx_workspace_bytes", "vx_bind_workspace", "vx_set_fixe
             "vx_read_state", "vx_write_state", "vx_read_flags", "vx_get_dt", "vx_get_time",
             "vx_counters", "vx_candidates", "vx_set_kernel", "vx_set_fused_tile", "vx_get_fused_tile",
             "vx_autotune", "vx_time_kernel", "vx_destroy", "vx_last_error",
-            "vx_step_enqueue", "vx_status", "vx_probe", "vx_energy", "vx_set_stiffness", "vx_set_density", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
+            "vx_step_enqueue", "vx_status", "vx_probe", "vx_set_collision_mode", "vx_energy", "vx_set_stiffness", "vx_set_density", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
             "vx_grad_backward",
             "vx_batch_create", "vx_batch_workspace_bytes", "vx_batch_bind_workspace", "vx_batch_step",
             "vx_batch_read_state", "vx_batch_write_state", "vx_batch_get_dt", "vx_batch_counters",
@@ -116,6 +116,7 @@ def lib():
     L.vx_step_enqueue.argtypes = [P, i64]
     L.vx_status.argtypes = [P]
     L.vx_probe.argtypes = [P, P, i32, i32, P]
+    L.vx_set_collision_mode.argtypes = [P, i32, i32]
     L.vx_set_stiffness.argtypes = [P, P]
     L.vx_set_density.argtypes = [P, P]
     L.vx_grad_workspace_bytes.argtypes = [P, i64, i32, C.POINTER(u64)]
@@ -309,6 +310,12 @@ class Sim:
     def status(self):
         """Wait for the stream; raise on a non-finite state or overflow."""
         self._check(lib().vx_status(self.h))
+
+    def set_collision_mode(self, all_voxels=False, every_step=False):
+        """Self-collision scheme (see vx_set_collision_mode): candidates from
+        all filled voxels or the surface only; rebuilt every step or by the
+        horizon rule."""
+        self._check(lib().vx_set_collision_mode(self.h, int(bool(all_voxels)), int(bool(every_step))))
 
     def probe(self, cells, word, out):
         """Enqueue a copy of state word ``word`` (0..12, see WORDS) of the

@@ -28,6 +28,15 @@ static long long cell_of(const vx_sim *h, int x, int y, int z) {
     return (long long)x + (long long)h->nx * ((long long)y + (long long)h->ny * z);
 }
 
+// Collision hash table: a power of two >= 2 x the number of cells taking
+// part, and the scan scratch it needs.
+static void size_collision_table(vx_sim *h) {
+    int ts = 1;
+    while (ts < 2 * (int)std::max<size_t>(h->coll_cells.size(), 1)) ts <<= 1;
+    h->table_size = ts;
+    h->scan_tmp_bytes = h->p.self_collision_on ? scan_temp_bytes(ts + 1) : 0;
+}
+
 static void compute_layout(vx_sim *h) {
     const uint64_t n = (uint64_t)h->ncell, ts = h->tsize;
     uint64_t off = 0;
@@ -48,7 +57,7 @@ static void compute_layout(vx_sim *h) {
     L.forced_cells = take((uint64_t)h->forced_cap * 4);
     L.forced_F = take((uint64_t)h->forced_cap * 3 * ts);
     const bool col = h->p.self_collision_on != 0;
-    const uint64_t ns = col ? h->surf_cells.size() : 0;
+    const uint64_t ns = col ? h->coll_cells.size() : 0;
     L.contact_F = take(col ? 3 * n * ts : 0);
     L.surf_cells = take(ns * 4);
     L.cand = take(ns * (uint64_t)h->cand_cap * 4);
@@ -420,11 +429,8 @@ int vx_create(const uint8_t *grid, int32_t nx, int32_t ny, int32_t nz, const vx_
     // rest state
     h->state0.assign((size_t)N_WORDS * ncell, 0.0);
     for (long long c = 0; c < ncell; ++c) h->state0[W_QW * ncell + c] = 1.0;
-    // collision hash table: power of two >= 2 x surface count
-    int ts = 1;
-    while (ts < 2 * (int)std::max<size_t>(h->surf_cells.size(), 1)) ts <<= 1;
-    h->table_size = ts;
-    h->scan_tmp_bytes = p.self_collision_on ? scan_temp_bytes(ts + 1) : 0;
+    h->coll_cells = h->surf_cells;
+    size_collision_table(h);
     update_cmax(h);
     *out = h;
     return VX_OK;
@@ -452,9 +458,9 @@ int vx_bind_workspace(vx_handle h, void *device_ptr, uint64_t bytes) {
     sc.rebuild_flag = h->p.self_collision_on ? 1u : 0u;
     HIP_OK(h, hipMemcpyAsync(h->ws + h->L.scalars, &sc, sizeof(sc), hipMemcpyHostToDevice, h->stream));
     if (h->p.self_collision_on) {
-        HIP_OK(h, hipMemcpyAsync(h->ws + h->L.surf_cells, h->surf_cells.data(), h->surf_cells.size() * 4,
+        HIP_OK(h, hipMemcpyAsync(h->ws + h->L.surf_cells, h->coll_cells.data(), h->coll_cells.size() * 4,
                                  hipMemcpyHostToDevice, h->stream));
-        std::vector<int> zeros(h->surf_cells.size(), 0);
+        std::vector<int> zeros(h->coll_cells.size(), 0);
         HIP_OK(h, hipMemcpyAsync(h->ws + h->L.cand_n, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice, h->stream));
         std::vector<int> zt(h->table_size, 0);
         HIP_OK(h, hipMemcpyAsync(h->ws + h->L.bfill, zt.data(), zt.size() * 4, hipMemcpyHostToDevice, h->stream));
@@ -759,7 +765,7 @@ int vx_candidates(vx_handle h, int32_t *cell_a, int32_t *cell_b, int32_t max_pai
     if (!h || !n_pairs || max_pairs < 0) return VX_EINVAL;
     *n_pairs = 0;
     if (!h->bound || !h->p.self_collision_on) return VX_OK;
-    const size_t ns = h->surf_cells.size();
+    const size_t ns = h->coll_cells.size();
     std::vector<int> cand(ns * h->cand_cap), cn(ns);
     HIP_OK(h, hipMemcpyAsync(cand.data(), h->ws + h->L.cand, cand.size() * 4, hipMemcpyDeviceToHost, h->stream));
     HIP_OK(h, hipMemcpyAsync(cn.data(), h->ws + h->L.cand_n, cn.size() * 4, hipMemcpyDeviceToHost, h->stream));
@@ -768,11 +774,30 @@ int vx_candidates(vx_handle h, int32_t *cell_a, int32_t *cell_b, int32_t max_pai
     for (size_t i = 0; i < ns; ++i)
         for (int j = 0; j < cn[i]; ++j) {
             const int other = cand[i * h->cand_cap + j];
-            if (other <= h->surf_cells[i]) continue;
-            if (k < max_pairs && cell_a && cell_b) { cell_a[k] = h->surf_cells[i]; cell_b[k] = other; }
+            if (other <= h->coll_cells[i]) continue;
+            if (k < max_pairs && cell_a && cell_b) { cell_a[k] = h->coll_cells[i]; cell_b[k] = other; }
             ++k;
         }
     *n_pairs = k;
+    return VX_OK;
+}
+
+int vx_set_collision_mode(vx_handle h, int32_t all_voxels, int32_t every_step) {
+    if (!h || (all_voxels != 0 && all_voxels != 1) || (every_step != 0 && every_step != 1)) return VX_EINVAL;
+    if (h->bound && (all_voxels != 0) != h->coll_all)
+        return fail(h, VX_ESTATE, "the voxels taking part in collision detection are fixed at bind");
+    h->coll_every = every_step != 0;
+    if (!h->bound && (all_voxels != 0) != h->coll_all) {
+        h->coll_all = all_voxels != 0;
+        if (h->coll_all) {
+            h->coll_cells.clear();
+            for (long long c = 0; c < h->ncell; ++c)
+                if (h->grid[c]) h->coll_cells.push_back((int)c);
+        } else {
+            h->coll_cells = h->surf_cells;
+        }
+        size_collision_table(h);
+    }
     return VX_OK;
 }
 

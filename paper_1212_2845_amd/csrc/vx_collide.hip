@@ -262,7 +262,7 @@ __global__ void k_motion(StepArgs<T> a, CollideArgs c) {
     *c.vmax_bits = 0ull;
     const double m = *c.macc + v * (double)a.dt;
     *c.macc = m;
-    if (2.0 * m >= c.threshold) *c.rebuild_flag = 1u;
+    if (c.every || 2.0 * m >= c.threshold) *c.rebuild_flag = 1u;
 }
 
 }  // namespace

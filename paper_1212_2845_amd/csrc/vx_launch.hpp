@@ -99,8 +99,9 @@ hipError_t launch_batch(const BatchArgs<T> &b, int n_wg, hipStream_t s);
 
 // Collision support (self-collision on).
 struct CollideArgs {
-    const int *surf_cells;       // surface voxel cells, ascending
+    const int *surf_cells;       // cells taking part (surface voxels, or all filled ones), ascending
     int n_surf;
+    int every;                   // 1: rebuild the candidates before every step
     int cap;                     // candidate slots per surface voxel
     int *cand;                   // n_surf x cap partner cells, ascending
     int *cand_n;                 // n_surf

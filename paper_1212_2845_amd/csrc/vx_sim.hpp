@@ -78,6 +78,11 @@ struct vx_sim {
     std::vector<double> forced_F;
     int forced_cap = 0;
     std::vector<int> surf_cells;
+    // collision detection: the cells that take part (the surface voxels, or
+    // every filled voxel), and whether candidates are rebuilt every step
+    // instead of when the accumulated motion reaches the horizon rule
+    std::vector<int> coll_cells;
+    bool coll_all = false, coll_every = false;
     long long nvox = 0;
     double dt = 0.0;
     long long step = 0;
@@ -184,7 +189,8 @@ inline vx::CollideArgs make_collide(vx_sim *h) {
     CollideArgs c{};
     char *ws = h->ws;
     c.surf_cells = (const int *)(ws + h->L.surf_cells);
-    c.n_surf = (int)h->surf_cells.size();
+    c.n_surf = (int)h->coll_cells.size();
+    c.every = h->coll_every ? 1 : 0;
     c.cap = h->cand_cap;
     c.cand = (int *)(ws + h->L.cand);
     c.cand_n = (int *)(ws + h->L.cand_n);

@@ -242,6 +242,29 @@ def grad_object(seed, n=4, scenario="free", steps=200, temp_freq=500.0):
     return w
 
 
+def clapper(freq=20.0, cte=0.02, amp=30.0, gap=5, steps=5000):
+    """A clapper for the collision-scheme comparison (section "Speedup of
+    self collision schemes"; the paper's geometry is only pictured): a
+    two-layer base, fixed at its bottom layer, carrying two 12-voxel arms
+    across a gap of ``gap`` cells, each arm a bilayer whose outer layer has
+    CTE +cte and inner layer -cte, so that the temperature signal (amp K,
+    freq Hz) bends the arms toward each other and apart.  All materials
+    1 MPa, self-collision on, no gravity.  cte 0.02 and 30 K are the paper's
+    values (60% expansion and contraction); the frequency is not given."""
+    nx, ny, nz = gap + 8, 3, 14
+    g = np.zeros((nz, ny, nx), np.uint8)
+    g[0:2, :, :] = 1
+    g[2:, :, 1] = 2
+    g[2:, :, 2] = 3
+    g[2:, :, nx - 2] = 2
+    g[2:, :, nx - 3] = 3
+    mats = [EMPTY, _mat(1e6), _mat(1e6, cte=cte), _mat(1e6, cte=-cte)]
+    params = _base_params(zeta_bond=0.5, zeta_col=0.5, self_collision_on=1, temp_amp=amp, temp_freq=freq)
+    _, _, z = cell_coords(g.shape)
+    fixed = ((z == 0) & (g.reshape(-1) > 0)).astype(np.uint8)
+    return _workload(g, mats, params, steps, fixed=fixed, name="clapper")
+
+
 def walker(nx=8, ny=2, nz=2, seed=6, freq=100.0, steps=6000):
     """A soft bar (E = 1 MPa, rho = 1000, CTE 0.01) lying on the floor under
     gravity with friction (mu_s 1, mu_d 0.5), every voxel actuated at 20 K
