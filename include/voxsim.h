@@ -204,6 +204,30 @@ int vx_candidates(vx_handle h, int32_t *cell_a, int32_t *cell_b, int32_t max_pai
  * Blocks until the result is on the host.  Errors: VX_ESTATE before bind. */
 int vx_energy(vx_handle h, double out[10]);
 
+/* Linear statics: the direct-stiffness solution K x = f of the lattice in
+ * its rest configuration (section Validation, the "direct stiffness" column
+ * of Table 1), solved on the GPU in FP64 by Jacobi-preconditioned conjugate
+ * gradients without assembling K.  Every face-adjacent filled pair is the
+ * 12-DOF beam element of Eq. (7) with the composite moduli of Eq. (1)-(2)
+ * and the section constants of Eq. (8)-(12); the moduli are those the step
+ * uses (the palette's, or the per-cell E of vx_set_stiffness, with the
+ * palette's Poisson ratio); the voxels of vx_set_fixed are clamped.
+ * F is the load, ncell x 3 N on the host (rows of empty or clamped cells are
+ * ignored).  u and theta (ncell x 3 each, host, either may be NULL) receive
+ * the displacement (m) and rotation (rad) of every cell, zero for empty and
+ * clamped ones.  The iteration stops once |r| <= rel_tol |f| (recursive
+ * residual, rel_tol > 0) or after max_iter iterations; *iters receives the
+ * count and *rel_residual the true |f - K x| / |f| (either may be NULL).
+ * `work` is a caller-owned device buffer of vx_static_workspace_bytes
+ * bytes, 256-byte aligned.  The state is not touched.  Blocks until done.
+ * Errors: VX_EINVAL for bad arguments, a non-finite load or a small or
+ * misaligned workspace; VX_ESTATE before bind; VX_EUNSTABLE when rel_tol
+ * was not reached (the outputs still hold the last iterate), e.g. for a
+ * body with no clamped voxel under a load with a net force. */
+int vx_static_workspace_bytes(vx_handle h, uint64_t *bytes);
+int vx_static_solve(vx_handle h, void *work, uint64_t work_bytes, const double *F, double rel_tol,
+                    int32_t max_iter, double *u, double *theta, int32_t *iters, double *rel_residual);
+
 /* Self-collision detection scheme (section "Self collision detection and
  * handling" and Table 3, "Speedup of self collision schemes"): all_voxels = 0
  * takes only the surface voxels into the candidate search (default), 1 every

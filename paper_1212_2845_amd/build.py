@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvoxsim.so")
 SOURCES = ["vx_api.cpp", "vx_grad.cpp", "vx_batch.cpp", "vx_split.hip", "vx_fused.hip", "vx_collide.hip",
-           "vx_adjoint.hip", "vx_adjoint_fused.hip", "vx_energy.hip"]
+           "vx_adjoint.hip", "vx_adjoint_fused.hip", "vx_energy.hip", "vx_static.hip", "vx_statics.cpp"]
 HEADERS = ["vx_types.hpp", "vx_device.hpp", "vx_launch.hpp", "vx_host.hpp", "vx_sim.hpp", "vx_adjoint.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

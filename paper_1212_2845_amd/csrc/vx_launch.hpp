@@ -59,6 +59,26 @@ int device_cus();
 int balanced_zc(int nz, long long cols, int wg_per_cu);
 // Resident workgroups per CU of the fused step kernel (register-bound).
 constexpr int fused_wg_per_cu(int tsize) { return tsize == 4 ? 3 : 1; }
+// Linear statics (matrix-free conjugate gradients): the lattice and the
+// per-cell moduli of the direct-stiffness operator.
+struct StaticArgs {
+    int nx, ny, nz;
+    long long n;                 // cells
+    double l;
+    const uint8_t *mat;          // material per cell (0 = empty)
+    const uint8_t *fixed;        // 1 = clamped
+    const double *E, *G;         // Young's and shear modulus per cell
+};
+int static_blocks(long long ncell);
+hipError_t launch_static_diag(const StaticArgs &s, double *diag, hipStream_t st);
+hipError_t launch_static_start(const StaticArgs &s, const double *f, const double *diag, double *x, double *r,
+                               double *z, double *p, double *partials, hipStream_t st);
+hipError_t launch_static_apply(const StaticArgs &s, const double *p, double *q, double *partials, hipStream_t st);
+hipError_t launch_static_step(const StaticArgs &s, double alpha, const double *p, const double *q,
+                              const double *diag, double *x, double *r, double *z, double *partials,
+                              hipStream_t st);
+hipError_t launch_static_dir(long long ncell, double beta, const double *z, double *p, hipStream_t st);
+
 // Largest palette whose tables fit the fused kernel's LDS.
 constexpr int kFusedMaxMat = 16;
 // The fused and batched kernels address all state words of one state array

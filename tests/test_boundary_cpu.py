@@ -302,3 +302,20 @@ def test_modal_helpers():
     assert len(got) == 3
     for a, b in zip(got, tones):
         assert abs(a / b - 1.0) < 2e-4, (got, tones)
+
+
+def test_static_solve_workspace_and_state_errors():
+    s = vx.Sim(np.ones((2, 3, 4), np.uint8), [workloads.EMPTY, M1])
+    n = C.c_uint64()
+    L = vx.lib()
+    assert L.vx_static_workspace_bytes(s.h, C.byref(n)) == vx.VX_OK
+    ncell = 24
+    # moduli (2 x 8 B), clamp mask (1 B), load, x, r, z, p, q, diagonal (7 x 48 B) per cell
+    assert n.value >= ncell * (16 + 1 + 7 * 48)
+    F = np.zeros((ncell, 3))
+    it = C.c_int32(); res = C.c_double()
+    rc = L.vx_static_solve(s.h, C.c_void_p(4096), n.value, F.ctypes.data_as(C.c_void_p), 1e-10, 100,
+                           None, None, C.byref(it), C.byref(res))
+    assert rc == vx.VX_ESTATE
+    assert L.vx_static_solve(s.h, C.c_void_p(4096), n.value, F.ctypes.data_as(C.c_void_p), 0.0, 100,
+                             None, None, None, None) == vx.VX_EINVAL
