@@ -148,3 +148,39 @@ def test_graph_captured_steps_replay_like_eager(collide):
         got = s.read_state()
         for k in ("u", "q", "v", "w"):
             assert np.array_equal(got[k], want[k]), (rep, k)
+
+
+def test_full_size_batch_sampled_against_oracle():
+    """The 4096-object batch of the benchmark (bounding boxes U{8..32}^3,
+    about 26M voxels, FP32) in the launch configuration bench.py times
+    (autotuned workgroup count, one persistent launch for all steps).  Four
+    objects (the largest, the smallest and two at random) start from a
+    perturbed state, the rest at rest on the floor; after 100 steps each of
+    the four equals the FP64 oracle run on that object alone, to the FP32
+    bar (largest displacement within 1e-4 relative)."""
+    objs = workloads.batch_objects(count=4096, seed=4, steps=100)
+    announce("full size batch 4096")
+    b = vx.Batch([o["grid"] for o in objs], objs[0]["materials"], precision=32, **objs[0]["params"])
+    b.bind()
+    b.autotune(steps=20)
+    sizes = np.array([int((o["grid"] > 0).sum()) for o in objs])
+    rng = np.random.Generator(np.random.PCG64(41))
+    picks = [int(sizes.argmax()), int(sizes.argmin())] + rng.choice(len(objs), 2, replace=False).tolist()
+    starts = {}
+    for i in picks:
+        starts[i] = perturbed_state(objs[i]["grid"].size, 300 + i, 1e-6, 1e-3, 0.5, 1e-3)
+        b.write_state(i, **starts[i])
+        starts[i] = b.read_state(i)      # the FP32-rounded input the oracle starts from
+    b.step(100)
+    for i in picks:
+        w = dict(objs[i])
+        w["state"] = starts[i]
+        o = build_oracle(w)
+        assert abs(o.dt / b.dt(i) - 1.0) < 1e-15
+        assert o.step(100) == 0
+        got, ref = b.read_state(i), o.read_state()
+        filled = objs[i]["grid"].reshape(-1) > 0
+        ug = np.linalg.norm(got["u"][filled], axis=1).max()
+        uo = np.linalg.norm(ref["u"][filled], axis=1).max()
+        e = compare(got, ref, filled)
+        assert abs(ug / uo - 1.0) < 1e-4 and e["u"] < 1e-3, (i, sizes[i], ug, uo, e)

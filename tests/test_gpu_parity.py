@@ -321,3 +321,44 @@ def test_full_size_blob_lattice_sampled(precision, tol):
             scale = max(np.abs(ref[k]).max(), np.abs(st[k][c]).max(), 1e-30)
             err = np.abs(out[k][c] - ref[k]).max() / scale
             assert err < tol, (c, k, err, out[k][c], ref[k])
+
+
+@pytest.mark.parametrize("precision,tol", [(64, 1e-10), (32, 1e-4)])
+def test_full_size_random_block_sampled(precision, tol):
+    """100^3 random block of the headline benchmark (same grid and
+    materials), placed on the floor and moving down at impact speed, in the
+    launch configuration bench.py times (fused kernel, autotuned tile): one
+    step from a perturbed state, so that about half of the bottom layer
+    penetrates the floor (penalty force, ground damping and Coulomb
+    friction), then 48 sampled filled voxels (24 of the bottom layer, corners,
+    the rest at random) recomputed one by one by the oracle on their
+    neighbourhood."""
+    n = 100
+    w = workloads.random_block(n=n, seed=2, impact=True)
+    ncell = n ** 3
+    announce("full size 100^3 impact p=%d" % precision)
+    st = perturbed_state(ncell, 99, 1e-6, 1e-3, 0.5, 1e-3)
+    st["v"] = st["v"] + w["velocity"]
+    g = vx.from_workload(w, precision=precision, kernel=vx.KERNEL_FUSED)
+    g.write_state(**st)
+    g.autotune(iters=1)
+    if precision == 32:
+        st = g.read_state()          # the FP32-rounded input both sides start from
+    g.step(1)
+    out = g.read_state()
+    filled = np.flatnonzero(w["grid"].reshape(-1) > 0)
+    bottom = filled[filled < n * n]
+    rng = np.random.Generator(np.random.PCG64(100))
+    picks = [c for c in (0, n - 1, n * n - 1, ncell - 1) if w["grid"].reshape(-1)[c] > 0]
+    picks += rng.choice(bottom, 24, replace=False).tolist()
+    picks += rng.choice(filled, 48 - len(picks), replace=False).tolist()
+    in_contact = 0
+    for c in picks:
+        x, y, z = c % n, (c // n) % n, c // (n * n)
+        in_contact += int(z == 0 and st["u"][c][2] < 0.0)
+        ref = _neighbourhood_oracle(w, st, int(c), n, n, n, g.dt)
+        for k in ("u", "v", "w", "q"):
+            scale = max(np.abs(ref[k]).max(), np.abs(st[k][c]).max(), 1e-30)
+            err = np.abs(out[k][c] - ref[k]).max() / scale
+            assert err < tol, (c, k, err, out[k][c], ref[k])
+    assert in_contact >= 5, in_contact

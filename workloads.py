@@ -77,14 +77,16 @@ def thin_beam(nx=20, rho=1.0, zeta_bond=0.01, tip_velocity=1e-3, steps=820000):
 
 def random_block(n=100, seed=2, steps=1000, drop_height=5e-3, impact=False):
     """n^3 cells iid {empty 0.1, soft 1 MPa 0.45, stiff 100 MPa 0.45} on a floor
-    with friction.  ``impact=False``: bottom at ``drop_height`` at rest.
-    ``impact=True``: bottom on the floor, moving down at the speed of a
-    ``drop_height`` free fall."""
+    with friction.  ``impact=False``: the bottom layer's centres at
+    ``drop_height``, at rest.  ``impact=True``: the bottom faces on the floor,
+    moving down at the speed of a ``drop_height`` free fall."""
     rng = np.random.Generator(np.random.PCG64(seed))
     grid = rng.choice(np.array([0, 1, 2], np.uint8), size=(n, n, n), p=[0.1, 0.45, 0.45])
     mats = [EMPTY, _mat(1e6), _mat(1e8)]
     g = 9.81
-    z0 = 0.0 if impact else drop_height
+    l = 1e-3
+    # origin = centre of cell (0, 0, 0); its bottom face lies half a voxel lower
+    z0 = 0.5 * l if impact else drop_height
     params = _base_params(gravity=g, zeta_bond=0.5, zeta_col=0.5, floor_on=1, origin=(0.0, 0.0, z0))
     vel = None
     if impact:
