@@ -17,7 +17,8 @@ Further legs: FP64 on the headline lattice; 4096 batched objects in one
 persistent launch against the same objects one at a time; the iteration
 rates of the paper's four self-collision schemes on a clapper; the
 differentiable rollout of the 64 x 20^3 design lattice (forward + reverse
-against the plain forward); the oracle on one host core.
+against the plain forward); the oracle on one host core, and on a sample of
+the batched objects across the host cores.
 
 The state is resident on the GPU before timing starts.  Prints one JSON line.
 voxel-steps/s = filled voxels x steps / wall time of the K timed steps (HIP
@@ -352,6 +353,41 @@ def cpu_baseline(w, budget_s=12.0, note=""):
                       % (n, nvox, w["name"], note)}
 
 
+def cpu_batch_baseline(count, sample_every=32, steps=60):
+    """The oracle (FP64) on a sample of the batched objects, one object per
+    thread across the host's cores (at most 16; the C oracle releases the GIL
+    while it steps), and the single-core rate of the same work."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    import workloads
+    objs = workloads.batch_objects(count=count, seed=4, steps=steps)[::sample_every]
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    threads = max(1, min(16, ncpu))
+
+    def make(o):
+        return oracle.Sim(o["grid"], o["materials"], **o["params"])
+
+    def run(sim):
+        t0 = time.perf_counter()
+        sim.step(steps)
+        return time.perf_counter() - t0
+
+    with ThreadPoolExecutor(threads) as ex:
+        sims = list(ex.map(make, objs))
+        nvox = sum(sim.num_voxels for sim in sims)
+        t0 = time.perf_counter()
+        busy = sum(ex.map(run, sims))
+        wall = time.perf_counter() - t0
+    return {"value": nvox * steps / wall, "unit": "voxel-steps/s", "cores": threads, "kind": "oracle",
+            "single_core_value": nvox * steps / busy,
+            "sample": "one in every %d of the %d objects (%d objects, %d voxels), %d steps each, FP64, one object "
+                      "per thread on %d threads; single_core_value: the same voxel-steps over the summed "
+                      "per-object step times" % (sample_every, count, len(objs), nvox, steps, threads)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -448,6 +484,11 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w)
+        if "batched" in out:
+            log("cpu baseline of the batched objects (oracle, all host cores)")
+            cb = cpu_batch_baseline(args.batch_objects)
+            out["batched"]["cpu_baseline"] = cb
+            out["batched"]["speedup_vs_cpu"] = out["batched"]["value"] / cb["value"]
     print(json.dumps(out), flush=True)
 
 
