@@ -362,3 +362,41 @@ def test_full_size_random_block_sampled(precision, tol):
             err = np.abs(out[k][c] - ref[k]).max() / scale
             assert err < tol, (c, k, err, out[k][c], ref[k])
     assert in_contact >= 5, in_contact
+
+
+_CROP = {}
+
+
+def _blob_crop():
+    """The 256^3 lattice's recipe cropped to 32^3 so that the oracle runs
+    all 1000 steps (4 materials on Voronoi blobs, the 5 Hz thermal actuation
+    from phase 0, self-collision on; the largest displacement reaches 9% of
+    a voxel), and the oracle's state after them (computed once for both
+    precisions)."""
+    if not _CROP:
+        w = workloads.blob_lattice(n=32, seed=3)
+        o = build_oracle(w)
+        assert o.step(1000) == 0
+        _CROP["w"], _CROP["ref"] = w, o.read_state()
+    return _CROP["w"], _CROP["ref"]
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_blob_lattice_crop_1000_steps(precision):
+    """1000 steps of the cropped blob lattice through the fused kernel with
+    an autotuned tile: FP64 within 1e-10 of the oracle, FP32 largest
+    displacement within 1e-4."""
+    w, ref = _blob_crop()
+    announce("blob lattice 32^3 x 1000 p=%d" % precision)
+    g = build_gpu(w, precision=precision, kernel=vx.KERNEL_FUSED)
+    g.autotune(iters=1)
+    g.step(1000)
+    got = g.read_state()
+    f = filled_of(w)
+    e = compare(got, ref, f)
+    if precision == 64:
+        assert max(e["u"], e["v"], e["w"]) < FP64_TOL and e["q"] < 1e-12, e
+    else:
+        ug = np.linalg.norm(got["u"][f], axis=1).max()
+        uo = np.linalg.norm(ref["u"][f], axis=1).max()
+        assert abs(ug / uo - 1.0) < FP32_MAXDISP_TOL and e["u"] < 1e-3, (ug, uo, e)
