@@ -85,9 +85,12 @@ def time_gpu(w, precision, kernel, steps, warmup, autotune=True, tile=None):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    c = s.counters()
     kernel_ms = s.time_kernel(iters=max(10, min(steps, 50)))
     out = {"voxels": nvox, "ms": ms, "kernel_ms": kernel_ms,
-           "tile": s.fused_tile() if kernel == vx.KERNEL_FUSED else None}
+           "tile": s.fused_tile() if kernel == vx.KERNEL_FUSED else None,
+           "collision": {"rebuilds": c["rebuilds"], "pairs": c["pairs"], "steps": c["steps"]}
+           if w["params"].get("self_collision_on") else None}
     del s
     torch.cuda.empty_cache()
     return out
@@ -328,6 +331,18 @@ def copy_probe(mib=1024, reps=5):
             "note": "torch device copy, best of %d; context for the 8 TB/s peak" % reps}
 
 
+def host_cpu():
+    """Model name of the host CPU, as /proc/cpuinfo gives it."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(w, budget_s=12.0, note=""):
     """The oracle (FP64, one thread) on a bounded sample of the workload."""
     import oracle
@@ -348,7 +363,7 @@ def cpu_baseline(w, budget_s=12.0, note=""):
         el = time.perf_counter() - t0
         if el > budget_s or n >= 2000:
             break
-    return {"value": nvox * n / el, "unit": "voxel-steps/s", "cores": 1, "kind": "oracle",
+    return {"value": nvox * n / el, "unit": "voxel-steps/s", "cores": 1, "kind": "oracle", "host": host_cpu(),
             "sample": "%d steps of the %d-voxel %s lattice after 1 untimed step, FP64, one thread%s"
                       % (n, nvox, w["name"], note)}
 
@@ -382,6 +397,7 @@ def cpu_batch_baseline(count, sample_every=32, steps=60):
         busy = sum(ex.map(run, sims))
         wall = time.perf_counter() - t0
     return {"value": nvox * steps / wall, "unit": "voxel-steps/s", "cores": threads, "kind": "oracle",
+            "host": host_cpu(),
             "single_core_value": nvox * steps / busy,
             "sample": "one in every %d of the %d objects (%d objects, %d voxels), %d steps each, FP64, one object "
                       "per thread on %d threads; single_core_value: the same voxel-steps over the summed "
@@ -470,7 +486,11 @@ def main():
         out["hbm_resident"] = {"workload": w3["name"], "dtype": "f32",
                                "value": r3["voxels"] * args.steps / (r3["ms"] / 1e3),
                                "ms_per_step": r3["ms"] / args.steps, "tile": r3["tile"],
-                               "roofline": roofline(32, r3["voxels"], r3["kernel_ms"], w3["name"], r3["tile"])}
+                               "roofline": roofline(32, r3["voxels"], r3["kernel_ms"], w3["name"], r3["tile"]),
+                               "collision": dict(r3["collision"], note="candidate-list rebuilds over all steps "
+                                                 "taken (warm-up included) and candidate pairs at the end; "
+                                                 "the contact kernels are timed inside value, not in the "
+                                                 "roofline of the step kernel")}
         del w3
     if not args.no_batch_leg:
         log("batched leg: %d objects, %d steps" % (args.batch_objects, args.batch_steps))
