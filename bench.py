@@ -3,7 +3,7 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload random_block_100]
                     [--precision 32|64] [--kernel fused|split] [--no-cpu] [--no-fp64]
                     [--no-hbm-leg] [--no-batch-leg] [--no-collision-leg] [--no-adjoint-leg]
-                    [--no-autotune]
+                    [--no-paper-shape-leg] [--no-autotune]
 
 Headline workload: a 100^3 lattice whose cells are drawn from a seed as empty
 (p = 0.1), soft 1 MPa (p = 0.45) or stiff 100 MPa (p = 0.45), density 1000,
@@ -17,8 +17,10 @@ Further legs: FP64 on the headline lattice; 4096 batched objects in one
 persistent launch against the same objects one at a time; the iteration
 rates of the paper's four self-collision schemes on a clapper; the
 differentiable rollout of the 64 x 20^3 design lattice (forward + reverse
-against the plain forward); the oracle on one host core, and on a sample of
-the batched objects across the host cores.
+against the plain forward); one object's iteration rate on cubes of 8^3 to
+40^3 on the GPU and the oracle (the paper's speed-versus-size sweep); the
+oracle on one host core, and on a sample of the batched objects across the
+host cores.
 
 The state is resident on the GPU before timing starts.  Prints one JSON line.
 voxel-steps/s = filled voxels x steps / wall time of the K timed steps (HIP
@@ -331,6 +333,67 @@ def copy_probe(mib=1024, reps=5):
             "note": "torch device copy, best of %d; context for the 8 TB/s peak" % reps}
 
 
+def time_paper_shape(ns=(8, 16, 24, 32, 40), steps=2000, cpu_budget_s=1.5):
+    """The paper's speed-versus-size sweep: cubic blocks of one 1 MPa
+    material, bottom layer fixed, gravity and bond damping on.  Iterations
+    per second of one object on the GPU (one vx_step call, and the same steps
+    replayed from one captured HIP graph) and on the oracle (FP64, one
+    thread), beside the paper's figure for a 4000-voxel object."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_1212_2845_amd as vx
+    import workloads
+    rows = []
+    for n in ns:
+        w = workloads.solid_cube(n, E=1e6, gravity=9.81, zeta_bond=0.5)
+        _, _, z = workloads.cell_coords(w["grid"].shape)
+        w["fixed"] = (z == 0).astype(np.uint8)
+        side = torch.cuda.Stream()
+        sim = vx.from_workload(w, precision=32, stream=side.cuda_stream)
+        sim.bind()
+        sim.step(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        eager = steps / (time.perf_counter() - t0)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            sim.step_enqueue(steps)          # even: replays continue the state
+        graph.replay()
+        torch.cuda.synchronize()
+        cs = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(cs)
+        graph.replay()
+        e1.record(cs)
+        torch.cuda.synchronize()
+        sim.status()
+        graph_its = steps / (e0.elapsed_time(e1) / 1e3)
+        del graph, sim
+        o = oracle.Sim(w["grid"], w["materials"], **w["params"])
+        o.set_fixed(w["fixed"])
+        o.step(1)
+        t0 = time.perf_counter()
+        k = 0
+        while True:
+            o.step(1)
+            k += 1
+            el = time.perf_counter() - t0
+            if el > cpu_budget_s or k >= 500:
+                break
+        rows.append({"n": n, "voxels": n ** 3, "gpu_its": eager, "gpu_graph_its": graph_its,
+                     "oracle_its": k / el, "gpu_graph_voxel_steps": graph_its * n ** 3,
+                     "oracle_voxel_steps": k / el * n ** 3})
+    torch.cuda.empty_cache()
+    return {"workload": "solid cubes n^3, 1 MPa, bottom layer fixed, gravity, zeta_bond 0.5", "dtype_gpu": "f32",
+            "steps_gpu": steps, "rows": rows,
+            "paper": {"its": 122, "voxels": 4000, "voxel_steps": 488000,
+                      "hardware": "one thread of a 2.67 GHz Core i7", "note": "context only"}}
+
+
 def host_cpu():
     """Model name of the host CPU, as /proc/cpuinfo gives it."""
     try:
@@ -419,6 +482,7 @@ def main():
     ap.add_argument("--no-batch-leg", action="store_true")
     ap.add_argument("--no-collision-leg", action="store_true")
     ap.add_argument("--no-adjoint-leg", action="store_true")
+    ap.add_argument("--no-paper-shape-leg", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
     ap.add_argument("--batch-objects", type=int, default=4096)
     ap.add_argument("--one-by-one-sample", type=int, default=64,
@@ -501,6 +565,9 @@ def main():
     if not args.no_adjoint_leg:
         log("adjoint leg: design lattice, %d steps" % args.adjoint_steps)
         out["adjoint"] = time_adjoint(args.adjoint_steps)
+    if not args.no_paper_shape_leg:
+        log("paper-shape leg: cubes 8^3 .. 40^3")
+        out["paper_shape"] = time_paper_shape()
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w)
