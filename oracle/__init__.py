@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY.  A ctypes binding to the plain C FP64 stepper in
 ``vx_oracle.c`` plus the small numpy helpers in this package (direct-stiffness
-solve, region selection).  Only the tests, the smoke check and the CPU-baseline
+solve, region selection in `regions.py`).  Only the tests, the smoke check and the CPU-baseline
 leg of the benchmark may import it; the GPU library never does.
 
 Arrays are dense over the nx*ny*nz cells (cell index x + nx*(y + ny*z)),

@@ -780,3 +780,36 @@ def test_thin_beam_modes_match_table2():
     assert abs(f1 - beam_hz[0]) < 0.5          # the printed 404 Hz is this formula
     assert abs(f[0] / f1 - 1.0) < 0.10
 
+
+
+def test_region_selection_appendix_program():
+    """The appendix program's regions on its 5x10x5 workspace: the fixed box
+    (0, 0, 0) + (1, 0.01, 1) is the -y face layer and the forced box
+    (0, 0.99, 0) + (1, 0.01, 1) the +y face layer (the program's comments
+    name these planes); the forced region's 1 kN splits over the 25 voxels
+    of that layer."""
+    from oracle import regions
+    g = np.ones((5, 10, 5), np.uint8)
+    _, y, _ = workloads.cell_coords(g.shape)
+    assert np.array_equal(regions.region_mask(g, (0, 0, 0), (1, 0.01, 1)), (y == 0).astype(np.uint8))
+    F = regions.forced_region_forces(g, (0, 0.99, 0), (1, 0.01, 1), (0, 0, -1000.0))
+    assert np.array_equal(F[:, 2] != 0, y == 9)
+    assert np.allclose(F[y == 9, 2], -40.0) and abs(F[:, 2].sum() + 1000.0) < 1e-9
+    assert not F[:, :2].any()
+
+
+def test_region_selection_needs_positive_volume():
+    """Touching means sharing a positive volume: a box whose faces lie on
+    voxel faces selects only the voxels inside it, a box of zero extent
+    selects nothing, a box inside one voxel selects that voxel, and empty
+    cells are never selected."""
+    from oracle import regions
+    g = np.ones((1, 1, 5), np.uint8)            # five voxels along x
+    assert regions.region_mask(g, (0.2, 0, 0), (0.2, 1, 1)).tolist() == [0, 1, 0, 0, 0]
+    assert regions.region_mask(g, (0.5, 0, 0), (0.0, 1, 1)).sum() == 0
+    assert regions.region_mask(g, (0.45, 0.4, 0.4), (0.02, 0.1, 0.1)).tolist() == [0, 0, 1, 0, 0]
+    g2 = g.copy()
+    g2[0, 0, 1] = 0
+    assert regions.region_mask(g2, (0.2, 0, 0), (0.2, 1, 1)).sum() == 0
+    F = regions.forced_region_forces(g2, (0.2, 0, 0), (0.2, 1, 1), (1.0, 0, 0))
+    assert not F.any()
