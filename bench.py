@@ -23,9 +23,10 @@ oracle on one host core, and on a sample of the batched objects across the
 host cores.
 
 The state is resident on the GPU before timing starts.  Prints one JSON line.
-voxel-steps/s = filled voxels x steps / wall time of the K timed steps (HIP
-events on the stream the kernels run on, device synchronisation on both
-sides).  The roofline figure uses the step kernel's own average launch time,
+voxel-steps/s = filled voxels x steps / time of the K timed steps: one
+replay of a captured HIP graph of the K steps (vx_step_enqueue), timed with
+HIP events on the replay stream, device synchronisation on both sides;
+eager_value gives the same K steps as one vx_step call.  The roofline figure uses the step kernel's own average launch time,
 measured the same way over dry-run launches that do not advance the state;
 roofline.copy_probe is the rate of a plain 1 GiB device copy on the same GPU,
 as context for the 8 TB/s peak.
@@ -65,12 +66,15 @@ def log(msg):
 def time_gpu(w, precision, kernel, steps, warmup, autotune=True, tile=None):
     """Returns a dict with voxels, ms for `steps` steps, the tile and the
     step kernel's own average launch time.  tile = (shape, zc) fixes the
-    fused kernel's tile instead of autotuning it."""
+    fused kernel's tile instead of autotuning it.  The timed steps are one
+    captured HIP graph of `steps` vx_step_enqueue steps (an even count, so
+    that the ping-pong state continues), replayed once after an untimed
+    replay; eager_ms times the same number of steps as one vx_step call."""
     import torch
     import paper_1212_2845_amd as vx
     torch.cuda.init()
-    stream = torch.cuda.current_stream()
-    s = vx.from_workload(w, precision=precision, kernel=kernel, stream=stream.cuda_stream)
+    side = torch.cuda.Stream()
+    s = vx.from_workload(w, precision=precision, kernel=kernel, stream=side.cuda_stream)
     s.bind()
     if tile is not None:
         s.set_fused_tile(*tile)
@@ -82,16 +86,31 @@ def time_gpu(w, precision, kernel, steps, warmup, autotune=True, tile=None):
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    s.step(steps)                     # launches on `stream`, ends with a status poll
-    e1.record(stream)
+    e0.record(side)
+    s.step(steps)                     # launches on `side`, ends with a status poll
+    e1.record(side)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    eager_ms = e0.elapsed_time(e1)
+    ms = eager_ms
+    if steps % 2 == 0:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            s.step_enqueue(steps)
+        graph.replay()
+        torch.cuda.synchronize()
+        cs = torch.cuda.current_stream()     # replay() launches on the current stream
+        e0.record(cs)
+        graph.replay()
+        e1.record(cs)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        s.status()                        # raises if a replayed step went non-finite
+        del graph
     c = s.counters()
     kernel_ms = s.time_kernel(iters=max(10, min(steps, 50)))
-    out = {"voxels": nvox, "ms": ms, "kernel_ms": kernel_ms,
+    out = {"voxels": nvox, "ms": ms, "eager_ms": eager_ms, "kernel_ms": kernel_ms,
            "tile": s.fused_tile() if kernel == vx.KERNEL_FUSED else None,
-           "collision": {"rebuilds": c["rebuilds"], "pairs": c["pairs"], "steps": c["steps"]}
+           "collision": {"rebuilds": c["rebuilds"], "pairs": c["pairs"]}
            if w["params"].get("self_collision_on") else None}
     del s
     torch.cuda.empty_cache()
@@ -535,6 +554,10 @@ def main():
                    (4 if args.precision == 32 else 8),
                    "cache_resident": 2 * int(w["grid"].size) * 13 * (4 if args.precision == 32 else 8) < 256e6},
         "roofline": roofline(args.precision, r["voxels"], r["kernel_ms"], w["name"], r["tile"]),
+        "timing": {"method": "one replay of a captured HIP graph of the K steps, HIP events on the replay "
+                             "stream, device synchronisation on both sides" if args.steps % 2 == 0 else
+                             "one vx_step call of K steps, HIP events on its stream",
+                   "eager_value": r["voxels"] * args.steps / (r["eager_ms"] / 1e3)},
     }
     out["roofline"]["copy_probe"] = copy_probe()
     if not args.no_fp64 and args.precision == 32:
@@ -542,6 +565,7 @@ def main():
         r64 = time_gpu(w, 64, kernel, args.steps, args.warmup, autotune)
         out["fp64"] = {"value": r64["voxels"] * args.steps / (r64["ms"] / 1e3),
                        "ms_per_step": r64["ms"] / args.steps, "tile": r64["tile"],
+                       "eager_value": r64["voxels"] * args.steps / (r64["eager_ms"] / 1e3),
                        "roofline": roofline(64, r64["voxels"], r64["kernel_ms"], w["name"], r64["tile"])}
     if not args.no_hbm_leg:
         log("hbm-resident leg: blob_lattice_256")
@@ -550,9 +574,11 @@ def main():
         out["hbm_resident"] = {"workload": w3["name"], "dtype": "f32",
                                "value": r3["voxels"] * args.steps / (r3["ms"] / 1e3),
                                "ms_per_step": r3["ms"] / args.steps, "tile": r3["tile"],
+                               "eager_value": r3["voxels"] * args.steps / (r3["eager_ms"] / 1e3),
                                "roofline": roofline(32, r3["voxels"], r3["kernel_ms"], w3["name"], r3["tile"]),
-                               "collision": dict(r3["collision"], note="candidate-list rebuilds over all steps "
-                                                 "taken (warm-up included) and candidate pairs at the end; "
+                               "collision": dict(r3["collision"], note="candidate-list rebuilds since creation "
+                                                 "(warm-up, eager and replayed steps) and candidate pairs at "
+                                                 "the end; "
                                                  "the contact kernels are timed inside value, not in the "
                                                  "roofline of the step kernel")}
         del w3
