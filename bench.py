@@ -3,7 +3,7 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload random_block_100]
                     [--precision 32|64] [--kernel fused|split] [--no-cpu] [--no-fp64]
                     [--no-hbm-leg] [--no-batch-leg] [--no-collision-leg] [--no-adjoint-leg]
-                    [--no-paper-shape-leg] [--no-autotune]
+                    [--no-paper-shape-leg] [--no-autotune] [--eager]
 
 Headline workload: a 100^3 lattice whose cells are drawn from a seed as empty
 (p = 0.1), soft 1 MPa (p = 0.45) or stiff 100 MPa (p = 0.45), density 1000,
@@ -63,13 +63,15 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def time_gpu(w, precision, kernel, steps, warmup, autotune=True, tile=None):
+def time_gpu(w, precision, kernel, steps, warmup, autotune=True, tile=None, graph=True):
     """Returns a dict with voxels, ms for `steps` steps, the tile and the
     step kernel's own average launch time.  tile = (shape, zc) fixes the
     fused kernel's tile instead of autotuning it.  The timed steps are one
     captured HIP graph of `steps` vx_step_enqueue steps (an even count, so
     that the ping-pong state continues), replayed once after an untimed
-    replay; eager_ms times the same number of steps as one vx_step call."""
+    replay; eager_ms times the same number of steps as one vx_step call
+    (and is the timed figure with graph=False, e.g. under a profiler's
+    counter collection, which does not follow graph replays)."""
     import torch
     import paper_1212_2845_amd as vx
     torch.cuda.init()
@@ -92,20 +94,20 @@ def time_gpu(w, precision, kernel, steps, warmup, autotune=True, tile=None):
     torch.cuda.synchronize()
     eager_ms = e0.elapsed_time(e1)
     ms = eager_ms
-    if steps % 2 == 0:
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph, stream=side):
+    if graph and steps % 2 == 0:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
             s.step_enqueue(steps)
-        graph.replay()
+        g.replay()
         torch.cuda.synchronize()
         cs = torch.cuda.current_stream()     # replay() launches on the current stream
         e0.record(cs)
-        graph.replay()
+        g.replay()
         e1.record(cs)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         s.status()                        # raises if a replayed step went non-finite
-        del graph
+        del g
     c = s.counters()
     kernel_ms = s.time_kernel(iters=max(10, min(steps, 50)))
     out = {"voxels": nvox, "ms": ms, "eager_ms": eager_ms, "kernel_ms": kernel_ms,
@@ -502,6 +504,9 @@ def main():
     ap.add_argument("--no-collision-leg", action="store_true")
     ap.add_argument("--no-adjoint-leg", action="store_true")
     ap.add_argument("--no-paper-shape-leg", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="time the lattice legs' K steps as one vx_step call instead of a graph replay "
+                         "(for profiler counter runs, which do not follow graph replays)")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
     ap.add_argument("--batch-objects", type=int, default=4096)
     ap.add_argument("--one-by-one-sample", type=int, default=64,
@@ -535,7 +540,8 @@ def main():
     w = build_workload(args.workload)
     log("workload %s precision %d kernel %s steps %d warmup %d"
         % (args.workload, args.precision, args.kernel, args.steps, args.warmup))
-    r = time_gpu(w, args.precision, kernel, args.steps, args.warmup, autotune, tile)
+    use_graph = not args.eager and args.steps % 2 == 0
+    r = time_gpu(w, args.precision, kernel, args.steps, args.warmup, autotune, tile, graph=use_graph)
     out = {
         "metric": "voxel-steps/s",
         "value": r["voxels"] * args.steps / (r["ms"] / 1e3),
@@ -555,14 +561,14 @@ def main():
                    "cache_resident": 2 * int(w["grid"].size) * 13 * (4 if args.precision == 32 else 8) < 256e6},
         "roofline": roofline(args.precision, r["voxels"], r["kernel_ms"], w["name"], r["tile"]),
         "timing": {"method": "one replay of a captured HIP graph of the K steps, HIP events on the replay "
-                             "stream, device synchronisation on both sides" if args.steps % 2 == 0 else
+                             "stream, device synchronisation on both sides" if use_graph else
                              "one vx_step call of K steps, HIP events on its stream",
                    "eager_value": r["voxels"] * args.steps / (r["eager_ms"] / 1e3)},
     }
     out["roofline"]["copy_probe"] = copy_probe()
     if not args.no_fp64 and args.precision == 32:
         log("fp64 leg")
-        r64 = time_gpu(w, 64, kernel, args.steps, args.warmup, autotune)
+        r64 = time_gpu(w, 64, kernel, args.steps, args.warmup, autotune, graph=use_graph)
         out["fp64"] = {"value": r64["voxels"] * args.steps / (r64["ms"] / 1e3),
                        "ms_per_step": r64["ms"] / args.steps, "tile": r64["tile"],
                        "eager_value": r64["voxels"] * args.steps / (r64["eager_ms"] / 1e3),
@@ -570,7 +576,7 @@ def main():
     if not args.no_hbm_leg:
         log("hbm-resident leg: blob_lattice_256")
         w3 = build_workload("blob_lattice_256")
-        r3 = time_gpu(w3, 32, kernel, args.steps, args.warmup, autotune)
+        r3 = time_gpu(w3, 32, kernel, args.steps, args.warmup, autotune, graph=use_graph)
         out["hbm_resident"] = {"workload": w3["name"], "dtype": "f32",
                                "value": r3["voxels"] * args.steps / (r3["ms"] / 1e3),
                                "ms_per_step": r3["ms"] / args.steps, "tile": r3["tile"],
