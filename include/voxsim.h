@@ -88,7 +88,8 @@ typedef struct vx_sim *vx_handle;
  * state is stored and stepped in.  Computes all per-bond constants (Eq. 1-12),
  * the stable timestep (Eq. 31-32) and the surface voxel list on the host.
  * Errors: VX_EINVAL for a bad size, material index >= n_mat, E <= 0,
- * rho <= 0, nu outside (-1, 0.5), l <= 0, or precision not 32/64.  On
+ * rho <= 0, nu outside (-1, 0.5), l <= 0, precision not 32/64, or
+ * self-collision on a lattice more than 2^20 cells long on an axis.  On
  * success *out is a new handle (free with vx_destroy). */
 int vx_create(const uint8_t *grid, int32_t nx, int32_t ny, int32_t nz,
               const vx_material *palette, int32_t n_mat, const vx_params *params,

@@ -44,6 +44,29 @@ __device__ __forceinline__ void grid_cell(T x, T y, T z, double H, int &cx, int 
     cz = (int)floor((double)z / H);
 }
 
+// Three integers of at most 21 bits each (offset by 2^20, so grid cells a
+// little below the origin pack too) in one 64-bit word.  Two neighbouring
+// grid cells never share a packed value.
+__device__ __forceinline__ long long pack3(int x, int y, int z) {
+    const unsigned long long m = 0x1FFFFFull, b = 1ull << 20;
+    return (long long)((((unsigned long long)(x + (int)b)) & m) | ((((unsigned long long)(y + (int)b)) & m) << 21) |
+                       ((((unsigned long long)(z + (int)b)) & m) << 42));
+}
+
+__device__ __forceinline__ void unpack3(long long v, int &x, int &y, int &z) {
+    const unsigned long long u = (unsigned long long)v, m = 0x1FFFFFull;
+    const int b = 1 << 20;
+    x = (int)(u & m) - b;
+    y = (int)((u >> 21) & m) - b;
+    z = (int)((u >> 42) & m) - b;
+}
+
+// Candidate slots per thread kept in LDS while one voxel's list is built;
+// larger caps keep the list in global memory.
+constexpr int kCandLdsCap = 48;
+// bucket entries whose loads the candidate search issues together
+constexpr int kGroup = 4;
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_keys(StepArgs<T> a, CollideArgs c, Origin3 o) {
     if (*c.rebuild_flag == 0) return;
@@ -57,6 +80,8 @@ __global__ void __launch_bounds__(256) k_keys(StepArgs<T> a, CollideArgs c, Orig
     grid_cell(x, y, z, c.horizon, cx, cy, cz);
     const int key = cell_hash(cx, cy, cz, c.table_size - 1);
     c.cell_keys[i] = key;
+    c.cell_gc[i] = pack3(cx, cy, cz);
+    c.cell_ijk[i] = pack3(ix, iy, iz);
     atomicAdd(&c.bucket_fill[key], 1);
 }
 
@@ -135,63 +160,104 @@ __global__ void __launch_bounds__(256) k_scan_apply(CollideArgs c) {
     if (blockIdx.x == 0 && threadIdx.x == 0) c.bucket_start[c.table_size] = c.n_surf;
 }
 
-__global__ void __launch_bounds__(256) k_scatter(CollideArgs c) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_scatter(StepArgs<T> a, CollideArgs c) {
     if (*c.rebuild_flag == 0) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= c.n_surf) return;
     const int pos = atomicAdd(&c.bucket_fill[c.cell_keys[i]], 1);
-    c.sorted_idx[pos] = i;
+    const int ci = c.surf_cells[i];
+    c.sorted_cell[pos] = ci;
+    c.sorted_gc[pos] = c.cell_gc[i];
+    c.sorted_ijk[pos] = c.cell_ijk[i];
+    T *su = (T *)c.sorted_u;
+    su[pos] = a.s_in[W_UX * a.stride + ci];
+    su[c.n_surf + pos] = a.s_in[W_UY * a.stride + ci];
+    su[2 * c.n_surf + pos] = a.s_in[W_UZ * a.stride + ci];
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_candidates(StepArgs<T> a, CollideArgs c, Origin3 o) {
+__global__ void __launch_bounds__(256) k_candidates(StepArgs<T> a, CollideArgs c) {
+    // slot p of thread t's list at lds_list[p * blockDim.x + t] (caps up to
+    // kCandLdsCap; the launch sizes it)
+    extern __shared__ int lds_list[];
     if (*c.rebuild_flag == 0) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= c.n_surf) return;
-    const T org[3] = {(T)o.v[0], (T)o.v[1], (T)o.v[2]};
+    const bool in_lds = c.cap <= kCandLdsCap;
     const int ci = c.surf_cells[i];
     int ix, iy, iz, cx, cy, cz;
-    T x, y, z;
-    voxel_pos(a, ci, ix, iy, iz, x, y, z, org);
-    grid_cell(x, y, z, c.horizon, cx, cy, cz);
+    unpack3(c.cell_ijk[i], ix, iy, iz);
+    unpack3(c.cell_gc[i], cx, cy, cz);
     const T uxi = a.s_in[W_UX * a.stride + ci], uyi = a.s_in[W_UY * a.stride + ci],
             uzi = a.s_in[W_UZ * a.stride + ci];
     const T H = (T)c.horizon;
+    const int ns = c.n_surf;
+    const T *su = (const T *)c.sorted_u;
     int *list = c.cand + (long long)i * c.cap;
+    const int step = blockDim.x;
+    int *mine = lds_list + threadIdx.x;
     int count = 0;
     for (int dz = -1; dz <= 1; ++dz)
         for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
                 const int tx = cx + dx, ty = cy + dy, tz = cz + dz;
                 const int key = cell_hash(tx, ty, tz, c.table_size - 1);
+                const long long want = pack3(tx, ty, tz);
                 const int b0 = c.bucket_start[key], b1 = c.bucket_start[key + 1];
-                for (int k = b0; k < b1; ++k) {
-                    const int j = c.sorted_idx[k];
-                    const int cj = c.surf_cells[j];
-                    if (cj == ci) continue;
-                    int jx, jy, jz, gx, gy, gz;
-                    T xj, yj, zj;
-                    voxel_pos(a, cj, jx, jy, jz, xj, yj, zj, org);
-                    grid_cell(xj, yj, zj, c.horizon, gx, gy, gz);
-                    if (gx != tx || gy != ty || gz != tz) continue;   // another cell in this bucket
-                    const int man = abs(jx - ix) + abs(jy - iy) + abs(jz - iz);
-                    if (man <= 3) continue;
-                    const T rx = T(ix - jx) * a.l + (uxi - a.s_in[W_UX * a.stride + cj]);
-                    const T ry = T(iy - jy) * a.l + (uyi - a.s_in[W_UY * a.stride + cj]);
-                    const T rz = T(iz - jz) * a.l + (uzi - a.s_in[W_UZ * a.stride + cj]);
-                    if (!(dsqrt(rx * rx + ry * ry + rz * rz) < H)) continue;
-                    if (count < c.cap) {
-                        // insertion keeps the list sorted by partner cell
-                        int p = count;
-                        while (p > 0 && list[p - 1] > cj) { list[p] = list[p - 1]; --p; }
-                        list[p] = cj;
-                    } else {
-                        atomicOr(c.overflow, 1u);
+                // entries in groups of kGroup: the loads of a group are issued
+                // together (a short last group re-reads its last entry, which
+                // is not processed twice), then the entries are taken in order
+                for (int k0 = b0; k0 < b1; k0 += kGroup) {
+                    int cjg[kGroup];
+                    long long gcg[kGroup], ijg[kGroup];
+                    T uxg[kGroup], uyg[kGroup], uzg[kGroup];
+#pragma unroll
+                    for (int q = 0; q < kGroup; ++q) {
+                        const int k = k0 + q < b1 ? k0 + q : b1 - 1;
+                        cjg[q] = c.sorted_cell[k];
+                        gcg[q] = c.sorted_gc[k];
+                        ijg[q] = c.sorted_ijk[k];
+                        uxg[q] = su[k];
+                        uyg[q] = su[ns + k];
+                        uzg[q] = su[2 * ns + k];
                     }
-                    ++count;
+#pragma unroll
+                    for (int q = 0; q < kGroup; ++q) {
+                        if (k0 + q >= b1) break;
+                        const int cj = cjg[q];
+                        if (cj == ci || gcg[q] != want) continue;   // another cell in this bucket
+                        int jx, jy, jz;
+                        unpack3(ijg[q], jx, jy, jz);
+                        const int man = abs(jx - ix) + abs(jy - iy) + abs(jz - iz);
+                        if (man <= 3) continue;
+                        const T rx = T(ix - jx) * a.l + (uxi - uxg[q]);
+                        const T ry = T(iy - jy) * a.l + (uyi - uyg[q]);
+                        const T rz = T(iz - jz) * a.l + (uzi - uzg[q]);
+                        if (!(dsqrt(rx * rx + ry * ry + rz * rz) < H)) continue;
+                        if (count < c.cap) {
+                            // insertion keeps the list sorted by partner cell
+                            int p = count;
+                            if (in_lds) {
+                                while (p > 0 && mine[(p - 1) * step] > cj) {
+                                    mine[p * step] = mine[(p - 1) * step];
+                                    --p;
+                                }
+                                mine[p * step] = cj;
+                            } else {
+                                while (p > 0 && list[p - 1] > cj) { list[p] = list[p - 1]; --p; }
+                                list[p] = cj;
+                            }
+                        } else {
+                            atomicOr(c.overflow, 1u);
+                        }
+                        ++count;
+                    }
                 }
             }
     const int kept = count < c.cap ? count : c.cap;
+    if (in_lds)
+        for (int p = 0; p < kept; ++p) list[p] = mine[p * step];
     c.cand_n[i] = kept;
     // the candidate bit lives in the flags of the current step
     uint8_t *flags = const_cast<uint8_t *>(a.flags);
@@ -280,8 +346,9 @@ hipError_t launch_rebuild(const StepArgs<T> &a, const CollideArgs &c, hipStream_
     k_scan_reduce<<<nblk, 256, 0, s>>>(c);
     k_scan_blocks<<<1, 1024, 0, s>>>(c, nblk);
     k_scan_apply<<<nblk, 256, 0, s>>>(c);
-    k_scatter<<<gs, 256, 0, s>>>(c);
-    k_candidates<T><<<gs, 256, 0, s>>>(a, c, o);
+    k_scatter<T><<<gs, 256, 0, s>>>(a, c);
+    const size_t lds = c.cap <= kCandLdsCap ? (size_t)256 * c.cap * sizeof(int) : 0;
+    k_candidates<T><<<gs, 256, lds, s>>>(a, c);
     k_rebuild_done<<<(unsigned)((c.table_size + 255) / 256), 256, 0, s>>>(c);
     k_rebuild_clear<<<1, 1, 0, s>>>(c);
     return hipGetLastError();

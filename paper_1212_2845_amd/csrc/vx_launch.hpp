@@ -130,7 +130,16 @@ struct CollideArgs {
     double *macc;                // accumulated maximum motion
     unsigned long long *vmax_bits;
     int *cell_keys;              // n_surf hashed cell keys
-    int *sorted_idx;             // n_surf surface indices sorted by key
+    long long *cell_gc;          // n_surf packed grid cells (21 bits per axis)
+    long long *cell_ijk;         // n_surf packed rest indices (21 bits per axis)
+    // the entries of every bucket, in bucket order: cell, packed grid cell,
+    // packed rest indices, and displacement (3 arrays of n_surf values of
+    // the state precision), so that the candidate search reads each entry
+    // with independent loads
+    int *sorted_cell;
+    long long *sorted_gc;
+    long long *sorted_ijk;
+    void *sorted_u;
     int *bucket_start;           // table_size + 1
     int *bucket_fill;            // table_size (scratch counters)
     int table_size;              // power of two

@@ -22,7 +22,8 @@ inline uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign
 
 struct Layout {
     uint64_t state[2], mat, flags[2], mats, pairs, bonds, act_amp, act_phase, forced_cells, forced_F;
-    uint64_t contact_F, surf_cells, cand, cand_n, keys, sorted, bstart, bfill, scalars, scan_tmp;
+    uint64_t contact_F, surf_cells, cand, cand_n, keys, gc, ijk, sorted, sgc, sijk, su, bstart, bfill, scalars,
+        scan_tmp;
     uint64_t E_cell, rho_cell;
     uint64_t energy;
     uint64_t total;
@@ -200,7 +201,12 @@ inline vx::CollideArgs make_collide(vx_sim *h) {
     c.macc = &sc->macc;
     c.vmax_bits = &sc->vmax_bits;
     c.cell_keys = (int *)(ws + h->L.keys);
-    c.sorted_idx = (int *)(ws + h->L.sorted);
+    c.cell_gc = (long long *)(ws + h->L.gc);
+    c.cell_ijk = (long long *)(ws + h->L.ijk);
+    c.sorted_cell = (int *)(ws + h->L.sorted);
+    c.sorted_gc = (long long *)(ws + h->L.sgc);
+    c.sorted_ijk = (long long *)(ws + h->L.sijk);
+    c.sorted_u = (void *)(ws + h->L.su);
     c.bucket_start = (int *)(ws + h->L.bstart);
     c.bucket_fill = (int *)(ws + h->L.bfill);
     c.table_size = h->table_size;

@@ -319,3 +319,13 @@ def test_static_solve_workspace_and_state_errors():
     assert rc == vx.VX_ESTATE
     assert L.vx_static_solve(s.h, C.c_void_p(4096), n.value, F.ctypes.data_as(C.c_void_p), 0.0, 100,
                              None, None, None, None) == vx.VX_EINVAL
+
+
+def test_self_collision_rejects_axes_beyond_packed_indices():
+    """The collision search packs rest indices into 21 bits per axis: a
+    lattice more than 2^20 cells long on an axis is refused with
+    self-collision on, and accepted without it."""
+    g = np.ones((1, 1, (1 << 20) + 1), np.uint8)
+    with pytest.raises(vx.VoxsimError):
+        vx.Sim(g, [workloads.EMPTY, M1], self_collision_on=1)
+    vx.Sim(g, [workloads.EMPTY, M1], self_collision_on=0)

@@ -101,3 +101,24 @@ def test_all_voxels_equals_surface_until_an_interior_voxel_is_a_candidate():
         assert a == b, k * 250
     print("[case] first interior candidate within step", first_inner, flush=True)
 
+
+
+def test_candidate_lists_in_lds_and_in_global_memory_agree():
+    """Candidate lists of up to 48 slots are built in LDS, larger ones in
+    global memory: with 100 slots the clapper's lists, pair count, rebuild
+    count and trajectory (every-step rebuilds, 1500 FP64 steps) are bitwise
+    those of the default 32 slots, none of which overflows."""
+    w = workloads.clapper()
+    out = []
+    for cap in (32, 100):
+        params = dict(w["params"], contact_cap=cap)
+        s = vx.Sim(w["grid"], w["materials"], precision=64, **params)
+        s.set_collision_mode(False, True)
+        s.set_fixed(w["fixed"])
+        s.step(1500)
+        out.append((s.read_state(), s.counters(), s.candidates()))
+    (sa, ca, la), (sb, cb, lb) = out
+    assert ca["rebuilds"] == cb["rebuilds"] and ca["pairs"] == cb["pairs"] and ca["pairs"] > 0, (ca, cb)
+    assert la == lb
+    for k in ("u", "q", "v", "w"):
+        assert np.array_equal(sa[k], sb[k]), k
