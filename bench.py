@@ -302,24 +302,34 @@ def time_adjoint(steps=5000, K=100):
                     "checkpoint and the host copies of the adjoint in and the gradients out"}
 
 
-def time_collision_schemes(steps=5000):
+def time_collision_schemes(steps=5000, graph=True):
     """Iteration rates of the self-collision schemes of the paper's Table 3
     (candidates from all voxels or the surface; rebuilt every step or by the
-    horizon rule) on the clapper, FP32, wall time of `steps` steps each."""
+    horizon rule) on the clapper, FP32: wall time of `steps` steps as one
+    vx_step call (host launches included), and the same steps from the same
+    start replayed from one captured HIP graph (device time; the rebuild
+    decisions are taken on the device, so the graph runs the same work)."""
     import torch
     import paper_1212_2845_amd as vx
     import workloads
     w = workloads.clapper(steps=steps)
     out = {"workload": w["name"], "voxels": int((w["grid"] > 0).sum()), "steps": steps, "dtype": "f32",
-           "unit": "iterations/s", "note": "wall time of vx_step over the steps, host launches included"}
+           "unit": "iterations/s",
+           "note": "NAME: wall time of vx_step over the steps, host launches included; NAME graph: one replay "
+                   "of the same steps captured as a HIP graph; NAME rebuilds: candidate-list rebuilds"}
     rates = {}
+    side = torch.cuda.Stream()
+
+    def make(all_voxels, every):
+        sim = vx.Sim(w["grid"], w["materials"], precision=32, stream=side.cuda_stream, **w["params"])
+        sim.set_collision_mode(all_voxels, every)
+        sim.set_fixed(w["fixed"])
+        sim.step(10)
+        return sim
+
     for all_voxels, every, name in [(1, 1, "all+every"), (0, 1, "surf+every"), (1, 0, "all+horizon"),
                                     (0, 0, "surf+horizon")]:
-        s = vx.Sim(w["grid"], w["materials"], precision=32, stream=torch.cuda.current_stream().cuda_stream,
-                   **w["params"])
-        s.set_collision_mode(all_voxels, every)
-        s.set_fixed(w["fixed"])
-        s.step(10)
+        s = make(all_voxels, every)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.step(steps)
@@ -327,6 +337,22 @@ def time_collision_schemes(steps=5000):
         rates[name] = steps / (time.perf_counter() - t0)
         rates[name + " rebuilds"] = s.counters()["rebuilds"]
         del s
+        if graph and steps % 2 == 0:
+            s = make(all_voxels, every)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                s.step_enqueue(steps)
+            cs = torch.cuda.current_stream()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(cs)
+            g.replay()
+            e1.record(cs)
+            torch.cuda.synchronize()
+            s.status()
+            rates[name + " graph"] = steps / (e0.elapsed_time(e1) / 1e3)
+            del g, s
     out["rates"] = rates
     return out
 
@@ -505,8 +531,8 @@ def main():
     ap.add_argument("--no-adjoint-leg", action="store_true")
     ap.add_argument("--no-paper-shape-leg", action="store_true")
     ap.add_argument("--eager", action="store_true",
-                    help="time the lattice legs' K steps as one vx_step call instead of a graph replay "
-                         "(for profiler counter runs, which do not follow graph replays)")
+                    help="no graph replays: the lattice legs' K steps as one vx_step call, and the collision "
+                         "leg's eager rates only (for profiler counter runs, which do not follow graph replays)")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
     ap.add_argument("--batch-objects", type=int, default=4096)
     ap.add_argument("--one-by-one-sample", type=int, default=64,
@@ -593,7 +619,7 @@ def main():
         out["batched"] = time_batch(args.batch_objects, args.batch_steps, args.one_by_one_sample)
     if not args.no_collision_leg:
         log("collision-scheme leg: clapper")
-        out["collision_schemes"] = time_collision_schemes()
+        out["collision_schemes"] = time_collision_schemes(graph=not args.eager)
     if not args.no_adjoint_leg:
         log("adjoint leg: design lattice, %d steps" % args.adjoint_steps)
         out["adjoint"] = time_adjoint(args.adjoint_steps)
