@@ -149,6 +149,26 @@ def measured_traffic(workload, precision, tile):
     return e
 
 
+# VALU issue peak of the chip: one wave64 instruction per CU per clock (no
+# packed FP32), 256 CUs at 2.4 GHz, in lane-instructions per second.
+VALU_PEAK_LANE_INSTR = 256 * 2.4e9 * 64
+
+
+def measured_valu(workload, precision, tile):
+    """VALU lane-instructions per voxel-step of the fused kernel (rocprofv3
+    SQ_INSTS_VALU x 64 / voxels) from profiles/valu.json, or None when none
+    was taken for this workload and tile on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "valu.json")
+    if tile is None or not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        db = json.load(fh)
+    e = db.get("%s|f%d|tile%d:%d" % (workload, precision, tile["shape"], tile["zc"]))
+    if e is None or e.get("src") != fused_source_hash():
+        return None
+    return e
+
+
 def roofline(precision, nvox, kernel_ms, workload=None, tile=None, kernel="k_fused"):
     alg = ALG_BYTES[precision]
     achieved = alg * nvox / (kernel_ms / 1e3) / 1e9
@@ -161,6 +181,14 @@ def roofline(precision, nvox, kernel_ms, workload=None, tile=None, kernel="k_fus
         out["traffic_unit"] = "bytes per launch"
         out["traffic_over_algorithmic"] = t["traffic"] / (alg * nvox)
         out["traffic_profile"] = "profiles/" + t["profile"]
+    v = measured_valu(workload, precision, tile) if workload else None
+    if v is not None:
+        rate = v["per_voxel_step"] * nvox / (kernel_ms / 1e3)
+        out["alu"] = {"achieved": rate / 1e12, "peak": VALU_PEAK_LANE_INSTR / 1e12,
+                      "unit": "T VALU lane-instructions/s", "frac": rate / VALU_PEAK_LANE_INSTR,
+                      "valu_per_voxel_step": v["per_voxel_step"], "profile": "profiles/" + v["profile"],
+                      "note": "the same launch against the chip's VALU issue rate; the step kernel is "
+                              "VALU-bound before it is HBM-bound"}
     return out
 
 
