@@ -77,7 +77,7 @@ typedef struct vx_params {
     double origin[3];       /* world position of the lower corner of cell 0 */
     int32_t floor_on;       /* 1: floor at z = 0 with friction */
     int32_t self_collision_on; /* 1: voxel-voxel contact between surface voxels */
-    int32_t contact_cap;    /* max collision candidates per surface voxel (0 -> 32) */
+    int32_t contact_cap;    /* max collision candidates per surface voxel (0 -> 32, at most 1024) */
     int32_t reserved;       /* must be 0 */
 } vx_params;
 
@@ -88,8 +88,9 @@ typedef struct vx_sim *vx_handle;
  * state is stored and stepped in.  Computes all per-bond constants (Eq. 1-12),
  * the stable timestep (Eq. 31-32) and the surface voxel list on the host.
  * Errors: VX_EINVAL for a bad size, material index >= n_mat, E <= 0,
- * rho <= 0, nu outside (-1, 0.5), l <= 0, precision not 32/64, or
- * self-collision on a lattice more than 2^20 cells long on an axis.  On
+ * rho <= 0, nu outside (-1, 0.5), l <= 0, precision not 32/64, contact_cap
+ * above 1024, or self-collision on a lattice more than 2^20 cells long on an
+ * axis.  On
  * success *out is a new handle (free with vx_destroy). */
 int vx_create(const uint8_t *grid, int32_t nx, int32_t ny, int32_t nz,
               const vx_material *palette, int32_t n_mat, const vx_params *params,

@@ -380,8 +380,10 @@ int vx_create(const uint8_t *grid, int32_t nx, int32_t ny, int32_t nz, const vx_
     if (!(p.voxel_size > 0.0) || !(p.gravity >= 0.0) || !(p.zeta_bond >= 0.0) || !(p.zeta_slow >= 0.0) ||
         !(p.zeta_col >= 0.0) || !(p.dt_scale >= 0.0) || p.dt_scale > 1.0 || p.contact_cap < 0 || p.reserved != 0)
         return VX_EINVAL;
-    // the collision search packs rest indices into 21 bits per axis
+    // the collision search packs rest indices into 21 bits per axis and
+    // builds each voxel's list in LDS
     if (p.self_collision_on && (nx > (1 << 20) || ny > (1 << 20) || nz > (1 << 20))) return VX_EINVAL;
+    if (p.contact_cap > kMaxContactCap) return VX_EINVAL;
     for (int i = 1; i < n_mat; ++i) {
         const vx_material &m = palette[i];
         if (!(m.E > 0.0) || !(m.rho > 0.0) || !(m.nu > -1.0 && m.nu < 0.5) || !(m.mu_s >= 0.0) || !(m.mu_d >= 0.0) ||

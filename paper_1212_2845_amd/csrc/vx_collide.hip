@@ -61,9 +61,10 @@ __device__ __forceinline__ void unpack3(long long v, int &x, int &y, int &z) {
     z = (int)((u >> 42) & m) - b;
 }
 
-// Candidate slots per thread kept in LDS while one voxel's list is built;
-// larger caps keep the list in global memory.
-constexpr int kCandLdsCap = 48;
+// Surface voxels per workgroup of the candidate search (27 threads each),
+// and the largest grid of that search (it strides over the voxel groups).
+constexpr int kCandVox = 9;
+constexpr int kCandGrid = 512;
 // bucket entries whose loads the candidate search issues together
 constexpr int kGroup = 4;
 
@@ -176,95 +177,104 @@ __global__ void __launch_bounds__(256) k_scatter(StepArgs<T> a, CollideArgs c) {
     su[2 * c.n_surf + pos] = a.s_in[W_UZ * a.stride + ci];
 }
 
+// One workgroup serves kCandVox surface voxels with one thread per (voxel,
+// neighbouring grid cell) pair: each thread scans its cell's bucket and
+// appends the voxel's candidates from that cell to the voxel's list in LDS
+// (an LDS counter per voxel); after a barrier every entry is written to the
+// voxel's global list at its rank among the voxel's entries, so each list is
+// sorted by partner cell.  Partners are distinct within a list, so the rank
+// is unique.  A list that would exceed cap raises the overflow flag and
+// keeps cap of its entries.
 template <typename T>
 __global__ void __launch_bounds__(256) k_candidates(StepArgs<T> a, CollideArgs c) {
-    // slot p of thread t's list at lds_list[p * blockDim.x + t] (caps up to
-    // kCandLdsCap; the launch sizes it)
-    extern __shared__ int lds_list[];
+    extern __shared__ int lds_list[];     // kCandVox x cap partner cells
+    __shared__ int lds_count[kCandVox];
     if (*c.rebuild_flag == 0) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= c.n_surf) return;
-    const bool in_lds = c.cap <= kCandLdsCap;
-    const int ci = c.surf_cells[i];
-    int ix, iy, iz, cx, cy, cz;
-    unpack3(c.cell_ijk[i], ix, iy, iz);
-    unpack3(c.cell_gc[i], cx, cy, cz);
-    const T uxi = a.s_in[W_UX * a.stride + ci], uyi = a.s_in[W_UY * a.stride + ci],
-            uzi = a.s_in[W_UZ * a.stride + ci];
-    const T H = (T)c.horizon;
-    const int ns = c.n_surf;
-    const T *su = (const T *)c.sorted_u;
-    int *list = c.cand + (long long)i * c.cap;
-    const int step = blockDim.x;
-    int *mine = lds_list + threadIdx.x;
-    int count = 0;
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int tx = cx + dx, ty = cy + dy, tz = cz + dz;
-                const int key = cell_hash(tx, ty, tz, c.table_size - 1);
-                const long long want = pack3(tx, ty, tz);
-                const int b0 = c.bucket_start[key], b1 = c.bucket_start[key + 1];
-                // entries in groups of kGroup: the loads of a group are issued
-                // together (a short last group re-reads its last entry, which
-                // is not processed twice), then the entries are taken in order
-                for (int k0 = b0; k0 < b1; k0 += kGroup) {
-                    int cjg[kGroup];
-                    long long gcg[kGroup], ijg[kGroup];
-                    T uxg[kGroup], uyg[kGroup], uzg[kGroup];
-#pragma unroll
-                    for (int q = 0; q < kGroup; ++q) {
-                        const int k = k0 + q < b1 ? k0 + q : b1 - 1;
-                        cjg[q] = c.sorted_cell[k];
-                        gcg[q] = c.sorted_gc[k];
-                        ijg[q] = c.sorted_ijk[k];
-                        uxg[q] = su[k];
-                        uyg[q] = su[ns + k];
-                        uzg[q] = su[2 * ns + k];
-                    }
-#pragma unroll
-                    for (int q = 0; q < kGroup; ++q) {
-                        if (k0 + q >= b1) break;
-                        const int cj = cjg[q];
-                        if (cj == ci || gcg[q] != want) continue;   // another cell in this bucket
-                        int jx, jy, jz;
-                        unpack3(ijg[q], jx, jy, jz);
-                        const int man = abs(jx - ix) + abs(jy - iy) + abs(jz - iz);
-                        if (man <= 3) continue;
-                        const T rx = T(ix - jx) * a.l + (uxi - uxg[q]);
-                        const T ry = T(iy - jy) * a.l + (uyi - uyg[q]);
-                        const T rz = T(iz - jz) * a.l + (uzi - uzg[q]);
-                        if (!(dsqrt(rx * rx + ry * ry + rz * rz) < H)) continue;
-                        if (count < c.cap) {
-                            // insertion keeps the list sorted by partner cell
-                            int p = count;
-                            if (in_lds) {
-                                while (p > 0 && mine[(p - 1) * step] > cj) {
-                                    mine[p * step] = mine[(p - 1) * step];
-                                    --p;
-                                }
-                                mine[p * step] = cj;
-                            } else {
-                                while (p > 0 && list[p - 1] > cj) { list[p] = list[p - 1]; --p; }
-                                list[p] = cj;
-                            }
-                        } else {
-                            atomicOr(c.overflow, 1u);
-                        }
-                        ++count;
-                    }
+    const int t = threadIdx.x;
+    const int v = t / 27, nb = t % 27;
+    const int groups = (c.n_surf + kCandVox - 1) / kCandVox;
+    // grid-stride over groups of voxels: the grid stays small for the steps
+    // whose launch only finds the rebuild flag clear
+    for (int grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+        const int i = grp * kCandVox + v;
+        const bool live = v < kCandVox && i < c.n_surf;
+        if (t < kCandVox) lds_count[t] = 0;
+        __syncthreads();
+        int ci = 0;
+        if (live) {
+            ci = c.surf_cells[i];
+            int ix, iy, iz, cx, cy, cz;
+            unpack3(c.cell_ijk[i], ix, iy, iz);
+            unpack3(c.cell_gc[i], cx, cy, cz);
+            const T uxi = a.s_in[W_UX * a.stride + ci], uyi = a.s_in[W_UY * a.stride + ci],
+                    uzi = a.s_in[W_UZ * a.stride + ci];
+            const T H = (T)c.horizon;
+            const int ns = c.n_surf;
+            const T *su = (const T *)c.sorted_u;
+            const int tx = cx + nb % 3 - 1, ty = cy + (nb / 3) % 3 - 1, tz = cz + nb / 9 - 1;
+            const int key = cell_hash(tx, ty, tz, c.table_size - 1);
+            const long long want = pack3(tx, ty, tz);
+            const int b0 = c.bucket_start[key], b1 = c.bucket_start[key + 1];
+            // entries in groups of kGroup: the loads of a group are issued
+            // together (a short last group re-reads its last entry, which is not
+            // processed twice)
+            for (int k0 = b0; k0 < b1; k0 += kGroup) {
+                int cjg[kGroup];
+                long long gcg[kGroup], ijg[kGroup];
+                T uxg[kGroup], uyg[kGroup], uzg[kGroup];
+    #pragma unroll
+                for (int q = 0; q < kGroup; ++q) {
+                    const int k = k0 + q < b1 ? k0 + q : b1 - 1;
+                    cjg[q] = c.sorted_cell[k];
+                    gcg[q] = c.sorted_gc[k];
+                    ijg[q] = c.sorted_ijk[k];
+                    uxg[q] = su[k];
+                    uyg[q] = su[ns + k];
+                    uzg[q] = su[2 * ns + k];
+                }
+    #pragma unroll
+                for (int q = 0; q < kGroup; ++q) {
+                    if (k0 + q >= b1) break;
+                    const int cj = cjg[q];
+                    if (cj == ci || gcg[q] != want) continue;   // another cell in this bucket
+                    int jx, jy, jz;
+                    unpack3(ijg[q], jx, jy, jz);
+                    const int man = abs(jx - ix) + abs(jy - iy) + abs(jz - iz);
+                    if (man <= 3) continue;
+                    const T rx = T(ix - jx) * a.l + (uxi - uxg[q]);
+                    const T ry = T(iy - jy) * a.l + (uyi - uyg[q]);
+                    const T rz = T(iz - jz) * a.l + (uzi - uzg[q]);
+                    if (!(dsqrt(rx * rx + ry * ry + rz * rz) < H)) continue;
+                    const int slot = atomicAdd(&lds_count[v], 1);
+                    if (slot < c.cap) lds_list[v * c.cap + slot] = cj;
                 }
             }
-    const int kept = count < c.cap ? count : c.cap;
-    if (in_lds)
-        for (int p = 0; p < kept; ++p) list[p] = mine[p * step];
-    c.cand_n[i] = kept;
-    // the candidate bit lives in the flags of the current step
-    uint8_t *flags = const_cast<uint8_t *>(a.flags);
-    uint8_t fl = flags[ci];
-    fl = kept > 0 ? (uint8_t)(fl | FLAG_CAND) : (uint8_t)(fl & ~FLAG_CAND);
-    flags[ci] = fl;
-    if (count) atomicAdd(c.pair_count, (unsigned long long)count);
+        }
+        __syncthreads();
+        if (live) {
+            const int count = lds_count[v];
+            const int kept = count < c.cap ? count : c.cap;
+            const int *mine = lds_list + v * c.cap;
+            int *list = c.cand + (long long)i * c.cap;
+            for (int e = nb; e < kept; e += 27) {
+                const int x = mine[e];
+                int rank = 0;
+                for (int k = 0; k < kept; ++k) rank += mine[k] < x ? 1 : 0;
+                list[rank] = x;
+            }
+            if (nb == 0) {
+                if (count > c.cap) atomicOr(c.overflow, 1u);
+                c.cand_n[i] = kept;
+                // the candidate bit lives in the flags of the current step
+                uint8_t *flags = const_cast<uint8_t *>(a.flags);
+                uint8_t fl = flags[ci];
+                fl = kept > 0 ? (uint8_t)(fl | FLAG_CAND) : (uint8_t)(fl & ~FLAG_CAND);
+                flags[ci] = fl;
+                if (count) atomicAdd(c.pair_count, (unsigned long long)count);
+            }
+        }
+        __syncthreads();   // the group's lists are read before the next group reuses LDS
+    }
 }
 
 __global__ void __launch_bounds__(256) k_rebuild_done(CollideArgs c) {
@@ -347,8 +357,9 @@ hipError_t launch_rebuild(const StepArgs<T> &a, const CollideArgs &c, hipStream_
     k_scan_blocks<<<1, 1024, 0, s>>>(c, nblk);
     k_scan_apply<<<nblk, 256, 0, s>>>(c);
     k_scatter<T><<<gs, 256, 0, s>>>(a, c);
-    const size_t lds = c.cap <= kCandLdsCap ? (size_t)256 * c.cap * sizeof(int) : 0;
-    k_candidates<T><<<gs, 256, lds, s>>>(a, c);
+    const int groups = (c.n_surf + kCandVox - 1) / kCandVox;
+    const unsigned gc = (unsigned)(groups < kCandGrid ? groups : kCandGrid);
+    k_candidates<T><<<gc, 256, (size_t)kCandVox * c.cap * sizeof(int), s>>>(a, c);
     k_rebuild_done<<<(unsigned)((c.table_size + 255) / 256), 256, 0, s>>>(c);
     k_rebuild_clear<<<1, 1, 0, s>>>(c);
     return hipGetLastError();

@@ -117,6 +117,9 @@ struct BatchArgs {
 template <typename T>
 hipError_t launch_batch(const BatchArgs<T> &b, int n_wg, hipStream_t s);
 
+// Largest number of collision candidates per voxel (vx_params.contact_cap).
+constexpr int kMaxContactCap = 1024;
+
 // Collision support (self-collision on).
 struct CollideArgs {
     const int *surf_cells;       // cells taking part (surface voxels, or all filled ones), ascending

@@ -329,3 +329,11 @@ def test_self_collision_rejects_axes_beyond_packed_indices():
     with pytest.raises(vx.VoxsimError):
         vx.Sim(g, [workloads.EMPTY, M1], self_collision_on=1)
     vx.Sim(g, [workloads.EMPTY, M1], self_collision_on=0)
+
+
+def test_contact_cap_is_bounded():
+    """Candidate lists are built in LDS, so contact_cap is at most 1024."""
+    g = np.ones((2, 2, 2), np.uint8)
+    vx.Sim(g, [workloads.EMPTY, M1], self_collision_on=1, contact_cap=1024)
+    with pytest.raises(vx.VoxsimError):
+        vx.Sim(g, [workloads.EMPTY, M1], self_collision_on=1, contact_cap=1025)
