@@ -10,6 +10,8 @@
 // power-of-two table and bucketed by a counting sort (count, scan,
 // scatter).  Bucket order is not deterministic; each voxel's list is kept
 // sorted by partner cell, so the lists themselves are.
+#include <algorithm>
+
 #include "vx_device.hpp"
 #include "vx_launch.hpp"
 
@@ -62,7 +64,7 @@ __device__ __forceinline__ void unpack3(long long v, int &x, int &y, int &z) {
 }
 
 // Surface voxels per workgroup of the candidate search (27 threads each),
-// and the largest grid of that search (it strides over the voxel groups).
+// and the largest grid of the rebuild kernels (they stride over their work).
 constexpr int kCandVox = 9;
 constexpr int kCandGrid = 512;
 // bucket entries whose loads the candidate search issues together
@@ -71,19 +73,20 @@ constexpr int kGroup = 4;
 template <typename T>
 __global__ void __launch_bounds__(256) k_keys(StepArgs<T> a, CollideArgs c, Origin3 o) {
     if (*c.rebuild_flag == 0) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *c.pair_count = 0ull;
-    if (i >= c.n_surf) return;
+    const int first = blockIdx.x * blockDim.x + threadIdx.x;
+    if (first == 0) *c.pair_count = 0ull;
     const T org[3] = {(T)o.v[0], (T)o.v[1], (T)o.v[2]};
-    int ix, iy, iz, cx, cy, cz;
-    T x, y, z;
-    voxel_pos(a, c.surf_cells[i], ix, iy, iz, x, y, z, org);
-    grid_cell(x, y, z, c.horizon, cx, cy, cz);
-    const int key = cell_hash(cx, cy, cz, c.table_size - 1);
-    c.cell_keys[i] = key;
-    c.cell_gc[i] = pack3(cx, cy, cz);
-    c.cell_ijk[i] = pack3(ix, iy, iz);
-    atomicAdd(&c.bucket_fill[key], 1);
+    for (int i = first; i < c.n_surf; i += gridDim.x * blockDim.x) {
+        int ix, iy, iz, cx, cy, cz;
+        T x, y, z;
+        voxel_pos(a, c.surf_cells[i], ix, iy, iz, x, y, z, org);
+        grid_cell(x, y, z, c.horizon, cx, cy, cz);
+        const int key = cell_hash(cx, cy, cz, c.table_size - 1);
+        c.cell_keys[i] = key;
+        c.cell_gc[i] = pack3(cx, cy, cz);
+        c.cell_ijk[i] = pack3(ix, iy, iz);
+        atomicAdd(&c.bucket_fill[key], 1);
+    }
 }
 
 // Scan of bucket counts -> bucket_start (exclusive), in three phases.
@@ -164,17 +167,17 @@ __global__ void __launch_bounds__(256) k_scan_apply(CollideArgs c) {
 template <typename T>
 __global__ void __launch_bounds__(256) k_scatter(StepArgs<T> a, CollideArgs c) {
     if (*c.rebuild_flag == 0) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= c.n_surf) return;
-    const int pos = atomicAdd(&c.bucket_fill[c.cell_keys[i]], 1);
-    const int ci = c.surf_cells[i];
-    c.sorted_cell[pos] = ci;
-    c.sorted_gc[pos] = c.cell_gc[i];
-    c.sorted_ijk[pos] = c.cell_ijk[i];
     T *su = (T *)c.sorted_u;
-    su[pos] = a.s_in[W_UX * a.stride + ci];
-    su[c.n_surf + pos] = a.s_in[W_UY * a.stride + ci];
-    su[2 * c.n_surf + pos] = a.s_in[W_UZ * a.stride + ci];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < c.n_surf; i += gridDim.x * blockDim.x) {
+        const int pos = atomicAdd(&c.bucket_fill[c.cell_keys[i]], 1);
+        const int ci = c.surf_cells[i];
+        c.sorted_cell[pos] = ci;
+        c.sorted_gc[pos] = c.cell_gc[i];
+        c.sorted_ijk[pos] = c.cell_ijk[i];
+        su[pos] = a.s_in[W_UX * a.stride + ci];
+        su[c.n_surf + pos] = a.s_in[W_UY * a.stride + ci];
+        su[2 * c.n_surf + pos] = a.s_in[W_UZ * a.stride + ci];
+    }
 }
 
 // One workgroup serves kCandVox surface voxels with one thread per (voxel,
@@ -279,8 +282,8 @@ __global__ void __launch_bounds__(256) k_candidates(StepArgs<T> a, CollideArgs c
 
 __global__ void __launch_bounds__(256) k_rebuild_done(CollideArgs c) {
     if (*c.rebuild_flag == 0) return;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < c.table_size) c.bucket_fill[j] = 0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < c.table_size; j += gridDim.x * blockDim.x)
+        c.bucket_fill[j] = 0;
 }
 
 __global__ void k_rebuild_clear(CollideArgs c) {
@@ -350,7 +353,10 @@ hipError_t launch_rebuild(const StepArgs<T> &a, const CollideArgs &c, hipStream_
     if (c.n_surf == 0) return hipSuccess;
     Origin3 o;
     o.v[0] = a.origin[0]; o.v[1] = a.origin[1]; o.v[2] = a.origin[2];
-    const unsigned gs = (unsigned)((c.n_surf + 255) / 256);
+    // grids of the per-voxel and per-bucket kernels, capped: they stride,
+    // and most launches only find the rebuild flag clear
+    const auto capped = [](long long n) { return (unsigned)std::min<long long>((n + 255) / 256, kCandGrid); };
+    const unsigned gs = capped(c.n_surf);
     const int nblk = (c.table_size + kScanBlock - 1) / kScanBlock;
     k_keys<T><<<gs, 256, 0, s>>>(a, c, o);
     k_scan_reduce<<<nblk, 256, 0, s>>>(c);
@@ -360,7 +366,7 @@ hipError_t launch_rebuild(const StepArgs<T> &a, const CollideArgs &c, hipStream_
     const int groups = (c.n_surf + kCandVox - 1) / kCandVox;
     const unsigned gc = (unsigned)(groups < kCandGrid ? groups : kCandGrid);
     k_candidates<T><<<gc, 256, (size_t)kCandVox * c.cap * sizeof(int), s>>>(a, c);
-    k_rebuild_done<<<(unsigned)((c.table_size + 255) / 256), 256, 0, s>>>(c);
+    k_rebuild_done<<<capped(c.table_size), 256, 0, s>>>(c);
     k_rebuild_clear<<<1, 1, 0, s>>>(c);
     return hipGetLastError();
 }
