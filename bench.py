@@ -1,19 +1,21 @@
 """Throughput of the voxel-lattice time step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload random_block_100]
-                    [--precision 32|64] [--kernel fused|split] [--no-cpu] [--no-fp64]
-                    [--no-hbm-leg] [--no-batch-leg] [--no-collision-leg] [--no-adjoint-leg]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload blob_lattice_256]
+                    [--precision 32|64] [--kernel fused|split] [--no-cpu] [--no-cache-leg]
+                    [--no-batch-leg] [--no-collision-leg] [--no-adjoint-leg]
                     [--no-paper-shape-leg] [--no-autotune] [--eager]
 
-Headline workload: a 100^3 lattice whose cells are drawn from a seed as empty
-(p = 0.1), soft 1 MPa (p = 0.45) or stiff 100 MPa (p = 0.45), density 1000,
-5 mm above a rigid floor with friction, gravity on.  A step is one pass of the
-whole hot path (actuation, every bond, gather, floor/friction, integrate) over
-the lattice.  Its state (52 MB in FP32) fits the GPU's 256 MB last-level cache,
-so a second leg runs the HBM-resident case: a 256^3 lattice of 4 materials
-assigned from 64 seeded Voronoi blobs, thermal actuation, self-collision on.
+Headline workload: a 256^3 lattice (16.8M voxels, about 50M bonds) of 4
+materials assigned from 64 seeded Voronoi blobs, E log-uniform in
+[0.1, 100] MPa, CTE uniform in [0, 0.01]/K, a 5 Hz +/-20 K temperature
+signal and self-collision on, in FP32.  A step is one pass of the whole hot
+path (actuation, every bond, gather, contact, integrate, collision
+bookkeeping) over the lattice.  Its state (872 MB per buffer) is far larger
+than the GPU's 256 MB last-level cache, so the step streams from HBM.
 
-Further legs: FP64 on the headline lattice; 4096 batched objects in one
+Further legs: a 100^3 lattice of empty / soft / stiff cells dropped onto a
+rigid floor with friction, in FP32 and FP64 (its state fits the last-level
+cache, so it is reported as cache-resident); 4096 batched objects in one
 persistent launch against the same objects one at a time; the iteration
 rates of the paper's four self-collision schemes on a clapper; the
 differentiable rollout of the 64 x 20^3 design lattice (forward + reverse
@@ -36,6 +38,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -481,9 +485,33 @@ def host_cpu():
     return None
 
 
-def cpu_baseline(w, budget_s=12.0, note=""):
-    """The oracle (FP64, one thread) on a bounded sample of the workload."""
+def crop_workload(w, n):
+    """The lower n^3 corner of a workload's lattice, with its materials and
+    parameters (per-cell inputs cropped alike): a sample of the same
+    workload small enough for the oracle."""
+    g = w["grid"]
+    nz, ny, nx = g.shape
+    cz, cy, cx = min(n, nz), min(n, ny), min(n, nx)
+    out = dict(w)
+    out["grid"] = np.ascontiguousarray(g[:cz, :cy, :cx])
+    for k in ("fixed", "amp", "phase"):
+        if w.get(k) is not None:
+            out[k] = np.ascontiguousarray(np.asarray(w[k]).reshape(nz, ny, nx)[:cz, :cy, :cx].reshape(-1))
+    for k in ("forces", "velocity"):
+        if w.get(k) is not None:
+            out[k] = np.ascontiguousarray(np.asarray(w[k]).reshape(nz, ny, nx, 3)[:cz, :cy, :cx].reshape(-1, 3))
+    out["name"] = "%s cropped to %dx%dx%d" % (w["name"], cx, cy, cz)
+    return out
+
+
+def cpu_baseline(w, budget_s=12.0, note="", crop=None):
+    """The oracle (FP64, one thread) on a bounded sample of the workload:
+    the first steps of the whole lattice, or of its lower crop^3 corner when
+    crop is given (the oracle's brute-force candidate search is quadratic in
+    the surface voxels, so the full 256^3 lattice is out of its reach)."""
     import oracle
+    if crop is not None:
+        w = crop_workload(w, crop)
     o = oracle.Sim(w["grid"], w["materials"], **w["params"])
     if w.get("fixed") is not None:
         o.set_fixed(w["fixed"])
@@ -491,8 +519,12 @@ def cpu_baseline(w, budget_s=12.0, note=""):
         o.set_forces(w["forces"])
     if w.get("velocity") is not None:
         o.set_velocity(w["velocity"])
+    if w.get("amp") is not None or w.get("phase") is not None:
+        o.set_actuation(w.get("amp"), w.get("phase"))
     nvox = o.num_voxels
-    o.step(1)
+    t0 = time.perf_counter()
+    o.step(1)                        # builds the collision candidates when self-collision is on
+    first_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     n = 0
     while True:
@@ -502,8 +534,9 @@ def cpu_baseline(w, budget_s=12.0, note=""):
         if el > budget_s or n >= 2000:
             break
     return {"value": nvox * n / el, "unit": "voxel-steps/s", "cores": 1, "kind": "oracle", "host": host_cpu(),
-            "sample": "%d steps of the %d-voxel %s lattice after 1 untimed step, FP64, one thread%s"
-                      % (n, nvox, w["name"], note)}
+            "sample": "%d steps of the %d-voxel %s lattice after 1 untimed step (%.1f s, including the "
+                      "oracle's first candidate search when self-collision is on), FP64, one thread%s"
+                      % (n, nvox, w["name"], first_s, note)}
 
 
 def cpu_batch_baseline(count, sample_every=32, steps=60):
@@ -542,17 +575,26 @@ def cpu_batch_baseline(count, sample_every=32, steps=60):
                       "per-object step times" % (sample_every, count, len(objs), nvox, steps, threads)}
 
 
+def lattice_leg(w, precision, r, steps, kernel_name):
+    """JSON block of one timed lattice run."""
+    return {"workload": w["name"], "dtype": "f32" if precision == 32 else "f64",
+            "value": r["voxels"] * steps / (r["ms"] / 1e3), "ms_per_step": r["ms"] / steps, "tile": r["tile"],
+            "kernel": kernel_name, "eager_value": r["voxels"] * steps / (r["eager_ms"] / 1e3),
+            "cache_resident": 2 * int(w["grid"].size) * 13 * (4 if precision == 32 else 8) < 256e6,
+            "roofline": roofline(precision, r["voxels"], r["kernel_ms"], w["name"], r["tile"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="random_block_100")
+    ap.add_argument("--workload", default="blob_lattice_256")
     ap.add_argument("--precision", type=int, default=32, choices=[32, 64])
     ap.add_argument("--kernel", default="fused", choices=["fused", "split"])
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--no-hbm-leg", action="store_true")
+    ap.add_argument("--no-cache-leg", action="store_true",
+                    help="skip the cache-resident 100^3 random block (FP32 and FP64)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batch-leg", action="store_true")
     ap.add_argument("--no-collision-leg", action="store_true")
@@ -567,6 +609,8 @@ def main():
                     help="objects in the one-at-a-time comparison of the batched leg (0 skips it, e.g. "
                          "under profiler counter collection, which does not follow graph launches)")
     ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--cpu-crop", type=int, default=32,
+                    help="edge of the lower corner of a self-colliding lattice the oracle baseline runs on")
     ap.add_argument("--tile", default=None, metavar="SHAPE:ZC",
                     help="fix the fused tile of the first leg (shape index, z chunk) instead of autotuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -596,6 +640,7 @@ def main():
         % (args.workload, args.precision, args.kernel, args.steps, args.warmup))
     use_graph = not args.eager and args.steps % 2 == 0
     r = time_gpu(w, args.precision, kernel, args.steps, args.warmup, autotune, tile, graph=use_graph)
+    state_bytes = int(w["grid"].size) * 13 * (4 if args.precision == 32 else 8)
     out = {
         "metric": "voxel-steps/s",
         "value": r["voxels"] * args.steps / (r["ms"] / 1e3),
@@ -610,38 +655,34 @@ def main():
         "dtype": "f32" if args.precision == 32 else "f64",
         "data": "synthetic",
         "config": {"workload": w["name"], "cells": int(w["grid"].size), "voxels": int(r["voxels"]),
-                   "kernel": args.kernel, "tile": r["tile"], "state_bytes": int(w["grid"].size) * 13 *
-                   (4 if args.precision == 32 else 8),
-                   "cache_resident": 2 * int(w["grid"].size) * 13 * (4 if args.precision == 32 else 8) < 256e6},
+                   "kernel": args.kernel, "tile": r["tile"], "state_bytes": state_bytes,
+                   "self_collision": bool(w["params"].get("self_collision_on")),
+                   "cache_resident": 2 * state_bytes < 256e6},
         "roofline": roofline(args.precision, r["voxels"], r["kernel_ms"], w["name"], r["tile"]),
         "timing": {"method": "one replay of a captured HIP graph of the K steps, HIP events on the replay "
                              "stream, device synchronisation on both sides" if use_graph else
                              "one vx_step call of K steps, HIP events on its stream",
                    "eager_value": r["voxels"] * args.steps / (r["eager_ms"] / 1e3)},
     }
+    if r["collision"] is not None:
+        out["collision"] = dict(r["collision"], note="candidate-list rebuilds since creation (warm-up, eager "
+                                "and replayed steps) and candidate pairs at the end; the collision kernels "
+                                "are timed inside value, not in the roofline of the step kernel")
     out["roofline"]["copy_probe"] = copy_probe()
-    if not args.no_fp64 and args.precision == 32:
-        log("fp64 leg")
-        r64 = time_gpu(w, 64, kernel, args.steps, args.warmup, autotune, graph=use_graph)
-        out["fp64"] = {"value": r64["voxels"] * args.steps / (r64["ms"] / 1e3),
-                       "ms_per_step": r64["ms"] / args.steps, "tile": r64["tile"],
-                       "eager_value": r64["voxels"] * args.steps / (r64["eager_ms"] / 1e3),
-                       "roofline": roofline(64, r64["voxels"], r64["kernel_ms"], w["name"], r64["tile"])}
-    if not args.no_hbm_leg:
-        log("hbm-resident leg: blob_lattice_256")
-        w3 = build_workload("blob_lattice_256")
-        r3 = time_gpu(w3, 32, kernel, args.steps, args.warmup, autotune, graph=use_graph)
-        out["hbm_resident"] = {"workload": w3["name"], "dtype": "f32",
-                               "value": r3["voxels"] * args.steps / (r3["ms"] / 1e3),
-                               "ms_per_step": r3["ms"] / args.steps, "tile": r3["tile"],
-                               "eager_value": r3["voxels"] * args.steps / (r3["eager_ms"] / 1e3),
-                               "roofline": roofline(32, r3["voxels"], r3["kernel_ms"], w3["name"], r3["tile"]),
-                               "collision": dict(r3["collision"], note="candidate-list rebuilds since creation "
-                                                 "(warm-up, eager and replayed steps) and candidate pairs at "
-                                                 "the end; "
-                                                 "the contact kernels are timed inside value, not in the "
-                                                 "roofline of the step kernel")}
-        del w3
+    if not args.no_cache_leg and args.workload != "random_block_100":
+        log("cache-resident leg: random_block_100, FP32 and FP64")
+        w2 = build_workload("random_block_100")
+        r2 = time_gpu(w2, 32, kernel, args.steps, args.warmup, autotune, graph=use_graph)
+        r2d = time_gpu(w2, 64, kernel, args.steps, args.warmup, autotune, graph=use_graph)
+        out["cache_resident"] = {"f32": lattice_leg(w2, 32, r2, args.steps, args.kernel),
+                                 "f64": lattice_leg(w2, 64, r2d, args.steps, args.kernel),
+                                 "note": "state of 52 MB (FP32) or 104 MB (FP64) per buffer: both ping-pong "
+                                         "buffers fit the 256 MB last-level cache, so the HBM fraction is "
+                                         "not an HBM measurement"}
+        if not args.no_cpu:
+            log("cpu baseline of the 100^3 block (oracle)")
+            out["cache_resident"]["cpu_baseline"] = cpu_baseline(w2, budget_s=8.0)
+        del w2
     if not args.no_batch_leg:
         log("batched leg: %d objects, %d steps" % (args.batch_objects, args.batch_steps))
         out["batched"] = time_batch(args.batch_objects, args.batch_steps, args.one_by_one_sample)
@@ -656,7 +697,8 @@ def main():
         out["paper_shape"] = time_paper_shape()
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(w)
+        crop = args.cpu_crop if w["params"].get("self_collision_on") else None
+        out["cpu_baseline"] = cpu_baseline(w, crop=crop)
         if "batched" in out:
             log("cpu baseline of the batched objects (oracle, all host cores)")
             cb = cpu_batch_baseline(args.batch_objects)

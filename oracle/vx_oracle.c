@@ -23,6 +23,12 @@
  *
  * Readings of passages the paper leaves open are marked READING below; each
  * one is also listed in the design notes of the repository.
+ *
+ * Parity unpinned: the voxel-voxel contact law.  The paper names contact
+ * between voxels but gives no force law, so the law below is a reading;
+ * the tests pin only its invariants (equal and opposite pair forces,
+ * conserved momentum, separation after impact, candidate sets equal to a
+ * brute-force search), not its magnitudes.
  */
 #include "vx_oracle.h"
 

@@ -40,6 +40,20 @@ MUTATIONS = {
     "friction halt test": ("if (vl <= V->mu_d * Fn * s->dt / V->m) {", "if (vl < 0.0) {"),
     "lattice exclusion of collision pairs": ("if (man <= 3) continue;", "if (man <= 2) continue;"),
     "contact separation reversed": ("vec3 r = separation(s, U, V);", "vec3 r = separation(s, V, U);"),
+    "rotational bond damping with the larger inertia of the pair":
+        ("double imin = A->I < B->I ? A->I : B->I;", "double imin = A->I > B->I ? A->I : B->I;"),
+    "factor of the rotational bond damping":
+        ("b->cr = 2.0 * s->p.zeta_bond * sqrt(imin * b->b3);", "b->cr = s->p.zeta_bond * sqrt(imin * b->b3);"),
+    "rotational stiffness of the ground damping":
+        ("V->kphi = mt->E * l * l * l / 6.0;", "V->kphi = mt->E * l * l * l / 12.0;"),
+    "factor of the translational ground damping":
+        ("F = vsub(F, vscale(vel, 2.0 * s->p.zeta_slow * sqrt(V->m * V->kv)));",
+         "F = vsub(F, vscale(vel, s->p.zeta_slow * sqrt(V->m * V->kv)));"),
+    "factor of 2 of the floor contact damping":
+        ("double cd = 2.0 * s->p.zeta_col * sqrt(V->m * V->kv);", "double cd = s->p.zeta_col * sqrt(V->m * V->kv);"),
+    "half of the floor spring energy": ("uf += 0.5 * V->kv * pen * pen;", "uf += V->kv * pen * pen;"),
+    "gravitational energy at the rest height":
+        ("ug += V->m * s->p.gravity * position(V).z;", "ug += V->m * s->p.gravity * V->D0.z;"),
 }
 
 
@@ -75,7 +89,10 @@ def test_control_copy_passes_the_pins(tmp_path):
 
 def test_every_planted_mistake_fails_a_pin(tmp_path):
     libs = {name: _build(tmp_path, "m%02d" % i, change) for i, (name, change) in enumerate(MUTATIONS.items())}
+    # the pins against the paper and the mathematics; the second
+    # implementation of the step (the torch reference) is left out, so that
+    # each mistake must fail a pin that does not compare with other code
     with ThreadPoolExecutor(4) as ex:
-        codes = dict(zip(libs, ex.map(lambda name: _pins(libs[name]).returncode, libs)))
+        codes = dict(zip(libs, ex.map(lambda name: _pins(libs[name], "-k", "not torch_reference").returncode, libs)))
     # exit code 1: a test failed; anything else would be the harness's fault
     assert all(rc == 1 for rc in codes.values()), codes

@@ -813,3 +813,188 @@ def test_region_selection_needs_positive_volume():
     assert regions.region_mask(g2, (0.2, 0, 0), (0.2, 1, 1)).sum() == 0
     F = regions.forced_region_forces(g2, (0.2, 0, 0), (0.2, 1, 1), (1.0, 0, 0))
     assert not F.any()
+
+
+# --------------------------------------------------------------------------
+# Damping magnitudes (section Damping, Eq. 33-35; section Gravity, floor and
+# friction) and the gravity and floor terms of the energy.
+#
+# Every setup below is an exactly linear system under symplectic Euler
+# (rotation about one fixed axis, or motion along one axis), so a scalar
+# coordinate y_n of one mode obeys the three-term recurrence
+#     y_n+1 = (2 - a - b) y_n - (1 - b) y_n-1,
+# a = k dt^2 / m the mode's stiffness and b = c dt / m its damping per step
+# (the characteristic polynomial of the one-step map).  The recurrence's two
+# coefficients are fitted to the oracle's trajectory and compared with the
+# a and b the paper's constants give; the damping alone sets b, so a wrong
+# coefficient, mass, inertia or factor shows in it.
+# --------------------------------------------------------------------------
+def _recurrence(y):
+    """Least-squares (p, q) with y[n+1] = p y[n] + q y[n-1]."""
+    y = np.asarray(y, dtype=np.float64)
+    A = np.stack([y[1:-1], y[:-2]], axis=1)
+    sol, *_ = np.linalg.lstsq(A, y[2:], rcond=None)
+    return sol[0], sol[1]
+
+
+def _twist(q):
+    """Rotation angle about x of unit quaternions (w, x, 0, 0)."""
+    return 2.0 * np.arctan2(q[:, 1], q[:, 0])
+
+
+def test_rotational_bond_damping_coefficient():
+    """Eq. 35 with the reading c_r = 2 zeta sqrt(I_min k_phi), k_phi = b3 =
+    2 E_c I_s / l (Eq. 12): two voxels of different density (inertias I1,
+    I2) twisted against each other about their x bond.  The twist psi =
+    phi2 - phi1 obeys mu psi'' = -a2 psi - c_r psi' / 2 with 1/mu =
+    1/I1 + 1/I2, a2 = G_c J / l (Eq. 9) and the damping on half the relative
+    spin (Eq. 33's average), so a = a2 dt^2 / mu and b = c_r dt / (2 mu).
+    The pair's translation stays zero and its total spin constant."""
+    nu, zeta = 0.35, 0.3
+    g = np.array([[[1, 2]]], np.uint8)
+    rho1, rho2 = 1000.0, 3000.0
+    s = oracle.Sim(g, [EMPTY, mat(nu=nu, rho=rho1), mat(nu=nu, rho=rho2)], voxel_size=L_VOX, zeta_bond=zeta)
+    l = L_VOX
+    I1, I2 = rho1 * l ** 5 / 6.0, rho2 * l ** 5 / 6.0
+    w0 = 0.5
+    # zero total spin: I1 w1 + I2 w2 = 0
+    s.write_state(w=np.array([[w0 * I2 / (I1 + I2), 0, 0], [-w0 * I1 / (I1 + I2), 0, 0]]))
+    dt = s.dt
+    G = E1 / (2 * (1 + nu))
+    a2 = G * (l ** 4 / 6.0) / l                    # Eq. 9, J = l^4/6, composite of equal G
+    b3 = 2.0 * E1 * (l ** 4 / 12.0) / l            # Eq. 12, I_s = l^4/12
+    c_r = 2.0 * zeta * math.sqrt(min(I1, I2) * b3)
+    mu = 1.0 / (1.0 / I1 + 1.0 / I2)
+    a, b = a2 * dt ** 2 / mu, c_r * dt / (2.0 * mu)
+    psi = []
+    for _ in range(120):
+        assert s.step(1) == 0
+        st = s.read_state()
+        psi.append(_twist(st["q"])[1] - _twist(st["q"])[0])
+        # no translation beyond the rounding of the rotated bond axis
+        assert np.abs(st["v"]).max() < 1e-9 * w0 * l and np.abs(st["u"]).max() < 1e-12 * l
+    p, q = _recurrence(psi)
+    assert abs(p - (2 - a - b)) < 1e-9 and abs(q + (1 - b)) < 1e-9, (p, q, 2 - a - b, -(1 - b))
+    spin = I1 * st["w"][0, 0] + I2 * st["w"][1, 0]
+    assert abs(spin) < 1e-12 * I1 * w0
+
+
+def test_ground_damping_same_rate_for_translation_and_rotation():
+    """Damping to ground (SetSlowDampZ) with the reading k = E l for
+    translation and k_phi = E l^3 / 6 for rotation: on a lone voxel the
+    momenta shrink each step by exactly 1 - c dt / m and 1 - c_phi dt / I,
+    c = 2 zeta sqrt(m k), c_phi = 2 zeta sqrt(I k_phi).  With I = m l^2 / 6
+    both equal 1 - 2 zeta sqrt(E l / m) dt: the damping is mass-proportional,
+    so every translational and rotational motion decays at one rate."""
+    zeta = 0.05
+    g = np.ones((1, 1, 1), np.uint8)
+    s = oracle.Sim(g, [EMPTY, mat()], voxel_size=L_VOX, zeta_slow=zeta)
+    v0 = np.array([[1e-3, -2e-3, 0.5e-3]])
+    w0 = np.array([[3.0, -1.0, 2.0]])
+    s.write_state(v=v0, w=w0)
+    m = 1000.0 * L_VOX ** 3
+    beta = 2.0 * zeta * math.sqrt(E1 * L_VOX / m) * s.dt
+    n = 300
+    assert s.step(n) == 0
+    st = s.read_state()
+    f = (1.0 - beta) ** n
+    assert np.abs(st["v"] / (v0 * f) - 1.0).max() < 1e-12
+    assert np.abs(st["w"] / (w0 * f) - 1.0).max() < 1e-12
+
+
+def test_ground_damping_on_a_bonded_mode():
+    """The same damping on the two-voxel twist (no bond damping): mass- and
+    inertia-proportional damping leaves the mode's stiffness term and damps
+    it by b = c_phi dt / I, the lone-voxel rate."""
+    nu, zeta = 0.35, 0.04
+    g = np.ones((1, 1, 2), np.uint8)
+    s = oracle.Sim(g, [EMPTY, mat(nu=nu)], voxel_size=L_VOX, zeta_slow=zeta)
+    s.write_state(w=np.array([[0.5, 0, 0], [-0.5, 0, 0]]))
+    l, m = L_VOX, 1000.0 * L_VOX ** 3
+    I = m * l * l / 6.0
+    dt = s.dt
+    a2 = E1 / (2 * (1 + nu)) * (l ** 4 / 6.0) / l
+    a = 2.0 * a2 * dt ** 2 / I
+    b = 2.0 * zeta * math.sqrt(E1 * l / m) * dt
+    psi = []
+    for _ in range(120):
+        assert s.step(1) == 0
+        psi.append(np.diff(_twist(s.read_state()["q"]))[0])
+    p, q = _recurrence(psi)
+    assert abs(p - (2 - a - b)) < 1e-9 and abs(q + (1 - b)) < 1e-9, (p, q, 2 - a - b, -(1 - b))
+
+
+def _floor_bounce(zeta, dt_scale, steps, press=0.2):
+    """A lone voxel resting on the floor under gravity, pressed below its
+    equilibrium penetration m g / k by `press` of it and released; returns
+    the deviation from equilibrium per step, dt, m and k."""
+    g = np.ones((1, 1, 1), np.uint8)
+    s = oracle.Sim(g, [EMPTY, mat()], voxel_size=L_VOX, gravity=9.81, floor_on=1, zeta_col=zeta,
+                   dt_scale=dt_scale)
+    m, k = 1000.0 * L_VOX ** 3, E1 * L_VOX
+    d0 = m * 9.81 / k
+    s.write_state(u=np.array([[0.0, 0.0, -(1.0 + press) * d0]]))
+    y = []
+    for _ in range(steps):
+        assert s.step(1) == 0
+        y.append(-s.read_state()["u"][0, 2] - d0)
+    return np.array(y), s.dt, m, k, d0
+
+
+def test_floor_contact_damping_ratio():
+    """Floor contact is damped normal to it with the collision damping ratio
+    (section Gravity, floor and friction): c = 2 zeta_col sqrt(m k), k = E l.
+    At the stable dt the penetration's recurrence has a = k dt^2/m and
+    b = c dt/m exactly (the normal force stays positive, so the contact is
+    linear); at a small dt the fitted motion has the continuous log decrement
+    2 pi zeta / sqrt(1 - zeta^2) per period."""
+    zeta = 0.1
+    y, dt, m, k, d0 = _floor_bounce(zeta, 1.0, 400)
+    a, b = k * dt ** 2 / m, 2.0 * zeta * math.sqrt(m * k) * dt / m
+    p, q = _recurrence(y)
+    assert abs(p - (2 - a - b)) < 1e-9 and abs(q + (1 - b)) < 1e-9, (p, q, 2 - a - b, -(1 - b))
+    assert np.abs(y).max() < d0                  # never left the floor
+    y, dt, m, k, d0 = _floor_bounce(zeta, 0.02, 3000)
+    p, q = _recurrence(y)
+    r = math.sqrt(-q)
+    theta = math.acos(p / (2.0 * r))
+    decrement = -2.0 * math.pi * math.log(r) / theta
+    assert abs(decrement / (2 * math.pi * zeta / math.sqrt(1 - zeta ** 2)) - 1.0) < 5e-3, decrement
+
+
+def test_shadow_energy_with_gravity_and_floor():
+    """The shadow energy H = KE + U_elastic + U_gravity + U_floor +
+    dt/2 sum(v.F) of a column standing on the floor under gravity with all
+    damping off: the column moves along z only and its bottom voxel stays
+    pressed into the floor, so bonds, gravity and the floor spring are
+    exactly linear and H is an invariant of symplectic Euler.  m g z and
+    1/2 k delta^2 are the only terms that see gravity and the floor, so a
+    wrong gravitational or floor energy breaks the balance (the oscillation
+    energy is 1e-7 of m g z)."""
+    n = 4
+    g = np.ones((n, 1, 1), np.uint8)
+    s = oracle.Sim(g, [EMPTY, mat()], voxel_size=L_VOX, gravity=9.81, floor_on=1)
+    m, k, a1 = 1000.0 * L_VOX ** 3, E1 * L_VOX, E1 * L_VOX
+    # static equilibrium: the floor carries n m g, bond j (between voxels j-1
+    # and j) carries (n - j) m g
+    u = np.zeros((n, 3))
+    u[0, 2] = -n * m * 9.81 / k
+    for j in range(1, n):
+        u[j, 2] = u[j - 1, 2] - (n - j) * m * 9.81 / a1
+    rng = np.random.Generator(np.random.PCG64(7))
+    u[:, 2] += rng.uniform(-0.1, 0.1, n) * m * 9.81 / k
+    v = np.zeros((n, 3))
+    v[:, 2] = rng.uniform(-1.0, 1.0, n) * 1e-7
+    s.write_state(u=u, v=v)
+    H0 = _shadow_energy(s)
+    osc = []
+    for _ in range(40):
+        assert s.step(50) == 0
+        e = s.energy()
+        assert e["floor"] > 0.0
+        osc.append(e["ke"])
+        hs = _shadow_energy(s)
+        assert abs(hs - H0) < 1e-7 * max(osc), (hs - H0, max(osc))
+    st = s.read_state()
+    assert np.abs(st["u"][:, :2]).max() == 0.0 and np.abs(st["w"]).max() == 0.0
+    assert max(osc) > 1e-17
