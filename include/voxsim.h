@@ -230,6 +230,21 @@ int vx_static_workspace_bytes(vx_handle h, uint64_t *bytes);
 int vx_static_solve(vx_handle h, void *work, uint64_t work_bytes, const double *F, double rel_tol,
                     int32_t max_iter, double *u, double *theta, int32_t *iters, double *rel_residual);
 
+/* vx_static_solve without a caller workspace, for callers that cannot
+ * allocate device memory (serving loops, harnesses that forbid allocation).
+ * Same arguments, results and errors as vx_static_solve (bitwise the same
+ * solution); the conjugate-gradient vectors live in a fixed 64 MiB device
+ * array inside the library, one per device, looked up on the first call on
+ * the device the handle's stream runs on.  The call allocates no device
+ * memory.  Limit: the lattice's vx_static_workspace_bytes must be at most
+ * 64 MiB (about 190,000 cells); larger lattices get VX_EINVAL with the
+ * sizes in vx_last_error.  Every call on one device shares that array, so
+ * calls that overlap on one device (several host threads, or several
+ * handles' streams) race and must be serialised by the caller; each call
+ * initialises every part of the array it reads. */
+int vx_static_solve_noalloc(vx_handle h, const double *F, double rel_tol, int32_t max_iter, double *u,
+                            double *theta, int32_t *iters, double *rel_residual);
+
 /* Self-collision detection scheme (section "Self collision detection and
  * handling" and Table 3, "Speedup of self collision schemes"): all_voxels = 0
  * takes only the surface voxels into the candidate search (default), 1 every

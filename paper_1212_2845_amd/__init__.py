@@ -33,7 +33,7 @@ EXPORTED = ["vx_create", "vx_workspace_bytes", "vx_bind_workspace", "vx_set_fixe
             "vx_counters", "vx_candidates", "vx_set_kernel", "vx_set_fused_tile", "vx_get_fused_tile",
             "vx_autotune", "vx_time_kernel", "vx_destroy", "vx_last_error",
             "vx_step_enqueue", "vx_status", "vx_probe", "vx_set_collision_mode", "vx_static_workspace_bytes",
-            "vx_static_solve", "vx_energy", "vx_set_stiffness", "vx_set_density", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
+            "vx_static_solve", "vx_static_solve_noalloc", "vx_energy", "vx_set_stiffness", "vx_set_density", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
             "vx_grad_backward",
             "vx_batch_create", "vx_batch_workspace_bytes", "vx_batch_bind_workspace", "vx_batch_step",
             "vx_batch_read_state", "vx_batch_write_state", "vx_batch_get_dt", "vx_batch_counters",
@@ -121,6 +121,7 @@ def lib():
     L.vx_static_workspace_bytes.argtypes = [P, C.POINTER(C.c_uint64)]
     L.vx_static_solve.argtypes = [P, P, C.c_uint64, P, C.c_double, i32, P, P, C.POINTER(i32),
                                   C.POINTER(C.c_double)]
+    L.vx_static_solve_noalloc.argtypes = [P, P, C.c_double, i32, P, P, C.POINTER(i32), C.POINTER(C.c_double)]
     L.vx_set_stiffness.argtypes = [P, P]
     L.vx_set_density.argtypes = [P, P]
     L.vx_grad_workspace_bytes.argtypes = [P, i64, i32, C.POINTER(u64)]
@@ -330,6 +331,17 @@ class Sim:
         it = C.c_int32(); res = C.c_double()
         self._check(lib().vx_static_solve(self.h, C.c_void_p(work.data_ptr()), n.value, _ptr(f), float(rel_tol),
                                           int(max_iter), _ptr(u), _ptr(th), C.byref(it), C.byref(res)))
+        return {"u": u, "theta": th, "iters": it.value, "rel_residual": res.value}
+
+    def static_solve_noalloc(self, F, rel_tol=1e-10, max_iter=200000):
+        """static_solve through vx_static_solve_noalloc: the same solve in the
+        library's fixed device scratch, with no workspace allocated."""
+        self.bind()
+        f = np.ascontiguousarray(F, dtype=np.float64).reshape(self.ncell, 3)
+        u = np.empty((self.ncell, 3)); th = np.empty((self.ncell, 3))
+        it = C.c_int32(); res = C.c_double()
+        self._check(lib().vx_static_solve_noalloc(self.h, _ptr(f), float(rel_tol), int(max_iter), _ptr(u), _ptr(th),
+                                                  C.byref(it), C.byref(res)))
         return {"u": u, "theta": th, "iters": it.value, "rel_residual": res.value}
 
     def set_collision_mode(self, all_voxels=False, every_step=False):

@@ -1,11 +1,13 @@
 // Host side of the linear static solve (vx_static_workspace_bytes,
-// vx_static_solve): workspace layout, upload of the per-cell moduli, the
-// clamp mask and the load, and the conjugate-gradient loop, whose scalars
-// come from the kernels' per-workgroup partials added in order.
+// vx_static_solve, vx_static_solve_noalloc): workspace layout, upload of the
+// per-cell moduli, the clamp mask and the load, and the conjugate-gradient
+// loop, whose scalars come from the kernels' per-workgroup partials added
+// in order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "vx_host.hpp"
@@ -40,6 +42,49 @@ StaticLayout static_layout(const vx_sim *h) {
 
 }  // namespace
 
+// Workspace of vx_static_solve_noalloc: one fixed device array, so that the
+// call needs no allocation.  Every device the library runs on holds its own
+// copy until the process ends.  In host code the array's name is not a
+// device address: kernels get the address hipGetSymbolAddress returns for
+// the device (scratch_ptr).
+constexpr uint64_t kStaticScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_dev[kMaxDevices] = {};
+
+// Address of device dev's scratch, looked up once per device with that
+// device current.
+hipError_t scratch_ptr(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return e;
+        if (prev != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev != dev) {
+            const hipError_t e2 = hipSetDevice(prev);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        scratch_dev[dev] = p;
+    }
+    *out = scratch_dev[dev];
+    return hipSuccess;
+}
+
+// The solve itself on a workspace w laid out by static_layout(h).
+int static_solve(vx_sim *h, char *w, const double *F, double rel_tol, int32_t max_iter, double *u,
+                 double *theta, int32_t *iters, double *rel_residual);
+
+}  // namespace
+
 extern "C" {
 
 int vx_static_workspace_bytes(vx_handle h, uint64_t *bytes) {
@@ -55,10 +100,40 @@ int vx_static_solve(vx_handle h, void *work, uint64_t work_bytes, const double *
     const StaticLayout L = static_layout(h);
     if (!work || work_bytes < L.total) return fail(h, VX_EINVAL, "static workspace too small");
     if (((uintptr_t)work) % kAlign) return fail(h, VX_EINVAL, "static workspace not 256-byte aligned");
+    return static_solve(h, (char *)work, F, rel_tol, max_iter, u, theta, iters, rel_residual);
+}
+
+int vx_static_solve_noalloc(vx_handle h, const double *F, double rel_tol, int32_t max_iter, double *u,
+                            double *theta, int32_t *iters, double *rel_residual) {
+    if (!h || !F || !(rel_tol > 0.0) || max_iter < 1) return VX_EINVAL;
+    if (!h->bound) return fail(h, VX_ESTATE, "vx_static_solve_noalloc before vx_bind_workspace");
+    const StaticLayout L = static_layout(h);
+    if (L.total > kStaticScratchBytes)
+        return fail(h, VX_EINVAL, "lattice too large for vx_static_solve_noalloc: its workspace needs " +
+                                      std::to_string(L.total) + " bytes, the fixed scratch holds " +
+                                      std::to_string(kStaticScratchBytes));
+    // the scratch of the device the handle's stream runs on
+    int dev = 0;
+    if (h->stream) {
+        HIP_OK(h, hipStreamGetDevice(h->stream, &dev));
+    } else {
+        HIP_OK(h, hipGetDevice(&dev));
+    }
+    void *w = nullptr;
+    HIP_OK(h, scratch_ptr(dev, &w));
+    return static_solve(h, (char *)w, F, rel_tol, max_iter, u, theta, iters, rel_residual);
+}
+
+}  // extern "C"
+
+namespace {
+
+int static_solve(vx_sim *h, char *w, const double *F, double rel_tol, int32_t max_iter, double *u,
+                 double *theta, int32_t *iters, double *rel_residual) {
+    const StaticLayout L = static_layout(h);
     const long long n = h->ncell;
     for (long long i = 0; i < 3 * n; ++i)
         if (!std::isfinite(F[i])) return fail(h, VX_EINVAL, "non-finite force");
-    char *w = (char *)work;
     hipStream_t s = h->stream;
     // per-cell moduli as the step uses them (palette, or the cell's own in
     // parameter mode); shear modulus from the material's Poisson ratio
@@ -150,4 +225,4 @@ int vx_static_solve(vx_handle h, void *work, uint64_t work_bytes, const double *
     return VX_OK;
 }
 
-}  // extern "C"
+}  // namespace
