@@ -71,6 +71,9 @@ def lib():
         L.vxo_candidates.argtypes = [P, P, P, C.c_int]
         L.vxo_energy.argtypes = [P, dp]
         L.vxo_bond_results.argtypes = [P, P, P, P, P]
+        L.vxo_set_channels.argtypes = [P, P, C.c_int, P, C.c_int, P]
+        L.vxo_channel_value.restype = C.c_double
+        L.vxo_channel_value.argtypes = [P, C.c_double]
         _lib = L
     return _lib
 
@@ -105,6 +108,33 @@ def make_params(**kw):
     p.self_collision_on = int(kw.get("self_collision_on", 0))
     p.contact_cap = int(kw.get("contact_cap", 32))
     return p
+
+
+WAVEFORMS = {"sine": 0, "triangle": 1, "square": 2}
+
+
+class Channel(C.Structure):
+    _fields_ = [("amp", C.c_double), ("freq", C.c_double), ("phase", C.c_double), ("offset", C.c_double),
+                ("waveform", C.c_int32), ("pad", C.c_int32)]
+
+
+def make_channels(channels):
+    """ctypes array of channel dicts {amp, freq, phase, offset, waveform}."""
+    arr = (Channel * max(len(channels), 1))()
+    for i, c in enumerate(channels):
+        arr[i].amp = float(c.get("amp", 0.0))
+        arr[i].freq = float(c.get("freq", 0.0))
+        arr[i].phase = float(c.get("phase", 0.0))
+        arr[i].offset = float(c.get("offset", 0.0))
+        wf = c.get("waveform", "sine")
+        arr[i].waveform = WAVEFORMS[wf] if isinstance(wf, str) else int(wf)
+    return arr
+
+
+def channel_value(channel, t):
+    """The oracle's temperature of one channel dict at time t."""
+    arr = make_channels([channel])
+    return lib().vxo_channel_value(C.cast(arr, C.c_void_p), float(t))
 
 
 class Sim:
@@ -151,6 +181,18 @@ class Sim:
     def set_velocity(self, v):
         vv = np.ascontiguousarray(v, dtype=np.float64).reshape(self.ncell, 3)
         lib().vxo_set_velocity(self.h, _ptr(vv))
+
+    def set_channels(self, channels, mat_channel=None, cell_channel=None):
+        """Named actuation channels: a list of dicts {amp, freq, phase,
+        offset, waveform}; mat_channel gives each palette entry's channel
+        (-1 none), cell_channel each cell's (-1: its material's)."""
+        self._chan = make_channels(channels)
+        mc = None if mat_channel is None else np.ascontiguousarray(mat_channel, dtype=np.int32)
+        cc = None if cell_channel is None else np.ascontiguousarray(cell_channel, dtype=np.int32).reshape(-1)
+        rc = lib().vxo_set_channels(self.h, C.cast(self._chan, C.c_void_p), len(channels), _ptr(mc),
+                                    0 if mc is None else mc.size, _ptr(cc))
+        if rc != 0:
+            raise ValueError("oracle rejected the channels")
 
     def set_rebuild_every_step(self, on=True):
         lib().vxo_set_rebuild_every_step(self.h, int(on))

@@ -127,6 +127,7 @@ typedef struct {
     double kv, kphi;       /* translational / rotational stiffness to ground */
     double cte, mu_s, mu_d;
     double amp, phase;     /* actuation amplitude (K) and phase (rad) */
+    int chan;              /* actuation channel, or -1 (own / global signal) */
     /* Position D of the paper's state, held as the rest position of the
      * cell plus a displacement U so that bond stretches never subtract two
      * large absolute coordinates (lattice offsets are exact integers times l). */
@@ -170,6 +171,8 @@ struct vxo_sim {
     int cand_cap;
     int rebuild_every_step;
     int overflow;
+    int n_chan;
+    vxo_channel chan[VXO_MAX_CHANNELS];
     char err[256];
 };
 
@@ -257,6 +260,7 @@ vxo_sim *vxo_create(const uint8_t *grid, int nx, int ny, int nz,
                 V->kphi = mt->E * l * l * l / 6.0;
                 V->cte = mt->cte; V->mu_s = mt->mu_s; V->mu_d = mt->mu_d;
                 V->amp = prm->temp_amp; V->phase = prm->temp_phase;
+                V->chan = -1;
                 V->D0 = v3(prm->origin[0] + (x + 0.5) * l, prm->origin[1] + (y + 0.5) * l,
                            prm->origin[2] + (z + 0.5) * l);
                 V->U = v3(0.0, 0.0, 0.0);
@@ -350,6 +354,51 @@ int vxo_set_actuation(vxo_sim *s, const double *amp, const double *phase) {
     return 0;
 }
 
+/* Named actuation channels (Volumetric Actuation: several independent
+ * "temperatures", each driving only some materials).  READING: a channel
+ * is a periodic signal of its own amplitude, frequency, phase, offset and
+ * waveform; a voxel follows the channel its cell names, else the channel
+ * its material names, else its own or the global signal. */
+int vxo_set_channels(vxo_sim *s, const vxo_channel *ch, int n_ch, const int *mat_channel, int n_mat,
+                     const int *cell_channel) {
+    if (n_ch < 0 || n_ch > VXO_MAX_CHANNELS) return -1;
+    for (int k = 0; k < n_ch; k++)
+        if (ch[k].waveform < VXO_WAVE_SINE || ch[k].waveform > VXO_WAVE_SQUARE) return -1;
+    s->n_chan = n_ch;
+    for (int k = 0; k < n_ch; k++) s->chan[k] = ch[k];
+    for (int v = 0; v < s->nvox; v++) {
+        voxel *V = &s->vox[v];
+        int k = -1;
+        if (cell_channel && cell_channel[V->cell] >= 0) k = cell_channel[V->cell];
+        else if (mat_channel && V->mat < n_mat) k = mat_channel[V->mat];
+        if (k >= n_ch) return -1;
+        V->chan = k < 0 ? -1 : k;
+    }
+    return 0;
+}
+
+/* Value of a channel's temperature signal at time t. */
+double vxo_channel_value(const vxo_channel *c, double t) {
+    double theta = 2.0 * M_PI * c->freq * t + c->phase;
+    double w;
+    if (c->waveform == VXO_WAVE_SINE) {
+        w = sin(theta);
+    } else {
+        /* position in the period, 0 <= x < 1; both waveforms start at 0
+         * (triangle) or +1 (square) and are in phase with the sine */
+        double turns = theta / (2.0 * M_PI);
+        double x = turns - floor(turns);
+        if (c->waveform == VXO_WAVE_TRIANGLE) {
+            if (x < 0.25) w = 4.0 * x;
+            else if (x < 0.75) w = 2.0 - 4.0 * x;
+            else w = 4.0 * x - 4.0;
+        } else {
+            w = x < 0.5 ? 1.0 : -1.0;
+        }
+    }
+    return c->offset + c->amp * w;
+}
+
 int vxo_set_velocity(vxo_sim *s, const double *vel) {
     for (int v = 0; v < s->nvox; v++) {
         voxel *V = &s->vox[v];
@@ -414,7 +463,9 @@ long long vxo_rebuilds(const vxo_sim *s) { return s->rebuilds; }
  * A sin(2 pi f t + phase); a global signal is the special case of equal A
  * and phase everywhere. */
 static double voxel_strain(const vxo_sim *s, const voxel *V, double t) {
-    double dT = V->amp * sin(2.0 * M_PI * s->p.temp_freq * t + V->phase);
+    double dT;
+    if (V->chan >= 0) dT = vxo_channel_value(&s->chan[V->chan], t);
+    else dT = V->amp * sin(2.0 * M_PI * s->p.temp_freq * t + V->phase);
     return V->cte * dT;
 }
 
@@ -652,7 +703,9 @@ int vxo_step(vxo_sim *s, long long n) {
         /* largest contact size the actuation can produce */
         double cmax = s->l;
         for (int v = 0; v < s->nvox; v++) {
-            double sz = s->l * (1.0 + fabs(s->vox[v].cte * s->vox[v].amp));
+            const voxel *V = &s->vox[v];
+            double a = V->chan >= 0 ? fabs(s->chan[V->chan].offset) + fabs(s->chan[V->chan].amp) : fabs(V->amp);
+            double sz = s->l * (1.0 + fabs(V->cte) * a);
             if (sz > cmax) cmax = sz;
         }
         s->cmax = cmax;

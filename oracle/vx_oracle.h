@@ -39,6 +39,18 @@ typedef struct {
     int32_t pad;
 } vxo_params;
 
+/* Named actuation channel: temperature offset + amp * waveform(theta),
+ * theta = 2 pi freq t + phase. */
+#define VXO_MAX_CHANNELS 8
+#define VXO_WAVE_SINE 0
+#define VXO_WAVE_TRIANGLE 1
+#define VXO_WAVE_SQUARE 2
+typedef struct {
+    double amp, freq, phase, offset;
+    int32_t waveform;
+    int32_t pad;
+} vxo_channel;
+
 typedef struct vxo_sim vxo_sim;
 
 vxo_sim *vxo_create(const uint8_t *grid, int nx, int ny, int nz,
@@ -48,6 +60,9 @@ int vxo_set_fixed(vxo_sim *s, const uint8_t *mask);
 int vxo_set_forces(vxo_sim *s, const double *F);
 int vxo_set_actuation(vxo_sim *s, const double *amp, const double *phase);
 int vxo_set_velocity(vxo_sim *s, const double *vel);
+int vxo_set_channels(vxo_sim *s, const vxo_channel *ch, int n_ch, const int *mat_channel, int n_mat,
+                     const int *cell_channel);
+double vxo_channel_value(const vxo_channel *c, double t);
 int vxo_step(vxo_sim *s, long long n);
 void vxo_read_state(const vxo_sim *s, double *u, double *q, double *vel, double *omega);
 void vxo_write_state(vxo_sim *s, const double *u, const double *q, const double *vel,

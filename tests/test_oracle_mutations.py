@@ -54,6 +54,11 @@ MUTATIONS = {
     "half of the floor spring energy": ("uf += 0.5 * V->kv * pen * pen;", "uf += V->kv * pen * pen;"),
     "gravitational energy at the rest height":
         ("ug += V->m * s->p.gravity * position(V).z;", "ug += V->m * s->p.gravity * V->D0.z;"),
+    "rising slope of the triangle channel": ("if (x < 0.25) w = 4.0 * x;", "if (x < 0.25) w = 2.0 * x;"),
+    "square channel switching a quarter period in": ("w = x < 0.5 ? 1.0 : -1.0;", "w = x < 0.25 ? 1.0 : -1.0;"),
+    "channel offset dropped": ("return c->offset + c->amp * w;", "return c->amp * w;"),
+    "channel frequency taken as an angular frequency":
+        ("double theta = 2.0 * M_PI * c->freq * t + c->phase;", "double theta = c->freq * t + c->phase;"),
 }
 
 

@@ -998,3 +998,140 @@ def test_shadow_energy_with_gravity_and_floor():
     st = s.read_state()
     assert np.abs(st["u"][:, :2]).max() == 0.0 and np.abs(st["w"]).max() == 0.0
     assert max(osc) > 1e-17
+
+
+# --------------------------------------------------------------------------
+# Named actuation channels (Volumetric Actuation: several independent
+# "temperatures", each driving only some materials)
+# --------------------------------------------------------------------------
+def test_channel_waveforms_at_known_phases():
+    """Values fixed by each waveform's definition: a sine peaks a quarter
+    period in; a triangle in phase with it is linear between its zero
+    crossings and its peaks (half the peak an eighth of a period in); a
+    square wave is +1 for the first half period and -1 for the second; a
+    phase of pi/2 moves the sine's peak to t = 0; every signal repeats
+    after one period and is shifted by its offset."""
+    f, A, O = 40.0, 3.0, 0.5
+    T = 1.0 / f
+    sine = {"amp": A, "freq": f, "phase": 0.0, "offset": O, "waveform": "sine"}
+    tri = dict(sine, waveform="triangle")
+    sq = dict(sine, waveform="square")
+    cv = oracle.channel_value
+    assert abs(cv(sine, T / 4) - (O + A)) < 1e-12
+    assert abs(cv(sine, 3 * T / 4) - (O - A)) < 1e-12
+    assert abs(cv(dict(sine, phase=math.pi / 2), 0.0) - (O + A)) < 1e-12
+    assert abs(cv(sine, T / 8) - (O + A * math.sqrt(0.5))) < 1e-12
+    assert abs(cv(tri, T / 8) - (O + A / 2)) < 1e-12
+    assert abs(cv(tri, T / 4) - (O + A)) < 1e-12
+    assert abs(cv(tri, 3 * T / 8) - (O + A / 2)) < 1e-12
+    assert abs(cv(tri, 5 * T / 8) - (O - A / 2)) < 1e-12
+    assert abs(cv(tri, 7 * T / 8) - (O - A / 2)) < 1e-12
+    assert abs(cv(sq, 0.3 * T) - (O + A)) < 1e-12
+    assert abs(cv(sq, 0.7 * T) - (O - A)) < 1e-12
+    assert abs(cv(dict(sq, phase=math.pi), 0.3 * T) - (O - A)) < 1e-12
+    for c in (sine, tri, sq):
+        for t in (0.1 * T, 0.37 * T, 0.81 * T):
+            assert abs(cv(c, t + 3 * T) - cv(c, t)) < 1e-9
+
+
+def _channel_bars(channels, mat_channel, steps_list, zeta_bond=0.5):
+    """Two free 3-voxel bars along x, of materials 1 and 2 (CTE 0.01 and
+    0.02), four empty cells apart; returns the spacings of each bar's two
+    bonds after each step count in steps_list, and the times."""
+    g = np.zeros((1, 1, 10), np.uint8)
+    g[0, 0, 0:3] = 1
+    g[0, 0, 7:10] = 2
+    mats = [EMPTY, mat(cte=0.01), mat(cte=0.02)]
+    s = oracle.Sim(g, mats, voxel_size=L_VOX, zeta_bond=zeta_bond)
+    s.set_channels(channels, mat_channel=mat_channel)
+    out, done = [], 0
+    for n in steps_list:
+        assert s.step(n - done) == 0
+        done = n
+        u = s.read_state()["u"][:, 0]
+        out.append((L_VOX + np.diff(u[0:3]), L_VOX + np.diff(u[7:10]), s.time))
+    return out
+
+
+def test_channel_square_wave_sets_the_free_bar_length():
+    """A free bar in a square-wave channel relaxes to zero stress at spacing
+    l (1 + alpha (offset +- amp)) while the signal holds each level; the bar
+    of the material no channel drives stays at its rest length."""
+    f, A, O = 5.0, 4.0, 1.0
+    ch = [{"amp": A, "freq": f, "phase": 0.0, "offset": O, "waveform": "square"}]
+    s0 = oracle.Sim(np.ones((1, 1, 2), np.uint8), [EMPTY, mat()], voxel_size=L_VOX)
+    n1, n2 = int(0.4 / f / s0.dt), int(0.9 / f / s0.dt)
+    (b1, r1, t1), (b2, r2, t2) = _channel_bars(ch, [-1, 0, -1], [n1, n2])
+    assert 0.35 < t1 * f < 0.45 and 0.85 < t2 * f < 0.95
+    assert np.allclose(b1, L_VOX * (1 + 0.01 * (O + A)), rtol=1e-10, atol=0)
+    assert np.allclose(b2, L_VOX * (1 + 0.01 * (O - A)), rtol=1e-10, atol=0)
+    assert np.array_equal(r1, np.full(2, L_VOX)) and np.array_equal(r2, np.full(2, L_VOX))
+
+
+def test_channel_waveform_drives_the_bar_quasistatically():
+    """Two channels at different frequencies, one per bar: a 2 Hz triangle
+    on material 1 and a 1 Hz sine on material 2.  Both signals are slow
+    against the bars' relaxation, so each bar tracks its own channel: an
+    eighth of a 2 Hz period in, the first bar's strain is alpha (O + A/2)
+    (the triangle's half peak) while the second's is alpha A sin(pi/8)
+    (a sixteenth of its own period), to the lag of the relaxation."""
+    c_tri = {"amp": 5.0, "freq": 2.0, "phase": 0.0, "offset": 0.5, "waveform": "triangle"}
+    c_sin = {"amp": 3.0, "freq": 1.0, "phase": 0.0, "offset": 0.0, "waveform": "sine"}
+    s0 = oracle.Sim(np.ones((1, 1, 2), np.uint8), [EMPTY, mat()], voxel_size=L_VOX)
+    n = int(round(1.0 / (8 * 2.0) / s0.dt))
+    ((b, r, t),) = _channel_bars([c_tri, c_sin], [-1, 0, 1], [n], zeta_bond=0.9)
+    eps1 = b / L_VOX - 1.0
+    eps2 = r / L_VOX - 1.0
+    want1 = 0.01 * (0.5 + 5.0 * 4 * 2.0 * t)          # the triangle's rising ramp at t
+    want2 = 0.02 * 3.0 * math.sin(2 * math.pi * 1.0 * t)
+    assert abs(t * 16 - 1.0) < 1e-3
+    assert np.abs(eps1 - want1).max() < 2e-3 * 0.01 * 5.0, (eps1, want1)
+    assert np.abs(eps2 - want2).max() < 2e-3 * 0.02 * 3.0, (eps2, want2)
+
+
+def test_sine_channel_equals_the_voxels_own_signal():
+    """A sine channel at the global frequency with no offset is the
+    per-voxel signal A sin(2 pi f t + phase) of the same voxels: the
+    trajectories are identical."""
+    mats = workloads.random_materials(3, seed=31, cte_max=0.01)
+    g = workloads.random_grid((4, 5, 6), 3, 0.9, 32)
+    params = dict(voxel_size=L_VOX, zeta_bond=0.3, temp_freq=300.0, temp_amp=0.0)
+    a = oracle.Sim(g, mats, **params)
+    b = oracle.Sim(g, mats, **params)
+    gr = g.reshape(-1)
+    amp = np.where(gr == 2, 12.0, 0.0)
+    ph = np.where(gr == 2, 0.9, 0.0)
+    a.set_actuation(amp, ph)
+    b.set_channels([{"amp": 12.0, "freq": 300.0, "phase": 0.9, "offset": 0.0, "waveform": "sine"}],
+                   mat_channel=[-1, -1, 0, -1])
+    assert a.step(400) == 0 and b.step(400) == 0
+    sa, sb = a.read_state(), b.read_state()
+    for k in ("u", "q", "v", "w"):
+        assert np.array_equal(sa[k], sb[k]), k
+    assert np.abs(sa["u"]).max() > 0
+
+
+def test_cell_channel_overrides_material_channel():
+    """A voxel follows the channel its cell names before its material's: a
+    material map and the equivalent per-cell map give identical runs."""
+    mats = workloads.random_materials(3, seed=33, cte_max=0.01)
+    g = workloads.random_grid((4, 4, 7), 3, 0.9, 34)
+    ch = [{"amp": 10.0, "freq": 250.0, "phase": 0.3, "offset": 1.0, "waveform": "triangle"},
+          {"amp": 6.0, "freq": 410.0, "phase": 2.0, "offset": 0.0, "waveform": "sine"}]
+    gr = g.reshape(-1)
+    params = dict(voxel_size=L_VOX, zeta_bond=0.3)
+    a = oracle.Sim(g, mats, **params)
+    a.set_channels(ch, mat_channel=[-1, 0, 1, -1])
+    b = oracle.Sim(g, mats, **params)
+    cell = np.where(gr == 1, 0, np.where(gr == 2, 1, -1)).astype(np.int32)
+    b.set_channels(ch, mat_channel=[-1, 1, 0, 0], cell_channel=np.where(gr == 3, -1, cell))
+    # material 3 is mapped to channel 0 in b but its cells name no channel,
+    # so they follow channel 0 there and nothing in a: make them agree
+    b2 = oracle.Sim(g, mats, **params)
+    b2.set_channels(ch, mat_channel=[-1, 1, 0, -1], cell_channel=cell)
+    assert a.step(300) == 0 and b2.step(300) == 0
+    sa, sb = a.read_state(), b2.read_state()
+    for k in ("u", "q", "v", "w"):
+        assert np.array_equal(sa[k], sb[k]), k
+    assert b.step(300) == 0
+    assert not np.array_equal(b.read_state()["u"], sa["u"])
