@@ -127,6 +127,37 @@ int vx_forced_region(vx_handle h, const double loc[3], const double size[3],
  * amp * sin(2 pi temp_freq t + phase) (Volumetric Actuation). */
 int vx_set_actuation(vx_handle h, const double *amp, const double *phase);
 
+/* Named actuation channels (Volumetric Actuation: several independent
+ * "temperatures", each driving only some materials).  Channel k's
+ * temperature at time t is offset + amp * w(2 pi freq t + phase), w the
+ * waveform: VX_WAVE_SINE sin; VX_WAVE_TRIANGLE the triangle wave in phase
+ * with the sine (0 at phase 0, peak +1 a quarter period in, -1 three
+ * quarters in, linear between); VX_WAVE_SQUARE +1 for the first half period
+ * and -1 for the second.  A voxel's strain is its material's CTE times the
+ * temperature of the channel it follows. */
+#define VX_MAX_CHANNELS 8
+#define VX_WAVE_SINE 0
+#define VX_WAVE_TRIANGLE 1
+#define VX_WAVE_SQUARE 2
+typedef struct vx_channel {
+    double amp;        /* K */
+    double freq;       /* Hz */
+    double phase;      /* rad */
+    double offset;     /* K, added to the waveform */
+    int32_t waveform;  /* VX_WAVE_* */
+    int32_t reserved;  /* must be 0 */
+} vx_channel;
+
+/* Set n_ch (0..VX_MAX_CHANNELS) channels, replacing earlier ones.  A filled
+ * cell follows channel cell_channel[c] when that is >= 0 (cell_channel:
+ * ncell entries, or NULL), else channel mat_channel[m] of its material m
+ * when that is >= 0 (mat_channel: n_mat entries indexed by material, or
+ * NULL), else its own signal of vx_set_actuation, else the global signal
+ * of vx_params.  Errors: VX_EINVAL for n_ch out of range, an unknown
+ * waveform, a non-finite field or a channel index >= n_ch. */
+int vx_set_channels(vx_handle h, const vx_channel *channels, int32_t n_ch, const int32_t *mat_channel,
+                    const int32_t *cell_channel);
+
 /* Initial velocity per cell, dense ncell x 3 (m/s); sets P = m v. */
 int vx_set_velocity(vx_handle h, const double *velocity);
 
@@ -355,7 +386,8 @@ int vx_grad_forward(vx_handle h, int64_t n);
  *            damping's dependence on the lighter mass is assigned to the
  *            voxel the forward takes it from (voxel 2 of the bond);
  *   g_phase  dL/dphase, g_amp dL/damp of vx_set_actuation's per-voxel
- *            signal (zero when the voxel follows the global signal);
+ *            signal (zero when the voxel follows the global signal or a
+ *            channel; see vx_grad_channels);
  *   g_u0, g_q0, g_v0, g_w0  adjoint of the rollout's initial state.
  * The adjoint state is kept in the state's precision; the parameter
  * gradients are accumulated in FP64. */
@@ -363,13 +395,23 @@ int vx_grad_backward(vx_handle h, const double *dL_du, const double *dL_dq, cons
                      const double *dL_dw, double *g_E, double *g_rho, double *g_phase, double *g_amp,
                      double *g_u0, double *g_q0, double *g_v0, double *g_w0);
 
+/* Gradients of the last vx_grad_backward's loss with respect to each
+ * actuation channel's phase (rad) and amplitude (K): g_phase[k], g_amp[k]
+ * for the n_ch channels of vx_set_channels (host arrays, NULL = not
+ * wanted).  They are the sums over the channel's voxels, in FP64 and cell
+ * order, of the per-voxel terms the reverse run accumulated (those voxels
+ * read zero in vx_grad_backward's per-voxel g_phase and g_amp).  Errors:
+ * VX_ESTATE before a vx_grad_backward. */
+int vx_grad_channels(vx_handle h, double *g_phase, double *g_amp);
+
 /* ------------------------------------------------------------------ */
 /* Batches: many independent objects stepped by one persistent launch  */
 /* ------------------------------------------------------------------ */
 
 /* One object of a batch: its own material grid (cell order as vx_create)
- * and the world position of its cell (0,0,0)'s lower corner (only z is
- * used, for the floor). */
+ * and the world position of its cell (0,0,0)'s lower corner (z places it
+ * above the floor; all three place it in the world shared by a batch with
+ * contact). */
 typedef struct vx_object {
     const uint8_t *grid;
     int32_t nx, ny, nz;
@@ -380,11 +422,20 @@ typedef struct vx_object {
 typedef struct vx_batch_sim *vx_batch;
 
 /* Create a batch of n_obj objects sharing one palette (at most 16
- * materials) and one parameter set (self-collision must be off: objects do
- * not interact).  Each object gets its own stable timestep (Eq. 31-32 over
- * its own bonds) and its own time.  The grids are copied.  Errors:
- * VX_EINVAL as vx_create, or if one state array (13 words per cell of all
- * objects) would span 2 GiB or more. */
+ * materials) and one parameter set.  The grids are copied.
+ * self_collision_on = 0: the objects are independent; each gets its own
+ * stable timestep (Eq. 31-32 over its own bonds) and its own time, and
+ * vx_batch_step runs max_steps_per_launch steps per persistent launch.
+ * self_collision_on = 1: the objects share one world, placed by their
+ * origins, and touch one another ("multiple bodies to interact",
+ * Introduction; Self collision detection and handling): the surface voxels
+ * of all objects form one candidate search (horizon 2 l, pairs of one
+ * object within lattice Manhattan distance 3 excluded, lazy rebuild), every
+ * voxel gathers its contact force from its own candidate list (no
+ * atomics), and all objects step with the smallest of their stable
+ * timesteps, one launch per step.  Errors: VX_EINVAL as vx_create, or if
+ * one state array (13 words per cell of all objects) would span 2 GiB or
+ * more. */
 int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *palette, int32_t n_mat,
                     const vx_params *params, int32_t precision, void *stream, vx_batch *out);
 int vx_batch_workspace_bytes(vx_batch b, uint64_t *bytes);
@@ -394,8 +445,10 @@ int vx_batch_bind_workspace(vx_batch b, void *device_ptr, uint64_t bytes);
 
 /* Advance every object n steps: one persistent kernel launch per
  * max_steps_per_launch steps (default 2000), each workgroup looping all
- * steps over its own objects.  Errors: VX_ESTATE before bind, VX_EUNSTABLE
- * on a non-finite state. */
+ * steps over its own objects (with contact: the collision chain, the
+ * contact forces and one launch per step).  Errors: VX_ESTATE before bind,
+ * VX_EUNSTABLE on a non-finite state, VX_EOVERFLOW if a candidate list
+ * overflowed. */
 int vx_batch_step(vx_batch b, int64_t n);
 
 /* Read / overwrite one object's state; layouts as vx_read_state over the
@@ -406,6 +459,17 @@ int vx_batch_write_state(vx_batch b, int32_t obj, const double *u, const double 
 int vx_batch_get_dt(vx_batch b, int32_t obj, double *dt);
 /* out[0] steps, out[1] objects, out[2] cells, out[3] filled voxels. */
 int vx_batch_counters(vx_batch b, int64_t out[4]);
+
+/* Contact between objects (self_collision_on = 1): the current candidate
+ * pairs as (object, cell within the object) twice, each pair once, in
+ * object-major order of the first voxel; writes at most max_pairs and
+ * returns the total in *n_pairs (0 without contact). */
+int vx_batch_candidates(vx_batch b, int32_t *obj_a, int32_t *cell_a, int32_t *obj_b, int32_t *cell_b,
+                        int32_t max_pairs, int32_t *n_pairs);
+/* out[0] candidate-list rebuilds, out[1] candidate entries (each pair
+ * counted from both sides), out[2] surface voxels taking part; zeros
+ * without contact. */
+int vx_batch_contact_counters(vx_batch b, int64_t out[3]);
 
 /* Workgroups of the persistent launch (0: a default of 4 per compute unit,
  * at most one per object) and steps per launch (0: keep).  Objects are

@@ -33,11 +33,12 @@ EXPORTED = ["vx_create", "vx_workspace_bytes", "vx_bind_workspace", "vx_set_fixe
             "vx_counters", "vx_candidates", "vx_set_kernel", "vx_set_fused_tile", "vx_get_fused_tile",
             "vx_autotune", "vx_time_kernel", "vx_destroy", "vx_last_error",
             "vx_step_enqueue", "vx_status", "vx_probe", "vx_set_collision_mode", "vx_static_workspace_bytes",
-            "vx_static_solve", "vx_static_solve_noalloc", "vx_energy", "vx_set_stiffness", "vx_set_density", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
+            "vx_static_solve", "vx_static_solve_noalloc", "vx_energy", "vx_set_channels", "vx_grad_channels", "vx_set_stiffness", "vx_set_density", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
             "vx_grad_backward",
             "vx_batch_create", "vx_batch_workspace_bytes", "vx_batch_bind_workspace", "vx_batch_step",
             "vx_batch_read_state", "vx_batch_write_state", "vx_batch_get_dt", "vx_batch_counters",
-            "vx_batch_set_launch", "vx_batch_autotune", "vx_batch_destroy", "vx_batch_last_error"]
+            "vx_batch_set_launch", "vx_batch_autotune", "vx_batch_destroy", "vx_batch_last_error",
+            "vx_batch_candidates", "vx_batch_contact_counters"]
 
 # state words, in the order vx_probe numbers them
 WORDS = ["ux", "uy", "uz", "qw", "qx", "qy", "qz", "px", "py", "pz", "lx", "ly", "lz"]
@@ -53,6 +54,15 @@ class VoxsimError(RuntimeError):
 class Material(C.Structure):
     _fields_ = [("E", C.c_double), ("nu", C.c_double), ("rho", C.c_double),
                 ("cte", C.c_double), ("mu_s", C.c_double), ("mu_d", C.c_double)]
+
+
+WAVEFORMS = {"sine": 0, "triangle": 1, "square": 2}
+MAX_CHANNELS = 8
+
+
+class Channel(C.Structure):
+    _fields_ = [("amp", C.c_double), ("freq", C.c_double), ("phase", C.c_double), ("offset", C.c_double),
+                ("waveform", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Object(C.Structure):
@@ -122,6 +132,8 @@ def lib():
     L.vx_static_solve.argtypes = [P, P, C.c_uint64, P, C.c_double, i32, P, P, C.POINTER(i32),
                                   C.POINTER(C.c_double)]
     L.vx_static_solve_noalloc.argtypes = [P, P, C.c_double, i32, P, P, C.POINTER(i32), C.POINTER(C.c_double)]
+    L.vx_set_channels.argtypes = [P, P, i32, P, P]
+    L.vx_grad_channels.argtypes = [P, P, P]
     L.vx_set_stiffness.argtypes = [P, P]
     L.vx_set_density.argtypes = [P, P]
     L.vx_grad_workspace_bytes.argtypes = [P, i64, i32, C.POINTER(u64)]
@@ -141,6 +153,8 @@ def lib():
     L.vx_batch_counters.argtypes = [P, C.POINTER(C.c_int64)]
     L.vx_batch_set_launch.argtypes = [P, i32, i32]
     L.vx_batch_autotune.argtypes = [P, i32, pi32]
+    L.vx_batch_candidates.argtypes = [P, P, P, P, P, i32, pi32]
+    L.vx_batch_contact_counters.argtypes = [P, C.POINTER(C.c_int64)]
     L.vx_batch_destroy.argtypes = [P]
     L.vx_batch_last_error.argtypes = [P]
     L.vx_batch_last_error.restype = C.c_char_p
@@ -203,6 +217,7 @@ class Sim:
         self.grid = g
         self.precision = int(precision)
         self._pal = make_palette(materials)
+        self.n_mat = len(materials)
         self._prm = make_params(**params)
         self._device = device
         self._stream = stream
@@ -344,6 +359,38 @@ class Sim:
                                                   C.byref(it), C.byref(res)))
         return {"u": u, "theta": th, "iters": it.value, "rel_residual": res.value}
 
+    def set_channels(self, channels, mat_channel=None, cell_channel=None):
+        """Named actuation channels (see vx_set_channels): a list of dicts
+        {amp, freq, phase, offset, waveform ('sine' | 'triangle' |
+        'square')}; mat_channel gives each palette entry's channel (-1:
+        none), cell_channel each cell's (-1: its material's)."""
+        n = len(channels)
+        arr = (Channel * max(n, 1))()
+        for i, c in enumerate(channels):
+            arr[i].amp = float(c.get("amp", 0.0))
+            arr[i].freq = float(c.get("freq", 0.0))
+            arr[i].phase = float(c.get("phase", 0.0))
+            arr[i].offset = float(c.get("offset", 0.0))
+            wf = c.get("waveform", "sine")
+            arr[i].waveform = WAVEFORMS[wf] if isinstance(wf, str) else int(wf)
+            arr[i].reserved = 0
+        mc = None
+        if mat_channel is not None:
+            mc = np.ascontiguousarray(mat_channel, dtype=np.int32)
+            assert mc.size == self.n_mat
+        cc = None if cell_channel is None else np.ascontiguousarray(cell_channel, dtype=np.int32).reshape(-1)
+        if cc is not None:
+            assert cc.size == self.ncell
+        self._check(lib().vx_set_channels(self.h, C.cast(arr, C.c_void_p), n, _ptr(mc), _ptr(cc)))
+        self._n_chan = n
+
+    def grad_channels(self):
+        """Per-channel dL/dphase and dL/damp of the last grad_backward."""
+        n = getattr(self, "_n_chan", 0)
+        gp = np.zeros(max(n, 1)); ga = np.zeros(max(n, 1))
+        self._check(lib().vx_grad_channels(self.h, _ptr(gp), _ptr(ga)))
+        return {"phase": gp[:n], "amp": ga[:n]}
+
     def set_collision_mode(self, all_voxels=False, every_step=False):
         """Self-collision scheme (see vx_set_collision_mode): candidates from
         all filled voxels or the surface only; rebuilt every step or by the
@@ -465,33 +512,40 @@ def _rollout_fn():
     class RolloutFn(torch.autograd.Function):
         """Final displacement and velocity (ncell x 3 each, float64, CPU) of an
         n-step rollout from the Sim's current state, differentiable w.r.t. the
-        per-voxel modulus E, density rho and actuation phase (ncell each).
-        The actuation amplitude is held fixed at amp."""
+        per-voxel modulus E, density rho, actuation phase and actuation
+        amplitude amp (ncell each, on any device).  Gradients come back on
+        each input's device and in its dtype."""
 
         @staticmethod
-        def forward(ctx, E, rho, phase, sim, amp, n):
+        def forward(ctx, E, rho, phase, amp, sim, n):
             sim.set_stiffness(E.detach().cpu().numpy())
             sim.set_density(rho.detach().cpu().numpy())
-            sim.set_actuation(amp, phase.detach().cpu().numpy())
+            sim.set_actuation(amp.detach().cpu().numpy(), phase.detach().cpu().numpy())
             sim.grad_forward(n)
             st = sim.read_state()
             ctx.sim = sim
+            ctx.like = [(t.device, t.dtype) for t in (E, rho, phase, amp)]
             return torch.from_numpy(st["u"]), torch.from_numpy(st["v"])
 
         @staticmethod
         def backward(ctx, gu, gv):
-            g = ctx.sim.grad_backward(dL_du=gu.cpu().numpy(), dL_dv=gv.cpu().numpy())
-            return (torch.from_numpy(g["E"]), torch.from_numpy(g["rho"]), torch.from_numpy(g["phase"]), None,
-                    None, None)
+            g = ctx.sim.grad_backward(dL_du=gu.detach().cpu().numpy(), dL_dv=gv.detach().cpu().numpy())
+            out = [torch.from_numpy(g[k]).to(device=d, dtype=t)
+                   for k, (d, t) in zip(("E", "rho", "phase", "amp"), ctx.like)]
+            return tuple(out) + (None, None)
 
     return RolloutFn
 
 
 def rollout(sim, E, rho, phase, amp, n):
     """(u, v) after n steps from sim's current state; differentiable in E,
-    rho and phase through the library's reverse run (sim needs grad_bind
-    first)."""
-    return _rollout_fn().apply(E, rho, phase, sim, amp, n)
+    rho, phase and amp (torch tensors of ncell values; amp may also be an
+    array, then held fixed) through the library's reverse run (sim needs
+    grad_bind first)."""
+    import torch
+    if not isinstance(amp, torch.Tensor):
+        amp = torch.as_tensor(np.asarray(amp, dtype=np.float64))
+    return _rollout_fn().apply(E, rho, phase, amp, sim, n)
 
 
 def from_workload(w, precision=64, kernel=KERNEL_FUSED, stream=None):
@@ -582,6 +636,21 @@ class Batch:
         out = (C.c_int64 * 4)()
         self._check(lib().vx_batch_counters(self.h, out))
         return {"steps": out[0], "objects": out[1], "cells": out[2], "voxels": out[3]}
+
+    def candidates(self):
+        """Contact candidate pairs ((obj_a, cell_a), (obj_b, cell_b)), each
+        pair once (see vx_batch_candidates)."""
+        n = C.c_int32()
+        self._check(lib().vx_batch_candidates(self.h, None, None, None, None, 0, C.byref(n)))
+        k = n.value
+        oa, ca, ob, cb = (np.zeros(max(k, 1), np.int32) for _ in range(4))
+        self._check(lib().vx_batch_candidates(self.h, _ptr(oa), _ptr(ca), _ptr(ob), _ptr(cb), k, C.byref(n)))
+        return [((int(oa[i]), int(ca[i])), (int(ob[i]), int(cb[i]))) for i in range(k)]
+
+    def contact_counters(self):
+        out = (C.c_int64 * 3)()
+        self._check(lib().vx_batch_contact_counters(self.h, out))
+        return {"rebuilds": out[0], "pairs": out[1], "surface": out[2]}
 
     def read_state(self, i):
         self.bind()

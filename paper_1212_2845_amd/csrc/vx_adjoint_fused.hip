@@ -50,7 +50,7 @@ struct AdjSmem {
 // ignored), so that the loads of a slab are in flight together.
 template <typename T>
 struct AdjPre {
-    uint8_t m, fl;
+    uint8_t m, fl, ch;
     T E, rho, amp, phase;
     VoxRaw<T> r;
     T gf[6];
@@ -64,6 +64,7 @@ __device__ __forceinline__ void issue_adj(const StepArgs<T> &a, const AdjArgs<T>
     p.rho = a.rho_cell ? ldc(a.rho_cell, c) : T(0);
     p.amp = ldc(a.act_amp, c);
     p.phase = ldc(a.act_phase, c);
+    p.ch = ldc(a.chan, c);
     p.r = load_raw(a.s_in, a.stride, c);
 #pragma unroll
     for (int i = 0; i < 6; ++i) p.gf[i] = ldc(g.gfm + i * a.stride, c);
@@ -72,9 +73,12 @@ __device__ __forceinline__ void issue_adj(const StepArgs<T> &a, const AdjArgs<T>
 // Strain of a cell from its prefetched signal: the same expression as
 // voxel_strain.
 template <typename T>
-__device__ __forceinline__ T strain_of(const StepArgs<T> &a, uint8_t fl, T cte, T amp, T phase) {
+__device__ __forceinline__ T strain_of(const StepArgs<T> &a, const T *chan_dT, uint8_t fl, T cte, T amp, T phase,
+                                       int ch) {
     T dT = a.dT_global;
-    if (fl & FLAG_ACT) {
+    if (fl & FLAG_CHAN) {
+        dT = chan_dT[ch];
+    } else if (fl & FLAG_ACT) {
         if constexpr (sizeof(T) == 8) {
             dT = amp * dsin<T>(a.wt + phase);
         } else {
@@ -85,11 +89,12 @@ __device__ __forceinline__ T strain_of(const StepArgs<T> &a, uint8_t fl, T cte, 
 }
 
 template <typename T>
-__device__ __forceinline__ void finish_adj(const StepArgs<T> &a, const AdjPre<T> &p, AdjCell<T> &o) {
+__device__ __forceinline__ void finish_adj(const StepArgs<T> &a, const T *chan_dT, const AdjPre<T> &p,
+                                           AdjCell<T> &o) {
     o.m = p.m;
     if (!p.m) return;
     const MatConst<T> mc = a.E_cell ? mat_with(a.mats[p.m], p.E, p.rho, a.l, a.zeta_slow, a.zeta_col) : a.mats[p.m];
-    const T eps = strain_of(a, p.fl, mc.cte, p.amp, p.phase);
+    const T eps = strain_of(a, chan_dT, p.fl, mc.cte, p.amp, p.phase, p.ch);
     o.k = kin_of(p.r, mc, eps);
     o.E = mc.E; o.mass = mc.m; o.gfac = mc.gfac;
 #pragma unroll
@@ -97,10 +102,11 @@ __device__ __forceinline__ void finish_adj(const StepArgs<T> &a, const AdjPre<T>
 }
 
 template <typename T>
-__device__ __forceinline__ void load_cell(const StepArgs<T> &a, const AdjArgs<T> &g, unsigned c, AdjCell<T> &o) {
+__device__ __forceinline__ void load_cell(const StepArgs<T> &a, const AdjArgs<T> &g, const T *chan_dT, unsigned c,
+                                          AdjCell<T> &o) {
     AdjPre<T> p;
     issue_adj(a, g, c, p);
-    finish_adj(a, p, o);
+    finish_adj(a, chan_dT, p, o);
 }
 
 template <typename T, typename S>
@@ -150,7 +156,8 @@ __device__ __forceinline__ void bond_ends(const AdjCell<T> &A, const AdjCell<T> 
 // Adjoint of x_n of cell c from its direct part (k_adj_update) and the sum k
 // of its bond ends; FP64 accumulation of the parameter gradients.
 template <typename T>
-__device__ __forceinline__ void finish_voxel(const StepArgs<T> &a, const AdjArgs<T> &g, unsigned c, uint8_t m,
+__device__ __forceinline__ void finish_voxel(const StepArgs<T> &a, const AdjArgs<T> &g, const T (*chan)[kMaxChan],
+                                             unsigned c, uint8_t m,
                                              const T k[kEnd]) {
     const long long st = a.stride;
     const MatConst<T> mc = mat_at(a, (long long)c, m);
@@ -170,10 +177,10 @@ __device__ __forceinline__ void finish_voxel(const StepArgs<T> &a, const AdjArgs
     g.g_E[c] += (double)gE;
     g.g_rho[c] += (double)gm * ((double)a.l * (double)a.l * (double)a.l);
     const uint8_t fl = ldc(a.flags, c);
-    if (fl & FLAG_ACT) {
+    if (fl & (FLAG_ACT | FLAG_CHAN)) {
         const T geps = ldc(g.gloc, c) + k[13];
         T dph, dam;
-        voxel_strain_d(a, c, mc.cte, &dph, &dam);
+        voxel_strain_d(a, chan[1], chan[2], c, fl, mc.cte, &dph, &dam);
         g.g_phase[c] += (double)(geps * dph);
         g.g_amp[c] += (double)(geps * dam);
     }
@@ -188,6 +195,15 @@ __global__ void __launch_bounds__(TX *TY) k_adj_fused(StepArgs<T> a, AdjArgs<T> 
     static_assert(2 * (TX + TY) <= TX * TY, "ring must fit one cell per thread");
     constexpr int RW = TX + 2, NR = (TX + 2) * (TY + 2), NBX = (TX + 1) * TY, NBY = TX * (TY + 1);
     __shared__ AdjSmem<T, NR, NBX, NBY> sm;
+    // the channels' temperatures and their derivatives at t_n, staged once
+    // (the step arguments' copies are not kept in registers)
+    __shared__ T s_chan[3][kMaxChan];
+    if ((int)threadIdx.x < kMaxChan) {
+        s_chan[0][threadIdx.x] = chan_pick(a.chan_dT, (int)threadIdx.x);
+        s_chan[1][threadIdx.x] = chan_pick(g.chan_dph, (int)threadIdx.x);
+        s_chan[2][threadIdx.x] = chan_pick(g.chan_dam, (int)threadIdx.x);
+    }
+    __syncthreads();
     // XCD-aware tile order, as in the forward kernel
     const int nwg = gridDim.x, b = blockIdx.x;
     const int q = nwg / kAdjXcds, rem = nwg % kAdjXcds, xcd = b % kAdjXcds, kk = b / kAdjXcds;
@@ -234,14 +250,14 @@ __global__ void __launch_bounds__(TX *TY) k_adj_fused(StepArgs<T> a, AdjArgs<T> 
         }
         if (ring) {
             AdjCell<T> R{};
-            if (ring_in) finish_adj(a, r, R);
+            if (ring_in) finish_adj(a, s_chan[0], r, R);
             if (R.m) put_cell<T>(sm, ring_slot, R);
             sm.mat[ring_slot] = R.m;
         }
     };
 
     AdjCell<T> A{}, B{};
-    if (inxy && z0 < z1) load_cell(a, g, col + (unsigned)z0 * nxy, A);
+    if (inxy && z0 < z1) load_cell(a, g, s_chan[0], col + (unsigned)z0 * nxy, A);
     AdjPre<T> rp{};
     if (ring_in && z0 < z1) issue_adj(a, g, ring_col + (unsigned)z0 * nxy, rp);
     // voxel-2 end of the bond entering the chunk from below
@@ -251,7 +267,7 @@ __global__ void __launch_bounds__(TX *TY) k_adj_fused(StepArgs<T> a, AdjArgs<T> 
     for (int i = 0; i < kEnd; ++i) cin[i] = T(0);
     if (A.m && z0 > 0) {
         AdjCell<T> P{};
-        load_cell(a, g, col + (unsigned)(z0 - 1) * nxy, P);
+        load_cell(a, g, s_chan[0], col + (unsigned)(z0 - 1) * nxy, P);
         if (P.m) {
             T ea[kEnd];
             bond_ends<T, 2>(P, A, a.zeta_bond, C, ea, cin);
@@ -313,7 +329,7 @@ __global__ void __launch_bounds__(TX *TY) k_adj_fused(StepArgs<T> a, AdjArgs<T> 
         nxt.m = 0;
         if (inxy && z + 1 < a.nz) {
             if constexpr (!early) issue_adj(a, g, col + (unsigned)(z + 1) * nxy, pn);
-            finish_adj(a, pn, nxt);
+            finish_adj(a, s_chan[0], pn, nxt);
         }
         T cout[kEnd];
         const bool has_z = cur.m && nxt.m;
@@ -345,7 +361,7 @@ __global__ void __launch_bounds__(TX *TY) k_adj_fused(StepArgs<T> a, AdjArgs<T> 
 #pragma unroll
                 for (int i = 0; i < kEnd; ++i) acc[i] += cin[i];
             }
-            finish_voxel(a, g, col + (unsigned)z * nxy, cur.m, acc);
+            finish_voxel(a, g, s_chan, col + (unsigned)z * nxy, cur.m, acc);
         }
         has_cin = has_z;
 #pragma unroll

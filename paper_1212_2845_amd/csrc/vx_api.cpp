@@ -34,7 +34,6 @@ static void size_collision_table(vx_sim *h) {
     int ts = 1;
     while (ts < 2 * (int)std::max<size_t>(h->coll_cells.size(), 1)) ts <<= 1;
     h->table_size = ts;
-    h->scan_tmp_bytes = h->p.self_collision_on ? scan_temp_bytes(ts + 1) : 0;
 }
 
 static void compute_layout(vx_sim *h) {
@@ -53,6 +52,7 @@ static void compute_layout(vx_sim *h) {
     L.bonds = take(27 * n * ts);
     L.act_amp = take(n * ts);
     L.act_phase = take(n * ts);
+    L.chan = take(n);
     h->forced_cap = std::max<int>((int)h->forced_cells.size(), 1024);
     L.forced_cells = take((uint64_t)h->forced_cap * 4);
     L.forced_F = take((uint64_t)h->forced_cap * 3 * ts);
@@ -60,19 +60,22 @@ static void compute_layout(vx_sim *h) {
     const uint64_t ns = col ? h->coll_cells.size() : 0;
     L.contact_F = take(col ? 3 * n * ts : 0);
     L.surf_cells = take(ns * 4);
+    L.surf_obj = take(ns * 4);
+    L.surf_ijk = take(ns * 8);
+    L.obj_origin = take(3 * 8);
     L.cand = take(ns * (uint64_t)h->cand_cap * 4);
     L.cand_n = take(ns * 4);
     L.keys = take(ns * 4);
     L.gc = take(ns * 8);
-    L.ijk = take(ns * 8);
     L.sorted = take(ns * 4);
     L.sgc = take(ns * 8);
     L.sijk = take(ns * 8);
+    L.sobj = take(ns * 4);
     L.su = take(3 * ns * ts);
     L.bstart = take(col ? ((uint64_t)h->table_size + 1) * 4 : 0);
     L.bfill = take(col ? (uint64_t)h->table_size * 4 : 0);
+    L.block_sum = take(col ? (uint64_t)scan_blocks(h->table_size) * 4 : 0);
     L.scalars = take(sizeof(Scalars));
-    L.scan_tmp = take(col ? h->scan_tmp_bytes : 0);
     L.E_cell = take(n * ts);
     L.rho_cell = take(n * ts);
     L.energy = take((uint64_t)energy_blocks((long long)n) * kEnergyWords * 8);
@@ -113,6 +116,10 @@ static int upload_static(vx_sim *h) {
         for (long long c = 0; c < h->ncell; ++c) { a[c] = (T)h->amp[c]; ph[c] = (T)h->phase[c]; }
     HIP_OK(h, hipMemcpyAsync(ws + h->L.act_amp, a.data(), h->ncell * sizeof(T), hipMemcpyHostToDevice, s));
     HIP_OK(h, hipMemcpyAsync(ws + h->L.act_phase, ph.data(), h->ncell * sizeof(T), hipMemcpyHostToDevice, s));
+    std::vector<uint8_t> ch(h->ncell, 0);
+    for (long long c = 0; c < h->ncell; ++c)
+        if (h->cell_chan[c] >= 0) ch[c] = (uint8_t)h->cell_chan[c];
+    HIP_OK(h, hipMemcpyAsync(ws + h->L.chan, ch.data(), h->ncell, hipMemcpyHostToDevice, s));
     // parameter mode: per-cell modulus and density, the palette's where not set
     std::vector<T> ec(h->ncell, T(0)), rc(h->ncell, T(0));
     if (h->param_mode())
@@ -168,10 +175,24 @@ static int put_state(vx_sim *h, const std::vector<double> &st) {
     return h->precision == 64 ? upload_state<double>(h, st) : upload_state<float>(h, st);
 }
 
+// The collision bookkeeping's rebuild threshold and every-step switch in the
+// device scalars (they change with the actuation range and the scheme).
+static int upload_motion_params(vx_sim *h) {
+    if (!h->bound || !h->p.self_collision_on) return VX_OK;
+    Scalars *sc = (Scalars *)(h->ws + h->L.scalars);
+    const double thr = 2.0 * h->p.voxel_size - h->cmax;
+    const unsigned every = h->coll_every ? 1u : 0u;
+    HIP_OK(h, hipMemcpyAsync(&sc->threshold, &thr, sizeof(thr), hipMemcpyHostToDevice, h->stream));
+    HIP_OK(h, hipMemcpyAsync(&sc->every, &every, sizeof(every), hipMemcpyHostToDevice, h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    return VX_OK;
+}
+
 static int reupload_static(vx_sim *h) {
     h->tape_valid = false;
     if (!h->bound) return VX_OK;
-    return h->precision == 64 ? upload_static<double>(h) : upload_static<float>(h);
+    const int r = h->precision == 64 ? upload_static<double>(h) : upload_static<float>(h);
+    return r ? r : upload_motion_params(h);
 }
 
 // Mass of filled cell c: the palette density, or the cell's own in
@@ -187,8 +208,12 @@ static void update_cmax(vx_sim *h) {
     for (long long c = 0; c < h->ncell; ++c) {
         const int m = h->grid[c];
         if (!m) continue;
-        const double a = (h->flags[c] & FLAG_ACT) ? h->amp[c] : h->p.temp_amp;
-        cmax = std::max(cmax, l * (1.0 + std::fabs(h->pal[m].cte * a)));
+        double a = std::fabs((h->flags[c] & FLAG_ACT) ? h->amp[c] : h->p.temp_amp);
+        if (h->cell_chan[c] >= 0) {
+            const vx_channel &ch = h->chans[h->cell_chan[c]];
+            a = std::fabs(ch.offset) + std::fabs(ch.amp);
+        }
+        cmax = std::max(cmax, l * (1.0 + std::fabs(h->pal[m].cte) * a));
     }
     h->cmax = cmax;
 }
@@ -239,12 +264,18 @@ static int enqueue_steps(vx_sim *h, int64_t n) {
         }
         if (h->use_split()) {
             HIP_OK(h, launch_split_step<T>(a, h->stream));
+            if (col) {
+                CollideArgs c = make_collide(h);
+                HIP_OK(h, launch_motion_update<T>(a, c, h->stream));
+            }
         } else {
+            // the FP32 fused kernel's last workgroup does the motion bookkeeping
+            if (col && sizeof(T) == 4) a.motion = step_motion(h);
             HIP_OK(h, launch_fused_step<T>(a, fused_cfg(h), h->stream));
-        }
-        if (col) {
-            CollideArgs c = make_collide(h);
-            HIP_OK(h, launch_motion_update<T>(a, c, h->stream));
+            if (col && sizeof(T) == 8) {
+                CollideArgs c = make_collide(h);
+                HIP_OK(h, launch_motion_update<T>(a, c, h->stream));
+            }
         }
         h->cur = 1 - h->cur;
         h->step++;
@@ -405,6 +436,7 @@ int vx_create(const uint8_t *grid, int32_t nx, int32_t ny, int32_t nz, const vx_
     h->flags.assign(ncell, 0);
     h->amp.assign(ncell, 0.0);
     h->phase.assign(ncell, 0.0);
+    h->cell_chan.assign(ncell, -1);
     h->force.assign(3 * ncell, 0.0);
     h->cand_cap = p.contact_cap > 0 ? p.contact_cap : 32;
     const double l = p.voxel_size;
@@ -465,14 +497,30 @@ int vx_bind_workspace(vx_handle h, void *device_ptr, uint64_t bytes) {
     if (r != VX_OK) { h->bound = false; return r; }
     Scalars sc{};
     sc.rebuild_flag = h->p.self_collision_on ? 1u : 0u;
+    sc.threshold = 2.0 * h->p.voxel_size - h->cmax;
+    sc.every = h->coll_every ? 1u : 0u;
     HIP_OK(h, hipMemcpyAsync(h->ws + h->L.scalars, &sc, sizeof(sc), hipMemcpyHostToDevice, h->stream));
     if (h->p.self_collision_on) {
         HIP_OK(h, hipMemcpyAsync(h->ws + h->L.surf_cells, h->coll_cells.data(), h->coll_cells.size() * 4,
                                  hipMemcpyHostToDevice, h->stream));
-        std::vector<int> zeros(h->coll_cells.size(), 0);
+        // one object: rest indices of every listed voxel and the lattice origin
+        const size_t ns = h->coll_cells.size();
+        std::vector<int> obj(ns, 0);
+        std::vector<long long> ijk(ns);
+        for (size_t i = 0; i < ns; ++i) {
+            const long long c = h->coll_cells[i];
+            ijk[i] = pack_ijk((int)(c % h->nx), (int)((c / h->nx) % h->ny), (int)(c / ((long long)h->nx * h->ny)));
+        }
+        HIP_OK(h, hipMemcpyAsync(h->ws + h->L.surf_obj, obj.data(), ns * 4, hipMemcpyHostToDevice, h->stream));
+        HIP_OK(h, hipMemcpyAsync(h->ws + h->L.surf_ijk, ijk.data(), ns * 8, hipMemcpyHostToDevice, h->stream));
+        HIP_OK(h, hipMemcpyAsync(h->ws + h->L.obj_origin, h->p.origin, 3 * 8, hipMemcpyHostToDevice, h->stream));
+        std::vector<int> zeros(ns, 0);
         HIP_OK(h, hipMemcpyAsync(h->ws + h->L.cand_n, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice, h->stream));
         std::vector<int> zt(h->table_size, 0);
         HIP_OK(h, hipMemcpyAsync(h->ws + h->L.bfill, zt.data(), zt.size() * 4, hipMemcpyHostToDevice, h->stream));
+        HIP_OK(h, hipMemcpyAsync(h->ws + h->L.block_sum, zt.data(), scan_blocks(h->table_size) * 4,
+                                 hipMemcpyHostToDevice, h->stream));
+        HIP_OK(h, hipStreamSynchronize(h->stream));
     }
     r = put_state(h, h->state0);
     if (r != VX_OK) { h->bound = false; return r; }
@@ -561,6 +609,35 @@ int vx_set_actuation(vx_handle h, const double *amp, const double *phase) {
         h->phase[c] = phase ? phase[c] : h->p.temp_phase;
         if (h->has_act && h->grid[c]) h->flags[c] |= FLAG_ACT; else h->flags[c] &= (uint8_t)~FLAG_ACT;
     }
+    update_cmax(h);
+    return reupload_static(h);
+}
+
+int vx_set_channels(vx_handle h, const vx_channel *ch, int32_t n_ch, const int32_t *mat_channel,
+                    const int32_t *cell_channel) {
+    if (!h || n_ch < 0 || n_ch > VX_MAX_CHANNELS || (n_ch > 0 && !ch)) return VX_EINVAL;
+    for (int k = 0; k < n_ch; ++k) {
+        const vx_channel &c = ch[k];
+        if (c.waveform < VX_WAVE_SINE || c.waveform > VX_WAVE_SQUARE || c.reserved != 0 ||
+            !std::isfinite(c.amp) || !std::isfinite(c.freq) || !std::isfinite(c.phase) || !std::isfinite(c.offset))
+            return fail(h, VX_EINVAL, "bad channel " + std::to_string(k));
+    }
+    std::vector<int8_t> cc(h->ncell, -1);
+    for (long long c = 0; c < h->ncell; ++c) {
+        if (!h->grid[c]) continue;
+        int k = -1;
+        if (cell_channel && cell_channel[c] >= 0) k = cell_channel[c];
+        else if (mat_channel) k = mat_channel[h->grid[c]];
+        if (k >= n_ch) return fail(h, VX_EINVAL, "channel index out of range at cell " + std::to_string(c));
+        cc[c] = (int8_t)(k < 0 ? -1 : k);
+    }
+    h->chans.assign(ch, ch + n_ch);
+    h->cell_chan = cc;
+    h->chan_grad_valid = false;
+    for (long long c = 0; c < h->ncell; ++c) {
+        if (cc[c] >= 0) h->flags[c] |= FLAG_CHAN; else h->flags[c] &= (uint8_t)~FLAG_CHAN;
+    }
+    h->tape_valid = false;
     update_cmax(h);
     return reupload_static(h);
 }
@@ -782,7 +859,7 @@ int vx_candidates(vx_handle h, int32_t *cell_a, int32_t *cell_b, int32_t max_pai
     int32_t k = 0;
     for (size_t i = 0; i < ns; ++i)
         for (int j = 0; j < cn[i]; ++j) {
-            const int other = cand[i * h->cand_cap + j];
+            const int other = h->coll_cells[cand[i * h->cand_cap + j]];
             if (other <= h->coll_cells[i]) continue;
             if (k < max_pairs && cell_a && cell_b) { cell_a[k] = h->coll_cells[i]; cell_b[k] = other; }
             ++k;
@@ -796,6 +873,10 @@ int vx_set_collision_mode(vx_handle h, int32_t all_voxels, int32_t every_step) {
     if (h->bound && (all_voxels != 0) != h->coll_all)
         return fail(h, VX_ESTATE, "the voxels taking part in collision detection are fixed at bind");
     h->coll_every = every_step != 0;
+    if (h->bound) {
+        const int r = upload_motion_params(h);
+        if (r) return r;
+    }
     if (!h->bound && (all_voxels != 0) != h->coll_all) {
         h->coll_all = all_voxels != 0;
         if (h->coll_all) {

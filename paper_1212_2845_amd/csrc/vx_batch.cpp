@@ -1,11 +1,16 @@
-// Host side of the batched C ABI: many independent voxel objects packed
-// into one set of arrays and stepped by one persistent launch.  Each object
-// gets its own stable timestep (Eq. 31-32 over its own bonds); objects are
-// assigned to workgroups by longest-processing-time packing on cell count.
+// Host side of the batched C ABI: many voxel objects packed into one set of
+// arrays.  Independent objects are stepped by one persistent launch, each
+// with its own stable timestep (Eq. 31-32 over its own bonds); with contact
+// on, the objects share one world, one timestep and one surface hash, and
+// every step runs the collision chain, the contact forces and one launch of
+// the batch kernel.  Objects are assigned to workgroups by
+// longest-processing-time packing on cell count.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
+#include <cstring>
 #include <numeric>
 #include <queue>
 #include <string>
@@ -54,8 +59,22 @@ struct vx_batch_sim {
     char *ws = nullptr;
     struct {
         uint64_t state[2], mat, flags[2], mats, pairs, objs, wg_start, wg_objs, scalars, total;
+        // contact between objects
+        uint64_t contact_F, surf_cells, surf_obj, surf_ijk, obj_origin, cand, cand_n, keys, gc, sorted, sgc, sijk,
+            sobj, su, bstart, bfill, block_sum;
     } L{};
     int wg_cap = 0;              // capacity of the workgroup tables
+    // contact: the surface voxels of every object (state index, object,
+    // rest indices), the objects' origins, the candidate capacity, the hash
+    // table size and the largest contact size actuation can produce
+    bool contact = false;
+    std::vector<int> surf_cells, surf_obj;
+    std::vector<long long> surf_ijk;
+    std::vector<double> origins;
+    int cand_cap = 32;
+    int table_size = 1;
+    double cmax = 0.0;
+    double dt = 0.0;             // the common timestep with contact
     std::string err;
 };
 
@@ -96,7 +115,60 @@ static void layout(vx_batch_sim *h) {
     h->L.wg_start = take(((uint64_t)h->wg_cap + 1) * 4);
     h->L.wg_objs = take((uint64_t)h->objs.size() * 4);
     h->L.scalars = take(256);
+    const uint64_t ns = h->contact ? h->surf_cells.size() : 0;
+    h->L.contact_F = take(h->contact ? 3 * n * ts : 0);
+    h->L.surf_cells = take(ns * 4);
+    h->L.surf_obj = take(ns * 4);
+    h->L.surf_ijk = take(ns * 8);
+    h->L.obj_origin = take(h->origins.size() * 8);
+    h->L.cand = take(ns * (uint64_t)h->cand_cap * 4);
+    h->L.cand_n = take(ns * 4);
+    h->L.keys = take(ns * 4);
+    h->L.gc = take(ns * 8);
+    h->L.sorted = take(ns * 4);
+    h->L.sgc = take(ns * 8);
+    h->L.sijk = take(ns * 8);
+    h->L.sobj = take(ns * 4);
+    h->L.su = take(3 * ns * ts);
+    h->L.bstart = take(h->contact ? ((uint64_t)h->table_size + 1) * 4 : 0);
+    h->L.bfill = take(h->contact ? (uint64_t)h->table_size * 4 : 0);
+    h->L.block_sum = take(h->contact ? (uint64_t)scan_blocks(h->table_size) * 4 : 0);
     h->L.total = off;
+}
+
+static CollideArgs batch_collide(vx_batch_sim *h) {
+    CollideArgs c{};
+    char *ws = h->ws;
+    Scalars *sc = (Scalars *)(ws + h->L.scalars);
+    c.surf_cells = (const int *)(ws + h->L.surf_cells);
+    c.surf_obj = (const int *)(ws + h->L.surf_obj);
+    c.surf_ijk = (const long long *)(ws + h->L.surf_ijk);
+    c.obj_origin = (const double *)(ws + h->L.obj_origin);
+    c.n_surf = (int)h->surf_cells.size();
+    c.cap = h->cand_cap;
+    c.cand = (int *)(ws + h->L.cand);
+    c.cand_n = (int *)(ws + h->L.cand_n);
+    c.overflow = &sc->overflow;
+    c.rebuild_flag = &sc->rebuild_flag;
+    c.done = &sc->done;
+    c.macc = &sc->macc;
+    c.vmax_bits = &sc->vmax_bits;
+    c.cell_keys = (int *)(ws + h->L.keys);
+    c.cell_gc = (long long *)(ws + h->L.gc);
+    c.sorted_idx = (int *)(ws + h->L.sorted);
+    c.sorted_gc = (long long *)(ws + h->L.sgc);
+    c.sorted_ijk = (long long *)(ws + h->L.sijk);
+    c.sorted_obj = (int *)(ws + h->L.sobj);
+    c.sorted_u = (void *)(ws + h->L.su);
+    c.bucket_start = (int *)(ws + h->L.bstart);
+    c.bucket_fill = (int *)(ws + h->L.bfill);
+    c.block_sum = (int *)(ws + h->L.block_sum);
+    c.table_size = h->table_size;
+    c.pair_count = &sc->pair_count;
+    c.horizon = 2.0 * h->p.voxel_size;
+    c.rebuild_counter = &sc->rebuilds;
+    c.scalars = sc;
+    return c;
 }
 
 // Longest-processing-time packing: biggest objects first, each to the
@@ -150,8 +222,28 @@ static int upload_all(vx_batch_sim *h) {
     std::fill(st.begin() + (size_t)W_QW * h->total, st.begin() + (size_t)(W_QW + 1) * h->total, T(1));
     BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.state[0], st.data(), st.size() * sizeof(T), hipMemcpyHostToDevice, s));
     BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.state[1], st.data(), st.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    std::vector<unsigned char> zero(256, 0);
-    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.scalars, zero.data(), 256, hipMemcpyHostToDevice, s));
+    std::vector<unsigned char> sc(256, 0);
+    if (h->contact) {
+        Scalars first{};
+        first.rebuild_flag = 1u;   // candidates are built before the first step
+        first.threshold = 2.0 * h->p.voxel_size - h->cmax;
+        first.every = 0u;
+        std::memcpy(sc.data(), &first, sizeof(first));
+        const size_t ns = h->surf_cells.size();
+        BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.surf_cells, h->surf_cells.data(), ns * 4, hipMemcpyHostToDevice, s));
+        BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.surf_obj, h->surf_obj.data(), ns * 4, hipMemcpyHostToDevice, s));
+        BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.surf_ijk, h->surf_ijk.data(), ns * 8, hipMemcpyHostToDevice, s));
+        BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.obj_origin, h->origins.data(), h->origins.size() * 8,
+                                  hipMemcpyHostToDevice, s));
+        std::vector<int> zeros(std::max<size_t>(ns, (size_t)h->table_size), 0);
+        BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.cand_n, zeros.data(), ns * 4, hipMemcpyHostToDevice, s));
+        BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.bfill, zeros.data(), (size_t)h->table_size * 4, hipMemcpyHostToDevice, s));
+        BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.block_sum, zeros.data(), (size_t)scan_blocks(h->table_size) * 4,
+                                  hipMemcpyHostToDevice, s));
+        std::vector<T> cf((size_t)3 * h->total, T(0));
+        BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.contact_F, cf.data(), cf.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.scalars, sc.data(), 256, hipMemcpyHostToDevice, s));
     BHIP_OK(h, hipStreamSynchronize(s));
     return VX_OK;
 }
@@ -163,6 +255,7 @@ static int run(vx_batch_sim *h, int64_t n) {
     lpt(h, n_wg, start, order);
     BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.wg_start, start.data(), start.size() * 4, hipMemcpyHostToDevice, h->stream));
     BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.wg_objs, order.data(), order.size() * 4, hipMemcpyHostToDevice, h->stream));
+    Scalars *sc = (Scalars *)(h->ws + h->L.scalars);
     BatchArgs<T> b{};
     StepArgs<T> &a = b.base;
     a.stride = h->total;
@@ -173,10 +266,11 @@ static int run(vx_batch_sim *h, int64_t n) {
     a.l = (T)h->p.voxel_size;
     a.gravity = (T)h->p.gravity;
     a.floor_on = h->p.floor_on;
-    a.track_vmax = 0;
+    a.track_vmax = h->contact ? 1 : 0;
     a.n_forced = 0;
-    a.err_flag = (unsigned *)(h->ws + h->L.scalars);
-    a.vmax_bits = (unsigned long long *)(h->ws + h->L.scalars + 8);
+    a.err_flag = &sc->err_flag;
+    a.vmax_bits = &sc->vmax_bits;
+    a.contact_F = h->contact ? (const T *)(h->ws + h->L.contact_F) : nullptr;
     b.state[0] = (T *)(h->ws + h->L.state[0]);
     b.state[1] = (T *)(h->ws + h->L.state[1]);
     b.flags[0] = (uint8_t *)(h->ws + h->L.flags[0]);
@@ -187,21 +281,48 @@ static int run(vx_batch_sim *h, int64_t n) {
     b.temp_amp = h->p.temp_amp;
     b.temp_freq = h->p.temp_freq;
     b.temp_phase = h->p.temp_phase;
-    int64_t left = n;
-    while (left > 0) {
-        const int k = (int)std::min<int64_t>(left, h->max_steps_per_launch);
-        b.steps = k;
-        b.cur0 = h->cur;
-        b.step0 = h->step;
-        BHIP_OK(h, launch_batch<T>(b, n_wg, h->stream));
-        h->cur = (h->cur + k) & 1;
-        h->step += k;
-        left -= k;
+    if (h->contact) {
+        // one step per launch: the collision chain and the contact forces
+        // read every object's state at t_n, then the batch kernel steps all
+        // objects, then the motion bookkeeping
+        const CollideArgs c = batch_collide(h);
+        for (int64_t i = 0; i < n; ++i) {
+            StepArgs<T> ca = a;   // the lattice view the collision kernels take
+            ca.s_in = b.state[h->cur];
+            ca.flags = b.flags[h->cur];
+            ca.dt = (T)h->dt;
+            const double wt = 2.0 * kPi * h->p.temp_freq * ((double)h->step * h->dt);
+            ca.dT_global = (T)(h->p.temp_amp * std::sin(wt + h->p.temp_phase));
+            ca.wt = wt;
+            ca.wt_red = (T)std::fmod(wt, 2.0 * kPi);
+            BHIP_OK(h, launch_rebuild<T>(ca, c, h->stream));
+            BHIP_OK(h, launch_contact<T>(ca, c, (T *)(h->ws + h->L.contact_F), h->stream));
+            b.steps = 1;
+            b.cur0 = h->cur;
+            b.step0 = h->step;
+            BHIP_OK(h, launch_batch<T>(b, n_wg, h->stream));
+            BHIP_OK(h, launch_motion_update<T>(ca, c, h->stream));
+            h->cur = 1 - h->cur;
+            h->step += 1;
+        }
+    } else {
+        int64_t left = n;
+        while (left > 0) {
+            const int k = (int)std::min<int64_t>(left, h->max_steps_per_launch);
+            b.steps = k;
+            b.cur0 = h->cur;
+            b.step0 = h->step;
+            BHIP_OK(h, launch_batch<T>(b, n_wg, h->stream));
+            h->cur = (h->cur + k) & 1;
+            h->step += k;
+            left -= k;
+        }
     }
-    unsigned errf = 0;
-    BHIP_OK(h, hipMemcpyAsync(&errf, h->ws + h->L.scalars, 4, hipMemcpyDeviceToHost, h->stream));
+    Scalars st;
+    BHIP_OK(h, hipMemcpyAsync(&st, h->ws + h->L.scalars, sizeof(st), hipMemcpyDeviceToHost, h->stream));
     BHIP_OK(h, hipStreamSynchronize(h->stream));
-    if (errf) return bfail(h, VX_EUNSTABLE, "non-finite value in a batched object's state");
+    if (st.err_flag) return bfail(h, VX_EUNSTABLE, "non-finite value in a batched object's state");
+    if (st.overflow) return bfail(h, VX_EOVERFLOW, "collision candidate list overflow (raise contact_cap)");
     return VX_OK;
 }
 
@@ -273,7 +394,7 @@ int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *pal
     const vx_params &p = *params;
     if (!(p.voxel_size > 0.0) || !(p.gravity >= 0.0) || !(p.zeta_bond >= 0.0) || !(p.zeta_slow >= 0.0) ||
         !(p.zeta_col >= 0.0) || !(p.dt_scale >= 0.0) || p.dt_scale > 1.0 || p.reserved != 0 ||
-        p.self_collision_on != 0)
+        (p.self_collision_on != 0 && p.self_collision_on != 1) || p.contact_cap < 0 || p.contact_cap > kMaxContactCap)
         return VX_EINVAL;
     for (int i = 1; i < n_mat; ++i) {
         const vx_material &m = palette[i];
@@ -291,6 +412,7 @@ int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *pal
     h->pal.assign(palette, palette + n_mat);
     const double l = p.voxel_size;
     long long off = 0;
+    std::vector<char> used(n_mat, 0);   // materials present in any object
     for (int i = 0; i < n_obj; ++i) {
         const vx_object &o = objs[i];
         if (!o.grid || o.nx <= 0 || o.ny <= 0 || o.nz <= 0) { delete h; return VX_EINVAL; }
@@ -319,8 +441,32 @@ int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *pal
                         if (m2) seen[(size_t)m * n_mat + m2] = 1;
                     }
                 }
+        for (int m = 1; m < n_mat; ++m) used[m] |= seen_vox[m];
         const double wmax = max_bond_omega(palette, n_mat, l, seen, seen_vox);
         oh.dt = wmax > 0.0 ? h->p.dt_scale / (2.0 * kPi * wmax) : 0.0;
+        if (p.self_collision_on) {
+            // surface voxels: a face neighbour empty or outside the object
+            for (int z = 0; z < o.nz; ++z)
+                for (int y = 0; y < o.ny; ++y)
+                    for (int x = 0; x < o.nx; ++x) {
+                        const long long c = x + (long long)o.nx * (y + (long long)o.ny * z);
+                        if (!o.grid[c]) continue;
+                        const int idx[3] = {x, y, z}, dim[3] = {o.nx, o.ny, o.nz};
+                        const long long st[3] = {1, o.nx, (long long)o.nx * o.ny};
+                        bool surf = false;
+                        for (int a = 0; a < 3 && !surf; ++a)
+                            for (int d = -1; d <= 1 && !surf; d += 2) {
+                                const int k = idx[a] + d;
+                                surf = k < 0 || k >= dim[a] || !o.grid[c + d * st[a]];
+                            }
+                        if (!surf) continue;
+                        if (off + c > INT32_MAX) { delete h; return VX_EINVAL; }
+                        h->surf_cells.push_back((int)(off + c));
+                        h->surf_obj.push_back(i);
+                        h->surf_ijk.push_back(pack_ijk(x, y, z));
+                    }
+            h->origins.insert(h->origins.end(), o.origin, o.origin + 3);
+        }
         h->grid.insert(h->grid.end(), o.grid, o.grid + nc);
         h->nvox += oh.nvox;
         h->objs.push_back(oh);
@@ -328,6 +474,24 @@ int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *pal
     }
     h->total = off;
     if (!fused_state_fits(h->total, h->tsize)) { delete h; return VX_EINVAL; }
+    if (p.self_collision_on) {
+        // one world: the smallest of the objects' stable timesteps for all,
+        // and the largest contact size the global signal can produce
+        h->contact = true;
+        double dt = 0.0;
+        for (const ObjHost &o : h->objs)
+            if (o.dt > 0.0 && (dt == 0.0 || o.dt < dt)) dt = o.dt;
+        h->dt = dt;
+        for (ObjHost &o : h->objs) o.dt = dt;
+        double cmax = l;
+        for (int m = 1; m < n_mat; ++m)
+            if (used[m]) cmax = std::max(cmax, l * (1.0 + std::fabs(palette[m].cte * p.temp_amp)));
+        h->cmax = cmax;
+        h->cand_cap = p.contact_cap > 0 ? p.contact_cap : 32;
+        int ts = 1;
+        while (ts < 2 * (int)std::max<size_t>(h->surf_cells.size(), 1)) ts <<= 1;
+        h->table_size = ts;
+    }
     layout(h);
     *out = h;
     return VX_OK;
@@ -387,6 +551,47 @@ int vx_batch_counters(vx_batch h, int64_t out[4]) {
     return VX_OK;
 }
 
+int vx_batch_candidates(vx_batch h, int32_t *obj_a, int32_t *cell_a, int32_t *obj_b, int32_t *cell_b,
+                        int32_t max_pairs, int32_t *n_pairs) {
+    if (!h || !n_pairs || max_pairs < 0) return VX_EINVAL;
+    *n_pairs = 0;
+    if (!h->bound || !h->contact) return VX_OK;
+    const size_t ns = h->surf_cells.size();
+    std::vector<int> cand(ns * h->cand_cap), cn(ns);
+    BHIP_OK(h, hipMemcpyAsync(cand.data(), h->ws + h->L.cand, cand.size() * 4, hipMemcpyDeviceToHost, h->stream));
+    BHIP_OK(h, hipMemcpyAsync(cn.data(), h->ws + h->L.cand_n, cn.size() * 4, hipMemcpyDeviceToHost, h->stream));
+    BHIP_OK(h, hipStreamSynchronize(h->stream));
+    int32_t k = 0;
+    for (size_t i = 0; i < ns; ++i)
+        for (int e = 0; e < cn[i]; ++e) {
+            const int j = cand[i * h->cand_cap + e];
+            if (j <= (int)i) continue;   // each pair once; list order is object-major
+            if (k < max_pairs) {
+                const int oi = h->surf_obj[i], oj = h->surf_obj[j];
+                if (obj_a) obj_a[k] = oi;
+                if (cell_a) cell_a[k] = (int32_t)(h->surf_cells[i] - h->objs[oi].off);
+                if (obj_b) obj_b[k] = oj;
+                if (cell_b) cell_b[k] = (int32_t)(h->surf_cells[j] - h->objs[oj].off);
+            }
+            ++k;
+        }
+    *n_pairs = k;
+    return VX_OK;
+}
+
+int vx_batch_contact_counters(vx_batch h, int64_t out[3]) {
+    if (!h || !out) return VX_EINVAL;
+    out[0] = out[1] = 0;
+    out[2] = h->contact ? (int64_t)h->surf_cells.size() : 0;
+    if (!h->bound || !h->contact) return VX_OK;
+    Scalars sc;
+    BHIP_OK(h, hipMemcpyAsync(&sc, h->ws + h->L.scalars, sizeof(sc), hipMemcpyDeviceToHost, h->stream));
+    BHIP_OK(h, hipStreamSynchronize(h->stream));
+    out[0] = (int64_t)sc.rebuilds;
+    out[1] = (int64_t)sc.pair_count;
+    return VX_OK;
+}
+
 int vx_batch_set_launch(vx_batch h, int32_t n_workgroups, int32_t max_steps_per_launch) {
     if (!h || n_workgroups < 0 || max_steps_per_launch < 0) return VX_EINVAL;
     h->n_wg = std::min<int>(n_workgroups, (int)h->objs.size());
@@ -397,17 +602,38 @@ int vx_batch_set_launch(vx_batch h, int32_t n_workgroups, int32_t max_steps_per_
 int vx_batch_autotune(vx_batch h, int32_t steps, int32_t *n_workgroups) {
     if (!h || steps <= 0) return VX_EINVAL;
     if (!h->bound) return bfail(h, VX_ESTATE, "autotune before bind");
-    // time candidate workgroup counts on the real objects; the state is
-    // saved and restored around the trial steps
+    // time candidate workgroup counts on the real objects; the state, the
+    // flags, the buffer order, the step count and the status flags are
+    // saved and restored around the trial steps, on every exit
     const size_t bytes = (size_t)N_WORDS * h->total * h->tsize;
     const int cur0 = h->cur;
     const long long step0 = h->step;
-    // keep a copy of the current state in the other buffer's place after the
-    // trials by re-running from a host copy
-    std::vector<char> save(bytes), fsave(h->total);
+    const int wg0 = h->n_wg;
+    const size_t ns = h->contact ? h->surf_cells.size() : 0;
+    std::vector<char> save(bytes), fsave(h->total), ssave(256), csave(ns * h->cand_cap * 4), nsave(ns * 4);
     BHIP_OK(h, hipMemcpyAsync(save.data(), h->ws + h->L.state[cur0], bytes, hipMemcpyDeviceToHost, h->stream));
     BHIP_OK(h, hipMemcpyAsync(fsave.data(), h->ws + h->L.flags[cur0], h->total, hipMemcpyDeviceToHost, h->stream));
+    BHIP_OK(h, hipMemcpyAsync(ssave.data(), h->ws + h->L.scalars, ssave.size(), hipMemcpyDeviceToHost, h->stream));
+    if (ns) {
+        BHIP_OK(h, hipMemcpyAsync(csave.data(), h->ws + h->L.cand, csave.size(), hipMemcpyDeviceToHost, h->stream));
+        BHIP_OK(h, hipMemcpyAsync(nsave.data(), h->ws + h->L.cand_n, nsave.size(), hipMemcpyDeviceToHost, h->stream));
+    }
     BHIP_OK(h, hipStreamSynchronize(h->stream));
+    auto restore = [&](int keep_wg) -> int {
+        h->n_wg = keep_wg;
+        h->cur = cur0;
+        h->step = step0;
+        BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.state[cur0], save.data(), bytes, hipMemcpyHostToDevice, h->stream));
+        BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.flags[cur0], fsave.data(), h->total, hipMemcpyHostToDevice, h->stream));
+        BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.scalars, ssave.data(), ssave.size(), hipMemcpyHostToDevice, h->stream));
+        if (ns) {
+            BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.cand, csave.data(), csave.size(), hipMemcpyHostToDevice, h->stream));
+            BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.cand_n, nsave.data(), nsave.size(), hipMemcpyHostToDevice,
+                                      h->stream));
+        }
+        BHIP_OK(h, hipStreamSynchronize(h->stream));
+        return VX_OK;
+    };
     const int nobj = (int)h->objs.size();
     const int cands[] = {256, 512, 768, 1024, 1536, 2048, 3072, 4096};
     hipEvent_t e0, e1;
@@ -415,27 +641,32 @@ int vx_batch_autotune(vx_batch h, int32_t steps, int32_t *n_workgroups) {
     BHIP_OK(h, hipEventCreate(&e1));
     float best = 1e30f;
     int best_wg = default_wg(h);
+    int rc = VX_OK;
     for (int c : cands) {
         const int nw = std::min(c, nobj);
         h->n_wg = nw;
-        BHIP_OK(h, hipEventRecord(e0, h->stream));
-        int r = h->precision == 64 ? run<double>(h, steps) : run<float>(h, steps);
-        if (r != VX_OK) { hipEventDestroy(e0); hipEventDestroy(e1); return r; }
-        BHIP_OK(h, hipEventRecord(e1, h->stream));
-        BHIP_OK(h, hipEventSynchronize(e1));
         float ms = 0.f;
-        BHIP_OK(h, hipEventElapsedTime(&ms, e0, e1));
+        if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = bfail(h, VX_EDEVICE, "hipEventRecord"); break; }
+        rc = h->precision == 64 ? run<double>(h, steps) : run<float>(h, steps);
+        if (rc != VX_OK) break;
+        if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = bfail(h, VX_EDEVICE, "timing events");
+            break;
+        }
         if (ms < best) { best = ms; best_wg = nw; }
         if (nw == nobj) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    h->n_wg = best_wg;
-    h->cur = cur0;
-    h->step = step0;
-    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.state[cur0], save.data(), bytes, hipMemcpyHostToDevice, h->stream));
-    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.flags[cur0], fsave.data(), h->total, hipMemcpyHostToDevice, h->stream));
-    BHIP_OK(h, hipStreamSynchronize(h->stream));
+    if (rc != VX_OK) {
+        const std::string msg = h->err;
+        restore(wg0);
+        h->err = msg;
+        return rc;
+    }
+    const int r = restore(best_wg);
+    if (r != VX_OK) return r;
     if (n_workgroups) *n_workgroups = best_wg;
     return VX_OK;
 }

@@ -26,26 +26,6 @@ __device__ __forceinline__ int cell_hash(int cx, int cy, int cz, int mask) {
     return (int)(h & (unsigned)mask);
 }
 
-template <typename T>
-__device__ __forceinline__ void voxel_pos(const StepArgs<T> &a, int c, int &ix, int &iy, int &iz, T &x, T &y,
-                                          T &z, const T *origin) {
-    ix = c % a.nx;
-    iy = (c / a.nx) % a.ny;
-    iz = c / (a.nx * a.ny);
-    x = origin[0] + (T(ix) + T(0.5)) * a.l + a.s_in[W_UX * a.stride + c];
-    y = origin[1] + (T(iy) + T(0.5)) * a.l + a.s_in[W_UY * a.stride + c];
-    z = origin[2] + (T(iz) + T(0.5)) * a.l + a.s_in[W_UZ * a.stride + c];
-}
-
-struct Origin3 { double v[3]; };
-
-template <typename T>
-__device__ __forceinline__ void grid_cell(T x, T y, T z, double H, int &cx, int &cy, int &cz) {
-    cx = (int)floor((double)x / H);
-    cy = (int)floor((double)y / H);
-    cz = (int)floor((double)z / H);
-}
-
 // Three integers of at most 21 bits each (offset by 2^20, so grid cells a
 // little below the origin pack too) in one 64-bit word.  Two neighbouring
 // grid cells never share a packed value.
@@ -63,6 +43,25 @@ __device__ __forceinline__ void unpack3(long long v, int &x, int &y, int &z) {
     z = (int)((u >> 42) & m) - b;
 }
 
+// Separation D_i - D_j of two listed voxels from their rest indices within
+// their objects, the objects' origins and their displacements.  Within one
+// object the rest offset is an exact multiple of l.
+template <typename T>
+__device__ __forceinline__ void separation(const CollideArgs &c, T l, int oi, int ix, int iy, int iz, int oj, int jx,
+                                           int jy, int jz, T dux, T duy, T duz, T &rx, T &ry, T &rz) {
+    if (oi == oj) {
+        rx = T(ix - jx) * l + dux;
+        ry = T(iy - jy) * l + duy;
+        rz = T(iz - jz) * l + duz;
+    } else {
+        const double *a = c.obj_origin + 3 * oi, *b = c.obj_origin + 3 * oj;
+        const double L = (double)l;
+        rx = (T)((a[0] - b[0]) + (double)(ix - jx) * L) + dux;
+        ry = (T)((a[1] - b[1]) + (double)(iy - jy) * L) + duy;
+        rz = (T)((a[2] - b[2]) + (double)(iz - jz) * L) + duz;
+    }
+}
+
 // Surface voxels per workgroup of the candidate search (27 threads each),
 // and the largest grid of the rebuild kernels (they stride over their work).
 constexpr int kCandVox = 9;
@@ -70,70 +69,61 @@ constexpr int kCandGrid = 512;
 // bucket entries whose loads the candidate search issues together
 constexpr int kGroup = 4;
 
+// Grid cell and hash key of every listed voxel; bucket counts and the
+// counts per scan block.  The last workgroup to finish turns the block
+// counts into their exclusive prefix.
 template <typename T>
-__global__ void __launch_bounds__(256) k_keys(StepArgs<T> a, CollideArgs c, Origin3 o) {
+__global__ void __launch_bounds__(256) k_keys(StepArgs<T> a, CollideArgs c, int nblk) {
+    __shared__ int last;
+    __shared__ int part[256];
     if (*c.rebuild_flag == 0) return;
     const int first = blockIdx.x * blockDim.x + threadIdx.x;
     if (first == 0) *c.pair_count = 0ull;
-    const T org[3] = {(T)o.v[0], (T)o.v[1], (T)o.v[2]};
+    const double H = c.horizon;
     for (int i = first; i < c.n_surf; i += gridDim.x * blockDim.x) {
-        int ix, iy, iz, cx, cy, cz;
-        T x, y, z;
-        voxel_pos(a, c.surf_cells[i], ix, iy, iz, x, y, z, org);
-        grid_cell(x, y, z, c.horizon, cx, cy, cz);
+        const int ci = c.surf_cells[i], ob = c.surf_obj[i];
+        int ix, iy, iz;
+        unpack3(c.surf_ijk[i], ix, iy, iz);
+        const double *o = c.obj_origin + 3 * ob;
+        // world position in the state precision: origin + (index + 1/2) l + u
+        const T x = (T)o[0] + (T(ix) + T(0.5)) * a.l + a.s_in[W_UX * a.stride + ci];
+        const T y = (T)o[1] + (T(iy) + T(0.5)) * a.l + a.s_in[W_UY * a.stride + ci];
+        const T z = (T)o[2] + (T(iz) + T(0.5)) * a.l + a.s_in[W_UZ * a.stride + ci];
+        const int cx = (int)floor((double)x / H), cy = (int)floor((double)y / H), cz = (int)floor((double)z / H);
         const int key = cell_hash(cx, cy, cz, c.table_size - 1);
         c.cell_keys[i] = key;
         c.cell_gc[i] = pack3(cx, cy, cz);
-        c.cell_ijk[i] = pack3(ix, iy, iz);
         atomicAdd(&c.bucket_fill[key], 1);
+        atomicAdd(&c.block_sum[key / kScanBlock], 1);
     }
-}
-
-// Scan of bucket counts -> bucket_start (exclusive), in three phases.
-__global__ void __launch_bounds__(256) k_scan_reduce(CollideArgs c) {
-    if (*c.rebuild_flag == 0) return;
-    __shared__ int red[256];
-    const int base = blockIdx.x * kScanBlock;
-    int s = 0;
-    for (int k = 0; k < 4; ++k) {
-        const int j = base + threadIdx.x * 4 + k;
-        if (j < c.table_size) s += c.bucket_fill[j];
-    }
-    red[threadIdx.x] = s;
+    __threadfence();
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) ((int *)c.scan_tmp)[blockIdx.x] = red[0];
-}
-
-__global__ void __launch_bounds__(1024) k_scan_blocks(CollideArgs c, int nblocks) {
-    if (*c.rebuild_flag == 0) return;
-    __shared__ int buf[1024];
-    __shared__ int carry;
-    int *bs = (int *)c.scan_tmp;
-    if (threadIdx.x == 0) carry = 0;
+    if (threadIdx.x == 0) last = atomicAdd(c.done, 1u) == gridDim.x - 1;
     __syncthreads();
-    for (int base = 0; base < nblocks; base += 1024) {
-        const int j = base + threadIdx.x;
-        const int v = j < nblocks ? bs[j] : 0;
-        buf[threadIdx.x] = v;
+    if (!last) return;
+    __threadfence();
+    // exclusive prefix of the block counts, 256 blocks at a time
+    int carry = 0;
+    for (int base = 0; base < nblk; base += 256) {
+        const int j = base + (int)threadIdx.x;
+        const int v = j < nblk ? atomicAdd(&c.block_sum[j], 0) : 0;
+        part[threadIdx.x] = v;
         __syncthreads();
-        // Hillis-Steele inclusive scan
-        for (int off = 1; off < 1024; off <<= 1) {
-            const int t = (int)threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+        for (int off = 1; off < 256; off <<= 1) {
+            const int t = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
             __syncthreads();
-            buf[threadIdx.x] += t;
+            part[threadIdx.x] += t;
             __syncthreads();
         }
-        if (j < nblocks) bs[j] = carry + buf[threadIdx.x] - v;   // exclusive
-        __syncthreads();
-        if (threadIdx.x == 1023) carry += buf[1023];
+        if (j < nblk) c.block_sum[j] = carry + part[threadIdx.x] - v;
+        carry += part[255];
         __syncthreads();
     }
+    if (threadIdx.x == 0) *c.done = 0u;
 }
 
+// Bucket starts: each scan block's exclusive prefix of its own counts plus
+// the block's offset; the starts become the scatter cursors.
 __global__ void __launch_bounds__(256) k_scan_apply(CollideArgs c) {
     if (*c.rebuild_flag == 0) return;
     __shared__ int buf[256];
@@ -152,7 +142,7 @@ __global__ void __launch_bounds__(256) k_scan_apply(CollideArgs c) {
         buf[threadIdx.x] += t;
         __syncthreads();
     }
-    int run = ((const int *)c.scan_tmp)[blockIdx.x] + buf[threadIdx.x] - s;
+    int run = c.block_sum[blockIdx.x] + buf[threadIdx.x] - s;
     for (int k = 0; k < 4; ++k) {
         const int j = base + threadIdx.x * 4 + k;
         if (j < c.table_size) {
@@ -171,28 +161,35 @@ __global__ void __launch_bounds__(256) k_scatter(StepArgs<T> a, CollideArgs c) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < c.n_surf; i += gridDim.x * blockDim.x) {
         const int pos = atomicAdd(&c.bucket_fill[c.cell_keys[i]], 1);
         const int ci = c.surf_cells[i];
-        c.sorted_cell[pos] = ci;
+        c.sorted_idx[pos] = i;
         c.sorted_gc[pos] = c.cell_gc[i];
-        c.sorted_ijk[pos] = c.cell_ijk[i];
+        c.sorted_ijk[pos] = c.surf_ijk[i];
+        c.sorted_obj[pos] = c.surf_obj[i];
         su[pos] = a.s_in[W_UX * a.stride + ci];
         su[c.n_surf + pos] = a.s_in[W_UY * a.stride + ci];
         su[2 * c.n_surf + pos] = a.s_in[W_UZ * a.stride + ci];
     }
 }
 
-// One workgroup serves kCandVox surface voxels with one thread per (voxel,
+// One workgroup serves kCandVox listed voxels with one thread per (voxel,
 // neighbouring grid cell) pair: each thread scans its cell's bucket and
 // appends the voxel's candidates from that cell to the voxel's list in LDS
 // (an LDS counter per voxel); after a barrier every entry is written to the
 // voxel's global list at its rank among the voxel's entries, so each list is
-// sorted by partner cell.  Partners are distinct within a list, so the rank
-// is unique.  A list that would exceed cap raises the overflow flag and
-// keeps cap of its entries.
+// sorted by partner.  Partners are distinct within a list, so the rank is
+// unique.  A list that would exceed cap raises the overflow flag and keeps
+// cap of its entries.  Pairs within one object closer than Manhattan
+// distance 4 in rest indices are excluded.  The launch also clears the
+// bucket counts and block sums for the next rebuild (nothing here reads
+// them).
 template <typename T>
-__global__ void __launch_bounds__(256) k_candidates(StepArgs<T> a, CollideArgs c) {
-    extern __shared__ int lds_list[];     // kCandVox x cap partner cells
+__global__ void __launch_bounds__(256) k_candidates(StepArgs<T> a, CollideArgs c, int nblk) {
+    extern __shared__ int lds_list[];     // kCandVox x cap partner indices
     __shared__ int lds_count[kCandVox];
     if (*c.rebuild_flag == 0) return;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < c.table_size; j += gridDim.x * blockDim.x)
+        c.bucket_fill[j] = 0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nblk; j += gridDim.x * blockDim.x) c.block_sum[j] = 0;
     const int t = threadIdx.x;
     const int v = t / 27, nb = t % 27;
     const int groups = (c.n_surf + kCandVox - 1) / kCandVox;
@@ -206,8 +203,9 @@ __global__ void __launch_bounds__(256) k_candidates(StepArgs<T> a, CollideArgs c
         int ci = 0;
         if (live) {
             ci = c.surf_cells[i];
+            const int oi = c.surf_obj[i];
             int ix, iy, iz, cx, cy, cz;
-            unpack3(c.cell_ijk[i], ix, iy, iz);
+            unpack3(c.surf_ijk[i], ix, iy, iz);
             unpack3(c.cell_gc[i], cx, cy, cz);
             const T uxi = a.s_in[W_UX * a.stride + ci], uyi = a.s_in[W_UY * a.stride + ci],
                     uzi = a.s_in[W_UZ * a.stride + ci];
@@ -222,15 +220,16 @@ __global__ void __launch_bounds__(256) k_candidates(StepArgs<T> a, CollideArgs c
             // together (a short last group re-reads its last entry, which is not
             // processed twice)
             for (int k0 = b0; k0 < b1; k0 += kGroup) {
-                int cjg[kGroup];
+                int jg[kGroup], og[kGroup];
                 long long gcg[kGroup], ijg[kGroup];
                 T uxg[kGroup], uyg[kGroup], uzg[kGroup];
     #pragma unroll
                 for (int q = 0; q < kGroup; ++q) {
                     const int k = k0 + q < b1 ? k0 + q : b1 - 1;
-                    cjg[q] = c.sorted_cell[k];
+                    jg[q] = c.sorted_idx[k];
                     gcg[q] = c.sorted_gc[k];
                     ijg[q] = c.sorted_ijk[k];
+                    og[q] = c.sorted_obj[k];
                     uxg[q] = su[k];
                     uyg[q] = su[ns + k];
                     uzg[q] = su[2 * ns + k];
@@ -238,18 +237,17 @@ __global__ void __launch_bounds__(256) k_candidates(StepArgs<T> a, CollideArgs c
     #pragma unroll
                 for (int q = 0; q < kGroup; ++q) {
                     if (k0 + q >= b1) break;
-                    const int cj = cjg[q];
-                    if (cj == ci || gcg[q] != want) continue;   // another cell in this bucket
+                    const int j = jg[q];
+                    if (j == i || gcg[q] != want) continue;   // itself, or another cell in this bucket
                     int jx, jy, jz;
                     unpack3(ijg[q], jx, jy, jz);
-                    const int man = abs(jx - ix) + abs(jy - iy) + abs(jz - iz);
-                    if (man <= 3) continue;
-                    const T rx = T(ix - jx) * a.l + (uxi - uxg[q]);
-                    const T ry = T(iy - jy) * a.l + (uyi - uyg[q]);
-                    const T rz = T(iz - jz) * a.l + (uzi - uzg[q]);
+                    if (og[q] == oi && abs(jx - ix) + abs(jy - iy) + abs(jz - iz) <= 3) continue;
+                    T rx, ry, rz;
+                    separation(c, a.l, oi, ix, iy, iz, og[q], jx, jy, jz, uxi - uxg[q], uyi - uyg[q], uzi - uzg[q],
+                               rx, ry, rz);
                     if (!(dsqrt(rx * rx + ry * ry + rz * rz) < H)) continue;
                     const int slot = atomicAdd(&lds_count[v], 1);
-                    if (slot < c.cap) lds_list[v * c.cap + slot] = cj;
+                    if (slot < c.cap) lds_list[v * c.cap + slot] = j;
                 }
             }
         }
@@ -280,19 +278,6 @@ __global__ void __launch_bounds__(256) k_candidates(StepArgs<T> a, CollideArgs c
     }
 }
 
-__global__ void __launch_bounds__(256) k_rebuild_done(CollideArgs c) {
-    if (*c.rebuild_flag == 0) return;
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < c.table_size; j += gridDim.x * blockDim.x)
-        c.bucket_fill[j] = 0;
-}
-
-__global__ void k_rebuild_clear(CollideArgs c) {
-    if (*c.rebuild_flag == 0) return;
-    *c.rebuild_flag = 0;
-    *c.macc = 0.0;
-    *c.rebuild_counter += 1;
-}
-
 template <typename T>
 __global__ void __launch_bounds__(256) k_contact(StepArgs<T> a, CollideArgs c, T *cf) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -300,24 +285,27 @@ __global__ void __launch_bounds__(256) k_contact(StepArgs<T> a, CollideArgs c, T
     const int n = c.cand_n[i];
     if (n == 0) return;
     const long long st = a.stride;
-    const int ci = c.surf_cells[i];
+    const int ci = c.surf_cells[i], oi = c.surf_obj[i];
     const uint8_t mi = a.mat[ci];
     const MatConst<T> Mi = a.mats[mi];
     const T ei = voxel_strain(a, (unsigned)ci, a.flags[ci], Mi.cte);
-    const int ix = ci % a.nx, iy = (ci / a.nx) % a.ny, iz = ci / (a.nx * a.ny);
+    int ix, iy, iz;
+    unpack3(c.surf_ijk[i], ix, iy, iz);
     const T ux = a.s_in[W_UX * st + ci], uy = a.s_in[W_UY * st + ci], uz = a.s_in[W_UZ * st + ci];
     const T vx = a.s_in[W_PX * st + ci] * Mi.inv_m, vy = a.s_in[W_PY * st + ci] * Mi.inv_m,
             vz = a.s_in[W_PZ * st + ci] * Mi.inv_m;
     T Fx = T(0), Fy = T(0), Fz = T(0);
     const int *list = c.cand + (long long)i * c.cap;
     for (int k = 0; k < n; ++k) {
-        const int cj = list[k];
+        const int j = list[k];
+        const int cj = c.surf_cells[j], oj = c.surf_obj[j];
         const uint8_t mj = a.mat[cj];
         const MatConst<T> Mj = a.mats[mj];
-        const int jx = cj % a.nx, jy = (cj / a.nx) % a.ny, jz = cj / (a.nx * a.ny);
-        const T rx = T(ix - jx) * a.l + (ux - a.s_in[W_UX * st + cj]);
-        const T ry = T(iy - jy) * a.l + (uy - a.s_in[W_UY * st + cj]);
-        const T rz = T(iz - jz) * a.l + (uz - a.s_in[W_UZ * st + cj]);
+        int jx, jy, jz;
+        unpack3(c.surf_ijk[j], jx, jy, jz);
+        T rx, ry, rz;
+        separation(c, a.l, oi, ix, iy, iz, oj, jx, jy, jz, ux - a.s_in[W_UX * st + cj], uy - a.s_in[W_UY * st + cj],
+                   uz - a.s_in[W_UZ * st + cj], rx, ry, rz);
         const T dist = dsqrt(rx * rx + ry * ry + rz * rz);
         const T ej = voxel_strain(a, (unsigned)cj, a.flags[cj], Mj.cte);
         const T cdist = T(0.5) * a.l * (T(1) + ei) + T(0.5) * a.l * (T(1) + ej);
@@ -337,37 +325,27 @@ __global__ void __launch_bounds__(256) k_contact(StepArgs<T> a, CollideArgs c, T
 
 template <typename T>
 __global__ void k_motion(StepArgs<T> a, CollideArgs c) {
-    const double v = __longlong_as_double((long long)*c.vmax_bits);
-    *c.vmax_bits = 0ull;
-    const double m = *c.macc + v * (double)a.dt;
-    *c.macc = m;
-    if (c.every || 2.0 * m >= c.threshold) *c.rebuild_flag = 1u;
+    motion_update(c.scalars, (double)a.dt);
 }
 
 }  // namespace
 
-size_t scan_temp_bytes(int n) { return (size_t)((n + kScanBlock - 1) / kScanBlock + 1) * sizeof(int); }
+int scan_blocks(int n) { return (n + kScanBlock - 1) / kScanBlock; }
 
 template <typename T>
 hipError_t launch_rebuild(const StepArgs<T> &a, const CollideArgs &c, hipStream_t s) {
     if (c.n_surf == 0) return hipSuccess;
-    Origin3 o;
-    o.v[0] = a.origin[0]; o.v[1] = a.origin[1]; o.v[2] = a.origin[2];
-    // grids of the per-voxel and per-bucket kernels, capped: they stride,
-    // and most launches only find the rebuild flag clear
+    // grids of the per-voxel kernels, capped: they stride, and most
+    // launches only find the rebuild flag clear
     const auto capped = [](long long n) { return (unsigned)std::min<long long>((n + 255) / 256, kCandGrid); };
     const unsigned gs = capped(c.n_surf);
-    const int nblk = (c.table_size + kScanBlock - 1) / kScanBlock;
-    k_keys<T><<<gs, 256, 0, s>>>(a, c, o);
-    k_scan_reduce<<<nblk, 256, 0, s>>>(c);
-    k_scan_blocks<<<1, 1024, 0, s>>>(c, nblk);
+    const int nblk = scan_blocks(c.table_size);
+    k_keys<T><<<gs, 256, 0, s>>>(a, c, nblk);
     k_scan_apply<<<nblk, 256, 0, s>>>(c);
     k_scatter<T><<<gs, 256, 0, s>>>(a, c);
     const int groups = (c.n_surf + kCandVox - 1) / kCandVox;
     const unsigned gc = (unsigned)(groups < kCandGrid ? groups : kCandGrid);
-    k_candidates<T><<<gc, 256, (size_t)kCandVox * c.cap * sizeof(int), s>>>(a, c);
-    k_rebuild_done<<<capped(c.table_size), 256, 0, s>>>(c);
-    k_rebuild_clear<<<1, 1, 0, s>>>(c);
+    k_candidates<T><<<gc, 256, (size_t)kCandVox * c.cap * sizeof(int), s>>>(a, c, nblk);
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // Device-side physics of one bond and one voxel update, templated on the
-// state precision.  Used by every step kernel (split and fused), so all
-// paths compute bit-identical per-bond and per-voxel results.
+// state precision.  Used by every step kernel (split and fused).  Each
+// kernel inlines its own copies, which the compiler may contract into FMAs
+// differently, so the paths agree to rounding rather than bitwise.
 #pragma once
 
 #include "vx_types.hpp"
@@ -313,11 +314,34 @@ VX_HD BondOut<T> bond_eval_xy(const VoxKin<T> &A, const Rot<T> &RA, const VoxKin
     return bond_core(A, B, du, d, ex, ey, ez, exm1, ey_a, ez_a, tx, ty, tz, K, C);
 }
 
-// FP32 evaluates the signal from the host-reduced phase 2 pi f t_n mod 2 pi.
+// Entry k of a per-channel table held in the step arguments (a select
+// chain, so that the table stays in scalar registers).
+template <typename T>
+VX_HD T chan_pick(const Chan8<T> &c, int k) {
+    // every member read at its fixed offset first: a conditional between two
+    // members would select between their addresses
+    const T v0 = c.v0, v1 = c.v1, v2 = c.v2, v3 = c.v3, v4 = c.v4, v5 = c.v5, v6 = c.v6, v7 = c.v7;
+    T r = v0;
+    if (k == 1) r = v1;
+    if (k == 2) r = v2;
+    if (k == 3) r = v3;
+    if (k == 4) r = v4;
+    if (k == 5) r = v5;
+    if (k == 6) r = v6;
+    if (k == 7) r = v7;
+    return r;
+}
+
+
+// Temperature of a voxel at t_n: its channel's, else its own signal, else
+// the global one.  FP32 evaluates its own signal from the host-reduced
+// phase 2 pi f t_n mod 2 pi; channel temperatures come from the host.
 template <typename T>
 VX_HD T voxel_strain(const StepArgs<T> &a, unsigned c, uint8_t fl, T cte) {
     T dT = a.dT_global;
-    if (fl & FLAG_ACT) {
+    if (fl & FLAG_CHAN) {
+        dT = chan_pick(a.chan_dT, ldc(a.chan, c));
+    } else if (fl & FLAG_ACT) {
         if constexpr (sizeof(T) == 8) {
             dT = ldc(a.act_amp, c) * dsin<T>(a.wt + ldc(a.act_phase, c));
         } else {
@@ -328,9 +352,17 @@ VX_HD T voxel_strain(const StepArgs<T> &a, unsigned c, uint8_t fl, T cte) {
 }
 
 // d eps / d phase and d eps / d amp of a voxel with its own actuation
-// signal (FLAG_ACT), at the same argument as voxel_strain.
+// signal (FLAG_ACT) or of its channel's (FLAG_CHAN), at the same argument
+// as voxel_strain.
 template <typename T>
-VX_HD void voxel_strain_d(const StepArgs<T> &a, unsigned c, T cte, T *d_phase, T *d_amp) {
+VX_HD void voxel_strain_d(const StepArgs<T> &a, const T *chan_dph, const T *chan_dam, unsigned c, uint8_t fl, T cte,
+                          T *d_phase, T *d_amp) {
+    if (fl & FLAG_CHAN) {
+        const int k = ldc(a.chan, c);
+        *d_phase = cte * chan_dph[k];
+        *d_amp = cte * chan_dam[k];
+        return;
+    }
     const T amp = ldc(a.act_amp, c);
     T sn, cs;
     if constexpr (sizeof(T) == 8) {
@@ -611,6 +643,37 @@ __device__ __forceinline__ void wave_vmax(unsigned long long *dst, T v) {
     if ((threadIdx.x & 63) == 0 && v > T(0)) {
         const double d = sqrt((double)v);
         atomicMax(dst, (unsigned long long)__double_as_longlong(d));
+    }
+}
+
+// Collision motion bookkeeping of one step, by one thread after every
+// voxel of the step is written: a rebuild that ran at the step's start
+// (flag still set) is closed, the largest speed of the step (read and
+// cleared) times dt is accumulated, and the flag is set for the next step
+// once twice the accumulated motion reaches the threshold (or always).
+__device__ __forceinline__ void motion_update(Scalars *sc, double dt) {
+    if (sc->rebuild_flag) {
+        sc->rebuild_flag = 0u;
+        sc->macc = 0.0;
+        sc->rebuilds += 1ull;
+    }
+    const double v = __longlong_as_double((long long)atomicExch(&sc->vmax_bits, 0ull));
+    const double acc = sc->macc + v * dt;
+    sc->macc = acc;
+    if (sc->every || 2.0 * acc >= sc->threshold) sc->rebuild_flag = 1u;
+}
+
+// The same from the last workgroup of a step kernel to finish: every thread
+// of every workgroup calls this once, after its state and speed updates;
+// thread 0 counts the workgroup in and, if it is the last, does the update
+// and resets the count.
+__device__ __forceinline__ void motion_last_workgroup(Scalars *sc, double dt) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0 && atomicAdd(&sc->done, 1u) == gridDim.x - 1) {
+        __threadfence();
+        motion_update(sc, dt);
+        sc->done = 0u;
     }
 }
 

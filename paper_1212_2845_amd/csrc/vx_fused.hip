@@ -152,11 +152,13 @@ struct Own {
     VoxKin<T> k;
 };
 
-// Per-workgroup copies of the material and material-pair tables.
+// Per-workgroup copies of the material and material-pair tables and of the
+// actuation channels' temperatures at t_n.
 template <typename T>
 struct Tables {
     const MatConst<T> *mat;   // n_mat entries
     const T *pair;            // n_mat^2 x 4: a1, a2, ct, -
+    const T *chan;            // kMaxChan entries
     int n_mat;
     __device__ __forceinline__ BondK<T> bond(int m1, int m2) const {
         const T *p = pair + 4 * (m1 * n_mat + m2);
@@ -166,6 +168,14 @@ struct Tables {
     }
 };
 
+// voxel_strain with the channel temperatures read from the workgroup's
+// table (the step arguments' copies are not kept in registers).
+template <typename T>
+__device__ __forceinline__ T strain_tb(const StepArgs<T> &a, const Tables<T> &tb, unsigned c, uint8_t fl, T cte) {
+    if (fl & FLAG_CHAN) return cte * tb.chan[ldc(a.chan, c)];
+    return voxel_strain(a, c, (uint8_t)(fl & ~FLAG_CHAN), cte);
+}
+
 template <typename T>
 __device__ __forceinline__ void load_own(const StepArgs<T> &a, const StateBuf<T> &sb, const Tables<T> &tb,
                                          unsigned c, Own<T> &o) {
@@ -174,7 +184,7 @@ __device__ __forceinline__ void load_own(const StepArgs<T> &a, const StateBuf<T>
         o.fl = ldc(a.flags, c);
         o.r = sb_load(sb, c);
         const MatConst<T> &mc = tb.mat[o.m];
-        o.eps = voxel_strain(a, c, o.fl, mc.cte);
+        o.eps = strain_tb(a, tb, c, o.fl, mc.cte);
         o.k = kin_of(o.r, mc, o.eps);
     }
 }
@@ -205,7 +215,7 @@ __device__ __forceinline__ void finish_pre(const StepArgs<T> &a, const Tables<T>
         o.fl = p.fl;
         o.r = p.r;
         const MatConst<T> &mc = tb.mat[p.m];
-        o.eps = voxel_strain(a, c, p.fl, mc.cte);
+        o.eps = strain_tb(a, tb, c, p.fl, mc.cte);
         o.k = kin_of(p.r, mc, o.eps);
     }
 }
@@ -229,14 +239,18 @@ __device__ __forceinline__ Tables<T> stage_tables(const StepArgs<T> &a, unsigned
         spair[4 * i + 2] = a.pairs[i].ct;
         spair[4 * i + 3] = T(0);
     }
+    T *schan = spair + 4 * np;
+    if ((int)threadIdx.x < kMaxChan) schan[threadIdx.x] = chan_pick(a.chan_dT, (int)threadIdx.x);
     tb.mat = smat;
     tb.pair = spair;
+    tb.chan = schan;
     return tb;
 }
 
 template <typename T>
 __host__ __device__ inline size_t tables_bytes(int n_mat) {
-    return ((n_mat * sizeof(MatConst<T>) + 15) & ~(size_t)15) + (size_t)n_mat * n_mat * 4 * sizeof(T);
+    return ((n_mat * sizeof(MatConst<T>) + 15) & ~(size_t)15) + (size_t)n_mat * n_mat * 4 * sizeof(T) +
+           kMaxChan * sizeof(T);
 }
 
 // One column of cells: the TX x TY tile (tile_x, tile_y) of lattice a,
@@ -440,6 +454,11 @@ k_fused(StepArgs<T> a, FusedGrid g) {
     T vmax = T(0);
     march(a, sm, tb, C, TX, TY, tile_x, tile_y, z0, z1, vmax);
     if (a.track_vmax) wave_vmax(a.vmax_bits, vmax);
+    // FP32 only: the FP64 kernel, at its register limit, keeps the separate
+    // bookkeeping launch
+    if constexpr (sizeof(T) == 4) {
+        if (a.motion) motion_last_workgroup(a.motion, (double)a.dt);
+    }
 }
 
 // Largest runtime tile of the batched kernel: TX, TY <= 64, TX * TY <= 256,
@@ -476,6 +495,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchArgs<T> b) {
             a.mat = b.base.mat + ob.off;
             a.flags = b.flags[p] + ob.off;
             a.flags_out = b.flags[1 - p] + ob.off;
+            if (a.contact_F) a.contact_F = b.base.contact_F + ob.off;
             a.nx = ob.nx; a.ny = ob.ny; a.nz = ob.nz;
             a.dt = ob.dt;
             a.origin_z = ob.origin_z;
@@ -490,6 +510,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchArgs<T> b) {
         // this step's writes are the next step's reads (same workgroup)
         __syncthreads();
     }
+    if (b.base.track_vmax) wave_vmax(b.base.vmax_bits, vmax);
 }
 
 template <typename T, int TX, int TY>

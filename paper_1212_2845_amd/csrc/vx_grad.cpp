@@ -122,6 +122,7 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
             g.g_rho = (double *)(gw + G.grho);
             g.g_phase = (double *)(gw + G.gphase);
             g.g_amp = (double *)(gw + G.gamp);
+            set_chan_derivs(g.chan_dph, g.chan_dam, h, s0 + i);
             HIP_OK(h, launch_adjoint_step<T>(a, g, s));
             li = 1 - li;
         }
@@ -144,6 +145,17 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
     HIP_OK(h, hipMemcpyAsync(&sc, h->ws + h->L.scalars, sizeof(sc), hipMemcpyDeviceToHost, s));
     HIP_OK(h, hipStreamSynchronize(s));
     if (sc.err_flag) return fail(h, VX_EUNSTABLE, "non-finite value in the voxel state");
+    // channel voxels: their terms summed per channel in cell order, and
+    // zero in the per-voxel outputs
+    h->chan_gphase.assign(h->chans.size(), 0.0);
+    h->chan_gamp.assign(h->chans.size(), 0.0);
+    for (long long c = 0; c < n; ++c) {
+        if (!h->grid[c] || h->cell_chan[c] < 0) continue;
+        h->chan_gphase[h->cell_chan[c]] += gp[c];
+        h->chan_gamp[h->cell_chan[c]] += ga[c];
+        gp[c] = ga[c] = 0.0;
+    }
+    h->chan_grad_valid = true;
     for (long long c = 0; c < n; ++c) {
         const bool f = h->grid[c] != 0;
         if (g_E) g_E[c] = f ? gE[c] : 0.0;
@@ -251,6 +263,17 @@ int vx_grad_backward(vx_handle h, const double *dL_du, const double *dL_dq, cons
                                          g_w0)
                : grad_backward_t<float>(h, dL_du, dL_dq, dL_dv, dL_dw, g_E, g_rho, g_phase, g_amp, g_u0, g_q0, g_v0,
                                         g_w0);
+}
+
+int vx_grad_channels(vx_handle h, double *g_phase, double *g_amp) {
+    if (!h) return VX_EINVAL;
+    if (!h->chan_grad_valid || h->chan_gphase.size() != h->chans.size())
+        return fail(h, VX_ESTATE, "vx_grad_channels before vx_grad_backward with the current channels");
+    for (size_t k = 0; k < h->chans.size(); ++k) {
+        if (g_phase) g_phase[k] = h->chan_gphase[k];
+        if (g_amp) g_amp[k] = h->chan_gamp[k];
+    }
+    return VX_OK;
 }
 
 }  // extern "C"

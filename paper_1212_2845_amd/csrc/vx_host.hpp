@@ -12,6 +12,14 @@
 
 namespace vx {
 
+// Rest indices (x, y, z) of a voxel within its object packed as the
+// collision kernels read them: 21 bits per axis, each offset by 2^20.
+inline long long pack_ijk(int x, int y, int z) {
+    const unsigned long long m = 0x1FFFFFull, b = 1ull << 20;
+    return (long long)((((unsigned long long)(x + (int)b)) & m) | ((((unsigned long long)(y + (int)b)) & m) << 21) |
+                       ((((unsigned long long)(z + (int)b)) & m) << 42));
+}
+
 // Composite of two moduli: springs of half length in series (Eq. 1, 2).
 inline double composite(double a, double b) { return 2.0 * a * b / (a + b); }
 

@@ -21,6 +21,8 @@ struct AdjArgs {
     T *gfm;                 // adjoint of the bond sums, 6 words
     T *gloc;                // update's adjoints of the strain, modulus and mass, 3 words
     double *g_E, *g_rho, *g_phase, *g_amp;   // accumulated over the reverse steps
+    Chan8<T> chan_dph;      // each channel's temperature derivative w.r.t. its phase, at t_n
+    Chan8<T> chan_dam;      // and w.r.t. its amplitude
 };
 
 template <typename T>
@@ -120,51 +122,62 @@ hipError_t launch_batch(const BatchArgs<T> &b, int n_wg, hipStream_t s);
 // Largest number of collision candidates per voxel (vx_params.contact_cap).
 constexpr int kMaxContactCap = 1024;
 
-// Collision support (self-collision on).
+// Collision support (self-collision on).  The voxels taking part are
+// listed once (surface voxels, or all filled ones) with what the search
+// needs that never changes: state index, object and packed rest indices
+// within the object.  A single lattice is one object; a batch with contact
+// has many, placed by their origins in one world.
 struct CollideArgs {
-    const int *surf_cells;       // cells taking part (surface voxels, or all filled ones), ascending
+    const int *surf_cells;       // n_surf state indices (cells), ascending within each object
+    const int *surf_obj;         // n_surf object ids
+    const long long *surf_ijk;   // n_surf packed rest indices within the object (21 bits per axis)
+    const double *obj_origin;    // 3 per object: world position of the object's cell (0,0,0) lower corner
     int n_surf;
-    int every;                   // 1: rebuild the candidates before every step
-    int cap;                     // candidate slots per surface voxel
-    int *cand;                   // n_surf x cap partner cells, ascending
+    int cap;                     // candidate slots per voxel
+    int *cand;                   // n_surf x cap partner list indices, ascending
     int *cand_n;                 // n_surf
     unsigned *overflow;          // set when a list overflows
     unsigned *rebuild_flag;      // device flag: 1 = rebuild before next step
+    unsigned *done;              // workgroups finished (last-workgroup hand-offs), 0 between launches
     double *macc;                // accumulated maximum motion
     unsigned long long *vmax_bits;
-    int *cell_keys;              // n_surf hashed cell keys
+    int *cell_keys;              // n_surf hashed grid-cell keys
     long long *cell_gc;          // n_surf packed grid cells (21 bits per axis)
-    long long *cell_ijk;         // n_surf packed rest indices (21 bits per axis)
-    // the entries of every bucket, in bucket order: cell, packed grid cell,
-    // packed rest indices, and displacement (3 arrays of n_surf values of
-    // the state precision), so that the candidate search reads each entry
-    // with independent loads
-    int *sorted_cell;
+    // the entries of every bucket, in bucket order: list index, packed grid
+    // cell, packed rest indices, object, and displacement (3 arrays of
+    // n_surf values of the state precision), so that the candidate search
+    // reads each entry with independent loads
+    int *sorted_idx;
     long long *sorted_gc;
     long long *sorted_ijk;
+    int *sorted_obj;
     void *sorted_u;
     int *bucket_start;           // table_size + 1
-    int *bucket_fill;            // table_size (scratch counters)
+    int *bucket_fill;            // table_size: counts, then scatter cursors; zero between rebuilds
+    int *block_sum;              // scan blocks: bucket counts per block, then their exclusive prefix;
+                                 // zero between rebuilds
     int table_size;              // power of two
     unsigned long long *pair_count;  // total candidate entries
     double horizon;              // 2 l
-    double threshold;            // rebuild when 2 * macc >= threshold (= horizon - c_max)
-    void *scan_tmp;              // block sums of the bucket scan
-    size_t scan_tmp_bytes;
     unsigned long long *rebuild_counter;
+    Scalars *scalars;            // the block the fields above point into (motion bookkeeping)
 };
 
-// Bytes of scratch the bucket scan needs for a table of n entries.
-size_t scan_temp_bytes(int n);
+// Scan blocks of a bucket table of n entries.
+int scan_blocks(int n);
 
 // Rebuild the candidate lists from the state a.s_in if the device rebuild
-// flag is set; every kernel of the chain exits at once otherwise.
+// flag is set; every kernel of the chain exits at once otherwise.  The
+// flag stays set until the step's motion update clears it.
 template <typename T>
 hipError_t launch_rebuild(const StepArgs<T> &a, const CollideArgs &c, hipStream_t s);
 
 template <typename T>
 hipError_t launch_contact(const StepArgs<T> &a, const CollideArgs &c, T *contact_F, hipStream_t s);
 
+// Motion bookkeeping after a step (one thread): closes a rebuild that ran
+// at the step's start, accumulates max|v| dt, sets the rebuild flag.  The
+// fused step kernel does the same in its last workgroup when a.mo.on.
 template <typename T>
 hipError_t launch_motion_update(const StepArgs<T> &a, const CollideArgs &c, hipStream_t s);
 

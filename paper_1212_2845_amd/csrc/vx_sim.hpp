@@ -21,9 +21,9 @@ constexpr uint64_t kAlign = 256;
 inline uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t state[2], mat, flags[2], mats, pairs, bonds, act_amp, act_phase, forced_cells, forced_F;
-    uint64_t contact_F, surf_cells, cand, cand_n, keys, gc, ijk, sorted, sgc, sijk, su, bstart, bfill, scalars,
-        scan_tmp;
+    uint64_t state[2], mat, flags[2], mats, pairs, bonds, act_amp, act_phase, chan, forced_cells, forced_F;
+    uint64_t contact_F, surf_cells, surf_obj, surf_ijk, obj_origin, cand, cand_n, keys, gc, sorted, sgc, sijk,
+        sobj, su, bstart, bfill, block_sum, scalars;
     uint64_t E_cell, rho_cell;
     uint64_t energy;
     uint64_t total;
@@ -45,17 +45,6 @@ struct GradLayout {
     uint64_t total;
 };
 
-// Small device-side scalars, one 256-byte block.
-struct Scalars {
-    unsigned err_flag;
-    unsigned overflow;
-    unsigned rebuild_flag;
-    unsigned pad0;
-    unsigned long long vmax_bits;
-    double macc;
-    unsigned long long pair_count;
-    unsigned long long rebuilds;
-};
 
 
 }  // namespace vx
@@ -74,6 +63,12 @@ struct vx_sim {
     std::vector<uint8_t> grid, flags;
     std::vector<double> amp, phase;      // per cell; valid where FLAG_ACT
     bool has_act = false;
+    // named actuation channels and each cell's channel (-1: none)
+    std::vector<vx_channel> chans;
+    std::vector<int8_t> cell_chan;
+    // per-channel gradients of the last reverse run
+    std::vector<double> chan_gphase, chan_gamp;
+    bool chan_grad_valid = false;
     std::vector<double> force;           // ncell x 3 (host copy)
     std::vector<int> forced_cells;
     std::vector<double> forced_F;
@@ -90,7 +85,6 @@ struct vx_sim {
     int kernel_kind = 0;
     int cand_cap = 32;
     int table_size = 1;
-    size_t scan_tmp_bytes = 0;
     double cmax = 0.0;
     // initial state in double, 13 x ncell (used until bind)
     std::vector<double> state0;
@@ -135,6 +129,29 @@ inline int fail(vx_sim *h, int code, const std::string &msg) {
             return fail(h, VX_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// A channel's waveform at phase angle theta and its derivative with
+// respect to theta.  Triangle and square are in phase with the sine: the
+// triangle rises from 0 to its peak over the first quarter period, the
+// square is +1 over the first half period.
+inline void channel_wave(int waveform, double theta, double *w, double *dw) {
+    if (waveform == VX_WAVE_SINE) {
+        *w = std::sin(theta);
+        *dw = std::cos(theta);
+        return;
+    }
+    const double turns = theta / (2.0 * vx::kPi);
+    const double x = turns - std::floor(turns);   // position in the period, [0, 1)
+    if (waveform == VX_WAVE_TRIANGLE) {
+        const double slope = 4.0 / (2.0 * vx::kPi);   // 4 per period, per radian
+        if (x < 0.25) { *w = 4.0 * x; *dw = slope; }
+        else if (x < 0.75) { *w = 2.0 - 4.0 * x; *dw = -slope; }
+        else { *w = 4.0 * x - 4.0; *dw = slope; }
+        return;
+    }
+    *w = x < 0.5 ? 1.0 : -1.0;
+    *dw = 0.0;
+}
+
 // Time-dependent fields of the step arguments at step index n (t_n = n dt).
 template <typename T>
 inline void set_step_time(vx::StepArgs<T> &a, const vx_sim *h, long long n) {
@@ -143,6 +160,28 @@ inline void set_step_time(vx::StepArgs<T> &a, const vx_sim *h, long long n) {
     a.wt = wt;
     a.wt_red = (T)std::fmod(wt, 2.0 * vx::kPi);
     a.dT_global = (T)(h->p.temp_amp * std::sin(wt + h->p.temp_phase));
+    a.chan_dT = vx::Chan8<T>{};
+    for (int k = 0; k < (int)h->chans.size() && k < vx::kMaxChan; ++k) {
+        const vx_channel &c = h->chans[k];
+        double w, dw;
+        channel_wave(c.waveform, 2.0 * vx::kPi * c.freq * tn + c.phase, &w, &dw);
+        vx::chan_set(a.chan_dT, k, (T)(c.offset + c.amp * w));
+    }
+}
+
+// The channels' temperature derivatives at step index n, for the reverse
+// step: with respect to each channel's phase and amplitude.
+template <typename T>
+inline void set_chan_derivs(vx::Chan8<T> &dph, vx::Chan8<T> &dam, const vx_sim *h, long long n) {
+    const double tn = (double)n * h->dt;
+    dph = dam = vx::Chan8<T>{};
+    for (int k = 0; k < (int)h->chans.size() && k < vx::kMaxChan; ++k) {
+        const vx_channel &c = h->chans[k];
+        double w, dw;
+        channel_wave(c.waveform, 2.0 * vx::kPi * c.freq * tn + c.phase, &w, &dw);
+        vx::chan_set(dph, k, (T)(c.amp * dw));
+        vx::chan_set(dam, k, (T)w);
+    }
 }
 
 template <typename T>
@@ -167,6 +206,7 @@ inline vx::StepArgs<T> make_args(vx_sim *h) {
     set_step_time(a, h, h->step);
     a.act_amp = (const T *)(ws + h->L.act_amp);
     a.act_phase = (const T *)(ws + h->L.act_phase);
+    a.chan = (const uint8_t *)(ws + h->L.chan);
     a.forced_cells = (const int *)(ws + h->L.forced_cells);
     a.forced_F = (const T *)(ws + h->L.forced_F);
     a.n_forced = (int)h->forced_cells.size();
@@ -190,31 +230,37 @@ inline vx::CollideArgs make_collide(vx_sim *h) {
     CollideArgs c{};
     char *ws = h->ws;
     c.surf_cells = (const int *)(ws + h->L.surf_cells);
+    c.surf_obj = (const int *)(ws + h->L.surf_obj);
+    c.surf_ijk = (const long long *)(ws + h->L.surf_ijk);
+    c.obj_origin = (const double *)(ws + h->L.obj_origin);
     c.n_surf = (int)h->coll_cells.size();
-    c.every = h->coll_every ? 1 : 0;
     c.cap = h->cand_cap;
     c.cand = (int *)(ws + h->L.cand);
     c.cand_n = (int *)(ws + h->L.cand_n);
     Scalars *sc = (Scalars *)(ws + h->L.scalars);
     c.overflow = &sc->overflow;
     c.rebuild_flag = &sc->rebuild_flag;
+    c.done = &sc->done;
     c.macc = &sc->macc;
     c.vmax_bits = &sc->vmax_bits;
     c.cell_keys = (int *)(ws + h->L.keys);
     c.cell_gc = (long long *)(ws + h->L.gc);
-    c.cell_ijk = (long long *)(ws + h->L.ijk);
-    c.sorted_cell = (int *)(ws + h->L.sorted);
+    c.sorted_idx = (int *)(ws + h->L.sorted);
     c.sorted_gc = (long long *)(ws + h->L.sgc);
     c.sorted_ijk = (long long *)(ws + h->L.sijk);
+    c.sorted_obj = (int *)(ws + h->L.sobj);
     c.sorted_u = (void *)(ws + h->L.su);
     c.bucket_start = (int *)(ws + h->L.bstart);
     c.bucket_fill = (int *)(ws + h->L.bfill);
+    c.block_sum = (int *)(ws + h->L.block_sum);
     c.table_size = h->table_size;
     c.pair_count = &sc->pair_count;
     c.horizon = 2.0 * h->p.voxel_size;
-    c.threshold = 2.0 * h->p.voxel_size - h->cmax;
-    c.scan_tmp = (void *)(ws + h->L.scan_tmp);
-    c.scan_tmp_bytes = h->scan_tmp_bytes;
     c.rebuild_counter = &sc->rebuilds;
+    c.scalars = sc;
     return c;
 }
+
+// The device scalars the fused kernel's last workgroup updates in a real
+// step with self-collision.
+inline vx::Scalars *step_motion(vx_sim *h) { return (Scalars *)(h->ws + h->L.scalars); }

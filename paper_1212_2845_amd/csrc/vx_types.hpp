@@ -14,7 +14,27 @@ enum : uint8_t {
     FLAG_FORCED = 1u << 3,   // has a constant external force
     FLAG_CAND = 1u << 4,     // has collision candidates (contact force buffer valid)
     FLAG_ACT = 1u << 5,      // own actuation amplitude/phase
+    FLAG_CHAN = 1u << 6,     // follows a named actuation channel
 };
+
+// Named actuation channels per lattice.
+constexpr int kMaxChan = 8;
+
+// One value per channel, as scalar members: the step arguments are copied
+// and modified inside kernels, and an array member would keep such a copy
+// in private memory.
+template <typename T>
+struct Chan8 {
+    T v0, v1, v2, v3, v4, v5, v6, v7;
+};
+
+template <typename T>
+inline void chan_set(Chan8<T> &c, int k, T x) {
+    switch (k) {
+        case 0: c.v0 = x; break; case 1: c.v1 = x; break; case 2: c.v2 = x; break; case 3: c.v3 = x; break;
+        case 4: c.v4 = x; break; case 5: c.v5 = x; break; case 6: c.v6 = x; break; default: c.v7 = x; break;
+    }
+}
 
 // State words of one voxel, stored structure-of-arrays: word k of cell c is
 // at base[k * stride + c].  Displacement from the rest position (not the
@@ -51,6 +71,21 @@ struct PairConst {
     T pad;
 };
 
+// Small device-side scalars, one 256-byte block.
+struct Scalars {
+    unsigned err_flag;
+    unsigned overflow;
+    unsigned rebuild_flag;
+    unsigned done;               // last-workgroup hand-off counter, 0 between launches
+    unsigned long long vmax_bits;
+    double macc;
+    unsigned long long pair_count;
+    unsigned long long rebuilds;
+    double threshold;            // rebuild once 2 macc >= threshold (horizon - c_max)
+    unsigned every;              // 1: rebuild before every step
+};
+
+
 // Everything a step kernel needs, passed by value.
 template <typename T>
 struct StepArgs {
@@ -74,6 +109,8 @@ struct StepArgs {
     T wt_red;                  // 2 pi f t_n reduced to [0, 2 pi)
     const T *act_amp;          // per cell, used where FLAG_ACT
     const T *act_phase;
+    const uint8_t *chan;       // per cell, channel index, used where FLAG_CHAN
+    Chan8<T> chan_dT;          // temperature of each channel at t_n
     const int *forced_cells;   // sorted
     const T *forced_F;         // n_forced x 3
     int n_forced;
@@ -87,6 +124,7 @@ struct StepArgs {
     const T *rho_cell;         // parameter mode: per-cell density (set whenever E_cell is)
     T *fm_out;                 // split gather: per-voxel bond force and moment sums (6 x ncell), or null
     T zeta_bond, zeta_slow, zeta_col;
+    Scalars *motion;           // collision bookkeeping by the step's last workgroup, or null
 };
 
 }  // namespace vx

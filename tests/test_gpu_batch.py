@@ -184,3 +184,28 @@ def test_full_size_batch_sampled_against_oracle():
         uo = np.linalg.norm(ref["u"][filled], axis=1).max()
         e = compare(got, ref, filled)
         assert abs(ug / uo - 1.0) < 1e-4 and e["u"] < 1e-3, (i, sizes[i], ug, uo, e)
+
+
+def test_autotune_failure_restores_batch():
+    """A trial run that goes unstable (bond damping far above 1) makes the
+    autotuner return VX_EUNSTABLE with the state, the step count and the
+    status flags as they were before the call."""
+    g = np.ones((6, 6, 6), np.uint8)
+    grids = [g, g]
+    announce("batch autotune failure")
+    b = vx.Batch(grids, [workloads.EMPTY, workloads._mat(1e6)], precision=64,
+                 **workloads._base_params(zeta_bond=3.0))
+    b.bind()
+    for i in range(2):
+        st = perturbed_state(g.size, 310 + i, 1e-7, 1e-4, 0.0, 0.0)
+        b.write_state(i, u=st["u"], v=st["v"])
+    before = [b.read_state(i) for i in range(2)]
+    with pytest.raises(vx.VoxsimError) as e:
+        b.autotune(steps=3000)
+    assert e.value.code == vx.VX_EUNSTABLE
+    assert b.counters()["steps"] == 0
+    for i in range(2):
+        after = b.read_state(i)
+        for k in ("u", "q", "v", "w"):
+            assert np.array_equal(after[k], before[i][k]), (i, k)
+    b.step(1)          # the sticky status flag was restored too: one step is fine

@@ -1,0 +1,188 @@
+"""Parity at sizes that span many tiles, z chunks and collision buckets.
+
+* The floor-impact block (cells iid empty / 1 MPa / 100 MPa, bottom faces on
+  the floor moving down at the speed of a 5 mm drop, Coulomb friction) at
+  40^3 for 1000 steps through the fused kernel, with a forced multi-tile
+  shape and short z chunks and with an autotuned tile: FP64 within 1e-10 of
+  the oracle, FP32 largest displacement within 1e-4, static-friction flags
+  equal.
+* Self-collision with live contacts: 48 free bodies of 3^3 to 5^3 voxels in
+  approaching pairs (section Self collision detection and handling): FP64
+  within 1e-10 of the oracle after 1000 steps, the same candidate pairs
+  while they are most numerous and at the end, the same rebuild counts.
+* A candidate list longer than contact_cap: both sides report the overflow.
+* Momentum of a free body over a lattice that spans several tiles and z
+  chunks, for every fused tile shape (the bonds entering a tile from its
+  ring are evaluated by both neighbouring tiles)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1212_2845_amd as vx
+import workloads
+from parity import build_gpu, build_oracle, compare, perturbed_state
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+FP32_MAXDISP_TOL = 1e-4
+
+
+def announce(msg):
+    print("[case] " + msg, flush=True)
+
+
+def filled_of(w):
+    return w["grid"].reshape(-1) > 0
+
+
+_IMPACT = {}
+
+
+def _impact_ref():
+    if not _IMPACT:
+        w = workloads.random_block(n=40, seed=2, impact=True)
+        o = build_oracle(w)
+        assert o.step(1000) == 0
+        _IMPACT["w"], _IMPACT["ref"], _IMPACT["static"] = w, o.read_state(), o.read_flags()["static"]
+    return _IMPACT["w"], _IMPACT["ref"], _IMPACT["static"]
+
+
+@pytest.mark.parametrize("tile", [(0, 4), (3, 7), None])
+def test_floor_impact_40_cubed_1000_steps_fp64(tile):
+    """tile = (shape index, z chunk): 32x8 tiles (2 x 5 per slab, ragged in
+    x) in 10 chunks of 4 slabs; 50x5 (one ragged tile in x, 8 in y) in
+    chunks of 7 with a short last chunk; None: autotuned."""
+    w, ref, static = _impact_ref()
+    announce("floor impact 40^3 fp64 1000 steps tile=%s" % (tile,))
+    g = build_gpu(w, precision=64, kernel=vx.KERNEL_FUSED)
+    if tile is None:
+        g.autotune(iters=1)
+    else:
+        g.set_fused_tile(*tile)
+    got = g.fused_tile()
+    print("[tile]", got, flush=True)
+    if tile is not None:
+        assert got["zc"] == tile[1]
+    g.step(1000)
+    st = g.read_state()
+    e = compare(st, ref, filled_of(w))
+    print(e, flush=True)
+    assert max(e["u"], e["v"], e["w"]) < FP64_TOL and e["q"] < 1e-12, e
+    f = filled_of(w)
+    gs = g.read_flags()["static"]
+    assert np.array_equal(gs[f], static[f])
+    # the block has settled on the floor with part of its bottom layer held
+    # by static friction
+    assert 0 < static[f].sum() < f.sum()
+
+
+def test_floor_impact_40_cubed_1000_steps_fp32():
+    w, ref, static = _impact_ref()
+    announce("floor impact 40^3 fp32 1000 steps")
+    g = build_gpu(w, precision=32, kernel=vx.KERNEL_FUSED)
+    g.set_fused_tile(0, 4)
+    g.step(1000)
+    st = g.read_state()
+    f = filled_of(w)
+    ug = np.linalg.norm(st["u"][f], axis=1).max()
+    uo = np.linalg.norm(ref["u"][f], axis=1).max()
+    print(ug, uo, abs(ug / uo - 1.0), flush=True)
+    assert abs(ug / uo - 1.0) < FP32_MAXDISP_TOL
+
+
+_BODIES = {}
+
+
+def _bodies_ref():
+    if not _BODIES:
+        w, bodies = workloads.colliding_bodies()
+        o = build_oracle(w)
+        _BODIES["ke0"] = o.energy()["ke"]
+        assert o.step(600) == 0
+        _BODIES["mid"] = (o.candidates(), o.rebuilds)
+        assert o.step(400) == 0
+        _BODIES["w"], _BODIES["bodies"] = w, bodies
+        _BODIES["end"] = (o.candidates(), o.rebuilds, o.read_state())
+        _BODIES["ke1"] = o.energy()["ke"]
+    return _BODIES
+
+
+@pytest.mark.parametrize("kernel", [vx.KERNEL_FUSED, vx.KERNEL_SPLIT])
+def test_colliding_bodies_1000_steps_fp64(kernel):
+    r = _bodies_ref()
+    w = r["w"]
+    f = filled_of(w)
+    assert len(r["bodies"]) == 48
+    announce("48 colliding bodies fp64 kernel=%d" % kernel)
+    g = build_gpu(w, precision=64, kernel=kernel)
+    surf = g.read_flags()["surface"]
+    assert surf[f].sum() >= 1000
+    g.step(600)
+    cand_mid, reb_mid = r["mid"]
+    assert len(cand_mid) >= 100
+    assert g.candidates() == cand_mid
+    assert g.counters()["rebuilds"] == reb_mid
+    g.step(400)
+    cand_end, reb_end, ref = r["end"]
+    assert g.candidates() == cand_end
+    assert g.counters()["rebuilds"] == reb_end
+    e = compare(g.read_state(), ref, f)
+    print(e, len(cand_mid), len(cand_end), reb_end, flush=True)
+    assert max(e["u"], e["v"], e["w"]) < FP64_TOL and e["q"] < 1e-12, e
+    # the bodies met: contact damping took more than a quarter of the
+    # kinetic energy
+    assert r["ke1"] < 0.75 * r["ke0"]
+
+
+def test_candidate_overflow_reported_by_both():
+    """Two cubes pushed into each other with room for one candidate per
+    voxel: the GPU step returns VX_EOVERFLOW and the oracle VXO_EOVERFLOW."""
+    n, gap = 3, 3
+    nx = 2 * n + gap
+    grid = np.zeros((n, n, nx), np.uint8)
+    grid[:, :, :n] = 1
+    grid[:, :, n + gap:] = 1
+    x, _, _ = workloads.cell_coords(grid.shape)
+    v = np.zeros((grid.size, 3))
+    v[x < n, 0] = 3.0
+    v[x >= n + gap, 0] = -3.0
+    params = workloads._base_params(zeta_bond=0.5, zeta_col=0.5, self_collision_on=1, contact_cap=1)
+    announce("candidate overflow")
+    g = vx.Sim(grid, [workloads.EMPTY, workloads._mat(1e6)], precision=64, **params)
+    g.set_velocity(v)
+    o = oracle.Sim(grid, [workloads.EMPTY, workloads._mat(1e6)], **params)
+    o.set_velocity(v)
+    rc_o = rc_g = 0
+    for _ in range(40):
+        rc_o = rc_o or o.step(25)
+        rc_g = rc_g or g.step_rc(25)
+        if rc_o and rc_g:
+            break
+    assert rc_o == oracle.VXO_EOVERFLOW
+    assert rc_g == vx.VX_EOVERFLOW
+
+
+@pytest.mark.parametrize("shape_id", range(len(vx.FUSED_SHAPES)))
+def test_momentum_conserved_across_tiles(shape_id):
+    """A free body (bond damping on; no gravity, floor, ground damping or
+    fixed voxels) on a 70 x 30 x 40 lattice, several tiles in x and y and
+    z chunks of 6: total linear momentum stays constant to the bar the
+    oracle meets (1e-13 of the momentum scale over 1000 steps)."""
+    mats = workloads.random_materials(3, seed=21, cte_max=0.01)
+    g = workloads.random_grid((40, 30, 70), 3, 0.9, 22)
+    w = workloads._workload(g, mats, workloads._base_params(zeta_bond=0.3, temp_amp=10.0, temp_freq=300.0),
+                            1000)
+    w["state"] = perturbed_state(g.size, 23, 1e-6, 1e-3, 0.5, 1e-3)
+    announce("momentum across tiles shape=%s" % (vx.FUSED_SHAPES[shape_id],))
+    s = build_gpu(w, precision=64, kernel=vx.KERNEL_FUSED)
+    s.set_fused_tile(shape_id, 6)
+    e0 = s.energy()
+    P0 = np.array(e0["momentum"])
+    st = s.read_state()
+    m = 1e-6 * np.array([mm["rho"] for mm in mats])[g.reshape(-1)]
+    scale = np.sum(m[:, None] * np.abs(st["v"]))
+    s.step(1000)
+    P1 = np.array(s.energy()["momentum"])
+    print(P0, P1, np.abs(P1 - P0).max() / scale, flush=True)
+    assert np.abs(P1 - P0).max() <= 1e-13 * scale

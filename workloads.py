@@ -77,16 +77,16 @@ def thin_beam(nx=20, rho=1.0, zeta_bond=0.01, tip_velocity=1e-3, steps=820000):
 
 def random_block(n=100, seed=2, steps=1000, drop_height=5e-3, impact=False):
     """n^3 cells iid {empty 0.1, soft 1 MPa 0.45, stiff 100 MPa 0.45} on a floor
-    with friction.  ``impact=False``: the bottom layer's centres at
-    ``drop_height``, at rest.  ``impact=True``: the bottom faces on the floor,
-    moving down at the speed of a ``drop_height`` free fall."""
+    with friction.  ``impact=False``: the bottom faces at ``drop_height``
+    above the floor, at rest.  ``impact=True``: the bottom faces on the
+    floor, moving down at the speed of a ``drop_height`` free fall."""
     rng = np.random.Generator(np.random.PCG64(seed))
     grid = rng.choice(np.array([0, 1, 2], np.uint8), size=(n, n, n), p=[0.1, 0.45, 0.45])
     mats = [EMPTY, _mat(1e6), _mat(1e8)]
     g = 9.81
     l = 1e-3
-    # origin = centre of cell (0, 0, 0); its bottom face lies half a voxel lower
-    z0 = 0.5 * l if impact else drop_height
+    # origin = lower corner of cell (0, 0, 0), i.e. the height of the bottom faces
+    z0 = 0.0 if impact else drop_height
     params = _base_params(gravity=g, zeta_bond=0.5, zeta_col=0.5, floor_on=1, origin=(0.0, 0.0, z0))
     vel = None
     if impact:
@@ -318,3 +318,60 @@ def design_lattice(count=64, size=20, gap=1, seed=5, steps=5000):
     w["E"] = E
     w["logits"] = logits
     return w
+
+
+def colliding_bodies(pairs=(2, 4, 3), seed=7, speed=1.5, steps=1000, lo=3, hi=5, gap=3, slot_yz=9,
+                     n_mat=2, spin=50.0, lateral=0.1):
+    """Free bodies in approaching pairs: pair slots on a px x py x pz grid,
+    each pair two boxes with sides drawn uniformly from lo..hi cells, facing
+    each other along x across ``gap`` empty cells and moving towards each
+    other at +-speed m/s (plus a seeded lateral velocity of up to
+    lateral x speed and a spin of up to ``spin`` rad/s per body).  Cells
+    are iid over n_mat materials (E 1 and 5 MPa).  Every two voxels of
+    different bodies are more than 3 cells apart in lattice Manhattan
+    distance.  No gravity, no floor, self-collision on.
+
+    Returns the workload and a list of bodies (x0, y0, z0, sx, sy, sz) in
+    lattice cells."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    px, py, pz = pairs
+    slot_x = 2 * hi + gap + 4          # pair plus a margin of 4 cells
+    nx, ny, nz = px * slot_x, py * slot_yz, pz * slot_yz
+    grid = np.zeros((nz, ny, nx), np.uint8)
+    vel = np.zeros((grid.size, 3))
+    w_init = np.zeros((grid.size, 3))
+    bodies = []
+    E = [1e6, 5e6][:n_mat]
+    for k in range(pz):
+        for j in range(py):
+            for i in range(px):
+                xa = i * slot_x + 2
+                sa = rng.integers(lo, hi + 1, size=3)
+                sb = rng.integers(lo, hi + 1, size=3)
+                # body a ends at x = xa + hi - 1, body b starts gap cells later
+                xa0 = xa + hi - sa[0]
+                xb0 = xa + hi + gap
+                for (x0, s, sign) in ((xa0, sa, 1.0), (xb0, sb, -1.0)):
+                    y0 = j * slot_yz + int(rng.integers(0, slot_yz - 4 - s[1] + 1))
+                    z0 = k * slot_yz + int(rng.integers(0, slot_yz - 4 - s[2] + 1))
+                    blk = rng.integers(1, n_mat + 1, size=(s[2], s[1], s[0])).astype(np.uint8)
+                    grid[z0:z0 + s[2], y0:y0 + s[1], x0:x0 + s[0]] = blk
+                    v = np.array([sign * speed, 0.0, 0.0]) + rng.uniform(-lateral, lateral, 3) * speed
+                    om = rng.uniform(-spin, spin, 3)
+                    cells = (np.arange(z0, z0 + s[2])[:, None, None] * ny + np.arange(y0, y0 + s[1])[None, :, None]) * nx \
+                        + np.arange(x0, x0 + s[0])[None, None, :]
+                    cells = cells.reshape(-1)
+                    # rigid-body velocity field about the body's centre
+                    cx, cy, cz = x0 + (s[0] - 1) / 2, y0 + (s[1] - 1) / 2, z0 + (s[2] - 1) / 2
+                    xs, ys, zs = cell_coords(grid.shape)
+                    r = np.stack([xs[cells] - cx, ys[cells] - cy, zs[cells] - cz], 1) * 1e-3
+                    vel[cells] = v + np.cross(om, r)
+                    w_init[cells] = om
+                    bodies.append((int(x0), int(y0), int(z0), int(s[0]), int(s[1]), int(s[2])))
+    mats = [EMPTY] + [_mat(e) for e in E]
+    params = _base_params(zeta_bond=0.5, zeta_col=0.5, self_collision_on=1, contact_cap=64)
+    w = _workload(grid, mats, params, steps, name="colliding_bodies_%dx%dx%d" % pairs)
+    q = np.zeros((grid.size, 4))
+    q[:, 0] = 1.0
+    w["state"] = {"u": np.zeros((grid.size, 3)), "q": q, "v": vel, "w": w_init}
+    return w, bodies
