@@ -311,6 +311,18 @@ def time_adjoint(steps=5000, K=100):
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
     del s
+    # the same lattice with the palette's moduli runs the fused step kernel:
+    # the fastest plain forward of this lattice, which parameter mode does
+    # not reach
+    s = vx.from_workload(w, precision=32, stream=stream.cuda_stream)
+    s.bind()
+    s.step(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t_fused = time.perf_counter() - t0
+    del s
     s = make(w)
     gbytes = s.grad_bind(steps, K)
     torch.cuda.synchronize()
@@ -328,10 +340,14 @@ def time_adjoint(steps=5000, K=100):
             "checkpoint_every": K, "dtype": "f32", "grad_workspace_bytes": int(gbytes),
             "forward_s": t_fwd, "grad_forward_s": t1 - t0, "grad_backward_s": t2 - t1,
             "fwd_adj_over_fwd": t_fa / t_fwd,
+            "fused_forward_s": t_fused, "fwd_adj_over_fused_fwd": t_fa / t_fused, "target_fwd_adj_over_fwd": 4.0,
             "value": nvox * steps / t_fa, "unit": "voxel-steps/s (forward + reverse)",
             "grad_E_absmax": float(np.abs(g["E"]).max()), "grad_phase_absmax": float(np.abs(g["phase"]).max()),
-            "note": "parameter mode runs the split kernels; wall time with host synchronisation at each "
-                    "checkpoint and the host copies of the adjoint in and the gradients out"}
+            "note": "forward_s: the plain forward in parameter mode (per-voxel moduli), which runs the split "
+                    "kernels, as the recorded forward and the recompute do; fused_forward_s: the same lattice with "
+                    "the palette's moduli through the fused step kernel, the fastest plain forward; the target is "
+                    "fwd+adj <= 4 x fwd; wall time with host synchronisation at each checkpoint and the host "
+                    "copies of the adjoint in and the gradients out"}
 
 
 def time_collision_schemes(steps=5000, graph=True):

@@ -249,6 +249,7 @@ static FusedCfg fused_cfg(const vx_sim *h) {
     FusedCfg c;
     c.shape = h->fused_shape >= 0 ? h->fused_shape : heuristic_shape(h);
     c.zc = h->fused_zc;
+    c.chan = h->any_chan ? 1 : 0;
     return c;
 }
 
@@ -264,18 +265,12 @@ static int enqueue_steps(vx_sim *h, int64_t n) {
         }
         if (h->use_split()) {
             HIP_OK(h, launch_split_step<T>(a, h->stream));
-            if (col) {
-                CollideArgs c = make_collide(h);
-                HIP_OK(h, launch_motion_update<T>(a, c, h->stream));
-            }
         } else {
-            // the FP32 fused kernel's last workgroup does the motion bookkeeping
-            if (col && sizeof(T) == 4) a.motion = step_motion(h);
             HIP_OK(h, launch_fused_step<T>(a, fused_cfg(h), h->stream));
-            if (col && sizeof(T) == 8) {
-                CollideArgs c = make_collide(h);
-                HIP_OK(h, launch_motion_update<T>(a, c, h->stream));
-            }
+        }
+        if (col) {
+            CollideArgs c = make_collide(h);
+            HIP_OK(h, launch_motion_update<T>(a, c, h->stream));
         }
         h->cur = 1 - h->cur;
         h->step++;
@@ -312,14 +307,14 @@ static int autotune(vx_sim *h, int iters, int32_t *shape_out, int32_t *zc_out) {
     HIP_OK(h, hipEventCreate(&e0));
     HIP_OK(h, hipEventCreate(&e1));
     float best = 1e30f;
-    FusedCfg best_cfg{0, 0};
+    FusedCfg best_cfg{0, 0, h->any_chan ? 1 : 0};
     // z chunks: the number of workgroups against the three resident per CU
     // decides the tail of the launch, so the grid is fine
     const int zcs[] = {2, 3, 4, 5, 6, 8, 10, 12, 16, 24, 32, 48, 64};
     for (int sh = 0; sh < kNumFusedShapes; ++sh)
         for (int zc : zcs) {
             if (zc > h->nz && zc != zcs[0]) continue;
-            FusedCfg cfg{sh, zc};
+            FusedCfg cfg{sh, zc, h->any_chan ? 1 : 0};
             // warm-up launch, then the timed ones; outputs go to the next
             // buffers and are overwritten by the first real step
             HIP_OK(h, launch_fused_step<T>(a, cfg, h->stream));
@@ -633,6 +628,7 @@ int vx_set_channels(vx_handle h, const vx_channel *ch, int32_t n_ch, const int32
     }
     h->chans.assign(ch, ch + n_ch);
     h->cell_chan = cc;
+    h->any_chan = std::any_of(cc.begin(), cc.end(), [](int8_t k) { return k >= 0; });
     h->chan_grad_valid = false;
     for (long long c = 0; c < h->ncell; ++c) {
         if (cc[c] >= 0) h->flags[c] |= FLAG_CHAN; else h->flags[c] &= (uint8_t)~FLAG_CHAN;

@@ -333,15 +333,13 @@ VX_HD T chan_pick(const Chan8<T> &c, int k) {
 }
 
 
-// Temperature of a voxel at t_n: its channel's, else its own signal, else
-// the global one.  FP32 evaluates its own signal from the host-reduced
-// phase 2 pi f t_n mod 2 pi; channel temperatures come from the host.
+// Strain of a voxel that follows no channel: its own signal, else the
+// global one.  FP32 evaluates its own signal from the host-reduced phase
+// 2 pi f t_n mod 2 pi.
 template <typename T>
-VX_HD T voxel_strain(const StepArgs<T> &a, unsigned c, uint8_t fl, T cte) {
+VX_HD T signal_strain(const StepArgs<T> &a, unsigned c, uint8_t fl, T cte) {
     T dT = a.dT_global;
-    if (fl & FLAG_CHAN) {
-        dT = chan_pick(a.chan_dT, ldc(a.chan, c));
-    } else if (fl & FLAG_ACT) {
+    if (fl & FLAG_ACT) {
         if constexpr (sizeof(T) == 8) {
             dT = ldc(a.act_amp, c) * dsin<T>(a.wt + ldc(a.act_phase, c));
         } else {
@@ -349,6 +347,14 @@ VX_HD T voxel_strain(const StepArgs<T> &a, unsigned c, uint8_t fl, T cte) {
         }
     }
     return cte * dT;
+}
+
+// Strain of a voxel at t_n: its channel's temperature (from the host), else
+// signal_strain.
+template <typename T>
+VX_HD T voxel_strain(const StepArgs<T> &a, unsigned c, uint8_t fl, T cte) {
+    if (fl & FLAG_CHAN) return cte * chan_pick(a.chan_dT, ldc(a.chan, c));
+    return signal_strain(a, c, fl, cte);
 }
 
 // d eps / d phase and d eps / d amp of a voxel with its own actuation
@@ -612,6 +618,8 @@ __device__ __forceinline__ void voxel_update(const StepArgs<T> &a, unsigned c, u
     store(c, o);
     stc(a.flags_out, c, nf);
     if (fl & FLAG_FIXED) return;
+    // a non-finite momentum reaches the displacement, and a non-finite
+    // angular momentum the orientation, in the same update
     const bool ok = dfinite(o.ux) && dfinite(o.uy) && dfinite(o.uz) && dfinite(o.qw) && dfinite(o.qx) &&
                     dfinite(o.qy) && dfinite(o.qz) && dfinite(o.px) && dfinite(o.py) && dfinite(o.pz) &&
                     dfinite(o.lx) && dfinite(o.ly) && dfinite(o.lz);
@@ -646,8 +654,8 @@ __device__ __forceinline__ void wave_vmax(unsigned long long *dst, T v) {
     }
 }
 
-// Collision motion bookkeeping of one step, by one thread after every
-// voxel of the step is written: a rebuild that ran at the step's start
+// Collision motion bookkeeping of one step, by one thread after the step
+// kernel: a rebuild that ran at the step's start
 // (flag still set) is closed, the largest speed of the step (read and
 // cleared) times dt is accumulated, and the flag is set for the next step
 // once twice the accumulated motion reaches the threshold (or always).
@@ -661,20 +669,6 @@ __device__ __forceinline__ void motion_update(Scalars *sc, double dt) {
     const double acc = sc->macc + v * dt;
     sc->macc = acc;
     if (sc->every || 2.0 * acc >= sc->threshold) sc->rebuild_flag = 1u;
-}
-
-// The same from the last workgroup of a step kernel to finish: every thread
-// of every workgroup calls this once, after its state and speed updates;
-// thread 0 counts the workgroup in and, if it is the last, does the update
-// and resets the count.
-__device__ __forceinline__ void motion_last_workgroup(Scalars *sc, double dt) {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0 && atomicAdd(&sc->done, 1u) == gridDim.x - 1) {
-        __threadfence();
-        motion_update(sc, dt);
-        sc->done = 0u;
-    }
 }
 
 }  // namespace vx

@@ -169,14 +169,17 @@ struct Tables {
 };
 
 // voxel_strain with the channel temperatures read from the workgroup's
-// table (the step arguments' copies are not kept in registers).
-template <typename T>
+// table (the step arguments' copies are not kept in registers); lattices
+// without channel voxels take the kernels built without the channel test.
+template <bool Chan, typename T>
 __device__ __forceinline__ T strain_tb(const StepArgs<T> &a, const Tables<T> &tb, unsigned c, uint8_t fl, T cte) {
-    if (fl & FLAG_CHAN) return cte * tb.chan[ldc(a.chan, c)];
-    return voxel_strain(a, c, (uint8_t)(fl & ~FLAG_CHAN), cte);
+    if constexpr (Chan) {
+        if (fl & FLAG_CHAN) return cte * tb.chan[ldc(a.chan, c)];
+    }
+    return signal_strain(a, c, fl, cte);
 }
 
-template <typename T>
+template <bool Chan, typename T>
 __device__ __forceinline__ void load_own(const StepArgs<T> &a, const StateBuf<T> &sb, const Tables<T> &tb,
                                          unsigned c, Own<T> &o) {
     o.m = ldc(a.mat, c);
@@ -184,7 +187,7 @@ __device__ __forceinline__ void load_own(const StepArgs<T> &a, const StateBuf<T>
         o.fl = ldc(a.flags, c);
         o.r = sb_load(sb, c);
         const MatConst<T> &mc = tb.mat[o.m];
-        o.eps = strain_tb(a, tb, c, o.fl, mc.cte);
+        o.eps = strain_tb<Chan>(a, tb, c, o.fl, mc.cte);
         o.k = kin_of(o.r, mc, o.eps);
     }
 }
@@ -207,7 +210,7 @@ __device__ __forceinline__ void issue_pre(const StepArgs<T> &a, const StateBuf<T
 }
 
 // Strain and kinematics of a prefetched cell.
-template <typename T>
+template <bool Chan, typename T>
 __device__ __forceinline__ void finish_pre(const StepArgs<T> &a, const Tables<T> &tb, unsigned c, const Pre<T> &p,
                                            Own<T> &o) {
     o.m = p.m;
@@ -215,7 +218,7 @@ __device__ __forceinline__ void finish_pre(const StepArgs<T> &a, const Tables<T>
         o.fl = p.fl;
         o.r = p.r;
         const MatConst<T> &mc = tb.mat[p.m];
-        o.eps = strain_tb(a, tb, c, p.fl, mc.cte);
+        o.eps = strain_tb<Chan>(a, tb, c, p.fl, mc.cte);
         o.k = kin_of(p.r, mc, o.eps);
     }
 }
@@ -258,7 +261,7 @@ __host__ __device__ inline size_t tables_bytes(int n_mat) {
 // (threads beyond TX * TY only help with the ring and the barriers).  TX and
 // TY may be compile-time constants (fused kernel) or runtime values within
 // the LDS sizes of S (batched kernel).
-template <typename T, typename S>
+template <bool Chan, typename T, typename S>
 __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<T> &tb, const LatK<T> &C,
                                       const int TX, const int TY, int tile_x, int tile_y, int z0, int z1,
                                       T &vmax) {
@@ -303,7 +306,7 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
             uint8_t mr = 0;
             if (ring_in) {
                 Own<T> R{};
-                finish_pre(a, tb, ring_col + (unsigned)z * nxy, r, R);
+                finish_pre<Chan>(a, tb, ring_col + (unsigned)z * nxy, r, R);
                 mr = R.m;
                 if (mr) put_kin<T, NR>(sm.kin, ring_slot, R.k);
             }
@@ -312,7 +315,7 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
     };
 
     Own<T> A{}, B{};
-    if (inxy && z0 < z1) load_own(a, sb, tb, col + (unsigned)z0 * nxy, A);
+    if (inxy && z0 < z1) load_own<Chan>(a, sb, tb, col + (unsigned)z0 * nxy, A);
     Pre<T> rp{};
     if (ring_in && z0 < z1) issue_pre(a, sb, ring_col + (unsigned)z0 * nxy, rp);
 
@@ -321,7 +324,7 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
     T cFx = T(0), cFy = T(0), cFz = T(0), cMx = T(0), cMy = T(0), cMz = T(0);
     if (A.m && z0 > 0) {
         Own<T> P{};
-        load_own(a, sb, tb, col + (unsigned)(z0 - 1) * nxy, P);
+        load_own<Chan>(a, sb, tb, col + (unsigned)(z0 - 1) * nxy, P);
         if (P.m) {
             const Rot<T> Rp = rot_of(P.k.qw, P.k.qx, P.k.qy, P.k.qz);
             const BondOut<T> o = bond_eval<T, 2>(P.k, Rp, A.k, tb.bond(P.m, A.m), C);
@@ -375,7 +378,7 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
             n_mx = sm.mat[own - 1] != 0; n_px = sm.mat[own + 1] != 0;
             n_my = sm.mat[own - RW] != 0; n_py = sm.mat[own + RW] != 0;
         }
-        finish_pre(a, tb, col + (unsigned)(z + 1) * nxy, pn, nxt);
+        finish_pre<Chan>(a, tb, col + (unsigned)(z + 1) * nxy, pn, nxt);
         const bool has_zb = cur.m && nxt.m;
         BondOut<T> oz{};
         if (has_zb) oz = bond_eval<T, 2>(cur.k, Rc, nxt.k, tb.bond(cur.m, nxt.m), C);
@@ -431,7 +434,7 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
 // FP32 is held to 168 VGPRs, so that three workgroups share a CU (three
 // waves per SIMD; two loop-invariant values go to scratch); FP64 needs more
 // than 256 and runs one wave per SIMD.
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, bool Chan>
 __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
 k_fused(StepArgs<T> a, FusedGrid g) {
     static_assert(2 * (TX + TY) <= TX * TY, "ring must fit one cell per thread");
@@ -452,13 +455,8 @@ k_fused(StepArgs<T> a, FusedGrid g) {
     __syncthreads();
 
     T vmax = T(0);
-    march(a, sm, tb, C, TX, TY, tile_x, tile_y, z0, z1, vmax);
+    march<Chan>(a, sm, tb, C, TX, TY, tile_x, tile_y, z0, z1, vmax);
     if (a.track_vmax) wave_vmax(a.vmax_bits, vmax);
-    // FP32 only: the FP64 kernel, at its register limit, keeps the separate
-    // bookkeeping launch
-    if constexpr (sizeof(T) == 4) {
-        if (a.motion) motion_last_workgroup(a.motion, (double)a.dt);
-    }
 }
 
 // Largest runtime tile of the batched kernel: TX, TY <= 64, TX * TY <= 256,
@@ -505,7 +503,8 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchArgs<T> b) {
             a.wt_red = (T)fmod(wt, 6.283185307179586);
             const int tiles_x = (ob.nx + ob.tx - 1) / ob.tx, tiles_y = (ob.ny + ob.ty - 1) / ob.ty;
             for (int ty = 0; ty < tiles_y; ++ty)
-                for (int tx = 0; tx < tiles_x; ++tx) march(a, sm, tb, C, ob.tx, ob.ty, tx, ty, 0, ob.nz, vmax);
+                for (int tx = 0; tx < tiles_x; ++tx)
+                    march<false>(a, sm, tb, C, ob.tx, ob.ty, tx, ty, 0, ob.nz, vmax);
         }
         // this step's writes are the next step's reads (same workgroup)
         __syncthreads();
@@ -514,7 +513,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchArgs<T> b) {
 }
 
 template <typename T, int TX, int TY>
-hipError_t launch_tiles(const StepArgs<T> &a, int zc, hipStream_t s) {
+hipError_t launch_tiles(const StepArgs<T> &a, int zc, bool chan, hipStream_t s) {
     FusedGrid g;
     g.tiles_x = (a.nx + TX - 1) / TX;
     g.tiles_y = (a.ny + TY - 1) / TY;
@@ -524,7 +523,10 @@ hipError_t launch_tiles(const StepArgs<T> &a, int zc, hipStream_t s) {
     g.zc = zc;
     g.chunks = (a.nz + zc - 1) / zc;
     const long long nwg = cols * g.chunks;
-    k_fused<T, TX, TY><<<(unsigned)nwg, TX * TY, tables_bytes<T>(a.n_mat), s>>>(a, g);
+    if (chan)
+        k_fused<T, TX, TY, true><<<(unsigned)nwg, TX * TY, tables_bytes<T>(a.n_mat), s>>>(a, g);
+    else
+        k_fused<T, TX, TY, false><<<(unsigned)nwg, TX * TY, tables_bytes<T>(a.n_mat), s>>>(a, g);
     return hipGetLastError();
 }
 
@@ -576,11 +578,11 @@ const FusedShape kFusedShapes[kNumFusedShapes] = {{32, 8}, {64, 4}, {16, 16}, {5
 template <typename T>
 hipError_t launch_fused_step(const StepArgs<T> &a, const FusedCfg &cfg, hipStream_t s) {
     switch (cfg.shape) {
-        case 1: return launch_tiles<T, 64, 4>(a, cfg.zc, s);
-        case 2: return launch_tiles<T, 16, 16>(a, cfg.zc, s);
-        case 3: return launch_tiles<T, 50, 5>(a, cfg.zc, s);
-        case 4: return launch_tiles<T, 20, 12>(a, cfg.zc, s);
-        default: return launch_tiles<T, 32, 8>(a, cfg.zc, s);
+        case 1: return launch_tiles<T, 64, 4>(a, cfg.zc, cfg.chan != 0, s);
+        case 2: return launch_tiles<T, 16, 16>(a, cfg.zc, cfg.chan != 0, s);
+        case 3: return launch_tiles<T, 50, 5>(a, cfg.zc, cfg.chan != 0, s);
+        case 4: return launch_tiles<T, 20, 12>(a, cfg.zc, cfg.chan != 0, s);
+        default: return launch_tiles<T, 32, 8>(a, cfg.zc, cfg.chan != 0, s);
     }
 }
 

@@ -53,6 +53,7 @@ extern const FusedShape kFusedShapes[kNumFusedShapes];
 struct FusedCfg {
     int shape;
     int zc;
+    int chan;   // 1: some voxel follows a named channel
 };
 // Compute units of the current device (256 if it cannot be queried).
 int device_cus();
@@ -176,8 +177,7 @@ template <typename T>
 hipError_t launch_contact(const StepArgs<T> &a, const CollideArgs &c, T *contact_F, hipStream_t s);
 
 // Motion bookkeeping after a step (one thread): closes a rebuild that ran
-// at the step's start, accumulates max|v| dt, sets the rebuild flag.  The
-// fused step kernel does the same in its last workgroup when a.mo.on.
+// at the step's start, accumulates max|v| dt, sets the rebuild flag.
 template <typename T>
 hipError_t launch_motion_update(const StepArgs<T> &a, const CollideArgs &c, hipStream_t s);
 

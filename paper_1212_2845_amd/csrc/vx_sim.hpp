@@ -66,6 +66,7 @@ struct vx_sim {
     // named actuation channels and each cell's channel (-1: none)
     std::vector<vx_channel> chans;
     std::vector<int8_t> cell_chan;
+    bool any_chan = false;            // some filled cell follows a channel
     // per-channel gradients of the last reverse run
     std::vector<double> chan_gphase, chan_gamp;
     bool chan_grad_valid = false;
@@ -261,6 +262,3 @@ inline vx::CollideArgs make_collide(vx_sim *h) {
     return c;
 }
 
-// The device scalars the fused kernel's last workgroup updates in a real
-// step with self-collision.
-inline vx::Scalars *step_motion(vx_sim *h) { return (Scalars *)(h->ws + h->L.scalars); }

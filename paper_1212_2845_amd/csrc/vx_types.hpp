@@ -124,7 +124,6 @@ struct StepArgs {
     const T *rho_cell;         // parameter mode: per-cell density (set whenever E_cell is)
     T *fm_out;                 // split gather: per-voxel bond force and moment sums (6 x ncell), or null
     T zeta_bond, zeta_slow, zeta_col;
-    Scalars *motion;           // collision bookkeeping by the step's last workgroup, or null
 };
 
 }  // namespace vx
