@@ -435,7 +435,7 @@ typedef struct vx_batch_sim *vx_batch;
  * atomics), and all objects step with the smallest of their stable
  * timesteps, one launch per step.  Errors: VX_EINVAL as vx_create, or if
  * one state array (13 words per cell of all objects) would span 2 GiB or
- * more. */
+ * more, or an object with a non-zero reserved field or a non-finite origin. */
 int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *palette, int32_t n_mat,
                     const vx_params *params, int32_t precision, void *stream, vx_batch *out);
 int vx_batch_workspace_bytes(vx_batch b, uint64_t *bytes);

@@ -415,7 +415,11 @@ int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *pal
     std::vector<char> used(n_mat, 0);   // materials present in any object
     for (int i = 0; i < n_obj; ++i) {
         const vx_object &o = objs[i];
-        if (!o.grid || o.nx <= 0 || o.ny <= 0 || o.nz <= 0) { delete h; return VX_EINVAL; }
+        if (!o.grid || o.nx <= 0 || o.ny <= 0 || o.nz <= 0 || o.reserved != 0 || !std::isfinite(o.origin[0]) ||
+            !std::isfinite(o.origin[1]) || !std::isfinite(o.origin[2])) {
+            delete h;
+            return VX_EINVAL;
+        }
         const long long nc = (long long)o.nx * o.ny * o.nz;
         ObjHost oh{};
         oh.off = off; oh.nx = o.nx; oh.ny = o.ny; oh.nz = o.nz;
