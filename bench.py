@@ -657,14 +657,17 @@ def main():
     use_graph = not args.eager and args.steps % 2 == 0
     r = time_gpu(w, args.precision, kernel, args.steps, args.warmup, autotune, tile, graph=use_graph)
     state_bytes = int(w["grid"].size) * 13 * (4 if args.precision == 32 else 8)
+    # the headline is the plain vx_step call; the replay of the same steps
+    # captured as a HIP graph is reported beside it (on this lattice its
+    # seven dependent nodes per step run slower than the eager launches)
     out = {
         "metric": "voxel-steps/s",
-        "value": r["voxels"] * args.steps / (r["ms"] / 1e3),
+        "value": r["voxels"] * args.steps / (r["eager_ms"] / 1e3),
         "unit": "voxel-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r["ms"] / args.steps,
+        "ms_per_step": r["eager_ms"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -675,10 +678,10 @@ def main():
                    "self_collision": bool(w["params"].get("self_collision_on")),
                    "cache_resident": 2 * state_bytes < 256e6},
         "roofline": roofline(args.precision, r["voxels"], r["kernel_ms"], w["name"], r["tile"]),
-        "timing": {"method": "one replay of a captured HIP graph of the K steps, HIP events on the replay "
-                             "stream, device synchronisation on both sides" if use_graph else
-                             "one vx_step call of K steps, HIP events on its stream",
-                   "eager_value": r["voxels"] * args.steps / (r["eager_ms"] / 1e3)},
+        "timing": {"method": "one vx_step call of the K steps (host launches included), HIP events on its "
+                             "stream, device synchronisation on both sides",
+                   "graph_value": r["voxels"] * args.steps / (r["ms"] / 1e3) if use_graph else None,
+                   "graph_method": "one replay of the K steps captured as a HIP graph, after an untimed replay"},
     }
     if r["collision"] is not None:
         out["collision"] = dict(r["collision"], note="candidate-list rebuilds since creation (warm-up, eager "

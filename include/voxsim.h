@@ -237,6 +237,19 @@ int vx_candidates(vx_handle h, int32_t *cell_a, int32_t *cell_b, int32_t max_pai
  * Blocks until the result is on the host.  Errors: VX_ESTATE before bind. */
 int vx_energy(vx_handle h, double out[10]);
 
+/* The same ten sums as vx_energy, written to out[0..9], a DEVICE array of
+ * doubles owned by the caller, by two kernels enqueued on the handle's
+ * stream (per-workgroup partials, then their sum in a fixed order on the
+ * device; the order differs from vx_energy's host sum, so the two agree to
+ * FP64 rounding).  No host synchronisation: alternated with
+ * vx_step_enqueue it records the energies of every step of a run (the
+ * energy-per-step record of the cantilever benchmark, Results) with one
+ * wait at the end, and it may be captured in a HIP graph (as vx_probe, the
+ * captured kernels read the ping-pong buffer current at capture time).
+ * Calls on one handle share its partials buffer, so they run in stream
+ * order.  Errors: VX_EINVAL for a NULL array, VX_ESTATE before bind. */
+int vx_energy_enqueue(vx_handle h, double *out);
+
 /* Linear statics: the direct-stiffness solution K x = f of the lattice in
  * its rest configuration (section Validation, the "direct stiffness" column
  * of Table 1), solved on the GPU in FP64 by Jacobi-preconditioned conjugate

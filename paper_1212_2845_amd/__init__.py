@@ -33,7 +33,7 @@ EXPORTED = ["vx_create", "vx_workspace_bytes", "vx_bind_workspace", "vx_set_fixe
             "vx_counters", "vx_candidates", "vx_set_kernel", "vx_set_fused_tile", "vx_get_fused_tile",
             "vx_autotune", "vx_time_kernel", "vx_destroy", "vx_last_error",
             "vx_step_enqueue", "vx_status", "vx_probe", "vx_set_collision_mode", "vx_static_workspace_bytes",
-            "vx_static_solve", "vx_static_solve_noalloc", "vx_energy", "vx_set_channels", "vx_grad_channels", "vx_set_stiffness", "vx_set_density", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
+            "vx_static_solve", "vx_static_solve_noalloc", "vx_energy", "vx_energy_enqueue", "vx_set_channels", "vx_grad_channels", "vx_set_stiffness", "vx_set_density", "vx_grad_workspace_bytes", "vx_grad_bind", "vx_grad_forward",
             "vx_grad_backward",
             "vx_batch_create", "vx_batch_workspace_bytes", "vx_batch_bind_workspace", "vx_batch_step",
             "vx_batch_read_state", "vx_batch_write_state", "vx_batch_get_dt", "vx_batch_counters",
@@ -124,6 +124,7 @@ def lib():
     L.vx_autotune.argtypes = [P, i32, pi32, pi32]
     L.vx_time_kernel.argtypes = [P, i32, C.POINTER(C.c_double)]
     L.vx_energy.argtypes = [P, C.POINTER(C.c_double)]
+    L.vx_energy_enqueue.argtypes = [P, P]
     L.vx_step_enqueue.argtypes = [P, i64]
     L.vx_status.argtypes = [P]
     L.vx_probe.argtypes = [P, P, i32, i32, P]
@@ -445,6 +446,33 @@ class Sim:
         v = list(out)
         return {"kinetic": v[0], "elastic": v[1], "gravity": v[2], "floor": v[3], "momentum": v[4:7],
                 "angular_momentum": v[7:10]}
+
+    ENERGY_KEYS = ("kinetic", "elastic", "gravity", "floor", "Px", "Py", "Pz", "Lx", "Ly", "Lz")
+
+    def energy_enqueue(self, out):
+        """Enqueue the vx_energy sums of the current state into ``out``, a
+        float64 device tensor of at least 10 elements, without waiting."""
+        import torch
+        assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() >= 10
+        self.bind()
+        self._check(lib().vx_energy_enqueue(self.h, C.c_void_p(out.data_ptr())))
+
+    def energy_record(self, steps, every=1, device=None):
+        """Run ``steps`` steps (a multiple of ``every``) with the energies of
+        the state before the first step and after every ``every`` steps
+        recorded on the device; one wait at the end.  Returns a float64
+        device tensor of shape (steps // every + 1, 10), columns as
+        ENERGY_KEYS."""
+        import torch
+        assert steps >= 0 and every >= 1 and steps % every == 0
+        self.bind()
+        rec = torch.empty((steps // every + 1, 10), dtype=torch.float64, device=device or "cuda")
+        self.energy_enqueue(rec[0])
+        for k in range(1, rec.shape[0]):
+            self._check(lib().vx_step_enqueue(self.h, every))
+            self.energy_enqueue(rec[k])
+        self.status()
+        return rec
 
     def read_flags(self):
         st = np.empty(self.ncell, np.uint8); su = np.empty(self.ncell, np.uint8)

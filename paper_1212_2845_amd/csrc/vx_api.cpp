@@ -388,6 +388,15 @@ static int energy(vx_sim *h, double *out) {
     return VX_OK;
 }
 
+template <typename T>
+static int energy_enqueue(vx_sim *h, double *out_dev) {
+    StepArgs<T> a = make_args<T>(h);
+    double *part = (double *)(h->ws + h->L.energy);
+    HIP_OK(h, launch_energy<T>(a, part, h->stream));
+    HIP_OK(h, launch_energy_sum(part, h->ncell, out_dev, h->stream));
+    return VX_OK;
+}
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -663,6 +672,12 @@ int vx_energy(vx_handle h, double out[10]) {
     if (!h || !out) return VX_EINVAL;
     if (!h->bound) return fail(h, VX_ESTATE, "vx_energy before vx_bind_workspace");
     return h->precision == 64 ? energy<double>(h, out) : energy<float>(h, out);
+}
+
+int vx_energy_enqueue(vx_handle h, double *out) {
+    if (!h || !out) return VX_EINVAL;
+    if (!h->bound) return fail(h, VX_ESTATE, "vx_energy_enqueue before vx_bind_workspace");
+    return h->precision == 64 ? energy_enqueue<double>(h, out) : energy_enqueue<float>(h, out);
 }
 
 int vx_probe(vx_handle h, const int32_t *cells, int32_t n, int32_t word, void *out) {

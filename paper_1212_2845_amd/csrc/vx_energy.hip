@@ -108,6 +108,29 @@ __global__ void __launch_bounds__(kEnergyThreads) k_energy(StepArgs<T> a, double
     if (threadIdx.x < kEnergyWords) partials[(long long)blockIdx.x * kEnergyWords + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Sum of the per-workgroup partials of k_energy into out[0..kEnergyWords),
+// on the device, in a fixed order: thread t adds rows t, t + 256, ... in
+// turn, then a fixed tree over the threads.
+__global__ void __launch_bounds__(kEnergyThreads) k_energy_sum(const double *partials, int nb, double *out) {
+    __shared__ double red[kEnergyWords][kEnergyThreads];
+    double acc[kEnergyWords];
+#pragma unroll
+    for (int i = 0; i < kEnergyWords; ++i) acc[i] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kEnergyThreads)
+#pragma unroll
+        for (int i = 0; i < kEnergyWords; ++i) acc[i] += partials[(long long)b * kEnergyWords + i];
+#pragma unroll
+    for (int i = 0; i < kEnergyWords; ++i) red[i][threadIdx.x] = acc[i];
+    __syncthreads();
+    for (int s = kEnergyThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+#pragma unroll
+            for (int i = 0; i < kEnergyWords; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < kEnergyWords) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
 // One state word of listed cells into a device array: the recording step of
 // a long run (e.g. a probe voxel's displacement every few steps for a modal
 // spectrum) without a host synchronisation.  An index outside the lattice
@@ -143,6 +166,11 @@ template <typename T>
 hipError_t launch_energy(const StepArgs<T> &a, double *partials, hipStream_t s) {
     const long long n = (long long)a.nx * a.ny * a.nz;
     k_energy<T><<<energy_blocks(n), kEnergyThreads, 0, s>>>(a, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_sum(const double *partials, long long ncell, double *out, hipStream_t s) {
+    k_energy_sum<<<1, kEnergyThreads, 0, s>>>(partials, energy_blocks(ncell), out);
     return hipGetLastError();
 }
 

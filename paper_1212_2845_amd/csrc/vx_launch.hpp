@@ -38,6 +38,8 @@ constexpr int kEnergyWords = 10;   // KE, U_elastic, U_gravity, U_floor, P (3), 
 int energy_blocks(long long ncell);
 template <typename T>
 hipError_t launch_energy(const StepArgs<T> &a, double *partials, hipStream_t s);
+// Fixed-order device sum of launch_energy's partials into out[0..kEnergyWords).
+hipError_t launch_energy_sum(const double *partials, long long ncell, double *out, hipStream_t s);
 template <typename T>
 hipError_t launch_probe(const T *state, long long stride, long long ncell, const int32_t *cells, int n, int word,
                         T *out, hipStream_t s);

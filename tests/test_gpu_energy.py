@@ -85,3 +85,47 @@ def test_momentum_conserved_on_gpu():
     g.step(1000)
     P1 = np.array(g.energy()["momentum"])
     assert np.abs(P1 - P0).max() <= 1e-12 * np.abs(P0).max()
+
+
+def test_energy_record_equals_host_sums():
+    """The device record (vx_energy_enqueue alternated with
+    vx_step_enqueue, one wait at the end) equals vx_energy taken with a
+    host wait after every 3 steps on an identical run, to FP64 rounding of
+    the different summation order."""
+    import torch
+    w = floor_block(seed=21)
+    announce("energy record vs host sums")
+    g = build_gpu(w, precision=64)
+    h = build_gpu(w, precision=64)
+    rec = g.energy_record(60, every=3).cpu().numpy()
+    assert rec.shape == (21, 10)
+    for k in range(rec.shape[0]):
+        if k:
+            h.step(3)
+        e = h.energy()
+        want = np.array([e["kinetic"], e["elastic"], e["gravity"], e["floor"]] + list(e["momentum"]) +
+                        list(e["angular_momentum"]))
+        scale = np.maximum(np.abs(want), 1e-300)
+        scale[4:7] = max(np.abs(want[4:7]).max(), 1e-300)
+        scale[7:10] = max(np.abs(want[7:10]).max(), 1e-300)
+        assert (np.abs(rec[k] - want) <= 1e-12 * scale).all(), (k, rec[k], want)
+    torch.cuda.synchronize()
+
+
+def test_energy_record_of_cantilever_matches_oracle():
+    """The energy-per-step record of the 20 x 4 x 4 cantilever under gravity
+    (the lattice clamped at x = 0), 200 steps in FP64, against the oracle's
+    energies after each step."""
+    w = workloads.cantilever(steps=200)
+    announce("cantilever energy record")
+    g = build_gpu(w, precision=64)
+    o = build_oracle(w)
+    rec = g.energy_record(200).cpu().numpy()
+    for k in range(rec.shape[0]):
+        if k:
+            assert o.step(1) == 0
+        eo = o.energy()
+        ref = np.array([eo["ke"], eo["elastic"], eo["gravity"], eo["floor"]])
+        assert (np.abs(rec[k, :4] - ref) <= 1e-9 * np.maximum(np.abs(ref), 1e-300) + 1e-30).all(), (k, rec[k], ref)
+    assert rec[-1, 0] > 0 and rec[-1, 1] > 0          # the beam moves and bends
+    assert rec[-1, 2] < rec[0, 2]                       # and sags
