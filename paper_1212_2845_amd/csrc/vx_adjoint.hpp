@@ -24,20 +24,6 @@ struct BondAdj {
     T a1, a2, ct;   // adjoints of the bond constants
 };
 
-// Bond constants from per-voxel moduli (Eq. 1, 2, 8-12, 34): g = 1/(2(1+nu))
-// turns E into the shear modulus; m_min the smaller voxel mass.
-template <typename T>
-VX_HD BondK<T> bond_k_from_E(T EA, T EB, T gA, T gB, T m_min, T zeta_bond, const LatK<T> &C) {
-    BondK<T> k;
-    const T Ec = T(2) * EA * EB / (EA + EB);
-    const T GA = EA * gA, GB = EB * gB;
-    const T Gc = T(2) * GA * GB / (GA + GB);
-    k.a1 = Ec * C.l;
-    k.a2 = Gc * C.l * C.l26;
-    k.ct = T(2) * zeta_bond * dsqrt(m_min * k.a1);
-    return k;
-}
-
 // Chain the bond-constant adjoints back to the two voxels' moduli.
 template <typename T>
 VX_HD void bond_k_from_E_vjp(T EA, T EB, T gA, T gB, const BondK<T> &k, T g_a1, T g_a2, T g_ct,

@@ -228,31 +228,6 @@ static int request_rebuild(vx_sim *h) {
     return VX_OK;
 }
 
-// Tile shape of the fused kernel: the one wasting the fewest lanes on the
-// lattice's x-y extent, with the ring (halo) and boundary-bond overhead of
-// small tiles as a tie breaker.
-static int heuristic_shape(const vx_sim *h) {
-    int best = 0;
-    double best_cost = 1e300;
-    for (int i = 0; i < kNumFusedShapes; ++i) {
-        const int tx = kFusedShapes[i].tx, ty = kFusedShapes[i].ty;
-        const double padded = (double)((h->nx + tx - 1) / tx * tx) * (double)((h->ny + ty - 1) / ty * ty);
-        const double slots = padded / ((double)h->nx * h->ny);
-        const double halo = 2.0 * (tx + ty) / (double)(tx * ty);
-        const double cost = slots * (1.0 + 0.3 * halo);
-        if (cost < best_cost - 1e-12) { best_cost = cost; best = i; }
-    }
-    return best;
-}
-
-static FusedCfg fused_cfg(const vx_sim *h) {
-    FusedCfg c;
-    c.shape = h->fused_shape >= 0 ? h->fused_shape : heuristic_shape(h);
-    c.zc = h->fused_zc;
-    c.chan = h->any_chan ? 1 : 0;
-    return c;
-}
-
 template <typename T>
 static int enqueue_steps(vx_sim *h, int64_t n) {
     const bool col = h->p.self_collision_on != 0;

@@ -423,8 +423,9 @@ int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *pal
         const long long nc = (long long)o.nx * o.ny * o.nz;
         ObjHost oh{};
         oh.off = off; oh.nx = o.nx; oh.ny = o.ny; oh.nz = o.nz;
+        // tile within the batch kernel's LDS: TX, TY <= 64, TX TY <= 256
         oh.tx = std::min(o.nx, 64);
-        oh.ty = std::min(o.ny, 256 / oh.tx);
+        oh.ty = std::min(std::min(o.ny, 256 / oh.tx), 64);
         oh.origin_z = o.origin[2];
         // the object's own stable timestep over its bonded material pairs
         std::vector<char> seen((size_t)n_mat * n_mat, 0), seen_vox(n_mat, 0);

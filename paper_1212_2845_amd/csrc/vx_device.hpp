@@ -441,6 +441,20 @@ VX_HD MatConst<T> mat_with(MatConst<T> mc, T E, T rho, T l, T zeta_slow, T zeta_
     return mc;
 }
 
+// Bond constants from per-voxel moduli (Eq. 1, 2, 8-12, 34): g = 1/(2(1+nu))
+// turns E into the shear modulus; m_min the smaller voxel mass.
+template <typename T>
+VX_HD BondK<T> bond_k_from_E(T EA, T EB, T gA, T gB, T m_min, T zeta_bond, const LatK<T> &C) {
+    BondK<T> k;
+    const T Ec = T(2) * EA * EB / (EA + EB);
+    const T GA = EA * gA, GB = EB * gB;
+    const T Gc = T(2) * GA * GB / (GA + GB);
+    k.a1 = Ec * C.l;
+    k.a2 = Gc * C.l * C.l26;
+    k.ct = T(2) * zeta_bond * dsqrt(m_min * k.a1);
+    return k;
+}
+
 // Constants of cell c: the palette entry, or in parameter mode the entry
 // with the cell's own modulus and density.
 template <typename T>

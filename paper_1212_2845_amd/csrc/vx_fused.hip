@@ -14,11 +14,16 @@
 // the fixed order -x, +x, -y, +y, -z, +z (no atomics) and integrates.  The
 // per-bond and per-voxel arithmetic is the same device code as the split
 // path; material and material-pair constants are staged in LDS once per
-// workgroup.
+// workgroup.  In parameter mode (per-cell modulus and density) each cell's
+// modulus and mass travel with its kinematics, the voxel and bond constants
+// are derived from them as the split path does, and the per-voxel bond sums
+// can be written out for the adjoint.
 //
 // Workgroups are numbered so that consecutive tiles land on the same XCD
 // (the dispatcher deals workgroups round-robin over the 8 XCDs), keeping
 // the ring loads of neighbouring tiles in one L2.
+#include <type_traits>
+
 #include "vx_device.hpp"
 #include "vx_launch.hpp"
 
@@ -41,8 +46,16 @@ struct Smem {
     uint8_t mat[NR];
 };
 
+// With parameter mode: each slot's modulus and mass as well.
+template <typename T, int NR_, int NBX_, int NBY_>
+struct SmemP : Smem<T, NR_, NBX_, NBY_> {
+    T pE[NR_], pM[NR_];
+};
+
 template <typename T, int TX, int TY>
 using TileSmem = Smem<T, (TX + 2) * (TY + 2), (TX + 1) * TY, TX * (TY + 1)>;
+template <typename T, int TX, int TY>
+using TileSmemP = SmemP<T, (TX + 2) * (TY + 2), (TX + 1) * TY, TX * (TY + 1)>;
 
 struct FusedGrid {
     int tiles_x, tiles_y, chunks, zc;
@@ -152,6 +165,30 @@ struct Own {
     VoxKin<T> k;
 };
 
+// Raw words of one cell in flight: material, flags and all state words,
+// loaded without waiting on any of them (also for an empty cell, whose
+// state words exist and are ignored), so that a prefetch one slab ahead
+// costs no stall until the values are used.
+template <typename T>
+struct Pre {
+    uint8_t m, fl;
+    VoxRaw<T> r;
+};
+
+// The same with the cell's modulus and density (parameter mode).
+template <typename T>
+struct OwnP : Own<T> {
+    T E, rho;
+};
+template <typename T>
+struct PreP : Pre<T> {
+    T E, rho;
+};
+template <bool Param, typename T>
+using OwnT = typename std::conditional<Param, OwnP<T>, Own<T>>::type;
+template <bool Param, typename T>
+using PreT = typename std::conditional<Param, PreP<T>, Pre<T>>::type;
+
 // Per-workgroup copies of the material and material-pair tables and of the
 // actuation channels' temperatures at t_n.
 template <typename T>
@@ -179,47 +216,53 @@ __device__ __forceinline__ T strain_tb(const StepArgs<T> &a, const Tables<T> &tb
     return signal_strain(a, c, fl, cte);
 }
 
-template <bool Chan, typename T>
+// f(constants of the voxel of o, an Own or a Pre): the workgroup's table
+// entry of its material, or in parameter mode the entry with the cell's own
+// modulus and density (as mat_at computes them).
+template <bool Param, typename T, typename O, typename F>
+__device__ __forceinline__ void with_mc(const StepArgs<T> &a, const Tables<T> &tb, const O &o, const F &f) {
+    if constexpr (Param) f(mat_with(tb.mat[o.m], o.E, o.rho, a.l, a.zeta_slow, a.zeta_col));
+    else f(tb.mat[o.m]);
+}
+
+template <bool Chan, bool Param, typename T>
 __device__ __forceinline__ void load_own(const StepArgs<T> &a, const StateBuf<T> &sb, const Tables<T> &tb,
-                                         unsigned c, Own<T> &o) {
+                                         unsigned c, OwnT<Param, T> &o) {
     o.m = ldc(a.mat, c);
     if (o.m) {
         o.fl = ldc(a.flags, c);
         o.r = sb_load(sb, c);
-        const MatConst<T> &mc = tb.mat[o.m];
-        o.eps = strain_tb<Chan>(a, tb, c, o.fl, mc.cte);
-        o.k = kin_of(o.r, mc, o.eps);
+        if constexpr (Param) { o.E = ldc(a.E_cell, c); o.rho = ldc(a.rho_cell, c); }
+        with_mc<Param>(a, tb, o, [&](const MatConst<T> &mc) __attribute__((always_inline)) {
+            o.eps = strain_tb<Chan>(a, tb, c, o.fl, mc.cte);
+            o.k = kin_of(o.r, mc, o.eps);
+        });
     }
 }
 
-// Raw words of one cell in flight: material, flags and all state words,
-// loaded without waiting on any of them (also for an empty cell, whose
-// state words exist and are ignored), so that a prefetch one slab ahead
-// costs no stall until the values are used.
-template <typename T>
-struct Pre {
-    uint8_t m, fl;
-    VoxRaw<T> r;
-};
 
-template <typename T>
-__device__ __forceinline__ void issue_pre(const StepArgs<T> &a, const StateBuf<T> &sb, unsigned c, Pre<T> &p) {
+template <bool Param, typename T>
+__device__ __forceinline__ void issue_pre(const StepArgs<T> &a, const StateBuf<T> &sb, unsigned c,
+                                          PreT<Param, T> &p) {
     p.m = ldc(a.mat, c);
     p.fl = ldc(a.flags, c);
     p.r = sb_load(sb, c);
+    if constexpr (Param) { p.E = ldc(a.E_cell, c); p.rho = ldc(a.rho_cell, c); }
 }
 
 // Strain and kinematics of a prefetched cell.
-template <bool Chan, typename T>
-__device__ __forceinline__ void finish_pre(const StepArgs<T> &a, const Tables<T> &tb, unsigned c, const Pre<T> &p,
-                                           Own<T> &o) {
+template <bool Chan, bool Param, typename T>
+__device__ __forceinline__ void finish_pre(const StepArgs<T> &a, const Tables<T> &tb, unsigned c,
+                                           const PreT<Param, T> &p, OwnT<Param, T> &o) {
     o.m = p.m;
     if (p.m) {
         o.fl = p.fl;
         o.r = p.r;
-        const MatConst<T> &mc = tb.mat[p.m];
-        o.eps = strain_tb<Chan>(a, tb, c, p.fl, mc.cte);
-        o.k = kin_of(p.r, mc, o.eps);
+        if constexpr (Param) { o.E = p.E; o.rho = p.rho; }
+        with_mc<Param>(a, tb, p, [&](const MatConst<T> &mc) __attribute__((always_inline)) {
+            o.eps = strain_tb<Chan>(a, tb, c, p.fl, mc.cte);
+            o.k = kin_of(p.r, mc, o.eps);
+        });
     }
 }
 
@@ -261,7 +304,7 @@ __host__ __device__ inline size_t tables_bytes(int n_mat) {
 // (threads beyond TX * TY only help with the ring and the barriers).  TX and
 // TY may be compile-time constants (fused kernel) or runtime values within
 // the LDS sizes of S (batched kernel).
-template <bool Chan, typename T, typename S>
+template <bool Chan, bool Param, typename T, typename S>
 __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<T> &tb, const LatK<T> &C,
                                       const int TX, const int TY, int tile_x, int tile_y, int z0, int z1,
                                       T &vmax) {
@@ -276,6 +319,20 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
     const unsigned col = inxy ? (unsigned)x + (unsigned)a.nx * (unsigned)y : 0u;
     const int own = (tx + 1) + RW * (ty + 1);
     const StateBuf<T> sb = state_buf(a);
+    // mass of a voxel of density rho (as mat_with), and the constants of the
+    // bond between materials m1, m2 with moduli E1, E2 and masses M1, M2
+    auto mass = [&](T rho) __attribute__((always_inline)) { return rho * a.l * a.l * a.l; };
+    auto bond_kc = [&](uint8_t m1, uint8_t m2, T E1, T E2, T M1, T M2) __attribute__((always_inline)) {
+        if constexpr (Param)
+            return bond_k_from_E(E1, E2, tb.mat[m1].gfac, tb.mat[m2].gfac, M1 < M2 ? M1 : M2, a.zeta_bond, C);
+        else
+            return tb.bond(m1, m2);
+    };
+    // the same between two cells held in registers
+    auto bond_oo = [&](const OwnT<Param, T> &p, const OwnT<Param, T> &q) __attribute__((always_inline)) {
+        if constexpr (Param) return bond_kc(p.m, q.m, p.E, q.E, mass(p.rho), mass(q.rho));
+        else return tb.bond(p.m, q.m);
+    };
 
     // ring cell of this thread (one-cell border of the tile, corners excluded)
     const bool ring = tid < 2 * (TX + TY);
@@ -297,37 +354,44 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
 
     // Stage slab z in LDS: kinematics and material of the own cell o and of
     // this thread's ring cell, whose loads r were issued earlier.
-    auto stage = [&](const Own<T> &o, const Pre<T> &r, int z) __attribute__((always_inline)) {
+    auto stage = [&](const OwnT<Param, T> &o, const PreT<Param, T> &r, int z) __attribute__((always_inline)) {
         if (lane_in) {
-            if (o.m) put_kin<T, NR>(sm.kin, own, o.k);
+            if (o.m) {
+                put_kin<T, NR>(sm.kin, own, o.k);
+                if constexpr (Param) { sm.pE[own] = o.E; sm.pM[own] = mass(o.rho); }
+            }
             sm.mat[own] = o.m;
         }
         if (ring) {
             uint8_t mr = 0;
             if (ring_in) {
-                Own<T> R{};
-                finish_pre<Chan>(a, tb, ring_col + (unsigned)z * nxy, r, R);
+                OwnT<Param, T> R{};
+                finish_pre<Chan, Param>(a, tb, ring_col + (unsigned)z * nxy, r, R);
                 mr = R.m;
-                if (mr) put_kin<T, NR>(sm.kin, ring_slot, R.k);
+                if (mr) {
+                    put_kin<T, NR>(sm.kin, ring_slot, R.k);
+                    if constexpr (Param) { sm.pE[ring_slot] = R.E; sm.pM[ring_slot] = mass(R.rho); }
+                }
             }
             sm.mat[ring_slot] = mr;
         }
     };
 
-    Own<T> A{}, B{};
-    if (inxy && z0 < z1) load_own<Chan>(a, sb, tb, col + (unsigned)z0 * nxy, A);
-    Pre<T> rp{};
-    if (ring_in && z0 < z1) issue_pre(a, sb, ring_col + (unsigned)z0 * nxy, rp);
+    OwnT<Param, T> A{}, B{};
+    if (inxy && z0 < z1) load_own<Chan, Param>(a, sb, tb, col + (unsigned)z0 * nxy, A);
+    PreT<Param, T> rp{};
+    if (ring_in && z0 < z1) issue_pre<Param>(a, sb, ring_col + (unsigned)z0 * nxy, rp);
 
     // bond from the slab below the chunk: only its voxel-2 half is needed
     bool has_carry = false;
     T cFx = T(0), cFy = T(0), cFz = T(0), cMx = T(0), cMy = T(0), cMz = T(0);
     if (A.m && z0 > 0) {
-        Own<T> P{};
-        load_own<Chan>(a, sb, tb, col + (unsigned)(z0 - 1) * nxy, P);
+        OwnT<Param, T> P{};
+        load_own<Chan, Param>(a, sb, tb, col + (unsigned)(z0 - 1) * nxy, P);
         if (P.m) {
             const Rot<T> Rp = rot_of(P.k.qw, P.k.qx, P.k.qy, P.k.qz);
-            const BondOut<T> o = bond_eval<T, 2>(P.k, Rp, A.k, tb.bond(P.m, A.m), C);
+            const BondOut<T> o =
+                bond_eval<T, 2>(P.k, Rp, A.k, bond_oo(P, A), C);
             cFx = o.f2x; cFy = o.f2y; cFz = o.f2z; cMx = o.m2x; cMy = o.m2y; cMz = o.m2z;
             has_carry = true;
         }
@@ -338,11 +402,11 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
     // z + 1, whose loads (own cell and ring cell) are issued at the start so
     // that they arrive during the bond evaluations, and which is staged in
     // LDS once every thread is past its bonds of slab z
-    auto slab = [&](Own<T> &cur, Own<T> &nxt, int z) __attribute__((always_inline)) {
-        Pre<T> pn{};
-        if (inxy && z + 1 < a.nz) issue_pre(a, sb, col + (unsigned)(z + 1) * nxy, pn);
+    auto slab = [&](OwnT<Param, T> &cur, OwnT<Param, T> &nxt, int z) __attribute__((always_inline)) {
+        PreT<Param, T> pn{};
+        if (inxy && z + 1 < a.nz) issue_pre<Param>(a, sb, col + (unsigned)(z + 1) * nxy, pn);
         rp.m = 0;
-        if (ring_in && z + 1 < z1) issue_pre(a, sb, ring_col + (unsigned)(z + 1) * nxy, rp);
+        if (ring_in && z + 1 < z1) issue_pre<Param>(a, sb, ring_col + (unsigned)(z + 1) * nxy, rp);
         __syncthreads();
 
         // bonds entering the tile from the ring: x from (-1, tid), y from
@@ -352,23 +416,30 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
             if (ml && mu) {
                 const VoxKin<T> kl = get_kin<T, NR>(sm.kin, bnd_lo), ku = get_kin<T, NR>(sm.kin, bnd_up);
                 const Rot<T> Rl = rot_of(kl.qw, kl.qx, kl.qy, kl.qz);
-                const BondOut<T> o = bond_eval_xy(kl, Rl, ku, tb.bond(ml, mu), C, bnd_y);
+                T El = T(0), Eu = T(0), Ml = T(0), Mu = T(0);
+                if constexpr (Param) { El = sm.pE[bnd_lo]; Eu = sm.pE[bnd_up]; Ml = sm.pM[bnd_lo]; Mu = sm.pM[bnd_up]; }
+                const BondOut<T> o = bond_eval_xy(kl, Rl, ku, bond_kc(ml, mu, El, Eu, Ml, Mu), C, bnd_y);
                 put_bond<T, NB>(sm.b[bnd_y ? 1 : 0], bnd_i, o);
             }
         }
         const Rot<T> Rc = rot_of(cur.k.qw, cur.k.qx, cur.k.qy, cur.k.qz);
+        // bond constants with the neighbour in LDS slot sl
+        auto kn = [&](uint8_t mu, int sl) __attribute__((always_inline)) {
+            if constexpr (Param) return bond_kc(cur.m, mu, cur.E, sm.pE[sl], mass(cur.rho), sm.pM[sl]);
+            else return tb.bond(cur.m, mu);
+        };
         {
             const uint8_t mu = lane_in ? sm.mat[own + 1] : 0;
             if (cur.m && mu) {
                 const VoxKin<T> ku = get_kin<T, NR>(sm.kin, own + 1);
-                put_bond<T, NB>(sm.b[0], (tx + 1) + (TX + 1) * ty, bond_eval<T, 0>(cur.k, Rc, ku, tb.bond(cur.m, mu), C));
+                put_bond<T, NB>(sm.b[0], (tx + 1) + (TX + 1) * ty, bond_eval<T, 0>(cur.k, Rc, ku, kn(mu, own + 1), C));
             }
         }
         {
             const uint8_t mu = lane_in ? sm.mat[own + RW] : 0;
             if (cur.m && mu) {
                 const VoxKin<T> ku = get_kin<T, NR>(sm.kin, own + RW);
-                put_bond<T, NB>(sm.b[1], tx + TX * (ty + 1), bond_eval<T, 1>(cur.k, Rc, ku, tb.bond(cur.m, mu), C));
+                put_bond<T, NB>(sm.b[1], tx + TX * (ty + 1), bond_eval<T, 1>(cur.k, Rc, ku, kn(mu, own + RW), C));
             }
         }
         // neighbour materials for the gather, read before the slab's LDS is
@@ -378,10 +449,11 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
             n_mx = sm.mat[own - 1] != 0; n_px = sm.mat[own + 1] != 0;
             n_my = sm.mat[own - RW] != 0; n_py = sm.mat[own + RW] != 0;
         }
-        finish_pre<Chan>(a, tb, col + (unsigned)(z + 1) * nxy, pn, nxt);
+        finish_pre<Chan, Param>(a, tb, col + (unsigned)(z + 1) * nxy, pn, nxt);
         const bool has_zb = cur.m && nxt.m;
         BondOut<T> oz{};
-        if (has_zb) oz = bond_eval<T, 2>(cur.k, Rc, nxt.k, tb.bond(cur.m, nxt.m), C);
+        if (has_zb)
+            oz = bond_eval<T, 2>(cur.k, Rc, nxt.k, bond_oo(cur, nxt), C);
         __syncthreads();
 
         // the bond results stay in LDS until the next slab's first barrier;
@@ -417,8 +489,17 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
                 Fx -= oz.f2x; Fy -= oz.f2y; Fz -= oz.f2z;
                 Mx += oz.m1x; My += oz.m1y; Mz += oz.m1z;
             }
-            voxel_update(a, col + (unsigned)z * nxy, cur.fl, tb.mat[cur.m], cur.eps, cur.r, Fx, Fy, Fz, Mx, My,
-                         Mz, &vmax, [&](unsigned c, const VoxRaw<T> &o) { sb_store(sb, c, o); });
+            if constexpr (Param) {
+                if (a.fm_out) {
+                    const long long st = a.stride, c = col + (unsigned)z * nxy;
+                    a.fm_out[0 * st + c] = Fx; a.fm_out[1 * st + c] = Fy; a.fm_out[2 * st + c] = Fz;
+                    a.fm_out[3 * st + c] = Mx; a.fm_out[4 * st + c] = My; a.fm_out[5 * st + c] = Mz;
+                }
+            }
+            with_mc<Param>(a, tb, cur, [&](const MatConst<T> &mc) __attribute__((always_inline)) {
+                voxel_update(a, col + (unsigned)z * nxy, cur.fl, mc, cur.eps, cur.r, Fx, Fy, Fz, Mx, My, Mz, &vmax,
+                             [&](unsigned c, const VoxRaw<T> &o) { sb_store(sb, c, o); });
+            });
         }
         has_carry = has_zb;
         cFx = oz.f2x; cFy = oz.f2y; cFz = oz.f2z; cMx = oz.m2x; cMy = oz.m2y; cMz = oz.m2z;
@@ -434,11 +515,11 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
 // FP32 is held to 168 VGPRs, so that three workgroups share a CU (three
 // waves per SIMD; two loop-invariant values go to scratch); FP64 needs more
 // than 256 and runs one wave per SIMD.
-template <typename T, int TX, int TY, bool Chan>
+template <typename T, int TX, int TY, bool Chan, bool Param>
 __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
 k_fused(StepArgs<T> a, FusedGrid g) {
     static_assert(2 * (TX + TY) <= TX * TY, "ring must fit one cell per thread");
-    __shared__ TileSmem<T, TX, TY> sm;
+    __shared__ typename std::conditional<Param, TileSmemP<T, TX, TY>, TileSmem<T, TX, TY>>::type sm;
     extern __shared__ __align__(16) unsigned char dyn[];
     const Tables<T> tb = stage_tables(a, dyn, TX * TY);
     const LatK<T> C = lat_consts(a.l);
@@ -455,7 +536,7 @@ k_fused(StepArgs<T> a, FusedGrid g) {
     __syncthreads();
 
     T vmax = T(0);
-    march<Chan>(a, sm, tb, C, TX, TY, tile_x, tile_y, z0, z1, vmax);
+    march<Chan, Param>(a, sm, tb, C, TX, TY, tile_x, tile_y, z0, z1, vmax);
     if (a.track_vmax) wave_vmax(a.vmax_bits, vmax);
 }
 
@@ -504,7 +585,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchArgs<T> b) {
             const int tiles_x = (ob.nx + ob.tx - 1) / ob.tx, tiles_y = (ob.ny + ob.ty - 1) / ob.ty;
             for (int ty = 0; ty < tiles_y; ++ty)
                 for (int tx = 0; tx < tiles_x; ++tx)
-                    march<false>(a, sm, tb, C, ob.tx, ob.ty, tx, ty, 0, ob.nz, vmax);
+                    march<false, false>(a, sm, tb, C, ob.tx, ob.ty, tx, ty, 0, ob.nz, vmax);
         }
         // this step's writes are the next step's reads (same workgroup)
         __syncthreads();
@@ -523,10 +604,14 @@ hipError_t launch_tiles(const StepArgs<T> &a, int zc, bool chan, hipStream_t s) 
     g.zc = zc;
     g.chunks = (a.nz + zc - 1) / zc;
     const long long nwg = cols * g.chunks;
-    if (chan)
-        k_fused<T, TX, TY, true><<<(unsigned)nwg, TX * TY, tables_bytes<T>(a.n_mat), s>>>(a, g);
+    // parameter mode takes the variant with the channel test (a voxel without
+    // a channel follows the global signal there too)
+    if (a.E_cell)
+        k_fused<T, TX, TY, true, true><<<(unsigned)nwg, TX * TY, tables_bytes<T>(a.n_mat), s>>>(a, g);
+    else if (chan)
+        k_fused<T, TX, TY, true, false><<<(unsigned)nwg, TX * TY, tables_bytes<T>(a.n_mat), s>>>(a, g);
     else
-        k_fused<T, TX, TY, false><<<(unsigned)nwg, TX * TY, tables_bytes<T>(a.n_mat), s>>>(a, g);
+        k_fused<T, TX, TY, false, false><<<(unsigned)nwg, TX * TY, tables_bytes<T>(a.n_mat), s>>>(a, g);
     return hipGetLastError();
 }
 

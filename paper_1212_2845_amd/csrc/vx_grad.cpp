@@ -103,7 +103,11 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
             a.flags_out = i + 1 < len ? fl_ptr(i + 1) : (uint8_t *)(gw + G.seg_flags);
             a.fm_out = (T *)(gw + G.fm + (uint64_t)i * fmb);
             a.track_vmax = 0;
-            HIP_OK(h, launch_split_step<T>(a, s));
+            if (h->use_split()) {
+                HIP_OK(h, launch_split_step<T>(a, s));
+            } else {
+                HIP_OK(h, launch_fused_step<T>(a, fused_cfg(h), s));
+            }
         }
         for (int i = len - 1; i >= 0; --i) {
             StepArgs<T> a = make_args<T>(h);

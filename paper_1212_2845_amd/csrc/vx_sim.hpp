@@ -97,16 +97,15 @@ struct vx_sim {
     bool flags_live = false;              // device flags hold dynamic bits
     int fused_shape = -1;                 // tile shape of the fused kernel (-1: heuristic)
     int fused_zc = 0;                     // z chunk of the fused kernel (0: heuristic)
-    // parameter mode (split kernels): per-cell elastic modulus and density;
-    // a quantity not set per cell takes its palette value
+    // parameter mode: per-cell elastic modulus and density; a quantity not
+    // set per cell takes its palette value
     bool has_E = false, has_rho = false;
     std::vector<double> E_cell, rho_cell;
     bool param_mode() const { return has_E || has_rho; }
-    // the split kernels run when asked for, for palettes over 16 materials,
-    // in parameter mode and for state arrays beyond the fused kernel's span
+    // the split kernels run when asked for, for palettes over 16 materials
+    // and for state arrays beyond the fused kernel's span
     bool use_split() const {
-        return kernel_kind == 1 || n_mat > vx::kFusedMaxMat || param_mode() ||
-               !vx::fused_state_fits(ncell, precision / 8);
+        return kernel_kind == 1 || n_mat > vx::kFusedMaxMat || !vx::fused_state_fits(ncell, precision / 8);
     }
     double wmax = 0.0;                    // sqrt(k_b / m_min) the timestep was chosen for
     // differentiable rollouts
@@ -262,3 +261,29 @@ inline vx::CollideArgs make_collide(vx_sim *h) {
     return c;
 }
 
+// Tile shape of the fused kernel: the one wasting the fewest lanes on the
+// lattice's x-y extent, with the ring (halo) and boundary-bond overhead of
+// small tiles as a tie breaker.
+inline int heuristic_shape(const vx_sim *h) {
+    int best = 0;
+    double best_cost = 1e300;
+    for (int i = 0; i < vx::kNumFusedShapes; ++i) {
+        const int tx = vx::kFusedShapes[i].tx, ty = vx::kFusedShapes[i].ty;
+        const double padded = (double)((h->nx + tx - 1) / tx * tx) * (double)((h->ny + ty - 1) / ty * ty);
+        const double slots = padded / ((double)h->nx * h->ny);
+        const double halo = 2.0 * (tx + ty) / (double)(tx * ty);
+        const double cost = slots * (1.0 + 0.3 * halo);
+        if (cost < best_cost - 1e-12) { best_cost = cost; best = i; }
+    }
+    return best;
+}
+
+// Launch configuration of the fused step kernel: the chosen or heuristic
+// tile shape, the z chunk, and whether any voxel follows a named channel.
+inline vx::FusedCfg fused_cfg(const vx_sim *h) {
+    vx::FusedCfg c;
+    c.shape = h->fused_shape >= 0 ? h->fused_shape : heuristic_shape(h);
+    c.zc = h->fused_zc;
+    c.chan = h->any_chan ? 1 : 0;
+    return c;
+}

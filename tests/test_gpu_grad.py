@@ -12,7 +12,9 @@ checkpoint segments that do not divide the step count.
 import numpy as np
 import pytest
 
+import oracle
 import paper_1212_2845_amd as vx
+import test_gpu_parity
 import workloads
 from gradcheck import fd_density, fd_direction, fd_modulus, fd_phase, loss_weights, oracle_loss
 from parity import build_oracle, compare
@@ -66,6 +68,71 @@ def test_parameter_mode_forward_matches_oracle(scenario):
     assert o.step(w["steps"]) == 0
     e = compare(s.read_state(), o.read_state(), w["grid"].reshape(-1) > 0)
     assert max(e["u"], e["v"], e["w"]) < 1e-10 and e["q"] < 1e-12, e
+
+
+def per_voxel_params(w, seed):
+    """Per-voxel moduli at most the palette's and densities at least its
+    (every bond within the timestep's bound)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = w["grid"].reshape(-1)
+    E = palette_field(w, "E") * rng.uniform(0.4, 1.0, g.size)
+    rho = palette_field(w, "rho") * rng.uniform(1.0, 2.5, g.size)
+    return np.where(g > 0, E, 0.0), np.where(g > 0, rho, 0.0)
+
+
+@pytest.mark.parametrize("kernel", [vx.KERNEL_FUSED, vx.KERNEL_SPLIT])
+def test_per_voxel_moduli_and_densities_match_oracle(kernel):
+    """Distinct modulus and density in every voxel (parameter mode of the
+    fused and of the split kernels) against the oracle given one palette
+    material per voxel with those values, the same timestep, 300 steps on
+    the floor with gravity, actuation and a perturbed start: FP64 1e-10."""
+    w = test_gpu_parity.hetero_block(shape=(6, 6, 6), seed=91)
+    w["params"] = dict(w["params"], gravity=9.81, floor_on=1, zeta_col=0.5)
+    E, rho = per_voxel_params(w, 92)
+    announce("per-voxel moduli vs oracle kernel=%d" % kernel)
+    s = vx.from_workload(w, precision=64, kernel=kernel)
+    s.write_state(**w["state"])
+    s.set_stiffness(E)
+    s.set_density(rho)
+    g = w["grid"].reshape(-1)
+    cells = np.flatnonzero(g)
+    assert len(cells) < 255
+    mats = [w["materials"][0]] + [dict(w["materials"][g[c]], E=float(E[c]), rho=float(rho[c])) for c in cells]
+    grid2 = np.zeros(g.size, np.uint8)
+    grid2[cells] = np.arange(1, len(cells) + 1)
+    w2 = dict(w, grid=grid2.reshape(w["grid"].shape), materials=mats)
+    own = oracle.Sim(w2["grid"], mats, **dict(w["params"], dt_scale=1.0)).dt
+    w2["params"] = dict(w["params"], dt_scale=s.dt / own)
+    o = build_oracle(w2)
+    assert abs(o.dt / s.dt - 1) < 1e-15
+    s.step(300)
+    assert o.step(300) == 0
+    e = compare(s.read_state(), o.read_state(), g > 0)
+    assert max(e["u"], e["v"], e["w"]) < 1e-10 and e["q"] < 1e-12, e
+
+
+@pytest.mark.parametrize("precision,tol", [(64, 1e-12), (32, 1e-5)])
+def test_parameter_mode_fused_matches_split(precision, tol):
+    """Parameter mode through the fused kernel (several tiles, two z
+    chunks) and through the split kernels: the same device arithmetic, equal
+    to rounding; the fused kernel bitwise equal run to run."""
+    w = test_gpu_parity.hetero_block(shape=(24, 13, 11), seed=93)
+    E, rho = per_voxel_params(w, 94)
+    announce("parameter mode fused vs split p=%d" % precision)
+    out = []
+    for kernel in (vx.KERNEL_FUSED, vx.KERNEL_FUSED, vx.KERNEL_SPLIT):
+        s = vx.from_workload(w, precision=precision, kernel=kernel)
+        s.write_state(**w["state"])
+        s.set_stiffness(E)
+        s.set_density(rho)
+        if kernel == vx.KERNEL_FUSED:
+            s.set_fused_tile(2, 6)          # 16 x 16 tiles: 2 x 1 tiles, chunks of 6 slabs
+        s.step(200)
+        out.append(s.read_state())
+    for k in ("u", "q", "v", "w"):
+        assert np.array_equal(out[0][k], out[1][k])
+    e = compare(out[2], out[0], w["grid"].reshape(-1) > 0)
+    assert max(e["u"], e["v"]) < tol and e["q"] < tol, e
 
 
 def smooth_fd(f, w, wu, wv, keys):
@@ -276,11 +343,11 @@ def test_design_lattice_gradient_full_size():
     steps, the bench's configuration), loss = mean x displacement.  The
     blocks share no bond, so each block's gradients must equal those of the
     same block run alone; the small runs are the regime the oracle
-    comparisons above cover.  The forward is bitwise the same; the reverse
-    bond pass evaluates a bond that crosses a tile edge in a second inlined
-    copy of the same code, which the compiler may contract differently, and
-    the block sits on other tile edges in the lattice than alone, so the
-    bar is FP32 rounding (1e-5 of each gradient's largest entry).  Central
+    comparisons above cover.  Forward and reverse evaluate a bond that
+    crosses a tile edge in a second inlined copy of the same code, which
+    the compiler may contract differently, and the block sits on other tile
+    edges in the lattice than alone, so the bar is FP32 rounding (1e-5 of
+    each gradient's largest entry).  Central
     differences are no check at this size: with half a million voxels on
     a floor, some voxel always sits at the static-friction threshold, where
     the step zeroes its lateral momentum, so the loss jumps inside any
