@@ -196,7 +196,7 @@ def roofline(precision, nvox, kernel_ms, workload=None, tile=None, kernel="k_fus
     return out
 
 
-def time_batch(count, steps, one_by_one_sample=64, one_by_one_steps=100):
+def time_batch(count, steps, one_by_one_sample=256, one_by_one_steps=100):
     """Batched objects: one persistent launch for all objects vs the same
     objects stepped one at a time through the single-lattice path."""
     import torch
@@ -226,10 +226,12 @@ def time_batch(count, steps, one_by_one_sample=64, one_by_one_steps=100):
                                note="kernel_ms is per step: one persistent launch runs all steps")}
     if one_by_one_sample <= 0:
         return result
-    # one at a time: a sample of the same objects, each its own lattice,
-    # every object's steps recorded into one HIP graph (stream capture of
-    # vx_step_enqueue) and replayed, so that launch overhead is not counted
-    sample = objs[:one_by_one_sample]
+    # one at a time: every k-th object of the same batch (a sample with the
+    # batch's mix of sizes and classes), each its own lattice, every object's
+    # steps recorded into one HIP graph (stream capture of vx_step_enqueue)
+    # and replayed, so that launch overhead is not counted
+    stride = max(1, count // one_by_one_sample)
+    sample = objs[::stride][:one_by_one_sample]
     side = torch.cuda.Stream()
     sims = [vx.from_workload(o, precision=32, stream=side.cuda_stream) for o in sample]
     for s in sims:
@@ -267,9 +269,13 @@ def time_batch(count, steps, one_by_one_sample=64, one_by_one_steps=100):
     return dict(result, **{
             "one_by_one": {"value": single, "objects": len(sample), "steps": one_by_one_steps,
                            "eager_value": single_eager,
-                           "note": "first %d objects, each stepped alone through the fused single-lattice "
-                                   "path; value: all these objects' steps in one captured HIP graph, "
-                                   "replayed; eager_value: one vx_step call per object" % len(sample)},
+                           "voxels": nvox1,
+                           "note": "a sample of the batch: every %d-th of its %d objects (%d objects, %d voxels, "
+                                   "the batch's mix of sizes), %d steps each, each stepped alone through the "
+                                   "fused single-lattice path; value: all these objects' steps in one captured HIP "
+                                   "graph, replayed; eager_value: one vx_step call per object; the speedup compares "
+                                   "voxel-step rates (batch: all objects, %d steps)"
+                                   % (stride, count, len(sample), nvox1, one_by_one_steps, steps)},
             "speedup": batched / single})
 
 
@@ -311,9 +317,8 @@ def time_adjoint(steps=5000, K=100):
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
     del s
-    # the same lattice with the palette's moduli runs the fused step kernel:
-    # the fastest plain forward of this lattice, which parameter mode does
-    # not reach
+    # the same lattice with the palette's moduli (no per-voxel constants to
+    # derive): the fastest plain forward of this lattice
     s = vx.from_workload(w, precision=32, stream=stream.cuda_stream)
     s.bind()
     s.step(5)
@@ -343,11 +348,11 @@ def time_adjoint(steps=5000, K=100):
             "fused_forward_s": t_fused, "fwd_adj_over_fused_fwd": t_fa / t_fused, "target_fwd_adj_over_fwd": 4.0,
             "value": nvox * steps / t_fa, "unit": "voxel-steps/s (forward + reverse)",
             "grad_E_absmax": float(np.abs(g["E"]).max()), "grad_phase_absmax": float(np.abs(g["phase"]).max()),
-            "note": "forward_s: the plain forward in parameter mode (per-voxel moduli), which runs the split "
-                    "kernels, as the recorded forward and the recompute do; fused_forward_s: the same lattice with "
-                    "the palette's moduli through the fused step kernel, the fastest plain forward; the target is "
-                    "fwd+adj <= 4 x fwd; wall time with host synchronisation at each checkpoint and the host "
-                    "copies of the adjoint in and the gradients out"}
+            "note": "forward_s: the plain forward in parameter mode (per-voxel moduli) through the fused step "
+                    "kernel, which the recorded forward and the segment recompute also run; fused_forward_s: the "
+                    "same lattice with the palette's moduli; the target is fwd+adj <= 4 x fwd; wall time with host "
+                    "synchronisation at each checkpoint and the host copies of the adjoint in and the gradients "
+                    "out"}
 
 
 def time_collision_schemes(steps=5000, graph=True):
@@ -621,7 +626,7 @@ def main():
                          "leg's eager rates only (for profiler counter runs, which do not follow graph replays)")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
     ap.add_argument("--batch-objects", type=int, default=4096)
-    ap.add_argument("--one-by-one-sample", type=int, default=64,
+    ap.add_argument("--one-by-one-sample", type=int, default=256,
                     help="objects in the one-at-a-time comparison of the batched leg (0 skips it, e.g. "
                          "under profiler counter collection, which does not follow graph launches)")
     ap.add_argument("--batch-steps", type=int, default=2000)

@@ -62,6 +62,24 @@ def test_batch_matches_single_objects(precision, tol):
         assert max(e["u"], e["v"], e["w"]) < tol and e["q"] < tol, (i, e)
 
 
+def test_batch_thin_objects_match_single_objects():
+    """Objects one or two cells thick and long in y, and one longer than a
+    tile in x: the batch kernel's tile (at most 64 x 64 cells, 256 in all)
+    covers each, FP64 equal to the single-lattice path to rounding."""
+    rng = np.random.Generator(np.random.PCG64(51))
+    shapes = [(3, 100, 1), (4, 150, 2), (3, 1, 70), (2, 70, 3), (5, 5, 5)]
+    grids = [rng.integers(1, 5, size=sh).astype(np.uint8) for sh in shapes]
+    states = [perturbed_state(g.size, 60 + i, 1e-6, 1e-3, 0.5, 1e-3) for i, g in enumerate(grids)]
+    announce("batch of thin objects")
+    b = run_batch(grids, states, 100, 64)
+    for i, g in enumerate(grids):
+        s = vx.Sim(g, MATS, precision=64, **PARAMS)
+        s.write_state(**states[i])
+        s.step(100)
+        e = compare(b.read_state(i), s.read_state(), g.reshape(-1) > 0)
+        assert max(e["u"], e["v"], e["w"]) < 1e-12 and e["q"] < 1e-12, (i, shapes[i], e)
+
+
 def test_batch_matches_oracle_fp64():
     grids, states = make_objects(4, seed=21, lo=3, hi=7)
     announce("batch vs oracle")

@@ -91,9 +91,9 @@ def test_per_voxel_moduli_and_densities_match_oracle(kernel):
     E, rho = per_voxel_params(w, 92)
     announce("per-voxel moduli vs oracle kernel=%d" % kernel)
     s = vx.from_workload(w, precision=64, kernel=kernel)
-    s.write_state(**w["state"])
     s.set_stiffness(E)
     s.set_density(rho)
+    s.write_state(**w["state"])        # velocities to momenta with the voxels' own masses
     g = w["grid"].reshape(-1)
     cells = np.flatnonzero(g)
     assert len(cells) < 255
@@ -122,9 +122,9 @@ def test_parameter_mode_fused_matches_split(precision, tol):
     out = []
     for kernel in (vx.KERNEL_FUSED, vx.KERNEL_FUSED, vx.KERNEL_SPLIT):
         s = vx.from_workload(w, precision=precision, kernel=kernel)
-        s.write_state(**w["state"])
         s.set_stiffness(E)
         s.set_density(rho)
+        s.write_state(**w["state"])
         if kernel == vx.KERNEL_FUSED:
             s.set_fused_tile(2, 6)          # 16 x 16 tiles: 2 x 1 tiles, chunks of 6 slabs
         s.step(200)

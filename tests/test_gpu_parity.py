@@ -293,12 +293,24 @@ def _neighbourhood_oracle(w, state, cell, nx, ny, nz, dt):
     return {k: r[k][13] for k in r}
 
 
-@pytest.mark.parametrize("precision,tol", [(64, 1e-10), (32, 1e-4)])
-def test_full_size_blob_lattice_sampled(precision, tol):
+# One FP32 step from a perturbed state (rotations of 1e-3 rad on 1 mm
+# voxels), error over the larger of the oracle's value and the start value,
+# per quantity.  The velocity bar is the loosest: the step's change of
+# velocity (up to eight times the start velocity) is the net of bond forces
+# whose rotational and translational parts nearly cancel, so FP32 rounding
+# of the terms shows up amplified in the net (measured on the samples:
+# u 5.7e-6, v 2.3e-5, w 5.5e-7, q 8.7e-8).
+FP32_ONE_STEP = {"u": 2e-5, "v": 5e-5, "w": 2e-6, "q": 5e-7}
+FP64_ONE_STEP = {"u": 1e-10, "v": 1e-10, "w": 1e-10, "q": 1e-10}
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_full_size_blob_lattice_sampled(precision):
     """256^3 lattice of the HBM-resident benchmark, in the launch
     configuration bench.py times (fused kernel, autotuned tile): one step
     from a perturbed state, then 48 sampled voxels (interior, faces, edges,
     corners) recomputed one by one by the oracle on their neighbourhood."""
+    tols = FP64_ONE_STEP if precision == 64 else FP32_ONE_STEP
     n = 256
     w = workloads.blob_lattice(n=n, seed=3)
     w["params"]["temp_phase"] = 0.7      # non-zero temperature at t = 0
@@ -320,11 +332,11 @@ def test_full_size_blob_lattice_sampled(precision, tol):
         for k in ("u", "v", "w", "q"):
             scale = max(np.abs(ref[k]).max(), np.abs(st[k][c]).max(), 1e-30)
             err = np.abs(out[k][c] - ref[k]).max() / scale
-            assert err < tol, (c, k, err, out[k][c], ref[k])
+            assert err < tols[k], (c, k, err, out[k][c], ref[k])
 
 
-@pytest.mark.parametrize("precision,tol", [(64, 1e-10), (32, 1e-4)])
-def test_full_size_random_block_sampled(precision, tol):
+@pytest.mark.parametrize("precision", [64, 32])
+def test_full_size_random_block_sampled(precision):
     """100^3 random block of the headline benchmark (same grid and
     materials), placed on the floor and moving down at impact speed, in the
     launch configuration bench.py times (fused kernel, autotuned tile): one
@@ -333,6 +345,7 @@ def test_full_size_random_block_sampled(precision, tol):
     friction), then 48 sampled filled voxels (24 of the bottom layer, corners,
     the rest at random) recomputed one by one by the oracle on their
     neighbourhood."""
+    tols = FP64_ONE_STEP if precision == 64 else FP32_ONE_STEP
     n = 100
     w = workloads.random_block(n=n, seed=2, impact=True)
     ncell = n ** 3
@@ -360,7 +373,7 @@ def test_full_size_random_block_sampled(precision, tol):
         for k in ("u", "v", "w", "q"):
             scale = max(np.abs(ref[k]).max(), np.abs(st[k][c]).max(), 1e-30)
             err = np.abs(out[k][c] - ref[k]).max() / scale
-            assert err < tol, (c, k, err, out[k][c], ref[k])
+            assert err < tols[k], (c, k, err, out[k][c], ref[k])
     assert in_contact >= 5, in_contact
 
 
