@@ -303,9 +303,10 @@ int vx_static_solve_noalloc(vx_handle h, const double *F, double rel_tol, int32_
 int vx_set_collision_mode(vx_handle h, int32_t all_voxels, int32_t every_step);
 
 /* Select the step implementation: 0 = fused LDS-tiled kernel (default;
- * palettes of more than 16 materials, parameter mode and lattices whose
- * state array (13 words per cell) spans 2 GiB or more always use the split
- * path), 1 = split per-axis bond kernels plus a gather kernel. */
+ * palettes of more than 16 materials and lattices whose state array (13
+ * words per cell) spans 4 GiB or more, i.e. beyond about 82 million cells
+ * in FP32 or 41 million in FP64, always use the split path), 1 = split
+ * per-axis bond kernels plus a gather kernel. */
 int vx_set_kernel(vx_handle h, int32_t kind);
 
 /* Tile of the fused kernel: shape index 0..4 = 32x8, 64x4, 16x16, 50x5,
@@ -318,7 +319,7 @@ int vx_get_fused_tile(vx_handle h, int32_t *shape, int32_t *tx, int32_t *ty, int
 /* Time every fused tile shape and z chunk on this lattice (iters launches
  * each, from the current state, without advancing it) and keep the fastest.
  * Errors: VX_ESTATE before bind, for a palette of more than 16 materials or
- * a state array spanning 2 GiB or more (the fused kernel does not run). */
+ * a state array spanning 4 GiB or more (the fused kernel does not run). */
 int vx_autotune(vx_handle h, int32_t iters, int32_t *shape, int32_t *zc);
 
 /* Average wall time of one launch of the step kernel(s) alone (the fused
@@ -447,7 +448,7 @@ typedef struct vx_batch_sim *vx_batch;
  * voxel gathers its contact force from its own candidate list (no
  * atomics), and all objects step with the smallest of their stable
  * timesteps, one launch per step.  Errors: VX_EINVAL as vx_create, or if
- * one state array (13 words per cell of all objects) would span 2 GiB or
+ * one state array (13 words per cell of all objects) would span 4 GiB or
  * more, or an object with a non-zero reserved field or a non-finite origin. */
 int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *palette, int32_t n_mat,
                     const vx_params *params, int32_t precision, void *stream, vx_batch *out);

@@ -94,23 +94,28 @@ __device__ __forceinline__ void put_bond(T (*b)[NB], int i, const BondOut<T> &o)
 // (c * sizeof(T)) and no per-word 64-bit address is formed or kept: with
 // one pointer per word the two state arrays alone take 52 scalar
 // registers, which the compiler spills into vector lanes and reads back
-// before every load and store.  The descriptor spans the 13 words; the host
-// runs this kernel only when that span is below 2^31 bytes.
+// before every load and store.  The descriptor spans the 13 words; its
+// record count, the per-lane offset and the per-word offset are unsigned
+// 32-bit byte counts, so the host runs this kernel only when that span is
+// below 2^32 bytes.
 constexpr int kRsrcWord3 = 0x00020000;   // raw 32-bit data format, gfx9 family
 
 template <typename T>
 struct StateBuf {
     __amdgpu_buffer_rsrc_t in, out;
-    int wb;   // bytes from one state word to the next
+    unsigned wb;   // bytes from one state word to the next
+    // scalar offset of word w, as the unsigned 32-bit pattern the
+    // instruction takes
+    __device__ __forceinline__ int word(int w) const { return (int)((unsigned)w * wb); }
 };
 
 template <typename T>
 __device__ __forceinline__ StateBuf<T> state_buf(const StepArgs<T> &a) {
     StateBuf<T> b;
-    const int bytes = (int)(N_WORDS * a.stride * (long long)sizeof(T));
-    b.in = __builtin_amdgcn_make_buffer_rsrc((void *)a.s_in, 0, bytes, kRsrcWord3);
-    b.out = __builtin_amdgcn_make_buffer_rsrc((void *)a.s_out, 0, bytes, kRsrcWord3);
-    b.wb = (int)(a.stride * (long long)sizeof(T));
+    const unsigned bytes = (unsigned)(N_WORDS * a.stride * (long long)sizeof(T));
+    b.in = __builtin_amdgcn_make_buffer_rsrc((void *)a.s_in, 0, (int)bytes, kRsrcWord3);
+    b.out = __builtin_amdgcn_make_buffer_rsrc((void *)a.s_out, 0, (int)bytes, kRsrcWord3);
+    b.wb = (unsigned)(a.stride * (long long)sizeof(T));
     return b;
 }
 
@@ -134,26 +139,26 @@ template <typename T>
 __device__ __forceinline__ VoxRaw<T> sb_load(const StateBuf<T> &b, unsigned c) {
     const unsigned o = c * (unsigned)sizeof(T);
     VoxRaw<T> r;
-    r.ux = buf_ld<T>(b.in, o, 0);           r.uy = buf_ld<T>(b.in, o, W_UY * b.wb);
-    r.uz = buf_ld<T>(b.in, o, W_UZ * b.wb); r.qw = buf_ld<T>(b.in, o, W_QW * b.wb);
-    r.qx = buf_ld<T>(b.in, o, W_QX * b.wb); r.qy = buf_ld<T>(b.in, o, W_QY * b.wb);
-    r.qz = buf_ld<T>(b.in, o, W_QZ * b.wb); r.px = buf_ld<T>(b.in, o, W_PX * b.wb);
-    r.py = buf_ld<T>(b.in, o, W_PY * b.wb); r.pz = buf_ld<T>(b.in, o, W_PZ * b.wb);
-    r.lx = buf_ld<T>(b.in, o, W_LX * b.wb); r.ly = buf_ld<T>(b.in, o, W_LY * b.wb);
-    r.lz = buf_ld<T>(b.in, o, W_LZ * b.wb);
+    r.ux = buf_ld<T>(b.in, o, 0);           r.uy = buf_ld<T>(b.in, o, b.word(W_UY));
+    r.uz = buf_ld<T>(b.in, o, b.word(W_UZ)); r.qw = buf_ld<T>(b.in, o, b.word(W_QW));
+    r.qx = buf_ld<T>(b.in, o, b.word(W_QX)); r.qy = buf_ld<T>(b.in, o, b.word(W_QY));
+    r.qz = buf_ld<T>(b.in, o, b.word(W_QZ)); r.px = buf_ld<T>(b.in, o, b.word(W_PX));
+    r.py = buf_ld<T>(b.in, o, b.word(W_PY)); r.pz = buf_ld<T>(b.in, o, b.word(W_PZ));
+    r.lx = buf_ld<T>(b.in, o, b.word(W_LX)); r.ly = buf_ld<T>(b.in, o, b.word(W_LY));
+    r.lz = buf_ld<T>(b.in, o, b.word(W_LZ));
     return r;
 }
 
 template <typename T>
 __device__ __forceinline__ void sb_store(const StateBuf<T> &b, unsigned c, const VoxRaw<T> &v) {
     const unsigned o = c * (unsigned)sizeof(T);
-    buf_st<T>(b.out, o, 0, v.ux);           buf_st<T>(b.out, o, W_UY * b.wb, v.uy);
-    buf_st<T>(b.out, o, W_UZ * b.wb, v.uz); buf_st<T>(b.out, o, W_QW * b.wb, v.qw);
-    buf_st<T>(b.out, o, W_QX * b.wb, v.qx); buf_st<T>(b.out, o, W_QY * b.wb, v.qy);
-    buf_st<T>(b.out, o, W_QZ * b.wb, v.qz); buf_st<T>(b.out, o, W_PX * b.wb, v.px);
-    buf_st<T>(b.out, o, W_PY * b.wb, v.py); buf_st<T>(b.out, o, W_PZ * b.wb, v.pz);
-    buf_st<T>(b.out, o, W_LX * b.wb, v.lx); buf_st<T>(b.out, o, W_LY * b.wb, v.ly);
-    buf_st<T>(b.out, o, W_LZ * b.wb, v.lz);
+    buf_st<T>(b.out, o, 0, v.ux);           buf_st<T>(b.out, o, b.word(W_UY), v.uy);
+    buf_st<T>(b.out, o, b.word(W_UZ), v.uz); buf_st<T>(b.out, o, b.word(W_QW), v.qw);
+    buf_st<T>(b.out, o, b.word(W_QX), v.qx); buf_st<T>(b.out, o, b.word(W_QY), v.qy);
+    buf_st<T>(b.out, o, b.word(W_QZ), v.qz); buf_st<T>(b.out, o, b.word(W_PX), v.px);
+    buf_st<T>(b.out, o, b.word(W_PY), v.py); buf_st<T>(b.out, o, b.word(W_PZ), v.pz);
+    buf_st<T>(b.out, o, b.word(W_LX), v.lx); buf_st<T>(b.out, o, b.word(W_LY), v.ly);
+    buf_st<T>(b.out, o, b.word(W_LZ), v.lz);
 }
 
 // Own voxel of one slab: material, flags, strain, raw state, kinematics.

@@ -87,9 +87,9 @@ hipError_t launch_static_dir(long long ncell, double beta, const double *z, doub
 // Largest palette whose tables fit the fused kernel's LDS.
 constexpr int kFusedMaxMat = 16;
 // The fused and batched kernels address all state words of one state array
-// through one buffer descriptor, whose byte span must stay below 2^31.
+// through one buffer descriptor, whose byte span must stay below 2^32.
 inline bool fused_state_fits(long long stride, int tsize) {
-    return (long long)N_WORDS * stride * tsize < (1LL << 31);
+    return (long long)N_WORDS * stride * tsize < (1LL << 32);
 }
 
 template <typename T>

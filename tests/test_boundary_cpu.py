@@ -273,8 +273,8 @@ def test_grad_bind_rejects_self_collision():
 
 def test_batch_state_span_limit():
     # the batched kernel addresses one state array (13 words per cell of all
-    # objects) through one buffer descriptor: the array must span < 2^31 B
-    lim = ((1 << 31) + 13 * 8 - 1) // (13 * 8)   # first FP64 cell count at or over 2^31 B
+    # objects) through one buffer descriptor: the array must span < 2^32 B
+    lim = ((1 << 32) + 13 * 8 - 1) // (13 * 8)   # first FP64 cell count at or over 2^32 B
     mats = [workloads.EMPTY, M1]
     b = vx.Batch([np.zeros((1, 1, lim - 1), np.uint8)], mats, precision=64)
     assert b.n == 1

@@ -186,3 +186,30 @@ def test_momentum_conserved_across_tiles(shape_id):
     P1 = np.array(s.energy()["momentum"])
     print(P0, P1, np.abs(P1 - P0).max() / scale, flush=True)
     assert np.abs(P1 - P0).max() <= 1e-13 * scale
+
+
+def test_fused_kernel_beyond_2_gib_state_span():
+    """A 350^3 FP32 lattice (42.9M cells: each state array spans 2.2 GB,
+    beyond 2^31 bytes) runs the fused kernel (the autotuner accepts it) and
+    equals the split path to FP32 rounding after 20 steps of a block
+    dropped onto the floor with gravity (largest displacement 1e-5)."""
+    n = 350
+    g = np.ones((n, n, n), np.uint8)
+    params = workloads._base_params(gravity=9.81, floor_on=1, zeta_bond=0.5, zeta_col=0.5)
+    params["origin"] = (0.0, 0.0, -2e-6)          # the bottom layer starts pressed into the floor
+    announce("fused beyond 2 GiB span")
+    out = {}
+    for kernel in (vx.KERNEL_FUSED, vx.KERNEL_SPLIT):
+        s = vx.Sim(g, [workloads.EMPTY, workloads._mat(1e6)], precision=32, kernel=kernel, **params)
+        s.bind()
+        if kernel == vx.KERNEL_FUSED:
+            s.autotune(iters=1)
+        s.step(20)
+        st = s.read_state()
+        out[kernel] = {k: st[k].astype(np.float32) for k in ("u", "v")}
+        del s, st
+    a, b = out[vx.KERNEL_FUSED], out[vx.KERNEL_SPLIT]
+    scale = np.abs(b["u"]).max()
+    assert scale > 1e-7
+    assert np.abs(a["u"] - b["u"]).max() <= 1e-5 * scale
+    assert np.abs(a["v"] - b["v"]).max() <= 1e-5 * np.abs(b["v"]).max()
