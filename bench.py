@@ -137,17 +137,17 @@ def fused_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision, tile):
+def measured_traffic(workload, precision, tile, key=None):
     """HBM bytes per launch of the fused kernel (rocprofv3 FETCH_SIZE +
     WRITE_SIZE, scaled by a plain copy's readings) from profiles/traffic.json,
     or None when none was taken for this workload and tile on the current
-    kernel source."""
+    kernel source.  key names another entry (the batch kernel's, per step)."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
-    if tile is None or not os.path.exists(p):
+    if (tile is None and key is None) or not os.path.exists(p):
         return None
     with open(p) as fh:
         db = json.load(fh)
-    e = db.get("%s|f%d|tile%d:%d" % (workload, precision, tile["shape"], tile["zc"]))
+    e = db.get(key or "%s|f%d|tile%d:%d" % (workload, precision, tile["shape"], tile["zc"]))
     if e is None or e.get("src") != fused_source_hash():
         return None
     return e
@@ -173,16 +173,16 @@ def measured_valu(workload, precision, tile):
     return e
 
 
-def roofline(precision, nvox, kernel_ms, workload=None, tile=None, kernel="k_fused"):
+def roofline(precision, nvox, kernel_ms, workload=None, tile=None, kernel="k_fused", traffic_key=None):
     alg = ALG_BYTES[precision]
     achieved = alg * nvox / (kernel_ms / 1e3) / 1e9
     out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
            "kernel_ms": kernel_ms, "alg_bytes_per_voxel_step": alg, "voxels_per_launch": nvox}
-    t = measured_traffic(workload, precision, tile) if workload else None
+    t = measured_traffic(workload, precision, tile, traffic_key) if workload else None
     if t is not None:
         out["traffic"] = t["traffic"]
-        out["traffic_unit"] = "bytes per launch"
+        out["traffic_unit"] = "bytes per launch" if traffic_key is None else "bytes per step"
         out["traffic_over_algorithmic"] = t["traffic"] / (alg * nvox)
         out["traffic_profile"] = "profiles/" + t["profile"]
     v = measured_valu(workload, precision, tile) if workload else None
@@ -222,7 +222,8 @@ def time_batch(count, steps, one_by_one_sample=256, one_by_one_steps=100):
     batched = nvox * steps / (ms / 1e3)
     result = {"workload": "batch_objects_%d" % count, "objects": count, "voxels": nvox, "steps": steps,
               "dtype": "f32", "value": batched, "ms": ms, "workgroups": n_wg,
-              "roofline": dict(roofline(32, nvox, ms / steps, kernel="k_batch"),
+              "roofline": dict(roofline(32, nvox, ms / steps, "batch_objects_%d" % count, kernel="k_batch",
+                                        traffic_key="batch_objects_%d|f32|k_batch" % count),
                                note="kernel_ms is per step: one persistent launch runs all steps")}
     if one_by_one_sample <= 0:
         return result
