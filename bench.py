@@ -609,8 +609,8 @@ def lattice_leg(w, precision, r, steps, kernel_name):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="blob_lattice_256")
     ap.add_argument("--precision", type=int, default=32, choices=[32, 64])
     ap.add_argument("--kernel", default="fused", choices=["fused", "split"])
