@@ -356,17 +356,19 @@ def time_adjoint(steps=5000, K=100):
                     "out"}
 
 
-def time_collision_schemes(steps=5000, graph=True):
+def time_collision_schemes(steps=5000, graph=True, w=None):
     """Iteration rates of the self-collision schemes of the paper's Table 3
     (candidates from all voxels or the surface; rebuilt every step or by the
-    horizon rule) on the clapper, FP32: wall time of `steps` steps as one
-    vx_step call (host launches included), and the same steps from the same
-    start replayed from one captured HIP graph (device time; the rebuild
-    decisions are taken on the device, so the graph runs the same work)."""
+    horizon rule) on the clapper (or on workload w), FP32: wall time of
+    `steps` steps as one vx_step call (host launches included), and the same
+    steps from the same start replayed from one captured HIP graph (device
+    time; the rebuild decisions are taken on the device, so the graph runs
+    the same work)."""
     import torch
     import paper_1212_2845_amd as vx
     import workloads
-    w = workloads.clapper(steps=steps)
+    if w is None:
+        w = workloads.clapper(steps=steps)
     out = {"workload": w["name"], "voxels": int((w["grid"] > 0).sum()), "steps": steps, "dtype": "f32",
            "unit": "iterations/s",
            "note": "NAME: wall time of vx_step over the steps, host launches included; NAME graph: one replay "
@@ -375,9 +377,10 @@ def time_collision_schemes(steps=5000, graph=True):
     side = torch.cuda.Stream()
 
     def make(all_voxels, every):
-        sim = vx.Sim(w["grid"], w["materials"], precision=32, stream=side.cuda_stream, **w["params"])
+        sim = vx.from_workload(w, precision=32, stream=side.cuda_stream)
         sim.set_collision_mode(all_voxels, every)
-        sim.set_fixed(w["fixed"])
+        if w.get("state") is not None:
+            sim.write_state(**w["state"])
         sim.step(10)
         return sim
 
@@ -389,7 +392,9 @@ def time_collision_schemes(steps=5000, graph=True):
         s.step(steps)
         torch.cuda.synchronize()
         rates[name] = steps / (time.perf_counter() - t0)
-        rates[name + " rebuilds"] = s.counters()["rebuilds"]
+        c = s.counters()
+        rates[name + " rebuilds"] = c["rebuilds"]
+        rates[name + " pairs"] = c["pairs"]
         del s
         if graph and steps % 2 == 0:
             s = make(all_voxels, every)
@@ -712,8 +717,12 @@ def main():
         log("batched leg: %d objects, %d steps" % (args.batch_objects, args.batch_steps))
         out["batched"] = time_batch(args.batch_objects, args.batch_steps, args.one_by_one_sample)
     if not args.no_collision_leg:
-        log("collision-scheme leg: clapper")
+        log("collision-scheme leg: clapper, 512 pairs of colliding bodies")
         out["collision_schemes"] = time_collision_schemes(graph=not args.eager)
+        import workloads
+        wb, _ = workloads.colliding_bodies(pairs=(8, 8, 8), steps=2000)
+        out["collision_schemes_bodies"] = time_collision_schemes(2000, graph=not args.eager, w=wb)
+        del wb
     if not args.no_adjoint_leg:
         log("adjoint leg: design lattice, %d steps" % args.adjoint_steps)
         out["adjoint"] = time_adjoint(args.adjoint_steps)
