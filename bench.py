@@ -342,12 +342,37 @@ def time_adjoint(steps=5000, K=100):
     del s
     torch.cuda.empty_cache()
     t_fa = t2 - t0
+    # the same rollout with the full tape (K = 1: every step's state and bond
+    # sums stored by the forward run, nothing recomputed), when it fits the
+    # free HBM
+    tape = None
+    s = make(w)
+    need = s.grad_workspace_bytes(steps, 1)
+    free = torch.cuda.mem_get_info()[0]
+    if need < 0.9 * free:
+        s.grad_bind(steps, 1)
+        torch.cuda.synchronize()
+        u0 = time.perf_counter()
+        s.grad_forward(steps)
+        torch.cuda.synchronize()
+        u1 = time.perf_counter()
+        gt = s.grad_backward(dL_du=wu)
+        torch.cuda.synchronize()
+        u2 = time.perf_counter()
+        same = all(np.array_equal(gt[k], g[k]) for k in ("E", "rho", "phase", "amp"))
+        tape = {"grad_workspace_bytes": int(need), "grad_forward_s": u1 - u0, "grad_backward_s": u2 - u1,
+                "fwd_adj_over_fwd": (u2 - u0) / t_fwd, "fwd_adj_over_fused_fwd": (u2 - u0) / t_fused,
+                "gradients_equal_to_checkpointed": bool(same)}
+    else:
+        tape = {"skipped": "tape of %d bytes does not fit %d free bytes" % (need, free)}
+    del s
+    torch.cuda.empty_cache()
     return {"workload": w["name"], "voxels": nvox, "cells": int(w["grid"].size), "steps": steps,
             "checkpoint_every": K, "dtype": "f32", "grad_workspace_bytes": int(gbytes),
             "forward_s": t_fwd, "grad_forward_s": t1 - t0, "grad_backward_s": t2 - t1,
             "fwd_adj_over_fwd": t_fa / t_fwd,
             "fused_forward_s": t_fused, "fwd_adj_over_fused_fwd": t_fa / t_fused, "target_fwd_adj_over_fwd": 4.0,
-            "value": nvox * steps / t_fa, "unit": "voxel-steps/s (forward + reverse)",
+            "value": nvox * steps / t_fa, "unit": "voxel-steps/s (forward + reverse)", "tape_K1": tape,
             "grad_E_absmax": float(np.abs(g["E"]).max()), "grad_phase_absmax": float(np.abs(g["phase"]).max()),
             "note": "forward_s: the plain forward in parameter mode (per-voxel moduli) through the fused step "
                     "kernel, which the recorded forward and the segment recompute also run; fused_forward_s: the "

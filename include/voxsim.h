@@ -369,7 +369,9 @@ int vx_set_density(vx_handle h, const double *rho);
  * with a checkpoint every K steps: ceil(max_steps/K) checkpoints plus a
  * K-step recompute buffer, adjoint state and per-voxel adjoint terms
  * (about (ceil(max_steps/K) + K) x (13 words + 1 byte) + K x 6 words +
- * 35 words + 4 FP64 words per cell). */
+ * 35 words + 4 FP64 words per cell).  K = 1 is the tape: the forward run
+ * stores every step's state, flags and 6 bond-sum words (about max_steps x
+ * (19 words + 1 byte) per cell) and the reverse run recomputes nothing. */
 int vx_grad_workspace_bytes(vx_handle h, int64_t max_steps, int32_t K, uint64_t *bytes);
 
 /* Bind a caller-owned, 256-byte aligned device buffer of at least

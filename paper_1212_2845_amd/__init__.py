@@ -503,6 +503,13 @@ class Sim:
             assert r.size == self.ncell
         self._check(lib().vx_set_density(self.h, _ptr(r)))
 
+    def grad_workspace_bytes(self, max_steps, K):
+        """Bytes vx_grad_bind needs for rollouts of up to max_steps steps
+        with a checkpoint every K steps (K = 1: the full tape)."""
+        n = C.c_uint64()
+        self._check(lib().vx_grad_workspace_bytes(self.h, int(max_steps), int(K), C.byref(n)))
+        return n.value
+
     def grad_bind(self, max_steps, K):
         """Allocate (torch) and bind the gradient workspace for rollouts of up
         to max_steps steps with a checkpoint every K steps."""

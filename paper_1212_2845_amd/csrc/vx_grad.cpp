@@ -2,7 +2,11 @@
 // stores a checkpoint of the state every K steps; the reverse run walks the
 // segments backwards, recomputes each segment's states and bond sums from
 // its checkpoint with the forward kernels, then applies the reverse step
-// kernels from the last step of the segment to the first.
+// kernels from the last step of the segment to the first.  With K = 1 the
+// forward run writes every step's state, flags and bond sums straight into
+// the tape (the step kernel's output goes to the next tape slot), and the
+// reverse run recomputes nothing: the memory-for-time end of the trade-off,
+// for rollouts whose tape fits the GPU's HBM.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,7 +32,7 @@ void grad_layout(const vx_sim *h, int64_t max_steps, int K, GradLayout &G) {
     G.ck_flags = take(G.n_ck * fb);
     G.seg_state = take((uint64_t)K * sb);
     G.seg_flags = take((uint64_t)K * fb);
-    G.fm = take((uint64_t)K * fmb);
+    G.fm = take((uint64_t)(K == 1 ? max_steps : K) * fmb);
     G.lam[0] = take(sb);
     G.lam[1] = take(sb);
     G.gfm = take(6 * n * ts);
@@ -93,8 +97,8 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
         };
         // recompute the segment: states x_s0+1 .. x_s0+len-1 and the bond
         // sums of every step (the last step's new state goes to the unused
-        // slot 0)
-        for (int i = 0; i < len; ++i) {
+        // slot 0); with K = 1 the forward run stored them
+        for (int i = 0; K > 1 && i < len; ++i) {
             StepArgs<T> a = make_args<T>(h);
             set_step_time(a, h, s0 + i);
             a.s_in = st_ptr(i);
@@ -117,7 +121,7 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
             a.s_out = nullptr;
             a.flags_out = nullptr;
             AdjArgs<T> g;
-            g.fm = (const T *)(gw + G.fm + (uint64_t)i * fmb);
+            g.fm = (const T *)(gw + G.fm + (uint64_t)(K > 1 ? i : j) * fmb);
             g.lam_in = (const T *)(gw + G.lam[li]);
             g.lam_out = (T *)(gw + G.lam[1 - li]);
             g.gfm = (T *)(gw + G.gfm);
@@ -193,6 +197,43 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
 }
 
 template <typename T>
+int checkpoint(vx_sim *h, int j);
+
+// Forward run with K = 1: step j reads tape slot j and writes slot j + 1
+// (the last step writes the handle's next state buffer) and its bond sums
+// to bond-sum slot j.
+template <typename T>
+int tape_forward(vx_sim *h, int64_t n) {
+    const GradLayout &G = h->GL;
+    const uint64_t sb = state_slot(h), fb = flags_slot(h), fmb = fm_slot(h);
+    char *gw = h->gws;
+    int r = checkpoint<T>(h, 0);
+    if (r) return r;
+    for (int64_t j = 0; j < n; ++j) {
+        StepArgs<T> a = make_args<T>(h);
+        const bool last = j + 1 == n;
+        a.s_in = (const T *)(gw + G.ck_state + (uint64_t)j * sb);
+        a.flags = (const uint8_t *)(gw + G.ck_flags + (uint64_t)j * fb);
+        a.s_out = last ? (T *)(h->ws + h->L.state[1 - h->cur]) : (T *)(gw + G.ck_state + (uint64_t)(j + 1) * sb);
+        a.flags_out = last ? (uint8_t *)(h->ws + h->L.flags[1 - h->cur])
+                           : (uint8_t *)(gw + G.ck_flags + (uint64_t)(j + 1) * fb);
+        a.fm_out = (T *)(gw + G.fm + (uint64_t)j * fmb);
+        if (h->use_split()) {
+            HIP_OK(h, launch_split_step<T>(a, h->stream));
+        } else {
+            HIP_OK(h, launch_fused_step<T>(a, fused_cfg(h), h->stream));
+        }
+        h->step++;
+    }
+    h->cur = 1 - h->cur;
+    Scalars sc;
+    HIP_OK(h, hipMemcpyAsync(&sc, h->ws + h->L.scalars, sizeof(sc), hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    if (sc.err_flag) return fail(h, VX_EUNSTABLE, "non-finite value in the voxel state");
+    return VX_OK;
+}
+
+template <typename T>
 int checkpoint(vx_sim *h, int j) {
     const uint64_t sb = state_slot(h), fb = flags_slot(h);
     HIP_OK(h, hipMemcpyAsync(h->gws + h->GL.ck_state + (uint64_t)j * sb, h->ws + h->L.state[h->cur],
@@ -244,7 +285,11 @@ int vx_grad_forward(vx_handle h, int64_t n) {
     }
     const long long step0 = h->step;
     const int K = h->GL.K;
-    for (int64_t done = 0, j = 0; done < n; done += K, ++j) {
+    if (K == 1) {
+        const int r = h->precision == 64 ? tape_forward<double>(h, n) : tape_forward<float>(h, n);
+        if (r) return r;
+    }
+    for (int64_t done = 0, j = 0; K > 1 && done < n; done += K, ++j) {
         int r = h->precision == 64 ? checkpoint<double>(h, (int)j) : checkpoint<float>(h, (int)j);
         if (r) return r;
         r = vx_step(h, std::min<int64_t>(K, n - done));

@@ -259,15 +259,42 @@ def test_gradient_of_initial_state_matches_oracle_fd():
 @pytest.mark.parametrize("precision", [64, 32])
 def test_checkpoint_interval_does_not_change_gradients(precision):
     """The reverse run recomputes each segment with the forward kernels, so
-    any checkpoint interval gives bitwise the same gradients."""
+    any checkpoint interval gives bitwise the same gradients; K = 1 (the
+    tape: the forward run stores every state and bond sum, nothing is
+    recomputed) too, with the same loss, i.e. the same final state."""
     w = workloads.grad_object(seed=41, scenario="slide", steps=60)
     wu, wv = loss_weights(w, seed=42)
     announce("checkpoint interval p=%d" % precision)
-    ref, _ = gpu_grad(w, wu, wv, precision, K=60)
+    ref, loss_ref = gpu_grad(w, wu, wv, precision, K=60)
     for K in (1, 7, 100):
-        g, _ = gpu_grad(w, wu, wv, precision, K=K)
-        for k in ("E", "rho", "phase", "u0", "v0"):
+        g, loss = gpu_grad(w, wu, wv, precision, K=K)
+        assert loss == loss_ref, K
+        for k in ("E", "rho", "phase", "amp", "u0", "v0"):
             assert np.array_equal(g[k], ref[k]), (K, k)
+
+
+def test_tape_forward_equals_plain_forward():
+    """The K = 1 forward run (each step written into the next tape slot) ends
+    in the state that plain stepping reaches, bitwise, with the step and
+    time counters advanced alike, on a lattice of several fused tiles."""
+    w = test_gpu_parity.hetero_block(shape=(24, 13, 11), seed=97)
+    E, rho = per_voxel_params(w, 98)
+    announce("tape forward")
+    out = []
+    for tape in (False, True):
+        s = vx.from_workload(w, precision=32)
+        s.set_stiffness(E)
+        s.set_density(rho)
+        s.write_state(**w["state"])
+        if tape:
+            s.grad_bind(37, 1)
+            s.grad_forward(37)
+        else:
+            s.step(37)
+        out.append((s.read_state(), s.counters()["steps"], s.time))
+    for k in ("u", "q", "v", "w"):
+        assert np.array_equal(out[0][0][k], out[1][0][k]), k
+    assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
 
 
 def test_fp32_gradient_close_to_fp64():
