@@ -343,26 +343,26 @@ int vx_time_kernel(vx_handle h, int32_t iters, double *ms_per_launch);
 /* Per-voxel elastic modulus E[ncell] (Pa; read only at filled cells; NULL
  * returns to the palette's moduli).  It replaces the palette modulus in
  * the bond constants (Eq. 1-2, 8-12), the bond damping (Eq. 34-35), the
- * floor stiffness and the ground damping; density, Poisson's ratio,
- * expansion and friction stay the palette's.  The timestep stays the one
- * chosen at create, so every bond's sqrt(k/m_min) must stay at or below
- * the bound it was chosen for (include a material as stiff as the stiffest
- * modulus in the palette).  While set, steps run the split kernels.
- * Errors: VX_EINVAL for a non-positive or non-finite modulus, or one above
- * the timestep's bound. */
+ * floor stiffness, the ground damping and the voxel-voxel contact
+ * stiffness and damping; density, Poisson's ratio, expansion and friction
+ * stay the palette's.  The timestep stays the one chosen at create, so
+ * every bond's sqrt(k/m_min) must stay at or below the bound it was chosen
+ * for (include a material as stiff as the stiffest modulus in the
+ * palette).  Steps run a variant of the fused kernel that reads the
+ * per-cell values.  Errors: VX_EINVAL for a non-positive or non-finite
+ * modulus, or one above the timestep's bound. */
 int vx_set_stiffness(vx_handle h, const double *E);
 
 /* Per-voxel density rho[ncell] (kg/m^3; read only at filled cells; NULL
  * returns to the palette's).  It replaces the palette density in the
  * voxel's mass and inertia (m = rho l^3, I = m l^2 / 6) and in every
- * mass-dependent damping coefficient (ground, floor and bond damping, the
- * last with the lighter voxel of the pair, Eq. 34).  The same stability
- * rule as vx_set_stiffness applies to the pair (modulus, density).  The
- * stored momenta are kept, and vx_read_state, vx_write_state and
- * vx_set_velocity convert them with the cell's own mass.  Both
- * calls need self-collision off (contact keeps the palette's constants):
- * VX_ESTATE otherwise.  Errors: VX_EINVAL for a non-positive or non-finite
- * density, or one that puts a bond above the timestep's bound. */
+ * mass-dependent damping coefficient (ground, floor, bond and contact
+ * damping, the last two with the lighter voxel of the pair, Eq. 34).  The
+ * same stability rule as vx_set_stiffness applies to the pair (modulus,
+ * density).  The stored momenta are kept, and vx_read_state,
+ * vx_write_state and vx_set_velocity convert them with the cell's own
+ * mass.  Errors: VX_EINVAL for a non-positive or non-finite density, or
+ * one that puts a bond above the timestep's bound. */
 int vx_set_density(vx_handle h, const double *rho);
 
 /* Bytes of the gradient workspace for rollouts of up to max_steps steps
@@ -376,8 +376,12 @@ int vx_grad_workspace_bytes(vx_handle h, int64_t max_steps, int32_t K, uint64_t 
 
 /* Bind a caller-owned, 256-byte aligned device buffer of at least
  * vx_grad_workspace_bytes(h, max_steps, K) bytes.  Needs the main
- * workspace bound and self-collision off.  Replaces an earlier binding.
- * Errors: VX_ESTATE, VX_EINVAL (too small, misaligned, K or max_steps < 1). */
+ * workspace bound; with self-collision on, the full tape (K = 1): the
+ * reverse run then rebuilds each step's candidate lists from the taped
+ * state and applies the contact forces' reverse (gradients through
+ * contact; the lists themselves are piecewise constant).  Replaces an
+ * earlier binding.  Errors: VX_ESTATE, VX_EINVAL (too small, misaligned, K
+ * or max_steps < 1). */
 int vx_grad_bind(vx_handle h, void *device_ptr, uint64_t bytes, int64_t max_steps, int32_t K);
 
 /* Advance n steps (1 <= n <= max_steps) like vx_step and record the

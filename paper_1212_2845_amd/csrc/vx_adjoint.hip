@@ -1,9 +1,11 @@
 // Reverse of one split step.  k_adj_update applies, per voxel, the VJP of
 // the update (environment, friction, integration): it gives the adjoint of
 // x_n through the voxel's own state, the adjoints of its bond sums, and the
-// update's adjoints of the voxel's strain, modulus and mass.  The bond pass
-// and the gather that complete the adjoint of x_n and accumulate the
-// parameter gradients run as one LDS-tiled launch (vx_adjoint_fused.hip).
+// update's adjoints of the voxel's strain, modulus and mass.  With
+// self-collision the contact forces' reverse (vx_collide.hip) adds to
+// these next.  The bond pass and the gather that complete the adjoint of
+// x_n and accumulate the parameter gradients run as one LDS-tiled launch
+// (vx_adjoint_fused.hip).
 // No atomics: every output word has one writer, so the reverse pass is as
 // deterministic as the forward one.
 #include "vx_adjoint.hpp"
@@ -48,16 +50,22 @@ __global__ void __launch_bounds__(256) k_adj_update(StepArgs<T> a, AdjArgs<T> g)
 }  // namespace
 
 template <typename T>
-hipError_t launch_adjoint_step(const StepArgs<T> &a, const AdjArgs<T> &g, hipStream_t s) {
+hipError_t launch_adjoint_step(const StepArgs<T> &a, const AdjArgs<T> &g, const CollideArgs *c, hipStream_t s) {
     const long long n = (long long)a.nx * a.ny * a.nz;
     const unsigned blocks = (unsigned)((n + 255) / 256);
     k_adj_update<T><<<blocks, 256, 0, s>>>(a, g);
-    const hipError_t e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (c) {
+        e = launch_adjoint_contact<T>(a, *c, g, s);
+        if (e != hipSuccess) return e;
+    }
     return launch_adjoint_fused<T>(a, g, s);
 }
 
-template hipError_t launch_adjoint_step<float>(const StepArgs<float> &, const AdjArgs<float> &, hipStream_t);
-template hipError_t launch_adjoint_step<double>(const StepArgs<double> &, const AdjArgs<double> &, hipStream_t);
+template hipError_t launch_adjoint_step<float>(const StepArgs<float> &, const AdjArgs<float> &, const CollideArgs *,
+                                               hipStream_t);
+template hipError_t launch_adjoint_step<double>(const StepArgs<double> &, const AdjArgs<double> &, const CollideArgs *,
+                                                hipStream_t);
 
 }  // namespace vx

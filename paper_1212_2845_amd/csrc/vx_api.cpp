@@ -713,8 +713,6 @@ static double param_omega(const vx_sim *h, const double *E, const double *rho) {
 // other's current values; the timestep stays the one chosen at create, so
 // no bond may become faster than the bound it was chosen for.
 static int set_param(vx_sim *h, const double *vals, bool is_E, const char *what) {
-    if (h->p.self_collision_on)
-        return fail(h, VX_ESTATE, "per-voxel parameters need self-collision off (contact uses the palette)");
     std::vector<double> &dst = is_E ? h->E_cell : h->rho_cell;
     bool &flag = is_E ? h->has_E : h->has_rho;
     if (!vals) {

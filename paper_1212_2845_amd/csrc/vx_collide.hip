@@ -278,6 +278,32 @@ __global__ void __launch_bounds__(256) k_candidates(StepArgs<T> a, CollideArgs c
     }
 }
 
+// Contact constants of a pair (the bond's translational stiffness and the
+// collision damping coefficient over the lighter mass, as the host tables
+// hold them per material pair), from the palette, or in parameter mode from
+// the two cells' own moduli and masses in the same order of operations.
+template <typename T>
+struct ContactK {
+    T kc, cc;
+};
+
+template <typename T>
+__device__ __forceinline__ ContactK<T> contact_k(const StepArgs<T> &a, unsigned ci, unsigned cj, uint8_t mi,
+                                                 uint8_t mj, const MatConst<T> &Mi, const MatConst<T> &Mj) {
+    ContactK<T> k;
+    if (a.E_cell) {
+        const T Ei = a.E_cell[ci], Ej = a.E_cell[cj];
+        k.kc = (T(2) * Ei * Ej / (Ei + Ej)) * a.l;
+        const T mmin = Mi.m < Mj.m ? Mi.m : Mj.m;
+        k.cc = T(2) * a.zeta_col * dsqrt(mmin * k.kc);
+    } else {
+        const PairConst<T> pc = a.pairs[mi * a.n_mat + mj];
+        k.kc = pc.kc;
+        k.cc = pc.cc;
+    }
+    return k;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_contact(StepArgs<T> a, CollideArgs c, T *cf) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -287,7 +313,7 @@ __global__ void __launch_bounds__(256) k_contact(StepArgs<T> a, CollideArgs c, T
     const long long st = a.stride;
     const int ci = c.surf_cells[i], oi = c.surf_obj[i];
     const uint8_t mi = a.mat[ci];
-    const MatConst<T> Mi = a.mats[mi];
+    const MatConst<T> Mi = mat_at(a, ci, mi);
     const T ei = voxel_strain(a, (unsigned)ci, a.flags[ci], Mi.cte);
     int ix, iy, iz;
     unpack3(c.surf_ijk[i], ix, iy, iz);
@@ -300,7 +326,7 @@ __global__ void __launch_bounds__(256) k_contact(StepArgs<T> a, CollideArgs c, T
         const int j = list[k];
         const int cj = c.surf_cells[j], oj = c.surf_obj[j];
         const uint8_t mj = a.mat[cj];
-        const MatConst<T> Mj = a.mats[mj];
+        const MatConst<T> Mj = mat_at(a, cj, mj);
         int jx, jy, jz;
         unpack3(c.surf_ijk[j], jx, jy, jz);
         T rx, ry, rz;
@@ -312,7 +338,7 @@ __global__ void __launch_bounds__(256) k_contact(StepArgs<T> a, CollideArgs c, T
         if (!(dist < cdist) || !(dist > T(0))) continue;
         const T inv = T(1) / dist;
         const T nx = rx * inv, ny = ry * inv, nz = rz * inv;
-        const PairConst<T> pc = a.pairs[mi * a.n_mat + mj];
+        const ContactK<T> pc = contact_k(a, (unsigned)ci, (unsigned)cj, mi, mj, Mi, Mj);
         const T vjx = a.s_in[W_PX * st + cj] * Mj.inv_m, vjy = a.s_in[W_PY * st + cj] * Mj.inv_m,
                 vjz = a.s_in[W_PZ * st + cj] * Mj.inv_m;
         const T vn = (vx - vjx) * nx + (vy - vjy) * ny + (vz - vjz) * nz;
@@ -326,6 +352,120 @@ __global__ void __launch_bounds__(256) k_contact(StepArgs<T> a, CollideArgs c, T
 template <typename T>
 __global__ void k_motion(StepArgs<T> a, CollideArgs c) {
     motion_update(c.scalars, (double)a.dt);
+}
+
+__global__ void k_force_rebuild(CollideArgs c) { *c.rebuild_flag = 1u; }
+
+// Reverse of one pair term f n of a contact force, with f = kc (cdist -
+// dist) - cc vn > 0, n = r / dist, vn = dv . n, given the adjoint lam of the
+// force: the adjoints of r, dv, cdist, kc and cc.
+template <typename T>
+struct PairAdj {
+    T r[3], dv[3], cdist, kc, cc;
+};
+
+template <typename T>
+__device__ __forceinline__ PairAdj<T> pair_vjp(const T lam[3], const T n[3], const T dv[3], T f, T inv, T kc, T cc,
+                                               T cdist, T dist, T vn) {
+    PairAdj<T> g;
+    const T gf = lam[0] * n[0] + lam[1] * n[1] + lam[2] * n[2];
+    T gn[3];
+    for (int k = 0; k < 3; ++k) gn[k] = f * lam[k] - gf * cc * dv[k];
+    const T gnn = gn[0] * n[0] + gn[1] * n[1] + gn[2] * n[2];
+    const T gdist = -gf * kc;
+    for (int k = 0; k < 3; ++k) {
+        g.r[k] = (gn[k] - gnn * n[k]) * inv + gdist * n[k];
+        g.dv[k] = -gf * cc * n[k];
+    }
+    g.cdist = gf * kc;
+    g.kc = gf * (cdist - dist);
+    g.cc = -gf * vn;
+    return g;
+}
+
+// Reverse of the contact forces of one step, per listed voxel i: the terms
+// of i's own force (adjoint: i's bond-sum force adjoint, which the update
+// adds the contact force to) and of each partner's force on which i's state
+// acts (the partner's adjoint), gathered without atomics from i's own list
+// (the lists are symmetric).  Adds to the adjoint of i's displacement and
+// momentum and to the update's adjoints of i's strain, modulus and mass;
+// runs between the update's and the bonds' reverse kernels of the step.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_contact(StepArgs<T> a, CollideArgs c, AdjArgs<T> g) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= c.n_surf) return;
+    const int n = c.cand_n[i];
+    if (n == 0) return;
+    const long long st = a.stride;
+    const int ci = c.surf_cells[i], oi = c.surf_obj[i];
+    const uint8_t mi = a.mat[ci];
+    const MatConst<T> Mi = mat_at(a, ci, mi);
+    const T ei = voxel_strain(a, (unsigned)ci, a.flags[ci], Mi.cte);
+    int ix, iy, iz;
+    unpack3(c.surf_ijk[i], ix, iy, iz);
+    const T ui[3] = {a.s_in[W_UX * st + ci], a.s_in[W_UY * st + ci], a.s_in[W_UZ * st + ci]};
+    const T Pi[3] = {a.s_in[W_PX * st + ci], a.s_in[W_PY * st + ci], a.s_in[W_PZ * st + ci]};
+    const T vi[3] = {Pi[0] * Mi.inv_m, Pi[1] * Mi.inv_m, Pi[2] * Mi.inv_m};
+    const T lami[3] = {g.gfm[ci], g.gfm[st + ci], g.gfm[2 * st + ci]};
+    T gu[3] = {T(0), T(0), T(0)}, gv[3] = {T(0), T(0), T(0)};
+    T geps = T(0), gE = T(0), gm = T(0);
+    const int *list = c.cand + (long long)i * c.cap;
+    for (int k = 0; k < n; ++k) {
+        const int j = list[k];
+        const int cj = c.surf_cells[j], oj = c.surf_obj[j];
+        const uint8_t mj = a.mat[cj];
+        const MatConst<T> Mj = mat_at(a, cj, mj);
+        int jx, jy, jz;
+        unpack3(c.surf_ijk[j], jx, jy, jz);
+        T r[3];
+        separation(c, a.l, oi, ix, iy, iz, oj, jx, jy, jz, ui[0] - a.s_in[W_UX * st + cj],
+                   ui[1] - a.s_in[W_UY * st + cj], ui[2] - a.s_in[W_UZ * st + cj], r[0], r[1], r[2]);
+        const T dist = dsqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        const T ej = voxel_strain(a, (unsigned)cj, a.flags[cj], Mj.cte);
+        const T cdist = T(0.5) * a.l * (T(1) + ei) + T(0.5) * a.l * (T(1) + ej);
+        if (!(dist < cdist) || !(dist > T(0))) continue;
+        const T inv = T(1) / dist;
+        const T nv[3] = {r[0] * inv, r[1] * inv, r[2] * inv};
+        const ContactK<T> K = contact_k(a, (unsigned)ci, (unsigned)cj, mi, mj, Mi, Mj);
+        const T Pj[3] = {a.s_in[W_PX * st + cj], a.s_in[W_PY * st + cj], a.s_in[W_PZ * st + cj]};
+        const T dv[3] = {vi[0] - Pj[0] * Mj.inv_m, vi[1] - Pj[1] * Mj.inv_m, vi[2] - Pj[2] * Mj.inv_m};
+        const T vn = dv[0] * nv[0] + dv[1] * nv[1] + dv[2] * nv[2];
+        const T f = K.kc * (cdist - dist) - K.cc * vn;
+        if (!(f > T(0))) continue;
+        // i's own force: pair (i, j), r = D_i - D_j, dv = v_i - v_j
+        const PairAdj<T> A = pair_vjp(lami, nv, dv, f, inv, K.kc, K.cc, cdist, dist, vn);
+        // j's force on which i acts: pair (j, i), r' = -r, dv' = -dv, the
+        // same f and vn
+        const T lamj[3] = {g.gfm[cj], g.gfm[st + cj], g.gfm[2 * st + cj]};
+        const T nm[3] = {-nv[0], -nv[1], -nv[2]}, dvm[3] = {-dv[0], -dv[1], -dv[2]};
+        const PairAdj<T> B = pair_vjp(lamj, nm, dvm, f, inv, K.kc, K.cc, cdist, dist, vn);
+        for (int q = 0; q < 3; ++q) {
+            gu[q] += A.r[q] - B.r[q];
+            gv[q] += A.dv[q] - B.dv[q];
+        }
+        geps += (A.cdist + B.cdist) * (T(0.5) * a.l);
+        if (a.E_cell) {
+            // kc = E_c l with E_c = 2 E_i E_j / (E_i + E_j); cc = 2 zeta
+            // sqrt(m_min kc); each term's m_min as its forward took it
+            const T Ei = a.E_cell[ci], Ej = a.E_cell[cj], s = Ei + Ej;
+            const T gkc = (A.kc + B.kc) + (A.cc + B.cc) * K.cc / (T(2) * K.kc);
+            gE += gkc * a.l * (T(2) * Ej * Ej / (s * s));
+            const T mmin = Mi.m < Mj.m ? Mi.m : Mj.m;
+            const T dcc_dm = K.cc / (T(2) * mmin);
+            if (Mi.m < Mj.m) gm += A.cc * dcc_dm;
+            if (!(Mj.m < Mi.m)) gm += B.cc * dcc_dm;
+        }
+    }
+    // v_i = P_i / m_i
+    const T ginv_m = gv[0] * Pi[0] + gv[1] * Pi[1] + gv[2] * Pi[2];
+    gm -= ginv_m * Mi.inv_m * Mi.inv_m;
+    T *lo = g.lam_out;
+    lo[W_UX * st + ci] += gu[0]; lo[W_UY * st + ci] += gu[1]; lo[W_UZ * st + ci] += gu[2];
+    lo[W_PX * st + ci] += gv[0] * Mi.inv_m; lo[W_PY * st + ci] += gv[1] * Mi.inv_m;
+    lo[W_PZ * st + ci] += gv[2] * Mi.inv_m;
+    g.gloc[ci] += geps;
+    g.gloc[st + ci] += gE;
+    g.gloc[2 * st + ci] += gm;
 }
 
 }  // namespace
@@ -362,11 +502,27 @@ hipError_t launch_motion_update(const StepArgs<T> &a, const CollideArgs &c, hipS
     return hipGetLastError();
 }
 
+hipError_t launch_force_rebuild(const CollideArgs &c, hipStream_t s) {
+    k_force_rebuild<<<1, 1, 0, s>>>(c);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adjoint_contact(const StepArgs<T> &a, const CollideArgs &c, const AdjArgs<T> &g, hipStream_t s) {
+    if (c.n_surf == 0) return hipSuccess;
+    k_adj_contact<T><<<(unsigned)((c.n_surf + 255) / 256), 256, 0, s>>>(a, c, g);
+    return hipGetLastError();
+}
+
 template hipError_t launch_rebuild<float>(const StepArgs<float> &, const CollideArgs &, hipStream_t);
 template hipError_t launch_rebuild<double>(const StepArgs<double> &, const CollideArgs &, hipStream_t);
 template hipError_t launch_contact<float>(const StepArgs<float> &, const CollideArgs &, float *, hipStream_t);
 template hipError_t launch_contact<double>(const StepArgs<double> &, const CollideArgs &, double *, hipStream_t);
 template hipError_t launch_motion_update<float>(const StepArgs<float> &, const CollideArgs &, hipStream_t);
+template hipError_t launch_adjoint_contact<float>(const StepArgs<float> &, const CollideArgs &,
+                                                  const AdjArgs<float> &, hipStream_t);
+template hipError_t launch_adjoint_contact<double>(const StepArgs<double> &, const CollideArgs &,
+                                                   const AdjArgs<double> &, hipStream_t);
 template hipError_t launch_motion_update<double>(const StepArgs<double> &, const CollideArgs &, hipStream_t);
 
 }  // namespace vx

@@ -83,6 +83,7 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
     HIP_OK(h, hipMemsetAsync(gw + G.gphase, 0, n * 8, s));
     HIP_OK(h, hipMemsetAsync(gw + G.gamp, 0, n * 8, s));
     int li = 0;
+    const bool col = h->p.self_collision_on != 0;
     const int64_t N = h->tape_n;
     const int K = G.K;
     const int nseg = (int)((N + K - 1) / K);
@@ -120,6 +121,23 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
             a.flags = fl_ptr(i);
             a.s_out = nullptr;
             a.flags_out = nullptr;
+            CollideArgs cl{};
+            if (col) {
+                // contact forces at x_n from candidate lists rebuilt for
+                // x_n: a list valid at x_n gives the forward's forces (only
+                // pairs in contact act), and the lists' candidate bits go
+                // to a scratch copy of the step's flags; zeroed forces for
+                // voxels whose fresh list is empty
+                cl = make_collide(h);
+                StepArgs<T> ac = a;
+                uint8_t *scratch = (uint8_t *)(h->ws + h->L.flags[1 - h->cur]);
+                HIP_OK(h, hipMemcpyAsync(scratch, a.flags, (size_t)n, hipMemcpyDeviceToDevice, s));
+                ac.flags = scratch;
+                HIP_OK(h, hipMemsetAsync(h->ws + h->L.contact_F, 0, (size_t)3 * n * sizeof(T), s));
+                HIP_OK(h, launch_force_rebuild(cl, s));
+                HIP_OK(h, launch_rebuild<T>(ac, cl, s));
+                HIP_OK(h, launch_contact<T>(ac, cl, (T *)(h->ws + h->L.contact_F), s));
+            }
             AdjArgs<T> g;
             g.fm = (const T *)(gw + G.fm + (uint64_t)(K > 1 ? i : j) * fmb);
             g.lam_in = (const T *)(gw + G.lam[li]);
@@ -131,9 +149,13 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
             g.g_phase = (double *)(gw + G.gphase);
             g.g_amp = (double *)(gw + G.gamp);
             set_chan_derivs(g.chan_dph, g.chan_dam, h, s0 + i);
-            HIP_OK(h, launch_adjoint_step<T>(a, g, s));
+            HIP_OK(h, launch_adjoint_step<T>(a, g, col ? &cl : nullptr, s));
             li = 1 - li;
         }
+    }
+    if (col) {
+        // the lists now hold the first step's pairs: rebuild before the next
+        HIP_OK(h, launch_force_rebuild(make_collide(h), s));
     }
     HIP_OK(h, hipMemcpyAsync(lam.data(), gw + G.lam[li], lam.size() * sizeof(T), hipMemcpyDeviceToHost, s));
     // initial state (checkpoint 0) and final state, for the density's
@@ -218,11 +240,19 @@ int tape_forward(vx_sim *h, int64_t n) {
         a.flags_out = last ? (uint8_t *)(h->ws + h->L.flags[1 - h->cur])
                            : (uint8_t *)(gw + G.ck_flags + (uint64_t)(j + 1) * fb);
         a.fm_out = (T *)(gw + G.fm + (uint64_t)j * fmb);
+        const bool col = h->p.self_collision_on != 0;
+        CollideArgs cl{};
+        if (col) {
+            cl = make_collide(h);
+            HIP_OK(h, launch_rebuild<T>(a, cl, h->stream));
+            HIP_OK(h, launch_contact<T>(a, cl, (T *)(h->ws + h->L.contact_F), h->stream));
+        }
         if (h->use_split()) {
             HIP_OK(h, launch_split_step<T>(a, h->stream));
         } else {
             HIP_OK(h, launch_fused_step<T>(a, fused_cfg(h), h->stream));
         }
+        if (col) HIP_OK(h, launch_motion_update<T>(a, cl, h->stream));
         h->step++;
     }
     h->cur = 1 - h->cur;
@@ -230,6 +260,7 @@ int tape_forward(vx_sim *h, int64_t n) {
     HIP_OK(h, hipMemcpyAsync(&sc, h->ws + h->L.scalars, sizeof(sc), hipMemcpyDeviceToHost, h->stream));
     HIP_OK(h, hipStreamSynchronize(h->stream));
     if (sc.err_flag) return fail(h, VX_EUNSTABLE, "non-finite value in the voxel state");
+    if (sc.overflow) return fail(h, VX_EOVERFLOW, "collision candidate list overflow (raise contact_cap)");
     return VX_OK;
 }
 
@@ -257,7 +288,8 @@ int vx_grad_workspace_bytes(vx_handle h, int64_t max_steps, int32_t K, uint64_t 
 
 int vx_grad_bind(vx_handle h, void *device_ptr, uint64_t bytes, int64_t max_steps, int32_t K) {
     if (!h || max_steps < 1 || K < 1) return VX_EINVAL;
-    if (h->p.self_collision_on) return fail(h, VX_ESTATE, "differentiable rollouts need self-collision off");
+    if (h->p.self_collision_on && std::min<int64_t>(K, max_steps) != 1)
+        return fail(h, VX_ESTATE, "differentiable rollouts with self-collision need the full tape (K = 1)");
     if (!h->bound) return fail(h, VX_ESTATE, "vx_grad_bind before vx_bind_workspace");
     GradLayout G;
     grad_layout(h, max_steps, (int)std::min<int64_t>(K, max_steps), G);

@@ -25,8 +25,11 @@ struct AdjArgs {
     Chan8<T> chan_dam;      // and w.r.t. its amplitude
 };
 
+struct CollideArgs;
+// One reverse step: the update's reverse per voxel, the contact forces'
+// reverse when c is given (self-collision), then the bonds' reverse.
 template <typename T>
-hipError_t launch_adjoint_step(const StepArgs<T> &a, const AdjArgs<T> &g, hipStream_t s);
+hipError_t launch_adjoint_step(const StepArgs<T> &a, const AdjArgs<T> &g, const CollideArgs *c, hipStream_t s);
 // Bond pass and gather of the reverse step in one LDS-tiled launch (after
 // the per-voxel update VJP); no per-bond records.
 template <typename T>
@@ -182,5 +185,13 @@ hipError_t launch_contact(const StepArgs<T> &a, const CollideArgs &c, T *contact
 // at the step's start, accumulates max|v| dt, sets the rebuild flag.
 template <typename T>
 hipError_t launch_motion_update(const StepArgs<T> &a, const CollideArgs &c, hipStream_t s);
+
+// Set the device rebuild flag (the next rebuild launch rebuilds).
+hipError_t launch_force_rebuild(const CollideArgs &c, hipStream_t s);
+
+// Reverse of the contact forces of one step (between the update's and the
+// bonds' reverse kernels; lists valid for a.s_in).
+template <typename T>
+hipError_t launch_adjoint_contact(const StepArgs<T> &a, const CollideArgs &c, const AdjArgs<T> &g, hipStream_t s);
 
 }  // namespace vx

@@ -220,14 +220,22 @@ def test_per_voxel_parameters_rejected_above_the_timestep_bound():
     s.set_density(rho)
 
 
-def test_per_voxel_parameters_need_self_collision_off():
+def test_per_voxel_parameters_with_self_collision():
+    # contact takes the per-voxel constants in parameter mode; checkpointed
+    # gradient rollouts with contact are refused (the full tape, K = 1, is
+    # what the contact reverse needs)
     g = np.ones((3, 3, 3), np.uint8)
     rc, h = _create(g, [workloads.EMPTY, M1], 64, **workloads._base_params(self_collision_on=1))
     assert rc == vx.VX_OK
     E = np.full(27, 1e6)
-    assert vx.lib().vx_set_stiffness(h, E.ctypes.data_as(C.c_void_p)) == vx.VX_ESTATE
-    assert vx.lib().vx_set_density(h, E.ctypes.data_as(C.c_void_p)) == vx.VX_ESTATE
+    assert vx.lib().vx_set_stiffness(h, E.ctypes.data_as(C.c_void_p)) == vx.VX_OK
+    rho = np.full(27, M1["rho"])
+    assert vx.lib().vx_set_density(h, rho.ctypes.data_as(C.c_void_p)) == vx.VX_OK
     vx.lib().vx_destroy(h)
+    s = vx.Sim(g, [workloads.EMPTY, M1], **workloads._base_params(self_collision_on=1))
+    L = vx.lib()
+    assert L.vx_grad_bind(s.h, C.c_void_p(4096), 1 << 40, 10, 2) == vx.VX_ESTATE
+    assert "K = 1" in L.vx_last_error(s.h).decode()
 
 
 def test_grad_calls_need_their_state():

@@ -410,3 +410,61 @@ def test_design_lattice_gradient_full_size():
             err = np.abs(gb[k] - g[k][cells]).max() / scale if scale > 0 else np.abs(gb[k]).max()
             print("[grad] block (%d, %d) %s alone vs in lattice %.3e" % (i, j, k, err), flush=True)
             assert err < 1e-5, (i, j, k, err)
+
+
+def contact_grad(w, wu, wv, precision=64):
+    s = gpu_sim(w, precision)
+    s.write_state(**w["state"])
+    s.grad_bind(w["steps"], 1)
+    s.grad_forward(w["steps"])
+    g = s.grad_backward(dL_du=wu, dL_dv=wv)
+    st = s.read_state()
+    return g, float((wu * st["u"]).sum() + (wv * st["v"]).sum()), s.counters()
+
+
+def test_gradient_through_contact_matches_oracle_fd():
+    """Two blocks of per-voxel moduli, densities and actuation phases pushed
+    into each other and apart again (self-collision on, 300 FP64 steps, the
+    full tape): the loss equals the oracle's, contact changes it, and dL/dE,
+    dL/drho and dL/dphase of every block voxel equal central differences of
+    the oracle (which perturbs the voxel's palette entry, i.e. its contact
+    stiffness and damping too) on the coordinates where the trajectory map
+    is smooth (at least 80% of them), to 1e-4 of the largest entry."""
+    w = workloads.contact_pair(seed=61)
+    wu, wv = loss_weights(w, seed=62)
+    announce("gradient through contact")
+    g, L, cnt = contact_grad(w, wu, wv)
+    assert abs(L / oracle_loss(w, wu, wv) - 1) < 1e-10
+    assert cnt["rebuilds"] >= 2
+    w_off = dict(w, params=dict(w["params"], self_collision_on=0))
+    assert abs(oracle_loss(w_off, wu, wv) / L - 1) > 1e-3        # the contact matters
+    b = w["block"]
+    idx = np.arange(b.size)
+    for name, f, keys, an in (("E", fd_modulus, idx, g["E"][b]), ("rho", fd_density, idx, g["rho"][b]),
+                              ("phase", fd_phase, b, g["phase"][b])):
+        fd, ok, scale = smooth_fd(f, w, wu, wv, keys)
+        err = np.abs(an[ok] - fd[ok]).max() / scale
+        print("[grad] contact %s err %.3e on %d of %d coordinates" % (name, err, ok.sum(), ok.size), flush=True)
+        assert ok.mean() >= 0.8, (name, ok.sum())
+        assert err < 1e-4, (name, err)
+
+
+def test_tape_forward_with_contact_equals_plain_forward():
+    """The K = 1 forward run with self-collision (lists rebuilt by the
+    horizon rule, contact forces each step) ends in the state plain
+    stepping reaches, bitwise, with the same rebuild count."""
+    w = workloads.contact_pair(seed=63)
+    announce("tape forward with contact")
+    out = []
+    for tape in (False, True):
+        s = gpu_sim(w, 64)
+        s.write_state(**w["state"])
+        if tape:
+            s.grad_bind(w["steps"], 1)
+            s.grad_forward(w["steps"])
+        else:
+            s.step(w["steps"])
+        out.append((s.read_state(), s.counters()["rebuilds"]))
+    for k in ("u", "q", "v", "w"):
+        assert np.array_equal(out[0][0][k], out[1][0][k]), k
+    assert out[0][1] == out[1][1] >= 2

@@ -244,6 +244,59 @@ def grad_object(seed, n=4, scenario="free", steps=200, temp_freq=500.0):
     return w
 
 
+def contact_pair(seed, n=3, steps=300, shift=1.4e-3, speed=0.5, temp_freq=500.0):
+    """Two n^3 blocks of one lattice that meet: block A at x = 0..n-1, block
+    B at x = n+3..2n+2 (rest indices at least 4 apart in Manhattan
+    distance, so their voxels may touch), displaced toward each other by
+    ``shift`` (m) and moving toward each other at ``speed`` m/s each, so
+    that they come into contact after about a third of the run and push
+    apart again.  As in grad_object every block voxel has its own palette
+    entry (modulus log-uniform in [0.5, 2] MPa, density in [500, 2000]
+    kg/m^3, CTE 0.01) and its own actuation phase (20 K), and a detached
+    two-voxel 8 MPa anchor beyond B sets the timestep.  Self-collision on,
+    no gravity or floor, bond and collision damping on.  Returns a workload
+    with ``state`` (the displaced start), ``block``, ``E_block`` and
+    ``rho_block``."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, nz = 2 * n + 6, n, n
+    grid = np.zeros((nz, ny, nx), np.uint8)
+    mats = [EMPTY]
+    nb = 2 * n ** 3
+    E_block = np.exp(rng.uniform(np.log(0.5e6), np.log(2e6), size=nb))
+    rho_block = np.exp(rng.uniform(np.log(500.0), np.log(2000.0), size=nb))
+    block, side = [], []
+    for z in range(nz):
+        for y in range(ny):
+            for x in list(range(n)) + list(range(n + 3, 2 * n + 3)):
+                k = len(block)
+                mats.append(_mat(E_block[k], rho=rho_block[k], cte=0.01))
+                grid[z, y, x] = len(mats) - 1
+                block.append(x + nx * (y + ny * z))
+                side.append(1.0 if x < n else -1.0)
+    mats.append(_mat(8e6))
+    grid[0, 0, 2 * n + 4] = grid[0, 0, 2 * n + 5] = len(mats) - 1
+    block = np.array(block)
+    order = np.argsort(block)
+    block, E_block, rho_block = block[order], E_block[order], rho_block[order]
+    side = np.array(side)[order]
+    ncell = grid.size
+    amp = np.zeros(ncell)
+    amp[block] = 20.0
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=ncell)
+    u = np.zeros((ncell, 3)); v = np.zeros((ncell, 3))
+    u[block, 0] = side * shift
+    v[block, 0] = side * speed
+    v[block] += rng.normal(0.0, 0.02 * speed, size=(block.size, 3))
+    q = np.zeros((ncell, 4)); q[:, 0] = 1.0
+    params = _base_params(zeta_bond=0.3, zeta_col=0.5, self_collision_on=1, contact_cap=64, temp_freq=temp_freq)
+    w = _workload(grid, mats, params, steps, amp=amp, phase=phase, name="contact_pair_%d" % n)
+    w["state"] = {"u": u, "q": q, "v": v, "w": np.zeros((ncell, 3))}
+    w["block"] = block
+    w["E_block"] = E_block
+    w["rho_block"] = rho_block
+    return w
+
+
 def clapper(freq=20.0, cte=0.02, amp=30.0, gap=5, steps=5000):
     """A clapper for the collision-scheme comparison (section "Speedup of
     self collision schemes"; the paper's geometry is only pictured): a
