@@ -37,25 +37,33 @@ constexpr int kKin = 14;   // ux uy uz qw qx qy qz vx vy vz wx wy wz eps
 // LDS of one workgroup: a slab of kinematics with its ring, and the x- and
 // y-bond results (b[0] and b[1]), sized for NR ring cells and NBX / NBY
 // bonds.  Both bond arrays have the larger length, so a bond whose axis is
-// chosen per lane is stored through one address.
-template <typename T, int NR_, int NBX_, int NBY_>
+// chosen per lane is stored through one address.  A bond result is the
+// force on voxel 2 (words 0-2), the moment on voxel 2 (the last three words)
+// and, with NW = 9, the moment on voxel 1 (words 3-5).  With NW = 6 the thread that evaluates a bond adds
+// voxel 1's half to that voxel's sums at once: less LDS and fewer LDS
+// accesses, at the price of six sums held in registers through the bond
+// evaluations, which the FP32 kernel's register budget (three waves per
+// SIMD) does not have room for.
+template <typename T, int NR_, int NBX_, int NBY_, int NW_>
 struct Smem {
-    static constexpr int NR = NR_, NB = NBX_ > NBY_ ? NBX_ : NBY_;
+    static constexpr int NR = NR_, NB = NBX_ > NBY_ ? NBX_ : NBY_, NW = NW_;
     T kin[kKin][NR];
-    T b[2][9][NB];
+    T b[2][NW][NB];
     uint8_t mat[NR];
 };
 
 // With parameter mode: each slot's modulus and mass as well.
-template <typename T, int NR_, int NBX_, int NBY_>
-struct SmemP : Smem<T, NR_, NBX_, NBY_> {
+template <typename T, int NR_, int NBX_, int NBY_, int NW_>
+struct SmemP : Smem<T, NR_, NBX_, NBY_, NW_> {
     T pE[NR_], pM[NR_];
 };
 
+template <typename T>
+constexpr int tile_bond_words() { return sizeof(T) == 4 ? 9 : 6; }
 template <typename T, int TX, int TY>
-using TileSmem = Smem<T, (TX + 2) * (TY + 2), (TX + 1) * TY, TX * (TY + 1)>;
+using TileSmem = Smem<T, (TX + 2) * (TY + 2), (TX + 1) * TY, TX * (TY + 1), tile_bond_words<T>()>;
 template <typename T, int TX, int TY>
-using TileSmemP = SmemP<T, (TX + 2) * (TY + 2), (TX + 1) * TY, TX * (TY + 1)>;
+using TileSmemP = SmemP<T, (TX + 2) * (TY + 2), (TX + 1) * TY, TX * (TY + 1), tile_bond_words<T>()>;
 
 struct FusedGrid {
     int tiles_x, tiles_y, chunks, zc;
@@ -81,11 +89,18 @@ __device__ __forceinline__ VoxKin<T> get_kin(const T (*kin)[NR], int slot) {
     return k;
 }
 
-template <typename T, int NB>
+template <typename T, int NB, int NW>
 __device__ __forceinline__ void put_bond(T (*b)[NB], int i, const BondOut<T> &o) {
     b[0][i] = o.f2x; b[1][i] = o.f2y; b[2][i] = o.f2z;
-    b[3][i] = o.m1x; b[4][i] = o.m1y; b[5][i] = o.m1z;
-    b[6][i] = o.m2x; b[7][i] = o.m2y; b[8][i] = o.m2z;
+    if constexpr (NW == 9) { b[3][i] = o.m1x; b[4][i] = o.m1y; b[5][i] = o.m1z; }
+    b[NW - 3][i] = o.m2x; b[NW - 2][i] = o.m2y; b[NW - 1][i] = o.m2z;
+}
+
+// Voxel 1's half of a bond added to its force and moment sums.
+template <typename T>
+__device__ __forceinline__ void add_end1(const BondOut<T> &o, T &Fx, T &Fy, T &Fz, T &Mx, T &My, T &Mz) {
+    Fx -= o.f2x; Fy -= o.f2y; Fz -= o.f2z;
+    Mx += o.m1x; My += o.m1y; Mz += o.m1z;
 }
 
 // The state words of a cell through one buffer descriptor per state array.
@@ -313,7 +328,8 @@ template <bool Chan, bool Param, typename T, typename S>
 __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<T> &tb, const LatK<T> &C,
                                       const int TX, const int TY, int tile_x, int tile_y, int z0, int z1,
                                       T &vmax) {
-    constexpr int NR = S::NR, NB = S::NB;
+    constexpr int NR = S::NR, NB = S::NB, NW = S::NW;
+    constexpr bool kEnd1Regs = NW == 6;
     const int RW = TX + 2;
     const int tid = threadIdx.x;
     const bool lane_in = tid < TX * TY;
@@ -424,7 +440,7 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
                 T El = T(0), Eu = T(0), Ml = T(0), Mu = T(0);
                 if constexpr (Param) { El = sm.pE[bnd_lo]; Eu = sm.pE[bnd_up]; Ml = sm.pM[bnd_lo]; Mu = sm.pM[bnd_up]; }
                 const BondOut<T> o = bond_eval_xy(kl, Rl, ku, bond_kc(ml, mu, El, Eu, Ml, Mu), C, bnd_y);
-                put_bond<T, NB>(sm.b[bnd_y ? 1 : 0], bnd_i, o);
+                put_bond<T, NB, NW>(sm.b[bnd_y ? 1 : 0], bnd_i, o);
             }
         }
         const Rot<T> Rc = rot_of(cur.k.qw, cur.k.qx, cur.k.qy, cur.k.qz);
@@ -433,18 +449,28 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
             if constexpr (Param) return bond_kc(cur.m, mu, cur.E, sm.pE[sl], mass(cur.rho), sm.pM[sl]);
             else return tb.bond(cur.m, mu);
         };
+        // the voxel's force and moment sums; with kEnd1Regs they start from
+        // the bond below (carried from the previous slab or evaluated at the
+        // chunk's start) and take the voxel-1 half of the +x, +y and +z bonds
+        // as these are evaluated
+        T Fx = T(0), Fy = T(0), Fz = T(0), Mx = T(0), My = T(0), Mz = T(0);
+        if constexpr (kEnd1Regs) { Fx = cFx; Fy = cFy; Fz = cFz; Mx = cMx; My = cMy; Mz = cMz; }
         {
             const uint8_t mu = lane_in ? sm.mat[own + 1] : 0;
             if (cur.m && mu) {
                 const VoxKin<T> ku = get_kin<T, NR>(sm.kin, own + 1);
-                put_bond<T, NB>(sm.b[0], (tx + 1) + (TX + 1) * ty, bond_eval<T, 0>(cur.k, Rc, ku, kn(mu, own + 1), C));
+                const BondOut<T> o = bond_eval<T, 0>(cur.k, Rc, ku, kn(mu, own + 1), C);
+                put_bond<T, NB, NW>(sm.b[0], (tx + 1) + (TX + 1) * ty, o);
+                if constexpr (kEnd1Regs) add_end1(o, Fx, Fy, Fz, Mx, My, Mz);
             }
         }
         {
             const uint8_t mu = lane_in ? sm.mat[own + RW] : 0;
             if (cur.m && mu) {
                 const VoxKin<T> ku = get_kin<T, NR>(sm.kin, own + RW);
-                put_bond<T, NB>(sm.b[1], tx + TX * (ty + 1), bond_eval<T, 1>(cur.k, Rc, ku, kn(mu, own + RW), C));
+                const BondOut<T> o = bond_eval<T, 1>(cur.k, Rc, ku, kn(mu, own + RW), C);
+                put_bond<T, NB, NW>(sm.b[1], tx + TX * (ty + 1), o);
+                if constexpr (kEnd1Regs) add_end1(o, Fx, Fy, Fz, Mx, My, Mz);
             }
         }
         // neighbour materials for the gather, read before the slab's LDS is
@@ -459,40 +485,47 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
         BondOut<T> oz{};
         if (has_zb)
             oz = bond_eval<T, 2>(cur.k, Rc, nxt.k, bond_oo(cur, nxt), C);
+        if constexpr (kEnd1Regs) {
+            if (has_zb) add_end1(oz, Fx, Fy, Fz, Mx, My, Mz);
+            cFx = oz.f2x; cFy = oz.f2y; cFz = oz.f2z; cMx = oz.m2x; cMy = oz.m2y; cMz = oz.m2z;
+        }
         __syncthreads();
 
         // the bond results stay in LDS until the next slab's first barrier;
         // the kinematics of slab z are no longer read
         if (z + 1 < z1) stage(nxt, rp, z + 1);
         if (cur.m) {
-            T Fx = T(0), Fy = T(0), Fz = T(0), Mx = T(0), My = T(0), Mz = T(0);
             if (n_mx) {
                 const int i = tx + (TX + 1) * ty;
                 Fx += sm.b[0][0][i]; Fy += sm.b[0][1][i]; Fz += sm.b[0][2][i];
-                Mx += sm.b[0][6][i]; My += sm.b[0][7][i]; Mz += sm.b[0][8][i];
+                Mx += sm.b[0][NW - 3][i]; My += sm.b[0][NW - 2][i]; Mz += sm.b[0][NW - 1][i];
             }
-            if (n_px) {
-                const int i = (tx + 1) + (TX + 1) * ty;
-                Fx -= sm.b[0][0][i]; Fy -= sm.b[0][1][i]; Fz -= sm.b[0][2][i];
-                Mx += sm.b[0][3][i]; My += sm.b[0][4][i]; Mz += sm.b[0][5][i];
+            if constexpr (!kEnd1Regs) {
+                if (n_px) {
+                    const int i = (tx + 1) + (TX + 1) * ty;
+                    Fx -= sm.b[0][0][i]; Fy -= sm.b[0][1][i]; Fz -= sm.b[0][2][i];
+                    Mx += sm.b[0][3][i]; My += sm.b[0][4][i]; Mz += sm.b[0][5][i];
+                }
             }
             if (n_my) {
                 const int i = tx + TX * ty;
                 Fx += sm.b[1][0][i]; Fy += sm.b[1][1][i]; Fz += sm.b[1][2][i];
-                Mx += sm.b[1][6][i]; My += sm.b[1][7][i]; Mz += sm.b[1][8][i];
+                Mx += sm.b[1][NW - 3][i]; My += sm.b[1][NW - 2][i]; Mz += sm.b[1][NW - 1][i];
             }
-            if (n_py) {
-                const int i = tx + TX * (ty + 1);
-                Fx -= sm.b[1][0][i]; Fy -= sm.b[1][1][i]; Fz -= sm.b[1][2][i];
-                Mx += sm.b[1][3][i]; My += sm.b[1][4][i]; Mz += sm.b[1][5][i];
-            }
-            if (has_carry) {
-                Fx += cFx; Fy += cFy; Fz += cFz;
-                Mx += cMx; My += cMy; Mz += cMz;
-            }
-            if (has_zb) {
-                Fx -= oz.f2x; Fy -= oz.f2y; Fz -= oz.f2z;
-                Mx += oz.m1x; My += oz.m1y; Mz += oz.m1z;
+            if constexpr (!kEnd1Regs) {
+                if (n_py) {
+                    const int i = tx + TX * (ty + 1);
+                    Fx -= sm.b[1][0][i]; Fy -= sm.b[1][1][i]; Fz -= sm.b[1][2][i];
+                    Mx += sm.b[1][3][i]; My += sm.b[1][4][i]; Mz += sm.b[1][5][i];
+                }
+                if (has_carry) {
+                    Fx += cFx; Fy += cFy; Fz += cFz;
+                    Mx += cMx; My += cMy; Mz += cMz;
+                }
+                if (has_zb) {
+                    Fx -= oz.f2x; Fy -= oz.f2y; Fz -= oz.f2z;
+                    Mx += oz.m1x; My += oz.m1y; Mz += oz.m1z;
+                }
             }
             if constexpr (Param) {
                 if (a.fm_out) {
@@ -506,8 +539,10 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
                              [&](unsigned c, const VoxRaw<T> &o) { sb_store(sb, c, o); });
             });
         }
-        has_carry = has_zb;
-        cFx = oz.f2x; cFy = oz.f2y; cFz = oz.f2z; cMx = oz.m2x; cMy = oz.m2y; cMz = oz.m2z;
+        if constexpr (!kEnd1Regs) {
+            has_carry = has_zb;
+            cFx = oz.f2x; cFy = oz.f2y; cFz = oz.f2z; cMx = oz.m2x; cMy = oz.m2y; cMz = oz.m2z;
+        }
     };
 
     // two slabs per trip so that the roles of A and B alternate without copies
@@ -548,8 +583,8 @@ k_fused(StepArgs<T> a, FusedGrid g) {
 // Largest runtime tile of the batched kernel: TX, TY <= 64, TX * TY <= 256,
 // so (TX + 2)(TY + 2) <= 396 ring slots and (TX + 1) TY, TX (TY + 1) <= 320.
 constexpr int kBatchThreads = 256;
-using BatchSmemF = Smem<float, 396, 320, 320>;
-using BatchSmemD = Smem<double, 396, 320, 320>;
+using BatchSmemF = Smem<float, 396, 320, 320, 6>;
+using BatchSmemD = Smem<double, 396, 320, 320, 6>;
 template <typename T> struct BatchSmemOf;
 template <> struct BatchSmemOf<float> { using type = BatchSmemF; };
 template <> struct BatchSmemOf<double> { using type = BatchSmemD; };
