@@ -40,8 +40,8 @@ __global__ void __launch_bounds__(256) k_adj_update(StepArgs<T> a, AdjArgs<T> g)
     // kv = E l; cg, cgr, cfloor are proportional to sqrt(E m) (I = m l^2/6);
     // inv_m = 1/m, inv_I = 6/(m l^2)
     const T gd = ad.cg * mc.cg + ad.cgr * mc.cgr + ad.cfloor * mc.cfloor;
-    const T gE = ad.kv * a.l + gd / (T(2) * mc.E);
-    const T gm = ad.m - (ad.inv_m * mc.inv_m + ad.inv_I * mc.inv_I) / mc.m + gd / (T(2) * mc.m);
+    const T gE = ad.kv * a.l + pdiv(gd, T(2) * mc.E);
+    const T gm = ad.m - (ad.inv_m * mc.inv_m + ad.inv_I * mc.inv_I) * mc.inv_m + gd * T(0.5) * mc.inv_m;
     g.gloc[c] = ad.eps;
     g.gloc[st + c] = gE;
     g.gloc[2 * st + c] = gm;

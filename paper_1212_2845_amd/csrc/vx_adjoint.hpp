@@ -29,11 +29,11 @@ template <typename T>
 VX_HD void bond_k_from_E_vjp(T EA, T EB, T gA, T gB, const BondK<T> &k, T g_a1, T g_a2, T g_ct,
                              const LatK<T> &C, T *g_EA, T *g_EB) {
     // ct = 2 zeta sqrt(m a1): d ct / d a1 = ct / (2 a1)
-    const T ga1 = g_a1 + (k.a1 > T(0) ? g_ct * k.ct / (T(2) * k.a1) : T(0));
-    const T s = EA + EB;
-    const T dEc_dA = T(2) * EB * EB / (s * s), dEc_dB = T(2) * EA * EA / (s * s);
-    const T GA = EA * gA, GB = EB * gB, sg = GA + GB;
-    const T dGc_dA = T(2) * GB * GB / (sg * sg) * gA, dGc_dB = T(2) * GA * GA / (sg * sg) * gB;
+    const T ga1 = g_a1 + (k.a1 > T(0) ? g_ct * pdiv(k.ct, T(2) * k.a1) : T(0));
+    const T is = pdiv(T(1), EA + EB), is2 = T(2) * is * is;
+    const T dEc_dA = EB * EB * is2, dEc_dB = EA * EA * is2;
+    const T GA = EA * gA, GB = EB * gB, isg = pdiv(T(1), GA + GB), isg2 = T(2) * isg * isg;
+    const T dGc_dA = GB * GB * isg2 * gA, dGc_dB = GA * GA * isg2 * gB;
     const T ga2 = g_a2 * C.l * C.l26;
     *g_EA = ga1 * C.l * dEc_dA + ga2 * dGc_dA;
     *g_EB = ga1 * C.l * dEc_dB + ga2 * dGc_dB;

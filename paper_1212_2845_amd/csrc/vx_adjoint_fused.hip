@@ -148,7 +148,7 @@ __device__ __forceinline__ void bond_ends(const AdjCell<T> &A, const AdjCell<T> 
     for (int i = 0; i < kAdjKin; ++i) { ea[i] = pa[i]; eb[i] = pb[i]; }
     bond_k_from_E_vjp(A.E, B.E, A.gfac, B.gfac, K, ad.a1, ad.a2, ad.ct, C, &ea[14], &eb[14]);
     // bond damping takes the lighter mass (B on a tie, as the forward)
-    const T gmmin = ad.ct * K.ct / (T(2) * mmin);
+    const T gmmin = ad.ct * pdiv(K.ct, T(2) * mmin);
     ea[15] = A.mass < B.mass ? gmmin : T(0);
     eb[15] = A.mass < B.mass ? T(0) : gmmin;
 }
@@ -173,7 +173,7 @@ __device__ __forceinline__ void finish_voxel(const StepArgs<T> &a, const AdjArgs
     const T g_inv_m = k[7] * r.px + k[8] * r.py + k[9] * r.pz;
     const T g_inv_I = k[10] * r.lx + k[11] * r.ly + k[12] * r.lz;
     const T gE = ldc(g.gloc + st, c) + k[14];
-    const T gm = ldc(g.gloc + 2 * st, c) + k[15] - (g_inv_m * mc.inv_m + g_inv_I * mc.inv_I) / mc.m;
+    const T gm = ldc(g.gloc + 2 * st, c) + k[15] - (g_inv_m * mc.inv_m + g_inv_I * mc.inv_I) * mc.inv_m;
     g.g_E[c] += (double)gE;
     g.g_rho[c] += (double)gm * ((double)a.l * (double)a.l * (double)a.l);
     const uint8_t fl = ldc(a.flags, c);

@@ -891,7 +891,7 @@ int vx_get_fused_tile(vx_handle h, int32_t *shape, int32_t *tx, int32_t *ty, int
     if (zc) {
         const int t = kFusedShapes[c.shape].tx, u = kFusedShapes[c.shape].ty;
         const long long cols = (long long)((h->nx + t - 1) / t) * ((h->ny + u - 1) / u);
-        *zc = c.zc > 0 ? std::min(c.zc, h->nz) : balanced_zc(h->nz, cols, fused_wg_per_cu(h->precision / 8));
+        *zc = c.zc > 0 ? std::min(c.zc, h->nz) : balanced_zc(h->nz, cols, fused_wg_per_cu(h->precision / 8, h->param_mode()));
     }
     return VX_OK;
 }

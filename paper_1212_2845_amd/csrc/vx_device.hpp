@@ -61,6 +61,23 @@ template <> VX_HD double frcp<double>(double x) {
     return fma(y, e, y);
 }
 
+// Quotient and square root of positive normal numbers, for the constants
+// derived from per-voxel moduli and densities: FP32 takes the hardware
+// reciprocal and square root (about 1 ulp, a few instructions instead of
+// the correctly rounded sequences), FP64 the correctly rounded operations.
+template <typename T> VX_HD T pdiv(T a, T b);
+template <> VX_HD float pdiv<float>(float a, float b) { return a * frcp(b); }
+template <> VX_HD double pdiv<double>(double a, double b) { return a / b; }
+template <typename T> VX_HD T psqrt(T x);
+template <> VX_HD float psqrt<float>(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return sqrtf(x);
+#endif
+}
+template <> VX_HD double psqrt<double>(double x) { return sqrt(x); }
+
 // Series used on the common path, with the library functions as fallback
 // outside their range.  Term counts make the truncation error smaller than
 // half an ulp of the type over the whole fast range.
@@ -425,19 +442,22 @@ VX_HD VoxKin<T> load_kin(const T *__restrict__ s, long long stride, unsigned c,
 
 // Material constants of one voxel whose modulus E and density rho override
 // the palette's (parameter mode): mass, inertia and the stiffness- and
-// mass-dependent coefficients recomputed as the host does for a palette
-// entry.
+// mass-dependent coefficients of a palette entry.  With I = m l^2/6 and the
+// rotational stiffness E l^3/6, sqrt(I E l^3/6) = sqrt(m k_v) l^2/6, so one
+// square root serves the three damping coefficients.
 template <typename T>
 VX_HD MatConst<T> mat_with(MatConst<T> mc, T E, T rho, T l, T zeta_slow, T zeta_col) {
+    const T l26 = pdiv(l * l, T(6));
     mc.m = rho * l * l * l;
-    mc.inv_m = T(1) / mc.m;
-    mc.I = mc.m * l * l / T(6);
-    mc.inv_I = T(1) / mc.I;
+    mc.inv_m = pdiv(T(1), mc.m);
+    mc.I = mc.m * l26;
+    mc.inv_I = pdiv(T(1), mc.I);
     mc.E = E;
     mc.kv = E * l;
-    mc.cg = T(2) * zeta_slow * dsqrt(mc.m * mc.kv);
-    mc.cgr = T(2) * zeta_slow * dsqrt(mc.I * E * l * l * l / T(6));
-    mc.cfloor = T(2) * zeta_col * dsqrt(mc.m * mc.kv);
+    const T s = psqrt(mc.m * mc.kv);
+    mc.cg = T(2) * zeta_slow * s;
+    mc.cgr = mc.cg * l26;
+    mc.cfloor = T(2) * zeta_col * s;
     return mc;
 }
 
@@ -446,12 +466,12 @@ VX_HD MatConst<T> mat_with(MatConst<T> mc, T E, T rho, T l, T zeta_slow, T zeta_
 template <typename T>
 VX_HD BondK<T> bond_k_from_E(T EA, T EB, T gA, T gB, T m_min, T zeta_bond, const LatK<T> &C) {
     BondK<T> k;
-    const T Ec = T(2) * EA * EB / (EA + EB);
+    const T Ec = pdiv(T(2) * EA * EB, EA + EB);
     const T GA = EA * gA, GB = EB * gB;
-    const T Gc = T(2) * GA * GB / (GA + GB);
+    const T Gc = pdiv(T(2) * GA * GB, GA + GB);
     k.a1 = Ec * C.l;
     k.a2 = Gc * C.l * C.l26;
-    k.ct = T(2) * zeta_bond * dsqrt(m_min * k.a1);
+    k.ct = T(2) * zeta_bond * psqrt(m_min * k.a1);
     return k;
 }
 

@@ -42,8 +42,8 @@ constexpr int kKin = 14;   // ux uy uz qw qx qy qz vx vy vz wx wy wz eps
 // and, with NW = 9, the moment on voxel 1 (words 3-5).  With NW = 6 the thread that evaluates a bond adds
 // voxel 1's half to that voxel's sums at once: less LDS and fewer LDS
 // accesses, at the price of six sums held in registers through the bond
-// evaluations, which the FP32 kernel's register budget (three waves per
-// SIMD) does not have room for.
+// evaluations, which the FP32 palette kernel's register budget (three waves
+// per SIMD) does not have room for.
 template <typename T, int NR_, int NBX_, int NBY_, int NW_>
 struct Smem {
     static constexpr int NR = NR_, NB = NBX_ > NBY_ ? NBX_ : NBY_, NW = NW_;
@@ -58,12 +58,12 @@ struct SmemP : Smem<T, NR_, NBX_, NBY_, NW_> {
     T pE[NR_], pM[NR_];
 };
 
-template <typename T>
-constexpr int tile_bond_words() { return sizeof(T) == 4 ? 9 : 6; }
+template <typename T, bool Param>
+constexpr int tile_bond_words() { return sizeof(T) == 4 && !Param ? 9 : 6; }
 template <typename T, int TX, int TY>
-using TileSmem = Smem<T, (TX + 2) * (TY + 2), (TX + 1) * TY, TX * (TY + 1), tile_bond_words<T>()>;
+using TileSmem = Smem<T, (TX + 2) * (TY + 2), (TX + 1) * TY, TX * (TY + 1), tile_bond_words<T, false>()>;
 template <typename T, int TX, int TY>
-using TileSmemP = SmemP<T, (TX + 2) * (TY + 2), (TX + 1) * TY, TX * (TY + 1), tile_bond_words<T>()>;
+using TileSmemP = SmemP<T, (TX + 2) * (TY + 2), (TX + 1) * TY, TX * (TY + 1), tile_bond_words<T, true>()>;
 
 struct FusedGrid {
     int tiles_x, tiles_y, chunks, zc;
@@ -553,10 +553,12 @@ __device__ __forceinline__ void march(const StepArgs<T> &a, S &sm, const Tables<
 }
 
 // FP32 is held to 168 VGPRs, so that three workgroups share a CU (three
-// waves per SIMD; two loop-invariant values go to scratch); FP64 needs more
-// than 256 and runs one wave per SIMD.
+// waves per SIMD; two loop-invariant values go to scratch); in parameter
+// mode, which derives every bond's constants from the two moduli and
+// masses, it needs about 200 and runs two (fused_wg_per_cu); FP64 needs
+// more than 256 and runs one wave per SIMD.
 template <typename T, int TX, int TY, bool Chan, bool Param>
-__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(fused_wg_per_cu(sizeof(T), Param))))
 k_fused(StepArgs<T> a, FusedGrid g) {
     static_assert(2 * (TX + TY) <= TX * TY, "ring must fit one cell per thread");
     __shared__ typename std::conditional<Param, TileSmemP<T, TX, TY>, TileSmem<T, TX, TY>>::type sm;
@@ -639,7 +641,7 @@ hipError_t launch_tiles(const StepArgs<T> &a, int zc, bool chan, hipStream_t s) 
     g.tiles_x = (a.nx + TX - 1) / TX;
     g.tiles_y = (a.ny + TY - 1) / TY;
     const long long cols = (long long)g.tiles_x * g.tiles_y;
-    if (zc <= 0) zc = balanced_zc(a.nz, cols, fused_wg_per_cu((int)sizeof(T)));
+    if (zc <= 0) zc = balanced_zc(a.nz, cols, fused_wg_per_cu((int)sizeof(T), a.E_cell != nullptr));
     zc = zc > a.nz ? a.nz : zc;
     g.zc = zc;
     g.chunks = (a.nz + zc - 1) / zc;

@@ -65,8 +65,9 @@ int device_cus();
 // Default z chunk of a column-marching kernel with cols tile columns and
 // wg_per_cu resident workgroups per CU.
 int balanced_zc(int nz, long long cols, int wg_per_cu);
-// Resident workgroups per CU of the fused step kernel (register-bound).
-constexpr int fused_wg_per_cu(int tsize) { return tsize == 4 ? 3 : 1; }
+// Resident workgroups per CU of the fused step kernel (register-bound), by
+// element size and parameter mode.
+constexpr int fused_wg_per_cu(int tsize, bool param) { return tsize == 4 ? (param ? 2 : 3) : 1; }
 // Linear statics (matrix-free conjugate gradients): the lattice and the
 // per-cell moduli of the direct-stiffness operator.
 struct StaticArgs {
