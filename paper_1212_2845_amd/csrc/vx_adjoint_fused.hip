@@ -384,7 +384,7 @@ hipError_t launch_adjoint_fused(const StepArgs<T> &a, const AdjArgs<T> &g, hipSt
     fg.tiles_x = (a.nx + TX - 1) / TX;
     fg.tiles_y = (a.ny + TY - 1) / TY;
     const long long cols = (long long)fg.tiles_x * fg.tiles_y;
-    // two workgroups per CU in FP32 (221 VGPRs, 67 KB LDS), one in FP64
+    // two workgroups per CU in FP32 (255 VGPRs, 67 KB LDS), one in FP64
     fg.zc = balanced_zc(a.nz, cols, sizeof(T) == 4 ? 2 : 1);
     fg.chunks = (a.nz + fg.zc - 1) / fg.zc;
     k_adj_fused<T, TX, TY><<<(unsigned)(cols * fg.chunks), TX * TY, 0, s>>>(a, g, fg);
