@@ -304,7 +304,7 @@ def time_adjoint(steps=5000, K=100):
     s.step(5)
     s.grad_bind(40, 10)
     s.grad_forward(40)
-    s.grad_backward(dL_du=np.ones((ws["grid"].size, 3)))
+    s.grad_backward(dL_du=np.ones((ws["grid"].size, 3)), initial_state=False)
     del s
     w = workloads.design_lattice(steps=steps)
     filled = w["grid"].reshape(-1) > 0
@@ -336,7 +336,7 @@ def time_adjoint(steps=5000, K=100):
     s.grad_forward(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    g = s.grad_backward(dL_du=wu)
+    g = s.grad_backward(dL_du=wu, initial_state=False)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     del s
@@ -356,7 +356,7 @@ def time_adjoint(steps=5000, K=100):
         s.grad_forward(steps)
         torch.cuda.synchronize()
         u1 = time.perf_counter()
-        gt = s.grad_backward(dL_du=wu)
+        gt = s.grad_backward(dL_du=wu, initial_state=False)
         torch.cuda.synchronize()
         u2 = time.perf_counter()
         same = all(np.array_equal(gt[k], g[k]) for k in ("E", "rho", "phase", "amp"))
@@ -378,7 +378,8 @@ def time_adjoint(steps=5000, K=100):
                     "kernel, which the recorded forward and the segment recompute also run; fused_forward_s: the "
                     "same lattice with the palette's moduli; the target is fwd+adj <= 4 x fwd; wall time with host "
                     "synchronisation at each checkpoint and the host copies of the adjoint in and the gradients "
-                    "out"}
+                    "out; the reverse run returns the per-voxel modulus, density, phase and amplitude gradients (the "
+                    "design loop's), not those of the initial state"}
 
 
 def time_collision_schemes(steps=5000, graph=True, w=None):

@@ -380,8 +380,11 @@ int vx_grad_workspace_bytes(vx_handle h, int64_t max_steps, int32_t K, uint64_t 
  * reverse run then rebuilds each step's candidate lists from the taped
  * state and applies the contact forces' reverse (gradients through
  * contact; the lists themselves are piecewise constant).  Replaces an
- * earlier binding.  Errors: VX_ESTATE, VX_EINVAL (too small, misaligned, K
- * or max_steps < 1). */
+ * earlier binding.  It also takes pinned host memory (about 25 words + 32
+ * bytes per cell, freed by vx_destroy) through which the reverse run's
+ * host copies go; if that allocation fails the reverse run stages in
+ * ordinary host memory instead.  Errors: VX_ESTATE, VX_EINVAL (too small,
+ * misaligned, K or max_steps < 1). */
 int vx_grad_bind(vx_handle h, void *device_ptr, uint64_t bytes, int64_t max_steps, int32_t K);
 
 /* Advance n steps (1 <= n <= max_steps) like vx_step and record the

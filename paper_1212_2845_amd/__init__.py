@@ -526,18 +526,22 @@ class Sim:
     def grad_forward(self, n):
         self._check(lib().vx_grad_forward(self.h, int(n)))
 
-    def grad_backward(self, dL_du=None, dL_dq=None, dL_dv=None, dL_dw=None):
+    def grad_backward(self, dL_du=None, dL_dq=None, dL_dv=None, dL_dw=None, initial_state=True):
         """Gradients of a function of the final state (adjoints given per
-        cell, None = 0) w.r.t. the moduli, the per-voxel actuation phase and
-        amplitude, and the rollout's initial state."""
+        cell, None = 0) w.r.t. the moduli, the densities, the per-voxel
+        actuation phase and amplitude, and (with initial_state) the
+        rollout's initial state (keys u0, q0, v0, w0)."""
         n = self.ncell
         conv = lambda a, k: None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(n, k)
         du, dq, dv, dw = conv(dL_du, 3), conv(dL_dq, 4), conv(dL_dv, 3), conv(dL_dw, 3)
-        out = {"E": np.empty(n), "rho": np.empty(n), "phase": np.empty(n), "amp": np.empty(n),
-               "u0": np.empty((n, 3)), "q0": np.empty((n, 4)), "v0": np.empty((n, 3)), "w0": np.empty((n, 3))}
+        out = {"E": np.empty(n), "rho": np.empty(n), "phase": np.empty(n), "amp": np.empty(n)}
+        if initial_state:
+            out.update({"u0": np.empty((n, 3)), "q0": np.empty((n, 4)), "v0": np.empty((n, 3)),
+                        "w0": np.empty((n, 3))})
         self._check(lib().vx_grad_backward(self.h, _ptr(du), _ptr(dq), _ptr(dv), _ptr(dw), _ptr(out["E"]),
                                            _ptr(out["rho"]), _ptr(out["phase"]), _ptr(out["amp"]),
-                                           _ptr(out["u0"]), _ptr(out["q0"]), _ptr(out["v0"]), _ptr(out["w0"])))
+                                           _ptr(out.get("u0")), _ptr(out.get("q0")), _ptr(out.get("v0")),
+                                           _ptr(out.get("w0"))))
         return out
 
 
@@ -564,7 +568,8 @@ def _rollout_fn():
 
         @staticmethod
         def backward(ctx, gu, gv):
-            g = ctx.sim.grad_backward(dL_du=gu.detach().cpu().numpy(), dL_dv=gv.detach().cpu().numpy())
+            g = ctx.sim.grad_backward(dL_du=gu.detach().cpu().numpy(), dL_dv=gv.detach().cpu().numpy(),
+                                      initial_state=False)
             out = [torch.from_numpy(g[k]).to(device=d, dtype=t)
                    for k, (d, t) in zip(("E", "rho", "phase", "amp"), ctx.like)]
             return tuple(out) + (None, None)

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <vector>
 
 #include "vx_host.hpp"
@@ -48,6 +49,13 @@ uint64_t state_slot(const vx_sim *h) { return align_up((uint64_t)N_WORDS * h->nc
 uint64_t flags_slot(const vx_sim *h) { return align_up((uint64_t)h->ncell); }
 uint64_t fm_slot(const vx_sim *h) { return align_up(6ull * h->ncell * h->tsize); }
 
+// Host staging of the reverse run: the adjoint of the state (13 words), the
+// momenta words (P, L) of the first and of the final state, and the four
+// FP64 per-cell gradients.
+uint64_t stage_bytes(const vx_sim *h) {
+    return (uint64_t)(N_WORDS + 12) * h->ncell * h->tsize + 32ull * h->ncell;
+}
+
 double voxel_mass_of(const vx_sim *h, long long c) {
     const double l = h->p.voxel_size;
     return h->has_rho ? h->rho_cell[c] * l * l * l : voxel_mass(h->pal[h->grid[c]], l);
@@ -63,21 +71,46 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
     char *gw = h->gws;
     hipStream_t s = h->stream;
     const uint64_t sb = state_slot(h), fb = flags_slot(h), fmb = fm_slot(h);
-    // adjoint of the final state, in the stored words (v = P / m, w = L / I)
-    std::vector<T> lam((size_t)N_WORDS * n, T(0));
-    for (long long c = 0; c < n; ++c) {
-        if (!h->grid[c]) continue;
-        const double m = voxel_mass_of(h, c), I = m * l * l / 6.0;
-        for (int k = 0; k < 3; ++k) {
-            if (dL_du) lam[(size_t)(W_UX + k) * n + c] = (T)dL_du[3 * c + k];
-            if (dL_dv) lam[(size_t)(W_PX + k) * n + c] = (T)(dL_dv[3 * c + k] / m);
-            if (dL_dw) lam[(size_t)(W_LX + k) * n + c] = (T)(dL_dw[3 * c + k] / I);
-        }
-        if (dL_dq)
-            for (int k = 0; k < 4; ++k) lam[(size_t)(W_QW + k) * n + c] = (T)dL_dq[4 * c + k];
+    // host staging (pinned when vx_grad_bind could take it)
+    const size_t nz = (size_t)n, lamB = (size_t)N_WORDS * nz * sizeof(T), momB = 6 * nz * sizeof(T);
+    std::unique_ptr<char[]> own_stage;
+    char *stage = (char *)h->pinned;
+    if (!stage || h->pinned_bytes < stage_bytes(h)) {
+        own_stage.reset(new char[stage_bytes(h)]);
+        stage = own_stage.get();
     }
-    HIP_OK(h, hipMemcpyAsync(gw + G.lam[0], lam.data(), lam.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    HIP_OK(h, hipMemsetAsync(gw + G.lam[1], 0, lam.size() * sizeof(T), s));
+    T *lam = (T *)stage;                                   // 13 words
+    T *x0m = (T *)(stage + lamB);                          // P, L of the first state
+    T *xNm = (T *)(stage + lamB + momB);                   // P, L of the final state
+    double *gE = (double *)(stage + lamB + 2 * momB), *gr = gE + nz, *gp = gr + nz, *ga = gp + nz;
+    // adjoint of the final state, in the stored words (v = P / m,
+    // w = L / I): each group of words with a given adjoint is uploaded, the
+    // others are cleared on the device
+    struct Group {
+        int w0, k;
+        const double *src;
+        int scale;   // 0: as given, 1: over m, 2: over I
+    };
+    const Group groups[4] = {{W_UX, 3, dL_du, 0}, {W_QW, 4, dL_dq, 0}, {W_PX, 3, dL_dv, 1}, {W_LX, 3, dL_dw, 2}};
+    for (const Group &gr_ : groups) {
+        T *dst = lam + (size_t)gr_.w0 * nz;
+        char *dev = gw + G.lam[0] + (size_t)gr_.w0 * nz * sizeof(T);
+        const size_t bytes = (size_t)gr_.k * nz * sizeof(T);
+        if (!gr_.src) {
+            HIP_OK(h, hipMemsetAsync(dev, 0, bytes, s));
+            continue;
+        }
+        for (long long c = 0; c < n; ++c) {
+            const bool f = h->grid[c] != 0;
+            const double m = f && gr_.scale ? voxel_mass_of(h, c) : 1.0, I = m * l * l / 6.0;
+            for (int k = 0; k < gr_.k; ++k) {
+                const double v = gr_.src[(size_t)gr_.k * c + k];
+                dst[(size_t)k * nz + c] = !f ? T(0) : gr_.scale == 1 ? (T)(v / m) : gr_.scale == 2 ? (T)(v / I) : (T)v;
+            }
+        }
+        HIP_OK(h, hipMemcpyAsync(dev, dst, bytes, hipMemcpyHostToDevice, s));
+    }
+    HIP_OK(h, hipMemsetAsync(gw + G.lam[1], 0, lamB, s));
     HIP_OK(h, hipMemsetAsync(gw + G.gE, 0, n * 8, s));
     HIP_OK(h, hipMemsetAsync(gw + G.grho, 0, n * 8, s));
     HIP_OK(h, hipMemsetAsync(gw + G.gphase, 0, n * 8, s));
@@ -157,19 +190,19 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
         // the lists now hold the first step's pairs: rebuild before the next
         HIP_OK(h, launch_force_rebuild(make_collide(h), s));
     }
-    HIP_OK(h, hipMemcpyAsync(lam.data(), gw + G.lam[li], lam.size() * sizeof(T), hipMemcpyDeviceToHost, s));
-    // initial state (checkpoint 0) and final state, for the density's
-    // effect through the conversions between momenta and velocities: the
-    // initial velocities are held fixed (P0 = m v0) and the loss reads the
-    // final velocities (v = P / m)
-    std::vector<T> x0(lam.size()), xN(lam.size());
-    HIP_OK(h, hipMemcpyAsync(x0.data(), gw + G.ck_state, x0.size() * sizeof(T), hipMemcpyDeviceToHost, s));
-    HIP_OK(h, hipMemcpyAsync(xN.data(), h->ws + h->L.state[h->cur], xN.size() * sizeof(T), hipMemcpyDeviceToHost, s));
-    std::vector<double> gE(n), gr(n), gp(n), ga(n);
-    HIP_OK(h, hipMemcpyAsync(gE.data(), gw + G.gE, n * 8, hipMemcpyDeviceToHost, s));
-    HIP_OK(h, hipMemcpyAsync(gr.data(), gw + G.grho, n * 8, hipMemcpyDeviceToHost, s));
-    HIP_OK(h, hipMemcpyAsync(gp.data(), gw + G.gphase, n * 8, hipMemcpyDeviceToHost, s));
-    HIP_OK(h, hipMemcpyAsync(ga.data(), gw + G.gamp, n * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(h, hipMemcpyAsync(lam, gw + G.lam[li], lamB, hipMemcpyDeviceToHost, s));
+    // momenta of the initial state (checkpoint 0) and of the final state,
+    // for the density's effect through the conversions between momenta and
+    // velocities: the initial velocities are held fixed (P0 = m v0) and the
+    // loss reads the final velocities (v = P / m); P and L are words 7-12
+    const bool want_xN = g_rho && (dL_dv || dL_dw);
+    const size_t mom0 = (size_t)W_PX * nz * sizeof(T);
+    if (g_rho) HIP_OK(h, hipMemcpyAsync(x0m, gw + G.ck_state + mom0, momB, hipMemcpyDeviceToHost, s));
+    if (want_xN) HIP_OK(h, hipMemcpyAsync(xNm, h->ws + h->L.state[h->cur] + mom0, momB, hipMemcpyDeviceToHost, s));
+    HIP_OK(h, hipMemcpyAsync(gE, gw + G.gE, nz * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(h, hipMemcpyAsync(gr, gw + G.grho, nz * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(h, hipMemcpyAsync(gp, gw + G.gphase, nz * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(h, hipMemcpyAsync(ga, gw + G.gamp, nz * 8, hipMemcpyDeviceToHost, s));
     HIP_OK(h, hipStreamSynchronize(s));
     Scalars sc;
     HIP_OK(h, hipMemcpyAsync(&sc, h->ws + h->L.scalars, sizeof(sc), hipMemcpyDeviceToHost, s));
@@ -186,19 +219,21 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
         gp[c] = ga[c] = 0.0;
     }
     h->chan_grad_valid = true;
+    const bool need_m = g_rho || g_v0 || g_w0;
     for (long long c = 0; c < n; ++c) {
         const bool f = h->grid[c] != 0;
+        const double m = f && need_m ? voxel_mass_of(h, c) : 0.0, I = m * l * l / 6.0;
         if (g_E) g_E[c] = f ? gE[c] : 0.0;
         if (g_rho) {
             // P0 = m v0 and L0 = I w0 with m, I proportional to rho
             double gi = 0.0;
             if (f) {
-                const double m = voxel_mass_of(h, c), I = m * l * l / 6.0, rho = m / (l * l * l);
+                const double rho = m / (l * l * l);
                 for (int k = 0; k < 3; ++k) {
-                    gi += (double)lam[(size_t)(W_PX + k) * n + c] * (double)x0[(size_t)(W_PX + k) * n + c] +
-                          (double)lam[(size_t)(W_LX + k) * n + c] * (double)x0[(size_t)(W_LX + k) * n + c];
-                    if (dL_dv) gi -= dL_dv[3 * c + k] * (double)xN[(size_t)(W_PX + k) * n + c] / m;
-                    if (dL_dw) gi -= dL_dw[3 * c + k] * (double)xN[(size_t)(W_LX + k) * n + c] / I;
+                    gi += (double)lam[(size_t)(W_PX + k) * n + c] * (double)x0m[(size_t)k * n + c] +
+                          (double)lam[(size_t)(W_LX + k) * n + c] * (double)x0m[(size_t)(3 + k) * n + c];
+                    if (dL_dv) gi -= dL_dv[3 * c + k] * (double)xNm[(size_t)k * n + c] / m;
+                    if (dL_dw) gi -= dL_dw[3 * c + k] * (double)xNm[(size_t)(3 + k) * n + c] / I;
                 }
                 gi /= rho;
             }
@@ -206,7 +241,6 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
         }
         if (g_phase) g_phase[c] = f ? gp[c] : 0.0;
         if (g_amp) g_amp[c] = f ? ga[c] : 0.0;
-        const double m = f ? voxel_mass_of(h, c) : 0.0, I = m * l * l / 6.0;
         for (int k = 0; k < 3; ++k) {
             if (g_u0) g_u0[3 * c + k] = f ? (double)lam[(size_t)(W_UX + k) * n + c] : 0.0;
             if (g_v0) g_v0[3 * c + k] = f ? (double)lam[(size_t)(W_PX + k) * n + c] * m : 0.0;
@@ -298,6 +332,18 @@ int vx_grad_bind(vx_handle h, void *device_ptr, uint64_t bytes, int64_t max_step
     h->gws = (char *)device_ptr;
     h->GL = G;
     h->tape_valid = false;
+    if (h->pinned_bytes < stage_bytes(h)) {
+        if (h->pinned) (void)hipHostFree(h->pinned);
+        h->pinned = nullptr;
+        h->pinned_bytes = 0;
+        void *p = nullptr;
+        if (hipHostMalloc(&p, stage_bytes(h), hipHostMallocDefault) == hipSuccess) {
+            h->pinned = p;
+            h->pinned_bytes = stage_bytes(h);
+        } else {
+            (void)hipGetLastError();   // the reverse run stages in ordinary host memory
+        }
+    }
     return VX_OK;
 }
 

@@ -114,7 +114,18 @@ struct vx_sim {
     bool tape_valid = false;              // a recorded rollout ends at the current state
     int64_t tape_n = 0;
     long long tape_step0 = 0;
+    // pinned host memory for the reverse run's host copies (taken at
+    // vx_grad_bind when it can be; ordinary host memory otherwise)
+    void *pinned = nullptr;
+    uint64_t pinned_bytes = 0;
     std::string err;
+
+    vx_sim() = default;
+    vx_sim(const vx_sim &) = delete;
+    vx_sim &operator=(const vx_sim &) = delete;
+    ~vx_sim() {
+        if (pinned) (void)hipHostFree(pinned);
+    }
 };
 
 inline int fail(vx_sim *h, int code, const std::string &msg) {

@@ -273,6 +273,27 @@ def test_checkpoint_interval_does_not_change_gradients(precision):
             assert np.array_equal(g[k], ref[k]), (K, k)
 
 
+def test_parameter_gradients_without_initial_state():
+    """A reverse run asked only for the parameter gradients (no initial-state
+    outputs) returns the same modulus, density, phase and amplitude
+    gradients, bitwise, as one that also returns the initial-state
+    gradients; so does one without the final-velocity adjoint, which then
+    skips reading the final momenta back."""
+    w = workloads.grad_object(seed=71, scenario="free")
+    wu, wv = loss_weights(w, seed=72)
+    announce("parameter gradients without the initial state")
+    for dv in (wv, None):
+        out = []
+        for full in (True, False):
+            s = gpu_sim(w, 64)
+            s.grad_bind(w["steps"], 20)
+            s.grad_forward(w["steps"])
+            out.append(s.grad_backward(dL_du=wu, dL_dv=dv, initial_state=full))
+        assert "v0" in out[0] and "v0" not in out[1]
+        for k in ("E", "rho", "phase", "amp"):
+            assert np.array_equal(out[0][k], out[1][k]), k
+
+
 def test_tape_forward_equals_plain_forward():
     """The K = 1 forward run (each step written into the next tape slot) ends
     in the state that plain stepping reaches, bitwise, with the step and
