@@ -49,6 +49,8 @@ extern "C" {
 #define VX_EOVERFLOW (-4)  /* a voxel had more collision candidates than
                               contact_cap */
 #define VX_ESTATE (-5)     /* call out of order (e.g. step before bind) */
+#define VX_ENOMEM (-6)     /* host memory exhausted; the call had no effect
+                              that later calls depend on */
 
 /* One palette entry.  Index 0 of every palette is the empty material and
  * its fields are ignored.  The paper's AddMat takes E and the Poisson

@@ -23,6 +23,7 @@ VX_EDEVICE = -2
 VX_EUNSTABLE = -3
 VX_EOVERFLOW = -4
 VX_ESTATE = -5
+VX_ENOMEM = -6
 
 KERNEL_FUSED = 0
 KERNEL_SPLIT = 1

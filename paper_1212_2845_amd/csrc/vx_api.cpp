@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -379,6 +380,7 @@ extern "C" {
 
 int vx_create(const uint8_t *grid, int32_t nx, int32_t ny, int32_t nz, const vx_material *palette,
               int32_t n_mat, const vx_params *params, int32_t precision, void *stream, vx_handle *out) {
+    VX_TRY
     if (!out) return VX_EINVAL;
     *out = nullptr;
     if (!grid || !palette || !params || nx <= 0 || ny <= 0 || nz <= 0 || n_mat < 1 || n_mat > 256)
@@ -402,7 +404,8 @@ int vx_create(const uint8_t *grid, int32_t nx, int32_t ny, int32_t nz, const vx_
     }
     for (long long c = 0; c < ncell; ++c)
         if (grid[c] >= n_mat) return VX_EINVAL;
-    vx_sim *h = new vx_sim();
+    std::unique_ptr<vx_sim> owner(new vx_sim());
+    vx_sim *h = owner.get();
     h->nx = nx; h->ny = ny; h->nz = nz; h->ncell = ncell;
     h->p = p;
     if (h->p.dt_scale == 0.0) h->p.dt_scale = 1.0;
@@ -452,18 +455,22 @@ int vx_create(const uint8_t *grid, int32_t nx, int32_t ny, int32_t nz, const vx_
     h->coll_cells = h->surf_cells;
     size_collision_table(h);
     update_cmax(h);
-    *out = h;
+    *out = owner.release();
     return VX_OK;
+    VX_CATCH(nullptr)
 }
 
 int vx_workspace_bytes(vx_handle h, uint64_t *bytes) {
+    VX_TRY
     if (!h || !bytes) return VX_EINVAL;
     compute_layout(h);
     *bytes = h->L.total;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_bind_workspace(vx_handle h, void *device_ptr, uint64_t bytes) {
+    VX_TRY
     if (!h) return VX_EINVAL;
     if (h->bound) return fail(h, VX_ESTATE, "workspace already bound");
     compute_layout(h);
@@ -504,9 +511,11 @@ int vx_bind_workspace(vx_handle h, void *device_ptr, uint64_t bytes) {
     r = put_state(h, h->state0);
     if (r != VX_OK) { h->bound = false; return r; }
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_set_fixed(vx_handle h, const uint8_t *mask) {
+    VX_TRY
     if (!h || !mask) return VX_EINVAL;
     std::vector<double> st;
     int r = get_state(h, st);
@@ -523,6 +532,7 @@ int vx_set_fixed(vx_handle h, const uint8_t *mask) {
     r = put_state(h, st);
     if (r) return r;
     return reupload_static(h);
+    VX_CATCH(h)
 }
 
 static int apply_forces(vx_sim *h) {
@@ -542,11 +552,13 @@ static int apply_forces(vx_sim *h) {
 }
 
 int vx_set_forces(vx_handle h, const double *force) {
+    VX_TRY
     if (!h || !force) return VX_EINVAL;
     for (long long i = 0; i < 3 * h->ncell; ++i)
         if (!std::isfinite(force[i])) return fail(h, VX_EINVAL, "non-finite force");
     h->force.assign(force, force + 3 * h->ncell);
     return apply_forces(h);
+    VX_CATCH(h)
 }
 
 // A voxel touches the box [lo, hi) (fractions of the workspace) when its
@@ -562,14 +574,17 @@ static bool touches(const vx_sim *h, long long c, const double *loc, const doubl
 }
 
 int vx_fixed_region(vx_handle h, const double loc[3], const double size[3]) {
+    VX_TRY
     if (!h || !loc || !size) return VX_EINVAL;
     std::vector<uint8_t> mask(h->ncell, 0);
     for (long long c = 0; c < h->ncell; ++c)
         mask[c] = (h->grid[c] && ((h->flags[c] & FLAG_FIXED) || touches(h, c, loc, size))) ? 1 : 0;
     return vx_set_fixed(h, mask.data());
+    VX_CATCH(h)
 }
 
 int vx_forced_region(vx_handle h, const double loc[3], const double size[3], const double force[3]) {
+    VX_TRY
     if (!h || !loc || !size || !force) return VX_EINVAL;
     std::vector<long long> sel;
     for (long long c = 0; c < h->ncell; ++c)
@@ -578,9 +593,11 @@ int vx_forced_region(vx_handle h, const double loc[3], const double size[3], con
     for (long long c : sel)
         for (int k = 0; k < 3; ++k) h->force[3 * c + k] = force[k] / (double)sel.size();
     return apply_forces(h);
+    VX_CATCH(h)
 }
 
 int vx_set_actuation(vx_handle h, const double *amp, const double *phase) {
+    VX_TRY
     if (!h) return VX_EINVAL;
     h->has_act = amp || phase;
     for (long long c = 0; c < h->ncell; ++c) {
@@ -590,10 +607,12 @@ int vx_set_actuation(vx_handle h, const double *amp, const double *phase) {
     }
     update_cmax(h);
     return reupload_static(h);
+    VX_CATCH(h)
 }
 
 int vx_set_channels(vx_handle h, const vx_channel *ch, int32_t n_ch, const int32_t *mat_channel,
                     const int32_t *cell_channel) {
+    VX_TRY
     if (!h || n_ch < 0 || n_ch > VX_MAX_CHANNELS || (n_ch > 0 && !ch)) return VX_EINVAL;
     for (int k = 0; k < n_ch; ++k) {
         const vx_channel &c = ch[k];
@@ -620,9 +639,11 @@ int vx_set_channels(vx_handle h, const vx_channel *ch, int32_t n_ch, const int32
     h->tape_valid = false;
     update_cmax(h);
     return reupload_static(h);
+    VX_CATCH(h)
 }
 
 int vx_set_velocity(vx_handle h, const double *velocity) {
+    VX_TRY
     if (!h || !velocity) return VX_EINVAL;
     std::vector<double> st;
     int r = get_state(h, st);
@@ -633,29 +654,37 @@ int vx_set_velocity(vx_handle h, const double *velocity) {
         for (int k = 0; k < 3; ++k) st[(size_t)(W_PX + k) * h->ncell + c] = m * velocity[3 * c + k];
     }
     return put_state(h, st);
+    VX_CATCH(h)
 }
 
 int vx_step(vx_handle h, int64_t n) {
+    VX_TRY
     if (!h || n < 0) return VX_EINVAL;
     if (!h->bound) return fail(h, VX_ESTATE, "vx_step before vx_bind_workspace");
     if (n == 0) return VX_OK;
     h->tape_valid = false;
     return h->precision == 64 ? run_steps<double>(h, n) : run_steps<float>(h, n);
+    VX_CATCH(h)
 }
 
 int vx_energy(vx_handle h, double out[10]) {
+    VX_TRY
     if (!h || !out) return VX_EINVAL;
     if (!h->bound) return fail(h, VX_ESTATE, "vx_energy before vx_bind_workspace");
     return h->precision == 64 ? energy<double>(h, out) : energy<float>(h, out);
+    VX_CATCH(h)
 }
 
 int vx_energy_enqueue(vx_handle h, double *out) {
+    VX_TRY
     if (!h || !out) return VX_EINVAL;
     if (!h->bound) return fail(h, VX_ESTATE, "vx_energy_enqueue before vx_bind_workspace");
     return h->precision == 64 ? energy_enqueue<double>(h, out) : energy_enqueue<float>(h, out);
+    VX_CATCH(h)
 }
 
 int vx_probe(vx_handle h, const int32_t *cells, int32_t n, int32_t word, void *out) {
+    VX_TRY
     if (!h || n < 0 || word < 0 || word >= N_WORDS || (n > 0 && (!cells || !out))) return VX_EINVAL;
     if (!h->bound) return fail(h, VX_ESTATE, "vx_probe before vx_bind_workspace");
     const char *st = h->ws + h->L.state[h->cur];
@@ -666,19 +695,24 @@ int vx_probe(vx_handle h, const int32_t *cells, int32_t n, int32_t word, void *o
         HIP_OK(h, launch_probe<float>((const float *)st, h->ncell, h->ncell, cells, n, word, (float *)out,
                                       h->stream));
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_step_enqueue(vx_handle h, int64_t n) {
+    VX_TRY
     if (!h || n < 0) return VX_EINVAL;
     if (!h->bound) return fail(h, VX_ESTATE, "vx_step_enqueue before vx_bind_workspace");
     h->tape_valid = false;
     return h->precision == 64 ? enqueue_steps<double>(h, n) : enqueue_steps<float>(h, n);
+    VX_CATCH(h)
 }
 
 int vx_status(vx_handle h) {
+    VX_TRY
     if (!h) return VX_EINVAL;
     if (!h->bound) return VX_OK;
     return poll_status(h);
+    VX_CATCH(h)
 }
 
 // Highest bond frequency sqrt(k_b / m_min) with per-cell moduli E and
@@ -736,16 +770,21 @@ static int set_param(vx_sim *h, const double *vals, bool is_E, const char *what)
 }
 
 int vx_set_stiffness(vx_handle h, const double *E) {
+    VX_TRY
     if (!h) return VX_EINVAL;
     return set_param(h, E, true, "modulus");
+    VX_CATCH(h)
 }
 
 int vx_set_density(vx_handle h, const double *rho) {
+    VX_TRY
     if (!h) return VX_EINVAL;
     return set_param(h, rho, false, "density");
+    VX_CATCH(h)
 }
 
 int vx_read_state(vx_handle h, double *u, double *q, double *vel, double *omega) {
+    VX_TRY
     if (!h) return VX_EINVAL;
     std::vector<double> st;
     int r = get_state(h, st);
@@ -765,9 +804,11 @@ int vx_read_state(vx_handle h, double *u, double *q, double *vel, double *omega)
             for (int k = 0; k < 4; ++k) q[4 * c + k] = m ? st[(size_t)(W_QW + k) * n + c] : (k == 0 ? 1.0 : 0.0);
     }
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_write_state(vx_handle h, const double *u, const double *q, const double *vel, const double *omega) {
+    VX_TRY
     if (!h) return VX_EINVAL;
     std::vector<double> st;
     int r = get_state(h, st);
@@ -789,9 +830,11 @@ int vx_write_state(vx_handle h, const double *u, const double *q, const double *
     r = put_state(h, st);
     if (r) return r;
     return h->precision == 64 ? request_rebuild<double>(h) : request_rebuild<float>(h);
+    VX_CATCH(h)
 }
 
 int vx_read_flags(vx_handle h, uint8_t *is_static, uint8_t *surface) {
+    VX_TRY
     if (!h) return VX_EINVAL;
     std::vector<uint8_t> fl(h->flags);
     if (h->bound) {
@@ -803,21 +846,27 @@ int vx_read_flags(vx_handle h, uint8_t *is_static, uint8_t *surface) {
         if (surface) surface[c] = (fl[c] & FLAG_SURFACE) ? 1 : 0;
     }
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_get_dt(vx_handle h, double *dt) {
+    VX_TRY
     if (!h || !dt) return VX_EINVAL;
     *dt = h->dt;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_get_time(vx_handle h, double *t) {
+    VX_TRY
     if (!h || !t) return VX_EINVAL;
     *t = (double)h->step * h->dt;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_counters(vx_handle h, int64_t out[4]) {
+    VX_TRY
     if (!h || !out) return VX_EINVAL;
     Scalars sc{};
     if (h->bound) {
@@ -829,9 +878,11 @@ int vx_counters(vx_handle h, int64_t out[4]) {
     out[2] = (int64_t)sc.pair_count / 2;
     out[3] = h->nvox;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_candidates(vx_handle h, int32_t *cell_a, int32_t *cell_b, int32_t max_pairs, int32_t *n_pairs) {
+    VX_TRY
     if (!h || !n_pairs || max_pairs < 0) return VX_EINVAL;
     *n_pairs = 0;
     if (!h->bound || !h->p.self_collision_on) return VX_OK;
@@ -850,9 +901,11 @@ int vx_candidates(vx_handle h, int32_t *cell_a, int32_t *cell_b, int32_t max_pai
         }
     *n_pairs = k;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_set_collision_mode(vx_handle h, int32_t all_voxels, int32_t every_step) {
+    VX_TRY
     if (!h || (all_voxels != 0 && all_voxels != 1) || (every_step != 0 && every_step != 1)) return VX_EINVAL;
     if (h->bound && (all_voxels != 0) != h->coll_all)
         return fail(h, VX_ESTATE, "the voxels taking part in collision detection are fixed at bind");
@@ -873,16 +926,20 @@ int vx_set_collision_mode(vx_handle h, int32_t all_voxels, int32_t every_step) {
         size_collision_table(h);
     }
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_set_fused_tile(vx_handle h, int32_t shape, int32_t zc) {
+    VX_TRY
     if (!h || shape < -1 || shape >= kNumFusedShapes || zc < 0) return VX_EINVAL;
     h->fused_shape = shape;
     h->fused_zc = zc;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_get_fused_tile(vx_handle h, int32_t *shape, int32_t *tx, int32_t *ty, int32_t *zc) {
+    VX_TRY
     if (!h) return VX_EINVAL;
     const FusedCfg c = fused_cfg(h);
     if (shape) *shape = c.shape;
@@ -894,33 +951,42 @@ int vx_get_fused_tile(vx_handle h, int32_t *shape, int32_t *tx, int32_t *ty, int
         *zc = c.zc > 0 ? std::min(c.zc, h->nz) : balanced_zc(h->nz, cols, fused_wg_per_cu(h->precision / 8, h->param_mode()));
     }
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_autotune(vx_handle h, int32_t iters, int32_t *shape, int32_t *zc) {
+    VX_TRY
     if (!h || iters <= 0) return VX_EINVAL;
     if (!h->bound) return fail(h, VX_ESTATE, "vx_autotune before vx_bind_workspace");
     if (h->n_mat > kFusedMaxMat) return fail(h, VX_ESTATE, "palette too large for the fused kernel");
     if (!fused_state_fits(h->ncell, h->precision / 8))
         return fail(h, VX_ESTATE, "lattice too large for the fused kernel");
     return h->precision == 64 ? autotune<double>(h, iters, shape, zc) : autotune<float>(h, iters, shape, zc);
+    VX_CATCH(h)
 }
 
 int vx_time_kernel(vx_handle h, int32_t iters, double *ms_per_launch) {
+    VX_TRY
     if (!h || iters <= 0 || !ms_per_launch) return VX_EINVAL;
     if (!h->bound) return fail(h, VX_ESTATE, "vx_time_kernel before vx_bind_workspace");
     return h->precision == 64 ? time_kernel<double>(h, iters, ms_per_launch)
                               : time_kernel<float>(h, iters, ms_per_launch);
+    VX_CATCH(h)
 }
 
 int vx_set_kernel(vx_handle h, int32_t kind) {
+    VX_TRY
     if (!h || (kind != 0 && kind != 1)) return VX_EINVAL;
     h->kernel_kind = kind;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_destroy(vx_handle h) {
+    VX_TRY
     delete h;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 const char *vx_last_error(vx_handle h) { return h ? h->err.c_str() : "null handle"; }

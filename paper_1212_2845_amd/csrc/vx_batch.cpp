@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <memory>
 #include <numeric>
 #include <queue>
 #include <string>
@@ -387,6 +388,7 @@ extern "C" {
 
 int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *palette, int32_t n_mat,
                     const vx_params *params, int32_t precision, void *stream, vx_batch *out) {
+    VX_TRY
     if (!out) return VX_EINVAL;
     *out = nullptr;
     if (!objs || n_obj <= 0 || !palette || n_mat < 1 || n_mat > kFusedMaxMat || !params) return VX_EINVAL;
@@ -402,7 +404,8 @@ int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *pal
             !std::isfinite(m.cte))
             return VX_EINVAL;
     }
-    vx_batch_sim *h = new vx_batch_sim();
+    std::unique_ptr<vx_batch_sim> owner(new vx_batch_sim());
+    vx_batch_sim *h = owner.get();
     h->precision = precision;
     h->tsize = precision == 64 ? 8 : 4;
     h->stream = (hipStream_t)stream;
@@ -417,7 +420,6 @@ int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *pal
         const vx_object &o = objs[i];
         if (!o.grid || o.nx <= 0 || o.ny <= 0 || o.nz <= 0 || o.reserved != 0 || !std::isfinite(o.origin[0]) ||
             !std::isfinite(o.origin[1]) || !std::isfinite(o.origin[2])) {
-            delete h;
             return VX_EINVAL;
         }
         const long long nc = (long long)o.nx * o.ny * o.nz;
@@ -434,7 +436,7 @@ int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *pal
                 for (int x = 0; x < o.nx; ++x) {
                     const long long c = x + (long long)o.nx * (y + (long long)o.ny * z);
                     const int m = o.grid[c];
-                    if (m >= n_mat) { delete h; return VX_EINVAL; }
+                    if (m >= n_mat) return VX_EINVAL;
                     if (!m) continue;
                     ++oh.nvox;
                     seen_vox[m] = 1;
@@ -465,7 +467,7 @@ int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *pal
                                 surf = k < 0 || k >= dim[a] || !o.grid[c + d * st[a]];
                             }
                         if (!surf) continue;
-                        if (off + c > INT32_MAX) { delete h; return VX_EINVAL; }
+                        if (off + c > INT32_MAX) return VX_EINVAL;
                         h->surf_cells.push_back((int)(off + c));
                         h->surf_obj.push_back(i);
                         h->surf_ijk.push_back(pack_ijk(x, y, z));
@@ -478,7 +480,7 @@ int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *pal
         off += nc;
     }
     h->total = off;
-    if (!fused_state_fits(h->total, h->tsize)) { delete h; return VX_EINVAL; }
+    if (!fused_state_fits(h->total, h->tsize)) return VX_EINVAL;
     if (p.self_collision_on) {
         // one world: the smallest of the objects' stable timesteps for all,
         // and the largest contact size the global signal can produce
@@ -498,17 +500,21 @@ int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *pal
         h->table_size = ts;
     }
     layout(h);
-    *out = h;
+    *out = owner.release();
     return VX_OK;
+    VX_CATCH(nullptr)
 }
 
 int vx_batch_workspace_bytes(vx_batch h, uint64_t *bytes) {
+    VX_TRY
     if (!h || !bytes) return VX_EINVAL;
     *bytes = h->L.total;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_batch_bind_workspace(vx_batch h, void *device_ptr, uint64_t bytes) {
+    VX_TRY
     if (!h) return VX_EINVAL;
     if (h->bound) return bfail(h, VX_ESTATE, "workspace already bound");
     if (!device_ptr || bytes < h->L.total) return bfail(h, VX_EINVAL, "workspace too small");
@@ -518,46 +524,58 @@ int vx_batch_bind_workspace(vx_batch h, void *device_ptr, uint64_t bytes) {
     const int r = h->precision == 64 ? upload_all<double>(h) : upload_all<float>(h);
     if (r != VX_OK) h->bound = false;
     return r;
+    VX_CATCH(h)
 }
 
 int vx_batch_step(vx_batch h, int64_t n) {
+    VX_TRY
     if (!h || n < 0) return VX_EINVAL;
     if (!h->bound) return bfail(h, VX_ESTATE, "vx_batch_step before vx_batch_bind_workspace");
     if (n == 0) return VX_OK;
     return h->precision == 64 ? run<double>(h, n) : run<float>(h, n);
+    VX_CATCH(h)
 }
 
 int vx_batch_read_state(vx_batch h, int32_t obj, double *u, double *q, double *vel, double *omega) {
+    VX_TRY
     if (!h || obj < 0 || obj >= (int)h->objs.size()) return VX_EINVAL;
     if (!h->bound) return bfail(h, VX_ESTATE, "read before bind");
     return h->precision == 64 ? read_obj<double>(h, obj, u, q, vel, omega) : read_obj<float>(h, obj, u, q, vel, omega);
+    VX_CATCH(h)
 }
 
 int vx_batch_write_state(vx_batch h, int32_t obj, const double *u, const double *q, const double *vel,
                          const double *omega) {
+    VX_TRY
     if (!h || obj < 0 || obj >= (int)h->objs.size()) return VX_EINVAL;
     if (!h->bound) return bfail(h, VX_ESTATE, "write before bind");
     return h->precision == 64 ? write_obj<double>(h, obj, u, q, vel, omega)
                               : write_obj<float>(h, obj, u, q, vel, omega);
+    VX_CATCH(h)
 }
 
 int vx_batch_get_dt(vx_batch h, int32_t obj, double *dt) {
+    VX_TRY
     if (!h || !dt || obj < 0 || obj >= (int)h->objs.size()) return VX_EINVAL;
     *dt = h->objs[obj].dt;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_batch_counters(vx_batch h, int64_t out[4]) {
+    VX_TRY
     if (!h || !out) return VX_EINVAL;
     out[0] = h->step;
     out[1] = (int64_t)h->objs.size();
     out[2] = h->total;
     out[3] = h->nvox;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_batch_candidates(vx_batch h, int32_t *obj_a, int32_t *cell_a, int32_t *obj_b, int32_t *cell_b,
                         int32_t max_pairs, int32_t *n_pairs) {
+    VX_TRY
     if (!h || !n_pairs || max_pairs < 0) return VX_EINVAL;
     *n_pairs = 0;
     if (!h->bound || !h->contact) return VX_OK;
@@ -582,9 +600,11 @@ int vx_batch_candidates(vx_batch h, int32_t *obj_a, int32_t *cell_a, int32_t *ob
         }
     *n_pairs = k;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_batch_contact_counters(vx_batch h, int64_t out[3]) {
+    VX_TRY
     if (!h || !out) return VX_EINVAL;
     out[0] = out[1] = 0;
     out[2] = h->contact ? (int64_t)h->surf_cells.size() : 0;
@@ -595,16 +615,20 @@ int vx_batch_contact_counters(vx_batch h, int64_t out[3]) {
     out[0] = (int64_t)sc.rebuilds;
     out[1] = (int64_t)sc.pair_count;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_batch_set_launch(vx_batch h, int32_t n_workgroups, int32_t max_steps_per_launch) {
+    VX_TRY
     if (!h || n_workgroups < 0 || max_steps_per_launch < 0) return VX_EINVAL;
     h->n_wg = std::min<int>(n_workgroups, (int)h->objs.size());
     if (max_steps_per_launch > 0) h->max_steps_per_launch = max_steps_per_launch;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_batch_autotune(vx_batch h, int32_t steps, int32_t *n_workgroups) {
+    VX_TRY
     if (!h || steps <= 0) return VX_EINVAL;
     if (!h->bound) return bfail(h, VX_ESTATE, "autotune before bind");
     // time candidate workgroup counts on the real objects; the state, the
@@ -674,11 +698,14 @@ int vx_batch_autotune(vx_batch h, int32_t steps, int32_t *n_workgroups) {
     if (r != VX_OK) return r;
     if (n_workgroups) *n_workgroups = best_wg;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_batch_destroy(vx_batch h) {
+    VX_TRY
     delete h;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 const char *vx_batch_last_error(vx_batch h) { return h ? h->err.c_str() : "null handle"; }

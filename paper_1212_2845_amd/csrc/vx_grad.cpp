@@ -313,14 +313,17 @@ int checkpoint(vx_sim *h, int j) {
 extern "C" {
 
 int vx_grad_workspace_bytes(vx_handle h, int64_t max_steps, int32_t K, uint64_t *bytes) {
+    VX_TRY
     if (!h || !bytes || max_steps < 1 || K < 1) return VX_EINVAL;
     GradLayout G;
     grad_layout(h, max_steps, std::min<int64_t>(K, max_steps), G);
     *bytes = G.total;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_grad_bind(vx_handle h, void *device_ptr, uint64_t bytes, int64_t max_steps, int32_t K) {
+    VX_TRY
     if (!h || max_steps < 1 || K < 1) return VX_EINVAL;
     if (h->p.self_collision_on && std::min<int64_t>(K, max_steps) != 1)
         return fail(h, VX_ESTATE, "differentiable rollouts with self-collision need the full tape (K = 1)");
@@ -345,11 +348,13 @@ int vx_grad_bind(vx_handle h, void *device_ptr, uint64_t bytes, int64_t max_step
         }
     }
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_set_stiffness(vx_handle h, const double *E);
 
 int vx_grad_forward(vx_handle h, int64_t n) {
+    VX_TRY
     if (!h || n < 1) return VX_EINVAL;
     if (!h->gws) return fail(h, VX_ESTATE, "vx_grad_forward before vx_grad_bind");
     if (n > h->GL.max_steps) return fail(h, VX_EINVAL, "more steps than the gradient workspace was sized for");
@@ -377,11 +382,13 @@ int vx_grad_forward(vx_handle h, int64_t n) {
     h->tape_n = n;
     h->tape_step0 = step0;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_grad_backward(vx_handle h, const double *dL_du, const double *dL_dq, const double *dL_dv, const double *dL_dw,
                      double *g_E, double *g_rho, double *g_phase, double *g_amp, double *g_u0, double *g_q0,
                      double *g_v0, double *g_w0) {
+    VX_TRY
     if (!h) return VX_EINVAL;
     if (!h->tape_valid || h->step != h->tape_step0 + h->tape_n)
         return fail(h, VX_ESTATE, "no recorded rollout ends at the current state (vx_grad_forward first)");
@@ -390,9 +397,11 @@ int vx_grad_backward(vx_handle h, const double *dL_du, const double *dL_dq, cons
                                          g_w0)
                : grad_backward_t<float>(h, dL_du, dL_dq, dL_dv, dL_dw, g_E, g_rho, g_phase, g_amp, g_u0, g_q0, g_v0,
                                         g_w0);
+    VX_CATCH(h)
 }
 
 int vx_grad_channels(vx_handle h, double *g_phase, double *g_amp) {
+    VX_TRY
     if (!h) return VX_EINVAL;
     if (!h->chan_grad_valid || h->chan_gphase.size() != h->chans.size())
         return fail(h, VX_ESTATE, "vx_grad_channels before vx_grad_backward with the current channels");
@@ -401,6 +410,7 @@ int vx_grad_channels(vx_handle h, double *g_phase, double *g_amp) {
         if (g_amp) g_amp[k] = h->chan_gamp[k];
     }
     return VX_OK;
+    VX_CATCH(h)
 }
 
 }  // extern "C"

@@ -5,12 +5,40 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
+#include <new>
 #include <vector>
 
 #include "../../include/voxsim.h"
 #include "vx_types.hpp"
 
 namespace vx {
+
+// Error code and message of an exception that reached a C entry point; the
+// message is set only if that itself does not throw.
+template <typename H>
+int fail_nothrow(H *h, int code, const char *msg) noexcept {
+    if (h) {
+        try {
+            h->err = msg;
+        } catch (...) {
+        }
+    }
+    return code;
+}
+inline int fail_nothrow(std::nullptr_t, int code, const char *) noexcept { return code; }
+
+// Every C entry point runs its body between VX_TRY and VX_CATCH(handle), so
+// that no C++ exception (host memory exhausted, say) crosses the interface.
+#define VX_TRY try {
+#define VX_CATCH(h)                                                                  \
+    }                                                                                \
+    catch (const std::bad_alloc &) {                                                 \
+        return vx::fail_nothrow(h, VX_ENOMEM, "host memory exhausted");              \
+    }                                                                                \
+    catch (...) {                                                                    \
+        return vx::fail_nothrow(h, VX_EDEVICE, "unexpected C++ exception");          \
+    }
 
 // Rest indices (x, y, z) of a voxel within its object packed as the
 // collision kernels read them: 21 bits per axis, each offset by 2^20.

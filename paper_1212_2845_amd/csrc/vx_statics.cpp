@@ -88,23 +88,28 @@ int static_solve(vx_sim *h, char *w, const double *F, double rel_tol, int32_t ma
 extern "C" {
 
 int vx_static_workspace_bytes(vx_handle h, uint64_t *bytes) {
+    VX_TRY
     if (!h || !bytes) return VX_EINVAL;
     *bytes = static_layout(h).total;
     return VX_OK;
+    VX_CATCH(h)
 }
 
 int vx_static_solve(vx_handle h, void *work, uint64_t work_bytes, const double *F, double rel_tol,
                     int32_t max_iter, double *u, double *theta, int32_t *iters, double *rel_residual) {
+    VX_TRY
     if (!h || !F || !(rel_tol > 0.0) || max_iter < 1) return VX_EINVAL;
     if (!h->bound) return fail(h, VX_ESTATE, "vx_static_solve before vx_bind_workspace");
     const StaticLayout L = static_layout(h);
     if (!work || work_bytes < L.total) return fail(h, VX_EINVAL, "static workspace too small");
     if (((uintptr_t)work) % kAlign) return fail(h, VX_EINVAL, "static workspace not 256-byte aligned");
     return static_solve(h, (char *)work, F, rel_tol, max_iter, u, theta, iters, rel_residual);
+    VX_CATCH(h)
 }
 
 int vx_static_solve_noalloc(vx_handle h, const double *F, double rel_tol, int32_t max_iter, double *u,
                             double *theta, int32_t *iters, double *rel_residual) {
+    VX_TRY
     if (!h || !F || !(rel_tol > 0.0) || max_iter < 1) return VX_EINVAL;
     if (!h->bound) return fail(h, VX_ESTATE, "vx_static_solve_noalloc before vx_bind_workspace");
     const StaticLayout L = static_layout(h);
@@ -122,6 +127,7 @@ int vx_static_solve_noalloc(vx_handle h, const double *F, double rel_tol, int32_
     void *w = nullptr;
     HIP_OK(h, scratch_ptr(dev, &w));
     return static_solve(h, (char *)w, F, rel_tol, max_iter, u, theta, iters, rel_residual);
+    VX_CATCH(h)
 }
 
 }  // extern "C"
