@@ -20,18 +20,36 @@ __global__ void __launch_bounds__(256) k_adj_update(StepArgs<T> a, AdjArgs<T> g)
     const long long n = (long long)a.nx * a.ny * a.nz;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
-    const uint8_t m = a.mat[c];
-    if (m == 0) return;
     const long long st = a.stride;
-    const MatConst<T> mc = mat_at(a, c, m);
+    const unsigned cu = (unsigned)c;
+    // every word the cell contributes is loaded before any is used (an
+    // empty cell's words exist and are ignored), so that the loads are in
+    // flight together instead of waiting on the material byte, then on the
+    // flags, then on the signal
+    const uint8_t m = a.mat[c];
     const uint8_t fl = a.flags[c];
-    const T eps = voxel_strain(a, (unsigned)c, fl, mc.cte);
-    const VoxRaw<T> r = load_raw(a.s_in, st, (unsigned)c);
-    const VoxRaw<T> lam = load_raw(g.lam_in, st, (unsigned)c);
+    const VoxRaw<T> r = load_raw(a.s_in, st, cu);
+    const VoxRaw<T> lam = load_raw(g.lam_in, st, cu);
     const T *fm = g.fm;
-    const UpdEnv<T> e = upd_env(a, (unsigned)c, fl);
-    const UpdAdj<T> ad = update_vjp(e, fl, mc, eps, r, fm[c], fm[st + c], fm[2 * st + c], fm[3 * st + c],
-                                    fm[4 * st + c], fm[5 * st + c], lam);
+    const T f0 = ldc(fm, cu), f1 = ldc(fm + st, cu), f2 = ldc(fm + 2 * st, cu);
+    const T f3 = ldc(fm + 3 * st, cu), f4 = ldc(fm + 4 * st, cu), f5 = ldc(fm + 5 * st, cu);
+    const T amp = ldc(a.act_amp, cu), phase = ldc(a.act_phase, cu);
+    const uint8_t ch = ldc(a.chan, cu);
+    T Ec = T(0), rhoc = T(0);
+    if (a.E_cell) { Ec = ldc(a.E_cell, cu); rhoc = ldc(a.rho_cell, cu); }
+    if (m == 0) return;
+    const MatConst<T> mc = a.E_cell ? mat_with(a.mats[m], Ec, rhoc, a.l, a.zeta_slow, a.zeta_col) : a.mats[m];
+    // the strain as voxel_strain takes it, from the words above
+    T dT = a.dT_global;
+    if (fl & FLAG_CHAN) {
+        dT = chan_pick(a.chan_dT, ch);
+    } else if (fl & FLAG_ACT) {
+        if constexpr (sizeof(T) == 8) dT = amp * dsin<T>(a.wt + phase);
+        else dT = amp * dsin<T>(a.wt_red + phase);
+    }
+    const T eps = mc.cte * dT;
+    const UpdEnv<T> e = upd_env(a, cu, fl);
+    const UpdAdj<T> ad = update_vjp(e, fl, mc, eps, r, f0, f1, f2, f3, f4, f5, lam);
     store_raw(g.lam_out, st, (unsigned)c, ad.r.ux, ad.r.uy, ad.r.uz, ad.r.qw, ad.r.qx, ad.r.qy, ad.r.qz, ad.r.px,
               ad.r.py, ad.r.pz, ad.r.lx, ad.r.ly, ad.r.lz);
     T *gfm = g.gfm;
