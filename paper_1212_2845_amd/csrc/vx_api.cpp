@@ -986,7 +986,7 @@ int vx_destroy(vx_handle h) {
     VX_TRY
     delete h;
     return VX_OK;
-    VX_CATCH(h)
+    VX_CATCH(nullptr)
 }
 
 const char *vx_last_error(vx_handle h) { return h ? h->err.c_str() : "null handle"; }

@@ -705,7 +705,7 @@ int vx_batch_destroy(vx_batch h) {
     VX_TRY
     delete h;
     return VX_OK;
-    VX_CATCH(h)
+    VX_CATCH(nullptr)
 }
 
 const char *vx_batch_last_error(vx_batch h) { return h ? h->err.c_str() : "null handle"; }
