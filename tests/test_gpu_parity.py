@@ -381,13 +381,13 @@ _CROP = {}
 
 
 def _blob_crop():
-    """The 256^3 lattice's recipe cropped to 32^3 so that the oracle runs
-    all 1000 steps (4 materials on Voronoi blobs, the 5 Hz thermal actuation
-    from phase 0, self-collision on; the largest displacement reaches 9% of
-    a voxel), and the oracle's state after them (computed once for both
-    precisions)."""
+    """The 256^3 lattice's recipe at 48^3 (several tiles of every fused
+    shape along x and y) so that the oracle runs all 1000 steps (4
+    materials on Voronoi blobs, the 5 Hz thermal actuation from phase 0,
+    self-collision on), and the oracle's state after them (computed once
+    for both precisions)."""
     if not _CROP:
-        w = workloads.blob_lattice(n=32, seed=3)
+        w = workloads.blob_lattice(n=48, seed=3)
         o = build_oracle(w)
         assert o.step(1000) == 0
         _CROP["w"], _CROP["ref"] = w, o.read_state()
@@ -400,7 +400,7 @@ def test_blob_lattice_crop_1000_steps(precision):
     an autotuned tile: FP64 within 1e-10 of the oracle, FP32 largest
     displacement within 1e-4."""
     w, ref = _blob_crop()
-    announce("blob lattice 32^3 x 1000 p=%d" % precision)
+    announce("blob lattice 48^3 x 1000 p=%d" % precision)
     g = build_gpu(w, precision=precision, kernel=vx.KERNEL_FUSED)
     g.autotune(iters=1)
     g.step(1000)
