@@ -294,6 +294,29 @@ def test_parameter_gradients_without_initial_state():
             assert np.array_equal(out[0][k], out[1][k]), k
 
 
+def test_rebinding_a_larger_gradient_workspace():
+    """A handle whose gradient workspace was bound for a short rollout and
+    then again for a longer one (the host staging taken at the first bind
+    is kept) gives, bitwise, the gradients of a fresh handle bound once;
+    a second reverse run over the same recorded rollout repeats them."""
+    w = workloads.grad_object(seed=73, scenario="free")
+    wu, wv = loss_weights(w, seed=74)
+    announce("gradient workspace bound twice")
+    s = gpu_sim(w, 32)
+    s.grad_bind(10, 5)
+    s.grad_bind(w["steps"], 20)
+    fresh = gpu_sim(w, 32)
+    fresh.grad_bind(w["steps"], 20)
+    out = []
+    for h in (s, fresh):
+        h.grad_forward(w["steps"])
+        out.append(h.grad_backward(dL_du=wu, dL_dv=wv))
+    out.append(s.grad_backward(dL_du=wu, dL_dv=wv))
+    for k in ("E", "rho", "phase", "amp", "u0", "v0"):
+        assert np.array_equal(out[0][k], out[1][k]), k
+        assert np.array_equal(out[0][k], out[2][k]), k
+
+
 def test_tape_forward_equals_plain_forward():
     """The K = 1 forward run (each step written into the next tape slot) ends
     in the state that plain stepping reaches, bitwise, with the step and
