@@ -493,6 +493,23 @@ def test_gradient_through_contact_matches_oracle_fd():
         assert err < 1e-4, (name, err)
 
 
+def test_fp32_gradient_through_contact_close_to_fp64():
+    """The same two colliding blocks in FP32: the contact branch taken (the
+    rebuild count) and the gradients agree with the FP64 run's, relative
+    to the largest entry."""
+    w = workloads.contact_pair(seed=61)
+    wu, wv = loss_weights(w, seed=62)
+    announce("fp32 vs fp64 gradient through contact")
+    g64, L64, c64 = contact_grad(w, wu, wv, 64)
+    g32, L32, c32 = contact_grad(w, wu, wv, 32)
+    assert c32["rebuilds"] == c64["rebuilds"]
+    assert abs(L32 / L64 - 1) < 1e-4, (L32, L64)
+    b = w["block"]
+    errs = {k: norm_err(g32[k][b], g64[k][b]) for k in ("E", "rho", "phase")}
+    print("[grad] contact fp32 vs fp64 %s" % errs, flush=True)
+    assert max(errs.values()) < 1e-4, errs
+
+
 def test_tape_forward_with_contact_equals_plain_forward():
     """The K = 1 forward run with self-collision (lists rebuilt by the
     horizon rule, contact forces each step) ends in the state plain
