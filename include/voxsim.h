@@ -378,10 +378,11 @@ int vx_grad_workspace_bytes(vx_handle h, int64_t max_steps, int32_t K, uint64_t 
 
 /* Bind a caller-owned, 256-byte aligned device buffer of at least
  * vx_grad_workspace_bytes(h, max_steps, K) bytes.  Needs the main
- * workspace bound; with self-collision on, the full tape (K = 1): the
- * reverse run then rebuilds each step's candidate lists from the taped
- * state and applies the contact forces' reverse (gradients through
- * contact; the lists themselves are piecewise constant).  Replaces an
+ * workspace bound.  With self-collision on, the reverse run (and the
+ * segment recompute) rebuild each step's candidate lists from that step's
+ * state and the reverse run applies the contact forces' reverse
+ * (gradients through contact; which pairs touch is held fixed, the map is
+ * piecewise smooth).  Replaces an
  * earlier binding.  It also takes pinned host memory (about 25 words + 32
  * bytes per cell, freed by vx_destroy) through which the reverse run's
  * host copies go; if that allocation fails the reverse run stages in

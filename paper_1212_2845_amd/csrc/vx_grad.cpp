@@ -141,6 +141,20 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
             a.flags_out = i + 1 < len ? fl_ptr(i + 1) : (uint8_t *)(gw + G.seg_flags);
             a.fm_out = (T *)(gw + G.fm + (uint64_t)i * fmb);
             a.track_vmax = 0;
+            if (col) {
+                // contact forces at x_n from candidate lists rebuilt for x_n:
+                // the forward's lists (built by the horizon rule) and these
+                // both hold every pair in contact, in the same order of
+                // partner, so the forces are the forward's; the candidate
+                // bits go to a scratch copy of the step's flags
+                const CollideArgs cl = make_collide(h);
+                uint8_t *scratch = (uint8_t *)(h->ws + h->L.flags[1 - h->cur]);
+                HIP_OK(h, hipMemcpyAsync(scratch, a.flags, (size_t)n, hipMemcpyDeviceToDevice, s));
+                a.flags = scratch;
+                HIP_OK(h, launch_force_rebuild(cl, s));
+                HIP_OK(h, launch_rebuild<T>(a, cl, s));
+                HIP_OK(h, launch_contact<T>(a, cl, (T *)(h->ws + h->L.contact_F), s));
+            }
             if (h->use_split()) {
                 HIP_OK(h, launch_split_step<T>(a, s));
             } else {
@@ -208,6 +222,7 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
     HIP_OK(h, hipMemcpyAsync(&sc, h->ws + h->L.scalars, sizeof(sc), hipMemcpyDeviceToHost, s));
     HIP_OK(h, hipStreamSynchronize(s));
     if (sc.err_flag) return fail(h, VX_EUNSTABLE, "non-finite value in the voxel state");
+    if (sc.overflow) return fail(h, VX_EOVERFLOW, "collision candidate list overflow (raise contact_cap)");
     // channel voxels: their terms summed per channel in cell order, and
     // zero in the per-voxel outputs
     h->chan_gphase.assign(h->chans.size(), 0.0);
@@ -325,8 +340,6 @@ int vx_grad_workspace_bytes(vx_handle h, int64_t max_steps, int32_t K, uint64_t 
 int vx_grad_bind(vx_handle h, void *device_ptr, uint64_t bytes, int64_t max_steps, int32_t K) {
     VX_TRY
     if (!h || max_steps < 1 || K < 1) return VX_EINVAL;
-    if (h->p.self_collision_on && std::min<int64_t>(K, max_steps) != 1)
-        return fail(h, VX_ESTATE, "differentiable rollouts with self-collision need the full tape (K = 1)");
     if (!h->bound) return fail(h, VX_ESTATE, "vx_grad_bind before vx_bind_workspace");
     GradLayout G;
     grad_layout(h, max_steps, (int)std::min<int64_t>(K, max_steps), G);

@@ -456,10 +456,10 @@ def test_design_lattice_gradient_full_size():
             assert err < 1e-5, (i, j, k, err)
 
 
-def contact_grad(w, wu, wv, precision=64):
+def contact_grad(w, wu, wv, precision=64, K=1):
     s = gpu_sim(w, precision)
     s.write_state(**w["state"])
-    s.grad_bind(w["steps"], 1)
+    s.grad_bind(w["steps"], K)
     s.grad_forward(w["steps"])
     g = s.grad_backward(dL_du=wu, dL_dv=wv)
     st = s.read_state()
@@ -508,6 +508,22 @@ def test_fp32_gradient_through_contact_close_to_fp64():
     errs = {k: norm_err(g32[k][b], g64[k][b]) for k in ("E", "rho", "phase")}
     print("[grad] contact fp32 vs fp64 %s" % errs, flush=True)
     assert max(errs.values()) < 1e-4, errs
+
+
+@pytest.mark.parametrize("K", [7, 60])
+def test_checkpointed_gradient_through_contact_equals_tape(K):
+    """With checkpoints every K steps the segment recompute rebuilds each
+    step's candidate lists, which holds every pair in contact as the
+    forward's horizon-rule lists did: the recomputed states, and so the
+    gradients through contact, are bitwise those of the full tape."""
+    w = workloads.contact_pair(seed=61)
+    wu, wv = loss_weights(w, seed=62)
+    announce("gradient through contact with K = %d" % K)
+    g1, L1, c1 = contact_grad(w, wu, wv, 64, K=1)
+    gk, Lk, ck = contact_grad(w, wu, wv, 64, K=K)
+    assert Lk == L1 and ck["rebuilds"] == c1["rebuilds"]
+    for k in ("E", "rho", "phase", "amp", "u0", "v0"):
+        assert np.array_equal(gk[k], g1[k]), k
 
 
 def test_tape_forward_with_contact_equals_plain_forward():
