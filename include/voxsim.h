@@ -416,7 +416,10 @@ int vx_grad_forward(vx_handle h, int64_t n);
  *            channel; see vx_grad_channels);
  *   g_u0, g_q0, g_v0, g_w0  adjoint of the rollout's initial state.
  * The adjoint state is kept in the state's precision; the parameter
- * gradients are accumulated in FP64. */
+ * gradients are accumulated in FP64.  Errors: VX_ESTATE as above,
+ * VX_EUNSTABLE for a non-finite value, VX_EOVERFLOW if a candidate list
+ * rebuilt during the run (self-collision) overflowed contact_cap,
+ * VX_ENOMEM if host staging could not be allocated. */
 int vx_grad_backward(vx_handle h, const double *dL_du, const double *dL_dq, const double *dL_dv,
                      const double *dL_dw, double *g_E, double *g_rho, double *g_phase, double *g_amp,
                      double *g_u0, double *g_q0, double *g_v0, double *g_w0);
