@@ -382,6 +382,73 @@ def time_adjoint(steps=5000, K=100):
                     "design loop's), not those of the initial state"}
 
 
+def time_adjoint_contact(steps=1000, K=100, pairs=(8, 8, 8)):
+    """Differentiable rollout through voxel-voxel contact: the colliding
+    bodies (pairs of free bodies driven into each other, self-collision on,
+    FP32) in parameter mode, a plain forward of `steps` steps against the
+    forward with checkpoints every K steps plus the reverse run (candidate
+    lists built where the forward rebuilt them, the contact forces' reverse
+    applied), and the same with the full tape; loss = mean x
+    displacement."""
+    import numpy as np
+    import torch
+    import paper_1212_2845_amd as vx
+    import workloads
+    stream = torch.cuda.current_stream()
+    w, _ = workloads.colliding_bodies(pairs=pairs, steps=steps)
+    filled = w["grid"].reshape(-1) > 0
+    nvox = int(filled.sum())
+    E = np.array([w["materials"][m]["E"] if m else 0.0 for m in w["grid"].reshape(-1)])
+    wu = np.zeros((w["grid"].size, 3))
+    wu[filled, 0] = 1.0 / nvox
+
+    def make():
+        s = vx.from_workload(w, precision=32, stream=stream.cuda_stream)
+        s.set_stiffness(E)
+        s.bind()
+        s.write_state(**w["state"])
+        return s
+
+    # warm-up of every kernel on a short rollout
+    s = make()
+    s.grad_bind(20, 10)
+    s.grad_forward(20)
+    s.grad_backward(dL_du=wu, initial_state=False)
+    del s
+    s = make()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    rebuilds = s.counters()["rebuilds"]
+    del s
+    out = {"workload": w["name"], "voxels": nvox, "cells": int(w["grid"].size), "steps": steps, "dtype": "f32",
+           "forward_s": t_fwd, "rebuilds": rebuilds}
+    grads = {}
+    for k in (K, 1):
+        s = make()
+        s.grad_bind(steps, k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.grad_forward(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        grads[k] = s.grad_backward(dL_du=wu, initial_state=False)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out["K%d" % k] = {"grad_forward_s": t1 - t0, "grad_backward_s": t2 - t1,
+                          "fwd_adj_over_fwd": (t2 - t0) / t_fwd}
+        del s
+        torch.cuda.empty_cache()
+    out["gradients_equal_K%d_K1" % K] = bool(all(np.array_equal(grads[K][q], grads[1][q])
+                                                 for q in ("E", "rho", "phase", "amp")))
+    out["note"] = ("wall time with host synchronisation; the reverse run (and the segment recompute with K > 1) "
+                   "builds candidate lists where the forward's horizon rule rebuilt them and at each segment's "
+                   "first step")
+    return out
+
+
 def time_collision_schemes(steps=5000, graph=True, w=None):
     """Iteration rates of the self-collision schemes of the paper's Table 3
     (candidates from all voxels or the surface; rebuilt every step or by the
@@ -752,6 +819,11 @@ def main():
     if not args.no_adjoint_leg:
         log("adjoint leg: design lattice, %d steps" % args.adjoint_steps)
         out["adjoint"] = time_adjoint(args.adjoint_steps)
+        log("adjoint leg through contact: colliding bodies, 1000 steps")
+        try:
+            out["adjoint_contact"] = time_adjoint_contact()
+        except Exception as e:   # reported, so that the other legs still print
+            out["adjoint_contact"] = {"error": "%s: %s" % (type(e).__name__, e)}
     if not args.no_paper_shape_leg:
         log("paper-shape leg: cubes 8^3 .. 40^3")
         out["paper_shape"] = time_paper_shape()

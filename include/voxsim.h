@@ -371,16 +371,19 @@ int vx_set_density(vx_handle h, const double *rho);
  * with a checkpoint every K steps: ceil(max_steps/K) checkpoints plus a
  * K-step recompute buffer, adjoint state and per-voxel adjoint terms
  * (about (ceil(max_steps/K) + K) x (13 words + 1 byte) + K x 6 words +
- * 35 words + 4 FP64 words per cell).  K = 1 is the tape: the forward run
+ * 35 words + 4 FP64 words per cell, and max_steps bytes for the forward's
+ * log of candidate-list rebuilds).  K = 1 is the tape: the forward run
  * stores every step's state, flags and 6 bond-sum words (about max_steps x
  * (19 words + 1 byte) per cell) and the reverse run recomputes nothing. */
 int vx_grad_workspace_bytes(vx_handle h, int64_t max_steps, int32_t K, uint64_t *bytes);
 
 /* Bind a caller-owned, 256-byte aligned device buffer of at least
  * vx_grad_workspace_bytes(h, max_steps, K) bytes.  Needs the main
- * workspace bound.  With self-collision on, the reverse run (and the
- * segment recompute) rebuild each step's candidate lists from that step's
- * state and the reverse run applies the contact forces' reverse
+ * workspace bound.  With self-collision on, the forward run logs where the
+ * horizon rule rebuilt the candidate lists, the reverse run (and the
+ * segment recompute) build them from the states of those steps (and of
+ * each segment's first step) and the reverse run applies the contact
+ * forces' reverse
  * (gradients through contact; which pairs touch is held fixed, the map is
  * piecewise smooth).  Replaces an
  * earlier binding.  It also takes pinned host memory (about 25 words + 32

@@ -351,6 +351,7 @@ __global__ void __launch_bounds__(256) k_contact(StepArgs<T> a, CollideArgs c, T
 
 template <typename T>
 __global__ void k_motion(StepArgs<T> a, CollideArgs c) {
+    if (c.rlog) *c.rlog = c.scalars->rebuild_flag ? 1 : 0;
     motion_update(c.scalars, (double)a.dt);
 }
 

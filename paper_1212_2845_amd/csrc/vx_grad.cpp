@@ -42,6 +42,7 @@ void grad_layout(const vx_sim *h, int64_t max_steps, int K, GradLayout &G) {
     G.grho = take(n * 8);
     G.gphase = take(n * 8);
     G.gamp = take(n * 8);
+    G.rlog = take((uint64_t)max_steps);
     G.total = off;
 }
 
@@ -120,6 +121,42 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
     const int64_t N = h->tape_n;
     const int K = G.K;
     const int nseg = (int)((N + K - 1) / K);
+    // With self-collision, candidate lists are built where the forward's
+    // were: a list built at the state of step r holds every pair that
+    // touches before the forward's next rebuild (the horizon rule), so one
+    // list serves a piece of steps from r, or from the first step of a
+    // segment (a later start within the piece, valid as long), to the next
+    // rebuild; the forward logged at which steps it rebuilt.  Lists built
+    // from the same state are the same, so the contact forces, and with
+    // them the recomputed states, are the forward's.
+    std::vector<unsigned char> rlog;
+    if (col) {
+        rlog.assign((size_t)N, 0);
+        HIP_OK(h, hipMemcpyAsync(rlog.data(), gw + G.rlog, (size_t)N, hipMemcpyDeviceToHost, s));
+        HIP_OK(h, hipStreamSynchronize(s));
+    }
+    // first step of the piece of step k (steps counted from the rollout's
+    // start) that begins at or after step lo
+    auto piece_start = [&](int64_t k, int64_t lo) {
+        int64_t r = k;
+        while (r > lo && !rlog[(size_t)r]) --r;
+        return r;
+    };
+    int64_t built = -1;   // step whose state the current lists were built from
+    // build the lists from state st with flags fl (into a scratch copy,
+    // which receives the candidate bits and is returned)
+    auto build_lists = [&](const StepArgs<T> &a, const T *st, const uint8_t *fl, uint8_t **scratch_out) -> int {
+        const CollideArgs cl = make_collide(h);
+        StepArgs<T> ab = a;
+        ab.s_in = st;
+        uint8_t *scratch = (uint8_t *)(h->ws + h->L.flags[1 - h->cur]);
+        HIP_OK(h, hipMemcpyAsync(scratch, fl, (size_t)n, hipMemcpyDeviceToDevice, s));
+        ab.flags = scratch;
+        HIP_OK(h, launch_force_rebuild(cl, s));
+        HIP_OK(h, launch_rebuild<T>(ab, cl, s));
+        if (scratch_out) *scratch_out = scratch;
+        return VX_OK;
+    };
     for (int j = nseg - 1; j >= 0; --j) {
         const long long s0 = h->tape_step0 + (long long)j * K;
         const int len = (int)std::min<int64_t>(K, N - (int64_t)j * K);
@@ -142,18 +179,18 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
             a.fm_out = (T *)(gw + G.fm + (uint64_t)i * fmb);
             a.track_vmax = 0;
             if (col) {
-                // contact forces at x_n from candidate lists rebuilt for x_n:
-                // the forward's lists (built by the horizon rule) and these
-                // both hold every pair in contact, in the same order of
-                // partner, so the forces are the forward's; the candidate
-                // bits go to a scratch copy of the step's flags
-                const CollideArgs cl = make_collide(h);
-                uint8_t *scratch = (uint8_t *)(h->ws + h->L.flags[1 - h->cur]);
-                HIP_OK(h, hipMemcpyAsync(scratch, a.flags, (size_t)n, hipMemcpyDeviceToDevice, s));
-                a.flags = scratch;
-                HIP_OK(h, launch_force_rebuild(cl, s));
-                HIP_OK(h, launch_rebuild<T>(a, cl, s));
-                HIP_OK(h, launch_contact<T>(a, cl, (T *)(h->ws + h->L.contact_F), s));
+                // at a piece's first step the lists are built from this
+                // state, and the step reads the fresh candidate bits; later
+                // steps of the piece carry them in their flags
+                const int64_t k = s0 - h->tape_step0 + i;
+                const int64_t start = piece_start(k, s0 - h->tape_step0);
+                if (start == k) {
+                    uint8_t *scratch = nullptr;
+                    if (int r = build_lists(a, a.s_in, a.flags, &scratch)) return r;
+                    a.flags = scratch;
+                    built = k;
+                }
+                HIP_OK(h, launch_contact<T>(a, make_collide(h), (T *)(h->ws + h->L.contact_F), s));
             }
             if (h->use_split()) {
                 HIP_OK(h, launch_split_step<T>(a, s));
@@ -170,20 +207,25 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
             a.flags_out = nullptr;
             CollideArgs cl{};
             if (col) {
-                // contact forces at x_n from candidate lists rebuilt for
-                // x_n: a list valid at x_n gives the forward's forces (only
-                // pairs in contact act), and the lists' candidate bits go
-                // to a scratch copy of the step's flags; zeroed forces for
-                // voxels whose fresh list is empty
+                // the lists of the step's piece (built from the piece's
+                // first state, unless they already are), then the contact
+                // forces at x_n; zeroed forces for voxels whose list is
+                // empty, since the update's reverse reads the step's own
+                // candidate bits
                 cl = make_collide(h);
-                StepArgs<T> ac = a;
-                uint8_t *scratch = (uint8_t *)(h->ws + h->L.flags[1 - h->cur]);
-                HIP_OK(h, hipMemcpyAsync(scratch, a.flags, (size_t)n, hipMemcpyDeviceToDevice, s));
-                ac.flags = scratch;
+                const int64_t k = s0 - h->tape_step0 + i;
+                const int64_t lo = K > 1 ? s0 - h->tape_step0 : 0;
+                const int64_t start = piece_start(k, lo);
+                if (start != built) {
+                    const T *st = K > 1 ? st_ptr((int)(start - lo))
+                                        : (const T *)(gw + G.ck_state + (uint64_t)start * sb);
+                    const uint8_t *fl = K > 1 ? fl_ptr((int)(start - lo))
+                                              : (const uint8_t *)(gw + G.ck_flags + (uint64_t)start * fb);
+                    if (int r = build_lists(a, st, fl, nullptr)) return r;
+                    built = start;
+                }
                 HIP_OK(h, hipMemsetAsync(h->ws + h->L.contact_F, 0, (size_t)3 * n * sizeof(T), s));
-                HIP_OK(h, launch_force_rebuild(cl, s));
-                HIP_OK(h, launch_rebuild<T>(ac, cl, s));
-                HIP_OK(h, launch_contact<T>(ac, cl, (T *)(h->ws + h->L.contact_F), s));
+                HIP_OK(h, launch_contact<T>(a, cl, (T *)(h->ws + h->L.contact_F), s));
             }
             AdjArgs<T> g;
             g.fm = (const T *)(gw + G.fm + (uint64_t)(K > 1 ? i : j) * fmb);
@@ -381,16 +423,19 @@ int vx_grad_forward(vx_handle h, int64_t n) {
     }
     const long long step0 = h->step;
     const int K = h->GL.K;
-    if (K == 1) {
-        const int r = h->precision == 64 ? tape_forward<double>(h, n) : tape_forward<float>(h, n);
-        if (r) return r;
+    // the motion bookkeeping of every step logs whether the step rebuilt
+    // the candidate lists, which the reverse run follows
+    h->rlog = (unsigned char *)(h->gws + h->GL.rlog);
+    h->rlog_step0 = step0;
+    h->rlog_n = n;
+    int r = 0;
+    if (K == 1) r = h->precision == 64 ? tape_forward<double>(h, n) : tape_forward<float>(h, n);
+    for (int64_t done = 0, j = 0; !r && K > 1 && done < n; done += K, ++j) {
+        r = h->precision == 64 ? checkpoint<double>(h, (int)j) : checkpoint<float>(h, (int)j);
+        if (!r) r = vx_step(h, std::min<int64_t>(K, n - done));
     }
-    for (int64_t done = 0, j = 0; K > 1 && done < n; done += K, ++j) {
-        int r = h->precision == 64 ? checkpoint<double>(h, (int)j) : checkpoint<float>(h, (int)j);
-        if (r) return r;
-        r = vx_step(h, std::min<int64_t>(K, n - done));
-        if (r) return r;
-    }
+    h->rlog = nullptr;
+    if (r) return r;
     h->tape_valid = true;
     h->tape_n = n;
     h->tape_step0 = step0;

@@ -168,6 +168,8 @@ struct CollideArgs {
     double horizon;              // 2 l
     unsigned long long *rebuild_counter;
     Scalars *scalars;            // the block the fields above point into (motion bookkeeping)
+    unsigned char *rlog;         // if set, the motion bookkeeping records there whether the step
+                                 // rebuilt the lists at its start (1) or not (0)
 };
 
 // Scan blocks of a bucket table of n entries.

@@ -42,6 +42,7 @@ struct GradLayout {
     uint64_t gfm;                // adjoint of the bond sums, 6 words x ncell
     uint64_t gloc;               // per-voxel adjoints of strain, modulus and mass from the update, 3 x ncell
     uint64_t gE, grho, gphase, gamp;   // FP64 accumulators, ncell each
+    uint64_t rlog;               // max_steps bytes: 1 where the forward rebuilt the candidate lists
     uint64_t total;
 };
 
@@ -114,6 +115,11 @@ struct vx_sim {
     bool tape_valid = false;              // a recorded rollout ends at the current state
     int64_t tape_n = 0;
     long long tape_step0 = 0;
+    // while a recorded forward runs: its rebuild log (device), first step
+    // and length
+    unsigned char *rlog = nullptr;
+    long long rlog_step0 = 0;
+    int64_t rlog_n = 0;
     // pinned host memory for the reverse run's host copies (taken at
     // vx_grad_bind when it can be; ordinary host memory otherwise)
     void *pinned = nullptr;
@@ -269,6 +275,8 @@ inline vx::CollideArgs make_collide(vx_sim *h) {
     c.horizon = 2.0 * h->p.voxel_size;
     c.rebuild_counter = &sc->rebuilds;
     c.scalars = sc;
+    const long long k = h->step - h->rlog_step0;
+    c.rlog = h->rlog && k >= 0 && k < h->rlog_n ? h->rlog + k : nullptr;
     return c;
 }
 
