@@ -724,6 +724,8 @@ def main():
                     help="no graph replays: the lattice legs' K steps as one vx_step call, and the collision "
                          "leg's eager rates only (for profiler counter runs, which do not follow graph replays)")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
+    ap.add_argument("--adjoint-contact-steps", type=int, default=1000,
+                    help="steps of the rollout through contact in the adjoint leg (0: skip it)")
     ap.add_argument("--batch-objects", type=int, default=4096)
     ap.add_argument("--one-by-one-sample", type=int, default=256,
                     help="objects in the one-at-a-time comparison of the batched leg (0 skips it, e.g. "
@@ -819,11 +821,12 @@ def main():
     if not args.no_adjoint_leg:
         log("adjoint leg: design lattice, %d steps" % args.adjoint_steps)
         out["adjoint"] = time_adjoint(args.adjoint_steps)
-        log("adjoint leg through contact: colliding bodies, 1000 steps")
-        try:
-            out["adjoint_contact"] = time_adjoint_contact()
-        except Exception as e:   # reported, so that the other legs still print
-            out["adjoint_contact"] = {"error": "%s: %s" % (type(e).__name__, e)}
+        if args.adjoint_contact_steps > 0:
+            log("adjoint leg through contact: colliding bodies, %d steps" % args.adjoint_contact_steps)
+            try:
+                out["adjoint_contact"] = time_adjoint_contact(args.adjoint_contact_steps)
+            except Exception as e:   # reported, so that the other legs still print
+                out["adjoint_contact"] = {"error": "%s: %s" % (type(e).__name__, e)}
     if not args.no_paper_shape_leg:
         log("paper-shape leg: cubes 8^3 .. 40^3")
         out["paper_shape"] = time_paper_shape()
