@@ -456,8 +456,10 @@ def test_design_lattice_gradient_full_size():
             assert err < 1e-5, (i, j, k, err)
 
 
-def contact_grad(w, wu, wv, precision=64, K=1):
+def contact_grad(w, wu, wv, precision=64, K=1, every_step=False):
     s = gpu_sim(w, precision)
+    if every_step:
+        s.set_collision_mode(all_voxels=0, every_step=1)
     s.write_state(**w["state"])
     s.grad_bind(w["steps"], K)
     s.grad_forward(w["steps"])
@@ -510,17 +512,18 @@ def test_fp32_gradient_through_contact_close_to_fp64():
     assert max(errs.values()) < 1e-4, errs
 
 
-@pytest.mark.parametrize("K", [7, 60])
-def test_checkpointed_gradient_through_contact_equals_tape(K):
-    """With checkpoints every K steps the segment recompute rebuilds each
-    step's candidate lists, which holds every pair in contact as the
-    forward's horizon-rule lists did: the recomputed states, and so the
+@pytest.mark.parametrize("K,every_step", [(7, False), (60, False), (7, True)])
+def test_checkpointed_gradient_through_contact_equals_tape(K, every_step):
+    """With checkpoints every K steps the segment recompute builds candidate
+    lists where the forward rebuilt them (by the horizon rule, or every
+    step) and at each segment's first step; such lists hold every pair in
+    contact, as the forward's did: the recomputed states, and so the
     gradients through contact, are bitwise those of the full tape."""
     w = workloads.contact_pair(seed=61)
     wu, wv = loss_weights(w, seed=62)
-    announce("gradient through contact with K = %d" % K)
-    g1, L1, c1 = contact_grad(w, wu, wv, 64, K=1)
-    gk, Lk, ck = contact_grad(w, wu, wv, 64, K=K)
+    announce("gradient through contact with K = %d, every step %d" % (K, every_step))
+    g1, L1, c1 = contact_grad(w, wu, wv, 64, K=1, every_step=every_step)
+    gk, Lk, ck = contact_grad(w, wu, wv, 64, K=K, every_step=every_step)
     assert Lk == L1 and ck["rebuilds"] == c1["rebuilds"]
     for k in ("E", "rho", "phase", "amp", "u0", "v0"):
         assert np.array_equal(gk[k], g1[k]), k
