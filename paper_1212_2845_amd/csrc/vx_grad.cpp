@@ -129,19 +129,18 @@ int grad_backward_t(vx_sim *h, const double *dL_du, const double *dL_dq, const d
     // rebuild; the forward logged at which steps it rebuilt.  Lists built
     // from the same state are the same, so the contact forces, and with
     // them the recomputed states, are the forward's.
-    std::vector<unsigned char> rlog;
+    // last[k]: the forward's last rebuild at or before step k (steps
+    // counted from the rollout's start), or 0
+    std::vector<int64_t> last;
     if (col) {
-        rlog.assign((size_t)N, 0);
+        std::vector<unsigned char> rlog((size_t)N, 0);
         HIP_OK(h, hipMemcpyAsync(rlog.data(), gw + G.rlog, (size_t)N, hipMemcpyDeviceToHost, s));
         HIP_OK(h, hipStreamSynchronize(s));
+        last.resize((size_t)N);
+        for (int64_t k = 0; k < N; ++k) last[(size_t)k] = rlog[(size_t)k] ? k : (k > 0 ? last[(size_t)k - 1] : 0);
     }
-    // first step of the piece of step k (steps counted from the rollout's
-    // start) that begins at or after step lo
-    auto piece_start = [&](int64_t k, int64_t lo) {
-        int64_t r = k;
-        while (r > lo && !rlog[(size_t)r]) --r;
-        return r;
-    };
+    // first step of the piece of step k that begins at or after step lo
+    auto piece_start = [&](int64_t k, int64_t lo) { return std::max(last[(size_t)k], lo); };
     int64_t built = -1;   // step whose state the current lists were built from
     // build the lists from state st with flags fl (into a scratch copy,
     // which receives the candidate bits and is returned)
