@@ -22,11 +22,12 @@ __global__ void __launch_bounds__(256) k_adj_update(StepArgs<T> a, AdjArgs<T> g)
     if (c >= n) return;
     const long long st = a.stride;
     const unsigned cu = (unsigned)c;
-    // every word the cell contributes is loaded before any is used (an
-    // empty cell's words exist and are ignored), so that the loads are in
-    // flight together instead of waiting on the material byte, then on the
-    // flags, then on the signal
+    // an empty cell stops at its material byte (on a sparse lattice whole
+    // waves do); every other word a filled cell contributes is loaded
+    // before any is used, so that the loads are in flight together instead
+    // of waiting on the flags, then on the parameters, then on the signal
     const uint8_t m = a.mat[c];
+    if (m == 0) return;
     const uint8_t fl = a.flags[c];
     const VoxRaw<T> r = load_raw(a.s_in, st, cu);
     const VoxRaw<T> lam = load_raw(g.lam_in, st, cu);
@@ -37,7 +38,6 @@ __global__ void __launch_bounds__(256) k_adj_update(StepArgs<T> a, AdjArgs<T> g)
     const uint8_t ch = ldc(a.chan, cu);
     T Ec = T(0), rhoc = T(0);
     if (a.E_cell) { Ec = ldc(a.E_cell, cu); rhoc = ldc(a.rho_cell, cu); }
-    if (m == 0) return;
     const MatConst<T> mc = a.E_cell ? mat_with(a.mats[m], Ec, rhoc, a.l, a.zeta_slow, a.zeta_col) : a.mats[m];
     // the strain as voxel_strain takes it, from the words above
     T dT = a.dT_global;
