@@ -495,6 +495,81 @@ def test_gradient_through_contact_matches_oracle_fd():
         assert err < 1e-4, (name, err)
 
 
+def _with_stiff_anchor(w, E=2e7):
+    """Copy of workload w with a bonded pair of voxels of a much stiffer
+    material added where the lattice is empty for 4 cells around, so that
+    the stable timestep (set by the stiffest bond) does not move when the
+    other materials' moduli or densities are perturbed."""
+    nz, ny, nx = w["grid"].shape
+    grid = w["grid"].copy()
+    occ = grid > 0
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx - 1):
+                zs, ys, xs = slice(max(z - 4, 0), z + 5), slice(max(y - 4, 0), y + 5), slice(max(x - 4, 0), x + 6)
+                if not occ[zs, ys, xs].any():
+                    grid[z, y, x] = grid[z, y, x + 1] = len(w["materials"])
+                    mats = list(w["materials"]) + [workloads._mat(E)]
+                    return dict(w, grid=grid, materials=mats)
+    raise AssertionError("no room for the anchor")
+
+
+def test_gradient_through_many_contacts_matches_material_fd():
+    """Eight pairs of free bodies driven into each other (two materials,
+    many contacts and several candidate-list rebuilds, FP64, full tape and
+    checkpoints every 25 steps; a stiff anchor pair fixes the timestep, and
+    the materials' densities differ): the
+    loss equals the oracle's, the two reverse runs agree bitwise, and the
+    per-voxel gradients summed over each body material equal central
+    differences of the oracle with respect to that material's modulus and
+    density (a perturbed palette entry changes every voxel of the material,
+    in the bonds and in the contact law)."""
+    w, _ = workloads.colliding_bodies(pairs=(2, 2, 2), steps=700)
+    # the two body materials get different densities: with equal ones the
+    # lighter-mass rule of the bond and contact damping would sit exactly
+    # at its kink for every bond and pair across materials, where a
+    # central difference averages the two sides
+    w = dict(w, materials=[dict(m) for m in w["materials"]])
+    w["materials"][2]["rho"] = 1300.0
+    w = _with_stiff_anchor(w)
+    g = w["grid"].reshape(-1)
+    filled = g > 0
+    rng = np.random.Generator(np.random.PCG64(81))
+    wu = np.zeros((g.size, 3)); wv = np.zeros((g.size, 3))
+    wu[filled] = rng.normal(0.0, 1.0, size=(filled.sum(), 3))
+    wv[filled] = rng.normal(0.0, 1e-3, size=(filled.sum(), 3))
+    announce("gradient through many contacts")
+    out = []
+    for K in (1, 25):
+        gr, L, cnt = contact_grad(w, wu, wv, 64, K=K)
+        out.append((gr, L, cnt))
+    (g1, L1, c1), (g25, L25, c25) = out
+    assert c1["rebuilds"] >= 2 and c1["rebuilds"] == c25["rebuilds"]
+    assert abs(L1 / oracle_loss(w, wu, wv) - 1) < 1e-10
+    for k in ("E", "rho", "phase", "amp"):
+        assert np.array_equal(g1[k], g25[k]), k
+
+    def fd(key, m, h):
+        vals = []
+        for sgn in (1.0, -1.0):
+            mats = [dict(x) for x in w["materials"]]
+            mats[m][key] *= 1.0 + sgn * h
+            vals.append(oracle_loss(dict(w, materials=mats), wu, wv))
+        return (vals[0] - vals[1]) / (2.0 * h * w["materials"][m][key])
+
+    usable = 0
+    for key in ("E", "rho"):
+        for m in (1, 2):
+            an = g1[key][g == m].sum()
+            a, c = fd(key, m, 1e-4), fd(key, m, 1e-5)
+            print("[grad] many contacts d/d%s[%d]: analytic %.6e fd %.6e / %.6e" % (key, m, an, a, c), flush=True)
+            if abs(a - c) > 1e-4 * abs(a):
+                continue           # a contact event inside the difference interval
+            usable += 1
+            assert abs(an - a) < 1e-4 * abs(a), (key, m, an, a)
+    assert usable >= 3, usable
+
+
 def test_fp32_gradient_through_contact_close_to_fp64():
     """The same two colliding blocks in FP32: the contact branch taken (the
     rebuild count) and the gradients agree with the FP64 run's, relative
