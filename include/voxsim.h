@@ -411,9 +411,10 @@ int vx_grad_forward(vx_handle h, int64_t n);
  *            the rollout's initial velocities and angular velocities held
  *            fixed (its initial momenta scale with the mass) and the loss a
  *            function of the final velocities (v = P / m); where two
- *            bonded voxels have equal mass, the bond
- *            damping's dependence on the lighter mass is assigned to the
- *            voxel the forward takes it from (voxel 2 of the bond);
+ *            bonded or touching voxels have equal mass, the damping's
+ *            dependence on the lighter mass (which has no derivative
+ *            there) is split evenly between them, the mean of the two
+ *            one-sided derivatives;
  *   g_phase  dL/dphase, g_amp dL/damp of vx_set_actuation's per-voxel
  *            signal (zero when the voxel follows the global signal or a
  *            channel; see vx_grad_channels);

@@ -147,10 +147,13 @@ __device__ __forceinline__ void bond_ends(const AdjCell<T> &A, const AdjCell<T> 
 #pragma unroll
     for (int i = 0; i < kAdjKin; ++i) { ea[i] = pa[i]; eb[i] = pb[i]; }
     bond_k_from_E_vjp(A.E, B.E, A.gfac, B.gfac, K, ad.a1, ad.a2, ad.ct, C, &ea[14], &eb[14]);
-    // bond damping takes the lighter mass (B on a tie, as the forward)
+    // bond damping takes the lighter mass; on a tie, where the smaller mass
+    // has no derivative, each voxel takes half (the mean of the two
+    // one-sided derivatives)
     const T gmmin = ad.ct * pdiv(K.ct, T(2) * mmin);
-    ea[15] = A.mass < B.mass ? gmmin : T(0);
-    eb[15] = A.mass < B.mass ? T(0) : gmmin;
+    const T wa = A.mass < B.mass ? T(1) : (B.mass < A.mass ? T(0) : T(0.5));
+    ea[15] = wa * gmmin;
+    eb[15] = (T(1) - wa) * gmmin;
 }
 
 // Adjoint of x_n of cell c from its direct part (k_adj_update) and the sum k

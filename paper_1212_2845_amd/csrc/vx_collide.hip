@@ -447,14 +447,16 @@ __global__ void __launch_bounds__(256) k_adj_contact(StepArgs<T> a, CollideArgs 
         geps += (A.cdist + B.cdist) * (T(0.5) * a.l);
         if (a.E_cell) {
             // kc = E_c l with E_c = 2 E_i E_j / (E_i + E_j); cc = 2 zeta
-            // sqrt(m_min kc); each term's m_min as its forward took it
+            // sqrt(m_min kc)
             const T Ei = a.E_cell[ci], Ej = a.E_cell[cj], s = Ei + Ej;
             const T gkc = (A.kc + B.kc) + (A.cc + B.cc) * K.cc / (T(2) * K.kc);
             gE += gkc * a.l * (T(2) * Ej * Ej / (s * s));
             const T mmin = Mi.m < Mj.m ? Mi.m : Mj.m;
             const T dcc_dm = K.cc / (T(2) * mmin);
-            if (Mi.m < Mj.m) gm += A.cc * dcc_dm;
-            if (!(Mj.m < Mi.m)) gm += B.cc * dcc_dm;
+            // both forces of the pair take the same smaller mass; on a
+            // tie each voxel takes half of its derivative
+            const T wi = Mi.m < Mj.m ? T(1) : (Mj.m < Mi.m ? T(0) : T(0.5));
+            gm += (A.cc + B.cc) * dcc_dm * wi;
         }
     }
     // v_i = P_i / m_i

@@ -495,7 +495,7 @@ def test_gradient_through_contact_matches_oracle_fd():
         assert err < 1e-4, (name, err)
 
 
-def _with_stiff_anchor(w, E=2e7):
+def _with_stiff_anchor(w, E=1e7):
     """Copy of workload w with a bonded pair of voxels of a much stiffer
     material added where the lattice is empty for 4 cells around, so that
     the stable timestep (set by the stiffest bond) does not move when the
@@ -514,23 +514,23 @@ def _with_stiff_anchor(w, E=2e7):
     raise AssertionError("no room for the anchor")
 
 
-def test_gradient_through_many_contacts_matches_material_fd():
+@pytest.mark.parametrize("rho2", [1000.0, 1300.0])
+def test_gradient_through_many_contacts_matches_material_fd(rho2):
     """Eight pairs of free bodies driven into each other (two materials,
     many contacts and several candidate-list rebuilds, FP64, full tape and
-    checkpoints every 25 steps; a stiff anchor pair fixes the timestep, and
-    the materials' densities differ): the
+    checkpoints every 25 steps; a stiff anchor pair fixes the timestep; the
+    materials' densities equal or not): the
     loss equals the oracle's, the two reverse runs agree bitwise, and the
     per-voxel gradients summed over each body material equal central
     differences of the oracle with respect to that material's modulus and
     density (a perturbed palette entry changes every voxel of the material,
     in the bonds and in the contact law)."""
     w, _ = workloads.colliding_bodies(pairs=(2, 2, 2), steps=700)
-    # the two body materials get different densities: with equal ones the
-    # lighter-mass rule of the bond and contact damping would sit exactly
-    # at its kink for every bond and pair across materials, where a
-    # central difference averages the two sides
+    # with equal densities (1000) every bond and pair across the materials
+    # sits at the kink of the lighter-mass rule, where the central
+    # difference and the reverse run both take the mean of the two sides
     w = dict(w, materials=[dict(m) for m in w["materials"]])
-    w["materials"][2]["rho"] = 1300.0
+    w["materials"][2]["rho"] = rho2
     w = _with_stiff_anchor(w)
     g = w["grid"].reshape(-1)
     filled = g > 0
@@ -546,6 +546,8 @@ def test_gradient_through_many_contacts_matches_material_fd():
     (g1, L1, c1), (g25, L25, c25) = out
     assert c1["rebuilds"] >= 2 and c1["rebuilds"] == c25["rebuilds"]
     assert abs(L1 / oracle_loss(w, wu, wv) - 1) < 1e-10
+    w_off = dict(w, params=dict(w["params"], self_collision_on=0))
+    assert abs(oracle_loss(w_off, wu, wv) / L1 - 1) > 1e-2        # the bodies do collide
     for k in ("E", "rho", "phase", "amp"):
         assert np.array_equal(g1[k], g25[k]), k
 
