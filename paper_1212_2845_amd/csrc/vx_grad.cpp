@@ -424,6 +424,10 @@ int vx_grad_forward(vx_handle h, int64_t n) {
     const int K = h->GL.K;
     // the motion bookkeeping of every step logs whether the step rebuilt
     // the candidate lists, which the reverse run follows
+    struct LogOn {   // the log is on for this call only, whatever ends it
+        vx_sim *h;
+        ~LogOn() { h->rlog = nullptr; }
+    } log_on{h};
     h->rlog = (unsigned char *)(h->gws + h->GL.rlog);
     h->rlog_step0 = step0;
     h->rlog_n = n;
@@ -433,7 +437,6 @@ int vx_grad_forward(vx_handle h, int64_t n) {
         r = h->precision == 64 ? checkpoint<double>(h, (int)j) : checkpoint<float>(h, (int)j);
         if (!r) r = vx_step(h, std::min<int64_t>(K, n - done));
     }
-    h->rlog = nullptr;
     if (r) return r;
     h->tape_valid = true;
     h->tape_n = n;
