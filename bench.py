@@ -208,6 +208,7 @@ def time_batch(count, steps, one_by_one_sample=256, one_by_one_steps=100):
     b = vx.Batch([o["grid"] for o in objs], mats, precision=32, stream=stream.cuda_stream, **params)
     b.bind()
     n_wg = b.autotune(steps=20)
+    tile_rule = b.tile(0)[0]
     nvox = b.counters()["voxels"]
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -221,7 +222,7 @@ def time_batch(count, steps, one_by_one_sample=256, one_by_one_steps=100):
     torch.cuda.empty_cache()
     batched = nvox * steps / (ms / 1e3)
     result = {"workload": "batch_objects_%d" % count, "objects": count, "voxels": nvox, "steps": steps,
-              "dtype": "f32", "value": batched, "ms": ms, "workgroups": n_wg,
+              "dtype": "f32", "value": batched, "ms": ms, "workgroups": n_wg, "tile_rule": tile_rule,
               "roofline": dict(roofline(32, nvox, ms / steps, "batch_objects_%d" % count, kernel="k_batch",
                                         traffic_key="batch_objects_%d|f32|k_batch" % count),
                                note="kernel_ms is per step: one persistent launch runs all steps")}

@@ -509,8 +509,27 @@ int vx_batch_contact_counters(vx_batch b, int64_t out[3]);
  * assigned to workgroups by longest-processing-time packing on cell count. */
 int vx_batch_set_launch(vx_batch b, int32_t n_workgroups, int32_t max_steps_per_launch);
 
-/* Time candidate workgroup counts over `steps` steps and keep the fastest;
- * the state and time are restored afterwards. */
+/* How each object's x-y footprint is cut into the batch kernel's tiles (at
+ * most 64 x 64 cells, 256 in all, marching the object's height): rule 0
+ * (the default) takes the widest rows, TX = min(nx, 64), then as many rows
+ * as fit; rule 1 keeps rule 0's number of tiles across x but evens their
+ * widths (nx = 70: two tiles 35 wide, not 64 and 6), then as many rows as
+ * fit, and differs from rule 0 only for footprints over 64 cells wide.
+ * Every rule computes the same step (the
+ * per-voxel method of Sec. 2-3); the last bits can differ, as a bond on a
+ * tile edge reaches its voxel's sum in another order.  May be called before
+ * or after binding; after, the object table is copied to the device and the
+ * call waits for it on the batch's stream.  VX_EINVAL for another rule. */
+int vx_batch_set_tile_rule(vx_batch b, int32_t rule);
+/* The tile rule in force and one object's tile: out[0] rule, out[1] TX,
+ * out[2] TY.  VX_EINVAL for an object index out of range. */
+int vx_batch_get_tile(vx_batch b, int32_t obj, int32_t out[3]);
+
+/* Time each tile rule with candidate workgroup counts over `steps` steps
+ * and keep the fastest pair (the rule reads back through
+ * vx_batch_get_tile); the state, the flags and the time are restored
+ * afterwards.  On an error (for instance VX_EUNSTABLE from a trial run) the
+ * rule, the workgroup count and the state are as before the call. */
 int vx_batch_autotune(vx_batch b, int32_t steps, int32_t *n_workgroups);
 int vx_batch_destroy(vx_batch b);
 const char *vx_batch_last_error(vx_batch b);

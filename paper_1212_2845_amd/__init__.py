@@ -39,7 +39,7 @@ EXPORTED = ["vx_create", "vx_workspace_bytes", "vx_bind_workspace", "vx_set_fixe
             "vx_batch_create", "vx_batch_workspace_bytes", "vx_batch_bind_workspace", "vx_batch_step",
             "vx_batch_read_state", "vx_batch_write_state", "vx_batch_get_dt", "vx_batch_counters",
             "vx_batch_set_launch", "vx_batch_autotune", "vx_batch_destroy", "vx_batch_last_error",
-            "vx_batch_candidates", "vx_batch_contact_counters"]
+            "vx_batch_candidates", "vx_batch_contact_counters", "vx_batch_set_tile_rule", "vx_batch_get_tile"]
 
 # state words, in the order vx_probe numbers them
 WORDS = ["ux", "uy", "uz", "qw", "qx", "qy", "qz", "px", "py", "pz", "lx", "ly", "lz"]
@@ -155,6 +155,8 @@ def lib():
     L.vx_batch_counters.argtypes = [P, C.POINTER(C.c_int64)]
     L.vx_batch_set_launch.argtypes = [P, i32, i32]
     L.vx_batch_autotune.argtypes = [P, i32, pi32]
+    L.vx_batch_set_tile_rule.argtypes = [P, i32]
+    L.vx_batch_get_tile.argtypes = [P, i32, pi32]
     L.vx_batch_candidates.argtypes = [P, P, P, P, P, i32, pi32]
     L.vx_batch_contact_counters.argtypes = [P, C.POINTER(C.c_int64)]
     L.vx_batch_destroy.argtypes = [P]
@@ -659,10 +661,23 @@ class Batch:
         self._check(lib().vx_batch_set_launch(self.h, int(n_workgroups), int(max_steps_per_launch)))
 
     def autotune(self, steps=20):
+        """Times each tile rule with candidate workgroup counts and keeps the
+        fastest pair; returns the workgroup count (the rule: tile(i)[0])."""
         self.bind()
         nw = C.c_int32()
         self._check(lib().vx_batch_autotune(self.h, int(steps), C.byref(nw)))
         return nw.value
+
+    def set_tile_rule(self, rule):
+        """0: the widest rows; 1: rule 0's tiles across x with their widths
+        evened out (differs for footprints over 64 cells wide)."""
+        self._check(lib().vx_batch_set_tile_rule(self.h, int(rule)))
+
+    def tile(self, i):
+        """(rule in force, TX, TY) of object i."""
+        out = (C.c_int32 * 3)()
+        self._check(lib().vx_batch_get_tile(self.h, int(i), out))
+        return out[0], out[1], out[2]
 
     def step(self, n=1):
         self.bind()

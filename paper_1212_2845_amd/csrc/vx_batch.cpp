@@ -3,8 +3,10 @@
 // with its own stable timestep (Eq. 31-32 over its own bonds); with contact
 // on, the objects share one world, one timestep and one surface hash, and
 // every step runs the collision chain, the contact forces and one launch of
-// the batch kernel.  Objects are assigned to workgroups by
-// longest-processing-time packing on cell count.
+// the batch kernel.  Each object's x-y footprint is cut into tiles by one of
+// two rules, objects are assigned to workgroups by longest-processing-time
+// packing on cell count, and the autotuner times both rules over a range of
+// workgroup counts.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,11 +35,30 @@ uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct ObjHost {
     long long off;
     int nx, ny, nz;
-    int tx, ty;
+    int tx, ty;                  // the tile in force
+    int tile[2][2];              // the tile of each rule
     double dt;
     double origin_z;
     long long nvox;
 };
+
+// Tiles of the batch kernel: TX, TY <= 64 and TX TY <= 256 (one 256-lane
+// workgroup, lane t at x = t mod TX, y = t / TX of the tile, marching the
+// object's height).  Rows as wide as the footprint keep each wavefront's
+// loads on few, long runs of cells, and fewer tiles mean fewer ring cells
+// loaded; narrower tiles that leave fewer lanes idle lost on both counts.
+// Rule 0: TX = min(nx, 64), then as many rows as fit.
+// Rule 1: as many tiles across x as rule 0, evened out (a footprint 70
+// wide takes two tiles of 35, not 64 and 6), then as many rows as fit.
+constexpr int kTileRules = 2;
+
+void choose_tiles(ObjHost &o) {
+    o.tile[0][0] = std::min(o.nx, 64);
+    o.tile[0][1] = std::min(std::min(o.ny, 256 / o.tile[0][0]), 64);
+    const int across = (o.nx + 63) / 64;
+    o.tile[1][0] = (o.nx + across - 1) / across;
+    o.tile[1][1] = std::min(std::min(o.ny, 256 / o.tile[1][0]), 64);
+}
 
 }  // namespace
 
@@ -53,6 +74,7 @@ struct vx_batch_sim {
     long long total = 0;         // cells
     long long nvox = 0;
     int n_wg = 0;                // workgroups of the persistent launch (0: default)
+    int tile_rule = 0;           // how the objects' footprints are tiled
     int max_steps_per_launch = 2000;
     long long step = 0;
     int cur = 0;
@@ -199,6 +221,32 @@ static void lpt(const vx_batch_sim *h, int n_wg, std::vector<int> &start, std::v
     start[n_wg] = (int)order.size();
 }
 
+// The object table (offsets, dimensions, tiles, timesteps); waits for the copy.
+template <typename T>
+static int upload_objs(vx_batch_sim *h) {
+    std::vector<BatchObj<T>> ob(h->objs.size());
+    for (size_t i = 0; i < ob.size(); ++i) {
+        const ObjHost &o = h->objs[i];
+        ob[i].off = (unsigned)o.off; ob[i].nx = o.nx; ob[i].ny = o.ny; ob[i].nz = o.nz;
+        ob[i].tx = o.tx; ob[i].ty = o.ty; ob[i].dt = (T)o.dt; ob[i].origin_z = (T)o.origin_z;
+    }
+    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.objs, ob.data(), ob.size() * sizeof(BatchObj<T>), hipMemcpyHostToDevice,
+                              h->stream));
+    BHIP_OK(h, hipStreamSynchronize(h->stream));
+    return VX_OK;
+}
+
+// Puts a tile rule in force; the object table on the device follows once bound.
+static int apply_tile_rule(vx_batch_sim *h, int rule) {
+    h->tile_rule = rule;
+    for (ObjHost &o : h->objs) {
+        o.tx = o.tile[rule][0];
+        o.ty = o.tile[rule][1];
+    }
+    if (!h->bound) return VX_OK;
+    return h->precision == 64 ? upload_objs<double>(h) : upload_objs<float>(h);
+}
+
 template <typename T>
 static int upload_all(vx_batch_sim *h) {
     hipStream_t s = h->stream;
@@ -211,13 +259,8 @@ static int upload_all(vx_batch_sim *h) {
     std::vector<uint8_t> fl(h->total, 0);
     BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.flags[0], fl.data(), h->total, hipMemcpyHostToDevice, s));
     BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.flags[1], fl.data(), h->total, hipMemcpyHostToDevice, s));
-    std::vector<BatchObj<T>> ob(h->objs.size());
-    for (size_t i = 0; i < ob.size(); ++i) {
-        const ObjHost &o = h->objs[i];
-        ob[i].off = (unsigned)o.off; ob[i].nx = o.nx; ob[i].ny = o.ny; ob[i].nz = o.nz;
-        ob[i].tx = o.tx; ob[i].ty = o.ty; ob[i].dt = (T)o.dt; ob[i].origin_z = (T)o.origin_z;
-    }
-    BHIP_OK(h, hipMemcpyAsync(h->ws + h->L.objs, ob.data(), ob.size() * sizeof(BatchObj<T>), hipMemcpyHostToDevice, s));
+    const int ro = upload_objs<T>(h);
+    if (ro != VX_OK) return ro;
     // rest state: zero everywhere except the quaternion w
     std::vector<T> st((size_t)N_WORDS * h->total, T(0));
     std::fill(st.begin() + (size_t)W_QW * h->total, st.begin() + (size_t)(W_QW + 1) * h->total, T(1));
@@ -425,9 +468,9 @@ int vx_batch_create(const vx_object *objs, int32_t n_obj, const vx_material *pal
         const long long nc = (long long)o.nx * o.ny * o.nz;
         ObjHost oh{};
         oh.off = off; oh.nx = o.nx; oh.ny = o.ny; oh.nz = o.nz;
-        // tile within the batch kernel's LDS: TX, TY <= 64, TX TY <= 256
-        oh.tx = std::min(o.nx, 64);
-        oh.ty = std::min(std::min(o.ny, 256 / oh.tx), 64);
+        choose_tiles(oh);
+        oh.tx = oh.tile[0][0];
+        oh.ty = oh.tile[0][1];
         oh.origin_z = o.origin[2];
         // the object's own stable timestep over its bonded material pairs
         std::vector<char> seen((size_t)n_mat * n_mat, 0), seen_vox(n_mat, 0);
@@ -627,17 +670,37 @@ int vx_batch_set_launch(vx_batch h, int32_t n_workgroups, int32_t max_steps_per_
     VX_CATCH(h)
 }
 
+int vx_batch_set_tile_rule(vx_batch h, int32_t rule) {
+    VX_TRY
+    if (!h || rule < 0 || rule >= kTileRules) return VX_EINVAL;
+    return apply_tile_rule(h, rule);
+    VX_CATCH(h)
+}
+
+int vx_batch_get_tile(vx_batch h, int32_t obj, int32_t out[3]) {
+    VX_TRY
+    if (!h || !out || obj < 0 || obj >= (int)h->objs.size()) return VX_EINVAL;
+    out[0] = h->tile_rule;
+    out[1] = h->objs[obj].tx;
+    out[2] = h->objs[obj].ty;
+    return VX_OK;
+    VX_CATCH(h)
+}
+
 int vx_batch_autotune(vx_batch h, int32_t steps, int32_t *n_workgroups) {
     VX_TRY
     if (!h || steps <= 0) return VX_EINVAL;
     if (!h->bound) return bfail(h, VX_ESTATE, "autotune before bind");
-    // time candidate workgroup counts on the real objects; the state, the
-    // flags, the buffer order, the step count and the status flags are
-    // saved and restored around the trial steps, on every exit
+    // time each tile rule with candidate workgroup counts on the real
+    // objects; the state, the flags, the buffer order, the step count and the
+    // status flags are saved and restored around the trial steps, and the
+    // tile rule and workgroup count are the fastest pair's, or as before the
+    // call on an error
     const size_t bytes = (size_t)N_WORDS * h->total * h->tsize;
     const int cur0 = h->cur;
     const long long step0 = h->step;
     const int wg0 = h->n_wg;
+    const int rule0 = h->tile_rule;
     const size_t ns = h->contact ? h->surf_cells.size() : 0;
     std::vector<char> save(bytes), fsave(h->total), ssave(256), csave(ns * h->cand_cap * 4), nsave(ns * 4);
     BHIP_OK(h, hipMemcpyAsync(save.data(), h->ws + h->L.state[cur0], bytes, hipMemcpyDeviceToHost, h->stream));
@@ -669,32 +732,43 @@ int vx_batch_autotune(vx_batch h, int32_t steps, int32_t *n_workgroups) {
     BHIP_OK(h, hipEventCreate(&e0));
     BHIP_OK(h, hipEventCreate(&e1));
     float best = 1e30f;
-    int best_wg = default_wg(h);
+    int best_wg = default_wg(h), best_rule = rule0;
     int rc = VX_OK;
-    for (int c : cands) {
-        const int nw = std::min(c, nobj);
-        h->n_wg = nw;
-        float ms = 0.f;
-        if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = bfail(h, VX_EDEVICE, "hipEventRecord"); break; }
-        rc = h->precision == 64 ? run<double>(h, steps) : run<float>(h, steps);
-        if (rc != VX_OK) break;
-        if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            rc = bfail(h, VX_EDEVICE, "timing events");
-            break;
+    for (int rule = 0; rule < kTileRules && rc == VX_OK; ++rule) {
+        bool same = rule > 0;   // a rule that tiles every object like rule 0 is not timed again
+        for (const ObjHost &o : h->objs)
+            same = same && o.tile[rule][0] == o.tile[0][0] && o.tile[rule][1] == o.tile[0][1];
+        if (same) continue;
+        rc = apply_tile_rule(h, rule);
+        for (int c : cands) {
+            if (rc != VX_OK) break;
+            const int nw = std::min(c, nobj);
+            h->n_wg = nw;
+            float ms = 0.f;
+            if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = bfail(h, VX_EDEVICE, "hipEventRecord"); break; }
+            rc = h->precision == 64 ? run<double>(h, steps) : run<float>(h, steps);
+            if (rc != VX_OK) break;
+            if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = bfail(h, VX_EDEVICE, "timing events");
+                break;
+            }
+            if (ms < best) { best = ms; best_wg = nw; best_rule = rule; }
+            if (nw == nobj) break;
         }
-        if (ms < best) { best = ms; best_wg = nw; }
-        if (nw == nobj) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != VX_OK) {
         const std::string msg = h->err;
+        apply_tile_rule(h, rule0);
         restore(wg0);
         h->err = msg;
         return rc;
     }
-    const int r = restore(best_wg);
+    int r = apply_tile_rule(h, best_rule);
+    if (r != VX_OK) return r;
+    r = restore(best_wg);
     if (r != VX_OK) return r;
     if (n_workgroups) *n_workgroups = best_wg;
     return VX_OK;

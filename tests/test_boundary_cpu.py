@@ -292,6 +292,58 @@ def test_batch_state_span_limit():
     assert e.value.code == vx.VX_EINVAL
 
 
+def _tiling_work(nx, ny, tx, ty):
+    """Brute force over the lanes of every tile of an nx x ny footprint
+    (lane t of a tile at x = t mod tx, y = t // tx; 64 lanes a wavefront):
+    (wavefronts holding a cell of the footprint, tiles)."""
+    waves = tiles = 0
+    lanes = np.arange(tx * ty)
+    for y0 in range(0, ny, ty):
+        for x0 in range(0, nx, tx):
+            inside = (x0 + lanes % tx < nx) & (y0 + lanes // tx < ny)
+            waves += sum(bool(inside[a:a + 64].any()) for a in range(0, tx * ty, 64))
+            tiles += 1
+    return waves, tiles
+
+
+def test_batch_tile_rules():
+    # both rules give tiles the batch kernel takes (TX, TY <= 64, TX TY <=
+    # 256, within the footprint); rule 0 is the widest rows; rule 1 equals
+    # it up to 64 cells across and otherwise evens the tile widths: the same
+    # tiles across x, fewer idle lanes (counted here lane by lane)
+    shapes = [(33, 30, 3), (64, 64, 1), (65, 3, 2), (70, 3, 2), (8, 8, 8), (100, 1, 1), (130, 20, 2), (200, 9, 1)]
+    grids = [np.ones((nz, ny, nx), np.uint8) for nx, ny, nz in shapes]
+    b = vx.Batch(grids, [workloads.EMPTY, M1], precision=32)
+    tiles = {}
+    for rule in (0, 1):
+        if rule:
+            b.set_tile_rule(rule)
+        for i, (nx, ny, nz) in enumerate(shapes):
+            r, tx, ty = b.tile(i)
+            assert r == rule
+            assert 1 <= tx <= min(nx, 64) and 1 <= ty <= min(ny, 64) and tx * ty <= 256, (rule, i, tx, ty)
+            assert ty == min(ny, 256 // tx, 64)
+            tiles[rule, i] = (tx, ty)
+    for i, (nx, ny, nz) in enumerate(shapes):
+        (tx0, ty0), (tx1, ty1) = tiles[0, i], tiles[1, i]
+        assert tx0 == min(nx, 64)
+        assert -(-nx // tx1) == -(-nx // tx0) and tx1 * (-(-nx // tx1)) - nx < -(-nx // tx1)
+        if nx <= 64:
+            assert (tx1, ty1) == (tx0, ty0)
+        else:
+            w0, w1 = _tiling_work(nx, ny, tx0, ty0), _tiling_work(nx, ny, tx1, ty1)
+            assert w1[0] <= w0[0] and w1[1] <= w0[1], (shapes[i], w0, w1)
+    assert tiles[1, 3] == (35, 3) and _tiling_work(70, 3, 35, 3)[0] < _tiling_work(70, 3, 64, 3)[0]
+    b.set_tile_rule(0)
+    assert b.tile(3) == (0, 64, 3)
+    for bad in (-1, 2):
+        with pytest.raises(vx.VoxsimError) as e:
+            b.set_tile_rule(bad)
+        assert e.value.code == vx.VX_EINVAL
+    with pytest.raises(vx.VoxsimError):
+        b.tile(len(shapes))
+
+
 def test_modal_helpers():
     # the beam formula at rho = 1 kg/m^3, L = 20 mm gives the printed
     # beam-theory column of Table 2 (section Validation), to its 4-5 digits

@@ -107,6 +107,41 @@ def test_batch_launch_split_is_bitwise():
             assert np.array_equal(a[k], r[k]), (i, k)
 
 
+@pytest.mark.parametrize("precision,tol", [(64, 1e-12), (32, 2e-5)])
+def test_tile_rules_match_single_objects(precision, tol):
+    """Footprints wider than one 64-cell tile, where the evened-width rule
+    cuts them otherwise than the widest-rows rule, and narrower ones: under
+    either rule each object equals the single-lattice path to rounding, and
+    the two rules agree."""
+    rng = np.random.Generator(np.random.PCG64(71))
+    shapes = [(70, 3, 2), (100, 5, 2), (130, 4, 2), (66, 12, 2), (33, 30, 4), (9, 40, 2)]
+    grids = [rng.integers(0, 5, size=(nz, ny, nx)).astype(np.uint8) for nx, ny, nz in shapes]
+    states = [perturbed_state(g.size, 80 + i, 1e-6, 1e-3, 0.5, 1e-3) for i, g in enumerate(grids)]
+    announce("tile rules p=%d" % precision)
+    runs = []
+    for rule in (0, 1):
+        b = vx.Batch(grids, MATS, precision=precision, **PARAMS)
+        b.set_tile_rule(rule)
+        b.bind()
+        for i, st in enumerate(states):
+            b.write_state(i, **st)
+        b.step(120)
+        runs.append(b)
+    differ = sum(runs[0].tile(i)[1:] != runs[1].tile(i)[1:] for i in range(len(grids)))
+    assert differ >= 4
+    for i, g in enumerate(grids):
+        s = vx.Sim(g, MATS, precision=precision, **PARAMS)
+        s.write_state(**states[i])
+        s.step(120)
+        want = s.read_state()
+        filled = g.reshape(-1) > 0
+        for b in runs:
+            e = compare(b.read_state(i), want, filled)
+            assert max(e["u"], e["v"], e["w"]) < tol and e["q"] < tol, (i, b.tile(i), e)
+        e = compare(runs[1].read_state(i), runs[0].read_state(i), filled)
+        assert max(e["u"], e["v"], e["w"]) < tol and e["q"] < tol, (i, e)
+
+
 def test_batch_autotune_restores_state():
     grids, states = make_objects(16, seed=41)
     announce("batch autotune")
@@ -117,6 +152,7 @@ def test_batch_autotune_restores_state():
     before = [b.read_state(i) for i in range(len(grids))]
     nw = b.autotune(steps=5)
     assert 1 <= nw <= len(grids)
+    assert b.tile(0)[0] in (0, 1)
     assert b.counters()["steps"] == 0
     for i in range(len(grids)):
         now = b.read_state(i)
@@ -206,8 +242,8 @@ def test_full_size_batch_sampled_against_oracle():
 
 def test_autotune_failure_restores_batch():
     """A trial run that goes unstable (bond damping far above 1) makes the
-    autotuner return VX_EUNSTABLE with the state, the step count and the
-    status flags as they were before the call."""
+    autotuner return VX_EUNSTABLE with the state, the step count, the
+    status flags and the tile rule as they were before the call."""
     g = np.ones((6, 6, 6), np.uint8)
     grids = [g, g]
     announce("batch autotune failure")
@@ -218,9 +254,11 @@ def test_autotune_failure_restores_batch():
         st = perturbed_state(g.size, 310 + i, 1e-7, 1e-4, 0.0, 0.0)
         b.write_state(i, u=st["u"], v=st["v"])
     before = [b.read_state(i) for i in range(2)]
+    b.set_tile_rule(1)
     with pytest.raises(vx.VoxsimError) as e:
         b.autotune(steps=3000)
     assert e.value.code == vx.VX_EUNSTABLE
+    assert b.tile(0)[0] == 1
     assert b.counters()["steps"] == 0
     for i in range(2):
         after = b.read_state(i)
