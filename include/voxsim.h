@@ -504,9 +504,10 @@ int vx_batch_candidates(vx_batch b, int32_t *obj_a, int32_t *cell_a, int32_t *ob
  * without contact. */
 int vx_batch_contact_counters(vx_batch b, int64_t out[3]);
 
-/* Workgroups of the persistent launch (0: a default of 4 per compute unit,
- * at most one per object) and steps per launch (0: keep).  Objects are
- * assigned to workgroups by longest-processing-time packing on cell count. */
+/* Workgroups of the persistent launch (0: the default, one per object;
+ * larger counts are cut to one per object) and steps per launch (0: keep).
+ * Objects are assigned to workgroups by longest-processing-time packing on
+ * cell count, the largest first. */
 int vx_batch_set_launch(vx_batch b, int32_t n_workgroups, int32_t max_steps_per_launch);
 
 /* How each object's x-y footprint is cut into the batch kernel's tiles (at
@@ -525,7 +526,8 @@ int vx_batch_set_tile_rule(vx_batch b, int32_t rule);
  * out[2] TY.  VX_EINVAL for an object index out of range. */
 int vx_batch_get_tile(vx_batch b, int32_t obj, int32_t out[3]);
 
-/* Time each tile rule with candidate workgroup counts over `steps` steps
+/* Time each tile rule with candidate workgroup counts (256 to 4096 and
+ * one per object) over `steps` steps
  * and keep the fastest pair (the rule reads back through
  * vx_batch_get_tile); the state, the flags and the time are restored
  * afterwards.  On an error (for instance VX_EUNSTABLE from a trial run) the

@@ -118,8 +118,10 @@ static void pack_tables(const vx_batch_sim *h, std::vector<MatConst<T>> &mc, std
 }
 
 static int default_wg(const vx_batch_sim *h) {
-    // a few workgroups per compute unit, never more than objects
-    return (int)std::min<long long>((long long)h->objs.size(), 256LL * 4);
+    // one workgroup per object: the hardware hands each free slot the next
+    // object in packing order (largest first), which balanced the
+    // 4096-object mix better than any static packing of fewer workgroups
+    return (int)std::min<size_t>(h->objs.size(), (size_t)INT32_MAX);
 }
 
 static void layout(vx_batch_sim *h) {
@@ -727,7 +729,7 @@ int vx_batch_autotune(vx_batch h, int32_t steps, int32_t *n_workgroups) {
         return VX_OK;
     };
     const int nobj = (int)h->objs.size();
-    const int cands[] = {256, 512, 768, 1024, 1536, 2048, 3072, 4096};
+    const int cands[] = {256, 512, 768, 1024, 1536, 2048, 3072, 4096, INT32_MAX};   // the last: one per object
     hipEvent_t e0, e1;
     BHIP_OK(h, hipEventCreate(&e0));
     BHIP_OK(h, hipEventCreate(&e1));
