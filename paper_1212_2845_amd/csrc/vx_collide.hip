@@ -351,8 +351,8 @@ __global__ void __launch_bounds__(256) k_contact(StepArgs<T> a, CollideArgs c, T
 
 template <typename T>
 __global__ void k_motion(StepArgs<T> a, CollideArgs c) {
-    if (c.rlog) *c.rlog = c.scalars->rebuild_flag ? 1 : 0;
-    motion_update(c.scalars, (double)a.dt);
+    const unsigned rebuilt = motion_update(c.scalars, (double)a.dt);
+    if (c.rlog) *c.rlog = rebuilt ? 1 : 0;
 }
 
 __global__ void k_force_rebuild(CollideArgs c) { *c.rebuild_flag = 1u; }

@@ -689,20 +689,22 @@ __device__ __forceinline__ void wave_vmax(unsigned long long *dst, T v) {
 }
 
 // Collision motion bookkeeping of one step, by one thread after the step
-// kernel: a rebuild that ran at the step's start
-// (flag still set) is closed, the largest speed of the step (read and
-// cleared) times dt is accumulated, and the flag is set for the next step
-// once twice the accumulated motion reaches the threshold (or always).
-__device__ __forceinline__ void motion_update(Scalars *sc, double dt) {
-    if (sc->rebuild_flag) {
-        sc->rebuild_flag = 0u;
-        sc->macc = 0.0;
-        sc->rebuilds += 1ull;
-    }
+// kernel: a rebuild that ran at the step's start (flag still set) is
+// closed, the largest speed of the step (read and cleared) times dt is
+// accumulated, and the flag is set for the next step once twice the
+// accumulated motion reaches the threshold (or always).  Every word is read
+// before any is written, so the thread waits on memory once.  Returns the
+// flag as found: whether a rebuild ran at the step's start.
+__device__ __forceinline__ unsigned motion_update(Scalars *sc, double dt) {
+    const unsigned flag = sc->rebuild_flag, every = sc->every;
+    const double macc = sc->macc, threshold = sc->threshold;
+    const unsigned long long rebuilds = sc->rebuilds;
     const double v = __longlong_as_double((long long)atomicExch(&sc->vmax_bits, 0ull));
-    const double acc = sc->macc + v * dt;
+    const double acc = (flag ? 0.0 : macc) + v * dt;
+    if (flag) sc->rebuilds = rebuilds + 1ull;
     sc->macc = acc;
-    if (sc->every || 2.0 * acc >= sc->threshold) sc->rebuild_flag = 1u;
+    sc->rebuild_flag = (every || 2.0 * acc >= threshold) ? 1u : 0u;
+    return flag;
 }
 
 }  // namespace vx
